@@ -1,0 +1,300 @@
+"""Seeded synthetic scenario generators.
+
+This module only draws random numbers and fills in problem data (mesh box,
+per-cell material draws, boundary-condition and source descriptions).  It
+contains none of the finite-element method's arithmetic, so both the GPU
+library binding and the CPU oracle consume exactly the same arrays.
+
+Conventions (shared vocabulary, not method):
+
+* z points up; the top of the box is ``origin[2] + extent[2]``.
+* Per-cell arrays are lexicographic with x fastest: ``c = i + nx*(j + ny*k)``.
+* Node arrays (degree p) are lexicographic with x fastest over
+  ``(p*nx+1) x (p*ny+1) x (p*nz+1)`` equispaced nodes.
+* Faces are numbered 0..5 = x-, x+, y-, y+, z-, z+.
+* Temperatures are in kelvin, pressures in pascal.
+
+A *time function* is the 8-tuple ``(kind, c0, cx, cy, cz, amp, period, phase)``
+whose value at point (x, y, z) and time t is
+``c0 + cx*x + cy*y + cz*z + amp*w(t)`` with ``w = 0`` (kind 0),
+``w = sin(2*pi*t/period + phase)`` (kind 1) or the square wave
+``w = +1 if sin(2*pi*t/period + phase) >= 0 else -1`` (kind 2).
+
+The concrete parameter choices follow the paper's workloads: layered soil
+with per-layer material classes (Section 3.3, Table 3), a hydrostatic
+pressure field plus a regional gradient (Section 3.3), energy piles on a
+regular spacing with seasonal loading (Sections 3.2-3.3) and an injection
+well (Section 2 benchmark, Table 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+PRESSURE = 0
+TEMPERATURE = 1
+
+DIRICHLET = 0
+NEUMANN = 1
+
+TF_CONST = 0
+TF_SIN = 1
+TF_SQUARE = 2
+
+LINE_HEAT = 0   # rate in W per metre of line
+LINE_WELL = 1   # rate in m^3/s for the whole screened interval
+
+DAY = 86400.0
+T15C = 288.15
+
+
+def timefn(c0=0.0, cx=0.0, cy=0.0, cz=0.0, amp=0.0, period=1.0, phase=0.0,
+           kind=TF_CONST) -> Tuple:
+    return (int(kind), float(c0), float(cx), float(cy), float(cz),
+            float(amp), float(period), float(phase))
+
+
+@dataclass
+class FaceBC:
+    field: int
+    face: int
+    kind: int
+    value: Tuple
+
+
+@dataclass
+class LineSource:
+    x: float
+    y: float
+    z0: float
+    z1: float
+    kind: int
+    rate: Tuple
+    T_inj: float = 0.0
+
+
+@dataclass
+class DirColumn:
+    field: int
+    x: float
+    y: float
+    z0: float
+    z1: float
+    value: Tuple
+
+
+@dataclass
+class Scenario:
+    name: str
+    origin: Tuple[float, float, float]
+    extent: Tuple[float, float, float]
+    ncells: Tuple[int, int, int]
+    degree: int
+    permeability: np.ndarray          # K_i [m^2], per cell
+    porosity: np.ndarray              # per cell
+    lambda_solid: np.ndarray          # W/m/K, per cell
+    rhoc_solid: np.ndarray            # J/m^3/K, per cell
+    rho_w: float = 1000.0
+    mu_w: float = 1.0e-3
+    c_w: float = 4.18e6
+    lambda_w: float = 0.6
+    g: float = 9.81
+    B_poro: float = 1.0e5             # <= 0 selects the steady pressure equation
+    heat_source: Optional[np.ndarray] = None   # W/m^3 per cell
+    bcs: List[FaceBC] = field(default_factory=list)
+    lines: List[LineSource] = field(default_factory=list)
+    dir_columns: List[DirColumn] = field(default_factory=list)
+    P0: Tuple = timefn()              # initial pressure (time function at t=0)
+    T0: Tuple = timefn(T15C)          # initial temperature
+    P0_steady: bool = False           # initial pressure = steady solution
+    dt: float = DAY
+    n_steps: int = 1
+    t0: float = 0.0
+
+    @property
+    def ncell(self) -> int:
+        nx, ny, nz = self.ncells
+        return nx * ny * nz
+
+    @property
+    def nodes_per_dim(self) -> Tuple[int, int, int]:
+        p = self.degree
+        return tuple(p * n + 1 for n in self.ncells)
+
+    @property
+    def nnode(self) -> int:
+        a, b, c = self.nodes_per_dim
+        return a * b * c
+
+    def replace(self, **kw) -> "Scenario":
+        return dataclasses.replace(self, **kw)
+
+
+# ----------------------------------------------------------------- helpers
+def hydrostatic(s_top_z: float, p_top: float, rho_w: float, g: float,
+                grad_x: float = 0.0, x_ref: float = 0.0) -> Tuple:
+    """p = p_top + rho*g*(z_top - z) + rho*g*grad_x*(x_ref - x)."""
+    rg = rho_w * g
+    return timefn(c0=p_top + rg * s_top_z + rg * grad_x * x_ref,
+                  cx=-rg * grad_x, cz=-rg)
+
+
+def _cell_centres_z(origin, extent, ncells):
+    nz = ncells[2]
+    hz = extent[2] / nz
+    return origin[2] + (np.arange(nz) + 0.5) * hz
+
+
+def layered_lognormal(rng, origin, extent, ncells, n_layers, mean_lo=-12.0,
+                      mean_hi=-10.0, sd=0.5, phi_lo=0.2, phi_hi=0.35):
+    """Horizontal layers with per-layer mean log10 permeability and i.i.d.
+    per-cell lognormal scatter; porosity uniform per cell."""
+    nx, ny, nz = ncells
+    zc = _cell_centres_z(origin, extent, ncells) - origin[2]
+    layer_h = extent[2] / n_layers
+    layer = np.minimum((zc / layer_h).astype(np.int64), n_layers - 1)
+    means = rng.uniform(mean_lo, mean_hi, size=n_layers)
+    logk = means[layer][:, None, None] + sd * rng.standard_normal((nz, ny, nx))
+    perm = np.power(10.0, logk).reshape(-1)
+    phi = rng.uniform(phi_lo, phi_hi, size=nx * ny * nz)
+    return perm, phi
+
+
+def _uniform(nc, v):
+    return np.full(nc, float(v))
+
+
+# ----------------------------------------------------------------- configs
+def config1(seed: int = 1) -> Scenario:
+    """100 m cube, 16^3 Q1, homogeneous medium, steady Darcy pressure with a
+    1e4 Pa drop across x, ten daily heat steps with a random 2x2x2-cell heat
+    source block and 15 C Dirichlet on every face."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = (16, 16, 16)
+    origin, extent = (0.0, 0.0, 0.0), (100.0, 100.0, 100.0)
+    nc = n[0] * n[1] * n[2]
+    s = Scenario("c1", origin, extent, n, 1,
+                 permeability=_uniform(nc, 1e-12), porosity=_uniform(nc, 0.3),
+                 lambda_solid=_uniform(nc, 2.5), rhoc_solid=_uniform(nc, 2.0e6),
+                 B_poro=0.0, dt=DAY, n_steps=10)
+    p_hyd = hydrostatic(100.0, 1.0e5, s.rho_w, s.g)
+    p_hi = (p_hyd[0], p_hyd[1] + 1.0e4) + p_hyd[2:]
+    s.bcs = [FaceBC(PRESSURE, 0, DIRICHLET, p_hi),
+             FaceBC(PRESSURE, 1, DIRICHLET, p_hyd)]
+    s.bcs += [FaceBC(TEMPERATURE, f, DIRICHLET, timefn(T15C)) for f in range(6)]
+    o = rng.integers(0, 15, size=3)
+    mag = rng.uniform(10.0, 50.0)
+    src = np.zeros((n[2], n[1], n[0]))
+    src[o[2]:o[2] + 2, o[1]:o[1] + 2, o[0]:o[0] + 2] = mag
+    s.heat_source = src.reshape(-1)
+    s.P0 = p_hyd
+    s.P0_steady = True
+    s.T0 = timefn(T15C)
+    return s
+
+
+def config2(seed: int = 2, ncells=(128, 128, 64), n_steps: int = 100) -> Scenario:
+    """500 x 500 x 100 m layered aquifer with an injection/extraction well
+    pair (+-0.01 m^3/s, injected water at 40 C), transient pressure."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    origin, extent = (0.0, 0.0, 0.0), (500.0, 500.0, 100.0)
+    perm, phi = layered_lognormal(rng, origin, extent, ncells, 5)
+    nc = perm.size
+    s = Scenario("c2", origin, extent, tuple(ncells), 1, permeability=perm,
+                 porosity=phi, lambda_solid=_uniform(nc, 2.5),
+                 rhoc_solid=_uniform(nc, 2.0e6), B_poro=1.0e5, dt=DAY,
+                 n_steps=n_steps)
+    p_hyd = hydrostatic(100.0, 1.0e5, s.rho_w, s.g)
+    s.bcs = [FaceBC(PRESSURE, f, DIRICHLET, p_hyd) for f in range(4)]
+    s.bcs += [FaceBC(TEMPERATURE, f, DIRICHLET, timefn(T15C)) for f in range(6)]
+    s.lines = [LineSource(150.0, 250.0, 0.0, 100.0, LINE_WELL, timefn(0.01),
+                          T_inj=313.15),
+               LineSource(350.0, 250.0, 0.0, 100.0, LINE_WELL, timefn(-0.01),
+                          T_inj=0.0)]
+    s.P0 = p_hyd
+    s.T0 = timefn(T15C)
+    return s
+
+
+def config3(seed: int = 3, degree: int = 1, ncells=None, n_steps: int = 365) -> Scenario:
+    """1 x 1 x 0.2 km energy-pile field: 400 piles on a 20 x 20 grid at 25 m
+    spacing, each a 30 m line heat source with a seasonal 50 W/m sine of
+    seeded phase; regional hydraulic gradient 0.001 along x."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if ncells is None:
+        ncells = (256, 256, 128) if degree == 1 else (128, 128, 64)
+    origin, extent = (0.0, 0.0, 0.0), (1000.0, 1000.0, 200.0)
+    perm, phi = layered_lognormal(rng, origin, extent, ncells, 5)
+    nc = perm.size
+    s = Scenario("c3q%d" % degree, origin, extent, tuple(ncells), degree,
+                 permeability=perm, porosity=phi,
+                 lambda_solid=_uniform(nc, 2.5), rhoc_solid=_uniform(nc, 2.0e6),
+                 B_poro=1.0e5, dt=DAY, n_steps=n_steps)
+    p_g = hydrostatic(200.0, 1.0e5, s.rho_w, s.g, grad_x=0.001, x_ref=1000.0)
+    s.bcs = [FaceBC(PRESSURE, 0, DIRICHLET, p_g), FaceBC(PRESSURE, 1, DIRICHLET, p_g)]
+    s.bcs += [FaceBC(TEMPERATURE, f, DIRICHLET, timefn(T15C)) for f in range(6)]
+    phases = rng.uniform(0.0, 2.0 * np.pi, size=400)
+    xs = 262.5 + 25.0 * np.arange(20)
+    k = 0
+    for jy in range(20):
+        for ix in range(20):
+            s.lines.append(LineSource(xs[ix], xs[jy], 170.0, 200.0, LINE_HEAT,
+                                      timefn(amp=50.0, period=365.0 * DAY,
+                                             phase=phases[k], kind=TF_SIN)))
+            k += 1
+    s.P0 = p_g
+    s.P0_steady = True
+    s.T0 = timefn(T15C)
+    return s
+
+
+def config4_instance(i: int, n_override: Optional[int] = None,
+                     n_steps: int = 50) -> Scenario:
+    """One design scenario of the batched set: n^3 Q1 cells on a 200 m cube,
+    layered lognormal permeability, 10-200 energy piles as Dirichlet
+    temperature columns on a 10 m lattice at a seeded 30-50 C."""
+    rng = np.random.Generator(np.random.PCG64(4000 + i))
+    n = int(rng.integers(32, 97))
+    if n_override is not None:
+        n = int(n_override)
+    ncells = (n, n, n)
+    origin, extent = (0.0, 0.0, 0.0), (200.0, 200.0, 200.0)
+    perm, phi = layered_lognormal(rng, origin, extent, ncells, 5)
+    nc = perm.size
+    s = Scenario("c4_%d" % i, origin, extent, ncells, 1, permeability=perm,
+                 porosity=phi, lambda_solid=_uniform(nc, 2.5),
+                 rhoc_solid=_uniform(nc, 2.0e6), B_poro=1.0e5, dt=DAY,
+                 n_steps=n_steps)
+    p_g = hydrostatic(200.0, 1.0e5, s.rho_w, s.g, grad_x=0.001, x_ref=200.0)
+    s.bcs = [FaceBC(PRESSURE, 0, DIRICHLET, p_g), FaceBC(PRESSURE, 1, DIRICHLET, p_g)]
+    s.bcs += [FaceBC(TEMPERATURE, f, DIRICHLET, timefn(T15C)) for f in range(6)]
+    n_piles = int(rng.integers(10, 201))
+    lattice = [(10.0 * (a + 1), 10.0 * (b + 1)) for b in range(19) for a in range(19)]
+    pick = rng.choice(len(lattice), size=n_piles, replace=False)
+    T_inj = rng.uniform(303.15, 323.15)
+    for q in sorted(pick.tolist()):
+        x, y = lattice[q]
+        s.dir_columns.append(DirColumn(TEMPERATURE, x, y, 170.0, 200.0, timefn(T_inj)))
+    s.P0 = p_g
+    s.P0_steady = True
+    s.T0 = timefn(T15C)
+    return s
+
+
+def config5(seed: int, ncells=(128, 128, 64), n_steps: int = 100) -> Scenario:
+    """The layered-aquifer setup with permeability/porosity re-drawn per seed
+    (training seeds 5000-5019, test seeds 5100-5109)."""
+    s = config2(seed=seed, ncells=ncells, n_steps=n_steps)
+    s.name = "c5_%d" % seed
+    return s
+
+
+def random_field(seed: int, n: int, kind: str = "normal") -> np.ndarray:
+    """Seeded random vector for operator-apply tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kind == "normal":
+        return rng.standard_normal(n)
+    return rng.uniform(-1.0, 1.0, n)
