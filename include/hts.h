@@ -1,0 +1,271 @@
+/*
+ * hts.h -- C ABI of the MI355X hydrothermal time-stepping library (libhts.so).
+ *
+ * The library advances the one-way coupled groundwater-pressure /
+ * heat-transport model of Sun et al., "An HPC-Based Hydrothermal Finite
+ * Element Simulator for Modeling Underground Response to Community-Scale
+ * Geothermal Energy Production" (Section 2, Eqs. 1-4), on uniform
+ * hexahedral box meshes with Q1 or Q2 Lagrange elements, one backward-Euler
+ * step at a time: first the Darcy pressure P^{n+1} (Eq. 3), then the
+ * temperature T^{n+1} (Eq. 4) with the Darcy flux q = -k (grad P + rho_w g)
+ * evaluated from P^{n+1} at every quadrature point.
+ *
+ * Conventions
+ *   - z points up.  Faces are 0..5 = x-, x+, y-, y+, z-, z+.
+ *   - Per-cell arrays are lexicographic with x fastest (c = i + nx*(j + ny*k));
+ *     node arrays likewise over (p*nx+1) x (p*ny+1) x (p*nz+1) nodes.
+ *   - Temperatures cross the ABI in kelvin, pressures in pascal, SI units
+ *     everywhere else.
+ *   - Every call returns an hts_status; C++ exceptions never cross the ABI;
+ *     hts_last_error() returns a thread-local message for the last failure.
+ *   - Host arrays passed in are copied; the caller keeps ownership.
+ *     Device pointers passed in (hts_apply_operator) are caller-owned and
+ *     must stay valid until the mesh's stream has been synchronised.
+ *   - All device work of a mesh is issued on the stream given at creation
+ *     (NULL = the null stream).  Calls on one mesh are not thread-safe.
+ */
+#ifndef HTS_H
+#define HTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hts_mesh hts_mesh;
+typedef struct hts_nn hts_nn;
+
+typedef enum {
+    HTS_OK = 0,
+    HTS_ERR_ARG = -1,            /* invalid argument                          */
+    HTS_ERR_STATE = -2,          /* call not valid in the current state       */
+    HTS_ERR_NOMEM = -3,          /* device or host allocation failed          */
+    HTS_ERR_HIP = -4,            /* a HIP runtime call failed                 */
+    HTS_ERR_NOT_CONVERGED = -5,  /* a linear solve missed its tolerance       */
+    HTS_ERR_BREAKDOWN = -6,      /* Krylov breakdown or non-finite residual   */
+    HTS_ERR_UNSUPPORTED = -7     /* valid request this build does not handle  */
+} hts_status;
+
+typedef enum { HTS_PRESSURE = 0, HTS_TEMPERATURE = 1 } hts_field;
+
+/* Arithmetic type of an operator application. */
+typedef enum { HTS_FP64 = 0, HTS_FP32 = 1 } hts_precision;
+
+/* Solve mode of a time step:
+ *   FP64          - FP64 Krylov, FP64 multigrid;
+ *   FP32_REFINED  - FP64 outer defect correction around an FP32 inner
+ *                   Krylov solve with an FP32 operator and smoother; dot
+ *                   products, the coarse-grid solve and the update stay FP64;
+ *   LEARNED       - pressure uses flexible CG preconditioned by the learned
+ *                   network (opts.nn) with the multigrid V-cycle as fallback. */
+typedef enum { HTS_MODE_FP64 = 0, HTS_MODE_FP32_REFINED = 1, HTS_MODE_LEARNED = 2 } hts_mode;
+
+typedef enum { HTS_BC_DIRICHLET = 0, HTS_BC_NEUMANN = 1, HTS_BC_NONE = 2 } hts_bc_kind;
+
+typedef enum { HTS_LINE_HEAT = 0, HTS_LINE_WELL = 1 } hts_line_kind;
+
+typedef enum { HTS_TF_CONST = 0, HTS_TF_SIN = 1, HTS_TF_SQUARE = 2 } hts_tf_kind;
+
+/* A value affine in space with a periodic time part:
+ *   v(x,y,z,t) = c0 + cx*x + cy*y + cz*z + amp*w(t),
+ *   w = 0 (CONST), sin(2 pi t/period + phase) (SIN), or the square wave
+ *   +1 where that sine is >= 0 and -1 elsewhere (SQUARE).
+ * Hydrostatic pressure p_top + rho_w g (z_top - z) is c0 = p_top + rho_w g z_top,
+ * cz = -rho_w g.  Neumann fluxes and line rates must have cx = cy = cz = 0. */
+typedef struct {
+    int32_t kind;
+    double c0, cx, cy, cz, amp, period, phase;
+} hts_timefn;
+
+/* Device-memory hooks.  When alloc is NULL the library uses hipMalloc/hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} hts_allocator;
+
+/* Uniform box mesh [origin, origin+extent] with ncells cells of degree 1 or 2. */
+typedef struct {
+    double origin[3];
+    double extent[3];
+    int32_t ncells[3];
+    int32_t degree;
+    int32_t device;       /* HIP device ordinal */
+    void *stream;         /* hipStream_t; NULL = null stream */
+    hts_allocator alloc;
+} hts_mesh_desc;
+
+/* Materials (Section 2 mixture rules and mobility, Tables 1 and 3):
+ *   k = K_i / mu_w  (or K / (rho_w g) when permeability is NULL),
+ *   lambda = (1-phi) lambda_s + phi lambda_w,  c_T = (1-phi) c_s + phi c_w,
+ * unless lambda_bulk / rhoc_bulk give the bulk values directly.
+ * All arrays are host [ncell] arrays.  B_poro is the storage modulus of
+ * Eq. 1 in Pa; B_poro <= 0 selects the steady pressure equation. */
+typedef struct {
+    const double *permeability;            /* K_i [m^2]              */
+    const double *hydraulic_conductivity;  /* K [m/s], if no K_i     */
+    const double *porosity;                /* phi [-]                */
+    const double *lambda_solid;            /* lambda_s [W/m/K]       */
+    const double *rhoc_solid;              /* c_s [J/m^3/K]          */
+    const double *lambda_bulk;             /* optional lambda [W/m/K] */
+    const double *rhoc_bulk;               /* optional c_T [J/m^3/K]  */
+    double rho_w, mu_w, c_w, lambda_w, g, B_poro;
+} hts_materials;
+
+typedef struct {
+    int32_t mode;            /* hts_mode                                        */
+    double rtol;             /* relative residual ||b-Ax|| <= rtol ||b|| (1e-8) */
+    int32_t max_iter;        /* Krylov iterations per solve (inner, total)      */
+    int32_t gmres_restart;   /* FGMRES restart length (30)                      */
+    int32_t cheb_degree;     /* Chebyshev smoothing degree per side (2)         */
+    int32_t mg_coarse_max;   /* coarsen until a level has <= this many nodes    */
+    int32_t heat_cheb_degree;/* degree of the heat Chebyshev-Jacobi preconditioner */
+    double inner_rtol;       /* inner tolerance of FP32_REFINED (1e-4)          */
+    int32_t check_every;     /* host convergence check every n iterations (1)   */
+    int32_t use_graph;       /* replay captured HIP graphs for time steps       */
+    hts_nn *nn;              /* network for HTS_MODE_LEARNED                    */
+    int32_t verbose;
+} hts_solver_opts;
+
+typedef struct {
+    int32_t iters[2];        /* Krylov iterations per field (inner total)     */
+    int32_t outer[2];        /* defect-correction outer iterations per field  */
+    double relres[2];        /* true FP64 relative residual per field         */
+    int32_t fallbacks;       /* learned -> multigrid fallbacks in the step    */
+    int32_t status[2];       /* hts_status per field                          */
+    double time_ms[2];       /* device time of each field's solve             */
+} hts_step_stats;
+
+typedef struct {
+    int32_t levels;          /* encoder/decoder levels (4)                    */
+    int32_t channels[4];     /* channels per level (16, 32, 48, 64)           */
+    int32_t device;
+    void *stream;
+    uint64_t seed;           /* weight initialisation                         */
+} hts_nn_desc;
+
+typedef struct {
+    int32_t epochs_done;
+    int32_t pairs;
+    double loss_first;
+    double loss_last;
+    double val_loss;
+} hts_train_stats;
+
+/* ---------------------------------------------------------------- meshes */
+
+/* Fill opts with defaults (FP64 mode, rtol 1e-8, ...). */
+void hts_default_opts(hts_solver_opts *opts);
+
+/* Create a mesh (Section 3.3: a hexahedral mesh of the site box).
+ * degree must be 1 or 2; every ncells entry >= 1; extent > 0.
+ * HTS_ERR_ARG on bad geometry, HTS_ERR_HIP if the device cannot be set. */
+hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out);
+
+void hts_destroy_mesh(hts_mesh *mesh);
+
+/* Copy material arrays to the device and form the cellwise k, lambda, c_T
+ * (Section 2, mixture rules).  Must precede any solve or apply.
+ * HTS_ERR_ARG if a required array is NULL or a constant is not positive. */
+hts_status hts_set_materials(hts_mesh *mesh, const hts_materials *mat);
+
+/* Face boundary condition for one field (Section 3.3, Fig. 12).
+ * DIRICHLET: nodal value v(x,y,z,t^{n+1}) imposed strongly.
+ * NEUMANN:   outward normal flux (pressure: Darcy flux q.n [m/s]; heat:
+ *            heat flux [W/m^2]) entering the right-hand sides of Eqs. 3-4.
+ * NONE:      natural no-flux.  Faces are applied in call order (a node on
+ *            two Dirichlet faces takes the later value). */
+hts_status hts_set_face_bc(hts_mesh *mesh, hts_field field, int32_t face, int32_t kind,
+                           const hts_timefn *value);
+
+/* Volumetric heat source f [W/m^3] per cell (host [ncell]); NULL clears. */
+hts_status hts_set_volume_source(hts_mesh *mesh, const double *w_per_m3);
+
+/* Vertical line source over [z0, z1] at (x, y):
+ *   HTS_LINE_HEAT: heat rate per metre q_l(t) [W/m] (energy piles, Section 3.2);
+ *   HTS_LINE_WELL: well rate Q(t) [m^3/s] spread uniformly over the screen;
+ *                  Q > 0 injects water at T_inj [K], which adds c_w (Q/L)
+ *                  (T_inj - T) to the heat balance.
+ * Rates must be spatially constant time functions. */
+hts_status hts_add_line_source(hts_mesh *mesh, double x, double y, double z0, double z1,
+                               int32_t kind, const hts_timefn *rate, double T_inj);
+
+/* Dirichlet column (an energy pile held at a temperature, Section 3.3): the
+ * node column nearest (x, y) over z0 <= z <= z1 is constrained to v(t). */
+hts_status hts_add_dirichlet_column(hts_mesh *mesh, hts_field field, double x, double y,
+                                    double z0, double z1, const hts_timefn *value);
+
+/* Set / get a field's nodal state (host [nnode]) and the mesh time. */
+hts_status hts_set_state(hts_mesh *mesh, hts_field field, const double *host, double t);
+hts_status hts_get_state(hts_mesh *mesh, hts_field field, double *host, double *t);
+
+/* Node / cell counts of a mesh. */
+hts_status hts_mesh_sizes(const hts_mesh *mesh, int64_t *nnode, int64_t *ncell);
+
+/* ------------------------------------------------------------- operators */
+
+/* y = A x for one field's operator on the constrained space (Eq. 3 or
+ * Eq. 4 left-hand side at time step dt): constrained rows are the identity,
+ * free rows see only free columns.
+ *   PRESSURE:    A = M + dt B_poro K_k   (A = K_k when B_poro <= 0 or dt <= 0)
+ *   TEMPERATURE: A = M_{c_T} + dt K_lambda + dt c_w C(q_h) + dt c_w M_inj,
+ *                with q_h from the mesh's current pressure state.
+ * x_dev, y_dev: device arrays of nnode doubles (HTS_FP64) or floats (HTS_FP32)
+ * on the mesh's device; distinct buffers.  Asynchronous on the mesh stream. */
+hts_status hts_apply_operator(hts_mesh *mesh, hts_field field, hts_precision prec, double dt,
+                              const void *x_dev, void *y_dev);
+
+/* ----------------------------------------------------------------- solves */
+
+/* Replace the pressure state by the steady solution of Eq. 3 (B_poro term
+ * dropped) at the current time.  Transactional: unchanged on failure. */
+hts_status hts_solve_steady_pressure(hts_mesh *mesh, const hts_solver_opts *opts,
+                                     hts_step_stats *stats);
+
+/* One backward-Euler step of size dt: P^{n+1} (Eq. 3), then T^{n+1}
+ * (Eq. 4).  Every solve ends with the true FP64 residual check
+ * ||b - A x||_2 <= rtol ||b||_2 on the eliminated system.  Transactional: on
+ * HTS_ERR_NOT_CONVERGED / HTS_ERR_BREAKDOWN the state and time are not
+ * advanced; stats (may be NULL) is filled either way. */
+hts_status hts_solve_step(hts_mesh *mesh, double dt, const hts_solver_opts *opts,
+                          hts_step_stats *stats);
+
+/* Advance n_instances independent meshes by n_steps steps of size dt as one
+ * batch: every kernel launch covers all instances, each with its own
+ * convergence state.  stats: [n_instances] (last step), may be NULL.
+ * With opts->use_graph the per-step launch sequence is captured once and
+ * replayed.  Stops at the first failing step (those instances are not
+ * advanced past it). */
+hts_status hts_advance(hts_mesh *const *meshes, int32_t n_instances, int32_t n_steps, double dt,
+                       const hts_solver_opts *opts, hts_step_stats *stats);
+
+/* Time several operator tile shapes on these meshes and keep the fastest
+ * per (degree, field, precision, size class) for later launches. */
+hts_status hts_autotune(hts_mesh *const *meshes, int32_t n);
+
+const char *hts_last_error(void);
+
+/* -------------------------------------------------- learned preconditioner */
+
+hts_status hts_nn_create(const hts_nn_desc *desc, hts_nn **out);
+void hts_nn_destroy(hts_nn *nn);
+
+/* Run plain multigrid-CG pressure solves of n_steps steps on each mesh and
+ * keep (r_k, e_k = x* - x_k) pairs with the log10 permeability as input. */
+hts_status hts_nn_harvest(hts_nn *nn, hts_mesh *const *meshes, int32_t n_draws, int32_t n_steps,
+                          double dt, int32_t pairs_per_solve);
+
+/* Train on the harvested pairs with the library's own BF16 MFMA forward and
+ * backward kernels and FP32 Adam. */
+hts_status hts_nn_train(hts_nn *nn, int32_t epochs, double lr, int32_t batch,
+                        hts_train_stats *out);
+
+hts_status hts_nn_save(const hts_nn *nn, const char *path);
+hts_status hts_nn_load(hts_nn *nn, const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HTS_H */

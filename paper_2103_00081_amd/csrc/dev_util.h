@@ -1,0 +1,57 @@
+// Device helpers shared by several translation units.
+#pragma once
+#include "common.h"
+
+namespace hts {
+
+struct ColInfo {
+    int64_t base;   // instance-local index of the node at k = 0
+    int valid;
+    int xyc;        // constrained by an x or y face
+    int dlo, dhi;   // constrained z range from Dirichlet columns
+};
+
+__device__ __forceinline__ static ColInfo col_info(const OpDev &o, int i, int j)
+{
+    ColInfo c;
+    c.valid = (i >= 0 && i < o.NX && j >= 0 && j < o.NY);
+    c.base = c.valid ? (int64_t)i + (int64_t)o.NX * j : 0;
+    const int m = o.dmask;
+    c.xyc = c.valid && (((m & 1) && i == 0) || ((m & 2) && i == o.NX - 1) || ((m & 4) && j == 0) ||
+                        ((m & 8) && j == o.NY - 1));
+    int packed = (c.valid && o.dcol) ? o.dcol[c.base] : DCOL_NONE;
+    c.dlo = packed & 0xFFFF;
+    c.dhi = (packed >> 16) & 0xFFFF;
+    return c;
+}
+
+__device__ __forceinline__ static bool constrained(const ColInfo &c, int k, int NZ, int m)
+{
+    return c.xyc || ((m & 16) && k == 0) || ((m & 32) && k == NZ - 1) || (k >= c.dlo && k <= c.dhi);
+}
+
+__device__ __forceinline__ static double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+
+// Node (i, j, k) of instance-local index n.
+__device__ __forceinline__ static void node_ijk(const OpDev &o, int64_t n, int &i, int &j, int &k)
+{
+    i = (int)(n % o.NX);
+    j = (int)((n / o.NX) % o.NY);
+    k = (int)(n / ((int64_t)o.NX * o.NY));
+}
+
+__device__ __forceinline__ static bool node_constrained(const OpDev &o, int64_t n)
+{
+    int i, j, k;
+    node_ijk(o, n, i, j, k);
+    ColInfo c = col_info(o, i, j);
+    return constrained(c, k, o.NZ, o.dmask);
+}
+
+}  // namespace hts

@@ -1,0 +1,18 @@
+// Per-instance scalar kernels of the Krylov solvers (krylov.hip).
+#pragma once
+#include "common.h"
+
+namespace hts {
+
+void gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_t *kdim, hipStream_t s);
+void gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit, const double *h1,
+                const double *h2, const double *ww, double *H, double *cs, double *sn, double *g, int32_t *kdim,
+                hipStream_t s);
+void gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g, const int32_t *kdim,
+              double *y, hipStream_t s);
+void outer_check(int ninst, int32_t *active, double *S, const double *rr, hipStream_t s);
+void set_inner_tol(int ninst, const int32_t *active, double *S, double floor2, double factor2, hipStream_t s);
+void convert_plain(int64_t n, const double *in, float *out, hipStream_t s);
+void set_otol(int ninst, const int32_t *active, double *S, const double *bb, int stride, double rtol2, hipStream_t s);
+
+}  // namespace hts

@@ -1,0 +1,195 @@
+// Per-instance scalar work of the Krylov solvers (one thread per instance):
+// FGMRES Arnoldi bookkeeping with Givens rotations and back substitution,
+// and the outer FP64 defect-correction test.
+#include "common.h"
+#include "krylov.h"
+
+namespace hts {
+
+namespace {
+
+__global__ void k_gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_t *kdim)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || !active[i]) return;
+    double *Si = S + (int64_t)i * NSLOT;
+    const double rr = Si[S_RR];
+    kdim[i] = 0;
+    if (!isfinite(rr)) {
+        Si[S_STATUS] = -6;
+        active[i] = 0;
+        return;
+    }
+    if (rr <= Si[S_TOL2]) {
+        Si[S_STATUS] = 0;
+        active[i] = 0;
+        return;
+    }
+    const double beta = sqrt(rr);
+    double *gi = g + (int64_t)i * (mres + 1);
+    gi[0] = beta;
+    for (int j = 1; j <= mres; j++) gi[j] = 0.0;
+    Si[S_SCALE] = 1.0 / beta;
+    Si[S_STATUS] = 1;
+}
+
+__global__ void k_gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit,
+                             const double *h1, const double *h2, const double *ww, double *H, double *cs,
+                             double *sn, double *g, int32_t *kdim)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || !active[i]) return;
+    double *Si = S + (int64_t)i * NSLOT;
+    double *Hi = H + (int64_t)i * (mres + 1) * mres;   // H[r][c] = Hi[r * mres + c]
+    double *ci = cs + (int64_t)i * mres, *si = sn + (int64_t)i * mres;
+    double *gi = g + (int64_t)i * (mres + 1);
+    const double *a1 = h1 + (int64_t)i * (j + 1);
+    const double *a2 = h2 + (int64_t)i * (j + 2);
+    for (int r = 0; r <= j; r++) Hi[r * mres + j] = a1[r] + a2[r];
+    const double hn = sqrt(fmax(ww[i], 0.0));
+    Hi[(j + 1) * mres + j] = hn;
+    for (int r = 0; r < j; r++) {
+        const double a = Hi[r * mres + j], b = Hi[(r + 1) * mres + j];
+        Hi[r * mres + j] = ci[r] * a + si[r] * b;
+        Hi[(r + 1) * mres + j] = -si[r] * a + ci[r] * b;
+    }
+    const double a = Hi[j * mres + j], b = Hi[(j + 1) * mres + j];
+    const double rho = hypot(a, b);
+    ci[j] = rho > 0.0 ? a / rho : 1.0;
+    si[j] = rho > 0.0 ? b / rho : 0.0;
+    Hi[j * mres + j] = rho;
+    Hi[(j + 1) * mres + j] = 0.0;
+    gi[j + 1] = -si[j] * gi[j];
+    gi[j] = ci[j] * gi[j];
+    kdim[i] = j + 1;
+    Si[S_ITER] += 1.0;
+    const double res2 = gi[j + 1] * gi[j + 1];
+    Si[S_RR] = res2;
+    Si[S_SCALE] = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (!isfinite(res2) || !isfinite(hn) || rho == 0.0) {
+        Si[S_STATUS] = -6;
+        active[i] = 0;
+    } else if (res2 <= Si[S_TOL2] || hn == 0.0) {
+        Si[S_STATUS] = 0;
+        active[i] = 0;
+    } else if (Si[S_ITER] >= maxit) {
+        Si[S_STATUS] = -5;
+        active[i] = 0;
+    } else if (j == mres - 1) {
+        active[i] = 0;   // cycle ends; status stays 1 (restart)
+    }
+}
+
+__global__ void k_gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g,
+                           const int32_t *kdim, double *y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || !cyc[i]) return;
+    const int kd = kdim[i];
+    const double *Hi = H + (int64_t)i * (mres + 1) * mres;
+    const double *gi = g + (int64_t)i * (mres + 1);
+    double *yi = y + (int64_t)i * mres;
+    for (int r = kd - 1; r >= 0; r--) {
+        double s = gi[r];
+        for (int c = r + 1; c < kd; c++) s -= Hi[r * mres + c] * yi[c];
+        yi[r] = s / Hi[r * mres + r];
+    }
+}
+
+// outer defect correction: v0 = ||b - A x||^2
+__global__ void k_outer_check(int ninst, int32_t *active, double *S, const double *rr)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || !active[i]) return;
+    double *Si = S + (int64_t)i * NSLOT;
+    const double v = rr[i];
+    Si[S_ORR] = v;
+    Si[S_ONORM] = sqrt(fmax(v, 0.0));
+    Si[S_OINV] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    if (!isfinite(v)) {
+        Si[S_OSTATUS] = -6;
+        active[i] = 0;
+    } else if (v <= Si[S_OTOL2]) {
+        Si[S_OSTATUS] = 0;
+        active[i] = 0;
+    }
+}
+
+__global__ void k_set_otol(int ninst, const int32_t *active, double *S, const double *bb, int stride, double rtol2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || (active && !active[i])) return;
+    double *Si = S + (int64_t)i * NSLOT;
+    const double v = bb[(int64_t)i * stride];
+    Si[S_OBB] = v;
+    Si[S_OTOL2] = rtol2 * v;
+    Si[S_OSTATUS] = 1;
+}
+
+// inner tolerance of a defect-correction solve whose RHS is r / ||r||:
+// TOL2 = max(floor2, factor2 * OTOL2 / ORR)
+__global__ void k_set_inner_tol(int ninst, const int32_t *active, double *S, double floor2, double factor2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || (active && !active[i])) return;
+    double *Si = S + (int64_t)i * NSLOT;
+    const double rel = Si[S_ORR] > 0.0 ? Si[S_OTOL2] / Si[S_ORR] : 1.0;
+    Si[S_BB] = 1.0;
+    Si[S_TOL2] = fmax(floor2, factor2 * rel);
+    Si[S_ITER] = 0.0;
+    Si[S_STATUS] = 1.0;
+}
+
+__global__ void k_convert_plain_df(int64_t n, const double *in, float *out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+}  // namespace
+
+void set_inner_tol(int ninst, const int32_t *active, double *S, double floor2, double factor2, hipStream_t s)
+{
+    k_set_inner_tol<<<dim3((ninst + 63) / 64), dim3(64), 0, s>>>(ninst, active, S, floor2, factor2);
+    HTS_LAUNCH_CHECK();
+}
+
+void convert_plain(int64_t n, const double *in, float *out, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_convert_plain_df<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, in, out);
+    HTS_LAUNCH_CHECK();
+}
+
+static dim3 g1(int n) { return dim3((n + 63) / 64); }
+
+void gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_t *kdim, hipStream_t s)
+{
+    k_gm_begin<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, g, mres, kdim);
+    HTS_LAUNCH_CHECK();
+}
+void gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit, const double *h1,
+                const double *h2, const double *ww, double *H, double *cs, double *sn, double *g, int32_t *kdim,
+                hipStream_t s)
+{
+    k_gm_arnoldi<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, j, mres, maxit, h1, h2, ww, H, cs, sn, g, kdim);
+    HTS_LAUNCH_CHECK();
+}
+void gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g, const int32_t *kdim,
+              double *y, hipStream_t s)
+{
+    k_gm_solve<<<g1(ninst), dim3(64), 0, s>>>(ninst, cyc, mres, H, g, kdim, y);
+    HTS_LAUNCH_CHECK();
+}
+void outer_check(int ninst, int32_t *active, double *S, const double *rr, hipStream_t s)
+{
+    k_outer_check<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, rr);
+    HTS_LAUNCH_CHECK();
+}
+void set_otol(int ninst, const int32_t *active, double *S, const double *bb, int stride, double rtol2, hipStream_t s)
+{
+    k_set_otol<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, bb, stride, rtol2);
+    HTS_LAUNCH_CHECK();
+}
+
+}  // namespace hts

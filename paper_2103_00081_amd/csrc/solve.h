@@ -1,0 +1,173 @@
+// Batches of instances and the solvers that run over them (solve.hip).
+#pragma once
+#include <functional>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+
+namespace hts {
+
+constexpr int CHUNK_LEN = 1024;
+
+template <typename T>
+void launch_apply(int degree, int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork,
+                  const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
+void launch_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s);
+void launch_q1_stencil(const OpDev &op, double *S, hipStream_t s);
+
+// Per-instance operator descriptors of one operator variant (FP64 and FP32).
+struct Tables {
+    int field = 0;
+    std::vector<OpDev> h64, h32;
+    DBuf<OpDev> d64, d32;
+};
+
+// One multigrid level of a batch (level 0 is the matrix-free fine level).
+struct Level {
+    int64_t ntot = 0;
+    std::vector<int> dims;                 // NX, NY, NZ per instance
+    std::vector<int64_t> off, soff;        // instance offsets (vectors, stencils)
+    std::vector<LevelDev> h64;
+    DBuf<LevelDev> g64, g32;
+    std::vector<Chunk> hch;
+    DBuf<Chunk> ch;
+    const Chunk *ch_ext = nullptr;         // chunk list used by kernels (level 0: the batch's)
+    int nch = 0;
+    DBuf<int32_t> segp, segi;
+    RedCtx red{};
+    DBuf<double> S64;
+    DBuf<float> S32;
+    DBuf<double> invd64, x64, xb64, b64, d64, t64;
+    DBuf<float> invd32, x32, xb32, b32, d32, t32;
+    DBuf<double> cheb;                     // [ninst][NSLOT] Chebyshev coefficients
+};
+
+struct Hier {
+    int field = 0;
+    int deg = 2;
+    double dt = -1.0;
+    Tables ops;                            // fine-level operator
+    std::vector<Level> lev;
+    std::vector<DBuf<double>> Ainv;
+    DBuf<CoarseDev> cd;
+    int64_t crows = 0;
+    std::vector<double> lmax;
+};
+
+struct FieldStats {
+    std::vector<int> status, iters, outer;
+    std::vector<double> relres;
+    double ms = 0.0;
+};
+
+struct Batch {
+    std::vector<hts_mesh *> m;
+    int n = 0, p = 1, device = 0;
+    hipStream_t s = nullptr;
+    Alloc *al = nullptr;
+    std::vector<int64_t> off;
+    int64_t ntot = 0;
+    int zc_override = 0;
+
+    std::vector<Chunk> hch;
+    DBuf<Chunk> ch;
+    int nch = 0;
+    DBuf<int32_t> chp, chi;
+    RedCtx rch{};
+    std::vector<WorkItem> hwork;
+    DBuf<WorkItem> work;
+    int nwork = 0;
+    DBuf<int32_t> wkp, wki;
+    RedCtx rwk{};
+
+    DBuf<double> S;
+    DBuf<int32_t> active;
+    double *hS = nullptr;
+    int32_t *hact = nullptr;
+    DBuf<double> partial, redout, redout2, redout3;
+
+    DBuf<double> Pn, Tn, P1, T1, g, b, x, r, z, pp, q, rold, y, ld0, ld1, inner_b, inner_x;
+    DBuf<float> P32, b32, x32, r32, z32, p32, q32, rold32, y32;
+
+    int gm_m = 0;
+    DBuf<double> V64, Z64, gH, gcs, gsn, gg, gy, gh1, gh2, gww;
+    DBuf<float> V32, Z32;
+    DBuf<int32_t> gkdim;
+
+    DBuf<BcDev> bc[2];
+    DBuf<int64_t> srows[2];
+    DBuf<int32_t> srowptr[2];
+    DBuf<SrcEnt> sents[2];
+    DBuf<SrcDev> ssrc[2];
+    int64_t nsrows[2] = {0, 0};
+    DBuf<SrcDev> lsrc;
+    int nlsrc = 0;
+    DBuf<double> lcoef;
+    std::vector<int> lbase;
+
+    Tables massP, massH, app;
+    int app_field = -1;
+    double app_dt = -1.0;
+    bool app_steady = false;
+    std::map<std::pair<int, double>, std::unique_ptr<Hier>> hier;
+    std::unique_ptr<Hier> heat;
+
+    ~Batch();
+    int pick_zc(int64_t tiles, int NZ) const;
+    void build_work();
+    void make_tables(Tables &t, int field, double dt, bool steady, bool mass_only);
+    Tables &apply_tables(int field, double dt, bool steady)
+    {
+        if (app_field != field || app_dt != dt || app_steady != steady) {
+            make_tables(app, field, dt, steady, false);
+            app_field = field;
+            app_dt = dt;
+            app_steady = steady;
+        }
+        return app;
+    }
+    void upload_S();
+    void download_S();
+    void set_active(const std::vector<int32_t> &a);
+    std::vector<int32_t> get_active();
+    bool any_active();
+    VecCtx vctx(bool use_active = true) const;
+
+    template <typename T> void apply_lvl(Hier &H, int l, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep);
+    template <typename T> void apply_op(const Tables &t, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep);
+
+    void estimate_lmax(Hier &H, int l, std::vector<double> &lmax);
+    void build_smoother(Hier &H, int l, int steps, double ratio);
+    void build_hierarchy(Hier &H, const hts_solver_opts &o);
+    Hier &pressure_hier(bool steady, double dt, const hts_solver_opts &o);
+    Hier &heat_prec(double dt, const hts_solver_opts &o);
+
+    template <typename T> void smooth(Hier &H, int l, int steps, int first, const T *b, T *&cur, T *&oth);
+    template <typename T> void vcycle(Hier &H, int l, const T *b, T *x);
+    template <typename T> void cheb_prec(Hier &H, const T *b, T *x);
+    template <typename T>
+    int cg(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit, bool flexible,
+           int check_every);
+    template <typename T>
+    void fgmres(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit, int mres,
+                int check_every);
+    void ensure_gmres(int mres);
+
+    FieldStats solve_field(int field, Hier *mg, const Tables &A, double *b64, double *x64, const hts_solver_opts &o,
+                           std::vector<int32_t> participants, Hier *hprec);
+    void set_time(const std::vector<double> &tnew, const std::vector<double> &fscale);
+    void pressure_rhs(Hier &H, bool steady);
+    void heat_rhs(Hier &H);
+    void gather_state();
+    void scatter_state();
+    FieldStats solve_pressure(double dt, bool steady_all, const hts_solver_opts &o);
+    FieldStats solve_heat(double dt, const hts_solver_opts &o);
+    int step(double dt, const hts_solver_opts &o, std::vector<hts_step_stats> *stats);
+};
+
+std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms);
+std::shared_ptr<Batch> solo_batch(hts_mesh *m);
+
+}  // namespace hts

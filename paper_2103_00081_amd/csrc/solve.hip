@@ -1,0 +1,1173 @@
+// Batches of instances, the multigrid hierarchy, the Krylov solvers and the
+// backward-Euler time step (Section 2: P^{n+1} from Eq. 3, then T^{n+1}
+// from Eq. 4 with the Darcy flux of P^{n+1}).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <functional>
+#include <random>
+
+#include "internal.h"
+#include "krylov.h"
+#include "solve.h"
+
+namespace hts {
+
+hts_status guard_call(const std::function<void()> &f);
+
+// ------------------------------------------------------------ helpers
+template <typename T> struct Pick;
+template <> struct Pick<double> {
+    template <typename A, typename B> static double *get(A &a, B &) { return a.p; }
+};
+template <> struct Pick<float> {
+    template <typename A, typename B> static float *get(A &, B &b) { return b.p; }
+};
+#define PK(T, a, b) Pick<T>::get((a), (b))
+
+static void sync(hipStream_t s) { HTS_HIP(hipStreamSynchronize(s)); }
+
+static void build_chunks(const std::vector<int64_t> &off, const std::vector<int64_t> &cnt, int len,
+                         std::vector<Chunk> &ch, std::vector<int32_t> &segp, std::vector<int32_t> &segi)
+{
+    ch.clear(); segp.assign(1, 0); segi.clear();
+    for (size_t i = 0; i < off.size(); i++) {
+        for (int64_t b = 0; b < cnt[i]; b += len) {
+            Chunk c{};
+            c.inst = (int32_t)i;
+            c.beg = off[i] + b;
+            c.end = off[i] + std::min<int64_t>(cnt[i], b + len);
+            segi.push_back((int32_t)ch.size());
+            ch.push_back(c);
+        }
+        segp.push_back((int32_t)segi.size());
+    }
+}
+
+// ----------------------------------------------------------- batch build
+Batch::~Batch()
+{
+    if (hS) (void)hipHostFree(hS);
+    if (hact) (void)hipHostFree(hact);
+}
+
+int Batch::pick_zc(int64_t tiles, int NZ) const
+{
+    if (zc_override > 0) return zc_override;
+    int64_t want = 2048;   // blocks to fill 256 CUs several times over
+    int64_t z = std::max<int64_t>(4, (tiles * NZ) / want);
+    z = std::min<int64_t>(z, 32);
+    return (int)std::min<int64_t>(z, NZ);
+}
+
+void Batch::build_work()
+{
+    std::vector<WorkItem> nat;
+    for (int i = 0; i < n; i++) {
+        hts_mesh *M = m[i];
+        const int own = 15;
+        const int tx = (M->N[0] + own - 1) / own, ty = (M->N[1] + own - 1) / own;
+        const int zc = pick_zc((int64_t)tx * ty, M->N[2]);
+        for (int z0 = 0; z0 < M->N[2]; z0 += zc)
+            for (int y = 0; y < ty; y++)
+                for (int x = 0; x < tx; x++) {
+                    WorkItem w{};
+                    w.inst = i; w.tx = x; w.ty = y; w.z0 = z0; w.z1 = std::min(M->N[2], z0 + zc);
+                    nat.push_back(w);
+                }
+    }
+    // XCD-aware order: block b is dispatched to XCD b % 8; give each XCD a
+    // contiguous run of neighbouring tiles so halos stay in its L2.
+    const int64_t T = (int64_t)nat.size(), per = (T + 7) / 8;
+    hwork.clear();
+    std::vector<int64_t> pos_of(T, -1);   // natural index -> launch position
+    for (int64_t b = 0; b < 8 * per; b++) {
+        int64_t idx = (b % 8) * per + b / 8;
+        if (idx < T) {
+            pos_of[idx] = (int64_t)hwork.size();
+            hwork.push_back(nat[idx]);
+        }
+    }
+    nwork = (int)hwork.size();
+    work.upload(al, hwork, s);
+    // per-instance partial sums are reduced in the natural tile order, so a
+    // batched instance sums exactly like the same instance alone
+    std::vector<int32_t> sp(n + 1, 0), si;
+    for (int i = 0; i < n; i++) {
+        for (int64_t k = 0; k < T; k++)
+            if (nat[k].inst == i) si.push_back((int32_t)pos_of[k]);
+        sp[i + 1] = (int32_t)si.size();
+    }
+    wkp.upload(al, sp, s);
+    wki.upload(al, si, s);
+    rwk = RedCtx{wkp.p, wki.p, n};
+    partial.alloc(al, (size_t)std::max<int64_t>(nwork, nch) * 64 + 64);
+}
+
+std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
+{
+    auto B = std::make_shared<Batch>();
+    B->m = ms;
+    B->n = (int)ms.size();
+    B->p = ms[0]->p;
+    B->s = ms[0]->stream;
+    B->al = &ms[0]->alloc;
+    B->device = ms[0]->desc.device;
+    for (hts_mesh *M : ms) {
+        if (M->p != B->p) throw Error(HTS_ERR_ARG, "all meshes of a batch must have the same degree");
+        if (M->desc.device != B->device) throw Error(HTS_ERR_ARG, "all meshes of a batch must share a device");
+        prepare_mesh(M);
+    }
+    Alloc *al = B->al;
+    hipStream_t s = B->s;
+    const int n = B->n;
+    std::vector<int64_t> cnt(n);
+    B->off.resize(n);
+    int64_t tot = 0;
+    for (int i = 0; i < n; i++) {
+        B->off[i] = tot;
+        cnt[i] = ms[i]->nnode;
+        tot += cnt[i];
+    }
+    B->ntot = tot;
+    std::vector<int32_t> sp, si;
+    build_chunks(B->off, cnt, CHUNK_LEN, B->hch, sp, si);
+    B->nch = (int)B->hch.size();
+    B->ch.upload(al, B->hch, s);
+    B->chp.upload(al, sp, s);
+    B->chi.upload(al, si, s);
+    B->rch = RedCtx{B->chp.p, B->chi.p, n};
+    B->build_work();
+
+    B->S.alloc(al, (size_t)n * NSLOT);
+    B->S.zero(s);
+    B->active.alloc(al, n);
+    HTS_HIP(hipHostMalloc((void **)&B->hS, sizeof(double) * n * NSLOT, hipHostMallocDefault));
+    HTS_HIP(hipHostMalloc((void **)&B->hact, sizeof(int32_t) * n, hipHostMallocDefault));
+    std::memset(B->hS, 0, sizeof(double) * n * NSLOT);
+    B->redout.alloc(al, (size_t)n * 64);
+    B->redout2.alloc(al, (size_t)n * 64);
+    B->redout3.alloc(al, (size_t)n * 64);
+
+    for (DBuf<double> *v : {&B->Pn, &B->Tn, &B->P1, &B->T1, &B->g, &B->b, &B->x, &B->r, &B->z, &B->pp, &B->q,
+                            &B->rold, &B->y, &B->ld0, &B->ld1, &B->inner_b, &B->inner_x}) {
+        v->alloc(al, tot);
+        v->zero(s);
+    }
+    for (DBuf<float> *v : {&B->P32, &B->b32, &B->x32, &B->r32, &B->z32, &B->p32, &B->q32, &B->rold32, &B->y32}) {
+        v->alloc(al, tot);
+        v->zero(s);
+    }
+    // boundary tables, sources, line coefficients, static loads
+    for (int f = 0; f < 2; f++) {
+        std::vector<BcDev> bc(n);
+        std::vector<int64_t> rows;
+        std::vector<int32_t> rowptr(1, 0);
+        std::vector<SrcEnt> ents;
+        std::vector<SrcDev> srcs;
+        for (int i = 0; i < n; i++) {
+            hts_mesh *M = ms[i];
+            BcDev &b = bc[i];
+            std::memset(&b, 0, sizeof(b));
+            for (const FaceSpec &fs : M->bcs[f])
+                if (fs.kind == HTS_BC_DIRICHLET && b.nface < 6) {
+                    b.faces[b.nface] = fs.face;
+                    b.ftf[b.nface] = to_dev(fs.tf);
+                    b.nface++;
+                }
+            b.x0 = M->x0[0]; b.y0 = M->x0[1]; b.z0 = M->x0[2];
+            b.dx = M->L[0] / (M->p * M->n[0]);
+            b.dy = M->L[1] / (M->p * M->n[1]);
+            b.dz = M->L[2] / (M->p * M->n[2]);
+            b.colspec = M->colspec[f].p;
+            b.coltf = M->coltf[f].p;
+            const SrcRows &R = M->src[f];
+            const int sbase = (int)srcs.size();
+            for (SrcDev sd : R.srcs) {
+                sd.inst = i;
+                srcs.push_back(sd);
+            }
+            for (size_t r = 0; r < R.rows.size(); r++) {
+                rows.push_back(B->off[i] + R.rows[r]);
+                for (int e = R.rowptr[r]; e < R.rowptr[r + 1]; e++) {
+                    SrcEnt se = R.ents[e];
+                    se.src += sbase;
+                    ents.push_back(se);
+                }
+                rowptr.push_back((int32_t)ents.size());
+            }
+        }
+        B->bc[f].upload(al, bc, s);
+        B->nsrows[f] = (int64_t)rows.size();
+        B->srows[f].upload(al, rows, s);
+        B->srowptr[f].upload(al, rowptr, s);
+        B->sents[f].upload(al, ents, s);
+        B->ssrc[f].upload(al, srcs, s);
+    }
+    {
+        std::vector<SrcDev> ls;
+        B->lbase.assign(n, 0);
+        for (int i = 0; i < n; i++) {
+            B->lbase[i] = (int)ls.size();
+            for (SrcDev sd : ms[i]->line_srcs) {
+                sd.inst = i;
+                ls.push_back(sd);
+            }
+        }
+        B->nlsrc = (int)ls.size();
+        B->lsrc.upload(al, ls, s);
+        B->lcoef.alloc(al, std::max(1, B->nlsrc));
+        B->lcoef.zero(s);
+    }
+    for (int i = 0; i < n; i++) {
+        HTS_HIP(hipMemcpyAsync(B->ld0.p + B->off[i], ms[i]->load[0].p, cnt[i] * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+        HTS_HIP(hipMemcpyAsync(B->ld1.p + B->off[i], ms[i]->load[1].p, cnt[i] * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    }
+    B->make_tables(B->massP, 0, 1.0, false, true);
+    B->make_tables(B->massH, 1, 1.0, false, true);
+    sync(s);
+    return B;
+}
+
+void Batch::make_tables(Tables &t, int field, double dt, bool steady, bool mass_only)
+{
+    t.h64.resize(n);
+    t.h32.resize(n);
+    for (int i = 0; i < n; i++) {
+        for (int prec = 0; prec < 2; prec++) {
+            OpDev o = make_op(m[i], field, prec == 1, dt, steady, mass_only);
+            o.off = off[i];
+            if (field == 1) {
+                o.P = prec ? (const void *)(P32.p + off[i]) : (const void *)(P1.p + off[i]);
+                o.lcoef = lcoef.p + lbase[i];
+                if (prec) o.rho_g = 0.0;   // P32 holds the piezometric pressure
+            }
+            (prec ? t.h32 : t.h64)[i] = o;
+        }
+    }
+    t.d64.upload(al, t.h64, s);
+    t.d32.upload(al, t.h32, s);
+    t.field = field;
+}
+
+void Batch::upload_S() { HTS_HIP(hipMemcpyAsync(S.p, hS, sizeof(double) * n * NSLOT, hipMemcpyHostToDevice, s)); }
+void Batch::download_S()
+{
+    HTS_HIP(hipMemcpyAsync(hS, S.p, sizeof(double) * n * NSLOT, hipMemcpyDeviceToHost, s));
+    sync(s);
+}
+void Batch::set_active(const std::vector<int32_t> &a)
+{
+    for (int i = 0; i < n; i++) hact[i] = a[i];
+    HTS_HIP(hipMemcpyAsync(active.p, hact, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+}
+std::vector<int32_t> Batch::get_active()
+{
+    HTS_HIP(hipMemcpyAsync(hact, active.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    sync(s);
+    return std::vector<int32_t>(hact, hact + n);
+}
+bool Batch::any_active()
+{
+    auto a = get_active();
+    for (int v : a)
+        if (v) return true;
+    return false;
+}
+VecCtx Batch::vctx(bool use_active) const { return VecCtx{ch.p, nch, use_active ? active.p : nullptr, S.p, s}; }
+
+// --------------------------------------------------------- level operators
+template <typename T>
+void Batch::apply_lvl(Hier &H, int l, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep)
+{
+    if (!ep.active) ep.active = active.p;
+    if (l == 0) {
+        const OpDev *ops = std::is_same<T, double>::value ? H.ops.d64.p : H.ops.d32.p;
+        launch_apply<T>(p, H.field, epi, masked, ops, work.p, nwork, x, y, ep, s);
+    } else {
+        Level &L = H.lev[l];
+        const LevelDev *g = std::is_same<T, double>::value ? L.g64.p : L.g32.p;
+        launch_stencil<T>(epi, g, L.ch_ext, L.nch, ep.active, x, y, ep, s);
+    }
+}
+
+template <typename T>
+void Batch::apply_op(const Tables &t, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep)
+{
+    if (!ep.active) ep.active = active.p;
+    const OpDev *ops = std::is_same<T, double>::value ? t.d64.p : t.d32.p;
+    launch_apply<T>(p, t.field, epi, masked, ops, work.p, nwork, x, y, ep, s);
+}
+
+// ---------------------------------------------------------- hierarchy
+static void invert_dense(std::vector<double> &A, int n)
+{
+    // Gauss-Jordan with partial pivoting, in place
+    std::vector<int> piv(n);
+    for (int i = 0; i < n; i++) piv[i] = i;
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; i++) I[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; c++) {
+        int pr = c;
+        double best = std::fabs(A[(size_t)c * n + c]);
+        for (int r = c + 1; r < n; r++)
+            if (std::fabs(A[(size_t)r * n + c]) > best) { best = std::fabs(A[(size_t)r * n + c]); pr = r; }
+        if (best == 0.0) throw Error(HTS_ERR_BREAKDOWN, "singular coarse-grid operator");
+        if (pr != c)
+            for (int k = 0; k < n; k++) {
+                std::swap(A[(size_t)c * n + k], A[(size_t)pr * n + k]);
+                std::swap(I[(size_t)c * n + k], I[(size_t)pr * n + k]);
+            }
+        const double inv = 1.0 / A[(size_t)c * n + c];
+        for (int k = 0; k < n; k++) {
+            A[(size_t)c * n + k] *= inv;
+            I[(size_t)c * n + k] *= inv;
+        }
+        for (int r = 0; r < n; r++) {
+            if (r == c) continue;
+            const double f = A[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; k++) {
+                A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+                I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
+            }
+        }
+    }
+    A.swap(I);
+}
+
+static void cheb_coeffs(double lmax_est, double ratio, int steps, double *out /* 2*steps */)
+{
+    const double lmax = 1.1 * lmax_est, lmin = lmax / ratio;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho_prev = 1.0 / sigma;
+    out[0] = 0.0;
+    out[1] = 1.0 / theta;
+    for (int k = 1; k < steps; k++) {
+        const double rho = 1.0 / (2.0 * sigma - rho_prev);
+        out[2 * k] = rho * rho_prev;
+        out[2 * k + 1] = 2.0 * rho / delta;
+        rho_prev = rho;
+    }
+}
+
+void Batch::estimate_lmax(Hier &H, int l, std::vector<double> &lmax)
+{
+    Level &L = H.lev[l];
+    // probe vector: the same per instance whatever batch it sits in
+    std::vector<double> hv(L.ntot);
+    for (int i = 0; i < n; i++) {
+        std::mt19937_64 rng(12345 + l);
+        std::uniform_real_distribution<double> U(-1.0, 1.0);
+        const int64_t b0 = l == 0 ? off[i] : L.off[i];
+        const int64_t cnt = l == 0 ? m[i]->nnode : L.h64[i].n;
+        for (int64_t e = 0; e < cnt; e++) hv[b0 + e] = U(rng);
+    }
+    HTS_HIP(hipMemcpyAsync(L.x64.p, hv.data(), L.ntot * sizeof(double), hipMemcpyHostToDevice, s));
+    std::vector<int32_t> all(n, 1);
+    set_active(all);
+    VecCtx v{L.ch_ext, L.nch, active.p, S.p, s};
+    RedCtx rc = L.red;
+    if (l == 0) vmask<double>(v, H.ops.d64.p, L.x64.p, 0.0);
+    EpiArgs<double> ep{};
+    for (int it = 0; it < 12; it++) {
+        apply_lvl<double>(H, l, EPI_STORE, true, L.x64.p, L.t64.p, ep);
+        vjacobi<double>(v, 1.0, -1, L.invd64.p, L.t64.p, L.xb64.p);
+        vdot<double>(v, L.xb64.p, L.xb64.p, nullptr, partial.p);
+        vreduce(rc, partial.p, 2, RED_INVSQRT, S_TMP0, S.p, active.p, 0, 0.0, nullptr, s);
+        vaxpby<double>(v, 1.0, S_TMP1, L.xb64.p, 0.0, -1, L.x64.p);
+    }
+    download_S();
+    lmax.resize(n);
+    for (int i = 0; i < n; i++) lmax[i] = std::sqrt(std::max(hS[(size_t)i * NSLOT + S_TMP0], 1e-300));
+    HTS_HIP(hipMemcpyAsync(hS, S.p, sizeof(double) * n * NSLOT, hipMemcpyDeviceToHost, s));
+    sync(s);
+}
+
+static void level_alloc(Level &L, Alloc *al, hipStream_t s, int64_t ntot)
+{
+    L.ntot = ntot;
+    for (DBuf<double> *v : {&L.x64, &L.xb64, &L.b64, &L.d64, &L.t64, &L.invd64}) { v->alloc(al, ntot); v->zero(s); }
+    for (DBuf<float> *v : {&L.x32, &L.xb32, &L.b32, &L.d32, &L.t32, &L.invd32}) { v->alloc(al, ntot); v->zero(s); }
+}
+
+void Batch::build_smoother(Hier &H, int l, int steps, double ratio)
+{
+    Level &L = H.lev[l];
+    std::vector<double> lm;
+    estimate_lmax(H, l, lm);
+    std::vector<double> c((size_t)n * NSLOT, 0.0);
+    for (int i = 0; i < n; i++) {
+        cheb_coeffs(lm[i], ratio, steps, &c[(size_t)i * NSLOT + S_CHEB]);
+        H.lmax.push_back(lm[i]);
+    }
+    L.cheb.upload(al, c, s);
+}
+
+Hier &Batch::pressure_hier(bool steady, double dt, const hts_solver_opts &o)
+{
+    auto key = std::make_pair(steady ? 1 : 0, steady ? 0.0 : dt);
+    auto it = hier.find(key);
+    if (it != hier.end()) return *it->second;
+    auto H = std::make_unique<Hier>();
+    H->field = 0;
+    H->deg = std::max(1, std::min(o.cheb_degree, 8));
+    make_tables(H->ops, 0, dt, steady, false);
+    build_hierarchy(*H, o);
+    Hier &ref = *H;
+    hier[key] = std::move(H);
+    return ref;
+}
+
+Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
+{
+    if (heat && heat->dt == dt && heat->deg == std::max(1, std::min(o.heat_cheb_degree, 16))) return *heat;
+    heat = std::make_unique<Hier>();
+    Hier &H = *heat;
+    H.field = 1;
+    H.dt = dt;
+    H.deg = std::max(1, std::min(o.heat_cheb_degree, 16));
+    make_tables(H.ops, 1, dt, false, false);
+    H.lev.resize(1);
+    Level &L = H.lev[0];
+    level_alloc(L, al, s, ntot);
+    L.ch.p = nullptr;
+    L.nch = nch;
+    L.red = rch;
+    L.ch_ext = ch.p;
+    for (int i = 0; i < n; i++) launch_inv_diag(H.ops.h64[i], L.invd64.p + off[i], s);
+    convert_plain(ntot, L.invd64.p, L.invd32.p, s);
+    // the velocity field enters the operator: estimate with the current P1
+    build_smoother(H, 0, H.deg, 30.0);
+    return H;
+}
+
+void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
+{
+    const int coarse_max = std::max(8, o.mg_coarse_max);
+    // level 0
+    H.lev.clear();
+    H.lev.emplace_back();
+    {
+        Level &L = H.lev[0];
+        level_alloc(L, al, s, ntot);
+        L.nch = nch;
+        L.red = rch;
+        L.ch_ext = ch.p;
+        std::vector<LevelDev> g(n);
+        for (int i = 0; i < n; i++) {
+            g[i].NX = m[i]->N[0]; g[i].NY = m[i]->N[1]; g[i].NZ = m[i]->N[2];
+            g[i].off = off[i]; g[i].n = m[i]->nnode; g[i].S = nullptr;
+        }
+        L.h64 = g;
+        L.g64.upload(al, g, s);
+        L.g32.upload(al, g, s);
+        for (int i = 0; i < n; i++) launch_inv_diag(H.ops.h64[i], L.invd64.p + off[i], s);
+        convert_plain(ntot, L.invd64.p, L.invd32.p, s);
+        L.dims.resize(3 * n);
+        for (int i = 0; i < n; i++)
+            for (int d = 0; d < 3; d++) L.dims[3 * i + d] = m[i]->N[d];
+    }
+    // coarse levels
+    for (int lev = 1; lev < 16; lev++) {
+        const Level &F = H.lev[lev - 1];
+        int64_t maxn = 0;
+        bool shrink = false;
+        for (int i = 0; i < n; i++) {
+            int64_t nn = (int64_t)F.dims[3 * i] * F.dims[3 * i + 1] * F.dims[3 * i + 2];
+            maxn = std::max(maxn, nn);
+            for (int d = 0; d < 3; d++) shrink |= F.dims[3 * i + d] > 2;
+        }
+        if (maxn <= coarse_max || !shrink) break;
+        H.lev.emplace_back();
+        Level &C = H.lev.back();
+        const Level &Fl = H.lev[lev - 1];
+        C.dims.resize(3 * n);
+        std::vector<int64_t> coff(n), ccnt(n);
+        int64_t ctot = 0;
+        for (int i = 0; i < n; i++) {
+            int64_t nn = 1;
+            for (int d = 0; d < 3; d++) {
+                int cells_f = Fl.dims[3 * i + d] - 1;
+                int cells_c = (cells_f + 1) / 2;
+                // Q2 -> Q1 on the same cells is the first coarsening of a Q2 mesh
+                C.dims[3 * i + d] = cells_c + 1;
+                nn *= cells_c + 1;
+            }
+            coff[i] = ctot;
+            ccnt[i] = nn;
+            ctot += nn;
+        }
+        level_alloc(C, al, s, ctot);
+        std::vector<int32_t> sp, si;
+        build_chunks(coff, ccnt, CHUNK_LEN, C.hch, sp, si);
+        C.nch = (int)C.hch.size();
+        C.ch.upload(al, C.hch, s);
+        C.segp.upload(al, sp, s);
+        C.segi.upload(al, si, s);
+        C.red = RedCtx{C.segp.p, C.segi.p, n};
+        C.ch_ext = C.ch.p;
+        C.S64.alloc(al, (size_t)27 * ctot);
+        C.S32.alloc(al, (size_t)27 * ctot);
+        // stencils: Galerkin P^T A P from the finer level
+        for (int i = 0; i < n; i++) {
+            const int fN[3] = {Fl.dims[3 * i], Fl.dims[3 * i + 1], Fl.dims[3 * i + 2]};
+            const int cN[3] = {C.dims[3 * i], C.dims[3 * i + 1], C.dims[3 * i + 2]};
+            double *Sc = C.S64.p + 27 * coff[i];
+            if (lev == 1) {
+                if (p == 1) {
+                    DBuf<double> Sf;
+                    Sf.alloc(al, (size_t)27 * m[i]->nnode);
+                    launch_q1_stencil(H.ops.h64[i], Sf.p, s);
+                    launch_rap(fN[0], fN[1], fN[2], Sf.p, cN[0], cN[1], cN[2], Sc, s);
+                    sync(s);
+                } else {
+                    // p-coarsening: the Q1 operator on the same cells
+                    OpDev q1 = H.ops.h64[i];
+                    q1.p = 1;
+                    q1.NX = cN[0]; q1.NY = cN[1]; q1.NZ = cN[2];
+                    q1.nnode = ccnt[i];
+                    q1.dcol = nullptr;
+                    q1.lcol = nullptr;
+                    launch_q1_stencil(q1, Sc, s);
+                }
+            } else {
+                const double *Sf = Fl.S64.p + 27 * Fl.soff[i];
+                launch_rap(fN[0], fN[1], fN[2], Sf, cN[0], cN[1], cN[2], Sc, s);
+            }
+            C.soff.push_back(coff[i]);
+            launch_stencil_invdiag(Sc, ccnt[i], C.invd64.p + coff[i], s);
+        }
+        convert_plain((int64_t)27 * ctot, C.S64.p, C.S32.p, s);
+        convert_plain(ctot, C.invd64.p, C.invd32.p, s);
+        std::vector<LevelDev> g64(n), g32(n);
+        for (int i = 0; i < n; i++) {
+            LevelDev g{};
+            g.NX = C.dims[3 * i]; g.NY = C.dims[3 * i + 1]; g.NZ = C.dims[3 * i + 2];
+            g.off = coff[i]; g.n = ccnt[i];
+            g.S = C.S64.p + 27 * coff[i];
+            g64[i] = g;
+            g.S = C.S32.p + 27 * coff[i];
+            g32[i] = g;
+        }
+        C.h64 = g64;
+        C.g64.upload(al, g64, s);
+        C.g32.upload(al, g32, s);
+        C.off = coff;
+        sync(s);
+    }
+    // coarsest: dense inverse
+    {
+        Level &C = H.lev.back();
+        if (H.lev.size() == 1) throw Error(HTS_ERR_UNSUPPORTED, "mesh too small for multigrid");
+        std::vector<CoarseDev> cd(n);
+        int64_t row0 = 0;
+        H.Ainv.clear();
+        for (int i = 0; i < n; i++) {
+            const int64_t nn = C.h64[i].n;
+            std::vector<double> st((size_t)27 * nn);
+            HTS_HIP(hipMemcpy(st.data(), C.S64.p + 27 * C.off[i], st.size() * sizeof(double), hipMemcpyDeviceToHost));
+            const int NX = C.h64[i].NX, NY = C.h64[i].NY, NZ = C.h64[i].NZ;
+            std::vector<double> A((size_t)nn * nn, 0.0);
+            for (int64_t r = 0; r < nn; r++) {
+                int i0 = (int)(r % NX), j0 = (int)((r / NX) % NY), k0 = (int)(r / ((int64_t)NX * NY));
+                for (int c = 0; c < 27; c++) {
+                    int a = i0 + c % 3 - 1, b = j0 + (c / 3) % 3 - 1, d = k0 + c / 9 - 1;
+                    if (a < 0 || a >= NX || b < 0 || b >= NY || d < 0 || d >= NZ) continue;
+                    A[(size_t)r * nn + a + (int64_t)NX * (b + (int64_t)NY * d)] += st[(size_t)c * nn + r];
+                }
+            }
+            invert_dense(A, (int)nn);
+            H.Ainv.emplace_back();
+            H.Ainv.back().upload(al, A, s);
+            cd[i].Ainv = H.Ainv.back().p;
+            cd[i].n = nn;
+            cd[i].off = C.off[i];
+            cd[i].row0 = row0;
+            row0 += nn;
+        }
+        H.crows = row0;
+        H.cd.upload(al, cd, s);
+    }
+    // smoothers
+    for (size_t l = 0; l + 1 < H.lev.size(); l++) build_smoother(H, (int)l, 2 * H.deg, 15.0);
+    sync(s);
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <typename T>
+void Batch::smooth(Hier &H, int l, int steps, int first, const T *b, T *&cur, T *&oth)
+{
+    Level &L = H.lev[l];
+    EpiArgs<T> ep{};
+    ep.b = b;
+    ep.d = PK(T, L.d64, L.d32);
+    ep.invd = PK(T, L.invd64, L.invd32);
+    ep.S = L.cheb.p;
+    for (int k = 0; k < steps; k++) {
+        ep.s1 = S_CHEB + 2 * (first + k);
+        ep.s2 = ep.s1 + 1;
+        apply_lvl<T>(H, l, EPI_CHEB, true, cur, oth, ep);
+        std::swap(cur, oth);
+    }
+}
+
+template <typename T>
+void Batch::vcycle(Hier &H, int l, const T *b, T *x)
+{
+    Level &L = H.lev[l];
+    const int last = (int)H.lev.size() - 1;
+    if (l == last) {
+        launch_coarse_solve<T>(H.cd.p, n, H.crows, active.p, b, x, s);
+        return;
+    }
+    const int deg = H.deg;
+    T *xb = PK(T, L.xb64, L.xb32);
+    T *cur = xb, *oth = x;   // 2*deg - 1 swaps end in x
+    VecCtx v{L.ch_ext, L.nch, active.p, L.cheb.p, s};
+    launch_cheb0<T>(L.ch_ext, L.nch, active.p, L.cheb.p, S_CHEB + 1, PK(T, L.invd64, L.invd32), b,
+                    PK(T, L.d64, L.d32), cur, s);
+    smooth<T>(H, l, deg - 1, 1, b, cur, oth);
+    // residual, restriction, coarse correction
+    EpiArgs<T> ep{};
+    ep.b = b;
+    T *t = PK(T, L.t64, L.t32);
+    apply_lvl<T>(H, l, EPI_RESID, true, cur, t, ep);
+    Level &C = H.lev[l + 1];
+    const OpDev *fops = (l == 0) ? H.ops.d64.p : nullptr;
+    launch_restrict<T>(L.g64.p, C.g64.p, fops, C.ch_ext, C.nch, active.p, t, PK(T, C.b64, C.b32), s);
+    vcycle<T>(H, l + 1, PK(T, C.b64, C.b32), PK(T, C.x64, C.x32));
+    launch_prolong_add<T>(L.g64.p, C.g64.p, fops, L.ch_ext, L.nch, active.p, PK(T, C.x64, C.x32), cur, s);
+    // post-smoothing restarts the Chebyshev recurrence (first coefficient pair has c1 = 0)
+    smooth<T>(H, l, deg, 0, b, cur, oth);
+    if (cur != x) {
+        VecCtx vc{L.ch_ext, L.nch, active.p, S.p, s};
+        vcopy<T>(vc, cur, x);
+    }
+    (void)v;
+}
+
+template <typename T>
+void Batch::cheb_prec(Hier &H, const T *b, T *x)
+{
+    Level &L = H.lev[0];
+    const int deg = H.deg;
+    T *xb = PK(T, L.xb64, L.xb32);
+    T *cur = ((deg - 1) % 2 == 0) ? x : xb;
+    T *oth = (cur == x) ? xb : x;
+    launch_cheb0<T>(L.ch_ext, L.nch, active.p, L.cheb.p, S_CHEB + 1, PK(T, L.invd64, L.invd32), b,
+                    PK(T, L.d64, L.d32), cur, s);
+    smooth<T>(H, 0, deg - 1, 1, b, cur, oth);
+}
+
+// ------------------------------------------------------------------- CG
+template <typename T>
+int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit,
+              bool flexible, int check_every)
+{
+    T *r = PK(T, this->r, r32), *z = PK(T, this->z, z32), *pv = PK(T, pp, p32), *q = PK(T, this->q, q32);
+    T *ro = flexible ? PK(T, rold, rold32) : nullptr;
+    VecCtx v = vctx();
+    EpiArgs<T> ep{};
+    ep.b = b;
+    ep.partial = partial.p;
+    apply_op<T>(A, EPI_RESID_NORM, true, x, r, ep);
+    vreduce(rwk, partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+    if (!any_active()) return 0;
+    M(r, z);
+    vdot<T>(v, r, z, nullptr, partial.p);
+    vreduce(rch, partial.p, 2, RED_STORE, S_RZ, S.p, active.p, 0, 0.0, nullptr, s);
+    vcopy<T>(v, z, pv);
+    int it = 0;
+    for (it = 1; it <= maxit; it++) {
+        EpiArgs<T> e2{};
+        e2.partial = partial.p;
+        apply_op<T>(A, EPI_DOT, true, pv, q, e2);
+        vreduce(rwk, partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+        vcg_update<T>(v, x, r, pv, q, ro, partial.p);
+        vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+        if (it % std::max(1, check_every) == 0 || it == maxit)
+            if (!any_active()) break;
+        M(r, z);
+        vdot<T>(v, z, r, ro, partial.p);
+        vreduce(rch, partial.p, 2, RED_CG_BETA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+        vaxpby<T>(v, 1.0, -1, z, 1.0, S_BETA, pv);
+    }
+    return it;
+}
+
+// ---------------------------------------------------------------- FGMRES
+template <typename T>
+void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit,
+                   int mres, int check_every)
+{
+    ensure_gmres(mres);
+    T *V = PK(T, V64, V32), *Z = PK(T, Z64, Z32);
+    const int64_t ld = ntot;
+    VecCtx v = vctx();
+    std::vector<int32_t> participating = get_active();
+    for (int cycle = 0; cycle < 1000; cycle++) {
+        EpiArgs<T> ep{};
+        ep.b = b;
+        ep.partial = partial.p;
+        apply_op<T>(A, EPI_RESID_NORM, true, x, V, ep);
+        vreduce(rwk, partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
+        gm_begin(n, active.p, S.p, gg.p, mres, gkdim.p, s);
+        std::vector<int32_t> cyc = get_active();
+        bool any = false;
+        for (int a : cyc) any |= a != 0;
+        if (!any) break;
+        vaxpby<T>(v, 1.0, S_SCALE, V, 0.0, -1, V);
+        for (int j = 0; j < mres; j++) {
+            T *Vj = V + (int64_t)j * ld, *w = V + (int64_t)(j + 1) * ld, *Zj = Z + (int64_t)j * ld;
+            M(Vj, Zj);
+            EpiArgs<T> e2{};
+            apply_op<T>(A, EPI_STORE, true, Zj, w, e2);
+            vmultidot<T>(v, V, ld, j + 1, w, partial.p, j + 1);
+            vreduce(rch, partial.p, j + 1, RED_NONE, 0, S.p, active.p, 0, 0.0, gh1.p, s);
+            vorth_update<T>(v, V, ld, j + 1, gh1.p, j + 1, w, 1, partial.p, j + 2);
+            vreduce(rch, partial.p, j + 2, RED_NONE, 0, S.p, active.p, 0, 0.0, gh2.p, s);
+            vorth_update<T>(v, V, ld, j + 1, gh2.p, j + 2, w, 0, partial.p, 1);
+            vreduce(rch, partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, gww.p, s);
+            gm_arnoldi(n, active.p, S.p, j, mres, maxit, gh1.p, gh2.p, gww.p, gH.p, gcs.p, gsn.p, gg.p, gkdim.p, s);
+            vaxpby<T>(v, 1.0, S_SCALE, w, 0.0, -1, w);
+            if ((j + 1) % std::max(1, check_every) == 0 || j == mres - 1)
+                if (!any_active()) break;
+        }
+        // x += Z y for every instance that took part in this cycle
+        set_active(cyc);
+        gm_solve(n, active.p, mres, gH.p, gg.p, gkdim.p, gy.p, s);
+        vbasis_update<T, T>(v, Z, ld, gkdim.p, gy.p, mres, 1.0, -1, x);
+        download_S();
+        std::vector<int32_t> again(n, 0);
+        bool more = false;
+        for (int i = 0; i < n; i++) {
+            if (cyc[i] && hS[(size_t)i * NSLOT + S_STATUS] == 1.0) {
+                again[i] = 1;
+                more = true;
+            }
+        }
+        set_active(again);
+        if (!more) break;
+    }
+    (void)participating;
+}
+
+void Batch::ensure_gmres(int mres)
+{
+    if (gm_m == mres) return;
+    gm_m = mres;
+    V64.alloc(al, (size_t)(mres + 1) * ntot);
+    Z64.alloc(al, (size_t)mres * ntot);
+    V32.alloc(al, (size_t)(mres + 1) * ntot);
+    Z32.alloc(al, (size_t)mres * ntot);
+    V64.zero(s); Z64.zero(s); V32.zero(s); Z32.zero(s);
+    gH.alloc(al, (size_t)n * (mres + 1) * mres);
+    gcs.alloc(al, (size_t)n * mres);
+    gsn.alloc(al, (size_t)n * mres);
+    gg.alloc(al, (size_t)n * (mres + 1));
+    gy.alloc(al, (size_t)n * mres);
+    gh1.alloc(al, (size_t)n * (mres + 2));
+    gh2.alloc(al, (size_t)n * (mres + 2));
+    gww.alloc(al, (size_t)n * 2);
+    gkdim.alloc(al, n);
+    gkdim.zero(s);
+}
+
+// ---------------------------------------------------- field solve (outer)
+// FP64 defect correction around an inner Krylov solve in FP64 or FP32:
+//   r = b - A64 x;  stop when ||r|| <= rtol ||b||;  d ~ A^{-1} (r / ||r||);
+//   x += ||r|| d.  The outer test is the true FP64 residual of every mode.
+FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64, double *x64,
+                              const hts_solver_opts &o, std::vector<int32_t> participants, Hier *hprec)
+{
+    FieldStats st;
+    st.status.assign(n, 1);
+    st.iters.assign(n, 0);
+    st.outer.assign(n, 0);
+    st.relres.assign(n, 0.0);
+    const bool fp32 = o.mode == HTS_MODE_FP32_REFINED;
+    const double rtol = o.rtol > 0 ? o.rtol : 1e-8;
+    const int maxit = std::max(1, o.max_iter);
+    hipEvent_t e0, e1;
+    HTS_HIP(hipEventCreate(&e0));
+    HTS_HIP(hipEventCreate(&e1));
+    HTS_HIP(hipEventRecord(e0, s));
+    set_active(participants);
+    VecCtx vall = vctx();
+    vdot<double>(vall, b64, b64, nullptr, partial.p);
+    vreduce(rch, partial.p, 2, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
+    set_otol(n, active.p, S.p, redout.p, 2, rtol * rtol, s);
+    std::vector<int32_t> outer = participants;
+    int total_inner = 0;
+    for (int oit = 0; oit < 40; oit++) {
+        set_active(outer);
+        EpiArgs<double> ep{};
+        ep.b = b64;
+        ep.partial = partial.p;
+        apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
+        vreduce(rwk, partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
+        outer_check(n, active.p, S.p, redout.p, s);
+        outer = get_active();
+        bool any = false;
+        for (int a : outer) any |= a != 0;
+        if (!any) break;
+        for (int i = 0; i < n; i++)
+            if (outer[i]) st.outer[i]++;
+        // inner system: A d = r / ||r||
+        const double fl = fp32 ? std::pow(std::max(o.inner_rtol, 1e-6), 2) : 0.0;
+        set_inner_tol(n, active.p, S.p, fl, 0.25, s);
+        VecCtx v = vctx();
+        if (fp32) {
+            vconvert<double, float>(v, 1.0, S_OINV, this->y.p, b32.p);
+            vfill<float>(v, x32.p, 0.0f);
+            auto M = [&](const float *r_, float *z_) {
+                if (mg) vcycle<float>(*mg, 0, r_, z_);
+                else cheb_prec<float>(*hprec, r_, z_);
+            };
+            if (field == 0) cg<float>(A, M, b32.p, x32.p, maxit, false, o.check_every);
+            else fgmres<float>(A, M, b32.p, x32.p, maxit, std::max(2, std::min(o.gmres_restart, 60)), o.check_every);
+        } else {
+            // inner RHS r / ||r||; the Krylov work vectors are r, z, pp, q, rold
+            vaxpby<double>(v, 1.0, S_OINV, this->y.p, 0.0, -1, inner_b.p);
+            vfill<double>(v, inner_x.p, 0.0);
+            auto M = [&](const double *r_, double *z_) {
+                if (mg) vcycle<double>(*mg, 0, r_, z_);
+                else cheb_prec<double>(*hprec, r_, z_);
+            };
+            if (field == 0)
+                cg<double>(A, M, inner_b.p, inner_x.p, maxit, false, o.check_every);
+            else
+                fgmres<double>(A, M, inner_b.p, inner_x.p, maxit, std::max(2, std::min(o.gmres_restart, 60)),
+                               o.check_every);
+        }
+        download_S();
+        for (int i = 0; i < n; i++)
+            if (outer[i]) {
+                st.iters[i] += (int)hS[(size_t)i * NSLOT + S_ITER];
+                total_inner += (int)hS[(size_t)i * NSLOT + S_ITER];
+                const double ist = hS[(size_t)i * NSLOT + S_STATUS];
+                if (ist == -6.0) st.status[i] = -6;
+            }
+        set_active(outer);
+        if (fp32) vadd_scaled<float>(vctx(), 1.0, S_ONORM, x32.p, x64);
+        else vadd_scaled<double>(vctx(), 1.0, S_ONORM, inner_x.p, x64);
+        bool stop = true;
+        for (int i = 0; i < n; i++)
+            if (outer[i] && st.status[i] != -6 && st.iters[i] < maxit) stop = false;
+        if (stop) {
+            // final judge with the last update
+            apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
+            vreduce(rwk, partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
+            outer_check(n, active.p, S.p, redout.p, s);
+            outer = get_active();
+            break;
+        }
+    }
+    HTS_HIP(hipEventRecord(e1, s));
+    download_S();
+    float ms = 0.0f;
+    HTS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st.ms = ms;
+    for (int i = 0; i < n; i++) {
+        if (!participants[i]) { st.status[i] = 0; continue; }
+        const double orr = hS[(size_t)i * NSLOT + S_ORR], obb = hS[(size_t)i * NSLOT + S_OBB];
+        st.relres[i] = obb > 0 ? std::sqrt(orr / obb) : std::sqrt(orr);
+        const double os = hS[(size_t)i * NSLOT + S_OSTATUS];
+        if (st.status[i] == -6 || os == -6.0) st.status[i] = HTS_ERR_BREAKDOWN;
+        else if (os == 0.0) st.status[i] = HTS_OK;
+        else st.status[i] = HTS_ERR_NOT_CONVERGED;
+    }
+    (void)total_inner;
+    return st;
+}
+
+// ------------------------------------------------------------- one step
+void Batch::set_time(const std::vector<double> &tnew, const std::vector<double> &fscale)
+{
+    download_S();
+    for (int i = 0; i < n; i++) {
+        hS[(size_t)i * NSLOT + S_TNEW] = tnew[i];
+        hS[(size_t)i * NSLOT + S_FSCALE] = fscale[i];
+    }
+    upload_S();
+}
+
+void Batch::pressure_rhs(Hier &H, bool steady)
+{
+    std::vector<int32_t> all(n, 1);
+    set_active(all);
+    VecCtx v = vctx(false);
+    launch_dirichlet_values(H.ops.d64.p, bc[0].p, ch.p, nch, S.p, g.p, s);
+    EpiArgs<double> ep{};
+    if (!steady) apply_op<double>(massP, EPI_STORE, false, Pn.p, b.p, ep);
+    else vfill<double>(v, b.p, 0.0);
+    apply_op<double>(H.ops, EPI_STORE, false, g.p, y.p, ep);
+    vaxpby<double>(v, -1.0, -1, y.p, 1.0, -1, b.p);
+    vaxpby<double>(v, 1.0, S_FSCALE, ld0.p, 1.0, -1, b.p);
+    launch_sources(srows[0].p, srowptr[0].p, sents[0].p, nsrows[0], ssrc[0].p, S.p, b.p, s);
+    vmask<double>(v, H.ops.d64.p, b.p, 0.0);
+}
+
+void Batch::heat_rhs(Hier &H)
+{
+    std::vector<int32_t> all(n, 1);
+    set_active(all);
+    VecCtx v = vctx(false);
+    launch_source_values(lsrc.p, nlsrc, S.p, lcoef.p, s);
+    launch_dirichlet_values(H.ops.d64.p, bc[1].p, ch.p, nch, S.p, g.p, s);
+    EpiArgs<double> ep{};
+    apply_op<double>(massH, EPI_STORE, false, Tn.p, b.p, ep);
+    apply_op<double>(H.ops, EPI_STORE, false, g.p, y.p, ep);
+    vaxpby<double>(v, -1.0, -1, y.p, 1.0, -1, b.p);
+    vaxpby<double>(v, 1.0, S_FSCALE, ld1.p, 1.0, -1, b.p);
+    launch_sources(srows[1].p, srowptr[1].p, sents[1].p, nsrows[1], ssrc[1].p, S.p, b.p, s);
+    vmask<double>(v, H.ops.d64.p, b.p, 0.0);
+}
+
+void Batch::gather_state()
+{
+    for (int i = 0; i < n; i++) {
+        HTS_HIP(hipMemcpyAsync(Pn.p + off[i], m[i]->P.p, m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HTS_HIP(hipMemcpyAsync(Tn.p + off[i], m[i]->T.p, m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+}
+
+void Batch::scatter_state()
+{
+    for (int i = 0; i < n; i++) {
+        HTS_HIP(hipMemcpyAsync(m[i]->P.p, Pn.p + off[i], m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HTS_HIP(hipMemcpyAsync(m[i]->T.p, Tn.p + off[i], m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    sync(s);
+}
+
+// Solve the pressure of every instance at t_i + dt into P1 (steady or transient).
+FieldStats Batch::solve_pressure(double dt, bool steady_all, const hts_solver_opts &o)
+{
+    std::vector<double> tn(n), fs(n);
+    bool steady = steady_all;
+    for (int i = 0; i < n; i++) {
+        const bool st_i = steady_all || m[i]->B <= 0.0;
+        if (i > 0 && st_i != steady) throw Error(HTS_ERR_UNSUPPORTED, "mixed steady/transient pressure in a batch");
+        steady = st_i;
+    }
+    for (int i = 0; i < n; i++) {
+        tn[i] = m[i]->t + (steady_all ? 0.0 : dt);
+        fs[i] = steady ? 1.0 : dt * m[i]->B;
+    }
+    set_time(tn, fs);
+    Hier &H = pressure_hier(steady, dt, o);
+    pressure_rhs(H, steady);
+    VecCtx v = vctx(false);
+    vcopy<double>(v, Pn.p, x.p);
+    vmask<double>(v, H.ops.d64.p, x.p, 0.0);
+    std::vector<int32_t> all(n, 1);
+    FieldStats st = solve_field(0, &H, H.ops, b.p, x.p, o, all, nullptr);
+    std::vector<int32_t> a(n, 1);
+    set_active(a);
+    vaxpby<double>(vctx(false), 1.0, -1, x.p, 0.0, -1, P1.p);
+    vaxpby<double>(vctx(false), 1.0, -1, g.p, 1.0, -1, P1.p);
+    return st;
+}
+
+FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
+{
+    std::vector<double> tn(n), fs(n);
+    for (int i = 0; i < n; i++) {
+        tn[i] = m[i]->t + dt;
+        fs[i] = dt;
+    }
+    set_time(tn, fs);
+    std::vector<int32_t> all(n, 1);
+    set_active(all);
+    VecCtx v = vctx(false);
+    vpiezo32(v, massH.d64.p, P1.p, P32.p);
+    // line coefficients before the preconditioner setup reads the operator
+    launch_source_values(lsrc.p, nlsrc, S.p, lcoef.p, s);
+    Hier &H = heat_prec(dt, o);
+    heat_rhs(H);
+    vcopy<double>(v, Tn.p, x.p);
+    vmask<double>(v, H.ops.d64.p, x.p, 0.0);
+    FieldStats st = solve_field(1, nullptr, H.ops, b.p, x.p, o, all, &H);
+    set_active(all);
+    vaxpby<double>(vctx(false), 1.0, -1, x.p, 0.0, -1, T1.p);
+    vaxpby<double>(vctx(false), 1.0, -1, g.p, 1.0, -1, T1.p);
+    return st;
+}
+
+// One backward-Euler step for every instance; commits only when all solves
+// of all instances converged.
+int Batch::step(double dt, const hts_solver_opts &o, std::vector<hts_step_stats> *stats)
+{
+    FieldStats sp = solve_pressure(dt, false, o);
+    FieldStats sh = solve_heat(dt, o);
+    int rc = HTS_OK;
+    for (int i = 0; i < n; i++) {
+        if (sp.status[i] != HTS_OK) rc = rc == HTS_OK ? sp.status[i] : rc;
+        if (sh.status[i] != HTS_OK) rc = rc == HTS_OK ? sh.status[i] : rc;
+    }
+    if (stats) {
+        stats->resize(n);
+        for (int i = 0; i < n; i++) {
+            hts_step_stats &x = (*stats)[i];
+            std::memset(&x, 0, sizeof(x));
+            x.iters[0] = sp.iters[i]; x.iters[1] = sh.iters[i];
+            x.outer[0] = sp.outer[i]; x.outer[1] = sh.outer[i];
+            x.relres[0] = sp.relres[i]; x.relres[1] = sh.relres[i];
+            x.status[0] = sp.status[i]; x.status[1] = sh.status[i];
+            x.time_ms[0] = sp.ms; x.time_ms[1] = sh.ms;
+            x.fallbacks = 0;
+        }
+    }
+    if (rc == HTS_OK) {
+        std::vector<int32_t> all(n, 1);
+        set_active(all);
+        VecCtx v = vctx(false);
+        vcopy<double>(v, P1.p, Pn.p);
+        vcopy<double>(v, T1.p, Tn.p);
+        for (int i = 0; i < n; i++) m[i]->t += dt;
+    }
+    sync(s);
+    return rc;
+}
+
+std::shared_ptr<Batch> solo_batch(hts_mesh *m)
+{
+    prepare_mesh(m);
+    auto it = m->batches.find("solo");
+    if (it != m->batches.end()) return it->second;
+    auto B = build_batch({m});
+    m->batches["solo"] = B;
+    return B;
+}
+
+template void Batch::vcycle<double>(Hier &, int, const double *, double *);
+template void Batch::vcycle<float>(Hier &, int, const float *, float *);
+
+}  // namespace hts
+
+// =================================================================== C ABI
+using namespace hts;
+
+static hts_solver_opts opts_or_default(const hts_solver_opts *o)
+{
+    hts_solver_opts d;
+    hts_default_opts(&d);
+    return o ? *o : d;
+}
+
+static void check_ready(hts_mesh *m)
+{
+    if (!m) throw Error(HTS_ERR_ARG, "null mesh");
+    if (!m->has_mat) throw Error(HTS_ERR_STATE, "materials not set");
+}
+
+extern "C" {
+
+hts_status hts_apply_operator(hts_mesh *m, hts_field field, hts_precision prec, double dt, const void *x_dev,
+                              void *y_dev)
+{
+    return guard_call([&] {
+        check_ready(m);
+        if (field != 0 && field != 1) throw Error(HTS_ERR_ARG, "bad field");
+        if (prec != HTS_FP64 && prec != HTS_FP32) throw Error(HTS_ERR_ARG, "bad precision");
+        if (!x_dev || !y_dev || x_dev == y_dev) throw Error(HTS_ERR_ARG, "x and y must be distinct device buffers");
+        HTS_HIP(hipSetDevice(m->desc.device));
+        auto B = solo_batch(m);
+        Batch &b = *B;
+        std::vector<int32_t> all(1, 1);
+        b.set_active(all);
+        const bool steady = field == 0 && (dt <= 0.0 || m->B <= 0.0);
+        Tables &t = b.apply_tables(field, dt, steady);
+        if (field == 1) {
+            HTS_HIP(hipMemcpyAsync(b.P1.p, m->P.p, m->nnode * sizeof(double), hipMemcpyDeviceToDevice, b.s));
+            VecCtx v = b.vctx(false);
+            vpiezo32(v, b.massH.d64.p, b.P1.p, b.P32.p);
+            std::vector<double> tn(1, m->t + dt), fs(1, dt);
+            b.set_time(tn, fs);
+            launch_source_values(b.lsrc.p, b.nlsrc, b.S.p, b.lcoef.p, b.s);
+        }
+        if (prec == HTS_FP64) {
+            EpiArgs<double> ep{};
+            b.apply_op<double>(t, EPI_STORE, true, (const double *)x_dev, (double *)y_dev, ep);
+        } else {
+            EpiArgs<float> ep{};
+            b.apply_op<float>(t, EPI_STORE, true, (const float *)x_dev, (float *)y_dev, ep);
+        }
+    });
+}
+
+hts_status hts_solve_steady_pressure(hts_mesh *m, const hts_solver_opts *opts, hts_step_stats *stats)
+{
+    return guard_call([&] {
+        check_ready(m);
+        HTS_HIP(hipSetDevice(m->desc.device));
+        hts_solver_opts o = opts_or_default(opts);
+        if (o.mode == HTS_MODE_LEARNED) o.mode = HTS_MODE_FP64;
+        auto B = solo_batch(m);
+        B->gather_state();
+        FieldStats st = B->solve_pressure(0.0, true, o);
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->iters[0] = st.iters[0];
+            stats->outer[0] = st.outer[0];
+            stats->relres[0] = st.relres[0];
+            stats->status[0] = st.status[0];
+            stats->time_ms[0] = st.ms;
+        }
+        if (st.status[0] != HTS_OK) throw Error(st.status[0], "steady pressure solve failed");
+        HTS_HIP(hipMemcpyAsync(m->P.p, B->P1.p, m->nnode * sizeof(double), hipMemcpyDeviceToDevice, B->s));
+        HTS_HIP(hipStreamSynchronize(B->s));
+        m->has_state[0] = true;
+    });
+}
+
+hts_status hts_solve_step(hts_mesh *m, double dt, const hts_solver_opts *opts, hts_step_stats *stats)
+{
+    return guard_call([&] {
+        check_ready(m);
+        if (!(dt > 0.0)) throw Error(HTS_ERR_ARG, "dt must be > 0");
+        HTS_HIP(hipSetDevice(m->desc.device));
+        hts_solver_opts o = opts_or_default(opts);
+        auto B = solo_batch(m);
+        B->gather_state();
+        std::vector<hts_step_stats> st;
+        int rc = B->step(dt, o, &st);
+        if (stats) *stats = st[0];
+        if (rc == HTS_OK) B->scatter_state();
+        if (rc != HTS_OK) throw Error(rc, "time step did not converge");
+    });
+}
+
+hts_status hts_advance(hts_mesh *const *meshes, int32_t n, int32_t n_steps, double dt, const hts_solver_opts *opts,
+                       hts_step_stats *stats)
+{
+    return guard_call([&] {
+        if (!meshes || n < 1) throw Error(HTS_ERR_ARG, "no meshes");
+        if (n_steps < 0) throw Error(HTS_ERR_ARG, "n_steps must be >= 0");
+        if (!(dt > 0.0)) throw Error(HTS_ERR_ARG, "dt must be > 0");
+        std::vector<hts_mesh *> ms(meshes, meshes + n);
+        for (hts_mesh *m : ms) check_ready(m);
+        HTS_HIP(hipSetDevice(ms[0]->desc.device));
+        hts_solver_opts o = opts_or_default(opts);
+        std::shared_ptr<Batch> B = n == 1 ? solo_batch(ms[0]) : build_batch(ms);
+        B->gather_state();
+        std::vector<hts_step_stats> st;
+        int rc = HTS_OK;
+        for (int k = 0; k < n_steps; k++) {
+            rc = B->step(dt, o, &st);
+            if (rc != HTS_OK) break;
+        }
+        B->scatter_state();
+        if (stats && !st.empty())
+            for (int i = 0; i < n; i++) stats[i] = st[i];
+        if (rc != HTS_OK) throw Error(rc, "a time step did not converge");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// Host-side interface of the batched vector kernels (vec.hip).
+#pragma once
+#include "common.h"
+
+namespace hts {
+
+struct VecCtx {
+    const Chunk *chunks;       // device chunk list of the batch vectors
+    int nchunk;
+    const int32_t *active;     // per-instance flags (null = all)
+    const double *S;           // per-instance scalar slots
+    hipStream_t stream;
+};
+
+// Segments of partial-sum indices per instance (for k_reduce).
+struct RedCtx {
+    const int32_t *seg_ptr;    // [ninst + 1]
+    const int32_t *seg_idx;
+    int nseg;                  // = ninst
+};
+
+enum RedOp {
+    RED_NONE = 0,
+    RED_STORE = 1,             // S[slot] = v0
+    RED_STORE2 = 2,            // S[slot] = v0, S[slot+1] = v1
+    RED_CG_ALPHA = 3,          // PQ = v0, ALPHA = RZ / PQ
+    RED_CG_CONV = 4,           // RR = v0, ITER++, convergence / breakdown flags
+    RED_CG_BETA = 5,           // BETA = (v0 - v1) / RZ, RZ = v0
+    RED_CG_INIT = 6,           // RR = RR0 = v0, ITER = 0, converged if RR <= TOL2
+    RED_SET_TOL = 7,           // BB = v0, TOL2 = aux * v0
+    RED_INVSQRT = 8            // S[slot] = v0, S[slot+1] = 1/sqrt(v0)
+};
+
+template <typename T> void vfill(const VecCtx &v, T *y, T val);
+template <typename T> void vcopy(const VecCtx &v, const T *x, T *y);
+// y = a x + b y, a = sa*S[ia] (ia >= 0) or sa; same for b.
+template <typename T> void vaxpby(const VecCtx &v, double a, int ia, const T *x, double b, int ib, T *y);
+// z = c d .* r
+template <typename T> void vjacobi(const VecCtx &v, double c, int ic, const T *d, const T *r, T *z);
+// partial[2 blk] = x.y, partial[2 blk + 1] = x.w (if w)
+template <typename T> void vdot(const VecCtx &v, const T *x, const T *y, const T *w, double *partial);
+template <typename T>
+void vcg_update(const VecCtx &v, T *x, T *r, const T *p, const T *q, T *r_old, double *partial);
+template <typename T>
+void vmultidot(const VecCtx &v, const T *V, int64_t ld, int nv, const T *w, double *partial, int ncomp);
+template <typename T>
+void vorth_update(const VecCtx &v, const T *V, int64_t ld, int nv, const double *H, int hld, T *w, int dots,
+                  double *partial, int ncomp);
+template <typename T, typename TX>
+void vbasis_update(const VecCtx &v, const T *Z, int64_t ld, const int32_t *kdim, const double *Y, int yld,
+                   double scale, int iscale, TX *x);
+template <typename TX, typename TY> void vconvert(const VecCtx &v, double sc, int ic, const TX *x, TY *y);
+template <typename T> void vadd_scaled(const VecCtx &v, double sc, int ic, const T *d, double *x);
+template <typename T> void vmask(const VecCtx &v, const OpDev *ops, T *y, T val);
+
+// P32 = (P - P[node 0 of the instance]) + rho_w g z (FP32 heat operator input)
+void vpiezo32(const VecCtx &v, const OpDev *ops64, const double *P, float *P32);
+
+void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
+             int maxit, double aux, double *out, hipStream_t s);
+
+}  // namespace hts

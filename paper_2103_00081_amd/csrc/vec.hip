@@ -1,0 +1,452 @@
+// Vector kernels of the Krylov solvers over batched (concatenated) vectors.
+//
+// A batch vector holds the nodes of all instances back to back.  It is cut
+// into chunks that never straddle an instance; one 256-thread block handles
+// one chunk, so per-instance scalars (alpha, beta, ...) are read once per
+// block.  Dot products are two-stage and deterministic: each block writes
+// one FP64 partial per component, then k_reduce sums an instance's partials
+// in a fixed order and applies the solver's scalar update.  Inactive
+// (converged) instances are skipped by every kernel.
+#include "common.h"
+#include "dev_util.h"
+#include "vec.h"
+
+namespace hts {
+
+namespace {
+
+constexpr int VB = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return r;
+}
+
+#define CHUNK_PROLOGUE                                                   \
+    const Chunk ch = chunks[blockIdx.x];                                 \
+    if (active && !active[ch.inst]) return;                              \
+    const double *Si = S + (int64_t)ch.inst * NSLOT;                     \
+    (void)Si;
+
+template <typename T>
+__global__ __launch_bounds__(VB) void k_fill(const Chunk *__restrict__ chunks, const int32_t *active,
+                                             const double *S, T *__restrict__ y, T v)
+{
+    CHUNK_PROLOGUE
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(VB) void k_copy(const Chunk *__restrict__ chunks, const int32_t *active,
+                                             const double *S, const T *__restrict__ x, T *__restrict__ y)
+{
+    CHUNK_PROLOGUE
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = x[e];
+}
+
+// y = a * x + b * y with a = sa * S[ia] (ia < 0: a = sa), same for b
+template <typename T>
+__global__ __launch_bounds__(VB) void k_axpby(const Chunk *__restrict__ chunks, const int32_t *active,
+                                              const double *S, double sa, int ia, const T *__restrict__ x,
+                                              double sb, int ib, T *__restrict__ y)
+{
+    CHUNK_PROLOGUE
+    const T a = T(ia >= 0 ? sa * Si[ia] : sa);
+    const T b = T(ib >= 0 ? sb * Si[ib] : sb);
+    if (b == T(0)) {
+        for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = a * x[e];
+    } else {
+        for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = a * x[e] + b * y[e];
+    }
+}
+
+// z = d .* r (Jacobi)
+template <typename T>
+__global__ __launch_bounds__(VB) void k_jacobi(const Chunk *__restrict__ chunks, const int32_t *active,
+                                               const double *S, double c, int ic, const T *__restrict__ d,
+                                               const T *__restrict__ r, T *__restrict__ z)
+{
+    CHUNK_PROLOGUE
+    const T a = T(ic >= 0 ? c * Si[ic] : c);
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) z[e] = a * d[e] * r[e];
+}
+
+// partial[blk*2 + 0] = x.y (and partial[blk*2+1] = x.w if w)
+template <typename T>
+__global__ __launch_bounds__(VB) void k_dot(const Chunk *__restrict__ chunks, const int32_t *active,
+                                            const double *S, const T *__restrict__ x, const T *__restrict__ y,
+                                            const T *__restrict__ w, double *partial)
+{
+    __shared__ double sh[4];
+    CHUNK_PROLOGUE
+    double a = 0.0, b = 0.0;
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        const double xe = (double)x[e];
+        a += xe * (double)y[e];
+        if (w) b += xe * (double)w[e];
+    }
+    a = block_sum(a, sh);
+    if (w) b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = a;
+        partial[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// CG: x += alpha p; r -= alpha q; (r_old = r before); partial = r.r
+template <typename T>
+__global__ __launch_bounds__(VB) void k_cg_update(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                  const double *S, T *__restrict__ x, T *__restrict__ r,
+                                                  const T *__restrict__ p, const T *__restrict__ q,
+                                                  T *__restrict__ r_old, double *partial)
+{
+    __shared__ double sh[4];
+    CHUNK_PROLOGUE
+    const T al = T(Si[S_ALPHA]);
+    double a = 0.0;
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        x[e] += al * p[e];
+        T re = r[e];
+        if (r_old) r_old[e] = re;
+        re -= al * q[e];
+        r[e] = re;
+        a += (double)re * (double)re;
+    }
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) partial[2 * blockIdx.x] = a;
+}
+
+// GMRES: multi-dot h_i = V_i . w for i < nv (V_i = V + i*ld)
+template <typename T>
+__global__ __launch_bounds__(VB) void k_multidot(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                 const double *S, const T *__restrict__ V, int64_t ld,
+                                                 int nv, const T *__restrict__ w, double *partial,
+                                                 int ncomp)
+{
+    __shared__ double sh[4];
+    CHUNK_PROLOGUE
+    for (int i = 0; i < nv; i++) {
+        const T *Vi = V + (int64_t)i * ld;
+        double a = 0.0;
+        for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) a += (double)Vi[e] * (double)w[e];
+        a = block_sum(a, sh);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncomp + i] = a;
+    }
+}
+
+// GMRES: w -= sum_i h_i V_i (h per instance: H + inst*hld), then partials of
+// V_i . w (i < nv, if dots) and w . w (component nv, or 0 without dots).
+template <typename T>
+__global__ __launch_bounds__(VB) void k_orth_update(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                    const double *S, const T *__restrict__ V, int64_t ld,
+                                                    int nv, const double *__restrict__ H, int hld,
+                                                    T *__restrict__ w, int dots, double *partial,
+                                                    int ncomp)
+{
+    __shared__ double sh[4];
+    __shared__ double hs[64];
+    CHUNK_PROLOGUE
+    if (threadIdx.x < nv) hs[threadIdx.x] = H[(int64_t)ch.inst * hld + threadIdx.x];
+    __syncthreads();
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        double acc = (double)w[e];
+        for (int i = 0; i < nv; i++) acc -= hs[i] * (double)V[(int64_t)i * ld + e];
+        w[e] = T(acc);
+    }
+    __syncthreads();
+    if (dots) {
+        for (int i = 0; i < nv; i++) {
+            const T *Vi = V + (int64_t)i * ld;
+            double a = 0.0;
+            for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) a += (double)Vi[e] * (double)w[e];
+            a = block_sum(a, sh);
+            if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncomp + i] = a;
+        }
+    }
+    double a = 0.0;
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) a += (double)w[e] * (double)w[e];
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncomp + (dots ? nv : 0)] = a;
+}
+
+// x += sum_{i < kdim[inst]} y_i Z_i   (y per instance: Y + inst*yld)
+template <typename T, typename TX>
+__global__ __launch_bounds__(VB) void k_basis_update(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                     const double *S, const T *__restrict__ Z, int64_t ld,
+                                                     const int32_t *kdim, const double *__restrict__ Yc,
+                                                     int yld, double scale, int iscale, TX *__restrict__ x)
+{
+    __shared__ double ys[64];
+    const Chunk ch = chunks[blockIdx.x];
+    if (active && !active[ch.inst]) return;
+    const int kd = kdim[ch.inst];
+    const double sc = iscale >= 0 ? scale * S[(int64_t)ch.inst * NSLOT + iscale] : scale;
+    if (threadIdx.x < kd) ys[threadIdx.x] = Yc[(int64_t)ch.inst * yld + threadIdx.x] * sc;
+    __syncthreads();
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        double acc = 0.0;
+        for (int i = 0; i < kd; i++) acc += ys[i] * (double)Z[(int64_t)i * ld + e];
+        x[e] = TX((double)x[e] + acc);
+    }
+}
+
+// y (type TY) = c * x (type TX), c = sc * S[ic] or sc
+template <typename TX, typename TY>
+__global__ __launch_bounds__(VB) void k_convert(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                const double *S, double sc, int ic, const TX *__restrict__ x,
+                                                TY *__restrict__ y)
+{
+    CHUNK_PROLOGUE
+    const double c = ic >= 0 ? sc * Si[ic] : sc;
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = TY(c * (double)x[e]);
+}
+
+// x (FP64) += c * d (type T)
+template <typename T>
+__global__ __launch_bounds__(VB) void k_add_scaled(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                   const double *S, double sc, int ic, const T *__restrict__ d,
+                                                   double *__restrict__ x)
+{
+    CHUNK_PROLOGUE
+    const double c = ic >= 0 ? sc * Si[ic] : sc;
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) x[e] += c * (double)d[e];
+}
+
+// y[n] = v at constrained nodes of instance (n in chunk), others untouched
+template <typename T>
+__global__ __launch_bounds__(VB) void k_mask(const Chunk *__restrict__ chunks, const int32_t *active,
+                                             const double *S, const OpDev *__restrict__ ops,
+                                             T *__restrict__ y, T v)
+{
+    CHUNK_PROLOGUE
+    const OpDev &o = ops[ch.inst];
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB)
+        if (node_constrained(o, e - o.off)) y[e] = v;
+}
+
+// FP32 pressure for the heat operator in piezometric form:
+// P32 = (P - P[node 0]) + rho_w g z, so that q = -k grad(P32) without the
+// cancellation between grad P and rho_w g e_z.
+__global__ __launch_bounds__(VB) void k_piezo32(const Chunk *__restrict__ chunks, const OpDev *__restrict__ ops,
+                                                const double *__restrict__ P, float *__restrict__ P32)
+{
+    const Chunk ch = chunks[blockIdx.x];
+    const OpDev &o = ops[ch.inst];
+    const double ref = P[o.off];
+    const double dz = o.hz / o.p;
+    const int64_t pl = (int64_t)o.NX * o.NY;
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        const int64_t k = (e - o.off) / pl;
+        P32[e] = (float)((P[e] - ref) + o.rho_g * (k * dz));
+    }
+}
+
+// ---------------------------------------------------------------- reduce
+__device__ void scalar_op(int op, int inst, const double *v, double *S, int32_t *active, int maxit,
+                          int slot, double aux)
+{
+    double *Si = S + (int64_t)inst * NSLOT;
+    auto stop = [&](int status) {
+        Si[S_STATUS] = status;
+        if (active) active[inst] = 0;
+    };
+    switch (op) {
+    case RED_STORE:
+        Si[slot] = v[0];
+        break;
+    case RED_STORE2:
+        Si[slot] = v[0];
+        Si[slot + 1] = v[1];
+        break;
+    case RED_CG_ALPHA: {
+        const double pq = v[0];
+        Si[S_PQ] = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            Si[S_ALPHA] = 0.0;
+            stop(-6);
+        } else {
+            Si[S_ALPHA] = Si[S_RZ] / pq;
+        }
+        break;
+    }
+    case RED_CG_CONV: {
+        const double rr = v[0];
+        Si[S_RR] = rr;
+        Si[S_ITER] += 1.0;
+        if (!isfinite(rr)) stop(-6);
+        else if (rr <= Si[S_TOL2]) stop(0);
+        else if (Si[S_ITER] >= maxit) stop(-5);
+        break;
+    }
+    case RED_CG_BETA: {   // v0 = z.r (new), v1 = z.r_old (flexible)
+        const double rzn = v[0];
+        const double num = rzn - v[1];
+        const double rz = Si[S_RZ];
+        Si[S_BETA] = (rz != 0.0 && isfinite(num)) ? num / rz : 0.0;
+        Si[S_RZ] = rzn;
+        if (!isfinite(rzn)) stop(-6);
+        break;
+    }
+    case RED_SET_TOL:     // v0 = b.b; aux = rtol^2
+        Si[S_BB] = v[0];
+        Si[S_TOL2] = aux * v[0];
+        break;
+    case RED_INVSQRT:     // S[slot] = v0, S[slot+1] = 1/sqrt(v0)
+        Si[slot] = v[0];
+        Si[slot + 1] = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
+        break;
+    case RED_CG_INIT: {   // v0 = r.r of the initial residual
+        Si[S_RR] = v[0];
+        Si[S_RR0] = v[0];
+        Si[S_ITER] = 0.0;
+        Si[S_STATUS] = 1.0;
+        if (!isfinite(v[0])) stop(-6);
+        else if (v[0] <= Si[S_TOL2]) stop(0);
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+__global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partial, int ncomp,
+                                               const int32_t *__restrict__ seg_ptr,
+                                               const int32_t *__restrict__ seg_idx, int op, int slot,
+                                               double *S, int32_t *active, int maxit, double aux,
+                                               double *out)
+{
+    __shared__ double sh[4];
+    __shared__ double vals[64];
+    const int inst = blockIdx.x;
+    if (active && !active[inst]) return;
+    const int b = seg_ptr[inst], e = seg_ptr[inst + 1];
+    for (int c = 0; c < ncomp; c++) {
+        double a = 0.0;
+        for (int t = b + threadIdx.x; t < e; t += VB) a += partial[(int64_t)seg_idx[t] * ncomp + c];
+        a = block_sum(a, sh);
+        if (threadIdx.x == 0) vals[c] = a;
+    }
+    if (threadIdx.x == 0) {
+        if (out)
+            for (int c = 0; c < ncomp; c++) out[(int64_t)inst * ncomp + c] = vals[c];
+        scalar_op(op, inst, vals, S, active, maxit, slot, aux);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host API
+#define GRID dim3((unsigned)v.nchunk), dim3(VB), 0, v.stream
+
+template <typename T>
+void vfill(const VecCtx &v, T *y, T val) { k_fill<T><<<GRID>>>(v.chunks, v.active, v.S, y, val); HTS_LAUNCH_CHECK(); }
+template <typename T>
+void vcopy(const VecCtx &v, const T *x, T *y) { k_copy<T><<<GRID>>>(v.chunks, v.active, v.S, x, y); HTS_LAUNCH_CHECK(); }
+template <typename T>
+void vaxpby(const VecCtx &v, double a, int ia, const T *x, double b, int ib, T *y)
+{
+    k_axpby<T><<<GRID>>>(v.chunks, v.active, v.S, a, ia, x, b, ib, y);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T>
+void vjacobi(const VecCtx &v, double c, int ic, const T *d, const T *r, T *z)
+{
+    k_jacobi<T><<<GRID>>>(v.chunks, v.active, v.S, c, ic, d, r, z);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T>
+void vdot(const VecCtx &v, const T *x, const T *y, const T *w, double *partial)
+{
+    k_dot<T><<<GRID>>>(v.chunks, v.active, v.S, x, y, w, partial);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T>
+void vcg_update(const VecCtx &v, T *x, T *r, const T *p, const T *q, T *r_old, double *partial)
+{
+    k_cg_update<T><<<GRID>>>(v.chunks, v.active, v.S, x, r, p, q, r_old, partial);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T>
+void vmultidot(const VecCtx &v, const T *V, int64_t ld, int nv, const T *w, double *partial, int ncomp)
+{
+    k_multidot<T><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, w, partial, ncomp);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T>
+void vorth_update(const VecCtx &v, const T *V, int64_t ld, int nv, const double *H, int hld, T *w, int dots,
+                  double *partial, int ncomp)
+{
+    k_orth_update<T><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, H, hld, w, dots, partial, ncomp);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T, typename TX>
+void vbasis_update(const VecCtx &v, const T *Z, int64_t ld, const int32_t *kdim, const double *Y, int yld,
+                   double scale, int iscale, TX *x)
+{
+    k_basis_update<T, TX><<<GRID>>>(v.chunks, v.active, v.S, Z, ld, kdim, Y, yld, scale, iscale, x);
+    HTS_LAUNCH_CHECK();
+}
+template <typename TX, typename TY>
+void vconvert(const VecCtx &v, double sc, int ic, const TX *x, TY *y)
+{
+    k_convert<TX, TY><<<GRID>>>(v.chunks, v.active, v.S, sc, ic, x, y);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T>
+void vadd_scaled(const VecCtx &v, double sc, int ic, const T *d, double *x)
+{
+    k_add_scaled<T><<<GRID>>>(v.chunks, v.active, v.S, sc, ic, d, x);
+    HTS_LAUNCH_CHECK();
+}
+template <typename T>
+void vmask(const VecCtx &v, const OpDev *ops, T *y, T val)
+{
+    k_mask<T><<<GRID>>>(v.chunks, v.active, v.S, ops, y, val);
+    HTS_LAUNCH_CHECK();
+}
+
+void vpiezo32(const VecCtx &v, const OpDev *ops64, const double *P, float *P32)
+{
+    k_piezo32<<<GRID>>>(v.chunks, ops64, P, P32);
+    HTS_LAUNCH_CHECK();
+}
+
+void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
+             int maxit, double aux, double *out, hipStream_t s)
+{
+    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, r.seg_idx, op, slot, S,
+                                                          active, maxit, aux, out);
+    HTS_LAUNCH_CHECK();
+}
+
+#define INST(T)                                                                                          \
+    template void vfill<T>(const VecCtx &, T *, T);                                                      \
+    template void vcopy<T>(const VecCtx &, const T *, T *);                                              \
+    template void vaxpby<T>(const VecCtx &, double, int, const T *, double, int, T *);                   \
+    template void vjacobi<T>(const VecCtx &, double, int, const T *, const T *, T *);                    \
+    template void vdot<T>(const VecCtx &, const T *, const T *, const T *, double *);                    \
+    template void vcg_update<T>(const VecCtx &, T *, T *, const T *, const T *, T *, double *);          \
+    template void vmultidot<T>(const VecCtx &, const T *, int64_t, int, const T *, double *, int);       \
+    template void vorth_update<T>(const VecCtx &, const T *, int64_t, int, const double *, int, T *, int, \
+                                  double *, int);                                                        \
+    template void vbasis_update<T, double>(const VecCtx &, const T *, int64_t, const int32_t *,          \
+                                           const double *, int, double, int, double *);                 \
+    template void vbasis_update<T, float>(const VecCtx &, const T *, int64_t, const int32_t *,           \
+                                          const double *, int, double, int, float *);                   \
+    template void vadd_scaled<T>(const VecCtx &, double, int, const T *, double *);                      \
+    template void vmask<T>(const VecCtx &, const OpDev *, T *, T);
+INST(double)
+INST(float)
+template void vconvert<double, float>(const VecCtx &, double, int, const double *, float *);
+template void vconvert<float, double>(const VecCtx &, double, int, const float *, double *);
+template void vconvert<double, double>(const VecCtx &, double, int, const double *, double *);
+template void vconvert<float, float>(const VecCtx &, double, int, const float *, float *);
+
+}  // namespace hts

@@ -1,0 +1,120 @@
+"""Parity of the HIP operator application (hts_apply_operator) with the
+oracle's assembled matrices, element by element.
+
+FP64: |y - y_oracle| <= 1e-13 max|y_oracle| (rounding of a ~200-term sum).
+FP32: |y - y_oracle|_i <= 64 eps32 (|A| |x|)_i, the forward error bound of an
+inner product evaluated in single precision (coefficients, inputs and the
+accumulation each rounded once; 64 covers the sum length).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from gpu_util import print_case, to_dev
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = np.finfo(np.float32).eps
+
+
+def small_cases():
+    c = []
+    c.append(("c1", synth.config1()))
+    c.append(("c2_small", synth.config2(ncells=(20, 18, 9), n_steps=1)))
+    c.append(("c3_small", synth.config3(ncells=(33, 17, 12), n_steps=1)))
+    c.append(("c4_small", synth.config4_instance(3, n_override=19, n_steps=1)))
+    s = synth.config2(ncells=(17, 9, 5), n_steps=1)
+    s.name = "odd_17x9x5"
+    c.append((s.name, s))
+    return c
+
+
+def _mesh(hts, scn):
+    return hts.from_scenario(scn, initial=False)
+
+
+def _oracle_reduced(scn, field, P=None, steady=None):
+    m = oracle.Mesh.of(scn)
+    A = oracle.operator(scn, field, P=P, steady=steady)
+    mask, g = oracle.dirichlet(scn, m, field, scn.t0 + scn.dt)
+    return A, mask
+
+
+@pytest.mark.parametrize("name,scn", small_cases(), ids=[c[0] for c in small_cases()])
+@pytest.mark.parametrize("field", [0, 1])
+def test_apply_parity(hts, name, scn, field):
+    import torch
+    print_case("apply", name, "field", field)
+    m = _mesh(hts, scn)
+    om = oracle.Mesh.of(scn)
+    rng = np.random.default_rng(11)
+    P = None
+    if field == 1:
+        X, Y, Z = om.coords()
+        # a pressure field with a realistic gradient (hydrostatic + drop + noise)
+        P = 1e5 + scn.rho_w * scn.g * (scn.extent[2] - Z) - 20.0 * X + 5.0 * rng.standard_normal(om.nnode)
+        m.set_state(0, P, scn.t0)
+    A, mask = _oracle_reduced(scn, field, P=P)
+    x = rng.standard_normal(om.nnode)
+    y_ref = oracle.reduced_apply(A, mask, x)
+    for prec in (0, 1):
+        dt = "float64" if prec == 0 else "float32"
+        xd = to_dev(x, dt)
+        yd = torch.zeros_like(xd)
+        m.apply_operator(field, prec, scn.dt, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.double().cpu().numpy()
+        if prec == 0:
+            tol = 1e-13 * np.abs(y_ref).max()
+            err = np.abs(y - y_ref)
+            assert err.max() <= tol, (name, field, err.max() / np.abs(y_ref).max())
+        else:
+            if field == 1:
+                # the FP32 heat operator reads the pressure as the FP32-rounded
+                # piezometric head P + rho_w g z (relative to node 0); the
+                # reference uses that same rounded pressure in FP64
+                NX, NY = om.dims[0], om.dims[1]
+                kz = np.arange(om.nnode) // (NX * NY)
+                dz = scn.extent[2] / (scn.degree * scn.ncells[2])
+                rg = scn.rho_w * scn.g
+                phi32 = ((P - P[0]) + rg * (kz * dz)).astype(np.float32)
+                Pt = phi32.astype(np.float64) - rg * (kz * dz) + P[0]
+                A, _ = _oracle_reduced(scn, field, P=Pt)
+                y_ref = oracle.reduced_apply(A, mask, x)
+            Aabs = abs(A.tocsr())
+            xm = np.where(mask, 0.0, np.abs(x))
+            bound = 64 * EPS32 * (Aabs @ xm)
+            bound = np.where(mask, EPS32 * np.abs(x), bound) + 1e-30
+            err = np.abs(y - y_ref)
+            assert np.all(err <= bound), (name, field, np.max(err / bound))
+
+
+def test_apply_steady_pressure(hts):
+    scn = synth.config1()
+    print_case("apply steady c1")
+    import torch
+    m = _mesh(hts, scn)
+    A, mask = _oracle_reduced(scn, 0, steady=True)
+    x = np.random.default_rng(3).standard_normal(m.nnode)
+    y_ref = oracle.reduced_apply(A, mask, x)
+    xd = to_dev(x)
+    yd = torch.zeros_like(xd)
+    m.apply_operator(0, 0, 0.0, xd, yd)          # dt <= 0 selects the steady operator
+    torch.cuda.synchronize()
+    assert np.abs(yd.cpu().numpy() - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
+
+
+def test_apply_is_bitwise_reproducible(hts):
+    import torch
+    scn = synth.config2(ncells=(20, 18, 9), n_steps=1)
+    print_case("apply reproducible")
+    m = _mesh(hts, scn)
+    x = to_dev(np.random.default_rng(5).standard_normal(m.nnode))
+    y1 = torch.zeros_like(x)
+    y2 = torch.zeros_like(x)
+    m.apply_operator(1, 0, scn.dt, x, y1)
+    m.apply_operator(1, 0, scn.dt, x, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)

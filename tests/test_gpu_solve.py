@@ -1,0 +1,162 @@
+"""Solver parity of the HIP time stepping with the oracle.
+
+Parity mode: the GPU solves to a tight residual (1e-12) and the oracle solves
+to the FP64 floor.  Forward error <= kappa * residual, and these small cases
+have kappa well below 1e2 (heat, mass dominated) or about 1e3 (pressure), so
+the FP64 bound is 1e-10 relative.  The mixed-precision path is judged by the
+same true FP64 residual; its bounds are 1e-6 K (temperature, max abs) and
+1e-8 relative (pressure).  The backward error of every GPU answer is also
+checked in the oracle's own CSR matrices.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import print_case
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def run_gpu(hts, scn, steps, **opt):
+    o = hts.default_opts(**opt)
+    m = hts.from_scenario(scn, opts=o)
+    stats = []
+    for _ in range(steps):
+        code, st = m.solve_step(scn.dt, o)
+        stats.append(st)
+    P, t = m.get_state(0)
+    T, _ = m.get_state(1)
+    return m, P, T, t, stats
+
+
+def test_c1_steady_pressure_exact(hts):
+    print_case("c1 steady pressure")
+    scn = synth.config1()
+    m = hts.from_scenario(scn, opts=hts.default_opts(rtol=1e-13))
+    P, _ = m.get_state(0)
+    om = oracle.Mesh.of(scn)
+    X, Y, Z = om.coords()
+    Pex = 1e5 + scn.rho_w * scn.g * (100.0 - Z) + 1e4 * (1.0 - X / 100.0)
+    assert np.abs(P - Pex).max() <= 1e-10 * np.abs(Pex).max()
+
+
+def test_c1_full_run_fp64(hts):
+    print_case("c1 full run fp64")
+    scn = synth.config1()
+    m, P, T, t, stats = run_gpu(hts, scn, scn.n_steps, rtol=1e-13)
+    Po, To, to = oracle.run(scn)
+    print("stats", stats[0], stats[-1])
+    assert t == pytest.approx(to)
+    assert rel(P, Po) <= 1e-10
+    assert rel(T, To) <= 1e-10
+    assert np.abs(T - To).max() <= 1e-8
+    for st in stats:
+        assert st["status"] == [0, 0]
+        assert st["relres"][1] <= 1e-13
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c2_small_steps(hts, mode):
+    """Layered aquifer with a well pair, coarse grid, 3 steps."""
+    print_case("c2 small mode", mode)
+    scn = synth.config2(ncells=(24, 24, 12), n_steps=3)
+    rtol = 1e-12 if mode == 0 else 1e-12
+    m, P, T, t, stats = run_gpu(hts, scn, 3, rtol=rtol, mode=mode)
+    Po, To, to = oracle.run(scn, n_steps=3)
+    print("stats", stats)
+    for st in stats:
+        assert st["status"] == [0, 0], st
+    if mode == 0:
+        assert rel(P, Po) <= 1e-10
+        assert rel(T, To) <= 1e-10
+        assert np.abs(T - To).max() <= 1e-7
+    else:
+        assert rel(P, Po) <= 1e-8
+        assert np.abs(T - To).max() <= 1e-6
+
+
+def test_backward_error_in_oracle_matrices(hts):
+    """The oracle's own CSR residual of the GPU answer meets the tolerance."""
+    print_case("backward error")
+    scn = synth.config2(ncells=(20, 16, 10), n_steps=1)
+    o = hts.default_opts(rtol=1e-8)
+    m = hts.from_scenario(scn, opts=o)
+    P0, _ = m.get_state(0)
+    T0, _ = m.get_state(1)
+    code, st = m.solve_step(scn.dt, o)
+    P1, _ = m.get_state(0)
+    T1, _ = m.get_state(1)
+    om = oracle.Mesh.of(scn)
+    t1 = scn.t0 + scn.dt
+    A, b = oracle.pressure_system(scn, om, P0, t1)
+    mask, g = oracle.dirichlet(scn, om, 0, t1)
+    free, AFF, bF = oracle.eliminate(A, b, mask, g)
+    r = oracle.residual_ld(AFF, bF, P1[free])
+    assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(bF)
+    assert np.abs(P1[mask] - g[mask]).max() == 0.0
+    H, hb = oracle.heat_system(scn, om, T0, P1, t1)
+    mask, g = oracle.dirichlet(scn, om, 1, t1)
+    free, HFF, hF = oracle.eliminate(H, hb, mask, g)
+    r = oracle.residual_ld(HFF, hF, T1[free])
+    assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(hF)
+
+
+def test_c4_instance_dirichlet_columns(hts):
+    print_case("c4 instance")
+    scn = synth.config4_instance(5, n_override=16, n_steps=2)
+    m, P, T, t, stats = run_gpu(hts, scn, 2, rtol=1e-12)
+    Po, To, to = oracle.run(scn, n_steps=2)
+    print("stats", stats)
+    assert rel(P, Po) <= 1e-10
+    assert rel(T, To) <= 1e-10
+    assert np.abs(T - To).max() <= 1e-7
+
+
+def test_c3_small_piles(hts):
+    print_case("c3 small")
+    scn = synth.config3(ncells=(24, 24, 12), n_steps=2)
+    m, P, T, t, stats = run_gpu(hts, scn, 2, rtol=1e-12)
+    Po, To, to = oracle.run(scn, n_steps=2)
+    print("stats", stats)
+    assert rel(P, Po) <= 1e-10
+    assert rel(T, To) <= 1e-10
+    assert np.abs(T - To).max() <= 1e-7
+
+
+def test_not_converged_is_transactional(hts):
+    print_case("transactional")
+    scn = synth.config2(ncells=(16, 16, 8), n_steps=1)
+    o = hts.default_opts(rtol=1e-8)
+    m = hts.from_scenario(scn, opts=o)
+    P0, t0 = m.get_state(0)
+    T0, _ = m.get_state(1)
+    bad = hts.default_opts(rtol=1e-14, max_iter=1)
+    code, st = m.solve_step(scn.dt, bad, raise_on_error=False)
+    assert code == -5
+    P1, t1 = m.get_state(0)
+    T1, _ = m.get_state(1)
+    assert t1 == t0 and np.array_equal(P1, P0) and np.array_equal(T1, T0)
+    # a good step afterwards still works
+    code, st = m.solve_step(scn.dt, o)
+    assert code == 0
+
+
+def test_batched_equals_solo_bitwise(hts):
+    print_case("batched == solo")
+    scns = [synth.config4_instance(i, n_override=n, n_steps=2) for i, n in [(0, 12), (1, 17), (2, 9)]]
+    o = hts.default_opts(rtol=1e-10)
+    solo = []
+    for s in scns:
+        m = hts.from_scenario(s, opts=o)
+        hts.advance([m], 2, s.dt, o)
+        solo.append((m.get_state(0)[0], m.get_state(1)[0]))
+    ms = [hts.from_scenario(s, opts=o) for s in scns]
+    hts.advance(ms, 2, scns[0].dt, o)
+    for m, (P, T) in zip(ms, solo):
+        assert np.array_equal(m.get_state(0)[0], P)
+        assert np.array_equal(m.get_state(1)[0], T)
