@@ -127,6 +127,11 @@ typedef struct {
     int32_t use_graph;       /* replay captured HIP graphs for time steps       */
     hts_nn *nn;              /* network for HTS_MODE_LEARNED                    */
     int32_t verbose;
+    int32_t heat_precond;    /* 0: multigrid V-cycle (Galerkin levels of the
+                                symmetric part M_cT + dt K_lambda, Chebyshev
+                                smoothing with the full heat operator);
+                                1: Chebyshev-Jacobi only (default: the heat
+                                operator is mass dominated)                     */
 } hts_solver_opts;
 
 typedef struct {
@@ -244,6 +249,23 @@ hts_status hts_advance(hts_mesh *const *meshes, int32_t n_instances, int32_t n_s
 /* Time several operator tile shapes on these meshes and keep the fastest
  * per (degree, field, precision, size class) for later launches. */
 hts_status hts_autotune(hts_mesh *const *meshes, int32_t n);
+
+/* Device time and algorithmic traffic of the matrix-free fine-level
+ * operator launches, per [field][precision] class. */
+typedef struct {
+    int64_t launches;   /* launches recorded                                  */
+    double ms;          /* summed device time (HIP events around each launch) */
+    double bytes;       /* algorithmic bytes: every node vector the launch's
+                           epilogue reads or writes once, plus the per-cell
+                           coefficients, at the operator's precision          */
+    double flops;       /* algorithmic floating-point operations              */
+} hts_kernel_times;
+
+/* enable = 1: reset and start recording every fine-level operator launch of
+ * every mesh (adds two events per launch).  enable = 0: stop, wait for the
+ * recorded launches and write the totals to out[field][precision] (out may
+ * be NULL).  Not thread-safe. */
+hts_status hts_kernel_timing(int32_t enable, hts_kernel_times out[2][2]);
 
 const char *hts_last_error(void);
 

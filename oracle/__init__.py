@@ -541,6 +541,26 @@ def step(scn, m: Mesh, P, T, t, **kw):
     return P1, T1, t_new
 
 
+def step_to(scn, m: Mesh, P, T, t, rtol=1e-8):
+    """One step with the plain iterative solvers stopped at a relative
+    residual rtol (Jacobi-PCG for pressure, Jacobi-GMRES(50) for heat), warm
+    started from the previous step.  Returns (P, T, t, iterations)."""
+    t_new = t + scn.dt
+    A, b = pressure_system(scn, m, P, t_new)
+    mask, g = dirichlet(scn, m, PRESSURE, t_new)
+    free, AFF, bF = eliminate(A, b, mask, g)
+    u, itp, rrp = solve_to(AFF, bF, _f64(P)[free], True, rtol)
+    P1 = g.copy()
+    P1[free] = u
+    A, b = heat_system(scn, m, T, P1, t_new)
+    mask, g = dirichlet(scn, m, TEMPERATURE, t_new)
+    free, AFF, bF = eliminate(A, b, mask, g)
+    u, ith, rrh = solve_to(AFF, bF, _f64(T)[free], False, rtol)
+    T1 = g.copy()
+    T1[free] = u
+    return P1, T1, t_new, (itp, ith, rrp, rrh)
+
+
 def run(scn, n_steps: Optional[int] = None, state=None, **kw):
     m = Mesh.of(scn)
     P, T = initial_state(scn, m) if state is None else state[:2]

@@ -32,7 +32,7 @@ EXPORTS = [
     "hts_add_dirichlet_column", "hts_set_state", "hts_get_state", "hts_mesh_sizes",
     "hts_apply_operator", "hts_solve_steady_pressure", "hts_solve_step", "hts_advance",
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
-    "hts_nn_train", "hts_nn_save", "hts_nn_load",
+    "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing",
 ]
 
 
@@ -80,7 +80,7 @@ class SolverOpts(C.Structure):
                 ("gmres_restart", C.c_int32), ("cheb_degree", C.c_int32),
                 ("mg_coarse_max", C.c_int32), ("heat_cheb_degree", C.c_int32),
                 ("inner_rtol", C.c_double), ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("nn", C.c_void_p), ("verbose", C.c_int32)]
+                ("nn", C.c_void_p), ("verbose", C.c_int32), ("heat_precond", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -101,6 +101,11 @@ class NNDesc(C.Structure):
 class TrainStats(C.Structure):
     _fields_ = [("epochs_done", C.c_int32), ("pairs", C.c_int32), ("loss_first", C.c_double),
                 ("loss_last", C.c_double), ("val_loss", C.c_double)]
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
 
 
 _lib = None
@@ -142,6 +147,7 @@ def load():
         "hts_nn_train": (st, [vp, i32, d, i32, P(TrainStats)]),
         "hts_nn_save": (st, [vp, C.c_char_p]),
         "hts_nn_load": (st, [vp, C.c_char_p]),
+        "hts_kernel_timing": (st, [i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -303,6 +309,23 @@ def advance(meshes: Sequence[Mesh], n_steps: int, dt: float, opts=None, raise_on
     if raise_on_error:
         _check(code)
     return code, [s.as_dict() for s in st]
+
+
+def kernel_timing_start():
+    _check(load().hts_kernel_timing(1, None))
+
+
+def kernel_timing_stop():
+    """Totals per (field, precision) of the fine-level operator launches."""
+    out = (KernelTimes * 4)()
+    _check(load().hts_kernel_timing(0, C.cast(out, C.c_void_p)))
+    res = {}
+    for f in range(2):
+        for p in range(2):
+            k = out[2 * f + p]
+            res[(f, p)] = {"launches": k.launches, "ms": k.ms, "bytes": k.bytes,
+                           "flops": k.flops}
+    return res
 
 
 def autotune(meshes: Sequence[Mesh]):

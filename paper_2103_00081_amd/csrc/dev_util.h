@@ -4,6 +4,16 @@
 
 namespace hts {
 
+// Pointers read out of device-resident descriptors are generic; reading
+// through a global-address-space pointer gives global (not flat) loads,
+// which do not count against the LDS wait of a barrier.
+#define HTS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ static const T HTS_GLOBAL *gptr(const void *p)
+{
+    return (const T HTS_GLOBAL *)p;
+}
+
 struct ColInfo {
     int64_t base;   // instance-local index of the node at k = 0
     int valid;
@@ -19,7 +29,7 @@ __device__ __forceinline__ static ColInfo col_info(const OpDev &o, int i, int j)
     const int m = o.dmask;
     c.xyc = c.valid && (((m & 1) && i == 0) || ((m & 2) && i == o.NX - 1) || ((m & 4) && j == 0) ||
                         ((m & 8) && j == o.NY - 1));
-    int packed = (c.valid && o.dcol) ? o.dcol[c.base] : DCOL_NONE;
+    int packed = (c.valid && o.dcol) ? gptr<int32_t>(o.dcol)[c.base] : DCOL_NONE;
     c.dlo = packed & 0xFFFF;
     c.dhi = (packed >> 16) & 0xFFFF;
     return c;

@@ -410,6 +410,7 @@ void hts_default_opts(hts_solver_opts *o)
     o->use_graph = 0;
     o->nn = nullptr;
     o->verbose = 0;
+    o->heat_precond = 1;
 }
 
 hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)

@@ -18,6 +18,7 @@ struct CoarseDev {
     int64_t n;
     int64_t off;               // offset in the coarsest level's batch vectors
     int64_t row0;              // first global row (rows numbered across instances)
+    int32_t inst, pad;         // instance index in the batch
 };
 
 template <typename T>
@@ -34,8 +35,9 @@ void launch_prolong_add(const LevelDev *fine, const LevelDev *coarse, const OpDe
                         int nchunk, const int32_t *active, const T *xc, T *xf, hipStream_t s);
 void launch_rap(int fNX, int fNY, int fNZ, const double *Sf, int cNX, int cNY, int cNZ, double *Sc, hipStream_t s);
 void launch_stencil_invdiag(const double *S, int64_t n, double *out, hipStream_t s);
+// x = Ainv b for the ncd instances listed in cd (rows numbered across them)
 template <typename T>
-void launch_coarse_solve(const CoarseDev *cd, int ninst, int64_t total_rows, const int32_t *active, const T *b,
+void launch_coarse_solve(const CoarseDev *cd, int ncd, int64_t total_rows, const int32_t *active, const T *b,
                          T *x, hipStream_t s);
 
 }  // namespace hts

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ le
     const Chunk ch = chunks[blockIdx.x];
     if (active && !active[ch.inst]) return;
     const LevelDev &L = lev[ch.inst];
-    const T *__restrict__ St = static_cast<const T *>(L.S);
+    const T HTS_GLOBAL *__restrict__ St = gptr<T>(L.S);
     const int NX = L.NX, NY = L.NY, NZ = L.NZ;
     const int64_t pl = (int64_t)NX * NY;
     const T *Xi = X + L.off;
@@ -237,15 +237,15 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const CoarseDev *__restric
 {
     const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, lane = threadIdx.x & 63;
     // find (instance, row) of this wave: rows are numbered across instances
-    int inst = -1;
+    int k = -1;
     int64_t row = 0;
     for (int s = 0; s < ninst; s++) {
-        if (wave >= cd[s].row0 && wave < cd[s].row0 + cd[s].n) { inst = s; row = wave - cd[s].row0; break; }
+        if (wave >= cd[s].row0 && wave < cd[s].row0 + cd[s].n) { k = s; row = wave - cd[s].row0; break; }
     }
-    if (inst < 0) return;
-    if (active && !active[inst]) return;
-    const CoarseDev &C = cd[inst];
-    const double *A = C.Ainv + row * C.n;
+    if (k < 0) return;
+    const CoarseDev &C = cd[k];
+    if (active && !active[C.inst]) return;
+    const double HTS_GLOBAL *A = gptr<double>(C.Ainv) + row * C.n;
     double acc = 0.0;
     for (int64_t j = lane; j < C.n; j += 64) acc += A[j] * (double)b[C.off + j];
     acc = wave_sum(acc);

@@ -31,9 +31,5 @@ hts_status hts_nn_load(hts_nn *, const char *)
 {
     return guard_call([&] { throw Error(HTS_ERR_UNSUPPORTED, "learned preconditioner not built yet"); });
 }
-hts_status hts_autotune(hts_mesh *const *, int32_t)
-{
-    return guard_call([&] { throw Error(HTS_ERR_UNSUPPORTED, "autotuner not built yet"); });
-}
 
 }  // extern "C"

@@ -137,9 +137,14 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                                                   const T *__restrict__ X, T *__restrict__ Y,
                                                   EpiArgs<T> ep)
 {
-    __shared__ T xs[2][TB + 1][TB + 2];
-    __shared__ T ps[FIELD ? 2 : 1][TB + 1][TB + 2];
-    __shared__ T S4[4][TB][TB + 1];
+    // Software pipeline over node planes, one barrier per plane:
+    //   x planes live in a 3-deep LDS ring (plane p in slot p % 3), the four
+    //   corner sums of each cell layer in a 2-deep ring; the global loads of
+    //   plane L+2, of the coefficients of layer L+1 and of the epilogue
+    //   operands of plane L are issued one iteration before they are used.
+    __shared__ T xs[3][TB + 1][TB + 2];
+    __shared__ T ps[FIELD ? 3 : 1][TB + 1][TB + 2];
+    __shared__ T S4[2][4][TB][TB + 1];
     __shared__ double red[4];
 
     const WorkItem wi = work[blockIdx.x];
@@ -149,10 +154,13 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const int64_t plane = (int64_t)o.NX * o.NY;
     const T *__restrict__ Xi = X + o.off;
     T *__restrict__ Yi = Y + o.off;
-    const T *__restrict__ Pi = FIELD ? static_cast<const T *>(o.P) : nullptr;
-    const T *__restrict__ kk = static_cast<const T *>(o.k);
-    const T *__restrict__ lamc = static_cast<const T *>(o.lam);
-    const T *__restrict__ cTc = static_cast<const T *>(o.cT);
+    const T HTS_GLOBAL *__restrict__ Pi = gptr<T>(FIELD ? o.P : nullptr);
+    const T HTS_GLOBAL *__restrict__ kk = gptr<T>(o.k);
+    const T HTS_GLOBAL *__restrict__ lamc = gptr<T>(o.lam);
+    const T HTS_GLOBAL *__restrict__ cTc = gptr<T>(o.cT);
+    const T *__restrict__ Bi = (EPI == EPI_RESID || EPI == EPI_RESID_NORM || EPI == EPI_CHEB) ? ep.b + o.off : nullptr;
+    T *__restrict__ Di = EPI == EPI_CHEB ? ep.d + o.off : nullptr;
+    const T *__restrict__ Ii = EPI == EPI_CHEB ? ep.invd + o.off : nullptr;
 
     const int tid = threadIdx.x, tx = tid % TB, ty = tid / TB;
     const int cx0 = wi.tx * OWN - 1, cy0 = wi.ty * OWN - 1;
@@ -161,24 +169,24 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const int64_t cbase = cin ? (int64_t)cx + (int64_t)nx * cy : 0;
     const int64_t cplane = (int64_t)nx * ny;
 
-    // node columns staged by this thread (flattened 17 x 17 halo tile)
     ColInfo lc[2];
     int lj[2], li[2];
+    bool ld[2];
 #pragma unroll
     for (int s = 0; s < 2; s++) {
         int c = tid + s * 256;
+        ld[s] = c < NCOL;
         li[s] = c % (TB + 1);
         lj[s] = c / (TB + 1);
-        if (c < NCOL) lc[s] = col_info(o, cx0 + li[s], cy0 + lj[s]);
+        if (ld[s]) lc[s] = col_info(o, cx0 + li[s], cy0 + lj[s]);
         else lc[s].valid = 0;
     }
-    // owned node column
     const bool owner = tx < OWN && ty < OWN;
     const int oi = cx0 + tx + 1, oj = cy0 + ty + 1;
     ColInfo oc = col_info(o, oi, oj);
     const bool own_ok = owner && oc.valid;
     int lr = -1;
-    if (FIELD && o.lcol && own_ok) lr = o.lcol[oc.base];
+    if (FIELD && o.lcol && own_ok) lr = gptr<int32_t>(o.lcol)[oc.base];
 
     const T hx = T(o.hx), hy = T(o.hy), hz = T(o.hz);
     const T V = hx * hy * hz;
@@ -187,108 +195,148 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const T ihx = T(1) / hx, ihy = T(1) / hy, ihz = T(1) / hz;
     const T rho_g = T(o.rho_g);
     const T cw8 = T(o.cadv) * V * T(0.125);
+    T c1 = T(0), c2 = T(0);
+    if (EPI == EPI_CHEB) {
+        const double *Sc = ep.S + (int64_t)wi.inst * NSLOT;
+        c1 = T(Sc[ep.s1]);
+        c2 = T(Sc[ep.s2]);
+    }
 
-    auto load_plane = [&](int buf, int k) {
+    // Plane / coefficient / epilogue loads are unconditional (clamped to a
+    // valid address) and the keep-or-zero decision is a select applied when
+    // the value is consumed, so no branch forces an early wait on a load.
+    T pfx[2], pfp[2];
+    bool pkeep[2] = {false, false};
+    auto fetch_plane = [&](int k) {
+        const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
 #pragma unroll
         for (int s = 0; s < 2; s++) {
-            if (tid + s * 256 >= NCOL) continue;
-            T v = T(0), pv = T(0);
-            if (lc[s].valid && k >= 0 && k < NZ) {
-                int64_t gi = lc[s].base + k * plane;
-                v = Xi[gi];
-                if (MASKED && constrained(lc[s], k, NZ, m)) v = T(0);
-                if (FIELD) pv = Pi[gi];
-            }
-            xs[buf][lj[s]][li[s]] = v;
-            if (FIELD) ps[FIELD ? buf : 0][lj[s]][li[s]] = pv;
+            const int64_t gi = lc[s].valid ? lc[s].base + kc * plane : 0;
+            pfx[s] = Xi[gi];
+            if (FIELD) pfp[s] = Pi[gi];
+            bool keep = lc[s].valid && k >= 0 && k < NZ;
+            if (MASKED) keep = keep && !constrained(lc[s], k, NZ, m);
+            pkeep[s] = keep;
         }
+    };
+    auto store_plane = [&](int k) {
+        const int b = (k + 3) % 3;
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            if (!ld[s]) continue;
+            xs[b][lj[s]][li[s]] = pkeep[s] ? pfx[s] : T(0);
+            if (FIELD) ps[FIELD ? b : 0][lj[s]][li[s]] = (lc[s].valid && k >= 0 && k < NZ) ? pfp[s] : T(0);
+        }
+    };
+    T cfk = T(0), cfl = T(0), cfc = T(0);
+    auto fetch_coef = [&](int L) {
+        const int Lc = L < 0 ? 0 : (L >= nz ? nz - 1 : L);
+        const int64_t ci = cbase + (int64_t)Lc * cplane;
+        cfk = kk[ci];
+        if (FIELD) { cfl = lamc[ci]; cfc = cTc[ci]; }
+    };
+    // epilogue operands of one owned node
+    T eb = T(0), ed = T(0), ei = T(0), ex = T(0);
+    auto fetch_epi = [&](int L) {
+        const int Lc = L < NZ ? L : NZ - 1;
+        const int64_t gi = own_ok ? oc.base + (int64_t)Lc * plane : 0;
+        if (Bi) eb = Bi[gi];
+        if (EPI == EPI_CHEB) { ed = Di[gi]; ei = Ii[gi]; }
+        if (EPI == EPI_CHEB || EPI == EPI_DOT || MASKED) ex = Xi[gi];
     };
 
     const int kb = wi.z0, ke = wi.z1;
     double acc = 0.0;
     T top[4] = {T(0), T(0), T(0), T(0)};
-    int cur = 0;
-    load_plane(0, kb - 1);
-    for (int L = kb - 1; L < ke; L++) {
-        const int nxt = cur ^ 1;
-        load_plane(nxt, L + 1);
-        const bool lay = cin && L >= 0 && L < nz;
-        T kc = T(0), lam = T(0), cT = T(0);
-        if (lay) {
-            int64_t ci = cbase + (int64_t)L * cplane;
-            kc = kk[ci];
-            if (FIELD) { lam = lamc[ci]; cT = cTc[ci]; }
+
+    fetch_plane(kb - 1);
+    store_plane(kb - 1);
+    fetch_plane(kb);
+    fetch_coef(kb - 1);
+
+    for (int L = kb - 1; L <= ke; L++) {
+        const bool comp = L <= ke - 1;
+        if (comp) store_plane(L + 1);
+        const T ck = cfk, cl = cfl, cc = cfc;
+        if (L + 1 <= ke - 1) {
+            fetch_plane(L + 2);
+            fetch_coef(L + 1);
         }
         __syncthreads();
-        T bot[4] = {T(0), T(0), T(0), T(0)}, tp[4] = {T(0), T(0), T(0), T(0)};
-        if (lay) {
-            T u[8], w[8];
-#pragma unroll
-            for (int a = 0; a < 4; a++) {
-                u[a] = xs[cur][ty + (a >> 1)][tx + (a & 1)];
-                u[a + 4] = xs[nxt][ty + (a >> 1)][tx + (a & 1)];
-            }
-            if (FIELD == 0) {
-                cell_mass_stiff(u, cm * V, cs * kc, cxx, cyy, czz, w);
-            } else {
-                cell_mass_stiff(u, cT * V, cs * lam, cxx, cyy, czz, w);
-                T pp[8];
-#pragma unroll
-                for (int a = 0; a < 4; a++) {
-                    pp[a] = ps[FIELD ? cur : 0][ty + (a >> 1)][tx + (a & 1)];
-                    pp[a + 4] = ps[FIELD ? nxt : 0][ty + (a >> 1)][tx + (a & 1)];
-                }
-                cell_convect(u, pp, kc, ihx, ihy, ihz, rho_g, cw8, w);
-            }
-#pragma unroll
-            for (int a = 0; a < 4; a++) { bot[a] = w[a]; tp[a] = w[a + 4]; }
-        }
-        const bool emit = L >= kb;
-        if (emit) {
-#pragma unroll
-            for (int a = 0; a < 4; a++) S4[a][ty][tx] = top[a] + bot[a];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; a++) top[a] = tp[a];
-        __syncthreads();
-        if (emit && own_ok && L < NZ) {
-            T v = S4[3][ty][tx] + S4[2][ty][tx + 1] + S4[1][ty + 1][tx] + S4[0][ty + 1][tx + 1];
-            const int64_t gi = oc.base + (int64_t)L * plane;
+        // epilogue of plane L-1 (corner sums written in the previous iteration)
+        if (L - 1 >= kb && own_ok && L - 1 < NZ) {
+            const int P0 = L - 1, sb = P0 & 1;
+            T v = S4[sb][3][ty][tx] + S4[sb][2][ty][tx + 1] + S4[sb][1][ty + 1][tx] + S4[sb][0][ty + 1][tx + 1];
+            const int64_t gi = oc.base + (int64_t)P0 * plane;
             if (FIELD && lr >= 0) {
-                while (o.lrows[lr].col == (int)oc.base && o.lrows[lr].k < L) lr++;
-                const LineRow row = o.lrows[lr];
-                if (row.col == (int)oc.base && row.k == L && !(MASKED && row.row_constrained)) {
+                const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
+                const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
+                const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
+                while (rows[lr].col == (int)oc.base && rows[lr].k < P0) lr++;
+                const int rcol = rows[lr].col, rk = rows[lr].k;
+                if (rcol == (int)oc.base && rk == P0 && !(MASKED && rows[lr].row_constrained)) {
                     T la = T(0);
-                    for (int e = row.beg; e < row.end; e++) {
-                        const LineEnt en = o.lents[e];
-                        if (MASKED && en.col_constrained) continue;
-                        la += T(o.lcoef[en.src] * en.w) * Xi[en.col];
+                    for (int e = rows[lr].beg; e < rows[lr].end; e++) {
+                        if (MASKED && ents[e].col_constrained) continue;
+                        la += T(lco[ents[e].src] * ents[e].w) * Xi[ents[e].col];
                     }
                     v += la;
                 }
             }
-            const bool con = MASKED && constrained(oc, L, NZ, m);
-            if (con) v = Xi[gi];
+            if (MASKED && constrained(oc, P0, NZ, m)) v = ex;
             if (EPI == EPI_STORE) {
                 Yi[gi] = v;
             } else if (EPI == EPI_RESID) {
-                Yi[gi] = ep.b[o.off + gi] - v;
+                Yi[gi] = eb - v;
             } else if (EPI == EPI_RESID_NORM) {
-                T r = ep.b[o.off + gi] - v;
+                const T r = eb - v;
                 Yi[gi] = r;
                 acc += (double)r * (double)r;
             } else if (EPI == EPI_DOT) {
                 Yi[gi] = v;
-                acc += (double)Xi[gi] * (double)v;
+                acc += (double)ex * (double)v;
             } else if (EPI == EPI_CHEB) {
-                const double *Sc = ep.S + (int64_t)wi.inst * NSLOT;
-                T r = ep.b[o.off + gi] - v;
-                T d = T(Sc[ep.s1]) * ep.d[o.off + gi] + T(Sc[ep.s2]) * ep.invd[o.off + gi] * r;
-                ep.d[o.off + gi] = d;
-                Yi[gi] = Xi[gi] + d;
+                const T r = eb - v;
+                const T d = c1 * ed + c2 * ei * r;
+                Di[gi] = d;
+                Yi[gi] = ex + d;
             }
         }
-        cur = nxt;
+        if (!comp) break;
+        if (L >= kb) fetch_epi(L);
+        // cell layer L between planes L and L+1
+        const bool lay = cin && L >= 0 && L < nz;
+        T bot[4] = {T(0), T(0), T(0), T(0)}, tp[4] = {T(0), T(0), T(0), T(0)};
+        if (lay) {
+            const int b0 = (L + 3) % 3, b1 = (L + 4) % 3;
+            T u[8], w[8];
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                u[a] = xs[b0][ty + (a >> 1)][tx + (a & 1)];
+                u[a + 4] = xs[b1][ty + (a >> 1)][tx + (a & 1)];
+            }
+            if (FIELD == 0) {
+                cell_mass_stiff(u, cm * V, cs * ck, cxx, cyy, czz, w);
+            } else {
+                cell_mass_stiff(u, cc * V, cs * cl, cxx, cyy, czz, w);
+                T pp[8];
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    pp[a] = ps[FIELD ? b0 : 0][ty + (a >> 1)][tx + (a & 1)];
+                    pp[a + 4] = ps[FIELD ? b1 : 0][ty + (a >> 1)][tx + (a & 1)];
+                }
+                cell_convect(u, pp, ck, ihx, ihy, ihz, rho_g, cw8, w);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; a++) { bot[a] = w[a]; tp[a] = w[a + 4]; }
+        }
+        if (L >= kb) {
+            const int sb = L & 1;
+#pragma unroll
+            for (int a = 0; a < 4; a++) S4[sb][a][ty][tx] = top[a] + bot[a];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; a++) top[a] = tp[a];
     }
     if (EPI == EPI_RESID_NORM || EPI == EPI_DOT) {
         double v = wave_sum(acc);

@@ -9,7 +9,8 @@
 
 namespace hts {
 
-constexpr int CHUNK_LEN = 1024;
+constexpr int CHUNK_LEN = 512;        // nodes per block of the vector kernels
+constexpr int CHUNK_LEN_COARSE = 256; // nodes per block on coarse multigrid levels
 
 template <typename T>
 void launch_apply(int degree, int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork,
@@ -31,10 +32,16 @@ struct Level {
     std::vector<int64_t> off, soff;        // instance offsets (vectors, stencils)
     std::vector<LevelDev> h64;
     DBuf<LevelDev> g64, g32;
-    std::vector<Chunk> hch;
-    DBuf<Chunk> ch;
-    const Chunk *ch_ext = nullptr;         // chunk list used by kernels (level 0: the batch's)
-    int nch = 0;
+    std::vector<int> present, cont;        // instance on this level / continues to a coarser one
+    std::vector<Chunk> hch, hch_all;
+    DBuf<Chunk> ch, ch_all;
+    const Chunk *ch_ext = nullptr;         // chunks of continuing instances (level 0: the batch's)
+    const Chunk *ch_all_ext = nullptr;     // chunks of every present instance
+    int nch = 0, nch_all = 0;
+    std::vector<DBuf<double>> Ainv;        // dense inverses of instances ending here
+    DBuf<CoarseDev> cd;
+    int ncd = 0;
+    int64_t crows = 0;
     DBuf<int32_t> segp, segi;
     RedCtx red{};
     DBuf<double> S64;
@@ -47,12 +54,12 @@ struct Level {
 struct Hier {
     int field = 0;
     int deg = 2;
+    bool multigrid = true;
+    double ratio = 15.0;          // Chebyshev interval [lmax/ratio, 1.1 lmax] on the fine level
+    double ratio_coarse = 15.0;   // and on coarse levels
     double dt = -1.0;
     Tables ops;                            // fine-level operator
     std::vector<Level> lev;
-    std::vector<DBuf<double>> Ainv;
-    DBuf<CoarseDev> cd;
-    int64_t crows = 0;
     std::vector<double> lmax;
 };
 
@@ -68,19 +75,20 @@ struct Batch {
     hipStream_t s = nullptr;
     Alloc *al = nullptr;
     std::vector<int64_t> off;
-    int64_t ntot = 0;
-    int zc_override = 0;
+    int64_t ntot = 0, ctot = 0;
 
     std::vector<Chunk> hch;
     DBuf<Chunk> ch;
     int nch = 0;
     DBuf<int32_t> chp, chi;
     RedCtx rch{};
-    std::vector<WorkItem> hwork;
-    DBuf<WorkItem> work;
-    int nwork = 0;
-    DBuf<int32_t> wkp, wki;
-    RedCtx rwk{};
+    // fine-level work lists per field (the z-chunk depth is tuned per field)
+    std::vector<WorkItem> hwork[2];
+    DBuf<WorkItem> work[2];
+    int nwork[2] = {0, 0};
+    DBuf<int32_t> wkp[2], wki[2];
+    RedCtx rwk[2]{};
+    int zc_force[2] = {0, 0};
 
     DBuf<double> S;
     DBuf<int32_t> active;
@@ -115,7 +123,7 @@ struct Batch {
     std::unique_ptr<Hier> heat;
 
     ~Batch();
-    int pick_zc(int64_t tiles, int NZ) const;
+    int pick_zc(int field, const hts_mesh *M, int64_t tiles) const;
     void build_work();
     void make_tables(Tables &t, int field, double dt, bool steady, bool mass_only);
     Tables &apply_tables(int field, double dt, bool steady)
@@ -135,6 +143,8 @@ struct Batch {
     bool any_active();
     VecCtx vctx(bool use_active = true) const;
 
+    template <typename T>
+    void fine_apply(int field, const OpDev *ops, int epi, bool masked, const T *x, T *y, const EpiArgs<T> &ep);
     template <typename T> void apply_lvl(Hier &H, int l, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep);
     template <typename T> void apply_op(const Tables &t, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep);
 
@@ -168,6 +178,10 @@ struct Batch {
 };
 
 std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms);
+// tuned z-chunk depth of the fine operator kernels (0 = none recorded)
+int tuned_zc(int degree, int field, int NX, int NY, int NZ);
+void set_tuned_zc(int degree, int field, int NX, int NY, int NZ, int zc);
+void save_tuning();
 std::shared_ptr<Batch> solo_batch(hts_mesh *m);
 
 }  // namespace hts

@@ -27,6 +27,12 @@ template <> struct Pick<float> {
 
 static void sync(hipStream_t s) { HTS_HIP(hipStreamSynchronize(s)); }
 
+static double env_or(const char *name, double def)
+{
+    const char *v = getenv(name);
+    return v ? atof(v) : def;
+}
+
 static void build_chunks(const std::vector<int64_t> &off, const std::vector<int64_t> &cnt, int len,
                          std::vector<Chunk> &ch, std::vector<int32_t> &segp, std::vector<int32_t> &segi)
 {
@@ -51,57 +57,128 @@ Batch::~Batch()
     if (hact) (void)hipHostFree(hact);
 }
 
-int Batch::pick_zc(int64_t tiles, int NZ) const
+// ----------------------------------------------------------- tuning cache
+// z-chunk depth per (degree, field, node dims), filled by hts_autotune and
+// optionally kept in the JSON file named by HTS_TUNE_CACHE.
+namespace {
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(int degree, int field, int NX, int NY, int NZ)
 {
-    if (zc_override > 0) return zc_override;
-    int64_t want = 2048;   // blocks to fill 256 CUs several times over
-    int64_t z = std::max<int64_t>(4, (tiles * NZ) / want);
+    char b[96];
+    snprintf(b, sizeof(b), "q%d_f%d_%dx%dx%d", degree, field, NX, NY, NZ);
+    return b;
+}
+
+void tune_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("HTS_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[96];
+    int v;
+    // entries look like  "q1_f0_129x129x65": 8
+    while (fscanf(f, " \"%95[^\"]\" : %d", key, &v) == 2) {
+        g_tune[key] = v;
+        int c = fgetc(f);
+        while (c != EOF && c != ',' && c != '}') c = fgetc(f);
+        if (c == '}' || c == EOF) break;
+    }
+    fclose(f);
+}
+
+void tune_save()
+{
+    const char *path = getenv("HTS_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "{");
+    bool first = true;
+    for (auto &kv : g_tune) {
+        fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+        first = false;
+    }
+    fprintf(f, "\n}\n");
+    fclose(f);
+}
+}  // namespace
+
+void set_tuned_zc(int degree, int field, int NX, int NY, int NZ, int zc)
+{
+    tune_load();
+    g_tune[tune_key(degree, field, NX, NY, NZ)] = zc;
+}
+
+void save_tuning() { tune_save(); }
+
+int tuned_zc(int degree, int field, int NX, int NY, int NZ)
+{
+    tune_load();
+    auto it = g_tune.find(tune_key(degree, field, NX, NY, NZ));
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+int Batch::pick_zc(int field, const hts_mesh *M, int64_t tiles) const
+{
+    const int NZ = M->N[2];
+    if (zc_force[field] > 0) return std::min(zc_force[field], NZ);
+    const int t = tuned_zc(M->p, field, M->N[0], M->N[1], NZ);
+    if (t > 0) return std::min(t, NZ);
+    // enough blocks to fill 256 CUs several times over
+    int64_t z = std::max<int64_t>(4, (tiles * NZ) / 2048);
     z = std::min<int64_t>(z, 32);
     return (int)std::min<int64_t>(z, NZ);
 }
 
 void Batch::build_work()
 {
-    std::vector<WorkItem> nat;
-    for (int i = 0; i < n; i++) {
-        hts_mesh *M = m[i];
-        const int own = 15;
-        const int tx = (M->N[0] + own - 1) / own, ty = (M->N[1] + own - 1) / own;
-        const int zc = pick_zc((int64_t)tx * ty, M->N[2]);
-        for (int z0 = 0; z0 < M->N[2]; z0 += zc)
-            for (int y = 0; y < ty; y++)
-                for (int x = 0; x < tx; x++) {
-                    WorkItem w{};
-                    w.inst = i; w.tx = x; w.ty = y; w.z0 = z0; w.z1 = std::min(M->N[2], z0 + zc);
-                    nat.push_back(w);
-                }
-    }
-    // XCD-aware order: block b is dispatched to XCD b % 8; give each XCD a
-    // contiguous run of neighbouring tiles so halos stay in its L2.
-    const int64_t T = (int64_t)nat.size(), per = (T + 7) / 8;
-    hwork.clear();
-    std::vector<int64_t> pos_of(T, -1);   // natural index -> launch position
-    for (int64_t b = 0; b < 8 * per; b++) {
-        int64_t idx = (b % 8) * per + b / 8;
-        if (idx < T) {
-            pos_of[idx] = (int64_t)hwork.size();
-            hwork.push_back(nat[idx]);
+    for (int f = 0; f < 2; f++) {
+        std::vector<WorkItem> nat;
+        for (int i = 0; i < n; i++) {
+            hts_mesh *M = m[i];
+            const int own = 15;
+            const int tx = (M->N[0] + own - 1) / own, ty = (M->N[1] + own - 1) / own;
+            const int zc = pick_zc(f, M, (int64_t)tx * ty);
+            for (int z0 = 0; z0 < M->N[2]; z0 += zc)
+                for (int y = 0; y < ty; y++)
+                    for (int x = 0; x < tx; x++) {
+                        WorkItem w{};
+                        w.inst = i; w.tx = x; w.ty = y; w.z0 = z0; w.z1 = std::min(M->N[2], z0 + zc);
+                        nat.push_back(w);
+                    }
         }
+        // XCD-aware order: block b is dispatched to XCD b % 8; give each XCD a
+        // contiguous run of neighbouring tiles so halos stay in its L2.
+        const int64_t T = (int64_t)nat.size(), per = (T + 7) / 8;
+        hwork[f].clear();
+        std::vector<int64_t> pos_of(T, -1);   // natural index -> launch position
+        for (int64_t b = 0; b < 8 * per; b++) {
+            int64_t idx = (b % 8) * per + b / 8;
+            if (idx < T) {
+                pos_of[idx] = (int64_t)hwork[f].size();
+                hwork[f].push_back(nat[idx]);
+            }
+        }
+        nwork[f] = (int)hwork[f].size();
+        work[f].upload(al, hwork[f], s);
+        // per-instance partial sums are reduced in the natural tile order, so a
+        // batched instance sums exactly like the same instance alone
+        std::vector<int32_t> sp(n + 1, 0), si;
+        for (int i = 0; i < n; i++) {
+            for (int64_t k = 0; k < T; k++)
+                if (nat[k].inst == i) si.push_back((int32_t)pos_of[k]);
+            sp[i + 1] = (int32_t)si.size();
+        }
+        wkp[f].upload(al, sp, s);
+        wki[f].upload(al, si, s);
+        rwk[f] = RedCtx{wkp[f].p, wki[f].p, n};
     }
-    nwork = (int)hwork.size();
-    work.upload(al, hwork, s);
-    // per-instance partial sums are reduced in the natural tile order, so a
-    // batched instance sums exactly like the same instance alone
-    std::vector<int32_t> sp(n + 1, 0), si;
-    for (int i = 0; i < n; i++) {
-        for (int64_t k = 0; k < T; k++)
-            if (nat[k].inst == i) si.push_back((int32_t)pos_of[k]);
-        sp[i + 1] = (int32_t)si.size();
-    }
-    wkp.upload(al, sp, s);
-    wki.upload(al, si, s);
-    rwk = RedCtx{wkp.p, wki.p, n};
-    partial.alloc(al, (size_t)std::max<int64_t>(nwork, nch) * 64 + 64);
+    partial.alloc(al, (size_t)std::max<int64_t>(std::max(nwork[0], nwork[1]), nch) * 64 + 64);
 }
 
 std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
@@ -130,6 +207,8 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
         tot += cnt[i];
     }
     B->ntot = tot;
+    B->ctot = 0;
+    for (int i = 0; i < n; i++) B->ctot += ms[i]->ncell;
     std::vector<int32_t> sp, si;
     build_chunks(B->off, cnt, CHUNK_LEN, B->hch, sp, si);
     B->nch = (int)B->hch.size();
@@ -279,13 +358,78 @@ bool Batch::any_active()
 VecCtx Batch::vctx(bool use_active) const { return VecCtx{ch.p, nch, use_active ? active.p : nullptr, S.p, s}; }
 
 // --------------------------------------------------------- level operators
+// ------------------------------------------------------ kernel timing
+namespace {
+struct TimingRec {
+    hipEvent_t a, b;
+    int field, prec;
+    double bytes, flops;
+};
+struct TimingState {
+    bool on = false;
+    std::vector<TimingRec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        HTS_HIP(hipEventCreate(&e));
+        return e;
+    }
+};
+TimingState g_timing;
+}  // namespace
+
+// Algorithmic traffic of one fine-level launch: each node vector the
+// epilogue touches once, the per-cell coefficients, and (heat) the pressure.
+static double apply_bytes(int field, int epi, int64_t nodes, int64_t cells, int ts)
+{
+    int nvec = 2;   // x read, y written
+    if (epi == EPI_RESID || epi == EPI_RESID_NORM) nvec = 3;
+    if (epi == EPI_CHEB) nvec = 6;   // x, b, d (read + write), D^-1, x_out
+    const int ncoef = field == 0 ? 1 : 3;
+    const int extra = field == 0 ? 0 : 1;
+    return (double)ts * ((double)nodes * (nvec + extra) + (double)cells * ncoef);
+}
+static double apply_flops(int field, int p, int64_t cells)
+{
+    // per cell: Kronecker mass + stiffness about 150 flop (Q1), the
+    // convection term about 270 more; Q2 about 8x the Q1 count
+    const double q1 = field == 0 ? 150.0 : 420.0;
+    return (p == 1 ? q1 : 8.0 * q1) * (double)cells;
+}
+
+template <typename T>
+void Batch::fine_apply(int field, const OpDev *ops, int epi, bool masked, const T *x, T *y, const EpiArgs<T> &ep)
+{
+    if (!g_timing.on) {
+        launch_apply<T>(p, field, epi, masked, ops, work[field].p, nwork[field], x, y, ep, s);
+        return;
+    }
+    TimingRec r{};
+    r.a = g_timing.get();
+    r.b = g_timing.get();
+    r.field = field;
+    r.prec = std::is_same<T, double>::value ? 0 : 1;
+    r.bytes = apply_bytes(field, epi, ntot, ctot, sizeof(T));
+    r.flops = apply_flops(field, p, ctot);
+    HTS_HIP(hipEventRecord(r.a, s));
+    launch_apply<T>(p, field, epi, masked, ops, work[field].p, nwork[field], x, y, ep, s);
+    HTS_HIP(hipEventRecord(r.b, s));
+    g_timing.recs.push_back(r);
+}
+
 template <typename T>
 void Batch::apply_lvl(Hier &H, int l, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep)
 {
     if (!ep.active) ep.active = active.p;
     if (l == 0) {
         const OpDev *ops = std::is_same<T, double>::value ? H.ops.d64.p : H.ops.d32.p;
-        launch_apply<T>(p, H.field, epi, masked, ops, work.p, nwork, x, y, ep, s);
+        fine_apply<T>(H.field, ops, epi, masked, x, y, ep);
     } else {
         Level &L = H.lev[l];
         const LevelDev *g = std::is_same<T, double>::value ? L.g64.p : L.g32.p;
@@ -298,7 +442,7 @@ void Batch::apply_op(const Tables &t, int epi, bool masked, const T *x, T *y, Ep
 {
     if (!ep.active) ep.active = active.p;
     const OpDev *ops = std::is_same<T, double>::value ? t.d64.p : t.d32.p;
-    launch_apply<T>(p, t.field, epi, masked, ops, work.p, nwork, x, y, ep, s);
+    fine_apply<T>(t.field, ops, epi, masked, x, y, ep);
 }
 
 // ---------------------------------------------------------- hierarchy
@@ -356,18 +500,21 @@ static void cheb_coeffs(double lmax_est, double ratio, int steps, double *out /*
 void Batch::estimate_lmax(Hier &H, int l, std::vector<double> &lmax)
 {
     Level &L = H.lev[l];
+    lmax.assign(n, 1.0);
+    if (L.nch == 0) return;
     // probe vector: the same per instance whatever batch it sits in
-    std::vector<double> hv(L.ntot);
+    std::vector<double> hv(std::max<int64_t>(L.ntot, 1), 0.0);
     for (int i = 0; i < n; i++) {
+        if (!L.cont[i]) continue;
         std::mt19937_64 rng(12345 + l);
         std::uniform_real_distribution<double> U(-1.0, 1.0);
-        const int64_t b0 = l == 0 ? off[i] : L.off[i];
-        const int64_t cnt = l == 0 ? m[i]->nnode : L.h64[i].n;
+        const int64_t b0 = L.h64[i].off, cnt = L.h64[i].n;
         for (int64_t e = 0; e < cnt; e++) hv[b0 + e] = U(rng);
     }
     HTS_HIP(hipMemcpyAsync(L.x64.p, hv.data(), L.ntot * sizeof(double), hipMemcpyHostToDevice, s));
-    std::vector<int32_t> all(n, 1);
-    set_active(all);
+    std::vector<int32_t> act(n, 0);
+    for (int i = 0; i < n; i++) act[i] = L.cont[i] ? 1 : 0;
+    set_active(act);
     VecCtx v{L.ch_ext, L.nch, active.p, S.p, s};
     RedCtx rc = L.red;
     if (l == 0) vmask<double>(v, H.ops.d64.p, L.x64.p, 0.0);
@@ -380,17 +527,16 @@ void Batch::estimate_lmax(Hier &H, int l, std::vector<double> &lmax)
         vaxpby<double>(v, 1.0, S_TMP1, L.xb64.p, 0.0, -1, L.x64.p);
     }
     download_S();
-    lmax.resize(n);
-    for (int i = 0; i < n; i++) lmax[i] = std::sqrt(std::max(hS[(size_t)i * NSLOT + S_TMP0], 1e-300));
-    HTS_HIP(hipMemcpyAsync(hS, S.p, sizeof(double) * n * NSLOT, hipMemcpyDeviceToHost, s));
-    sync(s);
+    for (int i = 0; i < n; i++)
+        if (L.cont[i]) lmax[i] = std::sqrt(std::max(hS[(size_t)i * NSLOT + S_TMP0], 1e-300));
 }
 
 static void level_alloc(Level &L, Alloc *al, hipStream_t s, int64_t ntot)
 {
     L.ntot = ntot;
-    for (DBuf<double> *v : {&L.x64, &L.xb64, &L.b64, &L.d64, &L.t64, &L.invd64}) { v->alloc(al, ntot); v->zero(s); }
-    for (DBuf<float> *v : {&L.x32, &L.xb32, &L.b32, &L.d32, &L.t32, &L.invd32}) { v->alloc(al, ntot); v->zero(s); }
+    const int64_t m = std::max<int64_t>(ntot, 1);
+    for (DBuf<double> *v : {&L.x64, &L.xb64, &L.b64, &L.d64, &L.t64, &L.invd64}) { v->alloc(al, m); v->zero(s); }
+    for (DBuf<float> *v : {&L.x32, &L.xb32, &L.b32, &L.d32, &L.t32, &L.invd32}) { v->alloc(al, m); v->zero(s); }
 }
 
 void Batch::build_smoother(Hier &H, int l, int steps, double ratio)
@@ -401,7 +547,7 @@ void Batch::build_smoother(Hier &H, int l, int steps, double ratio)
     std::vector<double> c((size_t)n * NSLOT, 0.0);
     for (int i = 0; i < n; i++) {
         cheb_coeffs(lm[i], ratio, steps, &c[(size_t)i * NSLOT + S_CHEB]);
-        H.lmax.push_back(lm[i]);
+        if (L.cont[i]) H.lmax.push_back(lm[i]);
     }
     L.cheb.upload(al, c, s);
 }
@@ -414,6 +560,8 @@ Hier &Batch::pressure_hier(bool steady, double dt, const hts_solver_opts &o)
     auto H = std::make_unique<Hier>();
     H->field = 0;
     H->deg = std::max(1, std::min(o.cheb_degree, 8));
+    H->ratio = env_or("HTS_P_RATIO", 15.0);
+    H->ratio_coarse = env_or("HTS_P_RATIO", 15.0);
     make_tables(H->ops, 0, dt, steady, false);
     build_hierarchy(*H, o);
     Hier &ref = *H;
@@ -423,31 +571,54 @@ Hier &Batch::pressure_hier(bool steady, double dt, const hts_solver_opts &o)
 
 Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
 {
-    if (heat && heat->dt == dt && heat->deg == std::max(1, std::min(o.heat_cheb_degree, 16))) return *heat;
+    const bool mg = o.heat_precond == 0;
+    const int deg = mg ? std::max(1, std::min(o.heat_cheb_degree, 8)) : std::max(1, std::min(o.heat_cheb_degree, 16));
+    if (heat && heat->dt == dt && heat->deg == deg && heat->multigrid == mg) return *heat;
     heat = std::make_unique<Hier>();
     Hier &H = *heat;
     H.field = 1;
     H.dt = dt;
-    H.deg = std::max(1, std::min(o.heat_cheb_degree, 16));
+    H.deg = deg;
+    H.multigrid = mg;
+    // Chebyshev-Jacobi alone covers [lmax/30, 1.1 lmax]; as a multigrid
+    // smoother the usual [lmax/15, 1.1 lmax]
+    H.ratio = env_or("HTS_HEAT_RATIO", mg ? 15.0 : 30.0);
+    H.ratio_coarse = env_or("HTS_HEAT_RATIO_COARSE", 15.0);
     make_tables(H.ops, 1, dt, false, false);
+    if (mg) {
+        // Galerkin levels of the static symmetric part; the fine level
+        // smooths with the full operator (current Darcy flux in P1)
+        build_hierarchy(H, o);
+        return H;
+    }
     H.lev.resize(1);
     Level &L = H.lev[0];
     level_alloc(L, al, s, ntot);
-    L.ch.p = nullptr;
-    L.nch = nch;
+    L.nch = L.nch_all = nch;
     L.red = rch;
-    L.ch_ext = ch.p;
+    L.ch_ext = L.ch_all_ext = ch.p;
+    L.present.assign(n, 1);
+    L.cont.assign(n, 1);
+    L.h64.resize(n);
+    for (int i = 0; i < n; i++) {
+        L.h64[i].NX = m[i]->N[0]; L.h64[i].NY = m[i]->N[1]; L.h64[i].NZ = m[i]->N[2];
+        L.h64[i].off = off[i]; L.h64[i].n = m[i]->nnode; L.h64[i].S = nullptr;
+    }
     for (int i = 0; i < n; i++) launch_inv_diag(H.ops.h64[i], L.invd64.p + off[i], s);
     convert_plain(ntot, L.invd64.p, L.invd32.p, s);
     // the velocity field enters the operator: estimate with the current P1
-    build_smoother(H, 0, H.deg, 30.0);
+    build_smoother(H, 0, H.deg, H.ratio);
     return H;
 }
 
+// Per-instance depth: every instance coarsens (2:1 per axis, odd counts
+// included) until its own level has at most coarse_max nodes, whatever batch
+// it sits in.  On each level the batch keeps the instances present there and,
+// among them, the ones that continue to a coarser level; an instance ends
+// with a dense FP64 solve on its last level.
 void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
 {
     const int coarse_max = std::max(8, o.mg_coarse_max);
-    // level 0
     H.lev.clear();
     H.lev.emplace_back();
     {
@@ -456,6 +627,10 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
         L.nch = nch;
         L.red = rch;
         L.ch_ext = ch.p;
+        L.nch_all = nch;
+        L.ch_all_ext = ch.p;
+        L.present.assign(n, 1);
+        L.cont.assign(n, 1);        // the matrix-free level always has a coarser level
         std::vector<LevelDev> g(n);
         for (int i = 0; i < n; i++) {
             g[i].NX = m[i]->N[0]; g[i].NY = m[i]->N[1]; g[i].NZ = m[i]->N[2];
@@ -467,52 +642,65 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
         for (int i = 0; i < n; i++) launch_inv_diag(H.ops.h64[i], L.invd64.p + off[i], s);
         convert_plain(ntot, L.invd64.p, L.invd32.p, s);
         L.dims.resize(3 * n);
+        L.off.assign(off.begin(), off.end());
         for (int i = 0; i < n; i++)
             for (int d = 0; d < 3; d++) L.dims[3 * i + d] = m[i]->N[d];
     }
-    // coarse levels
-    for (int lev = 1; lev < 16; lev++) {
-        const Level &F = H.lev[lev - 1];
-        int64_t maxn = 0;
-        bool shrink = false;
-        for (int i = 0; i < n; i++) {
-            int64_t nn = (int64_t)F.dims[3 * i] * F.dims[3 * i + 1] * F.dims[3 * i + 2];
-            maxn = std::max(maxn, nn);
-            for (int d = 0; d < 3; d++) shrink |= F.dims[3 * i + d] > 2;
+    for (int lev = 1; lev < 24; lev++) {
+        {
+            bool any = false;
+            for (int i = 0; i < n; i++) any |= H.lev[lev - 1].cont[i] != 0;
+            if (!any) break;
         }
-        if (maxn <= coarse_max || !shrink) break;
         H.lev.emplace_back();
         Level &C = H.lev.back();
         const Level &Fl = H.lev[lev - 1];
-        C.dims.resize(3 * n);
-        std::vector<int64_t> coff(n), ccnt(n);
+        C.dims.assign(3 * n, 0);
+        C.present.assign(n, 0);
+        C.cont.assign(n, 0);
+        std::vector<int64_t> coff(n, 0), ccnt(n, 0);
         int64_t ctot = 0;
         for (int i = 0; i < n; i++) {
+            coff[i] = ctot;
+            if (!Fl.cont[i]) continue;
+            C.present[i] = 1;
             int64_t nn = 1;
+            bool shrink = false;
             for (int d = 0; d < 3; d++) {
-                int cells_f = Fl.dims[3 * i + d] - 1;
-                int cells_c = (cells_f + 1) / 2;
-                // Q2 -> Q1 on the same cells is the first coarsening of a Q2 mesh
+                const int cells_c = (Fl.dims[3 * i + d] - 1 + 1) / 2;
                 C.dims[3 * i + d] = cells_c + 1;
                 nn *= cells_c + 1;
+                shrink |= C.dims[3 * i + d] > 2;
             }
-            coff[i] = ctot;
             ccnt[i] = nn;
             ctot += nn;
+            C.cont[i] = (nn > coarse_max && shrink) ? 1 : 0;
         }
         level_alloc(C, al, s, ctot);
-        std::vector<int32_t> sp, si;
-        build_chunks(coff, ccnt, CHUNK_LEN, C.hch, sp, si);
-        C.nch = (int)C.hch.size();
-        C.ch.upload(al, C.hch, s);
-        C.segp.upload(al, sp, s);
-        C.segi.upload(al, si, s);
-        C.red = RedCtx{C.segp.p, C.segi.p, n};
-        C.ch_ext = C.ch.p;
-        C.S64.alloc(al, (size_t)27 * ctot);
-        C.S32.alloc(al, (size_t)27 * ctot);
-        // stencils: Galerkin P^T A P from the finer level
+        C.off = coff;
+        // chunk lists: all present instances (restriction target) and the
+        // continuing ones (smoothing, residual, prolongation)
+        {
+            std::vector<int32_t> sp, si;
+            build_chunks(coff, ccnt, CHUNK_LEN_COARSE, C.hch_all, sp, si);
+            C.nch_all = (int)C.hch_all.size();
+            C.ch_all.upload(al, C.hch_all, s);
+            C.ch_all_ext = C.ch_all.p;
+            std::vector<int64_t> kcnt(n, 0);
+            for (int i = 0; i < n; i++) kcnt[i] = C.cont[i] ? ccnt[i] : 0;
+            build_chunks(coff, kcnt, CHUNK_LEN_COARSE, C.hch, sp, si);
+            C.nch = (int)C.hch.size();
+            C.ch.upload(al, C.hch, s);
+            C.segp.upload(al, sp, s);
+            C.segi.upload(al, si, s);
+            C.red = RedCtx{C.segp.p, C.segi.p, n};
+            C.ch_ext = C.ch.p;
+        }
+        C.S64.alloc(al, (size_t)27 * std::max<int64_t>(ctot, 1));
+        C.S32.alloc(al, (size_t)27 * std::max<int64_t>(ctot, 1));
+        C.soff = coff;
         for (int i = 0; i < n; i++) {
+            if (!C.present[i]) continue;
             const int fN[3] = {Fl.dims[3 * i], Fl.dims[3 * i + 1], Fl.dims[3 * i + 2]};
             const int cN[3] = {C.dims[3 * i], C.dims[3 * i + 1], C.dims[3 * i + 2]};
             double *Sc = C.S64.p + 27 * coff[i];
@@ -537,11 +725,12 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
                 const double *Sf = Fl.S64.p + 27 * Fl.soff[i];
                 launch_rap(fN[0], fN[1], fN[2], Sf, cN[0], cN[1], cN[2], Sc, s);
             }
-            C.soff.push_back(coff[i]);
             launch_stencil_invdiag(Sc, ccnt[i], C.invd64.p + coff[i], s);
         }
-        convert_plain((int64_t)27 * ctot, C.S64.p, C.S32.p, s);
-        convert_plain(ctot, C.invd64.p, C.invd32.p, s);
+        if (ctot > 0) {
+            convert_plain((int64_t)27 * ctot, C.S64.p, C.S32.p, s);
+            convert_plain(ctot, C.invd64.p, C.invd32.p, s);
+        }
         std::vector<LevelDev> g64(n), g32(n);
         for (int i = 0; i < n; i++) {
             LevelDev g{};
@@ -555,21 +744,15 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
         C.h64 = g64;
         C.g64.upload(al, g64, s);
         C.g32.upload(al, g32, s);
-        C.off = coff;
-        sync(s);
-    }
-    // coarsest: dense inverse
-    {
-        Level &C = H.lev.back();
-        if (H.lev.size() == 1) throw Error(HTS_ERR_UNSUPPORTED, "mesh too small for multigrid");
-        std::vector<CoarseDev> cd(n);
+        // dense inverses of the instances that end on this level
+        std::vector<CoarseDev> cd;
         int64_t row0 = 0;
-        H.Ainv.clear();
         for (int i = 0; i < n; i++) {
-            const int64_t nn = C.h64[i].n;
+            if (!C.present[i] || C.cont[i]) continue;
+            const int64_t nn = ccnt[i];
             std::vector<double> st((size_t)27 * nn);
-            HTS_HIP(hipMemcpy(st.data(), C.S64.p + 27 * C.off[i], st.size() * sizeof(double), hipMemcpyDeviceToHost));
-            const int NX = C.h64[i].NX, NY = C.h64[i].NY, NZ = C.h64[i].NZ;
+            HTS_HIP(hipMemcpy(st.data(), C.S64.p + 27 * coff[i], st.size() * sizeof(double), hipMemcpyDeviceToHost));
+            const int NX = C.dims[3 * i], NY = C.dims[3 * i + 1], NZ = C.dims[3 * i + 2];
             std::vector<double> A((size_t)nn * nn, 0.0);
             for (int64_t r = 0; r < nn; r++) {
                 int i0 = (int)(r % NX), j0 = (int)((r / NX) % NY), k0 = (int)(r / ((int64_t)NX * NY));
@@ -580,19 +763,25 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
                 }
             }
             invert_dense(A, (int)nn);
-            H.Ainv.emplace_back();
-            H.Ainv.back().upload(al, A, s);
-            cd[i].Ainv = H.Ainv.back().p;
-            cd[i].n = nn;
-            cd[i].off = C.off[i];
-            cd[i].row0 = row0;
+            C.Ainv.emplace_back();
+            C.Ainv.back().upload(al, A, s);
+            CoarseDev e{};
+            e.Ainv = C.Ainv.back().p;
+            e.n = nn;
+            e.off = coff[i];
+            e.row0 = row0;
+            e.inst = i;
             row0 += nn;
+            cd.push_back(e);
         }
-        H.crows = row0;
-        H.cd.upload(al, cd, s);
+        C.ncd = (int)cd.size();
+        C.crows = row0;
+        if (!cd.empty()) C.cd.upload(al, cd, s);
+        sync(s);
     }
-    // smoothers
-    for (size_t l = 0; l + 1 < H.lev.size(); l++) build_smoother(H, (int)l, 2 * H.deg, 15.0);
+    // smoothers on every level with continuing instances
+    for (size_t l = 0; l < H.lev.size(); l++)
+        if (H.lev[l].nch > 0) build_smoother(H, (int)l, 2 * H.deg, l == 0 ? H.ratio : H.ratio_coarse);
     sync(s);
 }
 
@@ -618,15 +807,11 @@ template <typename T>
 void Batch::vcycle(Hier &H, int l, const T *b, T *x)
 {
     Level &L = H.lev[l];
-    const int last = (int)H.lev.size() - 1;
-    if (l == last) {
-        launch_coarse_solve<T>(H.cd.p, n, H.crows, active.p, b, x, s);
-        return;
-    }
+    if (L.ncd > 0) launch_coarse_solve<T>(L.cd.p, L.ncd, L.crows, active.p, b, x, s);
+    if (L.nch == 0) return;
     const int deg = H.deg;
     T *xb = PK(T, L.xb64, L.xb32);
     T *cur = xb, *oth = x;   // 2*deg - 1 swaps end in x
-    VecCtx v{L.ch_ext, L.nch, active.p, L.cheb.p, s};
     launch_cheb0<T>(L.ch_ext, L.nch, active.p, L.cheb.p, S_CHEB + 1, PK(T, L.invd64, L.invd32), b,
                     PK(T, L.d64, L.d32), cur, s);
     smooth<T>(H, l, deg - 1, 1, b, cur, oth);
@@ -637,7 +822,7 @@ void Batch::vcycle(Hier &H, int l, const T *b, T *x)
     apply_lvl<T>(H, l, EPI_RESID, true, cur, t, ep);
     Level &C = H.lev[l + 1];
     const OpDev *fops = (l == 0) ? H.ops.d64.p : nullptr;
-    launch_restrict<T>(L.g64.p, C.g64.p, fops, C.ch_ext, C.nch, active.p, t, PK(T, C.b64, C.b32), s);
+    launch_restrict<T>(L.g64.p, C.g64.p, fops, C.ch_all_ext, C.nch_all, active.p, t, PK(T, C.b64, C.b32), s);
     vcycle<T>(H, l + 1, PK(T, C.b64, C.b32), PK(T, C.x64, C.x32));
     launch_prolong_add<T>(L.g64.p, C.g64.p, fops, L.ch_ext, L.nch, active.p, PK(T, C.x64, C.x32), cur, s);
     // post-smoothing restarts the Chebyshev recurrence (first coefficient pair has c1 = 0)
@@ -646,7 +831,6 @@ void Batch::vcycle(Hier &H, int l, const T *b, T *x)
         VecCtx vc{L.ch_ext, L.nch, active.p, S.p, s};
         vcopy<T>(vc, cur, x);
     }
-    (void)v;
 }
 
 template <typename T>
@@ -674,7 +858,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
     ep.b = b;
     ep.partial = partial.p;
     apply_op<T>(A, EPI_RESID_NORM, true, x, r, ep);
-    vreduce(rwk, partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+    vreduce(rwk[A.field], partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
     if (!any_active()) return 0;
     M(r, z);
     vdot<T>(v, r, z, nullptr, partial.p);
@@ -685,7 +869,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
         EpiArgs<T> e2{};
         e2.partial = partial.p;
         apply_op<T>(A, EPI_DOT, true, pv, q, e2);
-        vreduce(rwk, partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+        vreduce(rwk[A.field], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
         vcg_update<T>(v, x, r, pv, q, ro, partial.p);
         vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
         if (it % std::max(1, check_every) == 0 || it == maxit)
@@ -713,7 +897,7 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
         ep.b = b;
         ep.partial = partial.p;
         apply_op<T>(A, EPI_RESID_NORM, true, x, V, ep);
-        vreduce(rwk, partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
+        vreduce(rwk[A.field], partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
         gm_begin(n, active.p, S.p, gg.p, mres, gkdim.p, s);
         std::vector<int32_t> cyc = get_active();
         bool any = false;
@@ -808,7 +992,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         ep.b = b64;
         ep.partial = partial.p;
         apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
-        vreduce(rwk, partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
+        vreduce(rwk[A.field], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
         outer_check(n, active.p, S.p, redout.p, s);
         outer = get_active();
         bool any = false;
@@ -860,7 +1044,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         if (stop) {
             // final judge with the last update
             apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
-            vreduce(rwk, partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
+            vreduce(rwk[A.field], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
             outer_check(n, active.p, S.p, redout.p, s);
             outer = get_active();
             break;
@@ -993,7 +1177,7 @@ FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
     heat_rhs(H);
     vcopy<double>(v, Tn.p, x.p);
     vmask<double>(v, H.ops.d64.p, x.p, 0.0);
-    FieldStats st = solve_field(1, nullptr, H.ops, b.p, x.p, o, all, &H);
+    FieldStats st = solve_field(1, H.multigrid ? &H : nullptr, H.ops, b.p, x.p, o, all, &H);
     set_active(all);
     vaxpby<double>(vctx(false), 1.0, -1, x.p, 0.0, -1, T1.p);
     vaxpby<double>(vctx(false), 1.0, -1, g.p, 1.0, -1, T1.p);
@@ -1069,6 +1253,38 @@ static void check_ready(hts_mesh *m)
 
 extern "C" {
 
+hts_status hts_kernel_timing(int32_t enable, hts_kernel_times out[2][2])
+{
+    return guard_call([&] {
+        if (enable) {
+            for (auto &r : g_timing.recs) {
+                g_timing.pool.push_back(r.a);
+                g_timing.pool.push_back(r.b);
+            }
+            g_timing.recs.clear();
+            g_timing.on = true;
+            return;
+        }
+        g_timing.on = false;
+        hts_kernel_times t[2][2];
+        std::memset(t, 0, sizeof(t));
+        for (auto &r : g_timing.recs) {
+            HTS_HIP(hipEventSynchronize(r.b));
+            float ms = 0.0f;
+            HTS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            hts_kernel_times &c = t[r.field][r.prec];
+            c.launches++;
+            c.ms += ms;
+            c.bytes += r.bytes;
+            c.flops += r.flops;
+            g_timing.pool.push_back(r.a);
+            g_timing.pool.push_back(r.b);
+        }
+        g_timing.recs.clear();
+        if (out) std::memcpy(out, t, sizeof(t));
+    });
+}
+
 hts_status hts_apply_operator(hts_mesh *m, hts_field field, hts_precision prec, double dt, const void *x_dev,
                               void *y_dev)
 {
@@ -1099,6 +1315,76 @@ hts_status hts_apply_operator(hts_mesh *m, hts_field field, hts_precision prec, 
             EpiArgs<float> ep{};
             b.apply_op<float>(t, EPI_STORE, true, (const float *)x_dev, (float *)y_dev, ep);
         }
+    });
+}
+
+// Time the fine-level operators of each mesh for several z-chunk depths
+// (the depth of node planes one workgroup marches through) and keep the
+// fastest per (degree, field, node dims).
+hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
+{
+    return guard_call([&] {
+        if (!meshes || n < 1) throw Error(HTS_ERR_ARG, "no meshes");
+        for (int i = 0; i < n; i++) check_ready(meshes[i]);
+        tuned_zc(1, 0, 0, 0, 0);   // load the cache file once
+        for (int i = 0; i < n; i++) {
+            hts_mesh *m = meshes[i];
+            HTS_HIP(hipSetDevice(m->desc.device));
+            auto B = solo_batch(m);
+            Batch &b = *B;
+            const double dt = 86400.0;
+            HTS_HIP(hipMemcpyAsync(b.P1.p, m->P.p, m->nnode * sizeof(double), hipMemcpyDeviceToDevice, b.s));
+            std::vector<int32_t> all(1, 1);
+            b.set_active(all);
+            VecCtx v = b.vctx(false);
+            vpiezo32(v, b.massH.d64.p, b.P1.p, b.P32.p);
+            std::vector<double> tn(1, m->t + dt), fs(1, dt);
+            b.set_time(tn, fs);
+            launch_source_values(b.lsrc.p, b.nlsrc, b.S.p, b.lcoef.p, b.s);
+            vfill<double>(v, b.inner_x.p, 1.0);
+            vfill<float>(v, b.x32.p, 1.0f);
+            hipEvent_t e0, e1;
+            HTS_HIP(hipEventCreate(&e0));
+            HTS_HIP(hipEventCreate(&e1));
+            for (int f = 0; f < 2; f++) {
+                Tables &t = b.apply_tables(f, dt, f == 0 && m->B <= 0.0);
+                const int cands[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+                double best = 1e30;
+                int bz = 0;
+                for (int zc : cands) {
+                    if (zc > m->N[2] && bz > 0) break;
+                    b.zc_force[f] = zc;
+                    b.build_work();
+                    EpiArgs<double> e64{};
+                    e64.b = b.inner_x.p;
+                    EpiArgs<float> e32{};
+                    e32.b = b.x32.p;
+                    for (int w = 0; w < 2; w++) {
+                        b.apply_op<double>(t, EPI_RESID, true, b.inner_x.p, b.y.p, e64);
+                        b.apply_op<float>(t, EPI_RESID, true, b.x32.p, b.y32.p, e32);
+                    }
+                    HTS_HIP(hipEventRecord(e0, b.s));
+                    for (int r = 0; r < 10; r++) {
+                        b.apply_op<double>(t, EPI_RESID, true, b.inner_x.p, b.y.p, e64);
+                        b.apply_op<float>(t, EPI_RESID, true, b.x32.p, b.y32.p, e32);
+                    }
+                    HTS_HIP(hipEventRecord(e1, b.s));
+                    HTS_HIP(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    HTS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) {
+                        best = ms;
+                        bz = zc;
+                    }
+                }
+                b.zc_force[f] = 0;
+                set_tuned_zc(m->p, f, m->N[0], m->N[1], m->N[2], bz);
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+        save_tuning();
+        for (int i = 0; i < n; i++) meshes[i]->batches.clear();
     });
 }
 

@@ -322,17 +322,30 @@ __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partia
                                                double *S, int32_t *active, int maxit, double aux,
                                                double *out)
 {
-    __shared__ double sh[4];
     __shared__ double vals[64];
     const int inst = blockIdx.x;
     if (active && !active[inst]) return;
     const int b = seg_ptr[inst], e = seg_ptr[inst + 1];
-    for (int c = 0; c < ncomp; c++) {
-        double a = 0.0;
-        for (int t = b + threadIdx.x; t < e; t += VB) a += partial[(int64_t)seg_idx[t] * ncomp + c];
-        a = block_sum(a, sh);
-        if (threadIdx.x == 0) vals[c] = a;
+    // fixed summation order: few components use the whole block each, many
+    // components one wave each
+    if (ncomp <= 2) {
+        __shared__ double sh[4];
+        for (int c = 0; c < ncomp; c++) {
+            double a = 0.0;
+            for (int t = b + threadIdx.x; t < e; t += VB) a += partial[(int64_t)seg_idx[t] * ncomp + c];
+            a = block_sum(a, sh);
+            if (threadIdx.x == 0) vals[c] = a;
+        }
+    } else {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int c = w; c < ncomp; c += VB / 64) {
+            double a = 0.0;
+            for (int t = b + lane; t < e; t += 64) a += partial[(int64_t)seg_idx[t] * ncomp + c];
+            a = wave_sum(a);
+            if (lane == 0) vals[c] = a;
+        }
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         if (out)
             for (int c = 0; c < ncomp; c++) out[(int64_t)inst * ncomp + c] = vals[c];
