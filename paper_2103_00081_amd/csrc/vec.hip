@@ -328,19 +328,44 @@ __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partia
     const int b = seg_ptr[inst], e = seg_ptr[inst + 1];
     // fixed summation order: few components use the whole block each, many
     // components one wave each
+    // Each thread adds the entries t, t + stride, t + 2 stride, ... in that
+    // order; the loads of four consecutive entries are issued together.
     if (ncomp <= 2) {
         __shared__ double sh[4];
+        double a[2] = {0.0, 0.0};
+        for (int t = b + threadIdx.x; t < e; t += 4 * VB) {
+            int64_t id[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) id[u] = t + u * VB < e ? (int64_t)seg_idx[t + u * VB] * ncomp : -1;
+            double p[4][2];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) p[u][c] = (id[u] >= 0 && c < ncomp) ? partial[id[u] + c] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (id[u] >= 0) {
+                    a[0] += p[u][0];
+                    a[1] += p[u][1];
+                }
+        }
         for (int c = 0; c < ncomp; c++) {
-            double a = 0.0;
-            for (int t = b + threadIdx.x; t < e; t += VB) a += partial[(int64_t)seg_idx[t] * ncomp + c];
-            a = block_sum(a, sh);
-            if (threadIdx.x == 0) vals[c] = a;
+            const double r = block_sum(a[c], sh);
+            if (threadIdx.x == 0) vals[c] = r;
         }
     } else {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         for (int c = w; c < ncomp; c += VB / 64) {
             double a = 0.0;
-            for (int t = b + lane; t < e; t += 64) a += partial[(int64_t)seg_idx[t] * ncomp + c];
+            for (int t = b + lane; t < e; t += 4 * 64) {
+                double p[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    p[u] = t + u * 64 < e ? partial[(int64_t)seg_idx[t + u * 64] * ncomp + c] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    if (t + u * 64 < e) a += p[u];
+            }
             a = wave_sum(a);
             if (lane == 0) vals[c] = a;
         }
