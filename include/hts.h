@@ -270,20 +270,78 @@ hts_status hts_kernel_timing(int32_t enable, hts_kernel_times out[2][2]);
 const char *hts_last_error(void);
 
 /* -------------------------------------------------- learned preconditioner */
+/* A 3D convolutional encoder-decoder (levels L in 2..4, widths channels[l],
+ * multiples of 8 up to 64; 3x3x3 kernels, zero padding 1, ReLU, stride-2
+ * downsampling, linear upsampling, additive skips) maps the normalised
+ * pressure residual r / rms(r) and the standardised node log10 permeability
+ * to an error estimate e / (gamma rms(r)).  Layers in parameter order:
+ * enc0a (2 -> c0), enc0b (c0 -> c0), then down_l (stride 2, c_{l-1} -> c_l)
+ * and enc_l (c_l -> c_l) for l = 1..L-1, then dec_l (c_{l+1} -> c_l) for
+ * l = L-2..0 with d_l = relu(dec_l(up d_{l+1})) + e_l, then out (c0 -> 1).
+ * BF16 weights and activations, FP32 accumulation on the matrix cores, FP32
+ * master weights with Adam.  Used by HTS_MODE_LEARNED as the preconditioner
+ * of flexible CG for Eq. 3, with the V-cycle as fallback; every converged
+ * answer is judged by the FP64 residual. */
 
+/* Create a network with He-normal weights drawn from desc->seed (output
+ * layer scaled by 0.1, zero biases).  HTS_ERR_ARG on bad levels/channels. */
 hts_status hts_nn_create(const hts_nn_desc *desc, hts_nn **out);
 void hts_nn_destroy(hts_nn *nn);
 
-/* Run plain multigrid-CG pressure solves of n_steps steps on each mesh and
- * keep (r_k, e_k = x* - x_k) pairs with the log10 permeability as input. */
+/* Parameter vector in exchange layout: per layer in the order above,
+ * W[cout][cin][kz][ky][kx] (cross-correlation weights) then b[cout]; host
+ * FP64.  Set converts to FP32 masters and BF16 compute copies.
+ * HTS_ERR_ARG when count differs from hts_nn_num_params. */
+hts_status hts_nn_num_params(const hts_nn *nn, int64_t *count);
+hts_status hts_nn_set_params(hts_nn *nn, const double *theta, int64_t count);
+hts_status hts_nn_get_params(const hts_nn *nn, double *theta, int64_t count);
+
+/* One forward pass on a node grid dims = {NX, NY, NZ} (x fastest), host
+ * arrays: input [n][2] FP32 (residual, feature; rounded to BF16), out [n]
+ * FP32 network output.  With target [n] (rounded to BF16): loss = mean
+ * over nodes with mask == 0 (mask NULL: all) of (out - target)^2, and, if
+ * grad is not NULL, its gradient in exchange layout (FP64 host array of
+ * hts_nn_num_params entries), by the library's backward kernels. */
+hts_status hts_nn_eval(hts_nn *nn, const int32_t dims[3], const float *input, const float *target,
+                       const uint8_t *mask, float *out, double *loss, double *grad);
+
+/* One 3x3x3 convolution layer (zero padding 1, stride 1 or 2) on the BF16
+ * matrix cores, exposed for verification.  Host arrays; tensors are
+ * channels-last [voxel][channel] with x fastest, voxel grid din = {NX, NY,
+ * NZ} at the input and ((din - 1) / stride + 1) at the output; BF16 as
+ * uint16 bit patterns; w [cout][cin][3][3][3] (kz, ky, kx); cin, cout
+ * multiples of 8 in [8, 64].
+ *   op 0: out[o][co] = bias[co] + sum w x            (x, w, bias optional)
+ *   op 1: out[i][ci] = gradient of sum(g * conv(x)) w.r.t. x   (g, w)
+ *   op 2: out = gradient w.r.t. w in w's layout; out_bias[co] = sum g (x, g)
+ * FP32 results; stream may be NULL. */
+hts_status hts_nn_conv3d(int32_t op, int32_t cin, int32_t cout, int32_t stride, const int32_t din[3],
+                         const uint16_t *x, const uint16_t *w, const float *bias, const uint16_t *g, float *out,
+                         float *out_bias, void *stream);
+
+/* For each of the n_draws meshes (same node grid, pressure state set): run
+ * n_steps plain multigrid-CG pressure steps (Eq. 3, FP64, rtol 1e-10) from the
+ * mesh's state without changing it, and from every inner CG solve keep up to
+ * pairs_per_solve iterates x_k, evenly spaced, as pairs
+ * (r_k = A e_k, e_k = x* - x_k), both divided by rms(r_k) and stored as
+ * BF16, with the draw's node feature and Dirichlet mask.  Pairs accumulate
+ * over calls. */
 hts_status hts_nn_harvest(hts_nn *nn, hts_mesh *const *meshes, int32_t n_draws, int32_t n_steps,
                           double dt, int32_t pairs_per_solve);
 
-/* Train on the harvested pairs with the library's own BF16 MFMA forward and
- * backward kernels and FP32 Adam. */
-hts_status hts_nn_train(hts_nn *nn, int32_t epochs, double lr, int32_t batch,
+/* Train on the harvested pairs of every draw but the last val_draws with the
+ * library's BF16 forward and backward kernels and FP32 Adam (beta 0.9,
+ * 0.999, eps 1e-8), minibatches of `batch` pairs (gradients averaged),
+ * shuffled with the network seed.  On the first call gamma is set to the
+ * median rms(e)/rms(r) of the training pairs and targets are divided by
+ * it.  out: mean training loss of the first and last epoch and the mean loss
+ * on the pairs of the held-out draws. */
+hts_status hts_nn_train(hts_nn *nn, int32_t epochs, double lr, int32_t batch, int32_t val_draws,
                         hts_train_stats *out);
 
+/* Parameters and gamma to / from a binary file (magic "HTSNN001", levels,
+ * channels, gamma, count, FP64 exchange-layout parameters).  Load checks
+ * the architecture; HTS_ERR_ARG on mismatch or I/O failure. */
 hts_status hts_nn_save(const hts_nn *nn, const char *path);
 hts_status hts_nn_load(hts_nn *nn, const char *path);
 

@@ -100,22 +100,35 @@ def upsample_adj(f: np.ndarray, coarse_dims) -> np.ndarray:
     return np.einsum("zk,yj,xi,czyx->ckji", Uz, Uy, Ux, f, optimize=True)
 
 
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64.
+    Used to state the storage precision of the GPU network; the pins run the
+    oracle without it."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
 def _conv(x, w, b, s):
     return conv3d_fwd(x[None], w, b, stride=s, pad=1)[0]
 
 
-def forward(theta, levels, ch, inp: np.ndarray, cin: int = 2):
-    """inp [cin][z][y][x] -> (out [z][y][x], cache)."""
+def forward(theta, levels, ch, inp: np.ndarray, cin: int = 2, act_round=None):
+    """inp [cin][z][y][x] -> (out [z][y][x], cache).  act_round, if given, is
+    applied to every stored activation (each hidden layer output, each
+    upsampled tensor and each skip sum), as a network that keeps its
+    activations in a narrower type does."""
     layers = unpack(theta, levels, ch, cin)
-    cache = {"in": inp, "pre": [], "act": [], "skip_in": []}
-    li = 0
+    cache = {"in": inp, "pre": [], "act": []}
+    rnd = act_round if act_round is not None else (lambda a: a)
 
     def run(x, k):
         name, w, b, s, relu = layers[k]
         pre = _conv(x, w, b, s)
         cache["pre"].append(pre)
         cache["act"].append(x)
-        return np.maximum(pre, 0.0) if relu else pre
+        return rnd(np.maximum(pre, 0.0)) if relu else pre
 
     h = run(inp, 0)
     e = [run(h, 1)]
@@ -126,8 +139,8 @@ def forward(theta, levels, ch, inp: np.ndarray, cin: int = 2):
         li += 2
     d = e[-1]
     for l in range(levels - 2, -1, -1):
-        u = upsample(d, e[l].shape[1:])
-        d = run(u, li) + e[l]
+        u = rnd(upsample(d, e[l].shape[1:]))
+        d = rnd(run(u, li) + e[l])
         li += 1
     y = run(d, li)
     cache["e"] = e
@@ -141,16 +154,19 @@ def loss(y0, target, mask):
     return float((diff * diff).sum() / nf), 2.0 * diff / nf
 
 
-def backward(theta, levels, ch, cache, gy0: np.ndarray, cin: int = 2):
-    """Gradient of sum(gy0 * out) with respect to theta (flat, parameter order)."""
+def backward(theta, levels, ch, cache, gy0: np.ndarray, cin: int = 2, grad_round=None):
+    """Gradient of sum(gy0 * out) with respect to theta (flat, parameter order).
+    grad_round, if given, is applied to each layer's pre-activation gradient
+    before it enters the two convolution gradients."""
     layers = unpack(theta, levels, ch, cin)
     grads = [None] * len(layers)
+    rnd = grad_round if grad_round is not None else (lambda a: a)
 
     def back(k, gout):
         """gout: gradient w.r.t. the layer's output after its activation."""
         name, w, b, s, relu = layers[k]
         pre, x = cache["pre"][k], cache["act"][k]
-        g = gout * (pre > 0) if relu else gout
+        g = rnd(gout * (pre > 0) if relu else gout)
         gw, gb = conv3d_bwd_weight(x[None], g[None], 3, stride=s, pad=1)
         grads[k] = (gw, gb)
         return conv3d_bwd_data(g[None], w, (1,) + x.shape, stride=s, pad=1)[0]

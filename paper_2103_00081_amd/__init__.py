@@ -32,7 +32,8 @@ EXPORTS = [
     "hts_add_dirichlet_column", "hts_set_state", "hts_get_state", "hts_mesh_sizes",
     "hts_apply_operator", "hts_solve_steady_pressure", "hts_solve_step", "hts_advance",
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
-    "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing",
+    "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing", "hts_nn_num_params",
+    "hts_nn_set_params", "hts_nn_get_params", "hts_nn_eval", "hts_nn_conv3d",
 ]
 
 
@@ -144,7 +145,12 @@ def load():
         "hts_nn_create": (st, [P(NNDesc), P(vp)]),
         "hts_nn_destroy": (None, [vp]),
         "hts_nn_harvest": (st, [vp, P(vp), i32, i32, d, i32]),
-        "hts_nn_train": (st, [vp, i32, d, i32, P(TrainStats)]),
+        "hts_nn_train": (st, [vp, i32, d, i32, i32, P(TrainStats)]),
+        "hts_nn_num_params": (st, [vp, P(C.c_int64)]),
+        "hts_nn_set_params": (st, [vp, vp, C.c_int64]),
+        "hts_nn_get_params": (st, [vp, vp, C.c_int64]),
+        "hts_nn_eval": (st, [vp, P(i32), vp, vp, vp, vp, P(d), vp]),
+        "hts_nn_conv3d": (st, [i32, i32, i32, i32, P(i32), vp, vp, vp, vp, vp, vp, vp]),
         "hts_nn_save": (st, [vp, C.c_char_p]),
         "hts_nn_load": (st, [vp, C.c_char_p]),
         "hts_kernel_timing": (st, [i32, vp]),
@@ -332,6 +338,95 @@ def autotune(meshes: Sequence[Mesh]):
     n = len(meshes)
     arr = (C.c_void_p * n)(*[m.h.value for m in meshes])
     _check(load().hts_autotune(arr, n))
+
+
+# ------------------------------------------------- learned preconditioner
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Net:
+    """Owner of one hts_nn (the learned preconditioner network)."""
+
+    def __init__(self, levels=4, channels=(16, 32, 48, 64), device=0, stream=None, seed=0):
+        import torch
+        ch = list(channels) + [0] * (4 - len(channels))
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        d = NNDesc(levels, (C.c_int32 * 4)(*ch), device, C.c_void_p(stream), seed)
+        self.h = C.c_void_p()
+        _check(load().hts_nn_create(C.byref(d), C.byref(self.h)))
+        self.levels, self.channels = levels, tuple(channels[:levels])
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hts_nn_destroy(h)
+            self.h = None
+
+    def num_params(self) -> int:
+        n = C.c_int64()
+        _check(load().hts_nn_num_params(self.h, C.byref(n)))
+        return n.value
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        _check(load().hts_nn_set_params(self.h, _np_ptr(th), th.size))
+
+    def get_params(self):
+        th = np.empty(self.num_params())
+        _check(load().hts_nn_get_params(self.h, _np_ptr(th), th.size))
+        return th
+
+    def eval(self, dims, inp, target=None, mask=None, grad=False):
+        """dims (NX, NY, NZ); inp [n][2] -> (out [n], loss, grad or None)."""
+        n = int(np.prod(dims))
+        x = np.ascontiguousarray(inp, dtype=np.float32).reshape(n, 2)
+        t = None if target is None else np.ascontiguousarray(target, dtype=np.float32).reshape(n)
+        m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(n)
+        out = np.empty(n, dtype=np.float32)
+        lv = C.c_double(0.0)
+        g = np.empty(self.num_params()) if grad else None
+        dd = (C.c_int32 * 3)(*dims)
+        _check(load().hts_nn_eval(self.h, dd, _np_ptr(x), _np_ptr(t), _np_ptr(m), _np_ptr(out),
+                                  C.byref(lv) if t is not None else None, _np_ptr(g)))
+        return out, (lv.value if t is not None else None), g
+
+    def harvest(self, meshes, n_steps, dt, pairs_per_solve):
+        arr = (C.c_void_p * len(meshes))(*[mm.h.value for mm in meshes])
+        _check(load().hts_nn_harvest(self.h, arr, len(meshes), n_steps, dt, pairs_per_solve))
+
+    def train(self, epochs, lr, batch, val_draws):
+        st = TrainStats()
+        _check(load().hts_nn_train(self.h, epochs, lr, batch, val_draws, C.byref(st)))
+        return {"epochs": st.epochs_done, "pairs": st.pairs, "loss_first": st.loss_first,
+                "loss_last": st.loss_last, "val_loss": st.val_loss}
+
+    def save(self, path):
+        _check(load().hts_nn_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        _check(load().hts_nn_load(self.h, str(path).encode()))
+
+
+def conv3d(op, cin, cout, stride, din, x=None, w=None, bias=None, g=None):
+    """One BF16 matrix-core convolution layer (verification entry point).
+    x, g: uint16 BF16 bit patterns [voxel][channel]; w: uint16 [cout][cin][3][3][3]."""
+    di = (C.c_int32 * 3)(*din)
+    dout = [(n - 1) // stride + 1 for n in din]
+    nin, nout = int(np.prod(din)), int(np.prod(dout))
+    if op == 0:
+        out = np.empty((nout, cout), dtype=np.float32)
+    elif op == 1:
+        out = np.empty((nin, cin), dtype=np.float32)
+    else:
+        out = np.empty((cout, cin, 3, 3, 3), dtype=np.float32)
+    ob = np.empty(cout, dtype=np.float32) if op == 2 else None
+    c = lambda a, dt: None if a is None else np.ascontiguousarray(a, dtype=dt)
+    x, w, g, b = c(x, np.uint16), c(w, np.uint16), c(g, np.uint16), c(bias, np.float32)
+    _check(load().hts_nn_conv3d(op, cin, cout, stride, di, _np_ptr(x), _np_ptr(w), _np_ptr(b),
+                                _np_ptr(g), _np_ptr(out), _np_ptr(ob), None))
+    return (out, ob) if op == 2 else out
 
 
 # --------------------------------------------------- scenario marshalling

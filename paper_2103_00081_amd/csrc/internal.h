@@ -175,11 +175,19 @@ struct hts_mesh {
     hts::DBuf<double> load[2];
 
     std::map<std::string, std::shared_ptr<hts::Batch>> batches;   // cached solo batches
+
+    // learned-preconditioner inputs: normalised node log-permeability and
+    // the pressure Dirichlet mask (rebuilt after prepare_mesh)
+    hts::DBuf<float> nn_feat;
+    hts::DBuf<uint8_t> nn_mask;
+    double nn_nfree = 0.0;
+    bool nn_ready = false;
 };
 
 namespace hts {
 
 void prepare_mesh(hts_mesh *m);                 // (re)build derived device data
+bool is_constrained(const hts_mesh *m, int field, int i, int j, int k);   // host, after prepare_mesh
 OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, bool mass_only);
 
 }  // namespace hts

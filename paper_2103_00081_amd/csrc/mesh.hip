@@ -72,7 +72,7 @@ static inline int64_t node_index(const hts_mesh *m, int i, int j, int k)
     return (int64_t)i + (int64_t)m->N[0] * ((int64_t)j + (int64_t)m->N[1] * k);
 }
 
-static bool is_constrained(const hts_mesh *m, int field, int i, int j, int k)
+bool is_constrained(const hts_mesh *m, int field, int i, int j, int k)
 {
     const int dm = m->dmask[field];
     if (((dm & 1) && i == 0) || ((dm & 2) && i == m->N[0] - 1) || ((dm & 4) && j == 0) ||
@@ -351,6 +351,7 @@ void prepare_mesh(hts_mesh *m)
     }
     m->batches.clear();
     m->dirty = false;
+    m->nn_ready = false;
 }
 
 OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, bool mass_only)

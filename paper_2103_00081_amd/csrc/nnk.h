@@ -35,5 +35,12 @@ void nn_loss(const float *Y, int ldy, const uint16_t *T, const uint8_t *mask, in
 void nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
              int step, float gscale, uint16_t *wbf, const uint8_t *live, hipStream_t s);
 void nn_f32_to_bf16(const float *a, int64_t n, uint16_t *b, hipStream_t s);
+void nn_pack_input_bf(const uint16_t *r, const float *feat, int64_t n, uint16_t *X, hipStream_t s);
+void nn_pack_input_dev(const double *r, const double *rr, double nfree, const float *feat, int64_t n, uint16_t *X,
+                       hipStream_t s);
+void nn_unpack_output_dev(const float *Y, int ldy, const double *rr, double nfree, double gamma, const uint8_t *mask,
+                          int64_t n, double *z, hipStream_t s);
+void nn_scale_bf16(uint16_t *a, int64_t n, float c, hipStream_t s);
+void nn_add_bf16(const uint16_t *a, const uint16_t *b, int64_t n, uint16_t *c, hipStream_t s);
 
 }  // namespace hts

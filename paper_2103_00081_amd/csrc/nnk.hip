@@ -445,7 +445,10 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (live && !live[i]) { wbf[i] = 0; return; }
+    if (live && !live[i]) {
+        if (wbf) wbf[i] = 0;
+        return;
+    }
     const float gi = g[i] * gscale;
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -453,13 +456,69 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     v[i] = vi;
     const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
     w[i] = wi;
-    wbf[i] = f2bf(wi);
+    if (wbf) wbf[i] = f2bf(wi);
 }
 
 __global__ void k_f32_to_bf16(const float *__restrict__ a, int64_t n, uint16_t *__restrict__ b)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) b[i] = f2bf(a[i]);
+}
+
+// network input from a stored pair: channel 0 = r (BF16), channel 1 = feature
+__global__ void k_pack_input_bf(const uint16_t *__restrict__ r, const float *__restrict__ feat, int64_t n,
+                                uint16_t *__restrict__ X)
+{
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    uint16_t o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    o[0] = r[v];
+    o[1] = f2bf(feat[v]);
+    *reinterpret_cast<uint4 *>(X + v * 8) = __builtin_bit_cast(uint4, o);
+}
+
+// network input in a solve: channel 0 = r / rms(r) with rms(r)^2 = rr / nfree
+// read from device memory
+__global__ void k_pack_input_dev(const double *__restrict__ r, const double *__restrict__ rr, double nfree,
+                                 const float *__restrict__ feat, int64_t n, uint16_t *__restrict__ X)
+{
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const double q = *rr;
+    const double sc = q > 0.0 ? sqrt(nfree / q) : 0.0;
+    uint16_t o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    o[0] = f2bf((float)(r[v] * sc));
+    o[1] = f2bf(feat[v]);
+    *reinterpret_cast<uint4 *>(X + v * 8) = __builtin_bit_cast(uint4, o);
+}
+
+// z = gamma rms(r) out[v][0], zero where mask
+__global__ void k_unpack_output_dev(const float *__restrict__ Y, int ldy, const double *__restrict__ rr,
+                                    double nfree, double gamma, const uint8_t *__restrict__ mask, int64_t n,
+                                    double *__restrict__ z)
+{
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const double q = *rr;
+    const double sc = q > 0.0 ? sqrt(q / nfree) : 0.0;
+    double val = gamma * sc * (double)Y[v * ldy];
+    if (mask && mask[v]) val = 0.0;
+    z[v] = val;
+}
+
+// c = bf16(a + b)
+__global__ void k_add_bf16(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, int64_t n,
+                           uint16_t *__restrict__ c)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) c[e] = f2bf(bf2f(a[e]) + bf2f(b[e]));
+}
+
+// a = bf16(a * c)
+__global__ void k_scale_bf16(uint16_t *__restrict__ a, int64_t n, float c)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) a[e] = f2bf(bf2f(a[e]) * c);
 }
 
 inline dim3 g256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -606,6 +665,38 @@ void nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, 
 {
     const float c1 = 1.f / (1.f - powf(b1, (float)step)), c2 = 1.f / (1.f - powf(b2, (float)step));
     k_adam<<<g256(n), dim3(256), 0, s>>>(w, m, v, g, n, lr, b1, b2, eps, c1, c2, gscale, wbf, live);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_pack_input_bf(const uint16_t *r, const float *feat, int64_t n, uint16_t *X, hipStream_t s)
+{
+    k_pack_input_bf<<<g256(n), dim3(256), 0, s>>>(r, feat, n, X);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_pack_input_dev(const double *r, const double *rr, double nfree, const float *feat, int64_t n, uint16_t *X,
+                       hipStream_t s)
+{
+    k_pack_input_dev<<<g256(n), dim3(256), 0, s>>>(r, rr, nfree, feat, n, X);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_unpack_output_dev(const float *Y, int ldy, const double *rr, double nfree, double gamma, const uint8_t *mask,
+                          int64_t n, double *z, hipStream_t s)
+{
+    k_unpack_output_dev<<<g256(n), dim3(256), 0, s>>>(Y, ldy, rr, nfree, gamma, mask, n, z);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_add_bf16(const uint16_t *a, const uint16_t *b, int64_t n, uint16_t *c, hipStream_t s)
+{
+    k_add_bf16<<<g256(n), dim3(256), 0, s>>>(a, b, n, c);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_scale_bf16(uint16_t *a, int64_t n, float c, hipStream_t s)
+{
+    k_scale_bf16<<<g256(n), dim3(256), 0, s>>>(a, n, c);
     HTS_LAUNCH_CHECK();
 }
 

@@ -64,7 +64,7 @@ struct Hier {
 };
 
 struct FieldStats {
-    std::vector<int> status, iters, outer;
+    std::vector<int> status, iters, outer, fallbacks;
     std::vector<double> relres;
     double ms = 0.0;
 };
@@ -122,6 +122,12 @@ struct Batch {
     std::map<std::pair<int, double>, std::unique_ptr<Hier>> hier;
     std::unique_ptr<Hier> heat;
 
+    // observers used to harvest training pairs for the learned preconditioner:
+    // cg_hook(x, k) sees the iterate x_k of every FP64 CG solve (k = 0 first),
+    // inner_hook(A, x*) each converged FP64 inner pressure solution
+    std::function<void(const double *, int)> cg_hook;
+    std::function<void(const Tables &, const double *)> inner_hook;
+
     ~Batch();
     int pick_zc(int field, const hts_mesh *M, int64_t tiles) const;
     void build_work();
@@ -178,6 +184,8 @@ struct Batch {
 };
 
 std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms);
+// learned preconditioner on one instance's slice: z = gamma rms(r) Net(r / rms(r), feature)
+void nn_precondition(hts_nn *nn, Batch &B, int inst, const double *r, double *z);
 // tuned z-chunk depth of the fine operator kernels (0 = none recorded)
 int tuned_zc(int degree, int field, int NX, int NY, int NZ);
 void set_tuned_zc(int degree, int field, int NX, int NY, int NZ, int zc);

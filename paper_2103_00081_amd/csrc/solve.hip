@@ -860,6 +860,8 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
     apply_op<T>(A, EPI_RESID_NORM, true, x, r, ep);
     vreduce(rwk[A.field], partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
     if (!any_active()) return 0;
+    const bool hook = std::is_same<T, double>::value && cg_hook;
+    if (hook) cg_hook(reinterpret_cast<const double *>(x), 0);
     M(r, z);
     vdot<T>(v, r, z, nullptr, partial.p);
     vreduce(rch, partial.p, 2, RED_STORE, S_RZ, S.p, active.p, 0, 0.0, nullptr, s);
@@ -871,6 +873,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
         apply_op<T>(A, EPI_DOT, true, pv, q, e2);
         vreduce(rwk[A.field], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
         vcg_update<T>(v, x, r, pv, q, ro, partial.p);
+        if (hook) cg_hook(reinterpret_cast<const double *>(x), it);
         vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
         if (it % std::max(1, check_every) == 0 || it == maxit)
             if (!any_active()) break;
@@ -972,7 +975,11 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
     st.iters.assign(n, 0);
     st.outer.assign(n, 0);
     st.relres.assign(n, 0.0);
+    st.fallbacks.assign(n, 0);
     const bool fp32 = o.mode == HTS_MODE_FP32_REFINED;
+    const bool learned = o.mode == HTS_MODE_LEARNED && field == 0;
+    if (learned && !o.nn) throw Error(HTS_ERR_ARG, "learned mode needs opts.nn");
+    if (learned && !mg) throw Error(HTS_ERR_STATE, "learned mode needs the multigrid fallback");
     const double rtol = o.rtol > 0 ? o.rtol : 1e-8;
     const int maxit = std::max(1, o.max_iter);
     hipEvent_t e0, e1;
@@ -1021,12 +1028,60 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
                 if (mg) vcycle<double>(*mg, 0, r_, z_);
                 else cheb_prec<double>(*hprec, r_, z_);
             };
-            if (field == 0)
+            if (learned) {
+                // Flexible CG with the network as preconditioner.  Fallback:
+                // after two consecutive NN-preconditioned iterations that each
+                // leave ||r_{k+1}|| > 0.9 ||r_k||, or a non-finite residual or
+                // network output, the instance uses the V-cycle for the rest
+                // of this solve.
+                std::vector<double> prev(n, -1.0);
+                std::vector<int> fails(n, 0), fb(n, 0);
+                auto ML = [&](const double *r_, double *z_) {
+                    download_S();
+                    const std::vector<int32_t> act = get_active();
+                    std::vector<int32_t> use_nn(n, 0), use_mg(n, 0);
+                    bool any_nn = false, any_mg = false;
+                    for (int i = 0; i < n; i++) {
+                        if (!act[i]) continue;
+                        const double rr = hS[(size_t)i * NSLOT + S_RR];
+                        if (!fb[i]) {
+                            if (!std::isfinite(rr)) fb[i] = 1;
+                            else if (prev[i] >= 0.0 && rr > 0.81 * prev[i]) fb[i] = ++fails[i] >= 2;
+                            else fails[i] = 0;
+                            prev[i] = rr;
+                            if (fb[i]) st.fallbacks[i]++;
+                        }
+                        if (fb[i]) use_mg[i] = 1, any_mg = true;
+                        else use_nn[i] = 1, any_nn = true;
+                    }
+                    if (any_nn) {
+                        for (int i = 0; i < n; i++)
+                            if (use_nn[i]) nn_precondition(o.nn, *this, i, r_, z_);
+                        vdot<double>(vctx(), z_, z_, nullptr, partial.p);
+                        vreduce(rch, partial.p, 2, RED_STORE, S_TMP2, S.p, active.p, 0, 0.0, nullptr, s);
+                        download_S();
+                        for (int i = 0; i < n; i++)
+                            if (use_nn[i] && !std::isfinite(hS[(size_t)i * NSLOT + S_TMP2])) {
+                                fb[i] = 1;
+                                st.fallbacks[i]++;
+                                use_mg[i] = 1;
+                                any_mg = true;
+                            }
+                    }
+                    if (any_mg) {
+                        set_active(use_mg);
+                        vcycle<double>(*mg, 0, r_, z_);
+                        set_active(act);
+                    }
+                };
+                cg<double>(A, ML, inner_b.p, inner_x.p, maxit, true, 1);
+            } else if (field == 0) {
                 cg<double>(A, M, inner_b.p, inner_x.p, maxit, false, o.check_every);
-            else
+            } else
                 fgmres<double>(A, M, inner_b.p, inner_x.p, maxit, std::max(2, std::min(o.gmres_restart, 60)),
                                o.check_every);
         }
+        if (inner_hook && field == 0 && !fp32) inner_hook(A, inner_x.p);
         download_S();
         for (int i = 0; i < n; i++)
             if (outer[i]) {
@@ -1205,7 +1260,7 @@ int Batch::step(double dt, const hts_solver_opts &o, std::vector<hts_step_stats>
             x.relres[0] = sp.relres[i]; x.relres[1] = sh.relres[i];
             x.status[0] = sp.status[i]; x.status[1] = sh.status[i];
             x.time_ms[0] = sp.ms; x.time_ms[1] = sh.ms;
-            x.fallbacks = 0;
+            x.fallbacks = sp.fallbacks[i];
         }
     }
     if (rc == HTS_OK) {
@@ -1457,3 +1512,7 @@ hts_status hts_advance(hts_mesh *const *meshes, int32_t n, int32_t n_steps, doub
 }
 
 }  // extern "C"
+
+namespace hts {
+template void Batch::apply_op<double>(const Tables &, int, bool, const double *, double *, EpiArgs<double>);
+}  // namespace hts

@@ -133,3 +133,14 @@ def test_planted_backward_mistake_fails_the_check(monkeypatch):
               - nnet.loss(nnet.forward(tm, levels, ch, inp)[0], tgt, None)[0]) / (2 * h)
         worst = max(worst, abs(fd - g[i]) / (abs(fd) + 1e-12))
     assert worst > 1e-2
+
+
+def test_bf16_rounding_ties_to_even():
+    """The storage rounding used to mirror BF16 activations: 8 significant
+    bits, ties to even."""
+    v = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -7, -2.5, 3.0e38, 1e-40])
+    r = nnet.bf16(v)
+    np.testing.assert_array_equal(r[:5], [1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -2.5])
+    assert abs(r[5] - 3.0e38) <= 3.0e38 * 2.0 ** -8
+    x = np.random.default_rng(3).standard_normal(1000)
+    assert np.all(np.abs(nnet.bf16(x) - x) <= np.abs(x) * 2.0 ** -8)
