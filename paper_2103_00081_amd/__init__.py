@@ -191,7 +191,9 @@ def _torch_allocator(device: int) -> Allocator:
         return torch.cuda.caching_allocator_alloc(int(nbytes), device, s)
 
     def _free(ptr, ctx):
-        torch.cuda.caching_allocator_delete(int(ptr))
+        cuda = getattr(torch, "cuda", None)
+        if cuda is not None:   # None once the interpreter is shutting down
+            cuda.caching_allocator_delete(int(ptr))
 
     a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
     _keep.append(a)

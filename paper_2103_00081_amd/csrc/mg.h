@@ -28,8 +28,10 @@ template <typename T>
 void launch_cheb0(const Chunk *chunks, int nchunk, const int32_t *active, const double *S, int slot, const T *invd,
                   const T *b, T *d, T *x, hipStream_t s);
 template <typename T>
+// mask_coarse: zero the result at coarse nodes whose fine node is constrained
+// (coarse operators with eliminated rows there, e.g. the Q1 level under Q2)
 void launch_restrict(const LevelDev *fine, const LevelDev *coarse, const OpDev *fops, const Chunk *cchunks,
-                     int nchunk, const int32_t *active, const T *rf, T *bc, hipStream_t s);
+                     int nchunk, const int32_t *active, const T *rf, T *bc, int mask_coarse, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const LevelDev *fine, const LevelDev *coarse, const OpDev *fops, const Chunk *fchunks,
                         int nchunk, const int32_t *active, const T *xc, T *xf, hipStream_t s);

@@ -105,7 +105,8 @@ __global__ __launch_bounds__(256) void k_cheb0(const Chunk *__restrict__ chunks,
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const LevelDev *__restrict__ fine, const LevelDev *__restrict__ coarse,
                                                   const OpDev *__restrict__ fops, const Chunk *__restrict__ cchunks,
-                                                  const int32_t *active, const T *__restrict__ rf, T *__restrict__ bc)
+                                                  const int32_t *active, const T *__restrict__ rf, T *__restrict__ bc,
+                                                  int mask_coarse)
 {
     const Chunk ch = cchunks[blockIdx.x];
     if (active && !active[ch.inst]) return;
@@ -116,6 +117,12 @@ __global__ __launch_bounds__(256) void k_restrict(const LevelDev *__restrict__ f
         const int64_t n = e - Cc.off;
         const int I = (int)(n % Cc.NX), J = (int)((n / Cc.NX) % Cc.NY), K = (int)(n / cpl);
         const int fi = fpos(I, F.NX), fj = fpos(J, F.NY), fk = fpos(K, F.NZ);
+        // a coarse operator with eliminated (identity) rows where the fine
+        // node under the coarse node is constrained takes no residual there
+        if (mask_coarse && node_constrained(fops[ch.inst], fi + (int64_t)fj * F.NX + (int64_t)fk * fpl)) {
+            bc[e] = T(0);
+            continue;
+        }
         double acc = 0.0;
         for (int dz = -1; dz <= 1; dz++) {
             const int k = fk + dz;
@@ -280,10 +287,11 @@ void launch_cheb0(const Chunk *chunks, int nchunk, const int32_t *active, const 
 
 template <typename T>
 void launch_restrict(const LevelDev *fine, const LevelDev *coarse, const OpDev *fops, const Chunk *cchunks,
-                     int nchunk, const int32_t *active, const T *rf, T *bc, hipStream_t s)
+                     int nchunk, const int32_t *active, const T *rf, T *bc, int mask_coarse, hipStream_t s)
 {
     if (nchunk <= 0) return;
-    k_restrict<T><<<dim3(nchunk), dim3(256), 0, s>>>(fine, coarse, fops, cchunks, active, rf, bc);
+    if (mask_coarse && !fops) throw Error(-1, "coarse masking needs the fine operator descriptors");
+    k_restrict<T><<<dim3(nchunk), dim3(256), 0, s>>>(fine, coarse, fops, cchunks, active, rf, bc, mask_coarse);
     HTS_LAUNCH_CHECK();
 }
 
@@ -324,7 +332,7 @@ void launch_coarse_solve(const CoarseDev *cd, int ninst, int64_t total_rows, con
     template void launch_cheb0<T>(const Chunk *, int, const int32_t *, const double *, int, const T *, const T *, \
                                   T *, T *, hipStream_t);                                                        \
     template void launch_restrict<T>(const LevelDev *, const LevelDev *, const OpDev *, const Chunk *, int,       \
-                                     const int32_t *, const T *, T *, hipStream_t);                              \
+                                     const int32_t *, const T *, T *, int, hipStream_t);                              \
     template void launch_prolong_add<T>(const LevelDev *, const LevelDev *, const OpDev *, const Chunk *, int,   \
                                         const int32_t *, const T *, T *, hipStream_t);                           \
     template void launch_coarse_solve<T>(const CoarseDev *, int, int64_t, const int32_t *, const T *, T *,        \

@@ -1,21 +1,504 @@
-// Matrix-free Q2 operators (placeholder until the Q2 kernels land).
+// Matrix-free Q2 operators of the pressure (Eq. 3) and heat (Eq. 4)
+// equations on a uniform box (27-node hexahedra, 3-point Gauss rules).
+//
+// Kernel layout: a 256-thread workgroup owns the nodes of a 15 x 15 tile of
+// cell columns (30 x 30 node columns) and marches upward through its range of
+// node planes one cell layer at a time.  Each thread handles one cell column
+// of the 16 x 16 cells that touch the owned nodes (one-cell halo on the low
+// x/y side).  Per cell layer the three node planes of the layer are staged in
+// LDS; each thread evaluates its cell's 27 outputs:
+//   mass and stiffness by Kronecker sum factorisation with the 1D Q2
+//   matrices  h/30 [4 2 -1; 2 16 2; -1 2 4]  and  1/(3h) [7 -8 1; -8 16 -8;
+//   1 -8 7]  (exact for cellwise-constant coefficients);
+//   the convection term at the 27 Gauss points from the gradients of T and P
+//   (sum-factorised values and derivatives of the 1D basis).
+// The cell writes its bottom- and middle-plane contributions to LDS and keeps
+// its top plane for the next layer; the owner of a node adds the (up to
+// four) cell contributions of its plane in a fixed order.  No atomics,
+// bitwise reproducible, same epilogues as the Q1 kernel.
 #include "common.h"
+#include "dev_util.h"
 
 namespace hts {
 
+namespace {
+
+constexpr int TC = 16;            // cell columns per tile edge
+constexpr int OWNC = TC - 1;      // owned cells per tile edge
+constexpr int NL = 2 * TC + 1;    // node columns per tile edge staged in LDS
+constexpr int OWNN = 2 * OWNC;    // owned node columns per tile edge
+constexpr int NOWN = OWNN * OWNN; // owned node columns per tile
+constexpr int NSTAGE = NL * NL;   // staged node columns per tile
+constexpr int SPT = (NSTAGE + 255) / 256;   // staged columns per thread
+constexpr int OPT = (NOWN + 255) / 256;     // owned columns per thread
+
+// 1D Q2 basis on [0, 1] with nodes 0, 1/2, 1 at the 3 Gauss points
+constexpr double SQ35 = 0.77459666924148337704;   // sqrt(3/5)
+constexpr double G0 = 0.5 - 0.5 * SQ35, G2 = 0.5 + 0.5 * SQ35;
+constexpr double bN0(double x) { return (2 * x - 1) * (x - 1); }
+constexpr double bN1(double x) { return 4 * x * (1 - x); }
+constexpr double bN2(double x) { return x * (2 * x - 1); }
+constexpr double dN0(double x) { return 4 * x - 3; }
+constexpr double dN1(double x) { return 4 - 8 * x; }
+constexpr double dN2(double x) { return 4 * x - 1; }
+
 template <typename T>
-void launch_q2(int, int, bool, const OpDev *, const WorkItem *, int, const T *, T *, const EpiArgs<T> &, hipStream_t)
+struct Q2Tab {
+    // B[q][i] = N_i(g_q), D[q][i] = N_i'(g_q), W[q] Gauss weights on [0, 1]
+    static constexpr T B[3][3] = {{T(bN0(G0)), T(bN1(G0)), T(bN2(G0))},
+                                  {T(0), T(1), T(0)},
+                                  {T(bN0(G2)), T(bN1(G2)), T(bN2(G2))}};
+    static constexpr T D[3][3] = {{T(dN0(G0)), T(dN1(G0)), T(dN2(G0))},
+                                  {T(-1), T(0), T(1)},
+                                  {T(dN0(G2)), T(dN1(G2)), T(dN2(G2))}};
+    static constexpr T W[3] = {T(5.0 / 18.0), T(8.0 / 18.0), T(5.0 / 18.0)};
+    // reference mass (h = 1) and stiffness (h = 1)
+    static constexpr T M[3][3] = {{T(4.0 / 30), T(2.0 / 30), T(-1.0 / 30)},
+                                  {T(2.0 / 30), T(16.0 / 30), T(2.0 / 30)},
+                                  {T(-1.0 / 30), T(2.0 / 30), T(4.0 / 30)}};
+    static constexpr T K[3][3] = {{T(7.0 / 3), T(-8.0 / 3), T(1.0 / 3)},
+                                  {T(-8.0 / 3), T(16.0 / 3), T(-8.0 / 3)},
+                                  {T(1.0 / 3), T(-8.0 / 3), T(7.0 / 3)}};
+};
+
+// out = (A along the axis of stride S) in, for the 9 lines of a 3x3x3 block
+template <typename T, int S>
+__device__ __forceinline__ void along(const T (&A)[3][3], const T in[27], T out[27])
 {
-    throw Error(-7, "Q2 operators are not available in this build");
+#pragma unroll
+    for (int l = 0; l < 9; l++) {
+        const int base = S == 1 ? 3 * l : (S == 3 ? (l % 3) + 9 * (l / 3) : l);
+        const T a = in[base], b = in[base + S], c = in[base + 2 * S];
+#pragma unroll
+        for (int r = 0; r < 3; r++) out[base + r * S] = A[r][0] * a + A[r][1] * b + A[r][2] * c;
+    }
 }
+
+// w = mV (M x M x M) u + sk (cxx K x M x M + cyy M x K x M + czz M x M x K) u
+// (first factor along x)
+template <typename T>
+__device__ __forceinline__ void q2_mass_stiff(const T u[27], T mV, T sk, T cxx, T cyy, T czz, T w[27])
+{
+    using Q = Q2Tab<T>;
+    T a[27], b[27];
+    along<T, 9>(Q::M, u, a);
+    along<T, 9>(Q::K, u, b);
+    T c[27], d[27];
+    along<T, 3>(Q::M, a, c);
+    along<T, 3>(Q::K, a, d);
+    along<T, 3>(Q::M, b, a);          // a <- M_y K_z u
+    const T sky = sk * cyy, skz = sk * czz, skx = sk * cxx;
+#pragma unroll
+    for (int i = 0; i < 27; i++) b[i] = mV * c[i] + sky * d[i] + skz * a[i];
+    along<T, 1>(Q::M, b, w);
+    along<T, 1>(Q::K, c, d);
+#pragma unroll
+    for (int i = 0; i < 27; i++) w[i] += skx * d[i];
+}
+
+// w_a += cw sum_q W_q N_a(q) (q_h . grad u)(q), q_h = -k (grad P + rho_g e_z),
+// cw = dt c_w V; 3 x 3 x 3 Gauss points, processed one z-plane at a time.
+template <typename T>
+__device__ __forceinline__ void q2_convect(const T u[27], const T P[27], T kc, T ihx, T ihy, T ihz, T rho_g,
+                                          T cw, T w[27])
+{
+    using Q = Q2Tab<T>;
+#pragma unroll
+    for (int qz = 0; qz < 3; qz++) {
+        // values and z-derivatives on the plane qz: f[i + 3 j]
+        T fu[9], fuz[9], fp[9], fpz[9];
+#pragma unroll
+        for (int ij = 0; ij < 9; ij++) {
+            fu[ij] = Q::B[qz][0] * u[ij] + Q::B[qz][1] * u[ij + 9] + Q::B[qz][2] * u[ij + 18];
+            fuz[ij] = Q::D[qz][0] * u[ij] + Q::D[qz][1] * u[ij + 9] + Q::D[qz][2] * u[ij + 18];
+            fp[ij] = Q::B[qz][0] * P[ij] + Q::B[qz][1] * P[ij + 9] + Q::B[qz][2] * P[ij + 18];
+            fpz[ij] = Q::D[qz][0] * P[ij] + Q::D[qz][1] * P[ij + 9] + Q::D[qz][2] * P[ij + 18];
+        }
+        T a[9];   // a[qx + 3 qy]
+#pragma unroll
+        for (int qy = 0; qy < 3; qy++) {
+            // y pass: per x index i
+            T yu[3], yud[3], yuz[3], yp[3], ypd[3], ypz[3];
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                yu[i] = Q::B[qy][0] * fu[i] + Q::B[qy][1] * fu[i + 3] + Q::B[qy][2] * fu[i + 6];
+                yud[i] = Q::D[qy][0] * fu[i] + Q::D[qy][1] * fu[i + 3] + Q::D[qy][2] * fu[i + 6];
+                yuz[i] = Q::B[qy][0] * fuz[i] + Q::B[qy][1] * fuz[i + 3] + Q::B[qy][2] * fuz[i + 6];
+                yp[i] = Q::B[qy][0] * fp[i] + Q::B[qy][1] * fp[i + 3] + Q::B[qy][2] * fp[i + 6];
+                ypd[i] = Q::D[qy][0] * fp[i] + Q::D[qy][1] * fp[i + 3] + Q::D[qy][2] * fp[i + 6];
+                ypz[i] = Q::B[qy][0] * fpz[i] + Q::B[qy][1] * fpz[i + 3] + Q::B[qy][2] * fpz[i + 6];
+            }
+#pragma unroll
+            for (int qx = 0; qx < 3; qx++) {
+                const T gux = Q::D[qx][0] * yu[0] + Q::D[qx][1] * yu[1] + Q::D[qx][2] * yu[2];
+                const T guy = Q::B[qx][0] * yud[0] + Q::B[qx][1] * yud[1] + Q::B[qx][2] * yud[2];
+                const T guz = Q::B[qx][0] * yuz[0] + Q::B[qx][1] * yuz[1] + Q::B[qx][2] * yuz[2];
+                const T gpx = Q::D[qx][0] * yp[0] + Q::D[qx][1] * yp[1] + Q::D[qx][2] * yp[2];
+                const T gpy = Q::B[qx][0] * ypd[0] + Q::B[qx][1] * ypd[1] + Q::B[qx][2] * ypd[2];
+                const T gpz = Q::B[qx][0] * ypz[0] + Q::B[qx][1] * ypz[1] + Q::B[qx][2] * ypz[2];
+                const T flux = (gpx * ihx) * (gux * ihx) + (gpy * ihy) * (guy * ihy) +
+                               (gpz * ihz + rho_g) * (guz * ihz);
+                a[qx + 3 * qy] = -kc * cw * (Q::W[qx] * Q::W[qy] * Q::W[qz]) * flux;
+            }
+        }
+        // back-projection: s[i + 3 j] = sum_{qx, qy} B[qx][i] B[qy][j] a
+        T t[9];
+#pragma unroll
+        for (int qy = 0; qy < 3; qy++)
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                t[i + 3 * qy] = Q::B[0][i] * a[3 * qy] + Q::B[1][i] * a[1 + 3 * qy] + Q::B[2][i] * a[2 + 3 * qy];
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const T s = Q::B[0][j] * t[i] + Q::B[1][j] * t[i + 3] + Q::B[2][j] * t[i + 6];
+#pragma unroll
+                for (int k = 0; k < 3; k++) w[i + 3 * j + 9 * k] += Q::B[qz][k] * s;
+            }
+    }
+}
+
+template <typename T, int FIELD, int EPI, bool MASKED>
+__global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
+                                                  const WorkItem *__restrict__ work,
+                                                  const T *__restrict__ X, T *__restrict__ Y,
+                                                  EpiArgs<T> ep)
+{
+    __shared__ T xs[3][NL][NL + 1];
+    __shared__ T ps[FIELD ? 3 : 1][FIELD ? NL : 1][FIELD ? NL + 1 : 1];
+    __shared__ T C[2][9][256];
+    __shared__ double red[4];
+
+    const WorkItem wi = work[blockIdx.x];
+    if (ep.active && !ep.active[wi.inst]) return;
+    const OpDev &o = ops[wi.inst];
+    const int nx = o.nx, ny = o.ny, nz = o.nz, NZ = o.NZ, m = o.dmask;
+    const int64_t plane = (int64_t)o.NX * o.NY;
+    const T *__restrict__ Xi = X + o.off;
+    T *__restrict__ Yi = Y + o.off;
+    const T HTS_GLOBAL *__restrict__ Pi = gptr<T>(FIELD ? o.P : nullptr);
+    const T HTS_GLOBAL *__restrict__ kk = gptr<T>(o.k);
+    const T HTS_GLOBAL *__restrict__ lamc = gptr<T>(o.lam);
+    const T HTS_GLOBAL *__restrict__ cTc = gptr<T>(o.cT);
+    const T *__restrict__ Bi = (EPI == EPI_RESID || EPI == EPI_RESID_NORM || EPI == EPI_CHEB) ? ep.b + o.off : nullptr;
+    T *__restrict__ Di = EPI == EPI_CHEB ? ep.d + o.off : nullptr;
+    const T *__restrict__ Ii = EPI == EPI_CHEB ? ep.invd + o.off : nullptr;
+
+    const int tid = threadIdx.x, tx = tid % TC, ty = tid / TC;
+    const int cx0 = wi.tx * OWNC - 1, cy0 = wi.ty * OWNC - 1;   // first (halo) cell of the tile
+    const int cx = cx0 + tx, cy = cy0 + ty;
+    const bool cin = cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+    const int64_t cbase = cin ? (int64_t)cx + (int64_t)nx * cy : 0;
+    const int64_t cplane = (int64_t)nx * ny;
+    const int nx0 = 2 * cx0, ny0 = 2 * cy0;                     // node of local column 0
+
+    // staged node columns of this thread
+    ColInfo sc[SPT];
+    int sli[SPT], slj[SPT];
+#pragma unroll
+    for (int s = 0; s < SPT; s++) {
+        const int c = tid + 256 * s;
+        sli[s] = c % NL;
+        slj[s] = c / NL;
+        if (c < NSTAGE) sc[s] = col_info(o, nx0 + sli[s], ny0 + slj[s]);
+        else sc[s].valid = 0;
+    }
+    // owned node columns of this thread (local columns 2 .. 31)
+    ColInfo oc[OPT];
+    int oli[OPT], olj[OPT], lr[OPT];
+#pragma unroll
+    for (int s = 0; s < OPT; s++) {
+        const int c = tid + 256 * s;
+        oli[s] = 2 + c % OWNN;
+        olj[s] = 2 + c / OWNN;
+        if (c < NOWN) oc[s] = col_info(o, nx0 + oli[s], ny0 + olj[s]);
+        else oc[s].valid = 0;
+        lr[s] = -1;
+        if (FIELD && o.lcol && oc[s].valid) lr[s] = gptr<int32_t>(o.lcol)[oc[s].base];
+    }
+
+    const T hx = T(o.hx), hy = T(o.hy), hz = T(o.hz);
+    const T V = hx * hy * hz;
+    const T cxx = hy * hz / hx, cyy = hx * hz / hy, czz = hx * hy / hz;
+    const T cs = T(o.cs), cm = T(o.cm);
+    const T ihx = T(1) / hx, ihy = T(1) / hy, ihz = T(1) / hz;
+    const T rho_g = T(o.rho_g);
+    const T cw = T(o.cadv) * V;
+    T c1 = T(0), c2 = T(0);
+    if (EPI == EPI_CHEB) {
+        const double *Sc = ep.S + (int64_t)wi.inst * NSLOT;
+        c1 = T(Sc[ep.s1]);
+        c2 = T(Sc[ep.s2]);
+    }
+
+    // node plane k (k >= -2) lives in LDS slot (k + 6) % 3
+    auto stage = [&](int k) {
+        const int b = (k + 6) % 3;
+        const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
+#pragma unroll
+        for (int s = 0; s < SPT; s++) {
+            if (tid + 256 * s >= NSTAGE) continue;
+            const bool in = sc[s].valid && k >= 0 && k < NZ;
+            const int64_t gi = sc[s].valid ? sc[s].base + kc * plane : 0;
+            bool keep = in;
+            if (MASKED) keep = keep && !constrained(sc[s], k, NZ, m);
+            const T xv = Xi[gi];
+            xs[b][slj[s]][sli[s]] = keep ? xv : T(0);
+            if (FIELD) {
+                const T pv = Pi[gi];
+                ps[FIELD ? b : 0][FIELD ? slj[s] : 0][FIELD ? sli[s] : 0] = in ? pv : T(0);
+            }
+        }
+    };
+
+    const int z0 = wi.z0, z1 = wi.z1;            // owned node planes, z0 even
+    const int L0 = z0 / 2 - 1, L1 = (z1 - 1) / 2;  // cell layers marched
+    double acc = 0.0;
+    T top[9];
+#pragma unroll
+    for (int a = 0; a < 9; a++) top[a] = T(0);
+
+    stage(2 * L0);
+    for (int L = L0; L <= L1; L++) {
+        stage(2 * L + 1);
+        stage(2 * L + 2);
+        T ck = T(0), cl = T(0), cc = T(0);
+        const bool lay = cin && L >= 0 && L < nz;
+        if (lay) {
+            const int64_t ci = cbase + (int64_t)L * cplane;
+            ck = kk[ci];
+            if (FIELD) { cl = lamc[ci]; cc = cTc[ci]; }
+        }
+        __syncthreads();
+        T w[27];
+        if (lay) {
+            T u[27];
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+#pragma unroll
+                for (int b = 0; b < 3; b++)
+#pragma unroll
+                    for (int a = 0; a < 3; a++) u[a + 3 * b + 9 * c] = xs[(2 * L + 2 * 3 + c) % 3][2 * ty + b][2 * tx + a];
+            if (FIELD == 0) {
+                q2_mass_stiff(u, cm * V, cs * ck, cxx, cyy, czz, w);
+            } else {
+                q2_mass_stiff(u, cc * V, cs * cl, cxx, cyy, czz, w);
+                T pp[27];
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+#pragma unroll
+                    for (int b = 0; b < 3; b++)
+#pragma unroll
+                        for (int a = 0; a < 3; a++)
+                            pp[a + 3 * b + 9 * c] =
+                                ps[FIELD ? (2 * L + 2 * 3 + c) % 3 : 0][FIELD ? 2 * ty + b : 0][FIELD ? 2 * tx + a : 0];
+                q2_convect(u, pp, ck, ihx, ihy, ihz, rho_g, cw, w);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 27; a++) w[a] = T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < 9; a++) {
+            C[0][a][tid] = top[a] + w[a];
+            C[1][a][tid] = w[a + 9];
+            top[a] = w[a + 18];
+        }
+        __syncthreads();
+        // owners finish node planes 2L and 2L+1
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int P0 = 2 * L + h;
+            if (P0 < z0 || P0 >= z1 || P0 >= NZ) continue;
+#pragma unroll
+            for (int s = 0; s < OPT; s++) {
+                if (tid + 256 * s >= NOWN || !oc[s].valid) continue;
+                // cells around the node: x index i (local node column li)
+                const int li = oli[s], lj = olj[s];
+                int cxs[2], ixs[2], ncx, cys[2], iys[2], ncy;
+                if (li & 1) { cxs[0] = li >> 1; ixs[0] = 1; ncx = 1; }
+                else { cxs[0] = (li >> 1) - 1; ixs[0] = 2; cxs[1] = li >> 1; ixs[1] = 0; ncx = 2; }
+                if (lj & 1) { cys[0] = lj >> 1; iys[0] = 1; ncy = 1; }
+                else { cys[0] = (lj >> 1) - 1; iys[0] = 2; cys[1] = lj >> 1; iys[1] = 0; ncy = 2; }
+                T v = T(0);
+                for (int b = 0; b < ncy; b++)
+                    for (int a = 0; a < ncx; a++) {
+                        const int cell = cxs[a] + TC * cys[b];
+                        v += C[h][ixs[a] + 3 * iys[b]][cell];
+                    }
+                const int64_t gi = oc[s].base + (int64_t)P0 * plane;
+                if (FIELD && lr[s] >= 0) {
+                    const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
+                    const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
+                    const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
+                    int r = lr[s];
+                    while (rows[r].col == (int)oc[s].base && rows[r].k < P0) r++;
+                    lr[s] = r;
+                    if (rows[r].col == (int)oc[s].base && rows[r].k == P0 && !(MASKED && rows[r].row_constrained)) {
+                        T la = T(0);
+                        for (int e = rows[r].beg; e < rows[r].end; e++) {
+                            if (MASKED && ents[e].col_constrained) continue;
+                            la += T(lco[ents[e].src] * ents[e].w) * Xi[ents[e].col];
+                        }
+                        v += la;
+                    }
+                }
+                T ex = T(0);
+                if (EPI == EPI_CHEB || EPI == EPI_DOT || MASKED) ex = Xi[gi];
+                if (MASKED && constrained(oc[s], P0, NZ, m)) v = ex;
+                if (EPI == EPI_STORE) {
+                    Yi[gi] = v;
+                } else if (EPI == EPI_RESID) {
+                    Yi[gi] = Bi[gi] - v;
+                } else if (EPI == EPI_RESID_NORM) {
+                    const T r = Bi[gi] - v;
+                    Yi[gi] = r;
+                    acc += (double)r * (double)r;
+                } else if (EPI == EPI_DOT) {
+                    Yi[gi] = v;
+                    acc += (double)ex * (double)v;
+                } else if (EPI == EPI_CHEB) {
+                    const T r = Bi[gi] - v;
+                    const T d = c1 * Di[gi] + c2 * Ii[gi] * r;
+                    Di[gi] = d;
+                    Yi[gi] = ex + d;
+                }
+            }
+        }
+    }
+    if (EPI == EPI_RESID_NORM || EPI == EPI_DOT) {
+        double v = wave_sum(acc);
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) ep.partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// ----------------------------------------------------------- setup kernels
+// cells around node index g along one axis with the node's local index in each
+__device__ __forceinline__ int q2_cells(int g, int ncell, int *c, int *loc)
+{
+    int n = 0;
+    if (g & 1) {
+        c[0] = g >> 1; loc[0] = 1; n = 1;
+    } else {
+        if ((g >> 1) - 1 >= 0) { c[n] = (g >> 1) - 1; loc[n] = 2; n++; }
+        if ((g >> 1) < ncell) { c[n] = g >> 1; loc[n] = 0; n++; }
+    }
+    return n;
+}
+
+__global__ void k_q2_inv_diag(OpDev o, double *__restrict__ out)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= o.nnode) return;
+    const int NX = o.NX, NY = o.NY;
+    int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((int64_t)NX * NY));
+    ColInfo c = col_info(o, i, j);
+    if (constrained(c, k, o.NZ, o.dmask)) { out[n] = 1.0; return; }
+    const double md[3] = {4.0 / 30, 16.0 / 30, 4.0 / 30}, kd[3] = {7.0 / 3, 16.0 / 3, 7.0 / 3};
+    const double V = o.hx * o.hy * o.hz;
+    const double cxx = o.hy * o.hz / o.hx, cyy = o.hx * o.hz / o.hy, czz = o.hx * o.hy / o.hz;
+    int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+    const int nxc = q2_cells(i, o.nx, cx, lx), nyc = q2_cells(j, o.ny, cy, ly), nzc = q2_cells(k, o.nz, cz, lz);
+    double d = 0.0;
+    for (int c3 = 0; c3 < nzc; c3++)
+        for (int b = 0; b < nyc; b++)
+            for (int a = 0; a < nxc; a++) {
+                const int64_t ci = cx[a] + (int64_t)o.nx * (cy[b] + (int64_t)o.ny * cz[c3]);
+                const double mx = md[lx[a]], my = md[ly[b]], mz = md[lz[c3]];
+                const double kx = kd[lx[a]], ky = kd[ly[b]], kz = kd[lz[c3]];
+                double mc, sc;
+                if (o.field == 0) {
+                    mc = o.cm;
+                    sc = o.cs * static_cast<const double *>(o.k)[ci];
+                } else {
+                    mc = static_cast<const double *>(o.cT)[ci];
+                    sc = o.cs * static_cast<const double *>(o.lam)[ci];
+                }
+                d += mc * V * mx * my * mz + sc * (cxx * kx * my * mz + cyy * mx * ky * mz + czz * mx * my * kz);
+            }
+    out[n] = 1.0 / d;
+}
+
+// y_a = sum_c alpha_c int N_a + beta_c int dN_a/dz
+__global__ void k_q2_cell_loads(OpDev o, const double *__restrict__ alpha, const double *__restrict__ beta,
+                                double *__restrict__ y)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= o.nnode) return;
+    const int NX = o.NX, NY = o.NY;
+    int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((int64_t)NX * NY));
+    const double wint[3] = {1.0 / 6, 2.0 / 3, 1.0 / 6};   // int_0^1 N_i
+    const double dend[3] = {-1.0, 0.0, 1.0};              // N_i(1) - N_i(0)
+    const double V = o.hx * o.hy * o.hz, A = o.hx * o.hy;
+    int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+    const int nxc = q2_cells(i, o.nx, cx, lx), nyc = q2_cells(j, o.ny, cy, ly), nzc = q2_cells(k, o.nz, cz, lz);
+    double s = 0.0;
+    for (int c3 = 0; c3 < nzc; c3++)
+        for (int b = 0; b < nyc; b++)
+            for (int a = 0; a < nxc; a++) {
+                const int64_t ci = cx[a] + (int64_t)o.nx * (cy[b] + (int64_t)o.ny * cz[c3]);
+                const double wxy = wint[lx[a]] * wint[ly[b]];
+                if (alpha) s += alpha[ci] * V * wxy * wint[lz[c3]];
+                if (beta) s += beta[ci] * A * wxy * dend[lz[c3]];
+            }
+    y[n] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+template <typename T, int FIELD, bool MASKED>
+static void dispatch_epi2(int epi, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
+                          const EpiArgs<T> &ep, hipStream_t s)
+{
+    dim3 g(nwork), b(256);
+    switch (epi) {
+    case EPI_STORE: k_q2_apply<T, FIELD, EPI_STORE, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_RESID: k_q2_apply<T, FIELD, EPI_RESID, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_RESID_NORM:
+        k_q2_apply<T, FIELD, EPI_RESID_NORM, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep);
+        break;
+    case EPI_DOT: k_q2_apply<T, FIELD, EPI_DOT, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_CHEB: k_q2_apply<T, FIELD, EPI_CHEB, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    default: throw Error(-1, "bad epilogue");
+    }
+}
+
+template <typename T>
+void launch_q2(int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
+               const EpiArgs<T> &ep, hipStream_t s)
+{
+    if (nwork <= 0) return;
+    if (field == 0) {
+        if (masked) dispatch_epi2<T, 0, true>(epi, ops, work, nwork, x, y, ep, s);
+        else dispatch_epi2<T, 0, false>(epi, ops, work, nwork, x, y, ep, s);
+    } else {
+        if (masked) dispatch_epi2<T, 1, true>(epi, ops, work, nwork, x, y, ep, s);
+        else dispatch_epi2<T, 1, false>(epi, ops, work, nwork, x, y, ep, s);
+    }
+    HTS_LAUNCH_CHECK();
+}
+
 template void launch_q2<double>(int, int, bool, const OpDev *, const WorkItem *, int, const double *, double *,
                                 const EpiArgs<double> &, hipStream_t);
 template void launch_q2<float>(int, int, bool, const OpDev *, const WorkItem *, int, const float *, float *,
                                const EpiArgs<float> &, hipStream_t);
-void launch_q2_inv_diag(const OpDev &, double *, hipStream_t) { throw Error(-7, "Q2 not available"); }
-void launch_q2_cell_loads(const OpDev &, const double *, const double *, double *, hipStream_t)
+
+void launch_q2_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s)
 {
-    throw Error(-7, "Q2 not available");
+    int64_t nb = (op.nnode + 255) / 256;
+    k_q2_inv_diag<<<dim3((unsigned)nb), dim3(256), 0, s>>>(op, inv_diag);
+    HTS_LAUNCH_CHECK();
+}
+
+void launch_q2_cell_loads(const OpDev &op, const double *alpha, const double *beta, double *y, hipStream_t s)
+{
+    int64_t nb = (op.nnode + 255) / 256;
+    k_q2_cell_loads<<<dim3((unsigned)nb), dim3(256), 0, s>>>(op, alpha, beta, y);
+    HTS_LAUNCH_CHECK();
 }
 
 }  // namespace hts

@@ -49,6 +49,7 @@ struct Level {
     DBuf<double> invd64, x64, xb64, b64, d64, t64;
     DBuf<float> invd32, x32, xb32, b32, d32, t32;
     DBuf<double> cheb;                     // [ninst][NSLOT] Chebyshev coefficients
+    std::vector<DBuf<int32_t>> qdcol;      // Q1 vertex Dirichlet columns under a Q2 fine level
 };
 
 struct Hier {

@@ -1,6 +1,7 @@
 // Batches of instances, the multigrid hierarchy, the Krylov solvers and the
 // backward-Euler time step (Section 2: P^{n+1} from Eq. 3, then T^{n+1}
 // from Eq. 4 with the Darcy flux of P^{n+1}).
+#include <cstdio>
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -126,13 +127,15 @@ int tuned_zc(int degree, int field, int NX, int NY, int NZ)
 int Batch::pick_zc(int field, const hts_mesh *M, int64_t tiles) const
 {
     const int NZ = M->N[2];
-    if (zc_force[field] > 0) return std::min(zc_force[field], NZ);
+    // Q2 work items start on even node planes (cell-layer boundaries)
+    auto fit = [&](int z) { return M->p == 2 ? std::max(2, (std::min(z, NZ) + 1) / 2 * 2) : std::min(z, NZ); };
+    if (zc_force[field] > 0) return fit(zc_force[field]);
     const int t = tuned_zc(M->p, field, M->N[0], M->N[1], NZ);
-    if (t > 0) return std::min(t, NZ);
+    if (t > 0) return fit(t);
     // enough blocks to fill 256 CUs several times over
     int64_t z = std::max<int64_t>(4, (tiles * NZ) / 2048);
     z = std::min<int64_t>(z, 32);
-    return (int)std::min<int64_t>(z, NZ);
+    return fit((int)z);
 }
 
 void Batch::build_work()
@@ -141,7 +144,7 @@ void Batch::build_work()
         std::vector<WorkItem> nat;
         for (int i = 0; i < n; i++) {
             hts_mesh *M = m[i];
-            const int own = 15;
+            const int own = M->p == 2 ? 30 : 15;   // owned node columns per tile edge
             const int tx = (M->N[0] + own - 1) / own, ty = (M->N[1] + own - 1) / own;
             const int zc = pick_zc(f, M, (int64_t)tx * ty);
             for (int z0 = 0; z0 < M->N[2]; z0 += zc)
@@ -484,7 +487,8 @@ static void invert_dense(std::vector<double> &A, int n)
 
 static void cheb_coeffs(double lmax_est, double ratio, int steps, double *out /* 2*steps */)
 {
-    const double lmax = 1.1 * lmax_est, lmin = lmax / ratio;
+    static const double safety = env_or("HTS_LMAX_SAFETY", 1.1);
+    const double lmax = safety * lmax_est, lmin = lmax / ratio;
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
     double rho_prev = 1.0 / sigma;
     out[0] = 0.0;
@@ -519,7 +523,8 @@ void Batch::estimate_lmax(Hier &H, int l, std::vector<double> &lmax)
     RedCtx rc = L.red;
     if (l == 0) vmask<double>(v, H.ops.d64.p, L.x64.p, 0.0);
     EpiArgs<double> ep{};
-    for (int it = 0; it < 12; it++) {
+    const int iters = (int)env_or("HTS_LMAX_ITERS", 12.0);
+    for (int it = 0; it < iters; it++) {
         apply_lvl<double>(H, l, EPI_STORE, true, L.x64.p, L.t64.p, ep);
         vjacobi<double>(v, 1.0, -1, L.invd64.p, L.t64.p, L.xb64.p);
         vdot<double>(v, L.xb64.p, L.xb64.p, nullptr, partial.p);
@@ -545,9 +550,13 @@ void Batch::build_smoother(Hier &H, int l, int steps, double ratio)
     std::vector<double> lm;
     estimate_lmax(H, l, lm);
     std::vector<double> c((size_t)n * NSLOT, 0.0);
+    static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 0.0;
     for (int i = 0; i < n; i++) {
         cheb_coeffs(lm[i], ratio, steps, &c[(size_t)i * NSLOT + S_CHEB]);
         if (L.cont[i]) H.lmax.push_back(lm[i]);
+        if (verbose && L.cont[i])
+            std::fprintf(stderr, "[hts] field %d level %d instance %d lmax(D^-1 A) %.6g ratio %g steps %d\n", H.field, l,
+                         i, lm[i], ratio, steps);
     }
     L.cheb.upload(al, c, s);
 }
@@ -713,12 +722,29 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
                     sync(s);
                 } else {
                     // p-coarsening: the Q1 operator on the same cells
+                    // p-coarsening: the Q1 operator on the same cells, its
+                    // vertices constrained where the Q2 node at the vertex is
                     OpDev q1 = H.ops.h64[i];
                     q1.p = 1;
                     q1.NX = cN[0]; q1.NY = cN[1]; q1.NZ = cN[2];
                     q1.nnode = ccnt[i];
-                    q1.dcol = nullptr;
                     q1.lcol = nullptr;
+                    q1.dcol = nullptr;
+                    const std::vector<int32_t> &fd = m[i]->h_dcol[H.field];
+                    if (!fd.empty()) {
+                        std::vector<int32_t> cd((size_t)cN[0] * cN[1], DCOL_NONE);
+                        for (int J = 0; J < cN[1]; J++)
+                            for (int I = 0; I < cN[0]; I++) {
+                                const int packed = fd[(size_t)(2 * I) + (size_t)fN[0] * (2 * J)];
+                                const int lo = packed & 0xFFFF, hi = (packed >> 16) & 0xFFFF;
+                                if (packed == DCOL_NONE || lo > hi) continue;
+                                const int clo = (lo + 1) / 2, chi = hi / 2;
+                                if (clo <= chi) cd[(size_t)I + (size_t)cN[0] * J] = clo | (chi << 16);
+                            }
+                        C.qdcol.emplace_back();
+                        C.qdcol.back().upload(al, cd, s);
+                        q1.dcol = C.qdcol.back().p;
+                    }
                     launch_q1_stencil(q1, Sc, s);
                 }
             } else {
@@ -822,7 +848,11 @@ void Batch::vcycle(Hier &H, int l, const T *b, T *x)
     apply_lvl<T>(H, l, EPI_RESID, true, cur, t, ep);
     Level &C = H.lev[l + 1];
     const OpDev *fops = (l == 0) ? H.ops.d64.p : nullptr;
-    launch_restrict<T>(L.g64.p, C.g64.p, fops, C.ch_all_ext, C.nch_all, active.p, t, PK(T, C.b64, C.b32), s);
+    // the Q1 level under a Q2 fine level is re-discretised with its Dirichlet
+    // vertices eliminated; Galerkin levels keep them as coupled unknowns
+    const int mask_coarse = (l == 0 && p == 2) ? 1 : 0;
+    launch_restrict<T>(L.g64.p, C.g64.p, fops, C.ch_all_ext, C.nch_all, active.p, t, PK(T, C.b64, C.b32), mask_coarse,
+                       s);
     vcycle<T>(H, l + 1, PK(T, C.b64, C.b32), PK(T, C.x64, C.x32));
     launch_prolong_add<T>(L.g64.p, C.g64.p, fops, L.ch_ext, L.nch, active.p, PK(T, C.x64, C.x32), cur, s);
     // post-smoothing restarts the Chebyshev recurrence (first coefficient pair has c1 = 0)
@@ -875,6 +905,11 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
         vcg_update<T>(v, x, r, pv, q, ro, partial.p);
         if (hook) cg_hook(reinterpret_cast<const double *>(x), it);
         vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+        static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 1.0;
+        if (verbose) {
+            download_S();
+            std::fprintf(stderr, "[hts] cg it %d rr %.6e rr0 %.6e\n", it, hS[S_RR], hS[S_RR0]);
+        }
         if (it % std::max(1, check_every) == 0 || it == maxit)
             if (!any_active()) break;
         M(r, z);

@@ -28,6 +28,14 @@ def small_cases():
     s = synth.config2(ncells=(17, 9, 5), n_steps=1)
     s.name = "odd_17x9x5"
     c.append((s.name, s))
+    # Q2: the same scenarios on 27-node cells (cellwise data unchanged)
+    c.append(("c3_q2_small", synth.config3(degree=2, ncells=(17, 16, 5), n_steps=1)))
+    s = synth.config2(ncells=(19, 16, 6), n_steps=1)
+    s.degree, s.name = 2, "c2_q2_small"
+    c.append((s.name, s))
+    s = synth.config4_instance(3, n_override=11, n_steps=1)
+    s.degree, s.name = 2, "c4_q2_small"
+    c.append((s.name, s))
     return c
 
 

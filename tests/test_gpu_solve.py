@@ -128,6 +128,56 @@ def test_c3_small_piles(hts):
     assert np.abs(T - To).max() <= 1e-7
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c3_q2_small_piles(hts, mode):
+    """Q2 variant of the pile field (27-node cells, 3-point Gauss)."""
+    print_case("c3 q2 small mode", mode)
+    scn = synth.config3(degree=2, ncells=(12, 12, 6), n_steps=2)
+    m, P, T, t, stats = run_gpu(hts, scn, 2, rtol=1e-12, mode=mode)
+    Po, To, to = oracle.run(scn, n_steps=2)
+    print("stats", stats)
+    for st in stats:
+        assert st["status"] == [0, 0], st
+    if mode == 0:
+        assert rel(P, Po) <= 1e-10
+        assert rel(T, To) <= 1e-10
+        assert np.abs(T - To).max() <= 1e-7
+    else:
+        assert rel(P, Po) <= 1e-8
+        assert np.abs(T - To).max() <= 1e-6
+
+
+def test_c2_q2_well_pair(hts):
+    """Q2 layered aquifer with the injection/extraction wells (line operator
+    of the injection enthalpy term on 27-node cells)."""
+    print_case("c2 q2 small")
+    scn = synth.config2(ncells=(14, 12, 6), n_steps=2)
+    scn.degree = 2
+    m, P, T, t, stats = run_gpu(hts, scn, 2, rtol=1e-12)
+    Po, To, to = oracle.run(scn, n_steps=2)
+    print("stats", stats)
+    assert rel(P, Po) <= 1e-10
+    assert rel(T, To) <= 1e-10
+    assert np.abs(T - To).max() <= 1e-7
+
+
+@pytest.mark.parametrize("B", [1e5, 1e9])
+def test_q2_multigrid_rate(hts, B):
+    """The Q2 -> Q1 p-multigrid keeps a mesh-independent rate whatever the
+    scale of the operator (regression: residual restricted onto eliminated
+    Dirichlet vertices of the Q1 level was injected back as a correction)."""
+    print_case("q2 multigrid rate B", B)
+    scn = synth.config2(ncells=(14, 12, 6), n_steps=1)
+    scn.degree, scn.B_poro = 2, B
+    for hp in (0, 1):
+        o = hts.default_opts(rtol=1e-8, heat_precond=hp)
+        m = hts.from_scenario(scn, opts=o)
+        code, st = m.solve_step(scn.dt, o)
+        print("heat_precond", hp, st)
+        assert st["iters"][0] <= 20
+        assert st["iters"][1] <= 30
+
+
 def test_not_converged_is_transactional(hts):
     print_case("transactional")
     scn = synth.config2(ncells=(16, 16, 8), n_steps=1)
