@@ -66,6 +66,11 @@ def parse():
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--heat-precond", type=int, default=1, help="0 multigrid, 1 Chebyshev-Jacobi")
+    ap.add_argument("--use-graph", type=int, default=1,
+                    help="replay captured HIP graphs for the Krylov iteration chunks (1) or launch eagerly (0)")
+    ap.add_argument("--timing-steps", type=int, default=3,
+                    help="extra steps after the timed region with per-launch kernel events (eager launches) "
+                         "for the roofline figures")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the workload, run a plain elementwise copy of MIB MiB (FP32) three "
                          "times: the reference that scales hardware byte counters")
@@ -93,21 +98,21 @@ def main():
         del src, dst
 
     nc = tuple(int(v) for v in a.ncells.split(","))
-    scn = synth.config2(ncells=nc, n_steps=a.warmup + a.steps)
+    scn = synth.config2(ncells=nc, n_steps=a.warmup + a.steps + max(1, a.timing_steps))
     modes = [m.strip() for m in a.modes.split(",") if m.strip()]
     mode_id = {"fp64": hts.MODE_FP64, "fp32_refined": hts.MODE_FP32_REFINED}
     results = {}
     for mode in modes:
         o = hts.default_opts(mode=mode_id[mode], rtol=1e-8, check_every=a.check_every,
                              cheb_degree=a.cheb, heat_cheb_degree=a.heat_cheb,
-                             inner_rtol=a.inner_rtol, heat_precond=a.heat_precond)
+                             inner_rtol=a.inner_rtol, heat_precond=a.heat_precond,
+                             use_graph=a.use_graph)
         m = hts.from_scenario(scn, opts=o)
         if not a.no_autotune:
             hts.autotune([m])        # setup: picks the kernels' z-chunk depth
         for _ in range(a.warmup):
             m.solve_step(scn.dt, o)
         torch.cuda.synchronize()
-        hts.kernel_timing_start()
         iters = []
         t0 = time.perf_counter()
         for _ in range(a.steps):
@@ -115,6 +120,12 @@ def main():
             iters.append(st)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        # per-launch kernel times (events around every fine-level operator
+        # launch force eager launches, so they are taken after the timed region)
+        hts.kernel_timing_start()
+        for _ in range(max(1, a.timing_steps)):
+            m.solve_step(scn.dt, o)
+        torch.cuda.synchronize()
         kt = hts.kernel_timing_stop()
         dt_s = t1 - t0
         dofs = 2 * m.nnode
@@ -155,7 +166,7 @@ def main():
         "launches": k["launches"],
         "avg_us": round(1e3 * avg_ms, 2),
         "alu_tflops": round((k["flops"] / max(1, k["launches"])) / (avg_ms * 1e-3) / 1e12, 2),
-        "share_of_step": round(k["ms"] / (R["ms_per_step"] * a.steps), 3),
+        "share_of_step": round(k["ms"] / (R["ms_per_step"] * max(1, a.timing_steps)), 3),
     }
 
     cpu = None
@@ -194,7 +205,7 @@ def main():
         "config": {"workload": "layered aquifer %dx%dx%d Q1 (%d nodes/field), well pair, "
                                "dt = 1 day, rtol 1e-8, mode %s" % (nc + (R["nnode"], best)),
                    "seed": 2, "cheb_degree": a.cheb, "heat_cheb_degree": a.heat_cheb,
-                   "inner_rtol": a.inner_rtol, "autotune": not a.no_autotune,
+                   "inner_rtol": a.inner_rtol, "autotune": not a.no_autotune, "use_graph": bool(a.use_graph),
                    "heat_precond": ["multigrid", "chebyshev-jacobi"][a.heat_precond]},
         "roofline": roofline,
         "cpu_baseline": cpu,

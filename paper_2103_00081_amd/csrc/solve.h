@@ -129,6 +129,24 @@ struct Batch {
     std::function<void(const double *, int)> cg_hook;
     std::function<void(const Tables &, const double *)> inner_hook;
 
+    // Captured launch sequences (fixed-length Krylov chunks).  Every kernel
+    // in them is predicated on the per-instance active flags, so a chunk
+    // replayed past convergence does no work for converged instances.
+    // Graphs embed buffer addresses: drop them whenever a buffer they use
+    // is reallocated.
+    struct Graph {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t e = nullptr;
+    };
+    std::map<std::string, Graph> graphs;
+    hipStream_t cap = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    bool use_graph = false;
+    std::string graph_tag;   // identifies the preconditioner a captured chunk calls
+    std::map<std::string, int> last_iters;   // iterations of the previous solve per captured system
+    void drop_graphs();
+    void replay(const std::string &key, const std::function<void()> &body);
+
     ~Batch();
     int pick_zc(int field, const hts_mesh *M, int64_t tiles) const;
     void build_work();

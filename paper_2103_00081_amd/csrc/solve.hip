@@ -54,8 +54,59 @@ static void build_chunks(const std::vector<int64_t> &off, const std::vector<int6
 // ----------------------------------------------------------- batch build
 Batch::~Batch()
 {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+    for (hipEvent_t e : gev)
+        if (e) (void)hipEventDestroy(e);
     if (hS) (void)hipHostFree(hS);
     if (hact) (void)hipHostFree(hact);
+}
+
+void Batch::drop_graphs()
+{
+    for (auto &kv : graphs) {
+        if (kv.second.e) (void)hipGraphExecDestroy(kv.second.e);
+        if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+    }
+    graphs.clear();
+}
+
+// Run body's launches as one graph: captured on first use on a private
+// stream (the caller's stream may be the legacy default stream, which
+// cannot be captured), then replayed; ordered after and before the work of
+// the batch stream by events.
+void Batch::replay(const std::string &key, const std::function<void()> &body)
+{
+    if (!cap) {
+        HTS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        HTS_HIP(hipEventCreateWithFlags(&gev[0], hipEventDisableTiming));
+        HTS_HIP(hipEventCreateWithFlags(&gev[1], hipEventDisableTiming));
+    }
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+        Graph G;
+        hipStream_t saved = s;
+        s = cap;
+        HTS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(cap, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            s = saved;
+            throw;
+        }
+        s = saved;
+        HTS_HIP(hipStreamEndCapture(cap, &G.g));
+        HTS_HIP(hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0));
+        it = graphs.emplace(key, G).first;
+    }
+    HTS_HIP(hipEventRecord(gev[0], s));
+    HTS_HIP(hipStreamWaitEvent(cap, gev[0], 0));
+    HTS_HIP(hipGraphLaunch(it->second.e, cap));
+    HTS_HIP(hipEventRecord(gev[1], cap));
+    HTS_HIP(hipStreamWaitEvent(s, gev[1], 0));
 }
 
 // ----------------------------------------------------------- tuning cache
@@ -140,6 +191,7 @@ int Batch::pick_zc(int field, const hts_mesh *M, int64_t tiles) const
 
 void Batch::build_work()
 {
+    drop_graphs();
     for (int f = 0; f < 2; f++) {
         std::vector<WorkItem> nat;
         for (int i = 0; i < n; i++) {
@@ -583,6 +635,7 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     const bool mg = o.heat_precond == 0;
     const int deg = mg ? std::max(1, std::min(o.heat_cheb_degree, 8)) : std::max(1, std::min(o.heat_cheb_degree, 16));
     if (heat && heat->dt == dt && heat->deg == deg && heat->multigrid == mg) return *heat;
+    drop_graphs();
     heat = std::make_unique<Hier>();
     Hier &H = *heat;
     H.field = 1;
@@ -896,6 +949,45 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
     vdot<T>(v, r, z, nullptr, partial.p);
     vreduce(rch, partial.p, 2, RED_STORE, S_RZ, S.p, active.p, 0, 0.0, nullptr, s);
     vcopy<T>(v, z, pv);
+    if (use_graph && !hook && !g_timing.on) {
+        // Chunks replayed as graphs with a host check between them: the first
+        // chunk as long as the previous solve of this system took, then
+        // chunks of two (or check_every) iterations.
+        char key[256];
+        std::snprintf(key, sizeof key, "cg%d|%d|%p|%p|%p|%d|%d", (int)sizeof(T), A.field, (const void *)&A,
+                      (const void *)b, (const void *)x, maxit, flexible ? 1 : 0);
+        // the preconditioner closure is identified by its target, not its address
+        const std::string base = std::string(key) + "|" + graph_tag;
+        auto hist = last_iters.find(base);
+        int K = hist != last_iters.end() ? hist->second : 4;
+        int done = 0;
+        while (done < maxit) {
+            K = std::max(1, std::min(K, maxit - done));
+            replay(base + "|K" + std::to_string(K), [&] {
+                VecCtx vg = vctx();
+                for (int c = 0; c < K; c++) {
+                    EpiArgs<T> e2{};
+                    e2.partial = partial.p;
+                    apply_op<T>(A, EPI_DOT, true, pv, q, e2);
+                    vreduce(rwk[A.field], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+                    vcg_update<T>(vg, x, r, pv, q, ro, partial.p);
+                    vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+                    M(r, z);
+                    vdot<T>(vg, z, r, ro, partial.p);
+                    vreduce(rch, partial.p, 2, RED_CG_BETA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+                    vaxpby<T>(vg, 1.0, -1, z, 1.0, S_BETA, pv);
+                }
+            });
+            done += K;
+            if (!any_active()) break;
+            K = check_every > 1 ? check_every : 2;
+        }
+        download_S();
+        int used = 0;
+        for (int i = 0; i < n; i++) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
+        last_iters[base] = std::max(1, used);
+        return done;
+    }
     int it = 0;
     for (it = 1; it <= maxit; it++) {
         EpiArgs<T> e2{};
@@ -942,21 +1034,54 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
         for (int a : cyc) any |= a != 0;
         if (!any) break;
         vaxpby<T>(v, 1.0, S_SCALE, V, 0.0, -1, V);
-        for (int j = 0; j < mres; j++) {
+        // one Arnoldi step; every kernel skips instances whose cycle ended
+        auto step_j = [&](int j) {
+            VecCtx vj = vctx();
             T *Vj = V + (int64_t)j * ld, *w = V + (int64_t)(j + 1) * ld, *Zj = Z + (int64_t)j * ld;
             M(Vj, Zj);
             EpiArgs<T> e2{};
             apply_op<T>(A, EPI_STORE, true, Zj, w, e2);
-            vmultidot<T>(v, V, ld, j + 1, w, partial.p, j + 1);
+            vmultidot<T>(vj, V, ld, j + 1, w, partial.p, j + 1);
             vreduce(rch, partial.p, j + 1, RED_NONE, 0, S.p, active.p, 0, 0.0, gh1.p, s);
-            vorth_update<T>(v, V, ld, j + 1, gh1.p, j + 1, w, 1, partial.p, j + 2);
+            vorth_update<T>(vj, V, ld, j + 1, gh1.p, j + 1, w, 1, partial.p, j + 2);
             vreduce(rch, partial.p, j + 2, RED_NONE, 0, S.p, active.p, 0, 0.0, gh2.p, s);
-            vorth_update<T>(v, V, ld, j + 1, gh2.p, j + 2, w, 0, partial.p, 1);
+            vorth_update<T>(vj, V, ld, j + 1, gh2.p, j + 2, w, 0, partial.p, 1);
             vreduce(rch, partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, gww.p, s);
             gm_arnoldi(n, active.p, S.p, j, mres, maxit, gh1.p, gh2.p, gww.p, gH.p, gcs.p, gsn.p, gg.p, gkdim.p, s);
-            vaxpby<T>(v, 1.0, S_SCALE, w, 0.0, -1, w);
-            if ((j + 1) % std::max(1, check_every) == 0 || j == mres - 1)
+            vaxpby<T>(vj, 1.0, S_SCALE, w, 0.0, -1, w);
+        };
+        if (use_graph && !g_timing.on) {
+            // the whole cycle as one graph, in chunks of K steps with a host
+            // check between them
+            char key[256];
+            std::snprintf(key, sizeof key, "gm%d|%d|%p|%p|%p|%d|%d", (int)sizeof(T), A.field, (const void *)&A,
+                          (const void *)b, (const void *)x, maxit, mres);
+            const std::string base = std::string(key) + "|" + graph_tag;
+            auto hist = last_iters.find(base);
+            int K = hist != last_iters.end() ? hist->second : 8;
+            int j0 = 0;
+            for (; j0 < mres;) {
+                const int j1 = std::min(mres, j0 + std::max(1, K));
+                replay(base + "|" + std::to_string(j0) + "-" + std::to_string(j1), [&] {
+                    for (int j = j0; j < j1; j++) step_j(j);
+                });
+                j0 = j1;
                 if (!any_active()) break;
+                K = check_every > 1 ? check_every : 2;
+            }
+            if (cycle == 0) {
+                download_S();
+                int used = 0;
+                for (int i = 0; i < n; i++)
+                    if (cyc[i]) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
+                last_iters[base] = std::max(1, std::min(used, mres));
+            }
+        } else {
+            for (int j = 0; j < mres; j++) {
+                step_j(j);
+                if ((j + 1) % std::max(1, check_every) == 0 || j == mres - 1)
+                    if (!any_active()) break;
+            }
         }
         // x += Z y for every instance that took part in this cycle
         set_active(cyc);
@@ -980,6 +1105,7 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
 void Batch::ensure_gmres(int mres)
 {
     if (gm_m == mres) return;
+    drop_graphs();
     gm_m = mres;
     V64.alloc(al, (size_t)(mres + 1) * ntot);
     Z64.alloc(al, (size_t)mres * ntot);
@@ -1013,6 +1139,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
     st.fallbacks.assign(n, 0);
     const bool fp32 = o.mode == HTS_MODE_FP32_REFINED;
     const bool learned = o.mode == HTS_MODE_LEARNED && field == 0;
+    use_graph = o.use_graph != 0 && !learned;
     if (learned && !o.nn) throw Error(HTS_ERR_ARG, "learned mode needs opts.nn");
     if (learned && !mg) throw Error(HTS_ERR_STATE, "learned mode needs the multigrid fallback");
     const double rtol = o.rtol > 0 ? o.rtol : 1e-8;
@@ -1053,6 +1180,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
                 if (mg) vcycle<float>(*mg, 0, r_, z_);
                 else cheb_prec<float>(*hprec, r_, z_);
             };
+            graph_tag = (mg ? "mg" : "cheb") + std::to_string((uintptr_t)(mg ? mg : hprec));
             if (field == 0) cg<float>(A, M, b32.p, x32.p, maxit, false, o.check_every);
             else fgmres<float>(A, M, b32.p, x32.p, maxit, std::max(2, std::min(o.gmres_restart, 60)), o.check_every);
         } else {
@@ -1063,6 +1191,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
                 if (mg) vcycle<double>(*mg, 0, r_, z_);
                 else cheb_prec<double>(*hprec, r_, z_);
             };
+            graph_tag = (mg ? "mg" : "cheb") + std::to_string((uintptr_t)(mg ? mg : hprec));
             if (learned) {
                 // Flexible CG with the network as preconditioner.  Fallback:
                 // after two consecutive NN-preconditioned iterations that each

@@ -178,6 +178,44 @@ def test_q2_multigrid_rate(hts, B):
         assert st["iters"][1] <= 30
 
 
+@pytest.mark.parametrize("mode,hp", [(0, 1), (1, 1), (0, 0)])
+def test_graph_replay_matches_eager_bitwise(hts, mode, hp):
+    """Captured Krylov chunks replayed over several steps (with the eager
+    right-hand sides, outer corrections and host checks between replays)
+    give exactly the eager answer, step after step."""
+    print_case("graph replay mode", mode, "heat_precond", hp)
+    scn = synth.config2(ncells=(24, 20, 10), n_steps=4)
+    res = []
+    for g in (0, 1):
+        o = hts.default_opts(rtol=1e-10, mode=mode, heat_precond=hp, use_graph=g)
+        m = hts.from_scenario(scn, opts=o)
+        states = []
+        for _ in range(4):
+            code, st = m.solve_step(scn.dt, o)
+            states.append((m.get_state(0)[0], m.get_state(1)[0], st["iters"]))
+        res.append(states)
+    for (P0, T0, i0), (P1, T1, i1) in zip(*res):
+        assert i0 == i1
+        assert np.array_equal(P0, P1)
+        assert np.array_equal(T0, T1)
+
+
+def test_graph_replay_batched(hts):
+    """Batched instances of uneven size advance identically with and without
+    captured graphs."""
+    print_case("graph replay batched")
+    scns = [synth.config4_instance(i, n_override=n, n_steps=3) for i, n in [(0, 12), (1, 17), (2, 9)]]
+    out = []
+    for g in (0, 1):
+        o = hts.default_opts(rtol=1e-10, use_graph=g)
+        ms = [hts.from_scenario(s, opts=o) for s in scns]
+        hts.advance(ms, 3, scns[0].dt, o)
+        out.append([(m.get_state(0)[0], m.get_state(1)[0]) for m in ms])
+    for (P0, T0), (P1, T1) in zip(*out):
+        assert np.array_equal(P0, P1)
+        assert np.array_equal(T0, T1)
+
+
 def test_not_converged_is_transactional(hts):
     print_case("transactional")
     scn = synth.config2(ncells=(16, 16, 8), n_steps=1)
