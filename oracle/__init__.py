@@ -79,6 +79,7 @@ def lib():
             "orc_element_matrix": (None, [vp, vp, C.c_int, C.c_int, C.c_int, vp]),
             "orc_assemble": (None, [vp, vp, vp, vp]),
             "orc_apply_rows": (None, [vp, vp, vp, vp, vp, i64, vp]),
+            "orc_apply_rows_abs": (None, [vp, vp, vp, vp, vp, i64, vp]),
             "orc_load_qp": (None, [vp, C.c_int, vp, vp]),
             "orc_load_gradz": (None, [vp, vp, C.c_int, vp]),
             "orc_load_face": (None, [vp, C.c_int, d, C.c_int, vp]),
@@ -199,7 +200,9 @@ def element_matrix(m: Mesh, cell, mass=None, stiff=None, kvel=None, P=None, adv_
 
 
 def apply_rows(m: Mesh, rows, x, colmask=None, mass=None, stiff=None, kvel=None, P=None,
-               adv_scale=0.0, rho_g=0.0, nq=None) -> np.ndarray:
+               adv_scale=0.0, rho_g=0.0, nq=None, absolute=False) -> np.ndarray:
+    """Rows of the assembled operator times x, from the element integrals of
+    the cells around each row's node (absolute: sum |A_e| |x|)."""
     L = lib()
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     out = np.zeros(rows.size)
@@ -207,7 +210,8 @@ def apply_rows(m: Mesh, rows, x, colmask=None, mass=None, stiff=None, kvel=None,
     mk = None if colmask is None else np.ascontiguousarray(colmask, dtype=np.uint8)
     mc = m.c()
     xx = _f64(x)
-    L.orc_apply_rows(C.byref(mc), C.byref(op), _p(xx), _p(mk), _p(rows), rows.size, _p(out))
+    f = L.orc_apply_rows_abs if absolute else L.orc_apply_rows
+    f(C.byref(mc), C.byref(op), _p(xx), _p(mk), _p(rows), rows.size, _p(out))
     return out
 
 
@@ -568,6 +572,34 @@ def run(scn, n_steps: Optional[int] = None, state=None, **kw):
     for _ in range(scn.n_steps if n_steps is None else n_steps):
         P, T, t = step(scn, m, P, T, t, **kw)
     return P, T, t
+
+
+def operator_rows(scn, field: int, rows, x, P=None, t_new: Optional[float] = None, steady=None,
+                  absolute=False):
+    """Sampled rows of the operator on the constrained space (what
+    reduced_apply(operator(...), mask, x) gives), computed row by row from
+    the element integrals, for meshes too large to assemble whole.
+    absolute: the same rows of |A| |x| (an upper bound of them)."""
+    m = Mesh.of(scn)
+    t_new = scn.t0 + scn.dt if t_new is None else t_new
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    mask, _ = dirichlet(scn, m, field, t_new)
+    k, lam, cT = coefficients(scn)
+    if field == PRESSURE:
+        if steady is None:
+            steady = scn.B_poro <= 0.0
+        s = 1.0 if steady else scn.dt * scn.B_poro
+        y = apply_rows(m, rows, x, colmask=mask, mass=None if steady else np.ones(m.ncell), stiff=s * k,
+                       absolute=absolute)
+    else:
+        h = scn.dt
+        y = apply_rows(m, rows, x, colmask=mask, mass=cT, stiff=h * lam, kvel=k, P=P,
+                       adv_scale=h * scn.c_w, rho_g=scn.rho_w * scn.g, absolute=absolute)
+        Lm = heat_line_matrix(scn, m, t_new)[rows]
+        xm = np.where(mask, 0.0, _f64(x))
+        y = y + (abs(Lm) @ np.abs(xm) if absolute else Lm @ xm)
+    xr = _f64(x)[rows]
+    return np.where(mask[rows], np.abs(xr) if absolute else xr, y)
 
 
 def operator(scn, field: int, P=None, t_new: Optional[float] = None, steady=None):

@@ -302,6 +302,42 @@ void orc_apply_rows(const orc_mesh *m, const orc_op *op, const double *x, const 
     }
 }
 
+/* Same rows with every element entry and x entry taken in absolute value:
+ * an upper bound of (|A| |x|)_I used to scale rounding-error tolerances. */
+void orc_apply_rows_abs(const orc_mesh *m, const orc_op *op, const double *x, const uint8_t *colmask,
+                        const int64_t *rows, int64_t nrows, double *out)
+{
+    int p = m->p, n1 = p + 1, nl = n1 * n1 * n1;
+    int64_t NX = nodes_dim(m, 0), NY = nodes_dim(m, 1);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t I = rows[r];
+        int i = (int)(I % NX), j = (int)((I / NX) % NY), k = (int)(I / (NX * NY));
+        double Ae[MAXNL * MAXNL];
+        double acc = 0.0;
+        int c0[3], c1[3], idx[3] = {i, j, k};
+        for (int d = 0; d < 3; d++) {
+            if (idx[d] % p == 0) { c0[d] = idx[d] / p - 1; c1[d] = idx[d] / p; }
+            else { c0[d] = c1[d] = idx[d] / p; }
+            if (c0[d] < 0) c0[d] = 0;
+            if (c1[d] > m->n[d] - 1) c1[d] = m->n[d] - 1;
+        }
+        for (int cz = c0[2]; cz <= c1[2]; cz++)
+            for (int cy = c0[1]; cy <= c1[1]; cy++)
+                for (int cx = c0[0]; cx <= c1[0]; cx++) {
+                    orc_element_matrix(m, op, cx, cy, cz, Ae);
+                    int a = (i - p * cx) + n1 * ((j - p * cy) + n1 * (k - p * cz));
+                    for (int b = 0; b < nl; b++) {
+                        int bx = b % n1, by = (b / n1) % n1, bz = b / (n1 * n1);
+                        int64_t J = gnode(m, cx, cy, cz, bx, by, bz);
+                        if (colmask && colmask[J]) continue;
+                        acc += fabs(Ae[a * nl + b]) * fabs(x[J]);
+                    }
+                }
+        out[r] = acc;
+    }
+}
+
 /* --------------------------------------------------------- load vectors */
 /* out_a += sum_cells int N_a f dV, with f given at the nq^3 Gauss points of
  * every cell (cell-major, then qx fastest). */

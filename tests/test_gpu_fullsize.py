@@ -1,0 +1,163 @@
+"""Parity at the full workload sizes, on sampled outputs.
+
+The operators are applied on the GPU to a random vector at the sizes the
+benchmark runs (tile shapes autotuned as the benchmark does), and sampled
+rows are recomputed one by one by the oracle from the element integrals of
+the cells around each row (oracle.operator_rows).  Bound per row: the
+forward error of an inner product evaluated in the operator's precision,
+64 u (|A| |x|)_i, with |A| |x| bounded by the sum of absolute element
+contributions; the FP32 heat operator reads the pressure as the FP32
+piezometric head and its reference uses that same rounded pressure.  The FP64
+heat operator forms grad P at each Gauss point from nodal pressures of about
+1e6 Pa whose differences are tiny, so the rounding error of the Darcy flux is
+of order u k max|P| / h, far above u |q|; its bound adds 64 u times the
+convection rows of |A| |x| evaluated with that flux magnitude (a field with
+gradient max|P| / h_d along every axis).
+
+Samples: random rows, rows on and next to the 15-node tile edges (Q1) or
+30-node tile edges (Q2), domain faces, low and high z, and every node of
+the well columns (injection line operator).
+
+The batched design set (64 instances, 32^3 .. 96^3 cells) advances one
+step in one batch with captured graphs; sampled instances are judged by
+their true FP64 residual in the oracle's own assembled matrices, and the
+smallest one must equal its solo run bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import print_case, to_dev
+
+pytestmark = pytest.mark.gpu
+
+EPS = {0: np.finfo(np.float64).eps, 1: np.finfo(np.float32).eps}
+
+
+def sample_rows(scn, rng, n_random=2000):
+    p = scn.degree
+    NX, NY, NZ = (p * c + 1 for c in scn.ncells)
+    tile = 15 * p
+    edge = sorted({v for t in range(0, NX + tile, tile) for v in (t - 1, t, t + 1) if 0 <= v < NX} | {NX - 2})
+    edgy = sorted({v for t in range(0, NY + tile, tile) for v in (t - 1, t, t + 1) if 0 <= v < NY} | {NY - 2})
+    ks = sorted({0, 1, 2, NZ // 2, NZ - 3, NZ - 2, NZ - 1})
+    rows = [rng.integers(0, NX * NY * NZ, n_random)]
+    ii = rng.choice(edge, 300)
+    jj = rng.choice(edgy, 300)
+    kk = rng.choice(ks, 300)
+    rows.append(ii + NX * (jj + NY * kk))
+    om = oracle.Mesh.of(scn)
+    for ln in scn.lines:
+        if ln.kind != synth.LINE_WELL:
+            continue
+        i = int(np.floor((ln.x - scn.origin[0]) / (scn.extent[0] / (NX - 1)) + 0.5))
+        j = int(np.floor((ln.y - scn.origin[1]) / (scn.extent[1] / (NY - 1)) + 0.5))
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                if 0 <= i + di < NX and 0 <= j + dj < NY:
+                    rows.append(i + di + NX * (j + dj + NY * np.arange(NZ)))
+    r = np.unique(np.concatenate(rows).astype(np.int64))
+    assert r.max() < om.nnode
+    return r
+
+
+def check_apply(hts, scn, label):
+    import torch
+    m = hts.from_scenario(scn, initial=False)
+    hts.autotune([m])
+    om = oracle.Mesh.of(scn)
+    rng = np.random.default_rng(21)
+    X, Y, Z = om.coords()
+    P = 1e5 + scn.rho_w * scn.g * (scn.extent[2] - Z) - 0.02 * X + 5.0 * rng.standard_normal(om.nnode)
+    m.set_state(0, P, scn.t0)
+    x = rng.standard_normal(om.nnode)
+    rows = sample_rows(scn, rng)
+    NX, NY = om.dims[0], om.dims[1]
+    kz = np.arange(om.nnode) // (NX * NY)
+    dz = scn.extent[2] / (scn.degree * scn.ncells[2])
+    rg = scn.rho_w * scn.g
+    Pt = ((P - P[0]) + rg * (kz * dz)).astype(np.float32).astype(np.float64) - rg * (kz * dz) + P[0]
+    for field in (0, 1):
+        for prec in (0, 1):
+            print_case(label, "field", field, "prec", prec, "rows", rows.size)
+            dt = "float64" if prec == 0 else "float32"
+            xd = to_dev(x, dt)
+            yd = torch.zeros_like(xd)
+            m.apply_operator(field, prec, scn.dt, xd, yd)
+            torch.cuda.synchronize()
+            y = yd.double().cpu().numpy()[rows]
+            Pr = None if field == 0 else (P if prec == 0 else Pt)
+            xin = x if prec == 0 else x.astype(np.float32).astype(np.float64)
+            ref = oracle.operator_rows(scn, field, rows, xin, P=Pr)
+            bound = oracle.operator_rows(scn, field, rows, xin, P=Pr, absolute=True)
+            tol = 64 * EPS[prec] * bound + 1e-300
+            if field == 1 and prec == 0:
+                k, _, _ = oracle.coefficients(scn)
+                h = [scn.extent[d] / scn.ncells[d] for d in range(3)]
+                Pgrad = np.abs(P).max() * (X / h[0] + Y / h[1] + Z / h[2])
+                mask, _ = oracle.dirichlet(scn, om, 1, scn.t0 + scn.dt)
+                conv = oracle.apply_rows(om, rows, xin, colmask=mask, kvel=k, P=Pgrad,
+                                         adv_scale=scn.dt * scn.c_w, absolute=True)
+                tol = tol + 64 * EPS[0] * conv
+            err = np.abs(y - ref)
+            assert np.all(err <= tol), (label, field, prec, float(np.max(err / tol)))
+    del m
+    torch.cuda.synchronize()
+
+
+def test_c2_full_size_apply(hts):
+    check_apply(hts, synth.config2(ncells=(128, 128, 64), n_steps=1), "c2 128x128x64")
+
+
+def test_c3_q1_full_size_apply(hts):
+    check_apply(hts, synth.config3(degree=1, ncells=(256, 256, 128), n_steps=1), "c3 Q1 256x256x128")
+
+
+def test_c3_q2_full_size_apply(hts):
+    check_apply(hts, synth.config3(degree=2, ncells=(128, 128, 64), n_steps=1), "c3 Q2 128x128x64")
+
+
+def test_c4_batched_full_size_step(hts):
+    import torch
+    scns = [synth.config4_instance(i, n_steps=1) for i in range(64)]
+    sizes = [s.ncells[0] for s in scns]
+    print_case("c4 batched 64 instances, cells per edge", min(sizes), "..", max(sizes),
+               "total nodes", sum((n + 1) ** 3 for n in sizes))
+    o = hts.default_opts(rtol=1e-8, use_graph=1)
+    ms = [hts.from_scenario(s, opts=o) for s in scns]
+    P0 = [m.get_state(0)[0] for m in ms]
+    T0 = [m.get_state(1)[0] for m in ms]
+    code, stats = hts.advance(ms, 1, scns[0].dt, o)
+    assert code == 0
+    for st in stats:
+        assert st["status"] == [0, 0]
+        assert st["relres"][0] <= 1e-8 and st["relres"][1] <= 1e-8
+    order = np.argsort(sizes)
+    for idx in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        s = scns[idx]
+        print_case("c4 residual check instance", idx, "cells", s.ncells)
+        om = oracle.Mesh.of(s)
+        t1 = s.t0 + s.dt
+        P1, T1 = ms[idx].get_state(0)[0], ms[idx].get_state(1)[0]
+        A, b = oracle.pressure_system(s, om, P0[idx], t1)
+        mask, g = oracle.dirichlet(s, om, 0, t1)
+        free, AFF, bF = oracle.eliminate(A, b, mask, g)
+        r = oracle.residual_ld(AFF, bF, P1[free])
+        assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(bF)
+        # boundary data: the same affine function evaluated in another order
+        assert np.all(np.abs(P1[mask] - g[mask]) <= 4 * EPS[0] * np.abs(g[mask]))
+        H, hb = oracle.heat_system(s, om, T0[idx], P1, t1)
+        mask, g = oracle.dirichlet(s, om, 1, t1)
+        free, HFF, hF = oracle.eliminate(H, hb, mask, g)
+        r = oracle.residual_ld(HFF, hF, T1[free])
+        assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(hF)
+        assert np.all(np.abs(T1[mask] - g[mask]) <= 4 * EPS[0] * np.abs(g[mask]))
+    # the smallest instance alone gives the same bits
+    idx = int(order[0])
+    solo = hts.from_scenario(scns[idx], opts=o)
+    hts.advance([solo], 1, scns[idx].dt, o)
+    assert np.array_equal(solo.get_state(0)[0], ms[idx].get_state(0)[0])
+    assert np.array_equal(solo.get_state(1)[0], ms[idx].get_state(1)[0])
+    del ms, solo
+    torch.cuda.synchronize()
