@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0      # dense MFMA
 
 
 def measured_traffic(kernel_class: str, ncells):
@@ -71,10 +72,65 @@ def parse():
     ap.add_argument("--timing-steps", type=int, default=3,
                     help="extra steps after the timed region with per-launch kernel events (eager launches) "
                          "for the roofline figures")
+    ap.add_argument("--learned", type=int, default=1,
+                    help="also run the learned-preconditioner leg (c5: network trained in set-up on pairs "
+                         "harvested from plain multigrid solves of training draws, timed on an unseen draw)")
+    ap.add_argument("--nn-draws", type=int, default=5, help="harvest draws (the last one held out)")
+    ap.add_argument("--nn-steps", type=int, default=2)
+    ap.add_argument("--nn-pairs", type=int, default=6, help="pairs kept per inner solve")
+    ap.add_argument("--nn-epochs", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the workload, run a plain elementwise copy of MIB MiB (FP32) three "
                          "times: the reference that scales hardware byte counters")
     return ap.parse_args()
+
+
+def learned_leg(a, hts, synth, nc, np, torch):
+    """c5: the learned preconditioner against plain multigrid on one unseen
+    permeability draw of the layered aquifer (same grid as the headline)."""
+    t_setup = time.perf_counter()
+    o64 = hts.default_opts(mode=hts.MODE_FP64, rtol=1e-8)
+    draws = [hts.from_scenario(synth.config5(5000 + i, ncells=nc, n_steps=a.nn_steps), opts=o64)
+             for i in range(a.nn_draws)]
+    net = hts.Net(levels=4, channels=(16, 32, 48, 64), seed=7)
+    net.harvest(draws, a.nn_steps, synth.DAY, a.nn_pairs)
+    del draws
+    t_train = time.perf_counter()
+    tr = net.train(epochs=a.nn_epochs, lr=2e-3, batch=4, val_draws=1)
+    torch.cuda.synchronize()
+    t_done = time.perf_counter()
+    n_steps = a.warmup + a.steps
+    out = {"workload": "unseen draw seed 5100, %dx%dx%d Q1" % nc, "train": tr,
+           "harvest_s": round(t_train - t_setup, 2), "train_s": round(t_done - t_train, 2)}
+    for label, mode in (("learned", hts.MODE_LEARNED), ("multigrid_fp64", hts.MODE_FP64)):
+        o = hts.default_opts(mode=mode, rtol=1e-8, use_graph=a.use_graph)
+        if mode == hts.MODE_LEARNED:
+            o.nn = net.h.value
+        scn = synth.config5(5100, ncells=nc, n_steps=n_steps)
+        m = hts.from_scenario(scn, opts=o)
+        for _ in range(a.warmup):
+            m.solve_step(scn.dt, o)
+        torch.cuda.synchronize()
+        sts = []
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            sts.append(m.solve_step(scn.dt, o)[1])
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        out[label] = {"value": round(2 * m.nnode * a.steps / dt_s / 1e6, 3),
+                      "ms_per_step": round(1e3 * dt_s / a.steps, 3),
+                      "pressure_iters": float(np.mean([s["iters"][0] for s in sts])),
+                      "pressure_ms": round(float(np.mean([s["time_ms"][0] for s in sts])), 3),
+                      "fallbacks": int(sum(s["fallbacks"] for s in sts)),
+                      "max_relres": float(max(max(s["relres"]) for s in sts))}
+        del m
+    dims = tuple(c + 1 for c in nc)
+    ms, fl = net.time_forward(dims, reps=5)
+    out["forward"] = {"ms": round(ms, 3), "gflop": round(fl / 1e9, 2),
+                      "roofline": {"bound": "mfma", "achieved": round(fl / (ms * 1e-3) / 1e12, 2),
+                                   "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)}}
+    return out
 
 
 def main():
@@ -145,6 +201,10 @@ def main():
         del m
         torch.cuda.synchronize()
 
+    learned = None
+    if a.learned:
+        learned = learned_leg(a, hts, synth, nc, np, torch)
+
     best = max(results, key=lambda k: results[k]["value"])
     R = results[best]
     # dominant kernel class in the timed region
@@ -208,6 +268,7 @@ def main():
                    "inner_rtol": a.inner_rtol, "autotune": not a.no_autotune, "use_graph": bool(a.use_graph),
                    "heat_precond": ["multigrid", "chebyshev-jacobi"][a.heat_precond]},
         "roofline": roofline,
+        "learned": learned,
         "cpu_baseline": cpu,
         "modes": {mname: {"value": round(r["value"], 3), "ms_per_step": round(r["ms_per_step"], 3),
                           "pressure_iters": r["iters_p"], "heat_iters": r["iters_h"],

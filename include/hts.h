@@ -319,6 +319,13 @@ hts_status hts_nn_conv3d(int32_t op, int32_t cin, int32_t cout, int32_t stride, 
                          const uint16_t *x, const uint16_t *w, const float *bias, const uint16_t *g, float *out,
                          float *out_bias, void *stream);
 
+/* Time `reps` forward passes of the network on a node grid dims = {NX, NY,
+ * NZ} with HIP events on the network's stream; flop_per_forward (may be
+ * NULL) gets 2 * 27 * Cin * Cout * voxels summed over the layers (logical
+ * channels).  For measurement. */
+hts_status hts_nn_time_forward(hts_nn *nn, const int32_t dims[3], int32_t reps, double *ms_per_forward,
+                               double *flop_per_forward);
+
 /* For each of the n_draws meshes (same node grid, pressure state set): run
  * n_steps plain multigrid-CG pressure steps (Eq. 3, FP64, rtol 1e-10) from the
  * mesh's state without changing it, and from every inner CG solve keep up to

@@ -33,7 +33,7 @@ EXPORTS = [
     "hts_apply_operator", "hts_solve_steady_pressure", "hts_solve_step", "hts_advance",
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
     "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing", "hts_nn_num_params",
-    "hts_nn_set_params", "hts_nn_get_params", "hts_nn_eval", "hts_nn_conv3d",
+    "hts_nn_set_params", "hts_nn_get_params", "hts_nn_eval", "hts_nn_conv3d", "hts_nn_time_forward",
 ]
 
 
@@ -151,6 +151,7 @@ def load():
         "hts_nn_get_params": (st, [vp, vp, C.c_int64]),
         "hts_nn_eval": (st, [vp, P(i32), vp, vp, vp, vp, P(d), vp]),
         "hts_nn_conv3d": (st, [i32, i32, i32, i32, P(i32), vp, vp, vp, vp, vp, vp, vp]),
+        "hts_nn_time_forward": (st, [vp, P(i32), i32, P(d), P(d)]),
         "hts_nn_save": (st, [vp, C.c_char_p]),
         "hts_nn_load": (st, [vp, C.c_char_p]),
         "hts_kernel_timing": (st, [i32, vp]),
@@ -403,6 +404,12 @@ class Net:
         _check(load().hts_nn_train(self.h, epochs, lr, batch, val_draws, C.byref(st)))
         return {"epochs": st.epochs_done, "pairs": st.pairs, "loss_first": st.loss_first,
                 "loss_last": st.loss_last, "val_loss": st.val_loss}
+
+    def time_forward(self, dims, reps=5):
+        """(ms per forward pass, flops per forward pass) on a dims grid."""
+        ms, fl = C.c_double(), C.c_double()
+        _check(load().hts_nn_time_forward(self.h, (C.c_int32 * 3)(*dims), reps, C.byref(ms), C.byref(fl)))
+        return ms.value, fl.value
 
     def save(self, path):
         _check(load().hts_nn_save(self.h, str(path).encode()))

@@ -595,6 +595,42 @@ hts_status hts_nn_conv3d(int32_t op, int32_t cin, int32_t cout, int32_t stride, 
     });
 }
 
+hts_status hts_nn_time_forward(hts_nn *nn, const int32_t dims[3], int32_t reps, double *ms_per_forward,
+                               double *flop_per_forward)
+{
+    return guard_call([&] {
+        if (!nn || !dims || reps < 1 || !ms_per_forward) throw Error(HTS_ERR_ARG, "bad arguments");
+        const Dims d0{dims[0], dims[1], dims[2]};
+        NNWork &W = workspace(nn, d0);
+        hipStream_t s = nn->s;
+        // input: a smooth nonzero pattern (the time does not depend on values)
+        std::vector<float> ones((size_t)d0.n(), 1.0f);
+        DBuf<float> f;
+        f.upload(&nn->al, ones, s);
+        nn_f32_to_bf16(f.p, d0.n(), W.rbf.p, s);
+        nn_pack_input_bf(W.rbf.p, f.p, d0.n(), W.x0.p, s);
+        forward(nn, W, s);   // warm
+        hipEvent_t a, b;
+        HTS_HIP(hipEventCreate(&a));
+        HTS_HIP(hipEventCreate(&b));
+        HTS_HIP(hipEventRecord(a, s));
+        for (int r = 0; r < reps; r++) forward(nn, W, s);
+        HTS_HIP(hipEventRecord(b, s));
+        HTS_HIP(hipEventSynchronize(b));
+        float ms = 0.0f;
+        HTS_HIP(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        *ms_per_forward = ms / reps;
+        if (flop_per_forward) {
+            // 2 flops per multiply-add of every 3x3x3 convolution (logical channels)
+            double fl = 0.0;
+            for (const NNLayer &Ly : nn->layers) fl += 2.0 * 27.0 * Ly.cin * Ly.cout * (double)W.n[Ly.lout];
+            *flop_per_forward = fl;
+        }
+    });
+}
+
 hts_status hts_nn_harvest(hts_nn *nn, hts_mesh *const *meshes, int32_t n_draws, int32_t n_steps, double dt,
                           int32_t pairs_per_solve)
 {
