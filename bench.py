@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--heat-cheb", type=int, default=2, help="heat Chebyshev-Jacobi degree")
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--heat-precond", type=int, default=1, help="0 multigrid, 1 Chebyshev-Jacobi")
+    ap.add_argument("--heat-precond", type=int, default=1, help="0 multigrid, 1 Chebyshev-Jacobi, 2 separable mass")
     ap.add_argument("--use-graph", type=int, default=1,
                     help="replay captured HIP graphs for the Krylov iteration chunks (1) or launch eagerly (0)")
     ap.add_argument("--timing-steps", type=int, default=3,
@@ -266,7 +266,7 @@ def main():
                                "dt = 1 day, rtol 1e-8, mode %s" % (nc + (R["nnode"], best)),
                    "seed": 2, "cheb_degree": a.cheb, "heat_cheb_degree": a.heat_cheb,
                    "inner_rtol": a.inner_rtol, "autotune": not a.no_autotune, "use_graph": bool(a.use_graph),
-                   "heat_precond": ["multigrid", "chebyshev-jacobi"][a.heat_precond]},
+                   "heat_precond": ["multigrid", "chebyshev-jacobi", "tensor-mass"][a.heat_precond]},
         "roofline": roofline,
         "learned": learned,
         "cpu_baseline": cpu,

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "tmass.h"
 
 namespace hts {
 
@@ -62,6 +63,15 @@ struct Hier {
     Tables ops;                            // fine-level operator
     std::vector<Level> lev;
     std::vector<double> lmax;
+    // separable mass preconditioner (heat, Q1)
+    bool tensor = false;
+    DBuf<TMassInst> tm64, tm32;
+    std::vector<DBuf<double>> tfac;
+    DBuf<double> ts64;
+    DBuf<float> ts32;
+    DBuf<int64_t> tl[3];                   // first block of each instance per axis
+    int64_t tn[3] = {0, 0, 0};             // blocks per axis
+    int tlb[3] = {1, 1, 1}, tlds64[3] = {0, 0, 0}, tlds32[3] = {0, 0, 0};
 };
 
 struct FieldStats {
@@ -182,6 +192,8 @@ struct Batch {
     template <typename T> void smooth(Hier &H, int l, int steps, int first, const T *b, T *&cur, T *&oth);
     template <typename T> void vcycle(Hier &H, int l, const T *b, T *x);
     template <typename T> void cheb_prec(Hier &H, const T *b, T *x);
+    template <typename T> void tmass_prec(Hier &H, const T *b, T *x);
+    void build_tmass(Hier &H, double dt);
     template <typename T>
     int cg(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit, bool flexible,
            int check_every);

@@ -630,11 +630,127 @@ Hier &Batch::pressure_hier(bool steady, double dt, const hts_solver_opts &o)
     return ref;
 }
 
+// Separable heat preconditioner tables (Q1): nodal S = cbar_T^-1/2 and the
+// Thomas factors of each axis's 1D matrix B = M + alpha K, per cell
+// h [1/3 1/6; 1/6 1/3] + (alpha / h) [1 -1; -1 1], alpha = dt median(lambda /
+// c_T) of the instance, with identity end rows where that face is Dirichlet.
+void Batch::build_tmass(Hier &H, double dt)
+{
+    H.tensor = true;
+    std::vector<double> sv((size_t)ntot);
+    std::vector<TMassInst> h64(n), h32(n);
+    std::vector<int64_t> lb[3];
+    for (int a = 0; a < 3; a++) lb[a].assign(n + 1, 0);
+    H.tfac.clear();
+    H.tfac.reserve(3 * n);
+    for (int i = 0; i < n; i++) {
+        hts_mesh *M = m[i];
+        const int NX = M->N[0], NY = M->N[1], NZ = M->N[2];
+        for (int k = 0; k < NZ; k++)
+            for (int j = 0; j < NY; j++)
+                for (int x = 0; x < NX; x++) {
+                    double acc = 0.0;
+                    int cnt = 0;
+                    for (int dz = -1; dz <= 0; dz++)
+                        for (int dy = -1; dy <= 0; dy++)
+                            for (int dx = -1; dx <= 0; dx++) {
+                                const int cx = x + dx, cy = j + dy, cz = k + dz;
+                                if (cx < 0 || cx >= M->n[0] || cy < 0 || cy >= M->n[1] || cz < 0 || cz >= M->n[2])
+                                    continue;
+                                acc += M->hcT[(size_t)cx + (size_t)M->n[0] * (cy + (size_t)M->n[1] * cz)];
+                                cnt++;
+                            }
+                    sv[(size_t)off[i] + x + (size_t)NX * (j + (size_t)NY * k)] = 1.0 / std::sqrt(acc / cnt);
+                }
+        TMassInst t{};
+        t.N[0] = NX; t.N[1] = NY; t.N[2] = NZ;
+        t.off = off[i];
+        const int dm = M->dmask[1];
+        std::vector<double> ratio(M->hcT.size());
+        for (size_t c = 0; c < ratio.size(); c++) ratio[c] = M->hlam[c] / M->hcT[c];
+        std::nth_element(ratio.begin(), ratio.begin() + ratio.size() / 2, ratio.end());
+        const double alpha = dt * ratio[ratio.size() / 2];
+        for (int a = 0; a < 3; a++) {
+            const int nn = M->N[a];
+            const double h = M->h[a];
+            const bool dlo = (dm >> (2 * a)) & 1, dhi = (dm >> (2 * a + 1)) & 1;
+            std::vector<double> A(nn, 0.0), B(nn, 0.0), Cc(nn, 0.0);
+            for (int e = 0; e + 1 < nn; e++) {   // cell [e, e+1]
+                B[e] += h / 3.0 + alpha / h;
+                B[e + 1] += h / 3.0 + alpha / h;
+                Cc[e] += h / 6.0 - alpha / h;
+                A[e + 1] += h / 6.0 - alpha / h;
+            }
+            auto ident = [&](int e) {
+                A[e] = 0.0; B[e] = 1.0; Cc[e] = 0.0;
+                if (e > 0) Cc[e - 1] = 0.0;
+                if (e < nn - 1) A[e + 1] = 0.0;
+            };
+            if (dlo) ident(0);
+            if (dhi) ident(nn - 1);
+            std::vector<double> f(3 * (size_t)nn);
+            double cprev = 0.0;
+            for (int e = 0; e < nn; e++) {
+                const double piv = B[e] - A[e] * cprev;
+                const double inv = 1.0 / piv;
+                const double cp = Cc[e] * inv;
+                f[e] = A[e];
+                f[nn + e] = inv;
+                f[2 * nn + e] = cp;
+                cprev = cp;
+            }
+            H.tfac.emplace_back();
+            H.tfac.back().upload(al, f, s);
+            t.fac[a] = H.tfac.back().p;
+        }
+        h64[i] = t;
+        h32[i] = t;
+    }
+    // lines per wavefront (staged in at most 64 KB of LDS in FP64) and the
+    // first block of every instance along each axis
+    for (int a = 0; a < 3; a++) {
+        int nmax = 1;
+        for (int i = 0; i < n; i++) nmax = std::max(nmax, m[i]->N[a]);
+        const int ld = nmax | 1;
+        H.tlb[a] = std::max(1, std::min(64, 65536 / (ld * 8)));
+        H.tlds64[a] = H.tlb[a] * ld * 8;
+        H.tlds32[a] = H.tlb[a] * ld * 4;
+        for (int i = 0; i < n; i++) {
+            const int NX = m[i]->N[0], NY = m[i]->N[1], NZ = m[i]->N[2];
+            const int64_t lines = a == 0 ? (int64_t)NY * NZ : (a == 1 ? (int64_t)NX * NZ : (int64_t)NX * NY);
+            lb[a][i + 1] = lb[a][i] + (lines + H.tlb[a] - 1) / H.tlb[a];
+        }
+    }
+    H.ts64.upload(al, sv, s);
+    std::vector<float> sf(sv.begin(), sv.end());
+    H.ts32.upload(al, sf, s);
+    for (int i = 0; i < n; i++) {
+        h64[i].s = H.ts64.p;
+        h32[i].s = H.ts32.p;
+    }
+    H.tm64.upload(al, h64, s);
+    H.tm32.upload(al, h32, s);
+    for (int a = 0; a < 3; a++) {
+        H.tl[a].upload(al, lb[a], s);
+        H.tn[a] = lb[a][n];
+    }
+}
+
+template <typename T>
+void Batch::tmass_prec(Hier &H, const T *b, T *x)
+{
+    const int64_t *lb[3] = {H.tl[0].p, H.tl[1].p, H.tl[2].p};
+    const bool d = std::is_same<T, double>::value;
+    const OpDev *ops = d ? H.ops.d64.p : H.ops.d32.p;
+    launch_tmass<T>(d ? H.tm64.p : H.tm32.p, n, lb, H.tn, H.tlb, d ? H.tlds64 : H.tlds32, active.p, ops, b, x, s);
+}
+
 Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
 {
     const bool mg = o.heat_precond == 0;
+    const bool tensor = o.heat_precond == 2 && p == 1;
     const int deg = mg ? std::max(1, std::min(o.heat_cheb_degree, 8)) : std::max(1, std::min(o.heat_cheb_degree, 16));
-    if (heat && heat->dt == dt && heat->deg == deg && heat->multigrid == mg) return *heat;
+    if (heat && heat->dt == dt && heat->deg == deg && heat->multigrid == mg && heat->tensor == tensor) return *heat;
     drop_graphs();
     heat = std::make_unique<Hier>();
     Hier &H = *heat;
@@ -642,6 +758,11 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     H.dt = dt;
     H.deg = deg;
     H.multigrid = mg;
+    if (tensor) {
+        make_tables(H.ops, 1, dt, false, false);
+        build_tmass(H, dt);
+        return H;
+    }
     // Chebyshev-Jacobi alone covers [lmax/30, 1.1 lmax]; as a multigrid
     // smoother the usual [lmax/15, 1.1 lmax]
     H.ratio = env_or("HTS_HEAT_RATIO", mg ? 15.0 : 30.0);
@@ -1178,6 +1299,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
             vfill<float>(v, x32.p, 0.0f);
             auto M = [&](const float *r_, float *z_) {
                 if (mg) vcycle<float>(*mg, 0, r_, z_);
+                else if (hprec->tensor) tmass_prec<float>(*hprec, r_, z_);
                 else cheb_prec<float>(*hprec, r_, z_);
             };
             graph_tag = (mg ? "mg" : "cheb") + std::to_string((uintptr_t)(mg ? mg : hprec));
@@ -1189,6 +1311,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
             vfill<double>(v, inner_x.p, 0.0);
             auto M = [&](const double *r_, double *z_) {
                 if (mg) vcycle<double>(*mg, 0, r_, z_);
+                else if (hprec->tensor) tmass_prec<double>(*hprec, r_, z_);
                 else cheb_prec<double>(*hprec, r_, z_);
             };
             graph_tag = (mg ? "mg" : "cheb") + std::to_string((uintptr_t)(mg ? mg : hprec));
