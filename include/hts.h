@@ -130,8 +130,13 @@ typedef struct {
     int32_t heat_precond;    /* 0: multigrid V-cycle (Galerkin levels of the
                                 symmetric part M_cT + dt K_lambda, Chebyshev
                                 smoothing with the full heat operator);
-                                1: Chebyshev-Jacobi only (default: the heat
-                                operator is mass dominated)                     */
+                                1: Chebyshev-Jacobi with the full heat
+                                operator (default: the heat operator is mass
+                                dominated);
+                                2: separable (M_x + a K_x) x (M_y + a K_y) x
+                                (M_z + a K_z) line solves scaled by the nodal
+                                capacity, a = dt median(lambda / c_T) (Q1;
+                                Q2 uses 1)                                      */
 } hts_solver_opts;
 
 typedef struct {
