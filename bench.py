@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--heat-cheb", type=int, default=2, help="heat Chebyshev-Jacobi degree")
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--mg-coarse-max", type=int, default=5000,
+                    help="coarsen until a level has at most this many nodes (dense FP64 solve there)")
     ap.add_argument("--heat-precond", type=int, default=1, help="0 multigrid, 1 Chebyshev-Jacobi, 2 separable mass")
     ap.add_argument("--use-graph", type=int, default=1,
                     help="replay captured HIP graphs for the Krylov iteration chunks (1) or launch eagerly (0)")
@@ -162,7 +164,7 @@ def main():
         o = hts.default_opts(mode=mode_id[mode], rtol=1e-8, check_every=a.check_every,
                              cheb_degree=a.cheb, heat_cheb_degree=a.heat_cheb,
                              inner_rtol=a.inner_rtol, heat_precond=a.heat_precond,
-                             use_graph=a.use_graph)
+                             use_graph=a.use_graph, mg_coarse_max=a.mg_coarse_max)
         m = hts.from_scenario(scn, opts=o)
         if not a.no_autotune:
             hts.autotune([m])        # setup: picks the kernels' z-chunk depth
@@ -266,6 +268,7 @@ def main():
                                "dt = 1 day, rtol 1e-8, mode %s" % (nc + (R["nnode"], best)),
                    "seed": 2, "cheb_degree": a.cheb, "heat_cheb_degree": a.heat_cheb,
                    "inner_rtol": a.inner_rtol, "autotune": not a.no_autotune, "use_graph": bool(a.use_graph),
+                   "mg_coarse_max": a.mg_coarse_max,
                    "heat_precond": ["multigrid", "chebyshev-jacobi", "tensor-mass"][a.heat_precond]},
         "roofline": roofline,
         "learned": learned,

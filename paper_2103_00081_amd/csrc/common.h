@@ -73,7 +73,9 @@ struct OpDev {
 // One block of work of the z-marching operator kernels: node-column tile
 // (tx, ty) of instance inst, owning node planes [z0, z1).
 struct WorkItem {
-    int32_t inst, tx, ty, z0, z1, pad0, pad1, pad2;
+    int32_t inst, tx, ty, z0, z1;
+    int32_t slot;              // natural index: where the block's partial sum goes
+    int32_t pad1, pad2;
 };
 
 // Contiguous range [beg, end) of a batch vector belonging to one instance.

@@ -371,7 +371,7 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
         double v = wave_sum(acc);
         if ((tid & 63) == 0) red[tid >> 6] = v;
         __syncthreads();
-        if (tid == 0) ep.partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        if (tid == 0) ep.partial[wi.slot] = (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 

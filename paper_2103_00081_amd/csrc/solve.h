@@ -43,7 +43,7 @@ struct Level {
     DBuf<CoarseDev> cd;
     int ncd = 0;
     int64_t crows = 0;
-    DBuf<int32_t> segp, segi;
+    DBuf<int32_t> segp;
     RedCtx red{};
     DBuf<double> S64;
     DBuf<float> S32;
@@ -91,13 +91,13 @@ struct Batch {
     std::vector<Chunk> hch;
     DBuf<Chunk> ch;
     int nch = 0;
-    DBuf<int32_t> chp, chi;
+    DBuf<int32_t> chp;
     RedCtx rch{};
     // fine-level work lists per field (the z-chunk depth is tuned per field)
     std::vector<WorkItem> hwork[2];
     DBuf<WorkItem> work[2];
     int nwork[2] = {0, 0};
-    DBuf<int32_t> wkp[2], wki[2];
+    DBuf<int32_t> wkp[2];
     RedCtx rwk[2]{};
     int zc_force[2] = {0, 0};
 

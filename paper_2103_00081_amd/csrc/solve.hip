@@ -35,19 +35,18 @@ static double env_or(const char *name, double def)
 }
 
 static void build_chunks(const std::vector<int64_t> &off, const std::vector<int64_t> &cnt, int len,
-                         std::vector<Chunk> &ch, std::vector<int32_t> &segp, std::vector<int32_t> &segi)
+                         std::vector<Chunk> &ch, std::vector<int32_t> &segp)
 {
-    ch.clear(); segp.assign(1, 0); segi.clear();
+    ch.clear(); segp.assign(1, 0);
     for (size_t i = 0; i < off.size(); i++) {
         for (int64_t b = 0; b < cnt[i]; b += len) {
             Chunk c{};
             c.inst = (int32_t)i;
             c.beg = off[i] + b;
             c.end = off[i] + std::min<int64_t>(cnt[i], b + len);
-            segi.push_back((int32_t)ch.size());
             ch.push_back(c);
         }
-        segp.push_back((int32_t)segi.size());
+        segp.push_back((int32_t)ch.size());
     }
 }
 
@@ -204,6 +203,7 @@ void Batch::build_work()
                     for (int x = 0; x < tx; x++) {
                         WorkItem w{};
                         w.inst = i; w.tx = x; w.ty = y; w.z0 = z0; w.z1 = std::min(M->N[2], z0 + zc);
+                        w.slot = (int32_t)nat.size();
                         nat.push_back(w);
                     }
         }
@@ -211,27 +211,20 @@ void Batch::build_work()
         // contiguous run of neighbouring tiles so halos stay in its L2.
         const int64_t T = (int64_t)nat.size(), per = (T + 7) / 8;
         hwork[f].clear();
-        std::vector<int64_t> pos_of(T, -1);   // natural index -> launch position
         for (int64_t b = 0; b < 8 * per; b++) {
             int64_t idx = (b % 8) * per + b / 8;
-            if (idx < T) {
-                pos_of[idx] = (int64_t)hwork[f].size();
-                hwork[f].push_back(nat[idx]);
-            }
+            if (idx < T) hwork[f].push_back(nat[idx]);
         }
         nwork[f] = (int)hwork[f].size();
         work[f].upload(al, hwork[f], s);
-        // per-instance partial sums are reduced in the natural tile order, so a
-        // batched instance sums exactly like the same instance alone
-        std::vector<int32_t> sp(n + 1, 0), si;
-        for (int i = 0; i < n; i++) {
-            for (int64_t k = 0; k < T; k++)
-                if (nat[k].inst == i) si.push_back((int32_t)pos_of[k]);
-            sp[i + 1] = (int32_t)si.size();
-        }
+        // a block writes its partial sum at the tile's natural index, so the
+        // partials of an instance are contiguous and reduced in natural tile
+        // order: a batched instance sums exactly like the same instance alone
+        std::vector<int32_t> sp(n + 1, 0);
+        for (const WorkItem &w : nat) sp[w.inst + 1]++;
+        for (int i = 0; i < n; i++) sp[i + 1] += sp[i];
         wkp[f].upload(al, sp, s);
-        wki[f].upload(al, si, s);
-        rwk[f] = RedCtx{wkp[f].p, wki[f].p, n};
+        rwk[f] = RedCtx{wkp[f].p, n};
     }
     partial.alloc(al, (size_t)std::max<int64_t>(std::max(nwork[0], nwork[1]), nch) * 64 + 64);
 }
@@ -264,13 +257,12 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->ntot = tot;
     B->ctot = 0;
     for (int i = 0; i < n; i++) B->ctot += ms[i]->ncell;
-    std::vector<int32_t> sp, si;
-    build_chunks(B->off, cnt, CHUNK_LEN, B->hch, sp, si);
+    std::vector<int32_t> sp;
+    build_chunks(B->off, cnt, CHUNK_LEN, B->hch, sp);
     B->nch = (int)B->hch.size();
     B->ch.upload(al, B->hch, s);
     B->chp.upload(al, sp, s);
-    B->chi.upload(al, si, s);
-    B->rch = RedCtx{B->chp.p, B->chi.p, n};
+    B->rch = RedCtx{B->chp.p, n};
     B->build_work();
 
     B->S.alloc(al, (size_t)n * NSLOT);
@@ -864,19 +856,18 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
         // chunk lists: all present instances (restriction target) and the
         // continuing ones (smoothing, residual, prolongation)
         {
-            std::vector<int32_t> sp, si;
-            build_chunks(coff, ccnt, CHUNK_LEN_COARSE, C.hch_all, sp, si);
+            std::vector<int32_t> sp;
+            build_chunks(coff, ccnt, CHUNK_LEN_COARSE, C.hch_all, sp);
             C.nch_all = (int)C.hch_all.size();
             C.ch_all.upload(al, C.hch_all, s);
             C.ch_all_ext = C.ch_all.p;
             std::vector<int64_t> kcnt(n, 0);
             for (int i = 0; i < n; i++) kcnt[i] = C.cont[i] ? ccnt[i] : 0;
-            build_chunks(coff, kcnt, CHUNK_LEN_COARSE, C.hch, sp, si);
+            build_chunks(coff, kcnt, CHUNK_LEN_COARSE, C.hch, sp);
             C.nch = (int)C.hch.size();
             C.ch.upload(al, C.hch, s);
             C.segp.upload(al, sp, s);
-            C.segi.upload(al, si, s);
-            C.red = RedCtx{C.segp.p, C.segi.p, n};
+            C.red = RedCtx{C.segp.p, n};
             C.ch_ext = C.ch.p;
         }
         C.S64.alloc(al, (size_t)27 * std::max<int64_t>(ctot, 1));

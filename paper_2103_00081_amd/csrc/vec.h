@@ -12,10 +12,10 @@ struct VecCtx {
     hipStream_t stream;
 };
 
-// Segments of partial-sum indices per instance (for k_reduce).
+// Partial sums of instance i occupy partial[seg_ptr[i] .. seg_ptr[i+1]) (times
+// ncomp), in the natural order of its chunks or tiles (for k_reduce).
 struct RedCtx {
     const int32_t *seg_ptr;    // [ninst + 1]
-    const int32_t *seg_idx;
     int nseg;                  // = ninst
 };
 

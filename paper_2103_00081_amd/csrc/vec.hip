@@ -249,8 +249,9 @@ __global__ __launch_bounds__(VB) void k_piezo32(const Chunk *__restrict__ chunks
 }
 
 // ---------------------------------------------------------------- reduce
-__device__ void scalar_op(int op, int inst, const double *v, double *S, int32_t *active, int maxit,
-                          int slot, double aux)
+// pre: S_RZ, S_TOL2, S_ITER of the instance, read before the partial sums
+__device__ void scalar_op(int op, int inst, const double *v, const double *pre, double *S, int32_t *active,
+                          int maxit, int slot, double aux)
 {
     double *Si = S + (int64_t)inst * NSLOT;
     auto stop = [&](int status) {
@@ -272,23 +273,24 @@ __device__ void scalar_op(int op, int inst, const double *v, double *S, int32_t 
             Si[S_ALPHA] = 0.0;
             stop(-6);
         } else {
-            Si[S_ALPHA] = Si[S_RZ] / pq;
+            Si[S_ALPHA] = pre[0] / pq;
         }
         break;
     }
     case RED_CG_CONV: {
         const double rr = v[0];
+        const double iter = pre[2] + 1.0;
         Si[S_RR] = rr;
-        Si[S_ITER] += 1.0;
+        Si[S_ITER] = iter;
         if (!isfinite(rr)) stop(-6);
-        else if (rr <= Si[S_TOL2]) stop(0);
-        else if (Si[S_ITER] >= maxit) stop(-5);
+        else if (rr <= pre[1]) stop(0);
+        else if (iter >= maxit) stop(-5);
         break;
     }
     case RED_CG_BETA: {   // v0 = z.r (new), v1 = z.r_old (flexible)
         const double rzn = v[0];
         const double num = rzn - v[1];
-        const double rz = Si[S_RZ];
+        const double rz = pre[0];
         Si[S_BETA] = (rz != 0.0 && isfinite(num)) ? num / rz : 0.0;
         Si[S_RZ] = rzn;
         if (!isfinite(rzn)) stop(-6);
@@ -308,7 +310,7 @@ __device__ void scalar_op(int op, int inst, const double *v, double *S, int32_t 
         Si[S_ITER] = 0.0;
         Si[S_STATUS] = 1.0;
         if (!isfinite(v[0])) stop(-6);
-        else if (v[0] <= Si[S_TOL2]) stop(0);
+        else if (v[0] <= pre[1]) stop(0);
         break;
     }
     default:
@@ -316,35 +318,42 @@ __device__ void scalar_op(int op, int inst, const double *v, double *S, int32_t 
     }
 }
 
+// One block per instance.  The loads that do not depend on each other (the
+// instance's flag, its segment and the scalar slots the update reads) are
+// issued together, then the partial sums; a kernel of a few dependent memory
+// latencies in the solver's critical path.
 __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partial, int ncomp,
-                                               const int32_t *__restrict__ seg_ptr,
-                                               const int32_t *__restrict__ seg_idx, int op, int slot,
+                                               const int32_t *__restrict__ seg_ptr, int op, int slot,
                                                double *S, int32_t *active, int maxit, double aux,
                                                double *out)
 {
     __shared__ double vals[64];
     const int inst = blockIdx.x;
-    if (active && !active[inst]) return;
+    const int on = active ? active[inst] : 1;
     const int b = seg_ptr[inst], e = seg_ptr[inst + 1];
+    double pre[3] = {0.0, 0.0, 0.0};
+    if (threadIdx.x == 0) {
+        const double *Si = S + (int64_t)inst * NSLOT;
+        pre[0] = Si[S_RZ];
+        pre[1] = Si[S_TOL2];
+        pre[2] = Si[S_ITER];
+    }
     // fixed summation order: few components use the whole block each, many
-    // components one wave each
-    // Each thread adds the entries t, t + stride, t + 2 stride, ... in that
-    // order; the loads of four consecutive entries are issued together.
+    // components one wave each.  Each thread adds the entries t, t + stride,
+    // t + 2 stride, ... in that order; four consecutive loads go out together.
     if (ncomp <= 2) {
         __shared__ double sh[4];
         double a[2] = {0.0, 0.0};
         for (int t = b + threadIdx.x; t < e; t += 4 * VB) {
-            int64_t id[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) id[u] = t + u * VB < e ? (int64_t)seg_idx[t + u * VB] * ncomp : -1;
             double p[4][2];
 #pragma unroll
             for (int u = 0; u < 4; u++)
 #pragma unroll
-                for (int c = 0; c < 2; c++) p[u][c] = (id[u] >= 0 && c < ncomp) ? partial[id[u] + c] : 0.0;
+                for (int c = 0; c < 2; c++)
+                    p[u][c] = (t + u * VB < e && c < ncomp) ? partial[(int64_t)(t + u * VB) * ncomp + c] : 0.0;
 #pragma unroll
             for (int u = 0; u < 4; u++)
-                if (id[u] >= 0) {
+                if (t + u * VB < e) {
                     a[0] += p[u][0];
                     a[1] += p[u][1];
                 }
@@ -360,8 +369,7 @@ __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partia
             for (int t = b + lane; t < e; t += 4 * 64) {
                 double p[4];
 #pragma unroll
-                for (int u = 0; u < 4; u++)
-                    p[u] = t + u * 64 < e ? partial[(int64_t)seg_idx[t + u * 64] * ncomp + c] : 0.0;
+                for (int u = 0; u < 4; u++) p[u] = t + u * 64 < e ? partial[(int64_t)(t + u * 64) * ncomp + c] : 0.0;
 #pragma unroll
                 for (int u = 0; u < 4; u++)
                     if (t + u * 64 < e) a += p[u];
@@ -371,10 +379,10 @@ __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partia
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && on) {
         if (out)
             for (int c = 0; c < ncomp; c++) out[(int64_t)inst * ncomp + c] = vals[c];
-        scalar_op(op, inst, vals, S, active, maxit, slot, aux);
+        scalar_op(op, inst, vals, pre, S, active, maxit, slot, aux);
     }
 }
 
@@ -459,7 +467,7 @@ void vpiezo32(const VecCtx &v, const OpDev *ops64, const double *P, float *P32)
 void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
              int maxit, double aux, double *out, hipStream_t s)
 {
-    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, r.seg_idx, op, slot, S,
+    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, op, slot, S,
                                                           active, maxit, aux, out);
     HTS_LAUNCH_CHECK();
 }
