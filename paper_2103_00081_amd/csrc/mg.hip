@@ -55,8 +55,9 @@ __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ le
     const T *Xi = X + L.off;
     const double *Sc = ep.S ? ep.S + (int64_t)ch.inst * NSLOT : nullptr;
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += 256) {
-        const int64_t n = e - L.off;
-        const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / pl);
+        // instance-local indices fit 32 bits (meshes have < 2^31 nodes)
+        const int n = (int)(e - L.off);
+        const int nxy = n / NX, i = n - nxy * NX, k = nxy / NY, j = nxy - k * NY;
         T acc = T(0);
 #pragma unroll
         for (int dz = -1; dz <= 1; dz++) {
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ le
                 for (int dx = -1; dx <= 1; dx++) {
                     if (i + dx < 0 || i + dx >= NX) continue;
                     const int c = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-                    acc += St[(int64_t)c * L.n + n] * Xi[n + dx + (int64_t)dy * NX + (int64_t)dz * pl];
+                    acc += St[(int64_t)c * L.n + n] * Xi[n + dx + dy * NX + dz * (int)pl];
                 }
             }
         }
@@ -101,7 +102,23 @@ __global__ __launch_bounds__(256) void k_cheb0(const Chunk *__restrict__ chunks,
     }
 }
 
-// coarse b_c = P^T r_f (fine constrained rows excluded when fops != null)
+// Fine neighbours of coarse node I along one axis: fine nodes fi - 1 .. fi + 1
+// (fi = fpos(I, Nf)), with weight 0 and a clamped index where a node is
+// outside the grid or not a child of I.
+__device__ __forceinline__ void children(int I, int Nf, int idx[3], double w[3])
+{
+    const int fi = fpos(I, Nf);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int i = fi + d - 1;
+        const bool in = i >= 0 && i < Nf;
+        w[d] = in ? pw1(i, I, Nf) : 0.0;
+        idx[d] = in ? i : fi;
+    }
+}
+
+// coarse b_c = P^T r_f (fine constrained rows excluded when fops != null),
+// the fine rows summed z-outer, then y, then x
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const LevelDev *__restrict__ fine, const LevelDev *__restrict__ coarse,
                                                   const OpDev *__restrict__ fops, const Chunk *__restrict__ cchunks,
@@ -112,39 +129,69 @@ __global__ __launch_bounds__(256) void k_restrict(const LevelDev *__restrict__ f
     if (active && !active[ch.inst]) return;
     const LevelDev &F = fine[ch.inst];
     const LevelDev &Cc = coarse[ch.inst];
-    const int64_t cpl = (int64_t)Cc.NX * Cc.NY, fpl = (int64_t)F.NX * F.NY;
+    const int fNX = F.NX, fNY = F.NY, fNZ = F.NZ, cNX = Cc.NX, cNY = Cc.NY;
+    const int fpl = fNX * fNY;
+    const T *rfi = rf + F.off;
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += 256) {
-        const int64_t n = e - Cc.off;
-        const int I = (int)(n % Cc.NX), J = (int)((n / Cc.NX) % Cc.NY), K = (int)(n / cpl);
-        const int fi = fpos(I, F.NX), fj = fpos(J, F.NY), fk = fpos(K, F.NZ);
-        // a coarse operator with eliminated (identity) rows where the fine
-        // node under the coarse node is constrained takes no residual there
-        if (mask_coarse && node_constrained(fops[ch.inst], fi + (int64_t)fj * F.NX + (int64_t)fk * fpl)) {
-            bc[e] = T(0);
-            continue;
-        }
-        double acc = 0.0;
-        for (int dz = -1; dz <= 1; dz++) {
-            const int k = fk + dz;
-            if (k < 0 || k >= F.NZ) continue;
-            const double wz = pw1(k, K, F.NZ);
-            if (wz == 0.0) continue;
-            for (int dy = -1; dy <= 1; dy++) {
-                const int j = fj + dy;
-                if (j < 0 || j >= F.NY) continue;
-                const double wy = pw1(j, J, F.NY);
-                if (wy == 0.0) continue;
-                for (int dx = -1; dx <= 1; dx++) {
-                    const int i = fi + dx;
-                    if (i < 0 || i >= F.NX) continue;
-                    const double wx = pw1(i, I, F.NX);
-                    if (wx == 0.0) continue;
-                    const int64_t fn = i + (int64_t)j * F.NX + (int64_t)k * fpl;
-                    if (fops && node_constrained(fops[ch.inst], fn)) continue;
-                    acc += wx * wy * wz * (double)rf[F.off + fn];
+        const int n = (int)(e - Cc.off);
+        const int nxy = n / cNX, I = n - nxy * cNX, K = nxy / cNY, J = nxy - K * cNY;
+        int xi[3], yi[3], zi[3];
+        double wx[3], wy[3], wz[3];
+        children(I, fNX, xi, wx);
+        children(J, fNY, yi, wy);
+        children(K, fNZ, zi, wz);
+        // constraint data of the 3 x 3 fine columns
+        bool cxy[3][3];
+        int lo[3][3], hi[3][3];
+        int NZo = 0, m = 0;
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                cxy[b][a] = false;
+                lo[b][a] = 1;
+                hi[b][a] = 0;
+            }
+        if (fops) {
+            const OpDev &o = fops[ch.inst];
+            NZo = o.NZ;
+            m = o.dmask;
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const ColInfo c = col_info(o, xi[a], yi[b]);
+                    cxy[b][a] = c.xyc != 0;
+                    lo[b][a] = c.dlo;
+                    hi[b][a] = c.dhi;
+                }
+            // a coarse operator with eliminated (identity) rows where the fine
+            // node under the coarse node is constrained takes no residual there
+            if (mask_coarse) {
+                const ColInfo cc = col_info(o, fpos(I, fNX), fpos(J, fNY));
+                if (constrained(cc, fpos(K, fNZ), NZo, m)) {
+                    bc[e] = T(0);
+                    continue;
                 }
             }
         }
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const double w = wx[a] * wy[b] * wz[c];
+                    if (w == 0.0) continue;
+                    if (fops) {
+                        const int k = zi[c];
+                        if (cxy[b][a] || ((m & 16) && k == 0) || ((m & 32) && k == NZo - 1) ||
+                            (k >= lo[b][a] && k <= hi[b][a]))
+                            continue;
+                    }
+                    acc += w * (double)rfi[xi[a] + yi[b] * fNX + zi[c] * fpl];
+                }
         bc[e] = T(acc);
     }
 }
@@ -159,20 +206,24 @@ __global__ __launch_bounds__(256) void k_prolong_add(const LevelDev *__restrict_
     if (active && !active[ch.inst]) return;
     const LevelDev &F = fine[ch.inst];
     const LevelDev &Cc = coarse[ch.inst];
-    const int64_t cpl = (int64_t)Cc.NX * Cc.NY, fpl = (int64_t)F.NX * F.NY;
+    const int fNX = F.NX, fNY = F.NY, fNZ = F.NZ, cNX = Cc.NX;
+    const int cpl = Cc.NX * Cc.NY;
+    const T *xci = xc + Cc.off;
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += 256) {
-        const int64_t n = e - F.off;
-        if (fops && node_constrained(fops[ch.inst], n)) continue;
-        const int i = (int)(n % F.NX), j = (int)((n / F.NX) % F.NY), k = (int)(n / fpl);
+        const int n = (int)(e - F.off);
+        const int nxy = n / fNX, i = n - nxy * fNX, k = nxy / fNY, j = nxy - k * fNY;
+        if (fops) {
+            const OpDev &o = fops[ch.inst];
+            if (constrained(col_info(o, i, j), k, o.NZ, o.dmask)) continue;
+        }
         int Px[2], Py[2], Pz[2];
         double Wx[2], Wy[2], Wz[2];
-        const int nxp = parents(i, F.NX, Px, Wx), nyp = parents(j, F.NY, Py, Wy), nzp = parents(k, F.NZ, Pz, Wz);
+        const int nxp = parents(i, fNX, Px, Wx), nyp = parents(j, fNY, Py, Wy), nzp = parents(k, fNZ, Pz, Wz);
         double acc = 0.0;
         for (int c = 0; c < nzp; c++)
             for (int b = 0; b < nyp; b++)
                 for (int a = 0; a < nxp; a++)
-                    acc += Wx[a] * Wy[b] * Wz[c] *
-                           (double)xc[Cc.off + Px[a] + (int64_t)Py[b] * Cc.NX + (int64_t)Pz[c] * cpl];
+                    acc += Wx[a] * Wy[b] * Wz[c] * (double)xci[Px[a] + Py[b] * cNX + Pz[c] * cpl];
         xf[e] = T((double)xf[e] + acc);
     }
 }

@@ -22,13 +22,14 @@ constexpr int TB = 16;          // cell columns per tile edge
 constexpr int OWN = TB - 1;     // owned node columns per tile edge
 constexpr int NCOL = (TB + 1) * (TB + 1);
 
+// The 1D factors are applied unscaled, [2 1; 1 2] for the mass matrix
+// (h/6 times it) and [1 -1; -1 1] for the stiffness matrix (1/h times it);
+// the 1/6 factors and the cell sizes go into the per-cell coefficients.
 template <typename T>
 __device__ __forceinline__ void m1p(T &a, T &b)
 {
-    // [a; b] <- [2 1; 1 2]/6 [a; b]
-    T s = a + b;
-    T na = (a + s) * T(1.0 / 6.0);
-    T nb = (b + s) * T(1.0 / 6.0);
+    const T na = T(2) * a + b;
+    const T nb = T(2) * b + a;
     a = na;
     b = nb;
 }
@@ -36,7 +37,6 @@ __device__ __forceinline__ void m1p(T &a, T &b)
 template <typename T>
 __device__ __forceinline__ void k1p(T &a, T &b)
 {
-    // [a; b] <- [1 -1; -1 1] [a; b]
     T d = a - b;
     a = d;
     b = -d;
@@ -45,13 +45,13 @@ __device__ __forceinline__ void k1p(T &a, T &b)
 template <typename T>
 __device__ __forceinline__ void g1p(T &a, T &b)
 {
-    // values at the two Gauss points from nodal values (and its transpose,
-    // which is the same symmetric 2x2 matrix)
-    const T cg = T(0.28867513459481288225);   // 1 / (2 sqrt 3)
-    T s = (a + b) * T(0.5);
-    T d = (a - b) * cg;
-    a = s + d;
-    b = s - d;
+    // values at the two Gauss points 1/2 -+ 1/(2 sqrt 3) from nodal values;
+    // the matrix is symmetric, so it is also its own transpose
+    const T c1 = T(0.78867513459481288225), c2 = T(0.21132486540518711775);
+    const T na = c1 * a + c2 * b;
+    const T nb = c2 * a + c1 * b;
+    a = na;
+    b = nb;
 }
 
 #define PZ(F, v) F(v[0], v[4]); F(v[1], v[5]); F(v[2], v[6]); F(v[3], v[7]);
@@ -59,9 +59,11 @@ __device__ __forceinline__ void g1p(T &a, T &b)
 #define PX(F, v) F(v[0], v[1]); F(v[2], v[3]); F(v[4], v[5]); F(v[6], v[7]);
 #define P2(F, v) F(v[0], v[1]); F(v[2], v[3]); F(v[0], v[2]); F(v[1], v[3]);
 
-// w = mV (M1 x M1 x M1) u + sk (cxx K1xM1xM1 + cyy M1xK1xM1 + czz M1xM1xK1) u
+// w = m (M x M x M) u + (sx K x M x M + sy M x K x M + sz M x M x K) u with
+// the unscaled 1D factors; for mass coefficient c and stiffness coefficient
+// s of a cell: m = c V / 216, sx = s (hy hz / hx) / 36, and so on.
 template <typename T>
-__device__ __forceinline__ void cell_mass_stiff(const T u[8], T mV, T sk, T cxx, T cyy, T czz, T w[8])
+__device__ __forceinline__ void cell_mass_stiff(const T u[8], T m, T sx, T sy, T sz, T w[8])
 {
     T a[8], b[8];
 #pragma unroll
@@ -74,24 +76,25 @@ __device__ __forceinline__ void cell_mass_stiff(const T u[8], T mV, T sk, T cxx,
     PY(m1p, c);
     PY(k1p, d);
     PY(m1p, e);
+    // f = (m c + 6 sy d + 6 sz e) / 6 is what the x mass factor takes
     T f[8], g[8];
-    const T skx = sk * cxx, sky = sk * cyy, skz = sk * czz;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
-        f[i] = mV * c[i] + sky * d[i] + skz * e[i];
+        f[i] = m * c[i] + sy * d[i] + sz * e[i];
         g[i] = c[i];
     }
     PX(m1p, f);
     PX(k1p, g);
 #pragma unroll
-    for (int i = 0; i < 8; i++) w[i] = f[i] + skx * g[i];
+    for (int i = 0; i < 8; i++) w[i] = f[i] + sx * g[i];
 }
 
-// w += cw8 sum_q N_a(q) (q_h . grad u)(q), q_h = -k (grad P + rho_g e_z),
-// 2 x 2 x 2 Gauss points, cw8 = dt c_w V / 8.
+// w += sum_q N_a(q) (q_h . grad u)(q) dt c_w V / 8 at the 2 x 2 x 2 Gauss
+// points, q_h = -k (grad P + rho_g e_z).  A derivative along x of a trilinear
+// function is bilinear in (y, z), so it is needed at 4 Gauss points only.
+// ax, ay, az: -k dt c_w V / (8 h_d^2), per cell; pz0 = rho_g hz.
 template <typename T>
-__device__ __forceinline__ void cell_convect(const T u[8], const T P[8], T kc, T ihx, T ihy, T ihz,
-                                            T rho_g, T cw8, T w[8])
+__device__ __forceinline__ void cell_convect(const T u[8], const T P[8], T ax_, T ay_, T az_, T pz0, T w[8])
 {
     T gx[4], gy[4], gz[4], px[4], py[4], pz[4];
 #pragma unroll
@@ -111,13 +114,12 @@ __device__ __forceinline__ void cell_convect(const T u[8], const T P[8], T kc, T
     P2(g1p, px);
     P2(g1p, py);
     P2(g1p, pz);
-    const T nk = -kc;
     T ax[4], ay[4], az[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        ax[j] = nk * (px[j] * ihx) * (gx[j] * ihx);
-        ay[j] = nk * (py[j] * ihy) * (gy[j] * ihy);
-        az[j] = nk * (pz[j] * ihz + rho_g) * (gz[j] * ihz);
+        ax[j] = (ax_ * px[j]) * gx[j];
+        ay[j] = (ay_ * py[j]) * gy[j];
+        az[j] = (az_ * (pz[j] + pz0)) * gz[j];
     }
     P2(g1p, ax);
     P2(g1p, ay);
@@ -128,7 +130,7 @@ __device__ __forceinline__ void cell_convect(const T u[8], const T P[8], T kc, T
         for (int y = 0; y < 2; y++)
 #pragma unroll
             for (int x = 0; x < 2; x++)
-                w[x + 2 * y + 4 * z] += cw8 * (ax[y + 2 * z] + ay[x + 2 * z] + az[x + 2 * y]);
+                w[x + 2 * y + 4 * z] += (ax[y + 2 * z] + ay[x + 2 * z]) + az[x + 2 * y];
 }
 
 template <typename T, int FIELD, int EPI, bool MASKED>
@@ -188,13 +190,16 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     int lr = -1;
     if (FIELD && o.lcol && own_ok) lr = gptr<int32_t>(o.lcol)[oc.base];
 
-    const T hx = T(o.hx), hy = T(o.hy), hz = T(o.hz);
-    const T V = hx * hy * hz;
-    const T cxx = hy * hz / hx, cyy = hx * hz / hy, czz = hx * hy / hz;
-    const T cs = T(o.cs), cm = T(o.cm);
-    const T ihx = T(1) / hx, ihy = T(1) / hy, ihz = T(1) / hz;
-    const T rho_g = T(o.rho_g);
-    const T cw8 = T(o.cadv) * V * T(0.125);
+    // per-cell coefficient factors of the unscaled 1D products (in double,
+    // then rounded once)
+    const double V = o.hx * o.hy * o.hz;
+    const T fm = T(V / 216.0);
+    const T fx = T(o.cs * (o.hy * o.hz / o.hx) / 36.0), fy = T(o.cs * (o.hx * o.hz / o.hy) / 36.0),
+            fz = T(o.cs * (o.hx * o.hy / o.hz) / 36.0);
+    const double cw8 = o.cadv * V * 0.125;
+    const T vx = T(-cw8 / (o.hx * o.hx)), vy = T(-cw8 / (o.hy * o.hy)), vz = T(-cw8 / (o.hz * o.hz));
+    const T pz0 = T(o.rho_g * o.hz);
+    const T cm = T(o.cm);
     T c1 = T(0), c2 = T(0);
     if (EPI == EPI_CHEB) {
         const double *Sc = ep.S + (int64_t)wi.inst * NSLOT;
@@ -316,16 +321,16 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                 u[a + 4] = xs[b1][ty + (a >> 1)][tx + (a & 1)];
             }
             if (FIELD == 0) {
-                cell_mass_stiff(u, cm * V, cs * ck, cxx, cyy, czz, w);
+                cell_mass_stiff(u, cm * fm, ck * fx, ck * fy, ck * fz, w);
             } else {
-                cell_mass_stiff(u, cc * V, cs * cl, cxx, cyy, czz, w);
+                cell_mass_stiff(u, cc * fm, cl * fx, cl * fy, cl * fz, w);
                 T pp[8];
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
                     pp[a] = ps[FIELD ? b0 : 0][ty + (a >> 1)][tx + (a & 1)];
                     pp[a + 4] = ps[FIELD ? b1 : 0][ty + (a >> 1)][tx + (a & 1)];
                 }
-                cell_convect(u, pp, ck, ihx, ihy, ihz, rho_g, cw8, w);
+                cell_convect(u, pp, ck * vx, ck * vy, ck * vz, pz0, w);
             }
 #pragma unroll
             for (int a = 0; a < 4; a++) { bot[a] = w[a]; tp[a] = w[a + 4]; }

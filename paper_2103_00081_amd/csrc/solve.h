@@ -104,7 +104,8 @@ struct Batch {
     DBuf<double> S;
     DBuf<int32_t> active;
     double *hS = nullptr;
-    int32_t *hact = nullptr;
+    int32_t *hact = nullptr;      // flags as last exported (coherent pinned)
+    double *hexpS = nullptr;      // slots as last exported (coherent pinned)
     DBuf<double> partial, redout, redout2, redout3;
 
     DBuf<double> Pn, Tn, P1, T1, g, b, x, r, z, pp, q, rold, y, ld0, ld1, inner_b, inner_x;
@@ -172,6 +173,7 @@ struct Batch {
         return app;
     }
     void upload_S();
+    void export_state();
     void download_S();
     void set_active(const std::vector<int32_t> &a);
     std::vector<int32_t> get_active();

@@ -59,6 +59,7 @@ Batch::~Batch()
         if (e) (void)hipEventDestroy(e);
     if (hS) (void)hipHostFree(hS);
     if (hact) (void)hipHostFree(hact);
+    if (hexpS) (void)hipHostFree(hexpS);
 }
 
 void Batch::drop_graphs()
@@ -269,7 +270,8 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->S.zero(s);
     B->active.alloc(al, n);
     HTS_HIP(hipHostMalloc((void **)&B->hS, sizeof(double) * n * NSLOT, hipHostMallocDefault));
-    HTS_HIP(hipHostMalloc((void **)&B->hact, sizeof(int32_t) * n, hipHostMallocDefault));
+    HTS_HIP(hipHostMalloc((void **)&B->hact, sizeof(int32_t) * n, hipHostMallocCoherent));
+    HTS_HIP(hipHostMalloc((void **)&B->hexpS, sizeof(double) * n * NSLOT, hipHostMallocCoherent));
     std::memset(B->hS, 0, sizeof(double) * n * NSLOT);
     B->redout.alloc(al, (size_t)n * 64);
     B->redout2.alloc(al, (size_t)n * 64);
@@ -379,20 +381,23 @@ void Batch::make_tables(Tables &t, int field, double dt, bool steady, bool mass_
 }
 
 void Batch::upload_S() { HTS_HIP(hipMemcpyAsync(S.p, hS, sizeof(double) * n * NSLOT, hipMemcpyHostToDevice, s)); }
+// Host reads of the scalar slots and flags: one small kernel writes both into
+// coherent pinned memory (no copy engine round trip), then the stream is
+// synchronised; the slots are copied into hS, which the host may edit.
+void Batch::export_state()
+{
+    vexport(S.p, n * NSLOT, active.p, n, hexpS, hact, s);
+    sync(s);
+}
 void Batch::download_S()
 {
-    HTS_HIP(hipMemcpyAsync(hS, S.p, sizeof(double) * n * NSLOT, hipMemcpyDeviceToHost, s));
-    sync(s);
+    export_state();
+    std::memcpy(hS, hexpS, sizeof(double) * n * NSLOT);
 }
-void Batch::set_active(const std::vector<int32_t> &a)
-{
-    for (int i = 0; i < n; i++) hact[i] = a[i];
-    HTS_HIP(hipMemcpyAsync(active.p, hact, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-}
+void Batch::set_active(const std::vector<int32_t> &a) { vset_flags(a.data(), n, active.p, s); }
 std::vector<int32_t> Batch::get_active()
 {
-    HTS_HIP(hipMemcpyAsync(hact, active.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    sync(s);
+    export_state();
     return std::vector<int32_t>(hact, hact + n);
 }
 bool Batch::any_active()
@@ -1446,20 +1451,28 @@ void Batch::heat_rhs(Hier &H)
     vmask<double>(v, H.ops.d64.p, b.p, 0.0);
 }
 
+// State in and out of the batch vectors, one launch per field for up to 128
+// instances (a copy per instance would cost one launch each).
 void Batch::gather_state()
 {
+    std::vector<double *> P(n), T(n);
     for (int i = 0; i < n; i++) {
-        HTS_HIP(hipMemcpyAsync(Pn.p + off[i], m[i]->P.p, m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HTS_HIP(hipMemcpyAsync(Tn.p + off[i], m[i]->T.p, m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
+        P[i] = m[i]->P.p;
+        T[i] = m[i]->T.p;
     }
+    vgather_scatter(ch.p, hch, P, off, Pn.p, true, s);
+    vgather_scatter(ch.p, hch, T, off, Tn.p, true, s);
 }
 
 void Batch::scatter_state()
 {
+    std::vector<double *> P(n), T(n);
     for (int i = 0; i < n; i++) {
-        HTS_HIP(hipMemcpyAsync(m[i]->P.p, Pn.p + off[i], m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HTS_HIP(hipMemcpyAsync(m[i]->T.p, Tn.p + off[i], m[i]->nnode * sizeof(double), hipMemcpyDeviceToDevice, s));
+        P[i] = m[i]->P.p;
+        T[i] = m[i]->T.p;
     }
+    vgather_scatter(ch.p, hch, P, off, Pn.p, false, s);
+    vgather_scatter(ch.p, hch, T, off, Tn.p, false, s);
     sync(s);
 }
 

@@ -2,6 +2,8 @@
 #pragma once
 #include "common.h"
 
+#include <vector>
+
 namespace hts {
 
 struct VecCtx {
@@ -55,6 +57,26 @@ template <typename T> void vmask(const VecCtx &v, const OpDev *ops, T *y, T val)
 
 // P32 = (P - P[node 0 of the instance]) + rho_w g z (FP32 heat operator input)
 void vpiezo32(const VecCtx &v, const OpDev *ops64, const double *P, float *P32);
+
+struct FlagBlock {
+    static constexpr int N = 256;
+    int32_t v[N];
+};
+struct PtrBlock {
+    static constexpr int N = 128;
+    double *p[N];
+    int64_t off[N];
+};
+// Copy between a batch vector and per-instance device arrays ptrs[i] (which
+// hold the entries off[i] .. of the batch vector); hchunks is the host copy
+// of the chunk list (ordered by instance).
+void vgather_scatter(const Chunk *chunks, const std::vector<Chunk> &hchunks, const std::vector<double *> &ptrs,
+                     const std::vector<int64_t> &off, double *batch, bool to_batch, hipStream_t s);
+// dst[0 .. n) = flags (host array), in launches of up to 256 values
+void vset_flags(const int32_t *flags, int n, int32_t *dst, hipStream_t s);
+// hs[0 .. nS) = S, ha[0 .. n) = act; hs and ha are host memory the device can
+// write (pinned, coherent); valid on the host once the stream has synchronised
+void vexport(const double *S, int nS, const int32_t *act, int n, double *hs, int32_t *ha, hipStream_t s);
 
 void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
              int maxit, double aux, double *out, hipStream_t s);

@@ -11,6 +11,8 @@
 #include "dev_util.h"
 #include "vec.h"
 
+#include <algorithm>
+
 namespace hts {
 
 namespace {
@@ -386,6 +388,37 @@ __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partia
     }
 }
 
+// Copy between the batch vector (chunk ranges) and the per-instance arrays of
+// instances g0 .. g0 + PtrBlock::N - 1: to_batch ? batch = inst : inst = batch.
+__global__ __launch_bounds__(VB) void k_gather_scatter(const Chunk *__restrict__ chunks, PtrBlock pb, int g0,
+                                                       double *__restrict__ batch, int to_batch)
+{
+    const Chunk ch = chunks[blockIdx.x];
+    const int g = ch.inst - g0;
+    double *p = pb.p[g];
+    const int64_t off = pb.off[g];
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        if (to_batch) batch[e] = p[e - off];
+        else p[e - off] = batch[e];
+    }
+}
+
+// Per-instance flags set from the host: the values travel as a kernel
+// argument, so no host buffer has to stay untouched until a copy runs.
+__global__ __launch_bounds__(VB) void k_set_flags(FlagBlock f, int beg, int cnt, int32_t *__restrict__ dst)
+{
+    if ((int)threadIdx.x < cnt) dst[beg + threadIdx.x] = f.v[threadIdx.x];
+}
+
+// Scalar slots and flags written straight into host-visible memory.
+__global__ __launch_bounds__(VB) void k_export(const double *__restrict__ S, int nS,
+                                               const int32_t *__restrict__ act, int n, double *hs,
+                                               int32_t *ha)
+{
+    for (int i = threadIdx.x; i < nS; i += VB) hs[i] = S[i];
+    for (int i = threadIdx.x; i < n; i += VB) ha[i] = act[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host API
@@ -469,6 +502,45 @@ void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot
 {
     k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, op, slot, S,
                                                           active, maxit, aux, out);
+    HTS_LAUNCH_CHECK();
+}
+
+void vgather_scatter(const Chunk *chunks, const std::vector<Chunk> &hchunks, const std::vector<double *> &ptrs,
+                     const std::vector<int64_t> &off, double *batch, bool to_batch, hipStream_t s)
+{
+    const int n = (int)ptrs.size();
+    size_t c0 = 0;
+    for (int g0 = 0; g0 < n; g0 += PtrBlock::N) {
+        const int g1 = std::min(n, g0 + PtrBlock::N);
+        PtrBlock pb{};
+        for (int i = g0; i < g1; i++) {
+            pb.p[i - g0] = ptrs[i];
+            pb.off[i - g0] = off[i];
+        }
+        size_t c1 = c0;
+        while (c1 < hchunks.size() && hchunks[c1].inst < g1) c1++;
+        if (c1 > c0)
+            k_gather_scatter<<<dim3((unsigned)(c1 - c0)), dim3(VB), 0, s>>>(chunks + c0, pb, g0, batch,
+                                                                          to_batch ? 1 : 0);
+        HTS_LAUNCH_CHECK();
+        c0 = c1;
+    }
+}
+
+void vset_flags(const int32_t *flags, int n, int32_t *dst, hipStream_t s)
+{
+    for (int beg = 0; beg < n; beg += FlagBlock::N) {
+        FlagBlock f{};
+        const int cnt = std::min(FlagBlock::N, n - beg);
+        for (int i = 0; i < cnt; i++) f.v[i] = flags[beg + i];
+        k_set_flags<<<dim3(1), dim3(VB), 0, s>>>(f, beg, cnt, dst);
+        HTS_LAUNCH_CHECK();
+    }
+}
+
+void vexport(const double *S, int nS, const int32_t *act, int n, double *hs, int32_t *ha, hipStream_t s)
+{
+    k_export<<<dim3(1), dim3(VB), 0, s>>>(S, nS, act, n, hs, ha);
     HTS_LAUNCH_CHECK();
 }
 
