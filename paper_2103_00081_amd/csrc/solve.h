@@ -106,6 +106,11 @@ struct Batch {
     double *hS = nullptr;
     int32_t *hact = nullptr;      // flags as last exported (coherent pinned)
     double *hexpS = nullptr;      // slots as last exported (coherent pinned)
+    uint32_t *hseq = nullptr;     // sequence number of the last export (coherent pinned)
+    uint32_t exp_seq = 0;
+    // set by cg / fgmres on return: no work was queued after their last
+    // export, so hexpS still holds the current slots
+    bool exported_last = false;
     DBuf<double> partial, redout, redout2, redout3;
 
     DBuf<double> Pn, Tn, P1, T1, g, b, x, r, z, pp, q, rold, y, ld0, ld1, inner_b, inner_x;
@@ -151,7 +156,6 @@ struct Batch {
     };
     std::map<std::string, Graph> graphs;
     hipStream_t cap = nullptr;
-    hipEvent_t gev[2] = {nullptr, nullptr};
     bool use_graph = false;
     std::string graph_tag;   // identifies the preconditioner a captured chunk calls
     std::map<std::string, int> last_iters;   // iterations of the previous solve per captured system
@@ -175,6 +179,7 @@ struct Batch {
     void upload_S();
     void export_state();
     void download_S();
+    void slots_from_export();      // hS = hexpS (the last export is current)
     void set_active(const std::vector<int32_t> &a);
     std::vector<int32_t> get_active();
     bool any_active();

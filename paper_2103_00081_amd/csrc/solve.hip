@@ -12,6 +12,8 @@
 #include "krylov.h"
 #include "solve.h"
 
+#include <atomic>
+
 namespace hts {
 
 hts_status guard_call(const std::function<void()> &f);
@@ -55,11 +57,10 @@ Batch::~Batch()
 {
     drop_graphs();
     if (cap) (void)hipStreamDestroy(cap);
-    for (hipEvent_t e : gev)
-        if (e) (void)hipEventDestroy(e);
     if (hS) (void)hipHostFree(hS);
     if (hact) (void)hipHostFree(hact);
     if (hexpS) (void)hipHostFree(hexpS);
+    if (hseq) (void)hipHostFree(hseq);
 }
 
 void Batch::drop_graphs()
@@ -73,14 +74,11 @@ void Batch::drop_graphs()
 
 // Run body's launches as one graph: captured on first use on a private
 // stream (the caller's stream may be the legacy default stream, which
-// cannot be captured), then replayed; ordered after and before the work of
-// the batch stream by events.
+// cannot be captured), then replayed on the batch stream.
 void Batch::replay(const std::string &key, const std::function<void()> &body)
 {
     if (!cap) {
         HTS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        HTS_HIP(hipEventCreateWithFlags(&gev[0], hipEventDisableTiming));
-        HTS_HIP(hipEventCreateWithFlags(&gev[1], hipEventDisableTiming));
     }
     auto it = graphs.find(key);
     if (it == graphs.end()) {
@@ -102,11 +100,9 @@ void Batch::replay(const std::string &key, const std::function<void()> &body)
         HTS_HIP(hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0));
         it = graphs.emplace(key, G).first;
     }
-    HTS_HIP(hipEventRecord(gev[0], s));
-    HTS_HIP(hipStreamWaitEvent(cap, gev[0], 0));
-    HTS_HIP(hipGraphLaunch(it->second.e, cap));
-    HTS_HIP(hipEventRecord(gev[1], cap));
-    HTS_HIP(hipStreamWaitEvent(s, gev[1], 0));
+    // replayed on the batch stream itself: ordered with the surrounding work
+    // without a cross-stream event pair
+    HTS_HIP(hipGraphLaunch(it->second.e, s));
 }
 
 // ----------------------------------------------------------- tuning cache
@@ -272,6 +268,8 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     HTS_HIP(hipHostMalloc((void **)&B->hS, sizeof(double) * n * NSLOT, hipHostMallocDefault));
     HTS_HIP(hipHostMalloc((void **)&B->hact, sizeof(int32_t) * n, hipHostMallocCoherent));
     HTS_HIP(hipHostMalloc((void **)&B->hexpS, sizeof(double) * n * NSLOT, hipHostMallocCoherent));
+    HTS_HIP(hipHostMalloc((void **)&B->hseq, sizeof(uint32_t) * 64, hipHostMallocCoherent));
+    *B->hseq = 0;
     std::memset(B->hS, 0, sizeof(double) * n * NSLOT);
     B->redout.alloc(al, (size_t)n * 64);
     B->redout2.alloc(al, (size_t)n * 64);
@@ -386,14 +384,31 @@ void Batch::upload_S() { HTS_HIP(hipMemcpyAsync(S.p, hS, sizeof(double) * n * NS
 // synchronised; the slots are copied into hS, which the host may edit.
 void Batch::export_state()
 {
-    vexport(S.p, n * NSLOT, active.p, n, hexpS, hact, s);
-    sync(s);
+    const uint32_t want = ++exp_seq;
+    vexport(S.p, n * NSLOT, active.p, n, hexpS, hact, hseq, want, s);
+    // Spin on the sequence number the kernel writes last (a stream wait
+    // costs a much longer wake-up); every so often ask the runtime whether
+    // the stream has finished or failed, so a launch error cannot hang here.
+    const volatile uint32_t *seq = hseq;
+    for (uint64_t k = 1;; k++) {
+        if (*seq == want) break;
+        if ((k & 255) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (*seq == want) break;
+                throw Error(HTS_ERR_HIP, "state export finished without its sequence number");
+            }
+            if (e != hipErrorNotReady) HTS_HIP(e);
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
 }
 void Batch::download_S()
 {
     export_state();
-    std::memcpy(hS, hexpS, sizeof(double) * n * NSLOT);
+    slots_from_export();
 }
+void Batch::slots_from_export() { std::memcpy(hS, hexpS, sizeof(double) * n * NSLOT); }
 void Batch::set_active(const std::vector<int32_t> &a) { vset_flags(a.data(), n, active.p, s); }
 std::vector<int32_t> Batch::get_active()
 {
@@ -1057,16 +1072,23 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
     EpiArgs<T> ep{};
     ep.b = b;
     ep.partial = partial.p;
+    exported_last = false;
     apply_op<T>(A, EPI_RESID_NORM, true, x, r, ep);
     vreduce(rwk[A.field], partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
-    if (!any_active()) return 0;
     const bool hook = std::is_same<T, double>::value && cg_hook;
+    const bool graphed = use_graph && !hook && !g_timing.on;
+    // (replayed chunks skip instances that converged at the start, so only
+    // the eager loop checks here)
+    if (!graphed && !any_active()) {
+        exported_last = true;
+        return 0;
+    }
     if (hook) cg_hook(reinterpret_cast<const double *>(x), 0);
     M(r, z);
     vdot<T>(v, r, z, nullptr, partial.p);
     vreduce(rch, partial.p, 2, RED_STORE, S_RZ, S.p, active.p, 0, 0.0, nullptr, s);
     vcopy<T>(v, z, pv);
-    if (use_graph && !hook && !g_timing.on) {
+    if (graphed) {
         // Chunks replayed as graphs with a host check between them: the first
         // chunk as long as the previous solve of this system took, then
         // chunks of two (or check_every) iterations.
@@ -1099,7 +1121,9 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
             if (!any_active()) break;
             K = check_every > 1 ? check_every : 2;
         }
-        download_S();
+        // every chunk ends with an export: the slots are those of the last one
+        slots_from_export();
+        exported_last = true;
         int used = 0;
         for (int i = 0; i < n; i++) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
         last_iters[base] = std::max(1, used);
@@ -1120,7 +1144,10 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
             std::fprintf(stderr, "[hts] cg it %d rr %.6e rr0 %.6e\n", it, hS[S_RR], hS[S_RR0]);
         }
         if (it % std::max(1, check_every) == 0 || it == maxit)
-            if (!any_active()) break;
+            if (!any_active()) {
+                exported_last = true;
+                break;
+            }
         M(r, z);
         vdot<T>(v, z, r, ro, partial.p);
         vreduce(rch, partial.p, 2, RED_CG_BETA, 0, S.p, active.p, 0, 0.0, nullptr, s);
@@ -1138,7 +1165,6 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
     T *V = PK(T, V64, V32), *Z = PK(T, Z64, Z32);
     const int64_t ld = ntot;
     VecCtx v = vctx();
-    std::vector<int32_t> participating = get_active();
     for (int cycle = 0; cycle < 1000; cycle++) {
         EpiArgs<T> ep{};
         ep.b = b;
@@ -1187,7 +1213,7 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
                 K = check_every > 1 ? check_every : 2;
             }
             if (cycle == 0) {
-                download_S();
+                slots_from_export();   // the chunk loop ended with an export
                 int used = 0;
                 for (int i = 0; i < n; i++)
                     if (cyc[i]) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
@@ -1200,11 +1226,13 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
                     if (!any_active()) break;
             }
         }
-        // x += Z y for every instance that took part in this cycle
+        // x += Z y for every instance that took part in this cycle (neither
+        // kernel writes the slots, so the export that ended the Arnoldi steps
+        // still holds them)
         set_active(cyc);
         gm_solve(n, active.p, mres, gH.p, gg.p, gkdim.p, gy.p, s);
         vbasis_update<T, T>(v, Z, ld, gkdim.p, gy.p, mres, 1.0, -1, x);
-        download_S();
+        slots_from_export();
         std::vector<int32_t> again(n, 0);
         bool more = false;
         for (int i = 0; i < n; i++) {
@@ -1216,7 +1244,7 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
         set_active(again);
         if (!more) break;
     }
-    (void)participating;
+    exported_last = true;
 }
 
 void Batch::ensure_gmres(int mres)
@@ -1272,6 +1300,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
     set_otol(n, active.p, S.p, redout.p, 2, rtol * rtol, s);
     std::vector<int32_t> outer = participants;
     int total_inner = 0;
+    bool fresh = false;   // the last export holds the final slots
     for (int oit = 0; oit < 40; oit++) {
         set_active(outer);
         EpiArgs<double> ep{};
@@ -1280,10 +1309,13 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
         vreduce(rwk[A.field], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
         outer_check(n, active.p, S.p, redout.p, s);
+        HTS_HIP(hipEventRecord(e1, s));
         outer = get_active();
+        fresh = true;
         bool any = false;
         for (int a : outer) any |= a != 0;
         if (!any) break;
+        fresh = false;
         for (int i = 0; i < n; i++)
             if (outer[i]) st.outer[i]++;
         // inner system: A d = r / ||r||
@@ -1364,8 +1396,12 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
                 fgmres<double>(A, M, inner_b.p, inner_x.p, maxit, std::max(2, std::min(o.gmres_restart, 60)),
                                o.check_every);
         }
-        if (inner_hook && field == 0 && !fp32) inner_hook(A, inner_x.p);
-        download_S();
+        if (inner_hook && field == 0 && !fp32) {
+            inner_hook(A, inner_x.p);
+            exported_last = false;
+        }
+        if (exported_last) slots_from_export();
+        else download_S();
         for (int i = 0; i < n; i++)
             if (outer[i]) {
                 st.iters[i] += (int)hS[(size_t)i * NSLOT + S_ITER];
@@ -1384,12 +1420,19 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
             apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
             vreduce(rwk[A.field], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
             outer_check(n, active.p, S.p, redout.p, s);
+            HTS_HIP(hipEventRecord(e1, s));
             outer = get_active();
+            fresh = true;
             break;
         }
     }
-    HTS_HIP(hipEventRecord(e1, s));
-    download_S();
+    if (fresh) {
+        slots_from_export();
+    } else {
+        HTS_HIP(hipEventRecord(e1, s));
+        download_S();
+    }
+    HTS_HIP(hipEventSynchronize(e1));
     float ms = 0.0f;
     HTS_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -1411,12 +1454,9 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
 // ------------------------------------------------------------- one step
 void Batch::set_time(const std::vector<double> &tnew, const std::vector<double> &fscale)
 {
-    download_S();
-    for (int i = 0; i < n; i++) {
-        hS[(size_t)i * NSLOT + S_TNEW] = tnew[i];
-        hS[(size_t)i * NSLOT + S_FSCALE] = fscale[i];
-    }
-    upload_S();
+    const int slots[2] = {S_TNEW, S_FSCALE};
+    const double *vals[2] = {tnew.data(), fscale.data()};
+    vset_slots(slots, 2, vals, n, S.p, s);
 }
 
 void Batch::pressure_rhs(Hier &H, bool steady)

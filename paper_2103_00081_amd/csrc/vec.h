@@ -74,9 +74,18 @@ void vgather_scatter(const Chunk *chunks, const std::vector<Chunk> &hchunks, con
                      const std::vector<int64_t> &off, double *batch, bool to_batch, hipStream_t s);
 // dst[0 .. n) = flags (host array), in launches of up to 256 values
 void vset_flags(const int32_t *flags, int n, int32_t *dst, hipStream_t s);
-// hs[0 .. nS) = S, ha[0 .. n) = act; hs and ha are host memory the device can
-// write (pinned, coherent); valid on the host once the stream has synchronised
-void vexport(const double *S, int nS, const int32_t *act, int n, double *hs, int32_t *ha, hipStream_t s);
+// hs[0 .. nS) = S, ha[0 .. n) = act, then *seq_ptr = seq; hs, ha and seq_ptr
+// are host memory the device can write (pinned, coherent).  Once the host
+// reads seq from *seq_ptr, hs and ha hold the values.
+void vexport(const double *S, int nS, const int32_t *act, int n, double *hs, int32_t *ha, uint32_t *seq_ptr,
+             uint32_t seq, hipStream_t s);
+struct SlotBlock {
+    static constexpr int N = 64, NS = 4;
+    int32_t slot[NS];
+    double v[NS][N];
+};
+// S[i][slots[j]] = vals[j][i] (host arrays) for every instance i < n
+void vset_slots(const int *slots, int nslots, const double *const *vals, int n, double *S, hipStream_t s);
 
 void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
              int maxit, double aux, double *out, hipStream_t s);

@@ -410,13 +410,29 @@ __global__ __launch_bounds__(VB) void k_set_flags(FlagBlock f, int beg, int cnt,
     if ((int)threadIdx.x < cnt) dst[beg + threadIdx.x] = f.v[threadIdx.x];
 }
 
-// Scalar slots and flags written straight into host-visible memory.
+// Scalar slots and flags written straight into host-visible memory, then a
+// sequence number once all of them are visible system-wide (the host waits
+// for that number instead of a stream synchronisation).
 __global__ __launch_bounds__(VB) void k_export(const double *__restrict__ S, int nS,
                                                const int32_t *__restrict__ act, int n, double *hs,
-                                               int32_t *ha)
+                                               int32_t *ha, uint32_t *seq_ptr, uint32_t seq)
 {
     for (int i = threadIdx.x; i < nS; i += VB) hs[i] = S[i];
     for (int i = threadIdx.x; i < n; i += VB) ha[i] = act[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        __hip_atomic_store(seq_ptr, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// S[i * NSLOT + slot[j]] = v[j][i] for the instances beg .. beg + cnt - 1
+__global__ __launch_bounds__(VB) void k_set_slots(SlotBlock b, int beg, int cnt, int nslots, double *__restrict__ S)
+{
+    const int i = threadIdx.x;
+    if (i >= cnt) return;
+    for (int j = 0; j < nslots; j++) S[(int64_t)(beg + i) * NSLOT + b.slot[j]] = b.v[j][i];
 }
 
 }  // namespace
@@ -538,10 +554,26 @@ void vset_flags(const int32_t *flags, int n, int32_t *dst, hipStream_t s)
     }
 }
 
-void vexport(const double *S, int nS, const int32_t *act, int n, double *hs, int32_t *ha, hipStream_t s)
+void vexport(const double *S, int nS, const int32_t *act, int n, double *hs, int32_t *ha, uint32_t *seq_ptr,
+             uint32_t seq, hipStream_t s)
 {
-    k_export<<<dim3(1), dim3(VB), 0, s>>>(S, nS, act, n, hs, ha);
+    k_export<<<dim3(1), dim3(VB), 0, s>>>(S, nS, act, n, hs, ha, seq_ptr, seq);
     HTS_LAUNCH_CHECK();
+}
+
+void vset_slots(const int *slots, int nslots, const double *const *vals, int n, double *S, hipStream_t s)
+{
+    if (nslots > SlotBlock::NS) throw Error(-1, "too many slots");   // -1: invalid argument
+    for (int beg = 0; beg < n; beg += SlotBlock::N) {
+        SlotBlock b{};
+        const int cnt = std::min(SlotBlock::N, n - beg);
+        for (int j = 0; j < nslots; j++) {
+            b.slot[j] = slots[j];
+            for (int i = 0; i < cnt; i++) b.v[j][i] = vals[j][beg + i];
+        }
+        k_set_slots<<<dim3(1), dim3(VB), 0, s>>>(b, beg, cnt, nslots, S);
+        HTS_LAUNCH_CHECK();
+    }
 }
 
 #define INST(T)                                                                                          \
