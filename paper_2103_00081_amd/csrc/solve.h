@@ -159,6 +159,7 @@ struct Batch {
     bool use_graph = false;
     std::string graph_tag;   // identifies the preconditioner a captured chunk calls
     std::map<std::string, int> last_iters;   // iterations of the previous solve per captured system
+    int hist_tag = 0;                          // outer refinement step of the current inner solve
     void drop_graphs();
     void replay(const std::string &key, const std::function<void()> &body);
 

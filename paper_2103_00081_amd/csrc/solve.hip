@@ -1097,7 +1097,10 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
                       (const void *)b, (const void *)x, maxit, flexible ? 1 : 0);
         // the preconditioner closure is identified by its target, not its address
         const std::string base = std::string(key) + "|" + graph_tag;
-        auto hist = last_iters.find(base);
+        // iteration history per outer refinement step: later refinement
+        // steps usually need far fewer iterations than the first
+        const std::string hkey = base + "|o" + std::to_string(hist_tag);
+        auto hist = last_iters.find(hkey);
         int K = hist != last_iters.end() ? hist->second : 4;
         int done = 0;
         while (done < maxit) {
@@ -1126,7 +1129,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
         exported_last = true;
         int used = 0;
         for (int i = 0; i < n; i++) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
-        last_iters[base] = std::max(1, used);
+        last_iters[hkey] = std::max(1, used);
         return done;
     }
     int it = 0;
@@ -1200,7 +1203,8 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
             std::snprintf(key, sizeof key, "gm%d|%d|%p|%p|%p|%d|%d", (int)sizeof(T), A.field, (const void *)&A,
                           (const void *)b, (const void *)x, maxit, mres);
             const std::string base = std::string(key) + "|" + graph_tag;
-            auto hist = last_iters.find(base);
+            const std::string hkey = base + "|o" + std::to_string(hist_tag);
+            auto hist = last_iters.find(hkey);
             int K = hist != last_iters.end() ? hist->second : 8;
             int j0 = 0;
             for (; j0 < mres;) {
@@ -1217,7 +1221,7 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
                 int used = 0;
                 for (int i = 0; i < n; i++)
                     if (cyc[i]) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
-                last_iters[base] = std::max(1, std::min(used, mres));
+                last_iters[hkey] = std::max(1, std::min(used, mres));
             }
         } else {
             for (int j = 0; j < mres; j++) {
@@ -1319,6 +1323,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         for (int i = 0; i < n; i++)
             if (outer[i]) st.outer[i]++;
         // inner system: A d = r / ||r||
+        hist_tag = oit;
         const double fl = fp32 ? std::pow(std::max(o.inner_rtol, 1e-6), 2) : 0.0;
         set_inner_tol(n, active.p, S.p, fl, 0.25, s);
         VecCtx v = vctx();
