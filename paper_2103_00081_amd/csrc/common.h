@@ -100,7 +100,10 @@ enum Epi {
     EPI_RESID = 1,             // y = b - A x
     EPI_RESID_NORM = 2,        // y = b - A x, partial += y^2
     EPI_DOT = 3,               // y = A x, partial += x . y
-    EPI_CHEB = 4               // r = b - A x; d = c1 d + c2 D^-1 r; y = x + d
+    EPI_CHEB = 4,              // r = b - A x; d = c1 d + c2 D^-1 r; y = x + d
+    EPI_CHEB0 = 5              // the first two Chebyshev steps from x = 0: the
+                               // operand is x0 = c0 D^-1 b (x ignored), d = x0,
+                               // then as EPI_CHEB (Q1 and stencil levels)
 };
 
 template <typename T>
@@ -110,6 +113,7 @@ struct EpiArgs {
     const T *invd;
     const double *S;           // per-instance scalar slots
     int32_t s1, s2;            // slots of the Chebyshev coefficients
+    int32_t s0, pad;           // slot of c0 (EPI_CHEB0)
     double *partial;           // per work item partial sums
     const int32_t *active;     // per-instance flags (null = all active)
 };

@@ -33,9 +33,14 @@ __global__ void k_gm_begin(int ninst, int32_t *active, double *S, double *g, int
     Si[S_STATUS] = 1;
 }
 
+// Column j of the Hessenberg matrix from classical Gram-Schmidt applied twice:
+// h = h1 + h2.  The new basis vector is w' - V h2 with w' the vector after
+// the first projection; the basis is orthonormal and w' - V h2 is orthogonal
+// to it, so its squared norm is |w'|^2 - |h2|^2, where h2 is small (the
+// second pass only removes rounding), so the difference does not cancel.
 __global__ void k_gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit,
-                             const double *h1, const double *h2, const double *ww, double *H, double *cs,
-                             double *sn, double *g, int32_t *kdim)
+                             const double *h1, const double *h2, double *H, double *cs, double *sn, double *g,
+                             int32_t *kdim)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst || !active[i]) return;
@@ -45,8 +50,12 @@ __global__ void k_gm_arnoldi(int ninst, int32_t *active, double *S, int j, int m
     double *gi = g + (int64_t)i * (mres + 1);
     const double *a1 = h1 + (int64_t)i * (j + 1);
     const double *a2 = h2 + (int64_t)i * (j + 2);
-    for (int r = 0; r <= j; r++) Hi[r * mres + j] = a1[r] + a2[r];
-    const double hn = sqrt(fmax(ww[i], 0.0));
+    double h22 = 0.0;
+    for (int r = 0; r <= j; r++) {
+        Hi[r * mres + j] = a1[r] + a2[r];
+        h22 += a2[r] * a2[r];
+    }
+    const double hn = sqrt(fmax(a2[j + 1] - h22, 0.0));
     Hi[(j + 1) * mres + j] = hn;
     for (int r = 0; r < j; r++) {
         const double a = Hi[r * mres + j], b = Hi[(r + 1) * mres + j];
@@ -169,10 +178,9 @@ void gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_
     HTS_LAUNCH_CHECK();
 }
 void gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit, const double *h1,
-                const double *h2, const double *ww, double *H, double *cs, double *sn, double *g, int32_t *kdim,
-                hipStream_t s)
+                const double *h2, double *H, double *cs, double *sn, double *g, int32_t *kdim, hipStream_t s)
 {
-    k_gm_arnoldi<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, j, mres, maxit, h1, h2, ww, H, cs, sn, g, kdim);
+    k_gm_arnoldi<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, j, mres, maxit, h1, h2, H, cs, sn, g, kdim);
     HTS_LAUNCH_CHECK();
 }
 void gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g, const int32_t *kdim,

@@ -54,6 +54,9 @@ __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ le
     const int64_t pl = (int64_t)NX * NY;
     const T *Xi = X + L.off;
     const double *Sc = ep.S ? ep.S + (int64_t)ch.inst * NSLOT : nullptr;
+    const T c0 = EPI == EPI_CHEB0 ? T(Sc[ep.s0]) : T(0);
+    const T *Ii = EPI == EPI_CHEB0 ? ep.invd + L.off : nullptr;
+    const T *Bi = EPI == EPI_CHEB0 ? ep.b + L.off : nullptr;
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += 256) {
         // instance-local indices fit 32 bits (meshes have < 2^31 nodes)
         const int n = (int)(e - L.off);
@@ -69,7 +72,10 @@ __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ le
                 for (int dx = -1; dx <= 1; dx++) {
                     if (i + dx < 0 || i + dx >= NX) continue;
                     const int c = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-                    acc += St[(int64_t)c * L.n + n] * Xi[n + dx + dy * NX + dz * (int)pl];
+                    const int nb = n + dx + dy * NX + dz * (int)pl;
+                    // EPI_CHEB0 operand: x0 = c0 D^-1 b
+                    const T xv = EPI == EPI_CHEB0 ? c0 * Ii[nb] * Bi[nb] : Xi[nb];
+                    acc += St[(int64_t)c * L.n + n] * xv;
                 }
             }
         }
@@ -82,6 +88,12 @@ __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ le
             T d = T(Sc[ep.s1]) * ep.d[e] + T(Sc[ep.s2]) * ep.invd[e] * r;
             ep.d[e] = d;
             Y[e] = X[e] + d;
+        } else if (EPI == EPI_CHEB0) {
+            const T x0 = c0 * ep.invd[e] * ep.b[e];
+            T r = ep.b[e] - acc;
+            T d = T(Sc[ep.s1]) * x0 + T(Sc[ep.s2]) * ep.invd[e] * r;
+            ep.d[e] = d;
+            Y[e] = x0 + d;
         }
     }
 }
@@ -322,6 +334,7 @@ void launch_stencil(int epi, const LevelDev *lev, const Chunk *chunks, int nchun
     case EPI_STORE: k_stencil<T, EPI_STORE><<<g, b, 0, s>>>(lev, chunks, active, x, y, ep); break;
     case EPI_RESID: k_stencil<T, EPI_RESID><<<g, b, 0, s>>>(lev, chunks, active, x, y, ep); break;
     case EPI_CHEB: k_stencil<T, EPI_CHEB><<<g, b, 0, s>>>(lev, chunks, active, x, y, ep); break;
+    case EPI_CHEB0: k_stencil<T, EPI_CHEB0><<<g, b, 0, s>>>(lev, chunks, active, x, y, ep); break;
     default: throw Error(-1, "bad stencil epilogue");
     }
     HTS_LAUNCH_CHECK();

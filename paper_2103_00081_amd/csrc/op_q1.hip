@@ -160,9 +160,10 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const T HTS_GLOBAL *__restrict__ kk = gptr<T>(o.k);
     const T HTS_GLOBAL *__restrict__ lamc = gptr<T>(o.lam);
     const T HTS_GLOBAL *__restrict__ cTc = gptr<T>(o.cT);
-    const T *__restrict__ Bi = (EPI == EPI_RESID || EPI == EPI_RESID_NORM || EPI == EPI_CHEB) ? ep.b + o.off : nullptr;
-    T *__restrict__ Di = EPI == EPI_CHEB ? ep.d + o.off : nullptr;
-    const T *__restrict__ Ii = EPI == EPI_CHEB ? ep.invd + o.off : nullptr;
+    constexpr bool CHEB = EPI == EPI_CHEB || EPI == EPI_CHEB0;
+    const T *__restrict__ Bi = (EPI == EPI_RESID || EPI == EPI_RESID_NORM || CHEB) ? ep.b + o.off : nullptr;
+    T *__restrict__ Di = CHEB ? ep.d + o.off : nullptr;
+    const T *__restrict__ Ii = CHEB ? ep.invd + o.off : nullptr;
 
     const int tid = threadIdx.x, tx = tid % TB, ty = tid / TB;
     const int cx0 = wi.tx * OWN - 1, cy0 = wi.ty * OWN - 1;
@@ -200,11 +201,12 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const T vx = T(-cw8 / (o.hx * o.hx)), vy = T(-cw8 / (o.hy * o.hy)), vz = T(-cw8 / (o.hz * o.hz));
     const T pz0 = T(o.rho_g * o.hz);
     const T cm = T(o.cm);
-    T c1 = T(0), c2 = T(0);
-    if (EPI == EPI_CHEB) {
+    T c0 = T(0), c1 = T(0), c2 = T(0);
+    if (CHEB) {
         const double *Sc = ep.S + (int64_t)wi.inst * NSLOT;
         c1 = T(Sc[ep.s1]);
         c2 = T(Sc[ep.s2]);
+        if (EPI == EPI_CHEB0) c0 = T(Sc[ep.s0]);
     }
 
     // Plane / coefficient / epilogue loads are unconditional (clamped to a
@@ -217,7 +219,10 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
 #pragma unroll
         for (int s = 0; s < 2; s++) {
             const int64_t gi = lc[s].valid ? lc[s].base + kc * plane : 0;
-            pfx[s] = Xi[gi];
+            // EPI_CHEB0 operand: x0 = c0 D^-1 b, in the order of the
+            // separate first Chebyshev kernel
+            if (EPI == EPI_CHEB0) pfx[s] = c0 * Ii[gi] * Bi[gi];
+            else pfx[s] = Xi[gi];
             if (FIELD) pfp[s] = Pi[gi];
             bool keep = lc[s].valid && k >= 0 && k < NZ;
             if (MASKED) keep = keep && !constrained(lc[s], k, NZ, m);
@@ -247,7 +252,8 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         const int64_t gi = own_ok ? oc.base + (int64_t)Lc * plane : 0;
         if (Bi) eb = Bi[gi];
         if (EPI == EPI_CHEB) { ed = Di[gi]; ei = Ii[gi]; }
-        if (EPI == EPI_CHEB || EPI == EPI_DOT || MASKED) ex = Xi[gi];
+        if (EPI == EPI_CHEB0) ei = Ii[gi];
+        if (EPI == EPI_CHEB || EPI == EPI_DOT || (MASKED && EPI != EPI_CHEB0)) ex = Xi[gi];
     };
 
     const int kb = wi.z0, ke = wi.z1;
@@ -283,10 +289,16 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                     T la = T(0);
                     for (int e = rows[lr].beg; e < rows[lr].end; e++) {
                         if (MASKED && ents[e].col_constrained) continue;
-                        la += T(lco[ents[e].src] * ents[e].w) * Xi[ents[e].col];
+                        const int64_t col = ents[e].col;
+                        const T xc = EPI == EPI_CHEB0 ? c0 * Ii[col] * Bi[col] : Xi[col];
+                        la += T(lco[ents[e].src] * ents[e].w) * xc;
                     }
                     v += la;
                 }
+            }
+            if (EPI == EPI_CHEB0) {
+                ex = c0 * ei * eb;
+                ed = ex;
             }
             if (MASKED && constrained(oc, P0, NZ, m)) v = ex;
             if (EPI == EPI_STORE) {
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
             } else if (EPI == EPI_DOT) {
                 Yi[gi] = v;
                 acc += (double)ex * (double)v;
-            } else if (EPI == EPI_CHEB) {
+            } else if (CHEB) {
                 const T r = eb - v;
                 const T d = c1 * ed + c2 * ei * r;
                 Di[gi] = d;
@@ -471,6 +483,10 @@ static void dispatch_epi(int epi, const OpDev *ops, const WorkItem *work, int nw
         break;
     case EPI_DOT: k_q1_apply<T, FIELD, EPI_DOT, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
     case EPI_CHEB: k_q1_apply<T, FIELD, EPI_CHEB, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_CHEB0:
+        if (!MASKED) throw Error(-1, "EPI_CHEB0 is for masked operators");
+        k_q1_apply<T, FIELD, EPI_CHEB0, true><<<g, b, 0, s>>>(ops, work, x, y, ep);
+        break;
     default: throw Error(-1, "bad epilogue");
     }
 }

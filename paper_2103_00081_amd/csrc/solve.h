@@ -10,7 +10,7 @@
 
 namespace hts {
 
-constexpr int CHUNK_LEN = 512;        // nodes per block of the vector kernels
+constexpr int CHUNK_LEN = 1024;       // nodes per block of the vector kernels
 constexpr int CHUNK_LEN_COARSE = 256; // nodes per block on coarse multigrid levels
 
 template <typename T>
@@ -117,7 +117,7 @@ struct Batch {
     DBuf<float> P32, b32, x32, r32, z32, p32, q32, rold32, y32;
 
     int gm_m = 0;
-    DBuf<double> V64, Z64, gH, gcs, gsn, gg, gy, gh1, gh2, gww;
+    DBuf<double> V64, Z64, gH, gcs, gsn, gg, gy, gh1, gh2;
     DBuf<float> V32, Z32;
     DBuf<int32_t> gkdim;
 
@@ -200,6 +200,7 @@ struct Batch {
     template <typename T> void smooth(Hier &H, int l, int steps, int first, const T *b, T *&cur, T *&oth);
     template <typename T> void vcycle(Hier &H, int l, const T *b, T *x);
     template <typename T> void cheb_prec(Hier &H, const T *b, T *x);
+    template <typename T> void cheb_from_zero(Hier &H, int l, int deg, const T *b, T *&cur, T *&oth);
     template <typename T> void tmass_prec(Hier &H, const T *b, T *x);
     void build_tmass(Hier &H, double dt);
     template <typename T>

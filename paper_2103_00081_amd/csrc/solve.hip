@@ -458,6 +458,7 @@ static double apply_bytes(int field, int epi, int64_t nodes, int64_t cells, int 
     int nvec = 2;   // x read, y written
     if (epi == EPI_RESID || epi == EPI_RESID_NORM) nvec = 3;
     if (epi == EPI_CHEB) nvec = 6;   // x, b, d (read + write), D^-1, x_out
+    if (epi == EPI_CHEB0) nvec = 4;  // b, D^-1, d and x_out written
     const int ncoef = field == 0 ? 1 : 3;
     const int extra = field == 0 ? 0 : 1;
     return (double)ts * ((double)nodes * (nvec + extra) + (double)cells * ncoef);
@@ -1023,9 +1024,7 @@ void Batch::vcycle(Hier &H, int l, const T *b, T *x)
     const int deg = H.deg;
     T *xb = PK(T, L.xb64, L.xb32);
     T *cur = xb, *oth = x;   // 2*deg - 1 swaps end in x
-    launch_cheb0<T>(L.ch_ext, L.nch, active.p, L.cheb.p, S_CHEB + 1, PK(T, L.invd64, L.invd32), b,
-                    PK(T, L.d64, L.d32), cur, s);
-    smooth<T>(H, l, deg - 1, 1, b, cur, oth);
+    cheb_from_zero<T>(H, l, deg, b, cur, oth);
     // residual, restriction, coarse correction
     EpiArgs<T> ep{};
     ep.b = b;
@@ -1048,6 +1047,33 @@ void Batch::vcycle(Hier &H, int l, const T *b, T *x)
     }
 }
 
+// deg Chebyshev steps on level l from x = 0, leaving the result in cur
+// after deg - 1 swaps of (cur, oth).  The first two steps run as one
+// operator pass (EPI_CHEB0) where the level's kernel has that epilogue
+// (Q1 and stencil levels), else the first step is its own kernel.
+template <typename T>
+void Batch::cheb_from_zero(Hier &H, int l, int deg, const T *b, T *&cur, T *&oth)
+{
+    Level &L = H.lev[l];
+    if (deg >= 2 && !(l == 0 && p == 2)) {
+        EpiArgs<T> ep{};
+        ep.b = b;
+        ep.d = PK(T, L.d64, L.d32);
+        ep.invd = PK(T, L.invd64, L.invd32);
+        ep.S = L.cheb.p;
+        ep.s0 = S_CHEB + 1;
+        ep.s1 = S_CHEB + 2;
+        ep.s2 = S_CHEB + 3;
+        apply_lvl<T>(H, l, EPI_CHEB0, true, cur, oth, ep);
+        std::swap(cur, oth);
+        smooth<T>(H, l, deg - 2, 2, b, cur, oth);
+        return;
+    }
+    launch_cheb0<T>(L.ch_ext, L.nch, active.p, L.cheb.p, S_CHEB + 1, PK(T, L.invd64, L.invd32), b,
+                    PK(T, L.d64, L.d32), cur, s);
+    smooth<T>(H, l, deg - 1, 1, b, cur, oth);
+}
+
 template <typename T>
 void Batch::cheb_prec(Hier &H, const T *b, T *x)
 {
@@ -1056,9 +1082,7 @@ void Batch::cheb_prec(Hier &H, const T *b, T *x)
     T *xb = PK(T, L.xb64, L.xb32);
     T *cur = ((deg - 1) % 2 == 0) ? x : xb;
     T *oth = (cur == x) ? xb : x;
-    launch_cheb0<T>(L.ch_ext, L.nch, active.p, L.cheb.p, S_CHEB + 1, PK(T, L.invd64, L.invd32), b,
-                    PK(T, L.d64, L.d32), cur, s);
-    smooth<T>(H, 0, deg - 1, 1, b, cur, oth);
+    cheb_from_zero<T>(H, 0, deg, b, cur, oth);
 }
 
 // ------------------------------------------------------------------- CG
@@ -1191,10 +1215,10 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
             vreduce(rch, partial.p, j + 1, RED_NONE, 0, S.p, active.p, 0, 0.0, gh1.p, s);
             vorth_update<T>(vj, V, ld, j + 1, gh1.p, j + 1, w, 1, partial.p, j + 2);
             vreduce(rch, partial.p, j + 2, RED_NONE, 0, S.p, active.p, 0, 0.0, gh2.p, s);
-            vorth_update<T>(vj, V, ld, j + 1, gh2.p, j + 2, w, 0, partial.p, 1);
-            vreduce(rch, partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, gww.p, s);
-            gm_arnoldi(n, active.p, S.p, j, mres, maxit, gh1.p, gh2.p, gww.p, gH.p, gcs.p, gsn.p, gg.p, gkdim.p, s);
-            vaxpby<T>(vj, 1.0, S_SCALE, w, 0.0, -1, w);
+            // Hessenberg column and norm (from |w'|^2 - |h2|^2), then the
+            // second projection and the normalisation in one pass
+            gm_arnoldi(n, active.p, S.p, j, mres, maxit, gh1.p, gh2.p, gH.p, gcs.p, gsn.p, gg.p, gkdim.p, s);
+            vorth_update<T>(vj, V, ld, j + 1, gh2.p, j + 2, w, 0, nullptr, 0, S_SCALE);
         };
         if (use_graph && !g_timing.on) {
             // the whole cycle as one graph, in chunks of K steps with a host
@@ -1268,7 +1292,6 @@ void Batch::ensure_gmres(int mres)
     gy.alloc(al, (size_t)n * mres);
     gh1.alloc(al, (size_t)n * (mres + 2));
     gh2.alloc(al, (size_t)n * (mres + 2));
-    gww.alloc(al, (size_t)n * 2);
     gkdim.alloc(al, n);
     gkdim.zero(s);
 }

@@ -46,8 +46,11 @@ void vcg_update(const VecCtx &v, T *x, T *r, const T *p, const T *q, T *r_old, d
 template <typename T>
 void vmultidot(const VecCtx &v, const T *V, int64_t ld, int nv, const T *w, double *partial, int ncomp);
 template <typename T>
+// w -= sum_i h_i V_i; dots: partials of V_i . w (i < nv) and w . w (entry
+// nv); without dots: w . w (entry 0) when partial is not null; scale_slot >=
+// 0: the result is also scaled by that slot (no partials then)
 void vorth_update(const VecCtx &v, const T *V, int64_t ld, int nv, const double *H, int hld, T *w, int dots,
-                  double *partial, int ncomp);
+                  double *partial, int ncomp, int scale_slot = -1);
 template <typename T, typename TX>
 void vbasis_update(const VecCtx &v, const T *Z, int64_t ld, const int32_t *kdim, const double *Y, int yld,
                    double scale, int iscale, TX *x);

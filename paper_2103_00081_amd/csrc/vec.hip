@@ -150,18 +150,20 @@ __global__ __launch_bounds__(VB) void k_orth_update(const Chunk *__restrict__ ch
                                                     const double *S, const T *__restrict__ V, int64_t ld,
                                                     int nv, const double *__restrict__ H, int hld,
                                                     T *__restrict__ w, int dots, double *partial,
-                                                    int ncomp)
+                                                    int ncomp, int scale_slot)
 {
     __shared__ double sh[4];
     __shared__ double hs[64];
     CHUNK_PROLOGUE
     if (threadIdx.x < nv) hs[threadIdx.x] = H[(int64_t)ch.inst * hld + threadIdx.x];
     __syncthreads();
+    const double sc = scale_slot >= 0 ? Si[scale_slot] : 1.0;
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
         double acc = (double)w[e];
         for (int i = 0; i < nv; i++) acc -= hs[i] * (double)V[(int64_t)i * ld + e];
-        w[e] = T(acc);
+        w[e] = T(scale_slot >= 0 ? acc * sc : acc);
     }
+    if (!partial) return;
     __syncthreads();
     if (dots) {
         for (int i = 0; i < nv; i++) {
@@ -476,9 +478,10 @@ void vmultidot(const VecCtx &v, const T *V, int64_t ld, int nv, const T *w, doub
 }
 template <typename T>
 void vorth_update(const VecCtx &v, const T *V, int64_t ld, int nv, const double *H, int hld, T *w, int dots,
-                  double *partial, int ncomp)
+                  double *partial, int ncomp, int scale_slot)
 {
-    k_orth_update<T><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, H, hld, w, dots, partial, ncomp);
+    if (scale_slot >= 0 && partial) throw Error(-1, "vorth_update: scaling takes no partial sums");
+    k_orth_update<T><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, H, hld, w, dots, partial, ncomp, scale_slot);
     HTS_LAUNCH_CHECK();
 }
 template <typename T, typename TX>
@@ -585,7 +588,7 @@ void vset_slots(const int *slots, int nslots, const double *const *vals, int n, 
     template void vcg_update<T>(const VecCtx &, T *, T *, const T *, const T *, T *, double *);          \
     template void vmultidot<T>(const VecCtx &, const T *, int64_t, int, const T *, double *, int);       \
     template void vorth_update<T>(const VecCtx &, const T *, int64_t, int, const double *, int, T *, int, \
-                                  double *, int);                                                        \
+                                  double *, int, int);                                                   \
     template void vbasis_update<T, double>(const VecCtx &, const T *, int64_t, const int32_t *,          \
                                            const double *, int, double, int, double *);                 \
     template void vbasis_update<T, float>(const VecCtx &, const T *, int64_t, const int32_t *,           \
