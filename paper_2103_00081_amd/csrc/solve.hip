@@ -1541,7 +1541,7 @@ void Batch::scatter_state()
     }
     vgather_scatter(ch.p, hch, P, off, Pn.p, false, s);
     vgather_scatter(ch.p, hch, T, off, Tn.p, false, s);
-    sync(s);
+    export_state();   // completion wait (spin on the export's sequence number)
 }
 
 // Solve the pressure of every instance at t_i + dt into P1 (steady or transient).
@@ -1630,7 +1630,7 @@ int Batch::step(double dt, const hts_solver_opts &o, std::vector<hts_step_stats>
         vcopy<double>(v, T1.p, Tn.p);
         for (int i = 0; i < n; i++) m[i]->t += dt;
     }
-    sync(s);
+    export_state();   // completion wait
     return rc;
 }
 
