@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--modes", default="fp64,fp32_refined",
                     help="comma list of fp64, fp32_refined; the faster one is the headline")
     ap.add_argument("--ncells", default="128,128,64")
-    ap.add_argument("--cpu-steps", type=int, default=3,
+    ap.add_argument("--cpu-steps", type=int, default=5,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check-every", type=int, default=1)
