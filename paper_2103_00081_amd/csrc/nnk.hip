@@ -74,6 +74,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ X
 #pragma unroll
     for (int t = 0; t < NT; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int ktot = 27 * cin;
+    // unrolled so that the gathers of several K steps are in flight together
+#pragma unroll 4
     for (int kc = 0; kc < kp; kc += 32) {
         const int k0 = kc + 8 * kq;
         bf16x8 a = zero8();
@@ -106,6 +108,160 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ X
             else Ybf[vo * ldy + co] = f2bf(y);
         }
     }
+}
+
+// k_conv_fwd for small grids: the four waves of a block share one group of 16
+// output voxels and split the K steps (wave w takes steps w, w + 4, ...);
+// the four partial products are added in wave order through LDS.
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv_fwd_splitk(const uint16_t *__restrict__ X, int cin, int3 din,
+                                                         const uint16_t *__restrict__ W, int kp,
+                                                         const float *__restrict__ bias, int cout, int3 dout,
+                                                         int stride, int relu, const uint16_t *__restrict__ skip,
+                                                         uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy)
+{
+    __shared__ f32x4 part[4][NT][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t nout = (int64_t)dout.x * dout.y * dout.z;
+    const int64_t vbase = (int64_t)blockIdx.x * 16;
+    const int64_t v = vbase + (lane & 15);
+    const int kq = lane >> 4;
+    int oi = 0, oj = 0, ok = 0;
+    const bool vok = v < nout;
+    if (vok) vox_ijk(v, dout, oi, oj, ok);
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int ktot = 27 * cin;
+#pragma unroll 2
+    for (int kc = 32 * w; kc < kp; kc += 128) {
+        const int k0 = kc + 8 * kq;
+        bf16x8 a = zero8();
+        if (vok && k0 < ktot) {
+            const int tap = k0 / cin, c0 = k0 - tap * cin;
+            const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+            const int ii = oi * stride + dx - 1, jj = oj * stride + dy - 1, kk = ok * stride + dz - 1;
+            if (ii >= 0 && ii < din.x && jj >= 0 && jj < din.y && kk >= 0 && kk < din.z)
+                a = load8(X + ((int64_t)ii + (int64_t)din.x * (jj + (int64_t)din.y * kk)) * cin + c0);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int co = t * 16 + (lane & 15);
+            const bf16x8 b = load8(W + (int64_t)co * kp + k0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; t++) part[w][t][lane] = acc[t];
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+        const f32x4 sum = ((part[0][t][lane] + part[1][t][lane]) + part[2][t][lane]) + part[3][t][lane];
+        const int co = t * 16 + (lane & 15);
+        if (co >= cout) continue;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int64_t vo = vbase + 4 * kq + j;
+            if (vo >= nout) continue;
+            float y = sum[j] + bias[co];
+            if (relu) y = fmaxf(y, 0.f);
+            if (skip) y += bf2f(skip[vo * cout + co]);
+            if (Yf) Yf[vo * ldy + co] = y;
+            else Ybf[vo * ldy + co] = f2bf(y);
+        }
+    }
+}
+
+// Stride-1 convolution with the input tile in LDS.  A block computes an
+// 8 x 8 x 4 tile of output voxels (wave w: tile voxels 64 w .. 64 w + 63,
+// x fastest, as four 16-row A fragments); the 10 x 10 x 6 input voxels
+// around the tile are staged once with all their channels (voxel stride cs
+// bf16 in LDS), and each K step reads its A fragments from there.  Same
+// products and FP32 accumulation order as k_conv_fwd (K ascending).
+constexpr int CT_X = 8, CT_Y = 8, CT_Z = 4;
+constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_V = CH_X * CH_Y * CH_Z;
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv_fwd_tile(const uint16_t *__restrict__ X, int cin, int3 d,
+                                                       const uint16_t *__restrict__ W, int kp,
+                                                       const float *__restrict__ bias, int cout, int relu,
+                                                       const uint16_t *__restrict__ skip,
+                                                       uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy,
+                                                       int cs)
+{
+    extern __shared__ uint4 conv_tile_raw[];
+    uint16_t *tile = reinterpret_cast<uint16_t *>(conv_tile_raw);
+    const int nbx = (d.x + CT_X - 1) / CT_X, nby = (d.y + CT_Y - 1) / CT_Y;
+    const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+    const int x0 = bx * CT_X - 1, y0 = by * CT_Y - 1, z0 = bz * CT_Z - 1;   // halo origin
+    const int units = cin / 8;
+    for (int u = threadIdx.x; u < CH_V * units; u += 256) {
+        const int hv = u / units, cu = u - hv * units;
+        const int hx = hv % CH_X, hy = (hv / CH_X) % CH_Y, hz = hv / (CH_X * CH_Y);
+        const int gx = x0 + hx, gy = y0 + hy, gz = z0 + hz;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (gx >= 0 && gx < d.x && gy >= 0 && gy < d.y && gz >= 0 && gz < d.z)
+            val = *reinterpret_cast<const uint4 *>(
+                X + ((int64_t)gx + (int64_t)d.x * (gy + (int64_t)d.y * gz)) * cin + cu * 8);
+        *reinterpret_cast<uint4 *>(tile + hv * cs + cu * 8) = val;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4, r = lane & 15;
+    int abase[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int vt = w * 64 + a * 16 + r;
+        const int tx = vt % CT_X, ty = (vt / CT_X) % CT_Y, tz = vt / (CT_X * CT_Y);
+        abase[a] = (tz * CH_Y + ty) * CH_X + tx;   // halo index of the (0, 0, 0) neighbour
+    }
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[a][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int ktot = 27 * cin;
+    int tap = (8 * kq) / cin, c0 = 8 * kq - tap * cin;   // K index 8 kq of the first step
+    for (int kc = 0; kc < kp; kc += 32) {
+        const int k0 = kc + 8 * kq;
+        const bool kin = k0 < ktot;
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+        const int toff = (dz * CH_Y + dy) * CH_X + dx;
+        bf16x8 bfr[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) bfr[t] = load8(W + (int64_t)(t * 16 + r) * kp + k0);
+        bf16x8 afr[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) afr[a] = kin ? load8(tile + (abase[a] + toff) * cs + c0) : zero8();
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[a], bfr[t], acc[a][t], 0, 0, 0);
+        c0 += 32;
+        while (c0 >= cin) {
+            c0 -= cin;
+            tap++;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int co = t * 16 + r;
+            if (co >= cout) continue;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int vt = w * 64 + a * 16 + 4 * kq + j;
+                const int gx = x0 + 1 + vt % CT_X, gy = y0 + 1 + (vt / CT_X) % CT_Y, gz = z0 + 1 + vt / (CT_X * CT_Y);
+                if (gx >= d.x || gy >= d.y || gz >= d.z) continue;
+                const int64_t vo = (int64_t)gx + (int64_t)d.x * (gy + (int64_t)d.y * gz);
+                float y = acc[a][t][j] + bias[co];
+                if (relu) y = fmaxf(y, 0.f);
+                if (skip) y += bf2f(skip[vo * cout + co]);
+                if (Yf) Yf[vo * ldy + co] = y;
+                else Ybf[vo * ldy + co] = f2bf(y);
+            }
+        }
 }
 
 // ------------------------------------------------------- backward, data
@@ -333,6 +489,41 @@ __global__ void k_upsample(const uint16_t *__restrict__ C, int3 dc, int ch, uint
     F[e] = f2bf(s);
 }
 
+// k_upsample for ch a multiple of 8: one thread per fine voxel and group of
+// 8 channels (16-byte loads and stores), parents summed in the same order
+__global__ void k_upsample8(const uint16_t *__restrict__ C, int3 dc, int ch, uint16_t *__restrict__ F, int3 df)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nf = (int64_t)df.x * df.y * df.z;
+    const int groups = ch / 8;
+    if (e >= nf * groups) return;
+    const int64_t v = e / groups;
+    const int c0 = (int)(e - v * groups) * 8;
+    int i, j, k;
+    vox_ijk(v, df, i, j, k);
+    int px[2], py[2], pz[2];
+    float wx[2], wy[2], wz[2];
+    const int nx = up_parents(i, dc.x, px, wx), ny = up_parents(j, dc.y, py, wy), nz = up_parents(k, dc.z, pz, wz);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int c2 = 0; c2 < nz; c2++)
+        for (int b = 0; b < ny; b++)
+            for (int a = 0; a < nx; a++) {
+                const float w = wx[a] * wy[b] * wz[c2];
+                const uint4 q = *reinterpret_cast<const uint4 *>(
+                    C + ((int64_t)px[a] + (int64_t)dc.x * (py[b] + (int64_t)dc.y * pz[c2])) * ch + c0);
+                const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int h = 0; h < 4; h++) {
+                    s[2 * h] += w * bf2f((uint16_t)(u[h] & 0xFFFFu));
+                    s[2 * h + 1] += w * bf2f((uint16_t)(u[h] >> 16));
+                }
+            }
+    uint32_t o[4];
+#pragma unroll
+    for (int h = 0; h < 4; h++) o[h] = (uint32_t)f2bf(s[2 * h]) | ((uint32_t)f2bf(s[2 * h + 1]) << 16);
+    *reinterpret_cast<uint4 *>(F + v * ch + c0) = make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 // adjoint of k_upsample: gc[o] = sum_i w(i, o) gf[i]
 __global__ void k_upsample_adj(const float *__restrict__ GF, int3 df, int ch, float *__restrict__ GC, int3 dc)
 {
@@ -506,6 +697,24 @@ __global__ void k_unpack_output_dev(const float *__restrict__ Y, int ldy, const 
     z[v] = val;
 }
 
+// c = bf16(a + b), 8 entries per thread (n a multiple of 8)
+__global__ void k_add_bf16x8(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, int64_t n8,
+                             uint16_t *__restrict__ c)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n8) return;
+    const uint4 qa = reinterpret_cast<const uint4 *>(a)[e], qb = reinterpret_cast<const uint4 *>(b)[e];
+    const uint32_t ua[4] = {qa.x, qa.y, qa.z, qa.w}, ub[4] = {qb.x, qb.y, qb.z, qb.w};
+    uint32_t o[4];
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+        const uint16_t lo = f2bf(bf2f((uint16_t)(ua[h] & 0xFFFFu)) + bf2f((uint16_t)(ub[h] & 0xFFFFu)));
+        const uint16_t hi = f2bf(bf2f((uint16_t)(ua[h] >> 16)) + bf2f((uint16_t)(ub[h] >> 16)));
+        o[h] = (uint32_t)lo | ((uint32_t)hi << 16);
+    }
+    reinterpret_cast<uint4 *>(c)[e] = make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 // c = bf16(a + b)
 __global__ void k_add_bf16(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, int64_t n,
                            uint16_t *__restrict__ c)
@@ -534,6 +743,41 @@ void nn_conv_fwd(const uint16_t *X, int cin, Dims din, const uint16_t *W, int kp
     const dim3 g((unsigned)((nout + 63) / 64)), b(256);
     const int3 di{din.x, din.y, din.z}, dn{dout.x, dout.y, dout.z};
     const int nt = (cout + 15) / 16;
+    if (nout < 32768) {
+        // small grids (fewer than 2048 groups of 16 voxels): split K over the
+        // four waves of a block
+        const dim3 gs((unsigned)((nout + 15) / 16));
+        switch (nt) {
+        case 1: k_conv_fwd_splitk<1><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
+        case 2: k_conv_fwd_splitk<2><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
+        case 3: k_conv_fwd_splitk<3><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
+        case 4: k_conv_fwd_splitk<4><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
+        default: throw Error(-7, "at most 64 output channels");
+        }
+        HTS_LAUNCH_CHECK();
+        return;
+    }
+    // stride 1: the LDS-tiled kernel when the halo tile fits 64 KB (voxel
+    // stride padded by 8 channels where that still fits, which spreads the
+    // 16 rows of a fragment over distinct banks)
+    if (stride == 1 && din.x == dout.x && din.y == dout.y && din.z == dout.z && cin % 8 == 0 && nt <= 4) {
+        int cs = cin + 8;
+        if ((int64_t)CH_V * cs * 2 > 65536) cs = cin;
+        if ((int64_t)CH_V * cs * 2 <= 65536) {
+            const int64_t nb = (int64_t)((din.x + CT_X - 1) / CT_X) * ((din.y + CT_Y - 1) / CT_Y) *
+                               ((din.z + CT_Z - 1) / CT_Z);
+            const dim3 gt((unsigned)nb);
+            const size_t lds = (size_t)CH_V * cs * 2;
+            switch (nt) {
+            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
+            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
+            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
+            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
+            }
+            HTS_LAUNCH_CHECK();
+            return;
+        }
+    }
     switch (nt) {
     case 1: k_conv_fwd<1><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
     case 2: k_conv_fwd<2><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
@@ -614,9 +858,15 @@ void nn_transpose_w(const uint16_t *W, int cout, int cin, int kp, uint16_t *Wt, 
     HTS_LAUNCH_CHECK();
 }
 
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 void nn_upsample(const uint16_t *C, Dims dc, int ch, uint16_t *F, Dims df, hipStream_t s)
 {
-    k_upsample<<<g256(df.n() * ch), dim3(256), 0, s>>>(C, int3{dc.x, dc.y, dc.z}, ch, F, int3{df.x, df.y, df.z});
+    if (ch % 8 == 0 && aligned16(C) && aligned16(F))
+        k_upsample8<<<g256(df.n() * (ch / 8)), dim3(256), 0, s>>>(C, int3{dc.x, dc.y, dc.z}, ch, F,
+                                                                   int3{df.x, df.y, df.z});
+    else
+        k_upsample<<<g256(df.n() * ch), dim3(256), 0, s>>>(C, int3{dc.x, dc.y, dc.z}, ch, F, int3{df.x, df.y, df.z});
     HTS_LAUNCH_CHECK();
 }
 
@@ -690,7 +940,10 @@ void nn_unpack_output_dev(const float *Y, int ldy, const double *rr, double nfre
 
 void nn_add_bf16(const uint16_t *a, const uint16_t *b, int64_t n, uint16_t *c, hipStream_t s)
 {
-    k_add_bf16<<<g256(n), dim3(256), 0, s>>>(a, b, n, c);
+    if (n % 8 == 0 && aligned16(a) && aligned16(b) && aligned16(c))
+        k_add_bf16x8<<<g256(n / 8), dim3(256), 0, s>>>(a, b, n / 8, c);
+    else
+        k_add_bf16<<<g256(n), dim3(256), 0, s>>>(a, b, n, c);
     HTS_LAUNCH_CHECK();
 }
 

@@ -9,8 +9,12 @@ oracle on the same BF16 values.
 
 Network: the GPU keeps activations and layer gradients in BF16; the oracle
 runs with the same storage rounding (oracle.nnet.bf16 at the same points),
-so the two differ only by FP32 accumulation order and the rare BF16 values
-it flips: output within 2e-3 relative (L2), gradients within 2e-2 per layer.
+so the two differ only by FP32 accumulation order and the BF16 values it
+flips (one BF16 ulp, 2^-8 relative, each): output within 2e-3 relative (L2),
+weight gradients within 5e-2 per layer (the deepest layers sum over a few
+dozen voxels, where a flipped BF16 value next to zero also flips a ReLU
+gate, so a few flips move them by percents; a wiring error moves them by
+order one).  The grids keep 36 and 60 voxels on the coarsest level.
 
 Learned solve: every answer is judged by the true FP64 residual; the
 pressure must match the plain FP64 answer to 1e-8 relative.
@@ -61,6 +65,19 @@ def test_conv_forward_parity(hts, cin, cout, s, din):
     assert np.all(err <= 27 * cin * U32 * cl(bound) + 1e-30), err.max()
 
 
+# Grids of at least 32768 output voxels take the LDS-tiled kernel (stride 1,
+# halo tile within 64 KB) or the one-gather-per-step kernel (stride 2, or
+# 64 input channels); the small CASES take the split-K kernel.  Ragged tiles
+# on every axis.
+LARGE = [(16, 16, 1, (41, 33, 25)), (8, 16, 1, (37, 35, 27)), (48, 32, 1, (33, 33, 31)),
+         (16, 32, 2, (129, 65, 33)), (64, 16, 1, (34, 33, 30))]
+
+
+@pytest.mark.parametrize("cin,cout,s,din", LARGE)
+def test_conv_forward_parity_large(hts, cin, cout, s, din):
+    test_conv_forward_parity(hts, cin, cout, s, din)
+
+
 @pytest.mark.parametrize("cin,cout,s,din", CASES)
 def test_conv_data_gradient_parity(hts, cin, cout, s, din):
     print_case("conv bwd data", cin, cout, s, din)
@@ -107,7 +124,7 @@ def net_case(seed, dims):
     return theta, inp, tgt, mask
 
 
-@pytest.mark.parametrize("dims", [(17, 13, 9), (20, 11, 7)])
+@pytest.mark.parametrize("dims", [(33, 25, 17), (29, 22, 19)])
 def test_network_forward_and_gradient_parity(hts, dims):
     print_case("network", dims)
     X, Y, Z = dims
@@ -129,7 +146,7 @@ def test_network_forward_and_gradient_parity(hts, dims):
         a, b = g[o:o + nw], go[o:o + nw]
         r = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         print(name, "grad rel", r)
-        assert r <= 2e-2, name
+        assert r <= 5e-2, name
         o += nw
 
 
