@@ -221,7 +221,7 @@ void Batch::build_work()
         for (const WorkItem &w : nat) sp[w.inst + 1]++;
         for (int i = 0; i < n; i++) sp[i + 1] += sp[i];
         wkp[f].upload(al, sp, s);
-        rwk[f] = RedCtx{wkp[f].p, n};
+        rwk[f] = RedCtx{wkp[f].p, n, n == 1 ? sp[1] : -1};
     }
     partial.alloc(al, (size_t)std::max<int64_t>(std::max(nwork[0], nwork[1]), nch) * 64 + 64);
 }
@@ -259,7 +259,7 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->nch = (int)B->hch.size();
     B->ch.upload(al, B->hch, s);
     B->chp.upload(al, sp, s);
-    B->rch = RedCtx{B->chp.p, n};
+    B->rch = RedCtx{B->chp.p, n, n == 1 ? sp[1] : -1};
     B->build_work();
 
     B->S.alloc(al, (size_t)n * NSLOT);
@@ -889,7 +889,7 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
             C.nch = (int)C.hch.size();
             C.ch.upload(al, C.hch, s);
             C.segp.upload(al, sp, s);
-            C.red = RedCtx{C.segp.p, n};
+            C.red = RedCtx{C.segp.p, n, n == 1 ? sp[1] : -1};
             C.ch_ext = C.ch.p;
         }
         C.S64.alloc(al, (size_t)27 * std::max<int64_t>(ctot, 1));

@@ -19,6 +19,7 @@ struct VecCtx {
 struct RedCtx {
     const int32_t *seg_ptr;    // [ninst + 1]
     int nseg;                  // = ninst
+    int single = -1;           // one instance: its partial count (seg_ptr not read)
 };
 
 enum RedOp {

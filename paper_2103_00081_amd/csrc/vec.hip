@@ -327,14 +327,14 @@ __device__ void scalar_op(int op, int inst, const double *v, const double *pre, 
 // issued together, then the partial sums; a kernel of a few dependent memory
 // latencies in the solver's critical path.
 __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partial, int ncomp,
-                                               const int32_t *__restrict__ seg_ptr, int op, int slot,
-                                               double *S, int32_t *active, int maxit, double aux,
+                                               const int32_t *__restrict__ seg_ptr, int single, int op,
+                                               int slot, double *S, int32_t *active, int maxit, double aux,
                                                double *out)
 {
     __shared__ double vals[64];
     const int inst = blockIdx.x;
     const int on = active ? active[inst] : 1;
-    const int b = seg_ptr[inst], e = seg_ptr[inst + 1];
+    const int b = single >= 0 ? 0 : seg_ptr[inst], e = single >= 0 ? single : seg_ptr[inst + 1];
     double pre[3] = {0.0, 0.0, 0.0};
     if (threadIdx.x == 0) {
         const double *Si = S + (int64_t)inst * NSLOT;
@@ -519,7 +519,7 @@ void vpiezo32(const VecCtx &v, const OpDev *ops64, const double *P, float *P32)
 void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
              int maxit, double aux, double *out, hipStream_t s)
 {
-    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, op, slot, S,
+    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, r.single, op, slot, S,
                                                           active, maxit, aux, out);
     HTS_LAUNCH_CHECK();
 }
