@@ -229,7 +229,7 @@ static NNWork &workspace(hts_nn *nn, Dims d0)
     for (size_t k = 0; k < nl; k++) {
         const NNLayer &Ly = nn->layers[k];
         gmax = std::max(gmax, W->n[Ly.lout] * Ly.coutp);
-        pmax = std::max(pmax, nn_bwd_weight_chunks(W->d[Ly.lout]) * (int64_t)Ly.coutp * Ly.kp);
+        pmax = std::max(pmax, (nn_bwd_weight_chunks(W->d[Ly.lout]) + SUM_GROUPS) * (int64_t)Ly.coutp * Ly.kp);
         abmax = std::max(abmax, W->n[Ly.lout] * (int64_t)Ly.coutp);
         abmax = std::max(abmax, W->n[Ly.lin] * (int64_t)Ly.cinp);
     }
@@ -572,7 +572,7 @@ hts_status hts_nn_conv3d(int32_t op, int32_t cin, int32_t cout, int32_t stride, 
         } else {
             G.upload(&al, g, (size_t)dn.n() * cout, s);
             X.upload(&al, x, (size_t)di.n() * cin, s);
-            P.alloc(&al, (size_t)std::max<int64_t>(nn_bwd_weight_chunks(dn) * cout * kp, 1));
+            P.alloc(&al, (size_t)std::max<int64_t>((nn_bwd_weight_chunks(dn) + SUM_GROUPS) * cout * kp, 1));
             Y.alloc(&al, (size_t)cout * kp);
             nn_conv_bwd_weight(G.p, cout, dn, X.p, cin, di, stride, P.p, kp, Y.p, 0, s);
             std::vector<float> gw((size_t)cout * kp);

@@ -18,9 +18,13 @@ void nn_conv_fwd(const uint16_t *X, int cin, Dims din, const uint16_t *W, int kp
 void nn_conv_bwd_data(const uint16_t *G, int cout, Dims dout, const uint16_t *Wt, int ktp, int cin, Dims din,
                       int stride, float *GX, hipStream_t s);
 int64_t nn_bwd_weight_chunks(Dims dout);
-// gw [Cout][kp] (+)= sum_o g[o] x[in(o, k)]; partial: chunks * cout * kp floats
+// group count of the two-stage partial sums
+constexpr int SUM_GROUPS = 32;
+// gw [Cout][kp] (+)= sum_o g[o] x[in(o, k)]; partial: (chunks + SUM_GROUPS) *
+// cout * kp floats (the chunk partials, then the group sums)
 void nn_conv_bwd_weight(const uint16_t *G, int cout, Dims dout, const uint16_t *X, int cin, Dims din, int stride,
                         float *partial, int kp, float *gw, int accumulate, hipStream_t s);
+// gb (+)= sum_o g[o]; partial: (chunks + SUM_GROUPS) * cout floats
 void nn_bias_grad(const uint16_t *G, int64_t nvox, int cout, float *partial, float *gb, int accumulate, hipStream_t s);
 void nn_transpose_w(const uint16_t *W, int cout, int cin, int kp, uint16_t *Wt, int ktp, hipStream_t s);
 void nn_upsample(const uint16_t *C, Dims dc, int ch, uint16_t *F, Dims df, hipStream_t s);

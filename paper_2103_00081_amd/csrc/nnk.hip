@@ -415,14 +415,29 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const uint16_t *__restr
 // sum the per-chunk partials in chunk order: out[i] (+)= sum_c partial[c][i];
 // entries whose index within a row of length ld is >= valid are not
 // produced by the partial kernels and read as zero
-__global__ void k_sum_partials(const float *__restrict__ partial, int64_t nchunk, int64_t n, int ld, int valid,
-                               float *__restrict__ out, int accumulate)
+// In two stages with a fixed grouping (independent of the launch): group g
+// of SUM_GROUPS sums chunks [g L, (g + 1) L), L = ceil(nchunk / SUM_GROUPS),
+// in chunk order into tmp[g][i]; then the groups are added in order.
+__global__ void k_sum_partials_groups(const float *__restrict__ partial, int64_t nchunk, int64_t n, int ld,
+                                      int valid, float *__restrict__ tmp)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (i >= n) return;
+    const int64_t L = (nchunk + SUM_GROUPS - 1) / SUM_GROUPS;
+    const int64_t c0 = g * L, c1 = min(nchunk, c0 + L);
+    float s = 0.f;
+    if ((int)(i % ld) < valid)
+        for (int64_t c = c0; c < c1; c++) s += partial[c * n + i];
+    tmp[g * n + i] = s;
+}
+
+__global__ void k_sum_partials(const float *__restrict__ tmp, int64_t n, float *__restrict__ out, int accumulate)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     float s = 0.f;
-    if ((int)(i % ld) < valid)
-        for (int64_t c = 0; c < nchunk; c++) s += partial[c * n + i];
+    for (int g = 0; g < SUM_GROUPS; g++) s += tmp[g * n + i];
     out[i] = accumulate ? out[i] + s : s;
 }
 
@@ -807,6 +822,19 @@ void nn_conv_bwd_data(const uint16_t *G, int cout, Dims dout, const uint16_t *Wt
 
 int64_t nn_bwd_weight_chunks(Dims dout) { return (dout.n() + BW_CHUNK - 1) / BW_CHUNK; }
 
+// out (+)= sum over the nchunk partials [c][n]; the group sums go to
+// partial + nchunk n (the buffer holds (nchunk + SUM_GROUPS) n floats)
+static void sum_partials(float *partial, int64_t nch, int64_t n, int ld, int valid, float *out, int accumulate,
+                         hipStream_t s)
+{
+    float *tmp = partial + nch * n;
+    k_sum_partials_groups<<<dim3((unsigned)((n + 255) / 256), SUM_GROUPS), dim3(256), 0, s>>>(partial, nch, n, ld,
+                                                                                             valid, tmp);
+    HTS_LAUNCH_CHECK();
+    k_sum_partials<<<g256(n), dim3(256), 0, s>>>(tmp, n, out, accumulate);
+    HTS_LAUNCH_CHECK();
+}
+
 template <int MT>
 static void bw_dispatch(int ntc, dim3 g, hipStream_t s, const uint16_t *G, int cout, int3 dn, const uint16_t *X,
                         int cin, int3 di, int stride, float *partial, int kp)
@@ -838,8 +866,7 @@ void nn_conv_bwd_weight(const uint16_t *G, int cout, Dims dout, const uint16_t *
     }
     HTS_LAUNCH_CHECK();
     const int64_t n = (int64_t)cout * kp;
-    k_sum_partials<<<g256(n), dim3(256), 0, s>>>(partial, nch, n, kp, 27 * cin, gw, accumulate);
-    HTS_LAUNCH_CHECK();
+    sum_partials(partial, nch, n, kp, 27 * cin, gw, accumulate, s);
 }
 
 void nn_bias_grad(const uint16_t *G, int64_t nvox, int cout, float *partial, float *gb, int accumulate, hipStream_t s)
@@ -847,8 +874,7 @@ void nn_bias_grad(const uint16_t *G, int64_t nvox, int cout, float *partial, flo
     const int64_t nch = (nvox + BW_CHUNK - 1) / BW_CHUNK;
     k_bias_partial<<<dim3((unsigned)nch), dim3(256), 0, s>>>(G, nvox, cout, partial);
     HTS_LAUNCH_CHECK();
-    k_sum_partials<<<g256(cout), dim3(256), 0, s>>>(partial, nch, cout, cout, cout, gb, accumulate);
-    HTS_LAUNCH_CHECK();
+    sum_partials(partial, nch, cout, cout, cout, gb, accumulate, s);
 }
 
 void nn_transpose_w(const uint16_t *W, int cout, int cin, int kp, uint16_t *Wt, int ktp, hipStream_t s)
