@@ -24,7 +24,8 @@ constexpr int SUM_GROUPS = 32;
 // cout * kp floats (the chunk partials, then the group sums)
 void nn_conv_bwd_weight(const uint16_t *G, int cout, Dims dout, const uint16_t *X, int cin, Dims din, int stride,
                         float *partial, int kp, float *gw, int accumulate, hipStream_t s);
-// gb (+)= sum_o g[o]; partial: (chunks + SUM_GROUPS) * cout floats
+// gb (+)= sum_o g[o]; partial: (ceil(nvox / 512) + SUM_GROUPS) * cout floats
+// (within the weight-gradient buffer of the same layer, since kp >= 32)
 void nn_bias_grad(const uint16_t *G, int64_t nvox, int cout, float *partial, float *gb, int accumulate, hipStream_t s);
 void nn_transpose_w(const uint16_t *W, int cout, int cin, int kp, uint16_t *Wt, int ktp, hipStream_t s);
 void nn_upsample(const uint16_t *C, Dims dc, int ch, uint16_t *F, Dims df, hipStream_t s);

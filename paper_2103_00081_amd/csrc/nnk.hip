@@ -319,7 +319,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *__restric
 // partial[chunk][co][k] = sum_{o in chunk} g[o][co] x[in(o, k)], k = tap*Cin+ci.
 // One block per (voxel chunk, tap); each wave stages 32 voxels of g and x in
 // LDS and multiplies them transposed on the matrix cores.
-constexpr int BW_CHUNK = 512;    // output voxels per block
+constexpr int BW_CHUNK = 2048;   // output voxels per block (weight gradient)
+constexpr int BB_CHUNK = 512;    // output voxels per block (bias gradient)
 
 template <int MT, int NTC>
 __global__ __launch_bounds__(256) void k_conv_bwd_weight(const uint16_t *__restrict__ G, int cout, int3 dout,
@@ -331,15 +332,20 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const uint16_t *__restr
     __shared__ float red[64][65];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // columns beyond cin / cout of the last 16-wide tile stay zero
-    for (int e = threadIdx.x; e < 4 * 32 * 72; e += 256) {
-        (&gs[0][0][0])[e] = 0;
-        (&xs[0][0][0])[e] = 0;
+    if ((cout | cin) & 15) {
+        for (int e = threadIdx.x; e < 4 * 32 * 72; e += 256) {
+            (&gs[0][0][0])[e] = 0;
+            (&xs[0][0][0])[e] = 0;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const int tap = blockIdx.y;
+    // the 27 taps of a chunk are consecutive blocks, so the chunk's g rows
+    // and the x neighbourhood are read while still in cache
+    const int tap = blockIdx.x;
+    const int64_t chunk = blockIdx.y;
     const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
     const int64_t nout = (int64_t)dout.x * dout.y * dout.z;
-    const int64_t c0v = (int64_t)blockIdx.x * BW_CHUNK;
+    const int64_t c0v = chunk * BW_CHUNK;
     f32x4 acc[MT][NTC];
 #pragma unroll
     for (int a = 0; a < MT; a++)
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const uint16_t *__restr
         }
         __syncthreads();
     }
-    float *P = partial + ((int64_t)blockIdx.x) * cout * kp;
+    float *P = partial + chunk * cout * kp;
     for (int e = threadIdx.x; e < cout * cin; e += 256) {
         const int co = e / cin, ci = e % cin;
         P[(int64_t)co * kp + tap * cin + ci] = red[co][ci];
@@ -446,10 +452,10 @@ __global__ void k_bias_partial(const uint16_t *__restrict__ G, int64_t nvox, int
 {
     __shared__ float sh[256];
     const int co = threadIdx.x % 64, r = threadIdx.x / 64;
-    const int64_t b0 = (int64_t)blockIdx.x * BW_CHUNK;
+    const int64_t b0 = (int64_t)blockIdx.x * BB_CHUNK;
     float s = 0.f;
     if (co < cout)
-        for (int64_t v = b0 + r; v < b0 + BW_CHUNK && v < nvox; v += 4) s += bf2f(G[v * cout + co]);
+        for (int64_t v = b0 + r; v < b0 + BB_CHUNK && v < nvox; v += 4) s += bf2f(G[v * cout + co]);
     sh[threadIdx.x] = s;
     __syncthreads();
     if (r == 0 && co < cout)
@@ -854,7 +860,8 @@ void nn_conv_bwd_weight(const uint16_t *G, int cout, Dims dout, const uint16_t *
     if (cout % 8 != 0 || cin % 8 != 0 || cout > 64 || cin > 64)
         throw Error(-7, "weight gradient needs channel counts that are multiples of 8 up to 64");
     const int64_t nch = nn_bwd_weight_chunks(dout);
-    const dim3 g((unsigned)nch, 27);
+    if (nch > 65535) throw Error(-7, "weight gradient: more than 65535 chunks of 512 voxels");
+    const dim3 g(27, (unsigned)nch);
     const int3 di{din.x, din.y, din.z}, dn{dout.x, dout.y, dout.z};
     const int ntc = (cin + 15) / 16;
     switch ((cout + 15) / 16) {
@@ -871,7 +878,7 @@ void nn_conv_bwd_weight(const uint16_t *G, int cout, Dims dout, const uint16_t *
 
 void nn_bias_grad(const uint16_t *G, int64_t nvox, int cout, float *partial, float *gb, int accumulate, hipStream_t s)
 {
-    const int64_t nch = (nvox + BW_CHUNK - 1) / BW_CHUNK;
+    const int64_t nch = (nvox + BB_CHUNK - 1) / BB_CHUNK;
     k_bias_partial<<<dim3((unsigned)nch), dim3(256), 0, s>>>(G, nvox, cout, partial);
     HTS_LAUNCH_CHECK();
     sum_partials(partial, nch, cout, cout, cout, gb, accumulate, s);
