@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(const uint16_t *__restric
                                                        const float *__restrict__ bias, int cout, int relu,
                                                        const uint16_t *__restrict__ skip,
                                                        uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy,
-                                                       int cs)
+                                                       int cs, int flip)
 {
     extern __shared__ uint4 conv_tile_raw[];
     uint16_t *tile = reinterpret_cast<uint16_t *>(conv_tile_raw);
@@ -225,7 +225,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(const uint16_t *__restric
     for (int kc = 0; kc < kp; kc += 32) {
         const int k0 = kc + 8 * kq;
         const bool kin = k0 < ktot;
-        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+        // flip: the data gradient of a stride-1 convolution, the same
+        // product with every spatial offset mirrored (K index unchanged)
+        const int tq = flip ? 26 - tap : tap;
+        const int dz = tq / 9, dy = (tq / 3) % 3, dx = tq % 3;
         const int toff = (dz * CH_Y + dy) * CH_X + dx;
         bf16x8 bfr[NT];
 #pragma unroll
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(const uint16_t *__restric
                 const int gx = x0 + 1 + vt % CT_X, gy = y0 + 1 + (vt / CT_X) % CT_Y, gz = z0 + 1 + vt / (CT_X * CT_Y);
                 if (gx >= d.x || gy >= d.y || gz >= d.z) continue;
                 const int64_t vo = (int64_t)gx + (int64_t)d.x * (gy + (int64_t)d.y * gz);
-                float y = acc[a][t][j] + bias[co];
+                float y = acc[a][t][j] + (bias ? bias[co] : 0.f);
                 if (relu) y = fmaxf(y, 0.f);
                 if (skip) y += bf2f(skip[vo * cout + co]);
                 if (Yf) Yf[vo * ldy + co] = y;
@@ -327,9 +330,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const uint16_t *__restr
                                                          const uint16_t *__restrict__ X, int cin, int3 din,
                                                          int stride, float *__restrict__ partial, int kp)
 {
-    __shared__ uint16_t gs[4][32][64 + 8];
-    __shared__ uint16_t xs[4][32][64 + 8];
-    __shared__ float red[64][65];
+    // the wave reduction reuses the staging space once the loop has ended
+    // (its last barrier follows the last fragment reads): 36 KB per block
+    __shared__ uint4 bw_smem[2 * 4 * 32 * 72 * 2 / 16];
+    typedef uint16_t Stage[32][64 + 8];
+    Stage *gs = reinterpret_cast<Stage *>(bw_smem);
+    Stage *xs = gs + 4;
+    float(*red)[65] = reinterpret_cast<float(*)[65]>(bw_smem);
+    static_assert(sizeof(float) * 64 * 65 <= sizeof(uint16_t) * 2 * 4 * 32 * 72, "reduction space");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // columns beyond cin / cout of the last 16-wide tile stay zero
     if ((cout | cin) & 15) {
@@ -790,10 +798,10 @@ void nn_conv_fwd(const uint16_t *X, int cin, Dims din, const uint16_t *W, int kp
             const dim3 gt((unsigned)nb);
             const size_t lds = (size_t)CH_V * cs * 2;
             switch (nt) {
-            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
-            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
-            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
-            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs); break;
+            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
+            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
+            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
+            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
             }
             HTS_LAUNCH_CHECK();
             return;
@@ -816,6 +824,27 @@ void nn_conv_bwd_data(const uint16_t *G, int cout, Dims dout, const uint16_t *Wt
     const dim3 g((unsigned)((nin + 63) / 64)), b(256);
     const int3 di{din.x, din.y, din.z}, dn{dout.x, dout.y, dout.z};
     const int nt = (cin + 15) / 16;
+    // stride 1 on large grids: the LDS-tiled forward kernel over g with the
+    // transposed weights and mirrored offsets
+    if (stride == 1 && nin >= 32768 && din.x == dout.x && din.y == dout.y && din.z == dout.z && cout % 8 == 0 &&
+        nt <= 4) {
+        int cs = cout + 8;
+        if ((int64_t)CH_V * cs * 2 > 65536) cs = cout;
+        if ((int64_t)CH_V * cs * 2 <= 65536) {
+            const int64_t nb = (int64_t)((din.x + CT_X - 1) / CT_X) * ((din.y + CT_Y - 1) / CT_Y) *
+                               ((din.z + CT_Z - 1) / CT_Z);
+            const dim3 gt((unsigned)nb);
+            const size_t lds = (size_t)CH_V * cs * 2;
+            switch (nt) {
+            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
+            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
+            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
+            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
+            }
+            HTS_LAUNCH_CHECK();
+            return;
+        }
+    }
     switch (nt) {
     case 1: k_conv_bwd_data<1><<<g, b, 0, s>>>(G, cout, dn, Wt, ktp, cin, di, stride, GX); break;
     case 2: k_conv_bwd_data<2><<<g, b, 0, s>>>(G, cout, dn, Wt, ktp, cin, di, stride, GX); break;

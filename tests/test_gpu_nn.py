@@ -92,6 +92,17 @@ def test_conv_data_gradient_parity(hts, cin, cout, s, din):
     assert np.all(err <= 27 * cout * U32 * cl(bound) + 1e-30), err.max()
 
 
+# Stride 1 on at least 32768 voxels: the data gradient runs as the LDS-tiled
+# forward kernel with mirrored offsets.
+LARGE_DATA = [(16, 16, 1, (41, 33, 25)), (16, 48, 1, (33, 33, 31)), (8, 32, 1, (37, 35, 27)),
+              (48, 16, 1, (34, 33, 30))]
+
+
+@pytest.mark.parametrize("cin,cout,s,din", LARGE_DATA)
+def test_conv_data_gradient_parity_large(hts, cin, cout, s, din):
+    test_conv_data_gradient_parity(hts, cin, cout, s, din)
+
+
 @pytest.mark.parametrize("cin,cout,s,din", CASES + [(16, 16, 1, (33, 21, 9))])
 def test_conv_weight_gradient_parity(hts, cin, cout, s, din):
     print_case("conv bwd weight", cin, cout, s, din)
