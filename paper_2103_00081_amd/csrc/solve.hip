@@ -99,6 +99,8 @@ void Batch::replay(const std::string &key, const std::function<void()> &body)
         HTS_HIP(hipStreamEndCapture(cap, &G.g));
         HTS_HIP(hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0));
         it = graphs.emplace(key, G).first;
+        static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 2.0;
+        if (verbose) std::fprintf(stderr, "[hts] captured graph %zu: %s\n", graphs.size(), key.c_str());
     }
     // replayed on the batch stream itself: ordered with the surrounding work
     // without a cross-stream event pair
@@ -1338,14 +1340,21 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         vreduce(rwk[A.field], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
         outer_check(n, active.p, S.p, redout.p, s);
         HTS_HIP(hipEventRecord(e1, s));
-        outer = get_active();
-        fresh = true;
-        bool any = false;
-        for (int a : outer) any |= a != 0;
-        if (!any) break;
-        fresh = false;
-        for (int i = 0; i < n; i++)
-            if (outer[i]) st.outer[i]++;
+        // The first check is read back with the inner solve's last export
+        // (the inner kernels skip the instances it deactivated), which saves
+        // a host round trip; later checks are read at once.
+        const bool defer = oit == 0 && !learned;
+        const std::vector<int32_t> prev = outer;
+        if (!defer) {
+            outer = get_active();
+            fresh = true;
+            bool any = false;
+            for (int a : outer) any |= a != 0;
+            if (!any) break;
+            fresh = false;
+            for (int i = 0; i < n; i++)
+                if (outer[i]) st.outer[i]++;
+        }
         // inner system: A d = r / ||r||
         hist_tag = oit;
         const double fl = fp32 ? std::pow(std::max(o.inner_rtol, 1e-6), 2) : 0.0;
@@ -1431,6 +1440,18 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         }
         if (exported_last) slots_from_export();
         else download_S();
+        if (defer) {
+            bool any = false;
+            for (int i = 0; i < n; i++) {
+                outer[i] = prev[i] && hS[(size_t)i * NSLOT + S_OSTATUS] == 1.0;
+                any |= outer[i] != 0;
+                if (outer[i]) st.outer[i]++;
+            }
+            if (!any) {
+                fresh = true;   // hS is current: nothing was queued after its export
+                break;
+            }
+        }
         for (int i = 0; i < n; i++)
             if (outer[i]) {
                 st.iters[i] += (int)hS[(size_t)i * NSLOT + S_ITER];
@@ -1631,7 +1652,8 @@ int Batch::step(double dt, const hts_solver_opts &o, std::vector<hts_step_stats>
         vcopy<double>(v, T1.p, Tn.p);
         for (int i = 0; i < n; i++) m[i]->t += dt;
     }
-    export_state();   // completion wait
+    // no wait here: the statistics came from the solvers' exports, and the
+    // caller's scatter of the state waits for the stream
     return rc;
 }
 
