@@ -90,6 +90,7 @@ enum Slot {
     S_C1, S_C2, S_SCALE, S_TNEW, S_DT, S_TMP0, S_TMP1, S_TMP2, S_TMP3,
     // outer (FP64) system of a field solve
     S_OBB = 19, S_OTOL2, S_ORR, S_ONORM, S_OINV, S_OSTATUS, S_FSCALE,
+    S_CYC = 26,                // 1 if the instance takes part in the current FGMRES cycle
     S_CHEB = 28,               // Chebyshev coefficients: 2 per step, up to 16 steps
     NSLOT = 64
 };

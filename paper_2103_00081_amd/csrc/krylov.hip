@@ -11,8 +11,10 @@ namespace {
 __global__ void k_gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_t *kdim)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ninst || !active[i]) return;
+    if (i >= ninst) return;
     double *Si = S + (int64_t)i * NSLOT;
+    Si[S_CYC] = 0.0;
+    if (!active[i]) return;
     const double rr = Si[S_RR];
     kdim[i] = 0;
     if (!isfinite(rr)) {
@@ -25,6 +27,7 @@ __global__ void k_gm_begin(int ninst, int32_t *active, double *S, double *g, int
         active[i] = 0;
         return;
     }
+    Si[S_CYC] = 1.0;
     const double beta = sqrt(rr);
     double *gi = g + (int64_t)i * (mres + 1);
     gi[0] = beta;

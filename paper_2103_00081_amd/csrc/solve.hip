@@ -1201,11 +1201,9 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
         ep.partial = partial.p;
         apply_op<T>(A, EPI_RESID_NORM, true, x, V, ep);
         vreduce(rwk[A.field], partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
+        // which instances take part (S_CYC) is read back with the first
+        // check of the Arnoldi steps, not on its own
         gm_begin(n, active.p, S.p, gg.p, mres, gkdim.p, s);
-        std::vector<int32_t> cyc = get_active();
-        bool any = false;
-        for (int a : cyc) any |= a != 0;
-        if (!any) break;
         vaxpby<T>(v, 1.0, S_SCALE, V, 0.0, -1, V);
         // one Arnoldi step; every kernel skips instances whose cycle ended
         auto step_j = [&](int j) {
@@ -1243,19 +1241,31 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
                 if (!any_active()) break;
                 K = check_every > 1 ? check_every : 2;
             }
-            if (cycle == 0) {
-                slots_from_export();   // the chunk loop ended with an export
-                int used = 0;
-                for (int i = 0; i < n; i++)
-                    if (cyc[i]) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
-                last_iters[hkey] = std::max(1, std::min(used, mres));
-            }
         } else {
             for (int j = 0; j < mres; j++) {
                 step_j(j);
                 if ((j + 1) % std::max(1, check_every) == 0 || j == mres - 1)
                     if (!any_active()) break;
             }
+        }
+        // both loops end with an export
+        slots_from_export();
+        std::vector<int32_t> cyc(n, 0);
+        bool any = false;
+        for (int i = 0; i < n; i++) {
+            cyc[i] = hS[(size_t)i * NSLOT + S_CYC] == 1.0;
+            any |= cyc[i] != 0;
+        }
+        if (!any) break;
+        if (use_graph && !g_timing.on && cycle == 0) {
+            char key[256];
+            std::snprintf(key, sizeof key, "gm%d|%d|%p|%p|%p|%d|%d", (int)sizeof(T), A.field, (const void *)&A,
+                          (const void *)b, (const void *)x, maxit, mres);
+            const std::string hkey = std::string(key) + "|" + graph_tag + "|o" + std::to_string(hist_tag);
+            int used = 0;
+            for (int i = 0; i < n; i++)
+                if (cyc[i]) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
+            last_iters[hkey] = std::max(1, std::min(used, mres));
         }
         // x += Z y for every instance that took part in this cycle (neither
         // kernel writes the slots, so the export that ended the Arnoldi steps
