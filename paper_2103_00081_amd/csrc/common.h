@@ -44,6 +44,22 @@ struct LineEnt {
     double w;                  // int N_a N_b dz / L along the line
 };
 
+// The same operator for Q1 meshes, laid out for the owner of a node: per node
+// column the rows of planes kmin .. kmax are dense from index first (first < 0:
+// no line rows); each row lists its entries by offset from the row's node
+// (-1..1 per axis), so the kernel reads the operand from its staged planes.
+constexpr int LINE_MAXE = 16;
+struct LineCol {
+    int32_t first, kmin, kmax, pad;
+};
+struct LineFlat {
+    int32_t n;                 // entries (0: no row on this plane)
+    int32_t row_constrained;
+    uint8_t off[LINE_MAXE];    // (dx + 1) | (dy + 1) << 2 | (dk + 1) << 4
+    int32_t src[LINE_MAXE];    // line source index (coefficient slot)
+    double w[LINE_MAXE];
+};
+
 // Per-instance operator descriptor consumed by the apply kernels.
 struct OpDev {
     int32_t nx, ny, nz;        // cells
@@ -63,6 +79,8 @@ struct OpDev {
     const int32_t *lcol;       // [NX*NY] first LineRow of the column or -1; null = none
     const LineRow *lrows;
     const LineEnt *lents;
+    const LineCol *lfcol;      // [NX*NY] (Q1) dense per-column rows, or null
+    const LineFlat *lflat;
     const double *lcoef;       // per line source: dt c_w max(Q,0)/L at t^{n+1}
     int64_t off;               // offset of the instance in batch node vectors
     int64_t nnode;

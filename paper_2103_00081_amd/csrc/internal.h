@@ -166,6 +166,8 @@ struct hts_mesh {
     hts::DBuf<int32_t> lcol;
     hts::DBuf<hts::LineRow> lrows;
     hts::DBuf<hts::LineEnt> lents;
+    hts::DBuf<hts::LineCol> lfcol;           // Q1: rows by column and plane (LineFlat)
+    hts::DBuf<hts::LineFlat> lflat;
     std::vector<hts::SrcDev> line_srcs;      // coefficient sources (instance-local)
     bool has_lineop = false;
     // time-dependent sources per field

@@ -238,6 +238,7 @@ static void build_line_operator(hts_mesh *m)
     m->has_lineop = !rows.empty();
     if (!m->has_lineop) {
         m->lcol.release(); m->lrows.release(); m->lents.release();
+        m->lfcol.release(); m->lflat.release();
         return;
     }
     std::vector<int32_t> lcol((size_t)m->N[0] * m->N[1], -1);
@@ -263,6 +264,49 @@ static void build_line_operator(hts_mesh *m)
         r.end = (int32_t)le.size();
         if (lcol[r.col] < 0) lcol[r.col] = (int32_t)lr.size();
         lr.push_back(r);
+    }
+    // Q1: the same rows by column and plane with entries as node offsets
+    // (all within one node along each axis for Q1 lines); kept only when
+    // every row fits LINE_MAXE entries
+    m->lfcol.release();
+    m->lflat.release();
+    if (p == 1) {
+        std::vector<LineCol> hdr((size_t)m->N[0] * m->N[1], LineCol{-1, 0, -1, 0});
+        std::vector<LineFlat> flat;
+        bool ok = true;
+        for (size_t a = 0; a < lr.size() && ok;) {
+            size_t b = a;
+            while (b < lr.size() && lr[b].col == lr[a].col) b++;
+            LineCol &h = hdr[lr[a].col];
+            h.first = (int32_t)flat.size();
+            h.kmin = lr[a].k;
+            h.kmax = lr[b - 1].k;
+            flat.resize(flat.size() + (size_t)(h.kmax - h.kmin + 1));
+            const int i = lr[a].col % m->N[0], j = lr[a].col / m->N[0];
+            for (size_t r = a; r < b && ok; r++) {
+                LineFlat &f = flat[(size_t)h.first + (lr[r].k - h.kmin)];
+                f.row_constrained = lr[r].row_constrained;
+                for (int e = lr[r].beg; e < lr[r].end; e++) {
+                    const int64_t c = le[e].col;
+                    const int ci = (int)(c % m->N[0]), cj = (int)((c / m->N[0]) % m->N[1]),
+                              ck = (int)(c / ((int64_t)m->N[0] * m->N[1]));
+                    const int dx = ci - i, dy = cj - j, dk = ck - lr[r].k;
+                    if (f.n >= LINE_MAXE || dx < -1 || dx > 1 || dy < -1 || dy > 1 || dk < -1 || dk > 1) {
+                        ok = false;
+                        break;
+                    }
+                    f.off[f.n] = (uint8_t)((dx + 1) | (dy + 1) << 2 | (dk + 1) << 4);
+                    f.src[f.n] = le[e].src;
+                    f.w[f.n] = le[e].w;
+                    f.n++;
+                }
+            }
+            a = b;
+        }
+        if (ok) {
+            m->lfcol.upload(&m->alloc, hdr, m->stream);
+            m->lflat.upload(&m->alloc, flat, m->stream);
+        }
     }
     LineRow sent{};
     sent.col = -1;
@@ -384,6 +428,8 @@ OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, b
     o.lcol = (field == 1 && m->has_lineop && !mass_only) ? m->lcol.p : nullptr;
     o.lrows = m->lrows.p;
     o.lents = m->lents.p;
+    o.lfcol = (o.lcol && m->lfcol.p) ? m->lfcol.p : nullptr;
+    o.lflat = m->lflat.p;
     o.lcoef = nullptr;
     return o;
 }

@@ -144,7 +144,10 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     //   corner sums of each cell layer in a 2-deep ring; the global loads of
     //   plane L+2, of the coefficients of layer L+1 and of the epilogue
     //   operands of plane L are issued one iteration before they are used.
-    __shared__ T xs[3][TB + 1][TB + 2];
+    // heat: a 5-deep x ring, so that the epilogue of plane P can read planes
+    // P-1 .. P+1 of the injection-line rows while the next plane is stored
+    constexpr int XR = FIELD ? 5 : 3;
+    __shared__ T xs[XR][TB + 1][TB + 2];
     __shared__ T ps[FIELD ? 3 : 1][TB + 1][TB + 2];
     __shared__ T S4[2][4][TB][TB + 1];
     __shared__ double red[4];
@@ -189,7 +192,14 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     ColInfo oc = col_info(o, oi, oj);
     const bool own_ok = owner && oc.valid;
     int lr = -1;
-    if (FIELD && o.lcol && own_ok) lr = gptr<int32_t>(o.lcol)[oc.base];
+    LineCol lh{-1, 0, -1, 0};
+    if (FIELD && o.lfcol && own_ok) {
+        const LineCol HTS_GLOBAL *hp = gptr<LineCol>(o.lfcol) + oc.base;
+        lh.first = hp->first;
+        lh.kmin = hp->kmin;
+        lh.kmax = hp->kmax;
+    }
+    if (FIELD && !o.lfcol && o.lcol && own_ok) lr = gptr<int32_t>(o.lcol)[oc.base];
 
     // per-cell coefficient factors of the unscaled 1D products (in double,
     // then rounded once)
@@ -230,11 +240,11 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         }
     };
     auto store_plane = [&](int k) {
-        const int b = (k + 3) % 3;
+        const int b = (k + 3) % 3, bx = (k + XR) % XR;
 #pragma unroll
         for (int s = 0; s < 2; s++) {
             if (!ld[s]) continue;
-            xs[b][lj[s]][li[s]] = pkeep[s] ? pfx[s] : T(0);
+            xs[bx][lj[s]][li[s]] = pkeep[s] ? pfx[s] : T(0);
             if (FIELD) ps[FIELD ? b : 0][lj[s]][li[s]] = (lc[s].valid && k >= 0 && k < NZ) ? pfp[s] : T(0);
         }
     };
@@ -279,6 +289,22 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
             const int P0 = L - 1, sb = P0 & 1;
             T v = S4[sb][3][ty][tx] + S4[sb][2][ty][tx + 1] + S4[sb][1][ty + 1][tx] + S4[sb][0][ty + 1][tx + 1];
             const int64_t gi = oc.base + (int64_t)P0 * plane;
+            if (FIELD && lh.first >= 0 && P0 >= lh.kmin && P0 <= lh.kmax) {
+                // injection-line row: operand values from the staged planes
+                const LineFlat HTS_GLOBAL &R = gptr<LineFlat>(o.lflat)[lh.first + (P0 - lh.kmin)];
+                const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
+                const int ne = R.n;
+                if (ne > 0 && !(MASKED && R.row_constrained)) {
+                    T la = T(0);
+                    for (int e = 0; e < ne; e++) {
+                        const int of = R.off[e];
+                        const int dx = (of & 3) - 1, dy = ((of >> 2) & 3) - 1, dk = ((of >> 4) & 3) - 1;
+                        const T xc = xs[(P0 + dk + XR) % XR][ty + 1 + dy][tx + 1 + dx];
+                        la += T(lco[R.src[e]] * R.w[e]) * xc;
+                    }
+                    v += la;
+                }
+            }
             if (FIELD && lr >= 0) {
                 const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
                 const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
@@ -326,11 +352,12 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         T bot[4] = {T(0), T(0), T(0), T(0)}, tp[4] = {T(0), T(0), T(0), T(0)};
         if (lay) {
             const int b0 = (L + 3) % 3, b1 = (L + 4) % 3;
+            const int x0 = (L + XR) % XR, x1 = (L + 1 + XR) % XR;
             T u[8], w[8];
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                u[a] = xs[b0][ty + (a >> 1)][tx + (a & 1)];
-                u[a + 4] = xs[b1][ty + (a >> 1)][tx + (a & 1)];
+                u[a] = xs[x0][ty + (a >> 1)][tx + (a & 1)];
+                u[a + 4] = xs[x1][ty + (a >> 1)][tx + (a & 1)];
             }
             if (FIELD == 0) {
                 cell_mass_stiff(u, cm * fm, ck * fx, ck * fy, ck * fz, w);

@@ -1,6 +1,7 @@
 // Batches of instances, the multigrid hierarchy, the Krylov solvers and the
 // backward-Euler time step (Section 2: P^{n+1} from Eq. 3, then T^{n+1}
 // from Eq. 4 with the Darcy flux of P^{n+1}).
+#include <cctype>
 #include <cstdio>
 #include <algorithm>
 #include <chrono>
@@ -131,7 +132,10 @@ void tune_load()
     if (!f) return;
     char key[96];
     int v;
-    // entries look like  "q1_f0_129x129x65": 8
+    // {"q1_f0_129x129x65": 8, ...}: skip the opening brace first
+    int c0 = fgetc(f);
+    while (c0 != EOF && isspace(c0)) c0 = fgetc(f);
+    if (c0 != '{' && c0 != EOF) ungetc(c0, f);
     while (fscanf(f, " \"%95[^\"]\" : %d", key, &v) == 2) {
         g_tune[key] = v;
         int c = fgetc(f);
@@ -918,6 +922,7 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
                     q1.NX = cN[0]; q1.NY = cN[1]; q1.NZ = cN[2];
                     q1.nnode = ccnt[i];
                     q1.lcol = nullptr;
+                    q1.lfcol = nullptr;
                     q1.dcol = nullptr;
                     const std::vector<int32_t> &fd = m[i]->h_dcol[H.field];
                     if (!fd.empty()) {
