@@ -120,7 +120,10 @@ typedef struct {
     int32_t max_iter;        /* Krylov iterations per solve (inner, total)      */
     int32_t gmres_restart;   /* FGMRES restart length (30)                      */
     int32_t cheb_degree;     /* Chebyshev smoothing degree per side (2)         */
-    int32_t mg_coarse_max;   /* coarsen until a level has <= this many nodes    */
+    int32_t mg_coarse_max;   /* coarsen each instance until a level has <= this
+                                many nodes; that level is solved with a dense
+                                FP64 inverse (n^2 entries, read whole by every
+                                coarse solve)                                 */
     int32_t heat_cheb_degree;/* degree of the heat Chebyshev-Jacobi preconditioner */
     double inner_rtol;       /* inner tolerance of FP32_REFINED (1e-4)          */
     int32_t check_every;     /* host convergence check every n iterations (1)   */
@@ -247,7 +250,11 @@ hts_status hts_solve_step(hts_mesh *mesh, double dt, const hts_solver_opts *opts
  * convergence state.  stats: [n_instances] (last step), may be NULL.
  * With opts->use_graph the per-step launch sequence is captured once and
  * replayed.  Stops at the first failing step (those instances are not
- * advanced past it). */
+ * advanced past it).  The batch (work lists, multigrid hierarchies, dense
+ * coarse inverses, captured graphs) is kept for the next call with the same
+ * meshes in the same order, up to four such sets; changing a mesh's
+ * materials or boundary data, autotuning or destroying it drops them.
+ * Each mesh may appear once. */
 hts_status hts_advance(hts_mesh *const *meshes, int32_t n_instances, int32_t n_steps, double dt,
                        const hts_solver_opts *opts, hts_step_stats *stats);
 

@@ -176,7 +176,7 @@ struct hts_mesh {
     // heat: sum_c f_c int N (scaled by dt)
     hts::DBuf<double> load[2];
 
-    std::map<std::string, std::shared_ptr<hts::Batch>> batches;   // cached solo batches
+    std::map<std::string, std::shared_ptr<hts::Batch>> batches;   // cached solo batch
 
     // learned-preconditioner inputs: normalised node log-permeability and
     // the pressure Dirichlet mask (rebuilt after prepare_mesh)
@@ -189,6 +189,7 @@ struct hts_mesh {
 namespace hts {
 
 void prepare_mesh(hts_mesh *m);                 // (re)build derived device data
+void forget_batches(hts_mesh *m);               // drop every cached batch that holds m (solve.hip)
 bool is_constrained(const hts_mesh *m, int field, int i, int j, int k);   // host, after prepare_mesh
 OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, bool mass_only);
 

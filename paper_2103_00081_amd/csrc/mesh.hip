@@ -393,7 +393,7 @@ void prepare_mesh(hts_mesh *m)
         }
         HTS_HIP(hipStreamSynchronize(m->stream));
     }
-    m->batches.clear();
+    forget_batches(m);
     m->dirty = false;
     m->nn_ready = false;
 }
@@ -501,6 +501,10 @@ void hts_destroy_mesh(hts_mesh *m)
 {
     if (!m) return;
     (void)hipStreamSynchronize(m->stream);
+    try {
+        forget_batches(m);
+    } catch (...) {
+    }
     delete m;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 #include <functional>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <vector>
 
@@ -136,7 +137,8 @@ struct Batch {
     int app_field = -1;
     double app_dt = -1.0;
     bool app_steady = false;
-    std::map<std::pair<int, double>, std::unique_ptr<Hier>> hier;
+    // pressure hierarchies by (steady, dt, smoothing degree, coarse-level cap)
+    std::map<std::tuple<int, double, int, int>, std::unique_ptr<Hier>> hier;
     std::unique_ptr<Hier> heat;
 
     // observers used to harvest training pairs for the learned preconditioner:
@@ -231,5 +233,7 @@ int tuned_zc(int degree, int field, int NX, int NY, int NZ);
 void set_tuned_zc(int degree, int field, int NX, int NY, int NZ, int zc);
 void save_tuning();
 std::shared_ptr<Batch> solo_batch(hts_mesh *m);
+// cached batch of several meshes (same meshes, same order)
+std::shared_ptr<Batch> multi_batch(const std::vector<hts_mesh *> &ms);
 
 }  // namespace hts

@@ -14,6 +14,8 @@
 #include "solve.h"
 
 #include <atomic>
+#include <mutex>
+#include <thread>
 
 namespace hts {
 
@@ -556,6 +558,58 @@ static void invert_dense(std::vector<double> &A, int n)
     A.swap(I);
 }
 
+// Inverse of a symmetric positive definite 27-point operator in lexicographic
+// order (bandwidth bw = NX NY + NX + 1) from its banded Cholesky factor:
+// A = L L^T costs n bw^2 / 2, then column j of A^-1 is L^-T L^-1 e_j, the
+// columns split over host threads.  Returns false (A untouched) when a pivot
+// is not positive, i.e. the operator is not SPD.
+static bool invert_spd_banded(std::vector<double> &A, int n, int bw)
+{
+    bw = std::min(bw, n - 1);
+    const size_t W = (size_t)bw + 1;
+    std::vector<double> L((size_t)n * W, 0.0);   // L[i][j] at L[i*W + (i - j)], i - bw <= j <= i
+    auto l = [&](int i, int j) -> double & { return L[(size_t)i * W + (size_t)(i - j)]; };
+    for (int i = 0; i < n; i++) {
+        const int j0 = std::max(0, i - bw);
+        for (int j = j0; j <= i; j++) {
+            double s = A[(size_t)i * n + j];
+            for (int k = std::max(j0, j - bw); k < j; k++) s -= l(i, k) * l(j, k);
+            if (j == i) {
+                if (!(s > 0.0)) return false;
+                l(i, i) = std::sqrt(s);
+            } else {
+                l(i, j) = s / l(j, j);
+            }
+        }
+    }
+    const int nt = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+    std::atomic<int> next(0);
+    auto work = [&]() {
+        std::vector<double> y(n);
+        for (int j; (j = next.fetch_add(1)) < n;) {
+            for (int i = 0; i < j; i++) y[i] = 0.0;
+            for (int i = j; i < n; i++) {
+                double s = i == j ? 1.0 : 0.0;
+                for (int k = std::max(j, i - bw); k < i; k++) s -= l(i, k) * y[k];
+                y[i] = s / l(i, i);
+            }
+            for (int i = n - 1; i >= 0; i--) {
+                double s = y[i];
+                const int k1 = std::min(n - 1, i + bw);
+                for (int k = i + 1; k <= k1; k++) s -= l(k, i) * y[k];
+                y[i] = s / l(i, i);
+            }
+            // A^-1 is symmetric: column j is row j
+            std::copy(y.begin(), y.end(), A.begin() + (size_t)j * n);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; t++) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+    return true;
+}
+
 static void cheb_coeffs(double lmax_est, double ratio, int steps, double *out /* 2*steps */)
 {
     static const double safety = env_or("HTS_LMAX_SAFETY", 1.1);
@@ -634,12 +688,13 @@ void Batch::build_smoother(Hier &H, int l, int steps, double ratio)
 
 Hier &Batch::pressure_hier(bool steady, double dt, const hts_solver_opts &o)
 {
-    auto key = std::make_pair(steady ? 1 : 0, steady ? 0.0 : dt);
+    const int deg = std::max(1, std::min(o.cheb_degree, 8));
+    auto key = std::make_tuple(steady ? 1 : 0, steady ? 0.0 : dt, deg, o.mg_coarse_max);
     auto it = hier.find(key);
     if (it != hier.end()) return *it->second;
     auto H = std::make_unique<Hier>();
     H->field = 0;
-    H->deg = std::max(1, std::min(o.cheb_degree, 8));
+    H->deg = deg;
     H->ratio = env_or("HTS_P_RATIO", 15.0);
     H->ratio_coarse = env_or("HTS_P_RATIO", 15.0);
     make_tables(H->ops, 0, dt, steady, false);
@@ -982,7 +1037,7 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
                     A[(size_t)r * nn + a + (int64_t)NX * (b + (int64_t)NY * d)] += st[(size_t)c * nn + r];
                 }
             }
-            invert_dense(A, (int)nn);
+            if (!invert_spd_banded(A, (int)nn, NX * NY + NX + 1)) invert_dense(A, (int)nn);
             C.Ainv.emplace_back();
             C.Ainv.back().upload(al, A, s);
             CoarseDev e{};
@@ -1682,6 +1737,64 @@ std::shared_ptr<Batch> solo_batch(hts_mesh *m)
     return B;
 }
 
+// Batches of several meshes, kept for the next call with the same meshes in
+// the same order (hierarchies, dense coarse inverses, captured graphs and
+// iteration history survive between calls); the four most recent are kept.
+namespace {
+struct MultiEntry {
+    std::vector<hts_mesh *> ms;
+    std::shared_ptr<Batch> B;
+};
+std::mutex g_multi_mu;
+std::vector<MultiEntry> g_multi;
+constexpr size_t MULTI_KEEP = 4;
+}  // namespace
+
+std::shared_ptr<Batch> multi_batch(const std::vector<hts_mesh *> &ms)
+{
+    for (hts_mesh *m : ms) prepare_mesh(m);
+    {
+        std::lock_guard<std::mutex> lk(g_multi_mu);
+        for (size_t i = 0; i < g_multi.size(); i++)
+            if (g_multi[i].ms == ms) {
+                MultiEntry e = std::move(g_multi[i]);
+                g_multi.erase(g_multi.begin() + (long)i);
+                g_multi.push_back(std::move(e));
+                return g_multi.back().B;
+            }
+    }
+    auto B = build_batch(ms);
+    std::shared_ptr<Batch> old;
+    {
+        std::lock_guard<std::mutex> lk(g_multi_mu);
+        if (g_multi.size() >= MULTI_KEEP) {
+            old = std::move(g_multi.front().B);
+            g_multi.erase(g_multi.begin());
+        }
+        g_multi.push_back({ms, B});
+    }
+    return B;
+}
+
+void forget_batches(hts_mesh *m)
+{
+    m->batches.clear();
+    std::vector<std::shared_ptr<Batch>> drop;
+    {
+        std::lock_guard<std::mutex> lk(g_multi_mu);
+        for (size_t i = 0; i < g_multi.size();) {
+            if (std::find(g_multi[i].ms.begin(), g_multi[i].ms.end(), m) != g_multi[i].ms.end()) {
+                drop.push_back(std::move(g_multi[i].B));
+                g_multi.erase(g_multi.begin() + (long)i);
+            } else {
+                i++;
+            }
+        }
+    }
+    for (auto &B : drop)
+        if (B) (void)hipStreamSynchronize(B->s);
+}
+
 template void Batch::vcycle<double>(Hier &, int, const double *, double *);
 template void Batch::vcycle<float>(Hier &, int, const float *, float *);
 
@@ -1836,7 +1949,7 @@ hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
             (void)hipEventDestroy(e1);
         }
         save_tuning();
-        for (int i = 0; i < n; i++) meshes[i]->batches.clear();
+        for (int i = 0; i < n; i++) forget_batches(meshes[i]);
     });
 }
 
@@ -1891,9 +2004,14 @@ hts_status hts_advance(hts_mesh *const *meshes, int32_t n, int32_t n_steps, doub
         if (!(dt > 0.0)) throw Error(HTS_ERR_ARG, "dt must be > 0");
         std::vector<hts_mesh *> ms(meshes, meshes + n);
         for (hts_mesh *m : ms) check_ready(m);
+        {
+            std::vector<hts_mesh *> u = ms;
+            std::sort(u.begin(), u.end());
+            if (std::adjacent_find(u.begin(), u.end()) != u.end()) throw Error(HTS_ERR_ARG, "a mesh appears twice");
+        }
         HTS_HIP(hipSetDevice(ms[0]->desc.device));
         hts_solver_opts o = opts_or_default(opts);
-        std::shared_ptr<Batch> B = n == 1 ? solo_batch(ms[0]) : build_batch(ms);
+        std::shared_ptr<Batch> B = n == 1 ? solo_batch(ms[0]) : multi_batch(ms);
         B->gather_state();
         std::vector<hts_step_stats> st;
         int rc = HTS_OK;
