@@ -1,6 +1,12 @@
-"""Benchmark: MDoF-steps/s at 1e-8 relative residual on the layered-aquifer
-workload (500 x 500 x 100 m, 128 x 128 x 64 Q1 cells, 1,081,665 nodes per
-field, injection/extraction well pair, daily backward-Euler steps).
+"""Benchmark: MDoF-steps/s at 1e-8 relative residual.
+
+Default workload: the layered aquifer (500 x 500 x 100 m, 128 x 128 x 64 Q1
+cells, 1,081,665 nodes per field, injection/extraction well pair, daily
+backward-Euler steps).  --workload selects the others: the energy-pile field
+on 256 x 256 x 128 Q1 or 128 x 128 x 64 Q2 cells (8,520,321 nodes per field),
+the island-style pile field with site boundary data (256 x 160 x 64 Q1), and
+64 batched design instances of 32^3..96^3 cells advanced together (set
+against a host loop over the instances one at a time).
 
 A step is one backward-Euler step of the whole path: pressure right-hand
 side, multigrid-preconditioned CG for Eq. 3, heat right-hand side with the
@@ -57,7 +63,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--modes", default="fp64,fp32_refined",
                     help="comma list of fp64, fp32_refined; the faster one is the headline")
-    ap.add_argument("--ncells", default="128,128,64")
+    ap.add_argument("--workload", default="aquifer", choices=("aquifer", "piles", "piles-q2", "island", "batch"))
+    ap.add_argument("--ncells", default=None, help="cells per axis, e.g. 128,128,64 (default: the workload's)")
+    ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
+    ap.add_argument("--host-loop", type=int, default=1,
+                    help="batch workload: also time a host loop advancing the instances one at a time")
+    ap.add_argument("--operators", type=int, default=0,
+                    help="also time every fine-level operator class on the 256x256x128 Q1 and 128x128x64 "
+                         "Q2 pile-field meshes, cycling 4 (x, y) buffer pairs (beyond the 256 MB last-level "
+                         "cache)")
     ap.add_argument("--cpu-steps", type=int, default=5,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -66,8 +80,9 @@ def parse():
     ap.add_argument("--heat-cheb", type=int, default=2, help="heat Chebyshev-Jacobi degree")
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--mg-coarse-max", type=int, default=5000,
-                    help="coarsen until a level has at most this many nodes (dense FP64 solve there)")
+    ap.add_argument("--mg-coarse-max", type=int, default=None,
+                    help="coarsen until a level has at most this many nodes (dense FP64 solve there); "
+                         "default 5000 for one mesh, 600 per instance for the batch")
     ap.add_argument("--heat-precond", type=int, default=1, help="0 multigrid, 1 Chebyshev-Jacobi, 2 separable mass")
     ap.add_argument("--use-graph", type=int, default=1,
                     help="replay captured HIP graphs for the Krylov iteration chunks (1) or launch eagerly (0)")
@@ -135,6 +150,75 @@ def learned_leg(a, hts, synth, nc, np, torch):
     return out
 
 
+def note(msg):
+    """Progress of the long set-up phases, on stderr (the JSON line goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def workload(a, synth, n_steps):
+    """Scenarios of the selected workload and a description of it."""
+    nc = tuple(int(v) for v in a.ncells.split(",")) if a.ncells else None
+    if a.workload == "aquifer":
+        nc = nc or (128, 128, 64)
+        return [synth.config2(ncells=nc, n_steps=n_steps)], 2, \
+            "layered aquifer %dx%dx%d Q1 (%%d nodes/field), well pair" % nc
+    if a.workload in ("piles", "piles-q2"):
+        p = 1 if a.workload == "piles" else 2
+        nc = nc or ((256, 256, 128) if p == 1 else (128, 128, 64))
+        return [synth.config3(degree=p, ncells=nc, n_steps=n_steps)], 3, \
+            "energy-pile field %dx%dx%d Q%d (%%d nodes/field), 400 seasonal line heat sources, " \
+            "regional gradient" % (nc + (p,))
+    if a.workload == "island":
+        nc = nc or (256, 160, 64)
+        s = synth.island(ncells=nc, n_steps=n_steps)
+        return [s], 6, ("island-style pile field %dx%dx%d Q1 (%%d nodes/field), %d square-wave piles, "
+                         "seasonal surface, geothermal inflow" % (nc + (len(s.dir_columns),)))
+    scns = [synth.config4_instance(i, n_override=(nc[0] if nc else None), n_steps=n_steps)
+            for i in range(a.instances)]
+    return scns, 4000, ("%d batched design instances, 32^3..96^3 Q1 cells (%%d nodes/field in total), "
+                        "10-200 Dirichlet pile columns each" % a.instances)
+
+
+def time_operators(hts, synth, np, torch):
+    """Fine-level operator classes on the pile-field meshes (8.5 M nodes per
+    field): 4 rotating (x, y) buffer pairs so every apply streams from HBM;
+    device time of the apply kernel alone (events around each launch)."""
+    out = {}
+    for p, nc in ((1, (256, 256, 128)), (2, (128, 128, 64))):
+        scn = synth.config3(degree=p, ncells=nc, n_steps=1)
+        m = hts.from_scenario(scn, initial=False)
+        hts.autotune([m])
+        n = m.nnode
+        rng = np.random.default_rng(1)
+        X = np.linspace(0.0, 1000.0, n)
+        m.set_state(0, 1e5 + 9810.0 * rng.uniform(0, 200, n) - 3.0 * X, scn.t0)
+        for field in (0, 1):
+            for prec, dt in ((0, torch.float64), (1, torch.float32)):
+                if p == 2 and prec == 1:
+                    continue
+                xs = [torch.randn(n, dtype=dt, device="cuda") for _ in range(4)]
+                ys = [torch.zeros(n, dtype=dt, device="cuda") for _ in range(4)]
+                for r in range(4):
+                    m.apply_operator(field, prec, scn.dt, xs[r], ys[r])
+                torch.cuda.synchronize()
+                hts.kernel_timing_start()
+                for r in range(40):
+                    m.apply_operator(field, prec, scn.dt, xs[r % 4], ys[r % 4])
+                torch.cuda.synchronize()
+                k = hts.kernel_timing_stop()[(field, prec)]
+                us = 1e3 * k["ms"] / k["launches"]
+                gbs = k["bytes"] / k["launches"] / (us * 1e-6) / 1e9
+                name = "Q%d %s %s" % (p, ["pressure", "heat"][field], ["FP64", "FP32"][prec])
+                out[name] = {"us": round(us, 2), "bytes": k["bytes"] / k["launches"],
+                             "GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                             "flop_frac": round(k["flops"] / k["launches"] / (us * 1e-6) / 1e12 /
+                                                (PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_TFLOPS), 4)}
+                del xs, ys
+        del m
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -155,38 +239,66 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    nc = tuple(int(v) for v in a.ncells.split(","))
-    scn = synth.config2(ncells=nc, n_steps=a.warmup + a.steps + max(1, a.timing_steps))
+    batch = a.workload == "batch"
+    if a.mg_coarse_max is None:
+        a.mg_coarse_max = 600 if batch else 5000
+    scns, seed, wdesc = workload(a, synth, a.warmup + a.steps + max(1, a.timing_steps))
+    dt = scns[0].dt
     modes = [m.strip() for m in a.modes.split(",") if m.strip()]
     mode_id = {"fp64": hts.MODE_FP64, "fp32_refined": hts.MODE_FP32_REFINED}
     results = {}
+    t_setup0 = time.perf_counter()
     for mode in modes:
         o = hts.default_opts(mode=mode_id[mode], rtol=1e-8, check_every=a.check_every,
                              cheb_degree=a.cheb, heat_cheb_degree=a.heat_cheb,
                              inner_rtol=a.inner_rtol, heat_precond=a.heat_precond,
                              use_graph=a.use_graph, mg_coarse_max=a.mg_coarse_max)
-        m = hts.from_scenario(scn, opts=o)
+        ms = []
+        for i, sc in enumerate(scns):
+            ms.append(hts.from_scenario(sc, opts=o))
+            if len(scns) > 1 and (i % 8 == 7 or i == len(scns) - 1):
+                note("%s: %d of %d instances set up" % (mode, i + 1, len(scns)))
         if not a.no_autotune:
-            hts.autotune([m])        # setup: picks the kernels' z-chunk depth
-        for _ in range(a.warmup):
-            m.solve_step(scn.dt, o)
+            # setup: picks the kernels' z-chunk depth per mesh shape
+            for i in range(0, len(ms), 8):
+                hts.autotune(ms[i:i + 8])
+                if len(ms) > 8:
+                    note("%s: autotuned %d of %d" % (mode, min(i + 8, len(ms)), len(ms)))
+        t_setup = time.perf_counter() - t_setup0
+        note("%s: set up in %.1f s" % (mode, t_setup))
+
+        def step(k):
+            if batch:
+                return hts.advance(ms, k, dt, o)[1]
+            return [ms[0].solve_step(dt, o)[1] for _ in range(k)]
+
+        if a.warmup:
+            step(a.warmup)
         torch.cuda.synchronize()
-        iters = []
         t0 = time.perf_counter()
-        for _ in range(a.steps):
-            code, st = m.solve_step(scn.dt, o)
-            iters.append(st)
+        iters = step(a.steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        note("%s: %d timed steps in %.3f s" % (mode, a.steps, t1 - t0))
         # per-launch kernel times (events around every fine-level operator
         # launch force eager launches, so they are taken after the timed region)
         hts.kernel_timing_start()
-        for _ in range(max(1, a.timing_steps)):
-            m.solve_step(scn.dt, o)
+        step(max(1, a.timing_steps))
         torch.cuda.synchronize()
         kt = hts.kernel_timing_stop()
         dt_s = t1 - t0
-        dofs = 2 * m.nnode
+        dofs = 2 * sum(m.nnode for m in ms)
+        host = None
+        if batch and a.host_loop:
+            h0 = time.perf_counter()
+            for _ in range(a.steps):
+                for m in ms:
+                    hts.advance([m], 1, dt, o)
+            torch.cuda.synchronize()
+            h1 = time.perf_counter()
+            note("%s: host loop, %d steps in %.3f s" % (mode, a.steps, h1 - h0))
+            host = {"value": round(dofs * a.steps / (h1 - h0) / 1e6, 3),
+                    "ms_per_step": round(1e3 * (h1 - h0) / a.steps, 3)}
         results[mode] = {
             "value": dofs * a.steps / dt_s / 1e6,
             "ms_per_step": 1e3 * dt_s / a.steps,
@@ -198,14 +310,18 @@ def main():
             "relres_max": float(max(max(s["relres"]) for s in iters)),
             "ms_p": float(np.mean([s["time_ms"][0] for s in iters])),
             "ms_h": float(np.mean([s["time_ms"][1] for s in iters])),
-            "nnode": m.nnode,
+            "nnode": sum(m.nnode for m in ms),
+            "setup_s": t_setup,
+            "host_loop": host,
         }
-        del m
+        del ms
         torch.cuda.synchronize()
+        t_setup0 = time.perf_counter()
 
     learned = None
-    if a.learned:
-        learned = learned_leg(a, hts, synth, nc, np, torch)
+    if a.learned and a.workload == "aquifer":
+        learned = learned_leg(a, hts, synth, scns[0].ncells, np, torch)
+    operators = time_operators(hts, synth, np, torch) if a.operators else None
 
     best = max(results, key=lambda k: results[k]["value"])
     R = results[best]
@@ -224,7 +340,7 @@ def main():
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
-        "traffic": measured_traffic(names[key], nc),
+        "traffic": measured_traffic(names[key], scns[0].ncells) if a.workload == "aquifer" else None,
         "launches": k["launches"],
         "avg_us": round(1e3 * avg_ms, 2),
         "alu_tflops": round((k["flops"] / max(1, k["launches"])) / (avg_ms * 1e-3) / 1e12, 2),
@@ -234,10 +350,9 @@ def main():
     cpu = None
     if not a.no_cpu and a.cpu_steps > 0:
         import oracle
+        scn = scns[0]
         om = oracle.Mesh.of(scn)
-        X, Y, Z = om.coords()
-        P = oracle.tf_value(scn.P0, X, Y, Z, scn.t0) * np.ones(om.nnode)
-        T = oracle.tf_value(scn.T0, X, Y, Z, scn.t0) * np.ones(om.nnode)
+        P, T = oracle.initial_state(scn, om)
         t = scn.t0
         c0 = time.perf_counter()
         for _ in range(a.cpu_steps):
@@ -246,9 +361,10 @@ def main():
         cpu = {"value": round(2 * om.nnode * a.cpu_steps / (c1 - c0) / 1e6, 4),
                "unit": "MDoF-steps/s", "cores": int(oracle.lib().orc_num_threads()),
                "kind": "oracle",
-               "sample": "first %d steps of the same workload at full size: CSR assembly "
+               "sample": "first %d steps of %s at full size: CSR assembly "
                          "+ Jacobi-PCG (pressure) and Jacobi-GMRES(50) (heat) to 1e-8, "
-                         "%.1f s" % (a.cpu_steps, c1 - c0)}
+                         "%.1f s" % (a.cpu_steps, "the same workload" if not batch else
+                                     "instance 0 of the same workload", c1 - c0)}
 
     dtype = "f64" if best == "fp64" else "f32+f64"
     line = {
@@ -264,9 +380,8 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "layered aquifer %dx%dx%d Q1 (%d nodes/field), well pair, "
-                               "dt = 1 day, rtol 1e-8, mode %s" % (nc + (R["nnode"], best)),
-                   "seed": 2, "cheb_degree": a.cheb, "heat_cheb_degree": a.heat_cheb,
+        "config": {"workload": (wdesc % R["nnode"]) + ", dt = 1 day, rtol 1e-8, mode %s" % best,
+                   "seed": seed, "cheb_degree": a.cheb, "heat_cheb_degree": a.heat_cheb,
                    "inner_rtol": a.inner_rtol, "autotune": not a.no_autotune, "use_graph": bool(a.use_graph),
                    "mg_coarse_max": a.mg_coarse_max,
                    "heat_precond": ["multigrid", "chebyshev-jacobi", "tensor-mass"][a.heat_precond]},
@@ -277,9 +392,12 @@ def main():
                           "pressure_iters": r["iters_p"], "heat_iters": r["iters_h"],
                           "pressure_outer": r["outer_p"], "heat_outer": r["outer_h"],
                           "pressure_ms": round(r["ms_p"], 3), "heat_ms": round(r["ms_h"], 3),
-                          "max_relres": r["relres_max"]}
+                          "max_relres": r["relres_max"], "setup_s": round(r["setup_s"], 2),
+                          **({"host_loop": r["host_loop"]} if r["host_loop"] else {})}
                   for mname, r in results.items()},
     }
+    if operators:
+        line["operators"] = operators
     print(json.dumps(line), flush=True)
 
 

@@ -347,11 +347,24 @@ def tf_scalar(tf, t) -> float:
 
 # ---------------------------------------------------- method: coefficients
 def coefficients(scn):
-    """Cellwise k, lambda, c_T from the mixture rules (Section 2)."""
-    k = _f64(scn.permeability) / scn.mu_w
-    phi = _f64(scn.porosity)
-    lam = (1.0 - phi) * _f64(scn.lambda_solid) + phi * scn.lambda_w
-    cT = (1.0 - phi) * _f64(scn.rhoc_solid) + phi * scn.c_w
+    """Cellwise k, lambda, c_T from the mixture rules (Section 2).  The
+    mobility is k = K_i / mu_w; a hydraulic conductivity K = K_i rho_w g / mu_w
+    (the form Table 3 gives) is converted as k = K / (rho_w g).  Bulk thermal
+    values (Table 3 lists those of the soil) replace the mixture when given."""
+    if scn.permeability is not None:
+        k = _f64(scn.permeability) / scn.mu_w
+    else:
+        k = _f64(scn.hydraulic_conductivity) / (scn.rho_w * scn.g)
+    if scn.lambda_bulk is not None:
+        lam = _f64(scn.lambda_bulk)
+    else:
+        phi = _f64(scn.porosity)
+        lam = (1.0 - phi) * _f64(scn.lambda_solid) + phi * scn.lambda_w
+    if scn.rhoc_bulk is not None:
+        cT = _f64(scn.rhoc_bulk)
+    else:
+        phi = _f64(scn.porosity)
+        cT = (1.0 - phi) * _f64(scn.rhoc_solid) + phi * scn.c_w
     return k, lam, cT
 
 

@@ -460,7 +460,10 @@ def from_scenario(scn, device=0, stream=None, initial=True, opts=None) -> Mesh:
     initial functions, and the steady pressure is solved when requested."""
     m = Mesh(scn.origin, scn.extent, scn.ncells, scn.degree, device, stream)
     m.set_materials(scn.permeability, scn.porosity, scn.lambda_solid, scn.rhoc_solid,
-                    scn.rho_w, scn.mu_w, scn.c_w, scn.lambda_w, scn.g, scn.B_poro)
+                    scn.rho_w, scn.mu_w, scn.c_w, scn.lambda_w, scn.g, scn.B_poro,
+                    hydraulic_conductivity=getattr(scn, "hydraulic_conductivity", None),
+                    lambda_bulk=getattr(scn, "lambda_bulk", None),
+                    rhoc_bulk=getattr(scn, "rhoc_bulk", None))
     for bc in scn.bcs:
         m.set_face_bc(bc.field, bc.face, bc.kind, bc.value)
     if scn.heat_source is not None:

@@ -93,10 +93,10 @@ class Scenario:
     extent: Tuple[float, float, float]
     ncells: Tuple[int, int, int]
     degree: int
-    permeability: np.ndarray          # K_i [m^2], per cell
-    porosity: np.ndarray              # per cell
-    lambda_solid: np.ndarray          # W/m/K, per cell
-    rhoc_solid: np.ndarray            # J/m^3/K, per cell
+    permeability: Optional[np.ndarray]   # K_i [m^2], per cell (None: hydraulic_conductivity)
+    porosity: Optional[np.ndarray]       # per cell (None: bulk thermal values given)
+    lambda_solid: Optional[np.ndarray]   # W/m/K, per cell
+    rhoc_solid: Optional[np.ndarray]     # J/m^3/K, per cell
     rho_w: float = 1000.0
     mu_w: float = 1.0e-3
     c_w: float = 4.18e6
@@ -104,6 +104,12 @@ class Scenario:
     g: float = 9.81
     B_poro: float = 1.0e5             # <= 0 selects the steady pressure equation
     heat_source: Optional[np.ndarray] = None   # W/m^3 per cell
+    # Site tables may give hydraulic conductivity K [m/s] and the bulk (soil +
+    # water) conductivity and heat capacity directly; when set they are used
+    # in place of permeability and the mixture of solid and water values.
+    hydraulic_conductivity: Optional[np.ndarray] = None
+    lambda_bulk: Optional[np.ndarray] = None
+    rhoc_bulk: Optional[np.ndarray] = None
     bcs: List[FaceBC] = field(default_factory=list)
     lines: List[LineSource] = field(default_factory=list)
     dir_columns: List[DirColumn] = field(default_factory=list)
@@ -289,6 +295,84 @@ def config5(seed: int, ncells=(128, 128, 64), n_steps: int = 100) -> Scenario:
     (training seeds 5000-5019, test seeds 5100-5109)."""
     s = config2(seed=seed, ncells=ncells, n_steps=n_steps)
     s.name = "c5_%d" % seed
+    return s
+
+
+# Soil and rock classes of the island site (Table 3): hydraulic conductivity
+# [m/s], bulk volumetric heat capacity [J/m^3/K], bulk thermal conductivity
+# [W/m/K], and the depth [m] below the surface where the class ends (the
+# bedrock top is drawn per scenario between 70 and 80 m, Section 3.3).
+ISLAND_LAYERS = (
+    ("fill", 1.1e-5, 2.5e6, 2.2, 8.0),
+    ("shoal", 3.5e-5, 2.5e6, 2.2, 12.0),
+    ("young bay mud", 1.7e-9, 3.5e6, 1.5, 30.0),
+    ("old bay mud", 1.7e-9, 3.5e6, 1.7, None),
+    ("franciscan bedrock", 1.0e-6, 2.0e6, 2.97, float("inf")),
+)
+T_SEA = 287.45        # K, mean of the site record and the sea temperature
+
+
+def island(seed: int = 6, ncells=(256, 160, 64), n_steps: int = 365,
+           degree: int = 1) -> Scenario:
+    """Island-style pile field on a 640 x 400 x 100 m box (Section 3.3 on a
+    structured mesh): the five soil/rock classes of Table 3 with bulk thermal
+    values and a seeded scatter of hydraulic conductivity, the bedrock top on
+    a seeded plane between 70 and 80 m depth; a seasonal surface temperature
+    (a sinusoid about 287.45 K that starts at 287.65 K, standing in for the
+    monthly record), a geothermal inflow of 0.0891 W/m^2 through the bottom,
+    lateral temperatures held at the initial 0.03 K/m geotherm; pressure
+    hydrostatic on the left face and 5 Pa/m higher across the box on the
+    right, no flow elsewhere, starting from the steady solution; energy piles
+    60 m long on a 20 m lattice under seeded building footprints, held at
+    288.55 +- 13 K as a square wave of one year (summer half first)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    origin, extent = (0.0, 0.0, 0.0), (640.0, 400.0, 100.0)
+    nx, ny, nz = ncells
+    nc = nx * ny * nz
+    z_top = origin[2] + extent[2]
+    xc = origin[0] + (np.arange(nx) + 0.5) * extent[0] / nx
+    yc = origin[1] + (np.arange(ny) + 0.5) * extent[1] / ny
+    depth = z_top - _cell_centres_z(origin, extent, ncells)
+    a, b = rng.uniform(-1.0, 1.0, size=2)
+    plane = (a * (xc[None, :] / extent[0] - 0.5) + b * (yc[:, None] / extent[1] - 0.5))
+    d_rock = 75.0 + 5.0 * plane / max(1e-12, 0.5 * (abs(a) + abs(b)))   # [ny, nx] in [70, 80]
+    piles = set()
+    for _ in range(8):
+        w, d = rng.uniform(60.0, 160.0), rng.uniform(40.0, 100.0)
+        x0 = rng.uniform(60.0, extent[0] - 60.0 - w)
+        y0 = rng.uniform(60.0, extent[1] - 60.0 - d)
+        for i in range(int(np.ceil(x0 / 20.0)), int(np.floor((x0 + w) / 20.0)) + 1):
+            for j in range(int(np.ceil(y0 / 20.0)), int(np.floor((y0 + d) / 20.0)) + 1):
+                piles.add((i, j))
+    cls = np.zeros((nz, ny, nx), dtype=np.int64)
+    for q, (_, _, _, _, d_end) in enumerate(ISLAND_LAYERS[:3]):
+        cls[depth >= d_end] = q + 1
+    cls[(cls == 3) & (depth[:, None, None] >= d_rock[None, :, :])] = 4
+    cls = cls.reshape(-1)
+    logK = np.log10([r[1] for r in ISLAND_LAYERS])[cls] + 0.2 * rng.standard_normal(nc)
+    s = Scenario("island", origin, extent, tuple(ncells), degree,
+                 permeability=None, porosity=None, lambda_solid=None, rhoc_solid=None,
+                 hydraulic_conductivity=np.power(10.0, logK),
+                 lambda_bulk=np.array([r[3] for r in ISLAND_LAYERS])[cls],
+                 rhoc_bulk=np.array([r[2] for r in ISLAND_LAYERS])[cls],
+                 B_poro=1.0e5, dt=DAY, n_steps=n_steps)
+    p_left = hydrostatic(z_top, 1.0e5, s.rho_w, s.g)
+    p_right = (p_left[0], p_left[1] + 5.0 * extent[0]) + p_left[2:]
+    s.bcs = [FaceBC(PRESSURE, 0, DIRICHLET, p_left), FaceBC(PRESSURE, 1, DIRICHLET, p_right)]
+    geotherm = timefn(c0=T_SEA + 0.03 * z_top, cz=-0.03)
+    s.bcs += [FaceBC(TEMPERATURE, f, DIRICHLET, geotherm) for f in range(4)]
+    s.bcs += [FaceBC(TEMPERATURE, 4, NEUMANN, timefn(-0.0891)),
+              FaceBC(TEMPERATURE, 5, DIRICHLET,
+                     timefn(c0=T_SEA, amp=3.5, period=365.0 * DAY,
+                            phase=float(np.arcsin(0.2 / 3.5)), kind=TF_SIN))]
+    for i, j in sorted(piles):
+        s.dir_columns.append(DirColumn(TEMPERATURE, origin[0] + 20.0 * i, origin[1] + 20.0 * j,
+                                       z_top - 60.0, z_top,
+                                       timefn(c0=288.55, amp=13.0, period=365.0 * DAY,
+                                              kind=TF_SQUARE)))
+    s.P0 = p_left
+    s.P0_steady = True
+    s.T0 = geotherm
     return s
 
 

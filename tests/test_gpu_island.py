@@ -1,0 +1,71 @@
+"""Site-style boundary data on the GPU (Section 3.3): seasonal surface
+temperature, geothermal Neumann inflow at the bottom, square-wave pile
+temperatures, hydrostatic pressure with a lateral gradient, and the soil
+table's hydraulic conductivity and bulk thermal values.
+
+Parity with the oracle as in the other solver tests: the GPU solves to 1e-12
+and the oracle to the FP64 floor; FP64 within 1e-10 relative, the
+FP32-refined path within 1e-8 (pressure) and 1e-6 K (temperature).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import print_case
+from test_oracle_pins import geotherm_exact, geotherm_scn
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_layered_geotherm_fixed_point(hts, p):
+    """A step from the steady layered geotherm returns it (the Neumann
+    inflow balances conduction exactly in the finite element space)."""
+    n = (12, 8, 16) if p == 1 else (6, 4, 8)
+    print_case("geotherm fixed point p", p, n)
+    s = geotherm_scn(p, n=n)
+    o = hts.default_opts(rtol=1e-13)
+    m = hts.from_scenario(s, opts=o)
+    om = oracle.Mesh.of(s)
+    X, Y, Z = om.coords()
+    T0 = geotherm_exact(Z)
+    m.set_state(1, T0, s.t0)
+    code, st = m.solve_step(s.dt, o)
+    T1, _ = m.get_state(1)
+    assert st["status"] == [0, 0], st
+    assert np.abs(T1 - T0).max() <= 1e-9
+
+
+@pytest.mark.parametrize("ncells,degree,mode", [((32, 20, 8), 1, 0), ((32, 20, 8), 1, 1),
+                                                ((40, 25, 10), 1, 0), ((16, 10, 4), 2, 0)])
+def test_island_small_steps(hts, ncells, degree, mode):
+    """Three daily steps of the island-style pile field against the oracle."""
+    print_case("island", ncells, "p", degree, "mode", mode)
+    scn = synth.island(ncells=ncells, degree=degree, n_steps=3)
+    o = hts.default_opts(rtol=1e-12, mode=mode)
+    m = hts.from_scenario(scn, opts=o)
+    stats = []
+    for _ in range(3):
+        code, st = m.solve_step(scn.dt, o)
+        stats.append(st)
+    P, t = m.get_state(0)
+    T, _ = m.get_state(1)
+    Po, To, to = oracle.run(scn, n_steps=3)
+    print("stats", stats)
+    assert t == pytest.approx(to)
+    for st in stats:
+        assert st["status"] == [0, 0], st
+    # the piles are at their summer temperature and the column is warming
+    assert T.max() == pytest.approx(288.55 + 13.0)
+    if mode == 0:
+        assert rel(P, Po) <= 1e-10
+        assert rel(T, To) <= 1e-10
+        assert np.abs(T - To).max() <= 1e-7
+    else:
+        assert rel(P, Po) <= 1e-8
+        assert np.abs(T - To).max() <= 1e-6

@@ -444,6 +444,100 @@ def test_pressure_mass_balance_well(p):
     assert math.isclose(stored, expect, rel_tol=1e-9)
 
 
+# ------------------------------------------------- site-style boundary data
+GEO_LAYERS = ((0.0, 15.0, 2.97), (15.0, 30.0, 1.5), (30.0, 40.0, 2.2))
+
+
+def geotherm_scn(p, n=(3, 2, 8), q=0.0891, T_top=287.45):
+    """Conduction-only 40 m column: bulk conductivity in three layers whose
+    interfaces lie on cell faces, the surface temperature held at T_top and
+    a geothermal inflow q through the bottom (Section 3.3 boundary data)."""
+    nc = n[0] * n[1] * n[2]
+    k = np.arange(nc) // (n[0] * n[1])
+    zc = (k + 0.5) * 40.0 / n[2]
+    lam = np.select([zc < a[1] for a in GEO_LAYERS], [a[2] for a in GEO_LAYERS])
+    rng = np.random.default_rng(11)
+    s = synth.Scenario("geo", (0.0, 0.0, 0.0), (30.0, 20.0, 40.0), n, p,
+                       permeability=None, porosity=None, lambda_solid=None, rhoc_solid=None,
+                       hydraulic_conductivity=np.zeros(nc), lambda_bulk=lam,
+                       rhoc_bulk=rng.uniform(2.0e6, 3.5e6, nc))
+    s.bcs = [synth.FaceBC(synth.TEMPERATURE, 5, synth.DIRICHLET, synth.timefn(T_top)),
+             synth.FaceBC(synth.TEMPERATURE, 4, synth.NEUMANN, synth.timefn(-q))]
+    return s
+
+
+def geotherm_exact(Z, q=0.0891, T_top=287.45):
+    """Steady conduction with an upward flux q: -lambda dT/dz = q, so
+    T(z) = T_top + q int_z^top dz'/lambda(z'), piecewise linear."""
+    Z = np.asarray(Z, dtype=float)
+    acc = np.zeros_like(Z)
+    for a, b, lam in GEO_LAYERS:
+        acc += np.clip(b - np.maximum(a, Z), 0.0, None) / lam
+    return T_top + q * acc
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_layered_geotherm_is_a_fixed_point(p):
+    """The piecewise-linear steady geotherm lies in the finite element space
+    when the layer interfaces are cell faces, so a backward-Euler step from it
+    returns it: this fixes the sign and size of the Neumann flux term of
+    Eq. 4, the per-cell conductivity of the stiffness and the Dirichlet lift."""
+    s = geotherm_scn(p)
+    m = Mesh.of(s)
+    X, Y, Z = m.coords()
+    T0 = geotherm_exact(Z)
+    T1 = oracle.solve_heat(s, m, T0, np.zeros(m.nnode), s.dt)
+    assert np.abs(T1 - T0).max() <= 1e-10
+    # the same column with the flux sign flipped moves away from it
+    s.bcs[1] = synth.FaceBC(synth.TEMPERATURE, 4, synth.NEUMANN, synth.timefn(0.0891))
+    T2 = oracle.solve_heat(s, m, T0, np.zeros(m.nnode), s.dt)
+    assert np.abs(T2 - T0).max() > 1e-4
+
+
+def test_hydraulic_conductivity_and_bulk_values():
+    """A conductivity K [m/s] is K_i rho_w g / mu_w, and bulk thermal values
+    equal to the mixture of solid and water give the same systems."""
+    s = small_scn(n=(4, 3, 3))
+    s.B_poro = 1e5
+    s.lines = [synth.LineSource(1.3, 5.2, 0.2, 0.9, synth.LINE_WELL, synth.timefn(2e-4), T_inj=300.0)]
+    phi = s.porosity
+    s2 = s.replace(permeability=None, porosity=None, lambda_solid=None, rhoc_solid=None,
+                   hydraulic_conductivity=s.permeability * s.rho_w * s.g / s.mu_w,
+                   lambda_bulk=(1 - phi) * s.lambda_solid + phi * s.lambda_w,
+                   rhoc_bulk=(1 - phi) * s.rhoc_solid + phi * s.c_w)
+    m = Mesh.of(s)
+    X, Y, Z = m.coords()
+    P0 = 1e5 + s.rho_w * s.g * (1.0 - Z)
+    A1, b1 = oracle.pressure_system(s, m, P0, s.dt)
+    A2, b2 = oracle.pressure_system(s2, m, P0, s.dt)
+    assert abs(A1 - A2).max() <= 1e-12 * abs(A1).max()
+    assert np.abs(b1 - b2).max() <= 1e-12 * np.abs(b1).max()
+    P1 = P0 - 3.0 * X
+    H1, h1 = oracle.heat_system(s, m, np.full(m.nnode, 290.0), P1, s.dt)
+    H2, h2 = oracle.heat_system(s2, m, np.full(m.nnode, 290.0), P1, s.dt)
+    assert abs(H1 - H2).max() <= 1e-12 * abs(H1).max()
+    assert np.abs(h1 - h2).max() <= 1e-12 * np.abs(h1).max()
+
+
+def test_island_scenario_layout():
+    """The island generator: Table 3 classes by depth, bedrock top between
+    70 and 80 m, piles on the 20 m lattice 60 m long from the surface."""
+    s = synth.island(ncells=(64, 40, 20), n_steps=1)
+    nx, ny, nz = s.ncells
+    lam = s.lambda_bulk.reshape(nz, ny, nx)
+    depth = 100.0 - (np.arange(nz) + 0.5) * 100.0 / nz
+    rock = lam == 2.97
+    assert not rock[depth < 70.0].any() and rock[depth > 80.0].all()
+    assert (lam[depth < 8.0] == 2.2).all()
+    K = s.hydraulic_conductivity.reshape(nz, ny, nx)
+    assert np.all(np.abs(np.log10(K[depth > 80.0]) + 6.0) < 2.0)
+    assert len(s.dir_columns) > 20
+    for c in s.dir_columns:
+        assert c.x % 20.0 == 0.0 and c.y % 20.0 == 0.0
+        assert 60.0 <= c.x <= 580.0 and 60.0 <= c.y <= 340.0
+        assert (c.z0, c.z1) == (40.0, 100.0)
+
+
 # ----------------------------------------------------------------- solvers
 def test_iterative_solvers_match_lu():
     s = small_scn(n=(6, 5, 4))
