@@ -61,84 +61,128 @@ struct Q2Tab {
                                   {T(1.0 / 3), T(-8.0 / 3), T(7.0 / 3)}};
 };
 
-// out = (A along the axis of stride S) in, for the 9 lines of a 3x3x3 block
-template <typename T, int S>
-__device__ __forceinline__ void along(const T (&A)[3][3], const T in[27], T out[27])
+// The cell's 27 nodal values are read through an accessor (from the staged
+// LDS planes) one z-plane at a time, so that only the 27 outputs and a few
+// 9-value planes are live in registers.
+
+// w = mV (M x M x M) u + sk (cxx K x M x M + cyy M x K x M + czz M x M x K) u
+// (first factor along x), accumulated over the z-planes j of u:
+//   p_j = (M_x M_y) u_j,  q_j = mV p_j + skx (K_x M_y) u_j + sky (M_x K_y) u_j,
+//   w_k += M_z[k][j] q_j + skz K_z[k][j] p_j.
+template <typename T, typename UAt>
+__device__ __forceinline__ void q2_mass_stiff(const UAt &uat, T mV, T sk, T cxx, T cyy, T czz, T w[27])
 {
+    using Q = Q2Tab<T>;
+    const T sky = sk * cyy, skz = sk * czz, skx = sk * cxx;
 #pragma unroll
-    for (int l = 0; l < 9; l++) {
-        const int base = S == 1 ? 3 * l : (S == 3 ? (l % 3) + 9 * (l / 3) : l);
-        const T a = in[base], b = in[base + S], c = in[base + 2 * S];
+    for (int i = 0; i < 27; i++) w[i] = T(0);
 #pragma unroll
-        for (int r = 0; r < 3; r++) out[base + r * S] = A[r][0] * a + A[r][1] * b + A[r][2] * c;
+    for (int j = 0; j < 3; j++) {
+        T v[9];
+#pragma unroll
+        for (int i = 0; i < 9; i++) v[i] = uat(i + 9 * j);
+        // y pass (per x index a): my = M_y v, ky = K_y v
+        T my[9], ky[9];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                my[a + 3 * r] = Q::M[r][0] * v[a] + Q::M[r][1] * v[a + 3] + Q::M[r][2] * v[a + 6];
+                ky[a + 3 * r] = Q::K[r][0] * v[a] + Q::K[r][1] * v[a + 3] + Q::K[r][2] * v[a + 6];
+            }
+        // x pass (per y index b)
+        T pj[9], qj[9];
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                const T pm = Q::M[r][0] * my[3 * b] + Q::M[r][1] * my[3 * b + 1] + Q::M[r][2] * my[3 * b + 2];
+                const T kx = Q::K[r][0] * my[3 * b] + Q::K[r][1] * my[3 * b + 1] + Q::K[r][2] * my[3 * b + 2];
+                const T mk = Q::M[r][0] * ky[3 * b] + Q::M[r][1] * ky[3 * b + 1] + Q::M[r][2] * ky[3 * b + 2];
+                pj[r + 3 * b] = pm;
+                qj[r + 3 * b] = mV * pm + skx * kx + sky * mk;
+            }
+        // z accumulation
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const T mz = Q::M[k][j], kz = skz * Q::K[k][j];
+#pragma unroll
+            for (int i = 0; i < 9; i++) w[i + 9 * k] += mz * qj[i] + kz * pj[i];
+        }
     }
 }
 
-// w = mV (M x M x M) u + sk (cxx K x M x M + cyy M x K x M + czz M x M x K) u
-// (first factor along x)
-template <typename T>
-__device__ __forceinline__ void q2_mass_stiff(const T u[27], T mV, T sk, T cxx, T cyy, T czz, T w[27])
-{
-    using Q = Q2Tab<T>;
-    T a[27], b[27];
-    along<T, 9>(Q::M, u, a);
-    along<T, 9>(Q::K, u, b);
-    T c[27], d[27];
-    along<T, 3>(Q::M, a, c);
-    along<T, 3>(Q::K, a, d);
-    along<T, 3>(Q::M, b, a);          // a <- M_y K_z u
-    const T sky = sk * cyy, skz = sk * czz, skx = sk * cxx;
-#pragma unroll
-    for (int i = 0; i < 27; i++) b[i] = mV * c[i] + sky * d[i] + skz * a[i];
-    along<T, 1>(Q::M, b, w);
-    along<T, 1>(Q::K, c, d);
-#pragma unroll
-    for (int i = 0; i < 27; i++) w[i] += skx * d[i];
-}
-
 // w_a += cw sum_q W_q N_a(q) (q_h . grad u)(q), q_h = -k (grad P + rho_g e_z),
-// cw = dt c_w V; 3 x 3 x 3 Gauss points, processed one z-plane at a time.
-template <typename T>
-__device__ __forceinline__ void q2_convect(const T u[27], const T P[27], T kc, T ihx, T ihy, T ihz, T rho_g,
+// cw = dt c_w V; 3 x 3 x 3 Gauss points, processed one z-plane at a time:
+// first the flux factors of the plane's 9 points from P, then grad u there.
+template <typename T, typename UAt, typename PAt>
+__device__ __forceinline__ void q2_convect(const UAt &uat, const PAt &pat, T kc, T ihx, T ihy, T ihz, T rho_g,
                                           T cw, T w[27])
 {
     using Q = Q2Tab<T>;
-#pragma unroll
+    const T s0 = -kc * cw;
+#pragma unroll 1
     for (int qz = 0; qz < 3; qz++) {
-        // values and z-derivatives on the plane qz: f[i + 3 j]
-        T fu[9], fuz[9], fp[9], fpz[9];
+        const T bz0 = Q::B[qz][0], bz1 = Q::B[qz][1], bz2 = Q::B[qz][2];
+        const T dz0 = Q::D[qz][0], dz1 = Q::D[qz][1], dz2 = Q::D[qz][2];
+        const T sz = s0 * Q::W[qz];
+        // flux factors cx, cy, cz at the points (qx, qy) of this plane
+        T cx[9], cy[9], cz[9];
+        {
+            T fp[9], fpz[9];
 #pragma unroll
-        for (int ij = 0; ij < 9; ij++) {
-            fu[ij] = Q::B[qz][0] * u[ij] + Q::B[qz][1] * u[ij + 9] + Q::B[qz][2] * u[ij + 18];
-            fuz[ij] = Q::D[qz][0] * u[ij] + Q::D[qz][1] * u[ij + 9] + Q::D[qz][2] * u[ij + 18];
-            fp[ij] = Q::B[qz][0] * P[ij] + Q::B[qz][1] * P[ij + 9] + Q::B[qz][2] * P[ij + 18];
-            fpz[ij] = Q::D[qz][0] * P[ij] + Q::D[qz][1] * P[ij + 9] + Q::D[qz][2] * P[ij + 18];
-        }
-        T a[9];   // a[qx + 3 qy]
-#pragma unroll
-        for (int qy = 0; qy < 3; qy++) {
-            // y pass: per x index i
-            T yu[3], yud[3], yuz[3], yp[3], ypd[3], ypz[3];
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                yu[i] = Q::B[qy][0] * fu[i] + Q::B[qy][1] * fu[i + 3] + Q::B[qy][2] * fu[i + 6];
-                yud[i] = Q::D[qy][0] * fu[i] + Q::D[qy][1] * fu[i + 3] + Q::D[qy][2] * fu[i + 6];
-                yuz[i] = Q::B[qy][0] * fuz[i] + Q::B[qy][1] * fuz[i + 3] + Q::B[qy][2] * fuz[i + 6];
-                yp[i] = Q::B[qy][0] * fp[i] + Q::B[qy][1] * fp[i + 3] + Q::B[qy][2] * fp[i + 6];
-                ypd[i] = Q::D[qy][0] * fp[i] + Q::D[qy][1] * fp[i + 3] + Q::D[qy][2] * fp[i + 6];
-                ypz[i] = Q::B[qy][0] * fpz[i] + Q::B[qy][1] * fpz[i + 3] + Q::B[qy][2] * fpz[i + 6];
+            for (int ij = 0; ij < 9; ij++) {
+                const T p0 = pat(ij), p1 = pat(ij + 9), p2 = pat(ij + 18);
+                fp[ij] = bz0 * p0 + bz1 * p1 + bz2 * p2;
+                fpz[ij] = dz0 * p0 + dz1 * p1 + dz2 * p2;
             }
 #pragma unroll
-            for (int qx = 0; qx < 3; qx++) {
-                const T gux = Q::D[qx][0] * yu[0] + Q::D[qx][1] * yu[1] + Q::D[qx][2] * yu[2];
-                const T guy = Q::B[qx][0] * yud[0] + Q::B[qx][1] * yud[1] + Q::B[qx][2] * yud[2];
-                const T guz = Q::B[qx][0] * yuz[0] + Q::B[qx][1] * yuz[1] + Q::B[qx][2] * yuz[2];
-                const T gpx = Q::D[qx][0] * yp[0] + Q::D[qx][1] * yp[1] + Q::D[qx][2] * yp[2];
-                const T gpy = Q::B[qx][0] * ypd[0] + Q::B[qx][1] * ypd[1] + Q::B[qx][2] * ypd[2];
-                const T gpz = Q::B[qx][0] * ypz[0] + Q::B[qx][1] * ypz[1] + Q::B[qx][2] * ypz[2];
-                const T flux = (gpx * ihx) * (gux * ihx) + (gpy * ihy) * (guy * ihy) +
-                               (gpz * ihz + rho_g) * (guz * ihz);
-                a[qx + 3 * qy] = -kc * cw * (Q::W[qx] * Q::W[qy] * Q::W[qz]) * flux;
+            for (int qy = 0; qy < 3; qy++) {
+                T yp[3], ypd[3], ypz[3];
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    yp[i] = Q::B[qy][0] * fp[i] + Q::B[qy][1] * fp[i + 3] + Q::B[qy][2] * fp[i + 6];
+                    ypd[i] = Q::D[qy][0] * fp[i] + Q::D[qy][1] * fp[i + 3] + Q::D[qy][2] * fp[i + 6];
+                    ypz[i] = Q::B[qy][0] * fpz[i] + Q::B[qy][1] * fpz[i + 3] + Q::B[qy][2] * fpz[i + 6];
+                }
+#pragma unroll
+                for (int qx = 0; qx < 3; qx++) {
+                    const T gpx = Q::D[qx][0] * yp[0] + Q::D[qx][1] * yp[1] + Q::D[qx][2] * yp[2];
+                    const T gpy = Q::B[qx][0] * ypd[0] + Q::B[qx][1] * ypd[1] + Q::B[qx][2] * ypd[2];
+                    const T gpz = Q::B[qx][0] * ypz[0] + Q::B[qx][1] * ypz[1] + Q::B[qx][2] * ypz[2];
+                    const T sw = sz * (Q::W[qx] * Q::W[qy]);
+                    cx[qx + 3 * qy] = sw * ((gpx * ihx) * ihx);
+                    cy[qx + 3 * qy] = sw * ((gpy * ihy) * ihy);
+                    cz[qx + 3 * qy] = sw * ((gpz * ihz + rho_g) * ihz);
+                }
+            }
+        }
+        T a[9];   // a[qx + 3 qy]
+        {
+            T fu[9], fuz[9];
+#pragma unroll
+            for (int ij = 0; ij < 9; ij++) {
+                const T u0 = uat(ij), u1 = uat(ij + 9), u2 = uat(ij + 18);
+                fu[ij] = bz0 * u0 + bz1 * u1 + bz2 * u2;
+                fuz[ij] = dz0 * u0 + dz1 * u1 + dz2 * u2;
+            }
+#pragma unroll
+            for (int qy = 0; qy < 3; qy++) {
+                T yu[3], yud[3], yuz[3];
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    yu[i] = Q::B[qy][0] * fu[i] + Q::B[qy][1] * fu[i + 3] + Q::B[qy][2] * fu[i + 6];
+                    yud[i] = Q::D[qy][0] * fu[i] + Q::D[qy][1] * fu[i + 3] + Q::D[qy][2] * fu[i + 6];
+                    yuz[i] = Q::B[qy][0] * fuz[i] + Q::B[qy][1] * fuz[i + 3] + Q::B[qy][2] * fuz[i + 6];
+                }
+#pragma unroll
+                for (int qx = 0; qx < 3; qx++) {
+                    const T gux = Q::D[qx][0] * yu[0] + Q::D[qx][1] * yu[1] + Q::D[qx][2] * yu[2];
+                    const T guy = Q::B[qx][0] * yud[0] + Q::B[qx][1] * yud[1] + Q::B[qx][2] * yud[2];
+                    const T guz = Q::B[qx][0] * yuz[0] + Q::B[qx][1] * yuz[1] + Q::B[qx][2] * yuz[2];
+                    const int q = qx + 3 * qy;
+                    a[q] = cx[q] * gux + cy[q] * guy + cz[q] * guz;
+                }
             }
         }
         // back-projection: s[i + 3 j] = sum_{qx, qy} B[qx][i] B[qy][j] a
@@ -153,10 +197,32 @@ __device__ __forceinline__ void q2_convect(const T u[27], const T P[27], T kc, T
 #pragma unroll
             for (int i = 0; i < 3; i++) {
                 const T s = Q::B[0][j] * t[i] + Q::B[1][j] * t[i + 3] + Q::B[2][j] * t[i + 6];
-#pragma unroll
-                for (int k = 0; k < 3; k++) w[i + 3 * j + 9 * k] += Q::B[qz][k] * s;
+                w[i + 3 * j] += bz0 * s;
+                w[i + 3 * j + 9] += bz1 * s;
+                w[i + 3 * j + 18] += bz2 * s;
             }
     }
+}
+
+// Compact node-column data of the apply kernel (three registers per column
+// instead of ColInfo's six): node column index, packed constrained z-range,
+// bit 0 valid and bit 1 constrained by an x/y face.
+struct ColQ {
+    int32_t base, dl, f;
+};
+__device__ __forceinline__ static ColQ colq(const OpDev &o, int i, int j)
+{
+    const ColInfo c = col_info(o, i, j);
+    ColQ q;
+    q.base = (int32_t)c.base;
+    q.dl = c.dlo | (c.dhi << 16);
+    q.f = (c.valid ? 1 : 0) | (c.xyc ? 2 : 0);
+    return q;
+}
+__device__ __forceinline__ static bool constrained_q(const ColQ &c, int k, int NZ, int m)
+{
+    const int lo = c.dl & 0xFFFF, hi = (c.dl >> 16) & 0xFFFF;
+    return (c.f & 2) || ((m & 16) && k == 0) || ((m & 32) && k == NZ - 1) || (k >= lo && k <= hi);
 }
 
 template <typename T, int FIELD, int EPI, bool MASKED>
@@ -194,28 +260,28 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
     const int nx0 = 2 * cx0, ny0 = 2 * cy0;                     // node of local column 0
 
     // staged node columns of this thread
-    ColInfo sc[SPT];
+    ColQ sc[SPT];
     int sli[SPT], slj[SPT];
 #pragma unroll
     for (int s = 0; s < SPT; s++) {
         const int c = tid + 256 * s;
         sli[s] = c % NL;
         slj[s] = c / NL;
-        if (c < NSTAGE) sc[s] = col_info(o, nx0 + sli[s], ny0 + slj[s]);
-        else sc[s].valid = 0;
+        if (c < NSTAGE) sc[s] = colq(o, nx0 + sli[s], ny0 + slj[s]);
+        else sc[s] = ColQ{0, DCOL_NONE, 0};
     }
     // owned node columns of this thread (local columns 2 .. 31)
-    ColInfo oc[OPT];
+    ColQ oc[OPT];
     int oli[OPT], olj[OPT], lr[OPT];
 #pragma unroll
     for (int s = 0; s < OPT; s++) {
         const int c = tid + 256 * s;
         oli[s] = 2 + c % OWNN;
         olj[s] = 2 + c / OWNN;
-        if (c < NOWN) oc[s] = col_info(o, nx0 + oli[s], ny0 + olj[s]);
-        else oc[s].valid = 0;
+        if (c < NOWN) oc[s] = colq(o, nx0 + oli[s], ny0 + olj[s]);
+        else oc[s] = ColQ{0, DCOL_NONE, 0};
         lr[s] = -1;
-        if (FIELD && o.lcol && oc[s].valid) lr[s] = gptr<int32_t>(o.lcol)[oc[s].base];
+        if (FIELD && o.lcol && (oc[s].f & 1)) lr[s] = gptr<int32_t>(o.lcol)[oc[s].base];
     }
 
     const T hx = T(o.hx), hy = T(o.hy), hz = T(o.hz);
@@ -239,10 +305,10 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
 #pragma unroll
         for (int s = 0; s < SPT; s++) {
             if (tid + 256 * s >= NSTAGE) continue;
-            const bool in = sc[s].valid && k >= 0 && k < NZ;
-            const int64_t gi = sc[s].valid ? sc[s].base + kc * plane : 0;
+            const bool in = (sc[s].f & 1) && k >= 0 && k < NZ;
+            const int64_t gi = (sc[s].f & 1) ? (int64_t)sc[s].base + kc * plane : 0;
             bool keep = in;
-            if (MASKED) keep = keep && !constrained(sc[s], k, NZ, m);
+            if (MASKED) keep = keep && !constrained_q(sc[s], k, NZ, m);
             const T xv = Xi[gi];
             xs[b][slj[s]][sli[s]] = keep ? xv : T(0);
             if (FIELD) {
@@ -273,27 +339,22 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
         __syncthreads();
         T w[27];
         if (lay) {
-            T u[27];
-#pragma unroll
-            for (int c = 0; c < 3; c++)
-#pragma unroll
-                for (int b = 0; b < 3; b++)
-#pragma unroll
-                    for (int a = 0; a < 3; a++) u[a + 3 * b + 9 * c] = xs[(2 * L + 2 * 3 + c) % 3][2 * ty + b][2 * tx + a];
+            // node a + 3 b + 9 c of the cell: staged plane 2L + c, local column (2 tx + a, 2 ty + b)
+            const int s0 = (2 * L + 6) % 3, s1 = (2 * L + 7) % 3, s2 = (2 * L + 8) % 3;
+            auto uat = [&](int i) -> T {
+                const int c = i / 9, b = (i / 3) % 3, a = i % 3;
+                return xs[c == 0 ? s0 : (c == 1 ? s1 : s2)][2 * ty + b][2 * tx + a];
+            };
             if (FIELD == 0) {
-                q2_mass_stiff(u, cm * V, cs * ck, cxx, cyy, czz, w);
+                q2_mass_stiff(uat, cm * V, cs * ck, cxx, cyy, czz, w);
             } else {
-                q2_mass_stiff(u, cc * V, cs * cl, cxx, cyy, czz, w);
-                T pp[27];
-#pragma unroll
-                for (int c = 0; c < 3; c++)
-#pragma unroll
-                    for (int b = 0; b < 3; b++)
-#pragma unroll
-                        for (int a = 0; a < 3; a++)
-                            pp[a + 3 * b + 9 * c] =
-                                ps[FIELD ? (2 * L + 2 * 3 + c) % 3 : 0][FIELD ? 2 * ty + b : 0][FIELD ? 2 * tx + a : 0];
-                q2_convect(u, pp, ck, ihx, ihy, ihz, rho_g, cw, w);
+                q2_mass_stiff(uat, cc * V, cs * cl, cxx, cyy, czz, w);
+                auto pat = [&](int i) -> T {
+                    const int c = i / 9, b = (i / 3) % 3, a = i % 3;
+                    return ps[FIELD ? (c == 0 ? s0 : (c == 1 ? s1 : s2)) : 0][FIELD ? 2 * ty + b : 0]
+                             [FIELD ? 2 * tx + a : 0];
+                };
+                q2_convect(uat, pat, ck, ihx, ihy, ihz, rho_g, cw, w);
             }
         } else {
 #pragma unroll
@@ -313,7 +374,7 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
             if (P0 < z0 || P0 >= z1 || P0 >= NZ) continue;
 #pragma unroll
             for (int s = 0; s < OPT; s++) {
-                if (tid + 256 * s >= NOWN || !oc[s].valid) continue;
+                if (tid + 256 * s >= NOWN || !(oc[s].f & 1)) continue;
                 // cells around the node: x index i (local node column li)
                 const int li = oli[s], lj = olj[s];
                 int cxs[2], ixs[2], ncx, cys[2], iys[2], ncy;
@@ -327,15 +388,15 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
                         const int cell = cxs[a] + TC * cys[b];
                         v += C[h][ixs[a] + 3 * iys[b]][cell];
                     }
-                const int64_t gi = oc[s].base + (int64_t)P0 * plane;
+                const int64_t gi = (int64_t)oc[s].base + (int64_t)P0 * plane;
                 if (FIELD && lr[s] >= 0) {
                     const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
                     const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
                     const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
                     int r = lr[s];
-                    while (rows[r].col == (int)oc[s].base && rows[r].k < P0) r++;
+                    while (rows[r].col == oc[s].base && rows[r].k < P0) r++;
                     lr[s] = r;
-                    if (rows[r].col == (int)oc[s].base && rows[r].k == P0 && !(MASKED && rows[r].row_constrained)) {
+                    if (rows[r].col == oc[s].base && rows[r].k == P0 && !(MASKED && rows[r].row_constrained)) {
                         T la = T(0);
                         for (int e = rows[r].beg; e < rows[r].end; e++) {
                             if (MASKED && ents[e].col_constrained) continue;
@@ -346,7 +407,7 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
                 }
                 T ex = T(0);
                 if (EPI == EPI_CHEB || EPI == EPI_DOT || MASKED) ex = Xi[gi];
-                if (MASKED && constrained(oc[s], P0, NZ, m)) v = ex;
+                if (MASKED && constrained_q(oc[s], P0, NZ, m)) v = ex;
                 if (EPI == EPI_STORE) {
                     Yi[gi] = v;
                 } else if (EPI == EPI_RESID) {
