@@ -194,8 +194,6 @@ def time_operators(hts, synth, np, torch):
         m.set_state(0, 1e5 + 9810.0 * rng.uniform(0, 200, n) - 3.0 * X, scn.t0)
         for field in (0, 1):
             for prec, dt in ((0, torch.float64), (1, torch.float32)):
-                if p == 2 and prec == 1:
-                    continue
                 xs = [torch.randn(n, dtype=dt, device="cuda") for _ in range(4)]
                 ys = [torch.zeros(n, dtype=dt, device="cuda") for _ in range(4)]
                 for r in range(4):

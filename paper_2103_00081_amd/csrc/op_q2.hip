@@ -318,6 +318,30 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
         }
     };
 
+    // pressure: the two node planes of the next cell layer are loaded into
+    // registers while this layer is computed (the heat kernel has no
+    // registers to spare for it and stages synchronously)
+    constexpr bool PF = FIELD == 0;
+    T nxa[PF ? SPT : 1], nxb[PF ? SPT : 1];
+    auto fetch = [&](int k, T *dst) {
+        const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
+#pragma unroll
+        for (int s = 0; s < SPT; s++) {
+            const int64_t gi = (sc[s].f & 1) ? (int64_t)sc[s].base + kc * plane : 0;
+            dst[s] = Xi[gi];
+        }
+    };
+    auto put = [&](int k, const T *src) {
+        const int b = (k + 6) % 3;
+#pragma unroll
+        for (int s = 0; s < SPT; s++) {
+            if (tid + 256 * s >= NSTAGE) continue;
+            bool keep = (sc[s].f & 1) && k >= 0 && k < NZ;
+            if (MASKED) keep = keep && !constrained_q(sc[s], k, NZ, m);
+            xs[b][slj[s]][sli[s]] = keep ? src[s] : T(0);
+        }
+    };
+
     const int z0 = wi.z0, z1 = wi.z1;            // owned node planes, z0 even
     const int L0 = z0 / 2 - 1, L1 = (z1 - 1) / 2;  // cell layers marched
     double acc = 0.0;
@@ -326,15 +350,28 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
     for (int a = 0; a < 9; a++) top[a] = T(0);
 
     stage(2 * L0);
+    if (PF) {
+        fetch(2 * L0 + 1, nxa);
+        fetch(2 * L0 + 2, nxb);
+    }
     for (int L = L0; L <= L1; L++) {
-        stage(2 * L + 1);
-        stage(2 * L + 2);
+        if (PF) {
+            put(2 * L + 1, nxa);
+            put(2 * L + 2, nxb);
+        } else {
+            stage(2 * L + 1);
+            stage(2 * L + 2);
+        }
         T ck = T(0), cl = T(0), cc = T(0);
         const bool lay = cin && L >= 0 && L < nz;
         if (lay) {
             const int64_t ci = cbase + (int64_t)L * cplane;
             ck = kk[ci];
             if (FIELD) { cl = lamc[ci]; cc = cTc[ci]; }
+        }
+        if (PF && L < L1) {
+            fetch(2 * L + 3, nxa);
+            fetch(2 * L + 4, nxb);
         }
         __syncthreads();
         T w[27];
