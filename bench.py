@@ -4,8 +4,9 @@ Default workload: the layered aquifer (500 x 500 x 100 m, 128 x 128 x 64 Q1
 cells, 1,081,665 nodes per field, injection/extraction well pair, daily
 backward-Euler steps).  --workload selects the others: the energy-pile field
 on 256 x 256 x 128 Q1 or 128 x 128 x 64 Q2 cells (8,520,321 nodes per field),
-the island-style pile field with site boundary data (256 x 160 x 64 Q1), and
-64 batched design instances of 32^3..96^3 cells advanced together (set
+the island-style pile field with site boundary data (256 x 160 x 64 Q1), the
+three-formation hot-water injection column (64 x 64 x 240 Q1), and 64
+batched design instances of 32^3..96^3 cells advanced together (set
 against a host loop over the instances one at a time).
 
 A step is one backward-Euler step of the whole path: pressure right-hand
@@ -63,7 +64,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--modes", default="fp64,fp32_refined",
                     help="comma list of fp64, fp32_refined; the faster one is the headline")
-    ap.add_argument("--workload", default="aquifer", choices=("aquifer", "piles", "piles-q2", "island", "batch"))
+    ap.add_argument("--workload", default="aquifer",
+                    choices=("aquifer", "piles", "piles-q2", "island", "ates", "batch"))
     ap.add_argument("--ncells", default=None, help="cells per axis, e.g. 128,128,64 (default: the workload's)")
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--host-loop", type=int, default=1,
@@ -173,6 +175,11 @@ def workload(a, synth, n_steps):
         s = synth.island(ncells=nc, n_steps=n_steps)
         return [s], 6, ("island-style pile field %dx%dx%d Q1 (%%d nodes/field), %d square-wave piles, "
                          "seasonal surface, geothermal inflow" % (nc + (len(s.dir_columns),)))
+    if a.workload == "ates":
+        nc = nc or (64, 64, 240)
+        return [synth.ates(ncells=nc, n_steps=n_steps)], None, \
+            ("hot-water injection column 40x40x300 m, %dx%dx%d Q1 (%%d nodes/field), three formations, "
+             "wellbore flux 0.001 m/s at 288.15 K" % nc)
     scns = [synth.config4_instance(i, n_override=(nc[0] if nc else None), n_steps=n_steps)
             for i in range(a.instances)]
     return scns, 4000, ("%d batched design instances, 32^3..96^3 Q1 cells (%%d nodes/field in total), "

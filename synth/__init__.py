@@ -376,6 +376,49 @@ def island(seed: int = 6, ncells=(256, 160, 64), n_steps: int = 365,
     return s
 
 
+def ates(ncells=(64, 64, 240), n_steps: int = 180, degree: int = 1,
+         r_well: float = 0.1) -> Scenario:
+    """Three-dimensional analogue of the hot-water injection benchmark
+    (Section 2, Table 1, Fig. 2): a 40 x 40 x 300 m column with a caprock
+    (depth 0-100 m), an aquifer (100-200 m, hydraulic conductivity 1e-6 m/s)
+    and a basement (200-300 m, 1e-10 m/s); bulk c_T 1.2e6 J/m^3/K and
+    lambda 1.2 W/m/K everywhere, water heat capacity 1e6 J/m^3/K, storage
+    modulus 1e5 Pa.  A wellbore on the column axis injects an outward flux of
+    0.001 m/s through its surface over the aquifer (a line source of
+    0.001 * 2 pi r_well m^3/s per metre) at 288.15 K, and holds the aquifer
+    section of the axis at 288.15 K.  Surface 278.15 K, 0.05 K/m geotherm
+    (held on the lateral faces; the matching 0.06 W/m^2 enters through the
+    bottom), pressure hydrostatic from 0.1 MPa at the surface on the lateral
+    faces, no flow through top and bottom.  180 daily steps (six months)."""
+    origin, extent = (0.0, 0.0, 0.0), (40.0, 40.0, 300.0)
+    nx, ny, nz = ncells
+    nc = nx * ny * nz
+    z_top = extent[2]
+    depth = z_top - _cell_centres_z(origin, extent, ncells)
+    aquifer = (depth >= 100.0) & (depth < 200.0)
+    K = np.where(aquifer, 1.0e-6, 1.0e-10)[:, None, None] * np.ones((nz, ny, nx))
+    s = Scenario("ates", origin, extent, tuple(ncells), degree,
+                 permeability=None, porosity=None, lambda_solid=None, rhoc_solid=None,
+                 hydraulic_conductivity=K.reshape(-1), lambda_bulk=np.full(nc, 1.2),
+                 rhoc_bulk=np.full(nc, 1.2e6), c_w=1.0e6, B_poro=1.0e5, dt=DAY,
+                 n_steps=n_steps)
+    p_hyd = hydrostatic(z_top, 1.0e5, s.rho_w, s.g)
+    s.bcs = [FaceBC(PRESSURE, f, DIRICHLET, p_hyd) for f in range(4)]
+    geotherm = timefn(c0=278.15 + 0.05 * z_top, cz=-0.05)
+    s.bcs += [FaceBC(TEMPERATURE, f, DIRICHLET, geotherm) for f in range(4)]
+    s.bcs += [FaceBC(TEMPERATURE, 4, NEUMANN, timefn(-1.2 * 0.05)),
+              FaceBC(TEMPERATURE, 5, DIRICHLET, timefn(278.15))]
+    xc, yc = origin[0] + 0.5 * extent[0], origin[1] + 0.5 * extent[1]
+    rate = 0.001 * 2.0 * np.pi * r_well * 100.0
+    s.lines = [LineSource(xc, yc, z_top - 200.0, z_top - 100.0, LINE_WELL, timefn(rate),
+                          T_inj=288.15)]
+    s.dir_columns = [DirColumn(TEMPERATURE, xc, yc, z_top - 200.0, z_top - 100.0,
+                               timefn(288.15))]
+    s.P0 = p_hyd
+    s.T0 = geotherm
+    return s
+
+
 def random_field(seed: int, n: int, kind: str = "normal") -> np.ndarray:
     """Seeded random vector for operator-apply tests."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -538,6 +538,28 @@ def test_island_scenario_layout():
         assert (c.z0, c.z1) == (40.0, 100.0)
 
 
+def test_ates_scenario_layout():
+    """The injection benchmark analogue: Table 1 values, the aquifer between
+    100 and 200 m depth, the wellbore on the axis over the aquifer only, and
+    an injection rate equal to the wellbore flux times its surface."""
+    s = synth.ates(ncells=(8, 8, 30), n_steps=1)
+    nx, ny, nz = s.ncells
+    K = s.hydraulic_conductivity.reshape(nz, ny, nx)
+    depth = 300.0 - (np.arange(nz) + 0.5) * 10.0
+    aq = (depth > 100.0) & (depth < 200.0)
+    assert np.all(K[aq] == 1e-6) and np.all(K[~aq] == 1e-10)
+    assert np.all(s.lambda_bulk == 1.2) and np.all(s.rhoc_bulk == 1.2e6) and s.c_w == 1e6
+    (w,) = s.lines
+    assert (w.x, w.y, w.z0, w.z1) == (20.0, 20.0, 100.0, 200.0) and w.T_inj == 288.15
+    assert w.rate[1] == pytest.approx(0.001 * 2 * np.pi * 0.1 * 100.0)
+    (c,) = s.dir_columns
+    assert (c.x, c.y, c.z0, c.z1) == (20.0, 20.0, 100.0, 200.0) and c.value[1] == 288.15
+    m = Mesh.of(s)
+    X, Y, Z = m.coords()
+    T0 = oracle.tf_value(s.T0, X, Y, Z, 0.0)
+    assert T0.max() == pytest.approx(293.15) and T0.min() == pytest.approx(278.15)
+
+
 # ----------------------------------------------------------------- solvers
 def test_iterative_solvers_match_lu():
     s = small_scn(n=(6, 5, 4))
