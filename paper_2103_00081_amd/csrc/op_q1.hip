@@ -156,7 +156,6 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     if (ep.active && !ep.active[wi.inst]) return;
     const OpDev &o = ops[wi.inst];
     const int nx = o.nx, ny = o.ny, nz = o.nz, NZ = o.NZ, m = o.dmask;
-    const int64_t plane = (int64_t)o.NX * o.NY;
     const T *__restrict__ Xi = X + o.off;
     T *__restrict__ Yi = Y + o.off;
     const T HTS_GLOBAL *__restrict__ Pi = gptr<T>(FIELD ? o.P : nullptr);
@@ -168,24 +167,38 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     T *__restrict__ Di = CHEB ? ep.d + o.off : nullptr;
     const T *__restrict__ Ii = CHEB ? ep.invd + o.off : nullptr;
 
+    // Node and cell indices are instance-local and below 2^31: 32-bit index
+    // arithmetic (the vectors are offset to the instance already).
+    const int32_t plane32 = o.NX * o.NY;
     const int tid = threadIdx.x, tx = tid % TB, ty = tid / TB;
     const int cx0 = wi.tx * OWN - 1, cy0 = wi.ty * OWN - 1;
     const int cx = cx0 + tx, cy = cy0 + ty;
     const bool cin = cx >= 0 && cx < nx && cy >= 0 && cy < ny;
-    const int64_t cbase = cin ? (int64_t)cx + (int64_t)nx * cy : 0;
-    const int64_t cplane = (int64_t)nx * ny;
+    const int32_t cbase = cin ? cx + nx * cy : 0;
+    const int32_t cplane = nx * ny;
 
-    ColInfo lc[2];
+    // staged node columns of this thread: base index (0 outside the mesh, so
+    // that the loads stay in range; the value is then discarded), whether the
+    // column is in the mesh, whether its values are kept (not on a
+    // constraining x/y face), and its constrained z-range
     int lj[2], li[2];
-    bool ld[2];
+    bool ld[2], sval[2], scol[2];
+    int32_t sbase[2];
+    int sdlo[2], sdhi[2];
 #pragma unroll
     for (int s = 0; s < 2; s++) {
         int c = tid + s * 256;
         ld[s] = c < NCOL;
         li[s] = c % (TB + 1);
         lj[s] = c / (TB + 1);
-        if (ld[s]) lc[s] = col_info(o, cx0 + li[s], cy0 + lj[s]);
-        else lc[s].valid = 0;
+        ColInfo lc;
+        if (ld[s]) lc = col_info(o, cx0 + li[s], cy0 + lj[s]);
+        else { lc.valid = 0; lc.base = 0; lc.xyc = 0; lc.dlo = 1; lc.dhi = 0; }
+        sval[s] = lc.valid;
+        scol[s] = lc.valid && !(MASKED && lc.xyc);
+        sbase[s] = lc.valid ? (int32_t)lc.base : 0;
+        sdlo[s] = lc.dlo;
+        sdhi[s] = lc.dhi;
     }
     const bool owner = tx < OWN && ty < OWN;
     const int oi = cx0 + tx + 1, oj = cy0 + ty + 1;
@@ -223,43 +236,49 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     // valid address) and the keep-or-zero decision is a select applied when
     // the value is consumed, so no branch forces an early wait on a load.
     T pfx[2], pfp[2];
-    bool pkeep[2] = {false, false};
+    bool pkeep[2] = {false, false}, pin[2] = {false, false};
     auto fetch_plane = [&](int k) {
         const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
+        const int32_t koff = kc * plane32;
+        // the part of the keep decision that is the same for every column
+        const bool kin = k >= 0 && k < NZ;
+        const bool kkeep = kin && !(MASKED && (((m & 16) && k == 0) || ((m & 32) && k == NZ - 1)));
 #pragma unroll
         for (int s = 0; s < 2; s++) {
-            const int64_t gi = lc[s].valid ? lc[s].base + kc * plane : 0;
+            const int32_t gi = sbase[s] + koff;
             // EPI_CHEB0 operand: x0 = c0 D^-1 b, in the order of the
             // separate first Chebyshev kernel
             if (EPI == EPI_CHEB0) pfx[s] = c0 * Ii[gi] * Bi[gi];
             else pfx[s] = Xi[gi];
             if (FIELD) pfp[s] = Pi[gi];
-            bool keep = lc[s].valid && k >= 0 && k < NZ;
-            if (MASKED) keep = keep && !constrained(lc[s], k, NZ, m);
+            bool keep = kkeep && scol[s];
+            if (MASKED) keep = keep && !(k >= sdlo[s] && k <= sdhi[s]);
             pkeep[s] = keep;
+            pin[s] = kin && sval[s];
         }
     };
-    auto store_plane = [&](int k) {
-        const int b = (k + 3) % 3, bx = (k + XR) % XR;
+    // ring slots: x planes in a ring of XR, pressure planes in a ring of 3
+    auto store_plane = [&](int bx, int b) {
 #pragma unroll
         for (int s = 0; s < 2; s++) {
             if (!ld[s]) continue;
             xs[bx][lj[s]][li[s]] = pkeep[s] ? pfx[s] : T(0);
-            if (FIELD) ps[FIELD ? b : 0][lj[s]][li[s]] = (lc[s].valid && k >= 0 && k < NZ) ? pfp[s] : T(0);
+            if (FIELD) ps[FIELD ? b : 0][lj[s]][li[s]] = pin[s] ? pfp[s] : T(0);
         }
     };
     T cfk = T(0), cfl = T(0), cfc = T(0);
     auto fetch_coef = [&](int L) {
         const int Lc = L < 0 ? 0 : (L >= nz ? nz - 1 : L);
-        const int64_t ci = cbase + (int64_t)Lc * cplane;
+        const int32_t ci = cbase + Lc * cplane;
         cfk = kk[ci];
         if (FIELD) { cfl = lamc[ci]; cfc = cTc[ci]; }
     };
     // epilogue operands of one owned node
+    const int32_t obase = own_ok ? (int32_t)oc.base : 0;
     T eb = T(0), ed = T(0), ei = T(0), ex = T(0);
     auto fetch_epi = [&](int L) {
         const int Lc = L < NZ ? L : NZ - 1;
-        const int64_t gi = own_ok ? oc.base + (int64_t)Lc * plane : 0;
+        const int32_t gi = obase + Lc * plane32;
         if (Bi) eb = Bi[gi];
         if (EPI == EPI_CHEB) { ed = Di[gi]; ei = Ii[gi]; }
         if (EPI == EPI_CHEB0) ei = Ii[gi];
@@ -270,14 +289,17 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     double acc = 0.0;
     T top[4] = {T(0), T(0), T(0), T(0)};
 
+    // slots of plane L in the two rings, advanced by one per iteration
+    int sx = (kb - 1 + XR) % XR, sp = (kb - 1 + 3) % 3;
     fetch_plane(kb - 1);
-    store_plane(kb - 1);
+    store_plane(sx, sp);
     fetch_plane(kb);
     fetch_coef(kb - 1);
 
     for (int L = kb - 1; L <= ke; L++) {
         const bool comp = L <= ke - 1;
-        if (comp) store_plane(L + 1);
+        const int sx1 = sx + 1 == XR ? 0 : sx + 1, sp1 = sp + 1 == 3 ? 0 : sp + 1;
+        if (comp) store_plane(sx1, sp1);
         const T ck = cfk, cl = cfl, cc = cfc;
         if (L + 1 <= ke - 1) {
             fetch_plane(L + 2);
@@ -288,7 +310,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         if (L - 1 >= kb && own_ok && L - 1 < NZ) {
             const int P0 = L - 1, sb = P0 & 1;
             T v = S4[sb][3][ty][tx] + S4[sb][2][ty][tx + 1] + S4[sb][1][ty + 1][tx] + S4[sb][0][ty + 1][tx + 1];
-            const int64_t gi = oc.base + (int64_t)P0 * plane;
+            const int32_t gi = obase + P0 * plane32;
             if (FIELD && lh.first >= 0 && P0 >= lh.kmin && P0 <= lh.kmax) {
                 // injection-line row: operand values from the staged planes
                 const LineFlat HTS_GLOBAL &R = gptr<LineFlat>(o.lflat)[lh.first + (P0 - lh.kmin)];
@@ -299,7 +321,8 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                     for (int e = 0; e < ne; e++) {
                         const int of = R.off[e];
                         const int dx = (of & 3) - 1, dy = ((of >> 2) & 3) - 1, dk = ((of >> 4) & 3) - 1;
-                        const T xc = xs[(P0 + dk + XR) % XR][ty + 1 + dy][tx + 1 + dx];
+                        // plane P0 + dk = L - 1 + dk sits in slot sx - 1 + dk (mod XR)
+                        const T xc = xs[(sx + XR - 1 + dk) % XR][ty + 1 + dy][tx + 1 + dx];
                         la += T(lco[R.src[e]] * R.w[e]) * xc;
                     }
                     v += la;
@@ -351,8 +374,8 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         const bool lay = cin && L >= 0 && L < nz;
         T bot[4] = {T(0), T(0), T(0), T(0)}, tp[4] = {T(0), T(0), T(0), T(0)};
         if (lay) {
-            const int b0 = (L + 3) % 3, b1 = (L + 4) % 3;
-            const int x0 = (L + XR) % XR, x1 = (L + 1 + XR) % XR;
+            const int b0 = sp, b1 = sp1;
+            const int x0 = sx, x1 = sx1;
             T u[8], w[8];
 #pragma unroll
             for (int a = 0; a < 4; a++) {
@@ -381,6 +404,8 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         }
 #pragma unroll
         for (int a = 0; a < 4; a++) top[a] = tp[a];
+        sx = sx1;
+        sp = sp1;
     }
     if (EPI == EPI_RESID_NORM || EPI == EPI_DOT) {
         double v = wave_sum(acc);
