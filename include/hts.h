@@ -86,7 +86,13 @@ typedef struct {
     void *ctx;
 } hts_allocator;
 
-/* Uniform box mesh [origin, origin+extent] with ncells cells of degree 1 or 2. */
+/* Box mesh [origin, origin+extent] with ncells cells of degree 1 or 2.
+ * Uniform unless edges[d] is given: then axis d is graded, with the cell
+ * edges edges[d][0..ncells[d]] (host array, copied; strictly increasing from
+ * origin[d] to origin[d]+extent[d], within 1e-9 of the extent).  Graded
+ * (rectilinear) meshes refine around features, as the paper's site mesh is
+ * refined around the piles (Section 3.3, Fig. 10b); they are supported for
+ * degree 1. */
 typedef struct {
     double origin[3];
     double extent[3];
@@ -95,6 +101,7 @@ typedef struct {
     int32_t device;       /* HIP device ordinal */
     void *stream;         /* hipStream_t; NULL = null stream */
     hts_allocator alloc;
+    const double *edges[3];   /* NULL = uniform axis */
 } hts_mesh_desc;
 
 /* Materials (Section 2 mixture rules and mobility, Tables 1 and 3):

@@ -37,7 +37,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import Optional, Tuple
 
 import numpy as np
@@ -55,7 +55,7 @@ LINE_HEAT, LINE_WELL = 0, 1
 
 class _Mesh(C.Structure):
     _fields_ = [("x0", C.c_double * 3), ("L", C.c_double * 3),
-                ("n", C.c_int32 * 3), ("p", C.c_int32)]
+                ("n", C.c_int32 * 3), ("p", C.c_int32), ("edges", C.c_void_p * 3)]
 
 
 class _Op(C.Structure):
@@ -118,14 +118,26 @@ def _f64(a) -> np.ndarray:
 # ------------------------------------------------------------------ mesh
 @dataclass
 class Mesh:
+    """Box mesh of degree p: uniform, or rectilinear (graded) when edges
+    gives the cell-edge coordinates of every axis (n[d] + 1 increasing values
+    from x0[d] to x0[d] + L[d])."""
     x0: Tuple[float, float, float]
     L: Tuple[float, float, float]
     n: Tuple[int, int, int]
     p: int
+    edges: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = field(default=None, compare=False)
+
+    def __post_init__(self):
+        if self.edges is not None:
+            self.edges = tuple(_f64(e) for e in self.edges)
+            for d in range(3):
+                e = self.edges[d]
+                assert e.size == self.n[d] + 1 and np.all(np.diff(e) > 0)
 
     @classmethod
     def of(cls, scn) -> "Mesh":
-        return cls(tuple(scn.origin), tuple(scn.extent), tuple(scn.ncells), scn.degree)
+        return cls(tuple(scn.origin), tuple(scn.extent), tuple(scn.ncells), scn.degree,
+                   getattr(scn, "edges", None))
 
     def c(self) -> _Mesh:
         m = _Mesh()
@@ -133,8 +145,22 @@ class Mesh:
             m.x0[d] = self.x0[d]
             m.L[d] = self.L[d]
             m.n[d] = self.n[d]
+            m.edges[d] = None if self.edges is None else self.edges[d].ctypes.data
         m.p = self.p
         return m
+
+    def axis_nodes(self, d: int) -> np.ndarray:
+        """Node coordinates along axis d (cell edges, plus the midpoints
+        for p = 2)."""
+        if self.edges is None:
+            return self.x0[d] + np.arange(self.dims[d]) * (self.L[d] / (self.p * self.n[d]))
+        e = self.edges[d]
+        if self.p == 1:
+            return e.copy()
+        out = np.empty(2 * e.size - 1)
+        out[0::2] = e
+        out[1::2] = 0.5 * (e[:-1] + e[1:])
+        return out
 
     @property
     def dims(self):
@@ -151,9 +177,7 @@ class Mesh:
 
     def coords(self):
         """Node coordinates (x, y, z), each of length nnode."""
-        NX, NY, NZ = self.dims
-        ax = [self.x0[d] + np.arange(self.dims[d]) * (self.L[d] / (self.p * self.n[d]))
-              for d in range(3)]
+        ax = [self.axis_nodes(d) for d in range(3)]
         Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
         return X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
 
@@ -384,15 +408,20 @@ def dirichlet(scn, m: Mesh, field: int, t: float):
         mask |= sel
         g[sel] = tf_value(bc.value, X[sel], Y[sel], Z[sel], t)
     hn = [m.L[d] / (m.p * m.n[d]) for d in range(3)]
+
+    def nearest(d, v, N):
+        if m.edges is None:
+            return min(max(int(np.floor((v - m.x0[d]) / hn[d] + 0.5)), 0), N - 1)
+        dist = np.abs(m.axis_nodes(d) - v)
+        return int(N - 1 - np.argmin(dist[::-1]))   # the higher node on a tie
+
     for col in scn.dir_columns:
         if col.field != field:
             continue
-        ci = int(np.floor((col.x - m.x0[0]) / hn[0] + 0.5))
-        cj = int(np.floor((col.y - m.x0[1]) / hn[1] + 0.5))
-        ci = min(max(ci, 0), NX - 1)
-        cj = min(max(cj, 0), NY - 1)
+        ci = nearest(0, col.x, NX)
+        cj = nearest(1, col.y, NY)
         tol = 1e-9 * m.L[2]
-        zs = m.x0[2] + np.arange(NZ) * hn[2]
+        zs = m.axis_nodes(2)
         ks = np.nonzero((zs >= col.z0 - tol) & (zs <= col.z1 + tol))[0]
         nodes = ci + NX * (cj + NY * ks)
         mask[nodes] = True

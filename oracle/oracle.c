@@ -38,6 +38,9 @@ typedef struct {
     double L[3];
     int32_t n[3];
     int32_t p;
+    /* Rectilinear (graded) meshes: cell-edge coordinates per axis, n[d] + 1
+     * increasing values from x0[d] to x0[d] + L[d]; NULL = uniform spacing. */
+    const double *edges[3];
 } orc_mesh;
 
 typedef struct {
@@ -104,7 +107,15 @@ static void lagrange(int p, double xi, double *N, double *dN)
 
 static inline int64_t nodes_dim(const orc_mesh *m, int d) { return (int64_t)m->p * m->n[d] + 1; }
 
-static inline double cell_h(const orc_mesh *m, int d) { return m->L[d] / m->n[d]; }
+/* Lower coordinate and size of cell i along axis d. */
+static inline double cell_lo(const orc_mesh *m, int d, int i)
+{
+    return m->edges[d] ? m->edges[d][i] : m->x0[d] + i * (m->L[d] / m->n[d]);
+}
+static inline double cell_h(const orc_mesh *m, int d, int i)
+{
+    return m->edges[d] ? m->edges[d][i + 1] - m->edges[d][i] : m->L[d] / m->n[d];
+}
 
 /* Nodes whose shape functions share a cell with node i along one axis. */
 static void couple_range(int p, int n, int i, int *lo, int *hi)
@@ -187,7 +198,7 @@ static inline int64_t gnode(const orc_mesh *m, int cx, int cy, int cz, int ax, i
 void orc_element_matrix(const orc_mesh *m, const orc_op *op, int cx, int cy, int cz, double *Ae)
 {
     int p = m->p, n1 = p + 1, nl = n1 * n1 * n1, nq = op->nq;
-    double hx = cell_h(m, 0), hy = cell_h(m, 1), hz = cell_h(m, 2);
+    double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
     int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
@@ -344,7 +355,6 @@ void orc_apply_rows_abs(const orc_mesh *m, const orc_op *op, const double *x, co
 void orc_load_qp(const orc_mesh *m, int nq, const double *fq, double *out)
 {
     int p = m->p, n1 = p + 1;
-    double hx = cell_h(m, 0), hy = cell_h(m, 1), hz = cell_h(m, 2);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     double B[MAXQ][3], D[MAXQ][3];
@@ -354,6 +364,7 @@ void orc_load_qp(const orc_mesh *m, int nq, const double *fq, double *out)
         for (int cy = 0; cy < m->n[1]; cy++)
             for (int cx = 0; cx < m->n[0]; cx++) {
                 int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
                 for (int az = 0; az < n1; az++)
                     for (int ay = 0; ay < n1; ay++)
                         for (int ax = 0; ax < n1; ax++) {
@@ -374,7 +385,6 @@ void orc_load_qp(const orc_mesh *m, int nq, const double *fq, double *out)
 void orc_load_gradz(const orc_mesh *m, const double *g, int nq, double *out)
 {
     int p = m->p, n1 = p + 1;
-    double hx = cell_h(m, 0), hy = cell_h(m, 1), hz = cell_h(m, 2);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     double B[MAXQ][3], D[MAXQ][3];
@@ -383,6 +393,7 @@ void orc_load_gradz(const orc_mesh *m, const double *g, int nq, double *out)
         for (int cy = 0; cy < m->n[1]; cy++)
             for (int cx = 0; cx < m->n[0]; cx++) {
                 int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
                 for (int az = 0; az < n1; az++)
                     for (int ay = 0; ay < n1; ay++)
                         for (int ax = 0; ax < n1; ax++) {
@@ -404,7 +415,6 @@ void orc_load_face(const orc_mesh *m, int face, double value, int nq, double *ou
     int p = m->p, n1 = p + 1;
     int dn = face / 2, side = face % 2;
     int d1 = (dn + 1) % 3, d2 = (dn + 2) % 3;
-    double h1 = cell_h(m, d1), h2 = cell_h(m, d2);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     double B[MAXQ][3], D[MAXQ][3];
@@ -415,6 +425,7 @@ void orc_load_face(const orc_mesh *m, int face, double value, int nq, double *ou
         for (int c1 = 0; c1 < m->n[d1]; c1++)
             for (int a2 = 0; a2 < n1; a2++)
                 for (int a1 = 0; a1 < n1; a1++) {
+                    double h1 = cell_h(m, d1, c1), h2 = cell_h(m, d2, c2);
                     double s = 0.0;
                     for (int q2 = 0; q2 < nq; q2++)
                         for (int q1 = 0; q1 < nq; q1++)
@@ -430,7 +441,18 @@ void orc_load_face(const orc_mesh *m, int face, double value, int nq, double *ou
 /* Cell and local coordinate of a point along axis d (closed box). */
 static void locate(const orc_mesh *m, int d, double x, int *c, double *xi)
 {
-    double h = cell_h(m, d);
+    if (m->edges[d]) {
+        /* last cell whose lower edge is <= x, within 0 .. n-1 */
+        int lo = 0, hi = m->n[d] - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) / 2;
+            if (m->edges[d][mid] <= x) lo = mid; else hi = mid - 1;
+        }
+        *c = lo;
+        *xi = (x - m->edges[d][lo]) / (m->edges[d][lo + 1] - m->edges[d][lo]);
+        return;
+    }
+    double h = cell_h(m, d, 0);
     double s = (x - m->x0[d]) / h;
     int ci = (int)floor(s);
     if (ci < 0) ci = 0;
@@ -450,11 +472,10 @@ void orc_load_line(const orc_mesh *m, double x, double y, double z0, double z1, 
     double Bx[3], By[3], dd[3];
     lagrange(p, xi, Bx, dd);
     lagrange(p, eta, By, dd);
-    double hz = cell_h(m, 2);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     for (int cz = 0; cz < m->n[2]; cz++) {
-        double zlo = m->x0[2] + cz * hz, zhi = zlo + hz;
+        double hz = cell_h(m, 2, cz), zlo = cell_lo(m, 2, cz), zhi = zlo + hz;
         double a = z0 > zlo ? z0 : zlo, b = z1 < zhi ? z1 : zhi;
         if (!(b > a)) continue;
         for (int az = 0; az < n1; az++) {
@@ -485,12 +506,11 @@ int64_t orc_line_mass(const orc_mesh *m, double x, double y, double z0, double z
     double Bx[3], By[3], dd[3];
     lagrange(p, xi, Bx, dd);
     lagrange(p, eta, By, dd);
-    double hz = cell_h(m, 2);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     int64_t cnt = 0;
     for (int cz = 0; cz < m->n[2]; cz++) {
-        double zlo = m->x0[2] + cz * hz, zhi = zlo + hz;
+        double hz = cell_h(m, 2, cz), zlo = cell_lo(m, 2, cz), zhi = zlo + hz;
         double a = z0 > zlo ? z0 : zlo, b = z1 < zhi ? z1 : zhi;
         if (!(b > a)) continue;
         double Mz[3][3] = {{0}};
@@ -549,7 +569,6 @@ void orc_flux_qp(const orc_mesh *m, int nq, const double *kc, const double *P, d
                  double *out)
 {
     int p = m->p, n1 = p + 1;
-    double hx = cell_h(m, 0), hy = cell_h(m, 1), hz = cell_h(m, 2);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     double B[MAXQ][3], D[MAXQ][3];
@@ -560,6 +579,7 @@ void orc_flux_qp(const orc_mesh *m, int nq, const double *kc, const double *P, d
         for (int cy = 0; cy < m->n[1]; cy++)
             for (int cx = 0; cx < m->n[0]; cx++) {
                 int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
+                double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
                 for (int qz = 0; qz < nq; qz++)
                     for (int qy = 0; qy < nq; qy++)
                         for (int qx = 0; qx < nq; qx++) {

@@ -65,7 +65,7 @@ class Allocator(C.Structure):
 class MeshDesc(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("extent", C.c_double * 3), ("ncells", C.c_int32 * 3),
                 ("degree", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
-                ("alloc", Allocator)]
+                ("alloc", Allocator), ("edges", C.c_void_p * 3)]
 
 
 class Materials(C.Structure):
@@ -209,7 +209,7 @@ class Mesh:
     """Owner of one hts_mesh."""
 
     def __init__(self, origin, extent, ncells, degree=1, device=0, stream=None,
-                 torch_allocator=True):
+                 torch_allocator=True, edges=None):
         L = load()
         import torch
         self.device = int(device)
@@ -222,6 +222,16 @@ class Mesh:
             desc.ncells[k] = int(ncells[k])
         desc.degree = int(degree)
         desc.device = self.device
+        keep = []
+        if edges is not None:
+            for k in range(3):
+                if edges[k] is None:
+                    continue
+                e = np.ascontiguousarray(edges[k], dtype=np.float64)
+                if e.size != int(ncells[k]) + 1:
+                    raise ValueError("edges[%d] must have ncells + 1 values" % k)
+                keep.append(e)
+                desc.edges[k] = e.ctypes.data
         desc.stream = C.c_void_p(int(stream)) if stream else None
         if torch_allocator:
             desc.alloc = _torch_allocator(self.device)
@@ -441,7 +451,9 @@ def conv3d(op, cin, cout, stride, din, x=None, w=None, bias=None, g=None):
 # --------------------------------------------------- scenario marshalling
 def _node_coords(scn):
     p = scn.degree
-    ax = [scn.origin[d] + np.arange(p * scn.ncells[d] + 1) * (scn.extent[d] / (p * scn.ncells[d]))
+    edges = getattr(scn, "edges", None)
+    ax = [np.asarray(edges[d], dtype=np.float64) if edges is not None and edges[d] is not None
+          else scn.origin[d] + np.arange(p * scn.ncells[d] + 1) * (scn.extent[d] / (p * scn.ncells[d]))
           for d in range(3)]
     Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
     return X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
@@ -458,7 +470,8 @@ def from_scenario(scn, device=0, stream=None, initial=True, opts=None) -> Mesh:
     """Create and fill a Mesh from a synth.Scenario (same arrays the oracle
     receives).  With initial=True the state is set from the scenario's
     initial functions, and the steady pressure is solved when requested."""
-    m = Mesh(scn.origin, scn.extent, scn.ncells, scn.degree, device, stream)
+    m = Mesh(scn.origin, scn.extent, scn.ncells, scn.degree, device, stream,
+             edges=getattr(scn, "edges", None))
     m.set_materials(scn.permeability, scn.porosity, scn.lambda_solid, scn.rhoc_solid,
                     scn.rho_w, scn.mu_w, scn.c_w, scn.lambda_w, scn.g, scn.B_poro,
                     hydraulic_conductivity=getattr(scn, "hydraulic_conductivity", None),

@@ -28,7 +28,8 @@ struct BcDev {
     int32_t faces[6];          // Dirichlet faces in the order they were set
     TimeFnDev ftf[6];
     double x0, y0, z0;         // origin
-    double dx, dy, dz;         // node spacing
+    double dx, dy, dz;         // node spacing (uniform meshes)
+    const double *xn, *yn, *zn;   // node coordinates per axis (graded meshes; null = uniform)
     const int32_t *colspec;    // [NX*NY] Dirichlet column spec per node column or -1 (null = none)
     const TimeFnDev *coltf;    // column specs
 };

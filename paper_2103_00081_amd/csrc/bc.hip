@@ -20,7 +20,8 @@ __global__ __launch_bounds__(256) void k_dirichlet(const OpDev *__restrict__ ops
         const int64_t n = e - o.off;
         int i, j, k;
         node_ijk(o, n, i, j, k);
-        const double x = b.x0 + i * b.dx, y = b.y0 + j * b.dy, z = b.z0 + k * b.dz;
+        const double x = b.xn ? b.xn[i] : b.x0 + i * b.dx, y = b.yn ? b.yn[j] : b.y0 + j * b.dy,
+                     z = b.zn ? b.zn[k] : b.z0 + k * b.dz;
         double v = 0.0;
         for (int f = 0; f < b.nface; f++) {
             const int face = b.faces[f];

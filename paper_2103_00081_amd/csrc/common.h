@@ -66,7 +66,11 @@ struct OpDev {
     int32_t NX, NY, NZ;        // nodes
     int32_t p;                 // degree
     int32_t dmask;             // Dirichlet faces: bit f for face f
-    double hx, hy, hz;
+    double hx, hy, hz;         // cell sizes (uniform meshes)
+    // graded (rectilinear) meshes: cell sizes along each axis and node z
+    // coordinates; null on uniform meshes
+    const double *hxs, *hys, *hzs;
+    const double *zn;
     double cm;                 // pressure: mass coefficient (1 transient, 0 steady)
     double cs;                 // stiffness scale: pressure dt*B (or 1), heat dt
     double cadv;               // heat: dt * c_w
@@ -149,7 +153,7 @@ struct LevelGeo {              // one instance on one multigrid level
 // ------------------------------------------------------------ launchers
 // Operator kernels (op_q1.hip / op_q2.hip)
 template <typename T>
-void launch_apply(int degree, int field, int epi, bool masked, const OpDev *ops, const WorkItem *work,
+void launch_apply(int degree, int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work,
                   int nwork, const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
 // Setup kernels, one instance per launch (op is passed by value).
 // Inverse of the diagonal of the symmetric part of the operator (constrained

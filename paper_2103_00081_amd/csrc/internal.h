@@ -137,6 +137,13 @@ struct hts_mesh {
     int N[3] = {0, 0, 0};     // nodes
     double x0[3] = {0, 0, 0}, L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
     int64_t nnode = 0, ncell = 0;
+    // graded (rectilinear) meshes: cell edges and node coordinates per axis
+    // (host), cell sizes and node coordinates on the device
+    bool graded = false;
+    std::vector<double> edge[3], node[3];
+    hts::DBuf<double> dh[3], dnode[3];
+    double cell_lo(int d, int i) const { return graded ? edge[d][i] : x0[d] + i * h[d]; }
+    double cell_h(int d, int i) const { return graded ? edge[d][i + 1] - edge[d][i] : h[d]; }
 
     // materials
     bool has_mat = false;

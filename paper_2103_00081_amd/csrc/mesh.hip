@@ -60,11 +60,40 @@ static void gauss(int nq, double *x, double *w)
 
 static int locate(const hts_mesh *m, int d, double x, double *xi)
 {
+    if (m->graded) {
+        // last cell whose lower edge is <= x, within 0 .. n-1
+        int lo = 0, hi = m->n[d] - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (m->edge[d][mid] <= x) lo = mid;
+            else hi = mid - 1;
+        }
+        *xi = (x - m->edge[d][lo]) / (m->edge[d][lo + 1] - m->edge[d][lo]);
+        return lo;
+    }
     double s = (x - m->x0[d]) / m->h[d];
     int c = (int)std::floor(s);
     c = std::max(0, std::min(c, m->n[d] - 1));
     *xi = s - c;
     return c;
+}
+
+// Node nearest to x along axis d: round half up on uniform axes; on graded
+// axes the node at the smallest distance, the higher one on a tie.
+static int nearest_node(const hts_mesh *m, int d, double x)
+{
+    if (!m->graded) {
+        const double hn = m->L[d] / (m->p * m->n[d]);
+        const int c = (int)std::floor((x - m->x0[d]) / hn + 0.5);
+        return std::max(0, std::min(c, m->N[d] - 1));
+    }
+    int best = 0;
+    double bd = std::fabs(m->node[d][0] - x);
+    for (int i = 1; i < m->N[d]; i++) {
+        const double dd = std::fabs(m->node[d][i] - x);
+        if (dd <= bd) { bd = dd; best = i; }
+    }
+    return best;
 }
 
 static inline int64_t node_index(const hts_mesh *m, int i, int j, int k)
@@ -92,7 +121,7 @@ static std::vector<Seg> segments(const hts_mesh *m, double z0, double z1)
 {
     std::vector<Seg> out;
     for (int cz = 0; cz < m->n[2]; cz++) {
-        double lo = m->x0[2] + cz * m->h[2], hi = lo + m->h[2];
+        double lo = m->cell_lo(2, cz), hi = lo + m->cell_h(2, cz);
         double a = std::max(z0, lo), b = std::min(z1, hi);
         if (b > a) out.push_back({cz, a, b});
     }
@@ -130,12 +159,12 @@ static void build_sources(hts_mesh *m)
             double gx[3], gw[3];
             gauss(n1, gx, gw);
             for (const Seg &sg : segments(m, ln.z0, ln.z1)) {
-                double zlo = m->x0[2] + sg.cz * m->h[2];
+                double zlo = m->cell_lo(2, sg.cz), hz = m->cell_h(2, sg.cz);
                 double Iz[3] = {0, 0, 0};
                 for (int q = 0; q < n1; q++) {
                     double z = sg.a + (sg.b - sg.a) * gx[q];
                     double Bz[3];
-                    basis1(p, (z - zlo) / m->h[2], Bz);
+                    basis1(p, (z - zlo) / hz, Bz);
                     for (int s = 0; s < n1; s++) Iz[s] += gw[q] * (sg.b - sg.a) * Bz[s];
                 }
                 for (int az = 0; az < n1; az++)
@@ -153,23 +182,20 @@ static void build_sources(hts_mesh *m)
             int sid = add_src(fs.tf, -1.0, 0);
             const int dn = fs.face / 2, side = fs.face % 2;
             const int d1 = (dn + 1) % 3, d2 = (dn + 2) % 3;
-            double I1[3], I2[3];
             // int_0^h N_a: Q1 h/2, h/2; Q2 h/6, 2h/3, h/6
-            for (int a = 0; a < n1; a++) {
-                double u = (p == 1) ? 0.5 : (a == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
-                I1[a] = u * m->h[d1];
-                I2[a] = u * m->h[d2];
-            }
+            double U[3];
+            for (int a = 0; a < n1; a++) U[a] = (p == 1) ? 0.5 : (a == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
             const int cn = side ? m->n[dn] - 1 : 0, an = side ? p : 0;
             for (int c2 = 0; c2 < m->n[d2]; c2++)
                 for (int c1 = 0; c1 < m->n[d1]; c1++)
                     for (int a2 = 0; a2 < n1; a2++)
                         for (int a1 = 0; a1 < n1; a1++) {
+                            const double I1a = U[a1] * m->cell_h(d1, c1), I2a = U[a2] * m->cell_h(d2, c2);
                             int idx[3];
                             idx[dn] = p * cn + an;
                             idx[d1] = p * c1 + a1;
                             idx[d2] = p * c2 + a2;
-                            acc[node_index(m, idx[0], idx[1], idx[2])][sid] += I1[a1] * I2[a2];
+                            acc[node_index(m, idx[0], idx[1], idx[2])][sid] += I1a * I2a;
                         }
         }
         SrcRows &R = m->src[f];
@@ -210,12 +236,12 @@ static void build_line_operator(hts_mesh *m)
         double gx[3], gw[3];
         gauss(n1, gx, gw);
         for (const Seg &sg : segments(m, ln.z0, ln.z1)) {
-            double zlo = m->x0[2] + sg.cz * m->h[2];
+            double zlo = m->cell_lo(2, sg.cz), hz = m->cell_h(2, sg.cz);
             double Mz[3][3] = {{0}};
             for (int q = 0; q < n1; q++) {
                 double z = sg.a + (sg.b - sg.a) * gx[q];
                 double Bz[3];
-                basis1(p, (z - zlo) / m->h[2], Bz);
+                basis1(p, (z - zlo) / hz, Bz);
                 for (int s1 = 0; s1 < n1; s1++)
                     for (int t1 = 0; t1 < n1; t1++) Mz[s1][t1] += gw[q] * (sg.b - sg.a) * Bz[s1] * Bz[t1];
             }
@@ -322,7 +348,6 @@ void prepare_mesh(hts_mesh *m)
     if (!m->dirty) return;
     if (!m->has_mat) throw Error(HTS_ERR_STATE, "materials not set");
     const int64_t ncol = (int64_t)m->N[0] * m->N[1];
-    const double hn[3] = {m->L[0] / (m->p * m->n[0]), m->L[1] / (m->p * m->n[1]), m->L[2] / (m->p * m->n[2])};
     for (int f = 0; f < 2; f++) {
         int dm = 0;
         for (const FaceSpec &fs : m->bcs[f])
@@ -337,13 +362,10 @@ void prepare_mesh(hts_mesh *m)
             const double tol = 1e-9 * m->L[2];
             for (size_t s = 0; s < m->cols[f].size(); s++) {
                 const ColSpec &c = m->cols[f][s];
-                int ci = (int)std::floor((c.x - m->x0[0]) / hn[0] + 0.5);
-                int cj = (int)std::floor((c.y - m->x0[1]) / hn[1] + 0.5);
-                ci = std::max(0, std::min(ci, m->N[0] - 1));
-                cj = std::max(0, std::min(cj, m->N[1] - 1));
+                const int ci = nearest_node(m, 0, c.x), cj = nearest_node(m, 1, c.y);
                 int lo = -1, hi = -1;
                 for (int k = 0; k < m->N[2]; k++) {
-                    double z = m->x0[2] + k * hn[2];
+                    const double z = m->node[2][k];
                     if (z >= c.z0 - tol && z <= c.z1 + tol) {
                         if (lo < 0) lo = k;
                         hi = k;
@@ -406,6 +428,10 @@ OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, b
     o.p = m->p;
     o.dmask = m->dmask[field];
     o.hx = m->h[0]; o.hy = m->h[1]; o.hz = m->h[2];
+    o.hxs = m->graded ? m->dh[0].p : nullptr;
+    o.hys = m->graded ? m->dh[1].p : nullptr;
+    o.hzs = m->graded ? m->dh[2].p : nullptr;
+    o.zn = m->graded ? m->dnode[2].p : nullptr;
     o.rho_g = m->rho_w * m->g;
     o.field = field;
     o.nnode = m->nnode;
@@ -465,11 +491,22 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
     return guard([&] {
         ARG_CHECK(desc && out, "null argument");
         ARG_CHECK(desc->degree == 1 || desc->degree == 2, "degree must be 1 or 2");
+        bool graded = false;
         for (int d = 0; d < 3; d++) {
             ARG_CHECK(desc->ncells[d] >= 1, "ncells must be >= 1");
             ARG_CHECK(desc->extent[d] > 0.0, "extent must be > 0");
             ARG_CHECK((int64_t)desc->degree * desc->ncells[d] + 1 < 65535, "too many nodes along an axis");
+            if (const double *e = desc->edges[d]) {
+                graded = true;
+                const double tol = 1e-9 * desc->extent[d];
+                ARG_CHECK(std::fabs(e[0] - desc->origin[d]) <= tol &&
+                              std::fabs(e[desc->ncells[d]] - (desc->origin[d] + desc->extent[d])) <= tol,
+                          "graded axis must span [origin, origin + extent]");
+                for (int i = 0; i < desc->ncells[d]; i++)
+                    ARG_CHECK(e[i + 1] > e[i], "cell edges must increase strictly");
+            }
         }
+        ARG_CHECK(!graded || desc->degree == 1, "graded meshes are supported for degree 1");
         HTS_HIP(hipSetDevice(desc->device));
         std::unique_ptr<hts_mesh> m(new hts_mesh());
         m->desc = *desc;
@@ -489,6 +526,31 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
             m->ncell *= m->n[d];
         }
         ARG_CHECK(m->nnode < (int64_t)1 << 31, "mesh too large for 32-bit node indices");
+        // node coordinates of every axis; graded meshes keep their edges and
+        // upload the cell sizes and node coordinates
+        m->graded = graded;
+        for (int d = 0; d < 3; d++) {
+            m->edge[d].resize(m->n[d] + 1);
+            for (int i = 0; i <= m->n[d]; i++)
+                m->edge[d][i] = desc->edges[d] ? desc->edges[d][i] : m->x0[d] + i * m->h[d];
+            if (desc->edges[d]) {
+                m->edge[d][0] = m->x0[d];
+                m->edge[d][m->n[d]] = m->x0[d] + m->L[d];
+            }
+            m->node[d].resize(m->N[d]);
+            const double hn = m->L[d] / (m->p * m->n[d]);
+            for (int i = 0; i < m->N[d]; i++) m->node[d][i] = graded ? m->edge[d][i] : m->x0[d] + i * hn;
+            m->desc.edges[d] = nullptr;   // the caller's array is not kept
+        }
+        if (graded) {
+            for (int d = 0; d < 3; d++) {
+                std::vector<double> hs(m->n[d]);
+                for (int i = 0; i < m->n[d]; i++) hs[i] = m->edge[d][i + 1] - m->edge[d][i];
+                m->dh[d].upload(&m->alloc, hs, m->stream);
+                m->dnode[d].upload(&m->alloc, m->node[d], m->stream);
+            }
+            HTS_HIP(hipStreamSynchronize(m->stream));
+        }
         m->P.alloc(&m->alloc, m->nnode);
         m->T.alloc(&m->alloc, m->nnode);
         m->P.zero(m->stream);

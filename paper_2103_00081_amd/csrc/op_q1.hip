@@ -133,7 +133,7 @@ __device__ __forceinline__ void cell_convect(const T u[8], const T P[8], T ax_, 
                 w[x + 2 * y + 4 * z] += (ax[y + 2 * z] + ay[x + 2 * z]) + az[x + 2 * y];
 }
 
-template <typename T, int FIELD, int EPI, bool MASKED>
+template <typename T, int FIELD, int EPI, bool MASKED, bool GRADED>
 __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                                                   const WorkItem *__restrict__ work,
                                                   const T *__restrict__ X, T *__restrict__ Y,
@@ -224,6 +224,19 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const T vx = T(-cw8 / (o.hx * o.hx)), vy = T(-cw8 / (o.hy * o.hy)), vz = T(-cw8 / (o.hz * o.hz));
     const T pz0 = T(o.rho_g * o.hz);
     const T cm = T(o.cm);
+    // graded meshes: the factors depend on the cell column's hx, hy (fixed
+    // for this thread) and on the layer height, and are formed per layer
+    const bool graded = GRADED && o.hzs != nullptr;
+    double gihx = 0.0, gihy = 0.0, ghxy = 0.0, grx = 0.0, gry = 0.0;
+    if (graded) {
+        const int ix = cx < 0 ? 0 : (cx >= nx ? nx - 1 : cx), iy = cy < 0 ? 0 : (cy >= ny ? ny - 1 : cy);
+        const double ghx = o.hxs[ix], ghy = o.hys[iy];
+        gihx = 1.0 / ghx;
+        gihy = 1.0 / ghy;
+        ghxy = ghx * ghy;
+        grx = ghy * gihx;     // hy / hx
+        gry = ghx * gihy;     // hx / hy
+    }
     T c0 = T(0), c1 = T(0), c2 = T(0);
     if (CHEB) {
         const double *Sc = ep.S + (int64_t)wi.inst * NSLOT;
@@ -382,17 +395,32 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                 u[a] = xs[x0][ty + (a >> 1)][tx + (a & 1)];
                 u[a + 4] = xs[x1][ty + (a >> 1)][tx + (a & 1)];
             }
+            T lfm = fm, lfx = fx, lfy = fy, lfz = fz, lvx = vx, lvy = vy, lvz = vz, lpz0 = pz0;
+            if (graded) {
+                const double hz = o.hzs[L], ihz = 1.0 / hz, V = ghxy * hz;
+                lfm = T(V / 216.0);
+                lfx = T(o.cs * (grx * hz) / 36.0);
+                lfy = T(o.cs * (gry * hz) / 36.0);
+                lfz = T(o.cs * (ghxy * ihz) / 36.0);
+                if (FIELD) {
+                    const double cw8 = o.cadv * V * 0.125;
+                    lvx = T(-cw8 * (gihx * gihx));
+                    lvy = T(-cw8 * (gihy * gihy));
+                    lvz = T(-cw8 * (ihz * ihz));
+                    lpz0 = T(o.rho_g * hz);
+                }
+            }
             if (FIELD == 0) {
-                cell_mass_stiff(u, cm * fm, ck * fx, ck * fy, ck * fz, w);
+                cell_mass_stiff(u, cm * lfm, ck * lfx, ck * lfy, ck * lfz, w);
             } else {
-                cell_mass_stiff(u, cc * fm, cl * fx, cl * fy, cl * fz, w);
+                cell_mass_stiff(u, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
                 T pp[8];
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
                     pp[a] = ps[FIELD ? b0 : 0][ty + (a >> 1)][tx + (a & 1)];
                     pp[a + 4] = ps[FIELD ? b1 : 0][ty + (a >> 1)][tx + (a & 1)];
                 }
-                cell_convect(u, pp, ck * vx, ck * vy, ck * vz, pz0, w);
+                cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
             }
 #pragma unroll
             for (int a = 0; a < 4; a++) { bot[a] = w[a]; tp[a] = w[a + 4]; }
@@ -416,6 +444,14 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
 }
 
 // ----------------------------------------------------------- setup kernels
+// size of cell c along axis d (graded meshes: from the per-axis tables)
+__device__ __forceinline__ static double cell_h(const OpDev &o, int d, int c)
+{
+    if (d == 0) return o.hxs ? o.hxs[c] : o.hx;
+    if (d == 1) return o.hys ? o.hys[c] : o.hy;
+    return o.hzs ? o.hzs[c] : o.hz;
+}
+
 __global__ void k_q1_inv_diag(OpDev o, double *__restrict__ out)
 {
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -424,14 +460,15 @@ __global__ void k_q1_inv_diag(OpDev o, double *__restrict__ out)
     int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((int64_t)NX * NY));
     ColInfo c = col_info(o, i, j);
     if (constrained(c, k, o.NZ, o.dmask)) { out[n] = 1.0; return; }
-    const double V = o.hx * o.hy * o.hz;
-    const double kd = (o.hy * o.hz / o.hx + o.hx * o.hz / o.hy + o.hx * o.hy / o.hz) / 9.0;
     double d = 0.0;
     for (int dz = -1; dz <= 0; dz++)
         for (int dy = -1; dy <= 0; dy++)
             for (int dx = -1; dx <= 0; dx++) {
                 int a = i + dx, b = j + dy, cc = k + dz;
                 if (a < 0 || a >= o.nx || b < 0 || b >= o.ny || cc < 0 || cc >= o.nz) continue;
+                const double hx = cell_h(o, 0, a), hy = cell_h(o, 1, b), hz = cell_h(o, 2, cc);
+                const double V = hx * hy * hz;
+                const double kd = (hy * hz / hx + hx * hz / hy + hx * hy / hz) / 9.0;
                 int64_t ci = a + (int64_t)o.nx * (b + (int64_t)o.ny * cc);
                 const double *K = static_cast<const double *>(o.k);
                 if (o.field == 0) {
@@ -457,12 +494,12 @@ __global__ void k_q1_stencil(OpDev o, double *__restrict__ S)
     if (constrained(c, k, NZ, o.dmask)) {
         st[13] = 1.0;
     } else {
-        const double h[3] = {o.hx, o.hy, o.hz};
         for (int dz = -1; dz <= 0; dz++)
             for (int dy = -1; dy <= 0; dy++)
                 for (int dx = -1; dx <= 0; dx++) {
                     int cx = i + dx, cy = j + dy, cz = k + dz;
                     if (cx < 0 || cx >= o.nx || cy < 0 || cy >= o.ny || cz < 0 || cz >= o.nz) continue;
+                    const double h[3] = {cell_h(o, 0, cx), cell_h(o, 1, cy), cell_h(o, 2, cz)};
                     int64_t ci = cx + (int64_t)o.nx * (cy + (int64_t)o.ny * cz);
                     double mc, sc;
                     if (o.field == 0) {
@@ -504,13 +541,14 @@ __global__ void k_q1_cell_loads(OpDev o, const double *__restrict__ alpha,
     if (n >= o.nnode) return;
     const int NX = o.NX, NY = o.NY;
     int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((int64_t)NX * NY));
-    const double V8 = o.hx * o.hy * o.hz / 8.0, A4 = o.hx * o.hy / 4.0;
     double s = 0.0;
     for (int dz = -1; dz <= 0; dz++)
         for (int dy = -1; dy <= 0; dy++)
             for (int dx = -1; dx <= 0; dx++) {
                 int cx = i + dx, cy = j + dy, cz = k + dz;
                 if (cx < 0 || cx >= o.nx || cy < 0 || cy >= o.ny || cz < 0 || cz >= o.nz) continue;
+                const double hx = cell_h(o, 0, cx), hy = cell_h(o, 1, cy), hz = cell_h(o, 2, cz);
+                const double V8 = hx * hy * hz / 8.0, A4 = hx * hy / 4.0;
                 int64_t ci = cx + (int64_t)o.nx * (cy + (int64_t)o.ny * cz);
                 if (alpha) s += alpha[ci] * V8;
                 // node is the top corner (az = 1) when the cell lies below it
@@ -522,45 +560,55 @@ __global__ void k_q1_cell_loads(OpDev o, const double *__restrict__ alpha,
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-template <typename T, int FIELD, bool MASKED>
+template <typename T, int FIELD, bool MASKED, bool G>
 static void dispatch_epi(int epi, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
                          const EpiArgs<T> &ep, hipStream_t s)
 {
     dim3 g(nwork), b(256);
     switch (epi) {
-    case EPI_STORE: k_q1_apply<T, FIELD, EPI_STORE, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_RESID: k_q1_apply<T, FIELD, EPI_RESID, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_STORE: k_q1_apply<T, FIELD, EPI_STORE, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_RESID: k_q1_apply<T, FIELD, EPI_RESID, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
     case EPI_RESID_NORM:
-        k_q1_apply<T, FIELD, EPI_RESID_NORM, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep);
+        k_q1_apply<T, FIELD, EPI_RESID_NORM, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep);
         break;
-    case EPI_DOT: k_q1_apply<T, FIELD, EPI_DOT, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_CHEB: k_q1_apply<T, FIELD, EPI_CHEB, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_DOT: k_q1_apply<T, FIELD, EPI_DOT, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_CHEB: k_q1_apply<T, FIELD, EPI_CHEB, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
     case EPI_CHEB0:
         if (!MASKED) throw Error(-1, "EPI_CHEB0 is for masked operators");
-        k_q1_apply<T, FIELD, EPI_CHEB0, true><<<g, b, 0, s>>>(ops, work, x, y, ep);
+        k_q1_apply<T, FIELD, EPI_CHEB0, true, G><<<g, b, 0, s>>>(ops, work, x, y, ep);
         break;
     default: throw Error(-1, "bad epilogue");
     }
 }
 
+template <typename T, bool G>
+static void launch_q1_g(int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork,
+                        const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s)
+{
+    if (field == 0) {
+        if (masked) dispatch_epi<T, 0, true, G>(epi, ops, work, nwork, x, y, ep, s);
+        else dispatch_epi<T, 0, false, G>(epi, ops, work, nwork, x, y, ep, s);
+    } else {
+        if (masked) dispatch_epi<T, 1, true, G>(epi, ops, work, nwork, x, y, ep, s);
+        else dispatch_epi<T, 1, false, G>(epi, ops, work, nwork, x, y, ep, s);
+    }
+}
+
+// graded: some instance has a graded mesh; those kernels form the per-cell
+// factors per layer, the uniform ones keep them in registers
 template <typename T>
-void launch_q1(int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork,
+void launch_q1(int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work, int nwork,
                const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s)
 {
     if (nwork <= 0) return;
-    if (field == 0) {
-        if (masked) dispatch_epi<T, 0, true>(epi, ops, work, nwork, x, y, ep, s);
-        else dispatch_epi<T, 0, false>(epi, ops, work, nwork, x, y, ep, s);
-    } else {
-        if (masked) dispatch_epi<T, 1, true>(epi, ops, work, nwork, x, y, ep, s);
-        else dispatch_epi<T, 1, false>(epi, ops, work, nwork, x, y, ep, s);
-    }
+    if (graded) launch_q1_g<T, true>(field, epi, masked, ops, work, nwork, x, y, ep, s);
+    else launch_q1_g<T, false>(field, epi, masked, ops, work, nwork, x, y, ep, s);
     HTS_LAUNCH_CHECK();
 }
 
-template void launch_q1<double>(int, int, bool, const OpDev *, const WorkItem *, int, const double *,
+template void launch_q1<double>(int, int, bool, bool, const OpDev *, const WorkItem *, int, const double *,
                                 double *, const EpiArgs<double> &, hipStream_t);
-template void launch_q1<float>(int, int, bool, const OpDev *, const WorkItem *, int, const float *,
+template void launch_q1<float>(int, int, bool, bool, const OpDev *, const WorkItem *, int, const float *,
                                float *, const EpiArgs<float> &, hipStream_t);
 
 void launch_q1_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s)

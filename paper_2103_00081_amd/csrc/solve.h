@@ -15,8 +15,8 @@ constexpr int CHUNK_LEN = 1024;       // nodes per block of the vector kernels
 constexpr int CHUNK_LEN_COARSE = 256; // nodes per block on coarse multigrid levels
 
 template <typename T>
-void launch_apply(int degree, int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork,
-                  const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
+void launch_apply(int degree, int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work,
+                  int nwork, const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
 void launch_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s);
 void launch_q1_stencil(const OpDev &op, double *S, hipStream_t s);
 
@@ -88,6 +88,7 @@ struct Batch {
     Alloc *al = nullptr;
     std::vector<int64_t> off;
     int64_t ntot = 0, ctot = 0;
+    bool graded = false;       // some instance has a graded mesh
 
     std::vector<Chunk> hch;
     DBuf<Chunk> ch;

@@ -262,6 +262,8 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->ntot = tot;
     B->ctot = 0;
     for (int i = 0; i < n; i++) B->ctot += ms[i]->ncell;
+    B->graded = false;
+    for (int i = 0; i < n; i++) B->graded = B->graded || ms[i]->graded;
     std::vector<int32_t> sp;
     build_chunks(B->off, cnt, CHUNK_LEN, B->hch, sp);
     B->nch = (int)B->hch.size();
@@ -313,6 +315,9 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
             b.dx = M->L[0] / (M->p * M->n[0]);
             b.dy = M->L[1] / (M->p * M->n[1]);
             b.dz = M->L[2] / (M->p * M->n[2]);
+            b.xn = M->graded ? M->dnode[0].p : nullptr;
+            b.yn = M->graded ? M->dnode[1].p : nullptr;
+            b.zn = M->graded ? M->dnode[2].p : nullptr;
             b.colspec = M->colspec[f].p;
             b.coltf = M->coltf[f].p;
             const SrcRows &R = M->src[f];
@@ -483,7 +488,7 @@ template <typename T>
 void Batch::fine_apply(int field, const OpDev *ops, int epi, bool masked, const T *x, T *y, const EpiArgs<T> &ep)
 {
     if (!g_timing.on) {
-        launch_apply<T>(p, field, epi, masked, ops, work[field].p, nwork[field], x, y, ep, s);
+        launch_apply<T>(p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y, ep, s);
         return;
     }
     TimingRec r{};
@@ -494,7 +499,7 @@ void Batch::fine_apply(int field, const OpDev *ops, int epi, bool masked, const 
     r.bytes = apply_bytes(field, epi, ntot, ctot, sizeof(T));
     r.flops = apply_flops(field, p, ctot);
     HTS_HIP(hipEventRecord(r.a, s));
-    launch_apply<T>(p, field, epi, masked, ops, work[field].p, nwork[field], x, y, ep, s);
+    launch_apply<T>(p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y, ep, s);
     HTS_HIP(hipEventRecord(r.b, s));
     g_timing.recs.push_back(r);
 }
@@ -746,10 +751,10 @@ void Batch::build_tmass(Hier &H, double dt)
         const double alpha = dt * ratio[ratio.size() / 2];
         for (int a = 0; a < 3; a++) {
             const int nn = M->N[a];
-            const double h = M->h[a];
             const bool dlo = (dm >> (2 * a)) & 1, dhi = (dm >> (2 * a + 1)) & 1;
             std::vector<double> A(nn, 0.0), B(nn, 0.0), Cc(nn, 0.0);
             for (int e = 0; e + 1 < nn; e++) {   // cell [e, e+1]
+                const double h = M->cell_h(a, e);
                 B[e] += h / 3.0 + alpha / h;
                 B[e + 1] += h / 3.0 + alpha / h;
                 Cc[e] += h / 6.0 - alpha / h;

@@ -110,6 +110,9 @@ class Scenario:
     hydraulic_conductivity: Optional[np.ndarray] = None
     lambda_bulk: Optional[np.ndarray] = None
     rhoc_bulk: Optional[np.ndarray] = None
+    # Graded (rectilinear) meshes: cell-edge coordinates per axis (ncells + 1
+    # increasing values spanning the box); None = uniform spacing.
+    edges: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
     bcs: List[FaceBC] = field(default_factory=list)
     lines: List[LineSource] = field(default_factory=list)
     dir_columns: List[DirColumn] = field(default_factory=list)
@@ -171,6 +174,26 @@ def layered_lognormal(rng, origin, extent, ncells, n_layers, mean_lo=-12.0,
 
 def _uniform(nc, v):
     return np.full(nc, float(v))
+
+
+def graded_edges(lo: float, hi: float, n: int, fine=(), ratio: float = 3.0,
+                 blend: float = 0.1) -> np.ndarray:
+    """n + 1 cell edges on [lo, hi], cells about `ratio` times smaller inside
+    the intervals `fine` (list of (a, b)) than elsewhere, with smooth
+    transitions `blend` * (hi - lo) wide: the edges are equal quantiles of the
+    mesh density 1 + (ratio - 1) * window(x)."""
+    xs = np.linspace(lo, hi, 20001)
+    rho = np.ones_like(xs)
+    w = max(blend * (hi - lo), 1e-12)
+    for a, b in fine:
+        up = 0.5 * (1.0 + np.tanh((xs - a) / (0.25 * w)))
+        down = 0.5 * (1.0 - np.tanh((xs - b) / (0.25 * w)))
+        rho += (ratio - 1.0) * up * down
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (rho[1:] + rho[:-1]) * np.diff(xs))])
+    cdf /= cdf[-1]
+    e = np.interp(np.linspace(0.0, 1.0, n + 1), cdf, xs)
+    e[0], e[-1] = lo, hi
+    return e
 
 
 # ----------------------------------------------------------------- configs
@@ -313,7 +336,7 @@ T_SEA = 287.45        # K, mean of the site record and the sea temperature
 
 
 def island(seed: int = 6, ncells=(256, 160, 64), n_steps: int = 365,
-           degree: int = 1) -> Scenario:
+           degree: int = 1, graded: bool = False) -> Scenario:
     """Island-style pile field on a 640 x 400 x 100 m box (Section 3.3 on a
     structured mesh): the five soil/rock classes of Table 3 with bulk thermal
     values and a seeded scatter of hydraulic conductivity, the bedrock top on
@@ -324,18 +347,16 @@ def island(seed: int = 6, ncells=(256, 160, 64), n_steps: int = 365,
     hydrostatic on the left face and 5 Pa/m higher across the box on the
     right, no flow elsewhere, starting from the steady solution; energy piles
     60 m long on a 20 m lattice under seeded building footprints, held at
-    288.55 +- 13 K as a square wave of one year (summer half first)."""
+    288.55 +- 13 K as a square wave of one year (summer half first).
+    graded=True refines the mesh three times around the building footprints
+    and over the pile depth (the paper's site mesh is refined around the
+    piles, Fig. 10b)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     origin, extent = (0.0, 0.0, 0.0), (640.0, 400.0, 100.0)
     nx, ny, nz = ncells
     nc = nx * ny * nz
     z_top = origin[2] + extent[2]
-    xc = origin[0] + (np.arange(nx) + 0.5) * extent[0] / nx
-    yc = origin[1] + (np.arange(ny) + 0.5) * extent[1] / ny
-    depth = z_top - _cell_centres_z(origin, extent, ncells)
     a, b = rng.uniform(-1.0, 1.0, size=2)
-    plane = (a * (xc[None, :] / extent[0] - 0.5) + b * (yc[:, None] / extent[1] - 0.5))
-    d_rock = 75.0 + 5.0 * plane / max(1e-12, 0.5 * (abs(a) + abs(b)))   # [ny, nx] in [70, 80]
     piles = set()
     for _ in range(8):
         w, d = rng.uniform(60.0, 160.0), rng.uniform(40.0, 100.0)
@@ -344,6 +365,23 @@ def island(seed: int = 6, ncells=(256, 160, 64), n_steps: int = 365,
         for i in range(int(np.ceil(x0 / 20.0)), int(np.floor((x0 + w) / 20.0)) + 1):
             for j in range(int(np.ceil(y0 / 20.0)), int(np.floor((y0 + d) / 20.0)) + 1):
                 piles.add((i, j))
+    edges = None
+    if graded:
+        px = [20.0 * i for i, _ in piles] or [0.5 * extent[0]]
+        py = [20.0 * j for _, j in piles] or [0.5 * extent[1]]
+        edges = (graded_edges(origin[0], origin[0] + extent[0], nx,
+                              [(min(px) - 20.0, max(px) + 20.0)]),
+                 graded_edges(origin[1], origin[1] + extent[1], ny,
+                              [(min(py) - 20.0, max(py) + 20.0)]),
+                 graded_edges(origin[2], z_top, nz, [(z_top - 70.0, z_top)]))
+        xc, yc = 0.5 * (edges[0][1:] + edges[0][:-1]), 0.5 * (edges[1][1:] + edges[1][:-1])
+        depth = z_top - 0.5 * (edges[2][1:] + edges[2][:-1])
+    else:
+        xc = origin[0] + (np.arange(nx) + 0.5) * extent[0] / nx
+        yc = origin[1] + (np.arange(ny) + 0.5) * extent[1] / ny
+        depth = z_top - _cell_centres_z(origin, extent, ncells)
+    plane = (a * (xc[None, :] / extent[0] - 0.5) + b * (yc[:, None] / extent[1] - 0.5))
+    d_rock = 75.0 + 5.0 * plane / max(1e-12, 0.5 * (abs(a) + abs(b)))   # [ny, nx] in [70, 80]
     cls = np.zeros((nz, ny, nx), dtype=np.int64)
     for q, (_, _, _, _, d_end) in enumerate(ISLAND_LAYERS[:3]):
         cls[depth >= d_end] = q + 1
@@ -355,7 +393,7 @@ def island(seed: int = 6, ncells=(256, 160, 64), n_steps: int = 365,
                  hydraulic_conductivity=np.power(10.0, logK),
                  lambda_bulk=np.array([r[3] for r in ISLAND_LAYERS])[cls],
                  rhoc_bulk=np.array([r[2] for r in ISLAND_LAYERS])[cls],
-                 B_poro=1.0e5, dt=DAY, n_steps=n_steps)
+                 B_poro=1.0e5, dt=DAY, n_steps=n_steps, edges=edges)
     p_left = hydrostatic(z_top, 1.0e5, s.rho_w, s.g)
     p_right = (p_left[0], p_left[1] + 5.0 * extent[0]) + p_left[2:]
     s.bcs = [FaceBC(PRESSURE, 0, DIRICHLET, p_left), FaceBC(PRESSURE, 1, DIRICHLET, p_right)]

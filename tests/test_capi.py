@@ -50,3 +50,31 @@ def test_error_paths_without_device():
     assert L.hts_create_mesh(ctypes.byref(d), ctypes.byref(h)) == -1
     assert b"degree" in L.hts_last_error()
     assert L.hts_apply_operator(None, 0, 0, 1.0, None, None) == -1
+
+
+def test_graded_mesh_validation_without_device():
+    """Graded axes must span the box with increasing edges; degree 1 only."""
+    import numpy as np
+    import paper_2103_00081_amd as hts
+    L = hts.load()
+    h = ctypes.c_void_p()
+
+    def desc(edges_x, degree=1):
+        d = hts.MeshDesc()
+        d.degree = degree
+        for k in range(3):
+            d.origin[k] = 0.0
+            d.extent[k] = 10.0
+            d.ncells[k] = 4
+        d.edges[0] = edges_x.ctypes.data
+        return d
+
+    bad_order = np.array([0.0, 3.0, 2.0, 6.0, 10.0])
+    assert L.hts_create_mesh(ctypes.byref(desc(bad_order)), ctypes.byref(h)) == -1
+    assert b"increase" in L.hts_last_error()
+    short = np.array([0.0, 1.0, 2.0, 6.0, 9.0])
+    assert L.hts_create_mesh(ctypes.byref(desc(short)), ctypes.byref(h)) == -1
+    assert b"span" in L.hts_last_error()
+    ok = np.array([0.0, 1.0, 2.5, 6.0, 10.0])
+    assert L.hts_create_mesh(ctypes.byref(desc(ok, degree=2)), ctypes.byref(h)) == -1
+    assert b"degree 1" in L.hts_last_error()

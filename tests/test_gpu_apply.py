@@ -36,6 +36,21 @@ def small_cases():
     s = synth.config4_instance(3, n_override=11, n_steps=1)
     s.degree, s.name = 2, "c4_q2_small"
     c.append((s.name, s))
+    # graded (rectilinear) Q1 meshes: wells, line heat sources, Dirichlet
+    # columns and Neumann faces on non-uniform cells
+    s = synth.config2(ncells=(20, 18, 9), n_steps=1)
+    s.edges = (synth.graded_edges(0.0, 500.0, 20, [(120.0, 380.0)], ratio=4.0),
+               synth.graded_edges(0.0, 500.0, 18, [(200.0, 300.0)]),
+               synth.graded_edges(0.0, 100.0, 9, [(60.0, 100.0)], ratio=2.0))
+    s.name = "c2_graded"
+    c.append((s.name, s))
+    s = synth.config3(ncells=(33, 17, 12), n_steps=1)
+    s.edges = (synth.graded_edges(0.0, 1000.0, 33, [(250.0, 750.0)]),
+               synth.graded_edges(0.0, 1000.0, 17, [(250.0, 750.0)]),
+               synth.graded_edges(0.0, 200.0, 12, [(160.0, 200.0)]))
+    s.name = "c3_graded"
+    c.append((s.name, s))
+    c.append(("island_graded", synth.island(ncells=(32, 20, 10), n_steps=1, graded=True)))
     return c
 
 

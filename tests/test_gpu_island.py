@@ -69,3 +69,69 @@ def test_island_small_steps(hts, ncells, degree, mode):
     else:
         assert rel(P, Po) <= 1e-8
         assert np.abs(T - To).max() <= 1e-6
+
+
+# ------------------------------------------------ graded (rectilinear) meshes
+@pytest.mark.parametrize("mode", [0, 1])
+def test_island_graded_small_steps(hts, mode):
+    """Three steps of the island field on a mesh refined around the building
+    footprints and over the pile depth (Fig. 10b style grading)."""
+    print_case("island graded mode", mode)
+    scn = synth.island(ncells=(32, 20, 10), n_steps=3, graded=True)
+    o = hts.default_opts(rtol=1e-12, mode=mode)
+    m = hts.from_scenario(scn, opts=o)
+    for _ in range(3):
+        code, st = m.solve_step(scn.dt, o)
+        assert st["status"] == [0, 0], st
+    P, t = m.get_state(0)
+    T, _ = m.get_state(1)
+    Po, To, to = oracle.run(scn, n_steps=3)
+    if mode == 0:
+        assert rel(P, Po) <= 1e-10
+        assert rel(T, To) <= 1e-10
+        assert np.abs(T - To).max() <= 1e-7
+    else:
+        assert rel(P, Po) <= 1e-8
+        assert np.abs(T - To).max() <= 1e-6
+
+
+def test_graded_well_pair_steps(hts):
+    """The layered aquifer's well pair (injection-line operator) on graded
+    cells, refined around the wells; the separable heat preconditioner too."""
+    print_case("c2 graded well pair")
+    scn = synth.config2(ncells=(24, 20, 10), n_steps=2)
+    scn.edges = (synth.graded_edges(0.0, 500.0, 24, [(120.0, 380.0)], ratio=4.0),
+                 synth.graded_edges(0.0, 500.0, 20, [(200.0, 300.0)]),
+                 synth.graded_edges(0.0, 100.0, 10, [(60.0, 100.0)], ratio=2.0))
+    Po, To, to = oracle.run(scn, n_steps=2)
+    for hp in (1, 2):
+        o = hts.default_opts(rtol=1e-12, heat_precond=hp)
+        m = hts.from_scenario(scn, opts=o)
+        for _ in range(2):
+            code, st = m.solve_step(scn.dt, o)
+            assert st["status"] == [0, 0], st
+        P, _ = m.get_state(0)
+        T, _ = m.get_state(1)
+        assert rel(P, Po) <= 1e-10
+        assert rel(T, To) <= 1e-10
+
+
+def test_graded_geotherm_fixed_point(hts):
+    """The layered geotherm on graded cells stays fixed on the GPU too."""
+    from test_oracle_pins import GEO_LAYERS
+    print_case("graded geotherm")
+    gx, gy = np.array([0.0, 4.0, 13.0, 30.0]), np.array([0.0, 15.0, 20.0])
+    gz = np.array([0.0, 3.0, 15.0, 19.0, 30.0, 31.0, 36.0, 40.0])
+    s = geotherm_scn(1, n=(3, 2, 7))
+    s.edges = (gx, gy, gz)
+    zc = 0.5 * (gz[1:] + gz[:-1])[np.arange(s.ncell) // 6]
+    s.lambda_bulk = np.select([zc < a[1] for a in GEO_LAYERS], [a[2] for a in GEO_LAYERS])
+    o = hts.default_opts(rtol=1e-13)
+    m = hts.from_scenario(s, opts=o)
+    X, Y, Z = oracle.Mesh.of(s).coords()
+    T0 = geotherm_exact(Z)
+    m.set_state(1, T0, s.t0)
+    code, st = m.solve_step(s.dt, o)
+    T1, _ = m.get_state(1)
+    assert st["status"] == [0, 0], st
+    assert np.abs(T1 - T0).max() <= 1e-9

@@ -560,6 +560,87 @@ def test_ates_scenario_layout():
     assert T0.max() == pytest.approx(293.15) and T0.min() == pytest.approx(278.15)
 
 
+# ------------------------------------------------ graded (rectilinear) meshes
+GX = np.array([0.0, 7.0, 20.0, 31.0, 45.0, 60.0, 70.0, 81.0, 100.0])
+GY = np.array([0.0, 12.0, 25.0, 50.0, 60.0, 64.0, 80.0, 100.0])
+GZ = np.array([0.0, 5.0, 15.0, 22.0, 30.0, 45.0, 60.0, 63.0, 75.0, 100.0])
+
+
+def test_graded_uniform_darcy_flow_exact():
+    """Hydrostatic pressure plus a linear drop stays exact on graded cells,
+    and q_h = (k dp / L, 0, 0) at every Gauss point."""
+    s = synth.config1()
+    s.ncells = (GX.size - 1, GY.size - 1, GZ.size - 1)
+    nc = int(np.prod(s.ncells))
+    s.permeability, s.porosity = np.full(nc, 1e-12), np.full(nc, 0.3)
+    s.lambda_solid, s.rhoc_solid = np.full(nc, 2.5), np.full(nc, 2e6)
+    s.heat_source = None
+    s.edges = (GX, GY, GZ)
+    m = Mesh.of(s)
+    P, _ = oracle.initial_state(s, m)
+    X, Y, Z = m.coords()
+    assert np.allclose(np.unique(X), GX) and np.allclose(np.unique(Z), GZ)
+    Pex = 1e5 + s.rho_w * s.g * (100.0 - Z) + 1e4 * (1.0 - X / 100.0)
+    assert np.abs(P - Pex).max() <= 1e-12 * np.abs(Pex).max()
+    k = 1e-12 / s.mu_w
+    q = oracle.flux_qp(m, 2, np.full(m.ncell, k), P, s.rho_w * s.g)
+    assert np.allclose(q[:, :, 0], k * 1e4 / 100.0, rtol=1e-9)
+    assert np.abs(q[:, :, 1:]).max() <= 1e-9 * k * 1e4 / 100.0
+
+
+def test_graded_layered_geotherm_is_a_fixed_point():
+    """The layered geotherm of the uniform test on graded cells whose z-edges
+    include the layer interfaces (15 m, 30 m): still in the finite element
+    space, so a step returns it."""
+    gx, gy = np.array([0.0, 4.0, 13.0, 30.0]), np.array([0.0, 15.0, 20.0])
+    gz = np.array([0.0, 3.0, 15.0, 19.0, 30.0, 31.0, 36.0, 40.0])
+    s = geotherm_scn(1, n=(3, 2, 7))
+    s.edges = (gx, gy, gz)
+    k = np.arange(s.ncell) // 6
+    zc = 0.5 * (gz[1:] + gz[:-1])[k]
+    s.lambda_bulk = np.select([zc < a[1] for a in GEO_LAYERS], [a[2] for a in GEO_LAYERS])
+    m = Mesh.of(s)
+    X, Y, Z = m.coords()
+    T0 = geotherm_exact(Z)
+    T1 = oracle.solve_heat(s, m, T0, np.zeros(m.nnode), s.dt)
+    assert np.abs(T1 - T0).max() <= 1e-10
+
+
+def test_graded_heat_energy_balance():
+    """Insulated graded box: the stored heat equals the volume source over the
+    actual cell volumes minus the Neumann flux over the whole face."""
+    s = small_scn(n=(4, 3, 3))
+    s.edges = (np.array([0.0, 0.3, 1.0, 2.2, 3.0]), np.array([0.0, 1.0, 5.0, 8.0]),
+               np.array([0.0, 0.1, 0.5, 1.0]))
+    s.permeability[:] = 0.0
+    s.heat_source = np.random.default_rng(7).uniform(0, 30, s.ncell)
+    s.bcs = [synth.FaceBC(synth.TEMPERATURE, 3, synth.NEUMANN, synth.timefn(0.4))]
+    m = Mesh.of(s)
+    T0 = 290.0 + np.random.default_rng(8).uniform(-1, 1, m.nnode)
+    T1 = oracle.solve_heat(s, m, T0, np.zeros(m.nnode), s.dt)
+    k, lam, cT = oracle.coefficients(s)
+    Mc = oracle.assemble(m, mass=cT)
+    stored = np.ones(m.nnode) @ (Mc @ (T1 - T0))
+    ex, ey, ez = s.edges
+    V = (np.diff(ez)[:, None, None] * np.diff(ey)[None, :, None] * np.diff(ex)[None, None, :]).reshape(-1)
+    expect = s.dt * (V * s.heat_source).sum() - s.dt * 0.4 * (3.0 * 1.0)
+    assert math.isclose(stored, expect, rel_tol=1e-10)
+
+
+def test_graded_dirichlet_column_nearest_node():
+    """On a graded axis a column goes to the nearest node, the higher one on
+    a tie."""
+    s = small_scn(n=(4, 3, 3))
+    s.edges = (np.array([0.0, 0.3, 1.0, 2.2, 3.0]), np.array([0.0, 1.0, 5.0, 8.0]),
+               np.array([0.0, 0.1, 0.5, 1.0]))
+    s.dir_columns = [synth.DirColumn(synth.TEMPERATURE, 0.7, 3.0, 0.0, 1.0, synth.timefn(300.0))]
+    m = Mesh.of(s)
+    mask, g = oracle.dirichlet(s, m, synth.TEMPERATURE, 0.0)
+    X, Y, Z = m.coords()
+    sel = (X == 1.0) & (Y == 5.0)   # 0.7 is nearer 1.0 than 0.3; 3.0 ties 1.0 and 5.0
+    assert mask.sum() == 4 and mask[sel].all() and np.all(g[sel] == 300.0)
+
+
 # ----------------------------------------------------------------- solvers
 def test_iterative_solvers_match_lu():
     s = small_scn(n=(6, 5, 4))
