@@ -4,7 +4,8 @@ Default workload: the layered aquifer (500 x 500 x 100 m, 128 x 128 x 64 Q1
 cells, 1,081,665 nodes per field, injection/extraction well pair, daily
 backward-Euler steps).  --workload selects the others: the energy-pile field
 on 256 x 256 x 128 Q1 or 128 x 128 x 64 Q2 cells (8,520,321 nodes per field),
-the island-style pile field with site boundary data (256 x 160 x 64 Q1), the
+the island-style pile field with site boundary data (256 x 160 x 64 Q1,
+uniform or graded around the piles), the
 three-formation hot-water injection column (64 x 64 x 240 Q1), and 64
 batched design instances of 32^3..96^3 cells advanced together (set
 against a host loop over the instances one at a time).
@@ -65,7 +66,7 @@ def parse():
     ap.add_argument("--modes", default="fp64,fp32_refined",
                     help="comma list of fp64, fp32_refined; the faster one is the headline")
     ap.add_argument("--workload", default="aquifer",
-                    choices=("aquifer", "piles", "piles-q2", "island", "ates", "batch"))
+                    choices=("aquifer", "piles", "piles-q2", "island", "island-graded", "ates", "batch"))
     ap.add_argument("--ncells", default=None, help="cells per axis, e.g. 128,128,64 (default: the workload's)")
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--host-loop", type=int, default=1,
@@ -170,11 +171,14 @@ def workload(a, synth, n_steps):
         return [synth.config3(degree=p, ncells=nc, n_steps=n_steps)], 3, \
             "energy-pile field %dx%dx%d Q%d (%%d nodes/field), 400 seasonal line heat sources, " \
             "regional gradient" % (nc + (p,))
-    if a.workload == "island":
+    if a.workload in ("island", "island-graded"):
         nc = nc or (256, 160, 64)
-        s = synth.island(ncells=nc, n_steps=n_steps)
-        return [s], 6, ("island-style pile field %dx%dx%d Q1 (%%d nodes/field), %d square-wave piles, "
-                         "seasonal surface, geothermal inflow" % (nc + (len(s.dir_columns),)))
+        graded = a.workload == "island-graded"
+        s = synth.island(ncells=nc, n_steps=n_steps, graded=graded)
+        return [s], 6, ("island-style pile field %dx%dx%d Q1%s (%%d nodes/field), %d square-wave piles, "
+                         "seasonal surface, geothermal inflow"
+                         % (nc + (", graded 3:1 around the footprints and the pile depth" if graded else "",
+                                  len(s.dir_columns))))
     if a.workload == "ates":
         nc = nc or (64, 64, 240)
         return [synth.ates(ncells=nc, n_steps=n_steps)], None, \

@@ -70,6 +70,7 @@ struct OpDev {
     // graded (rectilinear) meshes: cell sizes along each axis and node z
     // coordinates; null on uniform meshes
     const double *hxs, *hys, *hzs;
+    const double *ihzs;        // 1 / hz per cell layer
     const double *zn;
     double cm;                 // pressure: mass coefficient (1 transient, 0 steady)
     double cs;                 // stiffness scale: pressure dt*B (or 1), heat dt

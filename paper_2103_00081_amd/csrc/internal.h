@@ -141,7 +141,7 @@ struct hts_mesh {
     // (host), cell sizes and node coordinates on the device
     bool graded = false;
     std::vector<double> edge[3], node[3];
-    hts::DBuf<double> dh[3], dnode[3];
+    hts::DBuf<double> dh[3], dnode[3], dihz;
     double cell_lo(int d, int i) const { return graded ? edge[d][i] : x0[d] + i * h[d]; }
     double cell_h(int d, int i) const { return graded ? edge[d][i + 1] - edge[d][i] : h[d]; }
 

@@ -431,6 +431,7 @@ OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, b
     o.hxs = m->graded ? m->dh[0].p : nullptr;
     o.hys = m->graded ? m->dh[1].p : nullptr;
     o.hzs = m->graded ? m->dh[2].p : nullptr;
+    o.ihzs = m->graded ? m->dihz.p : nullptr;
     o.zn = m->graded ? m->dnode[2].p : nullptr;
     o.rho_g = m->rho_w * m->g;
     o.field = field;
@@ -548,6 +549,10 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
                 for (int i = 0; i < m->n[d]; i++) hs[i] = m->edge[d][i + 1] - m->edge[d][i];
                 m->dh[d].upload(&m->alloc, hs, m->stream);
                 m->dnode[d].upload(&m->alloc, m->node[d], m->stream);
+                if (d == 2) {
+                    for (double &v : hs) v = 1.0 / v;
+                    m->dihz.upload(&m->alloc, hs, m->stream);
+                }
             }
             HTS_HIP(hipStreamSynchronize(m->stream));
         }

@@ -224,18 +224,21 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const T vx = T(-cw8 / (o.hx * o.hx)), vy = T(-cw8 / (o.hy * o.hy)), vz = T(-cw8 / (o.hz * o.hz));
     const T pz0 = T(o.rho_g * o.hz);
     const T cm = T(o.cm);
-    // graded meshes: the factors depend on the cell column's hx, hy (fixed
-    // for this thread) and on the layer height, and are formed per layer
+    // graded meshes: every factor is a per-column part (from this thread's
+    // hx, hy, formed once in double and rounded) times hz or 1 / hz of the
+    // layer (tables, one value per layer)
     const bool graded = GRADED && o.hzs != nullptr;
-    double gihx = 0.0, gihy = 0.0, ghxy = 0.0, grx = 0.0, gry = 0.0;
+    T gm = T(0), gx = T(0), gy = T(0), gz = T(0), gvx = T(0), gvy = T(0), gvz = T(0);
     if (graded) {
         const int ix = cx < 0 ? 0 : (cx >= nx ? nx - 1 : cx), iy = cy < 0 ? 0 : (cy >= ny ? ny - 1 : cy);
-        const double ghx = o.hxs[ix], ghy = o.hys[iy];
-        gihx = 1.0 / ghx;
-        gihy = 1.0 / ghy;
-        ghxy = ghx * ghy;
-        grx = ghy * gihx;     // hy / hx
-        gry = ghx * gihy;     // hx / hy
+        const double ghx = o.hxs[ix], ghy = o.hys[iy], hxy = ghx * ghy;
+        gm = T(hxy / 216.0);                           // x hz
+        gx = T(o.cs * (ghy / ghx) / 36.0);             // x hz
+        gy = T(o.cs * (ghx / ghy) / 36.0);             // x hz
+        gz = T(o.cs * hxy / 36.0);                     // x 1/hz
+        gvx = T(-o.cadv * 0.125 * ghy / ghx);          // x hz
+        gvy = T(-o.cadv * 0.125 * ghx / ghy);          // x hz
+        gvz = T(-o.cadv * 0.125 * hxy);                // x 1/hz
     }
     T c0 = T(0), c1 = T(0), c2 = T(0);
     if (CHEB) {
@@ -280,11 +283,13 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         }
     };
     T cfk = T(0), cfl = T(0), cfc = T(0);
+    double cfh = 0.0, cfih = 0.0;     // graded: hz and 1/hz of the layer
     auto fetch_coef = [&](int L) {
         const int Lc = L < 0 ? 0 : (L >= nz ? nz - 1 : L);
         const int32_t ci = cbase + Lc * cplane;
         cfk = kk[ci];
         if (FIELD) { cfl = lamc[ci]; cfc = cTc[ci]; }
+        if (graded) { cfh = o.hzs[Lc]; cfih = o.ihzs[Lc]; }
     };
     // epilogue operands of one owned node
     const int32_t obase = own_ok ? (int32_t)oc.base : 0;
@@ -314,6 +319,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         const int sx1 = sx + 1 == XR ? 0 : sx + 1, sp1 = sp + 1 == 3 ? 0 : sp + 1;
         if (comp) store_plane(sx1, sp1);
         const T ck = cfk, cl = cfl, cc = cfc;
+        const double lhz = cfh, lihz = cfih;
         if (L + 1 <= ke - 1) {
             fetch_plane(L + 2);
             fetch_coef(L + 1);
@@ -397,17 +403,16 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
             }
             T lfm = fm, lfx = fx, lfy = fy, lfz = fz, lvx = vx, lvy = vy, lvz = vz, lpz0 = pz0;
             if (graded) {
-                const double hz = o.hzs[L], ihz = 1.0 / hz, V = ghxy * hz;
-                lfm = T(V / 216.0);
-                lfx = T(o.cs * (grx * hz) / 36.0);
-                lfy = T(o.cs * (gry * hz) / 36.0);
-                lfz = T(o.cs * (ghxy * ihz) / 36.0);
+                const T hz = T(lhz), ihz = T(lihz);
+                lfm = gm * hz;
+                lfx = gx * hz;
+                lfy = gy * hz;
+                lfz = gz * ihz;
                 if (FIELD) {
-                    const double cw8 = o.cadv * V * 0.125;
-                    lvx = T(-cw8 * (gihx * gihx));
-                    lvy = T(-cw8 * (gihy * gihy));
-                    lvz = T(-cw8 * (ihz * ihz));
-                    lpz0 = T(o.rho_g * hz);
+                    lvx = gvx * hz;
+                    lvy = gvy * hz;
+                    lvz = gvz * ihz;
+                    lpz0 = T(o.rho_g) * hz;
                 }
             }
             if (FIELD == 0) {
