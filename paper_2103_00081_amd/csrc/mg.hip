@@ -41,6 +41,16 @@ __device__ __forceinline__ int parents(int i, int Nf, int *P, double *W)
     return 2;
 }
 
+// the same with always two entries: a single parent is repeated with weight 0
+__device__ __forceinline__ void parents2(int i, int Nf, int *P, double *W)
+{
+    const bool one = (i & 1) == 0 || i == Nf - 1;
+    P[0] = one ? (i + 1) >> 1 : (i - 1) >> 1;
+    P[1] = one ? P[0] : (i + 1) >> 1;
+    W[0] = one ? 1.0 : 0.5;
+    W[1] = one ? 0.0 : 0.5;
+}
+
 template <typename T, int EPI>
 __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ lev, const Chunk *__restrict__ chunks,
                                                  const int32_t *active, const T *__restrict__ X, T *__restrict__ Y,
@@ -61,24 +71,27 @@ __global__ __launch_bounds__(256) void k_stencil(const LevelDev *__restrict__ le
         // instance-local indices fit 32 bits (meshes have < 2^31 nodes)
         const int n = (int)(e - L.off);
         const int nxy = n / NX, i = n - nxy * NX, k = nxy / NY, j = nxy - k * NY;
+        // Neighbours outside the grid have zero coefficients (the assembled
+        // and Galerkin stencils never couple to them): their offsets are
+        // clamped to the node itself, so every load is unconditional and all
+        // 54 of them can be in flight together.
+        const int ox[3] = {i > 0 ? -1 : 0, 0, i < NX - 1 ? 1 : 0};
+        const int oy[3] = {j > 0 ? -NX : 0, 0, j < NY - 1 ? NX : 0};
+        const int oz[3] = {k > 0 ? -(int)pl : 0, 0, k < NZ - 1 ? (int)pl : 0};
+        const int ln = (int)L.n;
         T acc = T(0);
 #pragma unroll
-        for (int dz = -1; dz <= 1; dz++) {
-            if (k + dz < 0 || k + dz >= NZ) continue;
+        for (int dz = 0; dz < 3; dz++)
 #pragma unroll
-            for (int dy = -1; dy <= 1; dy++) {
-                if (j + dy < 0 || j + dy >= NY) continue;
+            for (int dy = 0; dy < 3; dy++)
 #pragma unroll
-                for (int dx = -1; dx <= 1; dx++) {
-                    if (i + dx < 0 || i + dx >= NX) continue;
-                    const int c = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-                    const int nb = n + dx + dy * NX + dz * (int)pl;
+                for (int dx = 0; dx < 3; dx++) {
+                    const int c = dx + 3 * dy + 9 * dz;
+                    const int nb = n + ox[dx] + oy[dy] + oz[dz];
                     // EPI_CHEB0 operand: x0 = c0 D^-1 b
                     const T xv = EPI == EPI_CHEB0 ? c0 * Ii[nb] * Bi[nb] : Xi[nb];
-                    acc += St[(int64_t)c * L.n + n] * xv;
+                    acc += St[c * ln + n] * xv;
                 }
-            }
-        }
         if (EPI == EPI_STORE) {
             Y[e] = acc;
         } else if (EPI == EPI_RESID) {
@@ -187,6 +200,9 @@ __global__ __launch_bounds__(256) void k_restrict(const LevelDev *__restrict__ f
                 }
             }
         }
+        // every child is loaded (the indices of absent children are clamped
+        // into the grid and their weight is 0; constrained children get weight
+        // 0), so the 27 loads are unconditional
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; c++)
@@ -194,13 +210,12 @@ __global__ __launch_bounds__(256) void k_restrict(const LevelDev *__restrict__ f
             for (int b = 0; b < 3; b++)
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
-                    const double w = wx[a] * wy[b] * wz[c];
-                    if (w == 0.0) continue;
+                    double w = wx[a] * wy[b] * wz[c];
                     if (fops) {
                         const int k = zi[c];
-                        if (cxy[b][a] || ((m & 16) && k == 0) || ((m & 32) && k == NZo - 1) ||
-                            (k >= lo[b][a] && k <= hi[b][a]))
-                            continue;
+                        const bool con = cxy[b][a] || ((m & 16) && k == 0) || ((m & 32) && k == NZo - 1) ||
+                                         (k >= lo[b][a] && k <= hi[b][a]);
+                        w = con ? 0.0 : w;
                     }
                     acc += w * (double)rfi[xi[a] + yi[b] * fNX + zi[c] * fpl];
                 }
@@ -224,19 +239,27 @@ __global__ __launch_bounds__(256) void k_prolong_add(const LevelDev *__restrict_
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += 256) {
         const int n = (int)(e - F.off);
         const int nxy = n / fNX, i = n - nxy * fNX, k = nxy / fNY, j = nxy - k * fNY;
+        bool con = false;
         if (fops) {
             const OpDev &o = fops[ch.inst];
-            if (constrained(col_info(o, i, j), k, o.NZ, o.dmask)) continue;
+            con = constrained(col_info(o, i, j), k, o.NZ, o.dmask);
         }
+        // two parents per axis, the second with weight 0 (and the first's
+        // index) where there is one: eight unconditional loads
         int Px[2], Py[2], Pz[2];
         double Wx[2], Wy[2], Wz[2];
-        const int nxp = parents(i, fNX, Px, Wx), nyp = parents(j, fNY, Py, Wy), nzp = parents(k, fNZ, Pz, Wz);
+        parents2(i, fNX, Px, Wx);
+        parents2(j, fNY, Py, Wy);
+        parents2(k, fNZ, Pz, Wz);
         double acc = 0.0;
-        for (int c = 0; c < nzp; c++)
-            for (int b = 0; b < nyp; b++)
-                for (int a = 0; a < nxp; a++)
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int a = 0; a < 2; a++)
                     acc += Wx[a] * Wy[b] * Wz[c] * (double)xci[Px[a] + Py[b] * cNX + Pz[c] * cpl];
-        xf[e] = T((double)xf[e] + acc);
+        if (!con) xf[e] = T((double)xf[e] + acc);
     }
 }
 
