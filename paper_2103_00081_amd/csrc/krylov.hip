@@ -3,6 +3,7 @@
 // and the outer FP64 defect-correction test.
 #include "common.h"
 #include "krylov.h"
+#include "arnoldi.h"
 
 namespace hts {
 
@@ -36,60 +37,12 @@ __global__ void k_gm_begin(int ninst, int32_t *active, double *S, double *g, int
     Si[S_STATUS] = 1;
 }
 
-// Column j of the Hessenberg matrix from classical Gram-Schmidt applied twice:
-// h = h1 + h2.  The new basis vector is w' - V h2 with w' the vector after
-// the first projection; the basis is orthonormal and w' - V h2 is orthogonal
-// to it, so its squared norm is |w'|^2 - |h2|^2, where h2 is small (the
-// second pass only removes rounding), so the difference does not cancel.
-__global__ void k_gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit,
-                             const double *h1, const double *h2, double *H, double *cs, double *sn, double *g,
-                             int32_t *kdim)
+// one thread per instance (the column update itself is in arnoldi.h)
+__global__ void k_gm_arnoldi(int ninst, int32_t *active, double *S, ArnArgs A, const double *h2)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst || !active[i]) return;
-    double *Si = S + (int64_t)i * NSLOT;
-    double *Hi = H + (int64_t)i * (mres + 1) * mres;   // H[r][c] = Hi[r * mres + c]
-    double *ci = cs + (int64_t)i * mres, *si = sn + (int64_t)i * mres;
-    double *gi = g + (int64_t)i * (mres + 1);
-    const double *a1 = h1 + (int64_t)i * (j + 1);
-    const double *a2 = h2 + (int64_t)i * (j + 2);
-    double h22 = 0.0;
-    for (int r = 0; r <= j; r++) {
-        Hi[r * mres + j] = a1[r] + a2[r];
-        h22 += a2[r] * a2[r];
-    }
-    const double hn = sqrt(fmax(a2[j + 1] - h22, 0.0));
-    Hi[(j + 1) * mres + j] = hn;
-    for (int r = 0; r < j; r++) {
-        const double a = Hi[r * mres + j], b = Hi[(r + 1) * mres + j];
-        Hi[r * mres + j] = ci[r] * a + si[r] * b;
-        Hi[(r + 1) * mres + j] = -si[r] * a + ci[r] * b;
-    }
-    const double a = Hi[j * mres + j], b = Hi[(j + 1) * mres + j];
-    const double rho = hypot(a, b);
-    ci[j] = rho > 0.0 ? a / rho : 1.0;
-    si[j] = rho > 0.0 ? b / rho : 0.0;
-    Hi[j * mres + j] = rho;
-    Hi[(j + 1) * mres + j] = 0.0;
-    gi[j + 1] = -si[j] * gi[j];
-    gi[j] = ci[j] * gi[j];
-    kdim[i] = j + 1;
-    Si[S_ITER] += 1.0;
-    const double res2 = gi[j + 1] * gi[j + 1];
-    Si[S_RR] = res2;
-    Si[S_SCALE] = hn > 0.0 ? 1.0 / hn : 0.0;
-    if (!isfinite(res2) || !isfinite(hn) || rho == 0.0) {
-        Si[S_STATUS] = -6;
-        active[i] = 0;
-    } else if (res2 <= Si[S_TOL2] || hn == 0.0) {
-        Si[S_STATUS] = 0;
-        active[i] = 0;
-    } else if (Si[S_ITER] >= maxit) {
-        Si[S_STATUS] = -5;
-        active[i] = 0;
-    } else if (j == mres - 1) {
-        active[i] = 0;   // cycle ends; status stays 1 (restart)
-    }
+    arnoldi_column(i, active, S, A, h2 + (int64_t)i * (A.j + 2));
 }
 
 __global__ void k_gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g,
@@ -183,7 +136,8 @@ void gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_
 void gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit, const double *h1,
                 const double *h2, double *H, double *cs, double *sn, double *g, int32_t *kdim, hipStream_t s)
 {
-    k_gm_arnoldi<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, j, mres, maxit, h1, h2, H, cs, sn, g, kdim);
+    ArnArgs A{j, mres, maxit, 0, h1, H, cs, sn, g, kdim};
+    k_gm_arnoldi<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, A, h2);
     HTS_LAUNCH_CHECK();
 }
 void gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g, const int32_t *kdim,

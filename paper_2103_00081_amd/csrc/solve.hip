@@ -1280,10 +1280,11 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
             vmultidot<T>(vj, V, ld, j + 1, w, partial.p, j + 1);
             vreduce(rch, partial.p, j + 1, RED_NONE, 0, S.p, active.p, 0, 0.0, gh1.p, s);
             vorth_update<T>(vj, V, ld, j + 1, gh1.p, j + 1, w, 1, partial.p, j + 2);
-            vreduce(rch, partial.p, j + 2, RED_NONE, 0, S.p, active.p, 0, 0.0, gh2.p, s);
-            // Hessenberg column and norm (from |w'|^2 - |h2|^2), then the
-            // second projection and the normalisation in one pass
-            gm_arnoldi(n, active.p, S.p, j, mres, maxit, gh1.p, gh2.p, gH.p, gcs.p, gsn.p, gg.p, gkdim.p, s);
+            // the second pass's sums, the Hessenberg column and the norm
+            // (from |w'|^2 - |h2|^2) in one kernel, then the second
+            // projection and the normalisation in one pass
+            const ArnArgs arn{j, mres, maxit, 0, gh1.p, gH.p, gcs.p, gsn.p, gg.p, gkdim.p};
+            vreduce_arnoldi(rch, partial.p, j + 2, S.p, active.p, arn, gh2.p, s);
             vorth_update<T>(vj, V, ld, j + 1, gh2.p, j + 2, w, 0, nullptr, 0, S_SCALE);
         };
         if (use_graph && !g_timing.on) {

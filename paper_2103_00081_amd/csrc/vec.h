@@ -1,5 +1,6 @@
 // Host-side interface of the batched vector kernels (vec.hip).
 #pragma once
+#include "arnoldi.h"
 #include "common.h"
 
 #include <vector>
@@ -31,7 +32,8 @@ enum RedOp {
     RED_CG_BETA = 5,           // BETA = (v0 - v1) / RZ, RZ = v0
     RED_CG_INIT = 6,           // RR = RR0 = v0, ITER = 0, converged if RR <= TOL2
     RED_SET_TOL = 7,           // BB = v0, TOL2 = aux * v0
-    RED_INVSQRT = 8            // S[slot] = v0, S[slot+1] = 1/sqrt(v0)
+    RED_INVSQRT = 8,           // S[slot] = v0, S[slot+1] = 1/sqrt(v0)
+    RED_ARNOLDI = 9            // FGMRES column update (vreduce_arnoldi)
 };
 
 template <typename T> void vfill(const VecCtx &v, T *y, T val);
@@ -93,5 +95,9 @@ void vset_slots(const int *slots, int nslots, const double *const *vals, int n, 
 
 void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
              int maxit, double aux, double *out, hipStream_t s);
+// reduction of the second Gram-Schmidt pass (h2 and |w'|^2, ncomp = j + 2)
+// followed by the Arnoldi column update of each active instance
+void vreduce_arnoldi(const RedCtx &r, const double *partial, int ncomp, double *S, int32_t *active,
+                     const ArnArgs &arn, double *out, hipStream_t s);
 
 }  // namespace hts

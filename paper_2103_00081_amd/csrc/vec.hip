@@ -330,7 +330,7 @@ __device__ void scalar_op(int op, int inst, const double *v, const double *pre, 
 __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partial, int ncomp,
                                                const int32_t *__restrict__ seg_ptr, int single, int op,
                                                int slot, double *S, int32_t *active, int maxit, double aux,
-                                               double *out)
+                                               double *out, ArnArgs arn)
 {
     __shared__ double vals[64];
     const int inst = blockIdx.x;
@@ -387,7 +387,10 @@ __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partia
     if (threadIdx.x == 0 && on) {
         if (out)
             for (int c = 0; c < ncomp; c++) out[(int64_t)inst * ncomp + c] = vals[c];
-        scalar_op(op, inst, vals, pre, S, active, maxit, slot, aux);
+        // FGMRES: the second-pass coefficients and |w'|^2 go straight into
+        // the Arnoldi column update of this instance
+        if (op == RED_ARNOLDI) arnoldi_column(inst, active, S, arn, vals);
+        else scalar_op(op, inst, vals, pre, S, active, maxit, slot, aux);
     }
 }
 
@@ -521,7 +524,15 @@ void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot
              int maxit, double aux, double *out, hipStream_t s)
 {
     k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, r.single, op, slot, S,
-                                                          active, maxit, aux, out);
+                                                          active, maxit, aux, out, ArnArgs{});
+    HTS_LAUNCH_CHECK();
+}
+
+void vreduce_arnoldi(const RedCtx &r, const double *partial, int ncomp, double *S, int32_t *active,
+                     const ArnArgs &arn, double *out, hipStream_t s)
+{
+    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, r.single, RED_ARNOLDI, 0, S,
+                                                          active, 0, 0.0, out, arn);
     HTS_LAUNCH_CHECK();
 }
 
