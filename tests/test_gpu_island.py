@@ -135,3 +135,23 @@ def test_graded_geotherm_fixed_point(hts):
     T1, _ = m.get_state(1)
     assert st["status"] == [0, 0], st
     assert np.abs(T1 - T0).max() <= 1e-9
+
+
+def test_graded_and_uniform_meshes_in_one_batch(hts):
+    """A batch mixing a graded and a uniform mesh launches the graded kernel
+    instances for both; each instance still gives its solo answer bit for
+    bit."""
+    print_case("graded + uniform batch")
+    scns = [synth.island(ncells=(24, 16, 8), n_steps=2, graded=True),
+            synth.island(ncells=(20, 12, 8), n_steps=2)]
+    o = hts.default_opts(rtol=1e-10)
+    solo = []
+    for s in scns:
+        m = hts.from_scenario(s, opts=o)
+        hts.advance([m], 2, s.dt, o)
+        solo.append((m.get_state(0)[0], m.get_state(1)[0]))
+    ms = [hts.from_scenario(s, opts=o) for s in scns]
+    hts.advance(ms, 2, scns[0].dt, o)
+    for m, (P, T) in zip(ms, solo):
+        assert np.array_equal(m.get_state(0)[0], P)
+        assert np.array_equal(m.get_state(1)[0], T)

@@ -272,3 +272,36 @@ def test_batched_equals_solo_bitwise(hts):
     for m, (P, T) in zip(ms, solo):
         assert np.array_equal(m.get_state(0)[0], P)
         assert np.array_equal(m.get_state(1)[0], T)
+
+
+def test_cached_batch_is_dropped_when_a_mesh_changes(hts):
+    """hts_advance keeps the batch of a mesh list between calls; changing a
+    member's boundary data must rebuild it.  Two calls of one step equal one
+    call of two steps bit for bit, and after a change the batch answers like
+    freshly created meshes with the new data."""
+    print_case("batch cache")
+    scns = [synth.config4_instance(i, n_override=n, n_steps=3) for i, n in [(0, 12), (1, 9)]]
+    o = hts.default_opts(rtol=1e-10)
+    a = [hts.from_scenario(s, opts=o) for s in scns]
+    b = [hts.from_scenario(s, opts=o) for s in scns]
+    hts.advance(a, 2, scns[0].dt, o)
+    hts.advance(b, 1, scns[0].dt, o)
+    hts.advance(b, 1, scns[0].dt, o)
+    for ma, mb in zip(a, b):
+        assert np.array_equal(ma.get_state(1)[0], mb.get_state(1)[0])
+    # a new Dirichlet face on the second mesh, then one more step
+    hot = synth.timefn(330.0)
+    b[1].set_face_bc(synth.TEMPERATURE, 5, synth.DIRICHLET, hot)
+    hts.advance(b, 1, scns[0].dt, o)
+    s1 = scns[1]
+    s1.bcs = list(s1.bcs) + [synth.FaceBC(synth.TEMPERATURE, 5, synth.DIRICHLET, hot)]
+    c = [hts.from_scenario(scns[0], opts=o), hts.from_scenario(s1, opts=o)]
+    for m, src in zip(c, a):
+        m.set_state(0, src.get_state(0)[0], src.get_state(0)[1])
+        m.set_state(1, src.get_state(1)[0], src.get_state(1)[1])
+    hts.advance(c, 1, scns[0].dt, o)
+    for mb, mc in zip(b, c):
+        assert np.array_equal(mb.get_state(0)[0], mc.get_state(0)[0])
+        assert np.array_equal(mb.get_state(1)[0], mc.get_state(1)[0])
+    T1 = b[1].get_state(1)[0]
+    assert np.isclose(T1.max(), 330.0)
