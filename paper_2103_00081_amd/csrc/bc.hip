@@ -17,9 +17,9 @@ __global__ __launch_bounds__(256) void k_dirichlet(const OpDev *__restrict__ ops
     const BcDev &b = bcs[ch.inst];
     const double t = S[(int64_t)ch.inst * NSLOT + S_TNEW];
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += 256) {
-        const int64_t n = e - o.off;
-        int i, j, k;
-        node_ijk(o, n, i, j, k);
+        // instance-local node index (below 2^31): 32-bit index arithmetic
+        const int n = (int)(e - o.off);
+        const int nxy = n / o.NX, i = n - nxy * o.NX, k = nxy / o.NY, j = nxy - k * o.NY;
         const double x = b.xn ? b.xn[i] : b.x0 + i * b.dx, y = b.yn ? b.yn[j] : b.y0 + j * b.dy,
                      z = b.zn ? b.zn[k] : b.z0 + k * b.dz;
         double v = 0.0;

@@ -339,9 +339,20 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const CoarseDev *__restric
     const CoarseDev &C = cd[k];
     if (active && !active[C.inst]) return;
     const double HTS_GLOBAL *A = gptr<double>(C.Ainv) + row * C.n;
-    double acc = 0.0;
-    for (int64_t j = lane; j < C.n; j += 64) acc += A[j] * (double)b[C.off + j];
-    acc = wave_sum(acc);
+    const T *bi = b + C.off;
+    const int n = (int)C.n;
+    // four independent partial sums per lane, so that four row segments
+    // are in flight at once
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = lane;
+    for (; j + 192 < n; j += 256) {
+        a0 += A[j] * (double)bi[j];
+        a1 += A[j + 64] * (double)bi[j + 64];
+        a2 += A[j + 128] * (double)bi[j + 128];
+        a3 += A[j + 192] * (double)bi[j + 192];
+    }
+    for (; j < n; j += 64) a0 += A[j] * (double)bi[j];
+    double acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) x[C.off + row] = T(acc);
 }
 
