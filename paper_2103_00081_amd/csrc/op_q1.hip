@@ -224,6 +224,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const T vx = T(-cw8 / (o.hx * o.hx)), vy = T(-cw8 / (o.hy * o.hy)), vz = T(-cw8 / (o.hz * o.hz));
     const T pz0 = T(o.rho_g * o.hz);
     const T cm = T(o.cm);
+    const bool adv = o.cadv != 0.0;
     // graded meshes: every factor is a per-column part (from this thread's
     // hx, hy, formed once in double and rounded) times hz or 1 / hz of the
     // layer (tables, one value per layer)
@@ -419,13 +420,15 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                 cell_mass_stiff(u, cm * lfm, ck * lfx, ck * lfy, ck * lfz, w);
             } else {
                 cell_mass_stiff(u, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
-                T pp[8];
+                if (adv) {   // no convection in the mass-only heat operator
+                    T pp[8];
 #pragma unroll
-                for (int a = 0; a < 4; a++) {
-                    pp[a] = ps[FIELD ? b0 : 0][ty + (a >> 1)][tx + (a & 1)];
-                    pp[a + 4] = ps[FIELD ? b1 : 0][ty + (a >> 1)][tx + (a & 1)];
+                    for (int a = 0; a < 4; a++) {
+                        pp[a] = ps[FIELD ? b0 : 0][ty + (a >> 1)][tx + (a & 1)];
+                        pp[a + 4] = ps[FIELD ? b1 : 0][ty + (a >> 1)][tx + (a & 1)];
+                    }
+                    cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
                 }
-                cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
             }
 #pragma unroll
             for (int a = 0; a < 4; a++) { bot[a] = w[a]; tp[a] = w[a + 4]; }
