@@ -92,7 +92,7 @@ typedef struct {
  * origin[d] to origin[d]+extent[d], within 1e-9 of the extent).  Graded
  * (rectilinear) meshes refine around features, as the paper's site mesh is
  * refined around the piles (Section 3.3, Fig. 10b); they are supported for
- * degree 1. */
+ * degree 1.  Zero-initialise the descriptor so that unused fields are NULL. */
 typedef struct {
     double origin[3];
     double extent[3];
