@@ -190,11 +190,31 @@ def workload(a, synth, n_steps):
                         "10-200 Dirichlet pile columns each" % a.instances)
 
 
+def stream_copy_gbs(torch, mib=1024, reps=20):
+    """Achievable device-to-device copy bandwidth (read + write bytes per
+    second) of a plain copy of mib MiB, for comparison with the 8 TB/s peak."""
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    del src, dst
+    return 2.0 * n * 4 / sec / 1e9
+
+
 def time_operators(hts, synth, np, torch):
     """Fine-level operator classes on the pile-field meshes (8.5 M nodes per
     field): 4 rotating (x, y) buffer pairs so every apply streams from HBM;
     device time of the apply kernel alone (events around each launch)."""
-    out = {}
+    out = {"stream_copy_GBs": round(stream_copy_gbs(torch), 1)}
     for p, nc in ((1, (256, 256, 128)), (2, (128, 128, 64))):
         scn = synth.config3(degree=p, ncells=nc, n_steps=1)
         m = hts.from_scenario(scn, initial=False)
