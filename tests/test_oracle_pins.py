@@ -641,6 +641,46 @@ def test_graded_dirichlet_column_nearest_node():
     assert mask.sum() == 4 and mask[sel].all() and np.all(g[sel] == 300.0)
 
 
+def test_graded_convection_skew_for_uniform_flux():
+    """On graded cells a linear P still gives a uniform Darcy flux, so the
+    convection matrix stays skew on fields vanishing at the boundary and
+    annihilates constants (the per-cell 1/h of the gradients)."""
+    m = Mesh((0.0, 0.0, 0.0), (3.0, 3.0, 3.0), (4, 3, 5), 1,
+             (np.array([0.0, 0.2, 1.1, 2.0, 3.0]), np.array([0.0, 1.7, 2.2, 3.0]),
+              np.array([0.0, 0.5, 0.9, 1.0, 2.4, 3.0])))
+    X, Y, Z = m.coords()
+    rho_g, kk = 9810.0, 1e-9
+    P = 1e5 - 300.0 * X + 120.0 * Y + rho_g * (3.0 - Z) - 50.0 * Z
+    Cm = oracle.assemble(m, kvel=np.full(m.ncell, kk), P=P, adv_scale=4e6, rho_g=rho_g)
+    NX, NY, NZ = m.dims
+    I = np.arange(m.nnode)
+    i, j, kz = I % NX, (I // NX) % NY, I // (NX * NY)
+    bnd = (i == 0) | (i == NX - 1) | (j == 0) | (j == NY - 1) | (kz == 0) | (kz == NZ - 1)
+    x = np.random.default_rng(4).standard_normal(m.nnode)
+    x[bnd] = 0.0
+    assert abs(x @ (Cm @ x)) <= 1e-12 * abs(Cm).max() * (x @ x)
+    assert np.abs(Cm @ np.ones(m.nnode)).max() <= 1e-12 * abs(Cm).max()
+    # and a linear field is advected at the uniform flux: C x = (q . grad x) * (row sums of M)
+    q = np.array([300.0, -120.0, 50.0]) * kk * 4e6
+    M = oracle.assemble(m, mass=np.ones(m.ncell))
+    lin = 2.0 * X - 1.0 * Y + 0.5 * Z
+    assert np.allclose(Cm @ lin, (q @ np.array([2.0, -1.0, 0.5])) * (M @ np.ones(m.nnode)),
+                       rtol=1e-10, atol=1e-10 * abs(Cm @ lin).max())
+
+
+def test_island_graded_layout():
+    """The graded island keeps its piles and materials per cell and refines
+    about 3:1 over the footprints and the top 70 m."""
+    s = synth.island(ncells=(64, 40, 20), n_steps=1, graded=True)
+    ex, ey, ez = s.edges
+    assert ex[0] == 0.0 and ex[-1] == 640.0 and ez[-1] == 100.0
+    hx, hz = np.diff(ex), np.diff(ez)
+    assert 2.0 < hx.max() / hx.min() < 3.5 and 2.0 < hz.max() / hz.min() < 3.5
+    assert hz[-1] < hz[0]      # finer at the top, where the piles are
+    u = synth.island(ncells=(64, 40, 20), n_steps=1)
+    assert [(c.x, c.y) for c in s.dir_columns] == [(c.x, c.y) for c in u.dir_columns]
+
+
 # ----------------------------------------------------------------- solvers
 def test_iterative_solvers_match_lu():
     s = small_scn(n=(6, 5, 4))
