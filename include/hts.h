@@ -91,8 +91,9 @@ typedef struct {
  * edges edges[d][0..ncells[d]] (host array, copied; strictly increasing from
  * origin[d] to origin[d]+extent[d], within 1e-9 of the extent).  Graded
  * (rectilinear) meshes refine around features, as the paper's site mesh is
- * refined around the piles (Section 3.3, Fig. 10b); they are supported for
- * degree 1.  Zero-initialise the descriptor so that unused fields are NULL. */
+ * refined around the piles (Section 3.3, Fig. 10b); degree-2 cells keep
+ * their mid-edge nodes at the cell midpoints.  Zero-initialise the
+ * descriptor so that unused fields are NULL. */
 typedef struct {
     double origin[3];
     double extent[3];

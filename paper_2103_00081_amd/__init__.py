@@ -452,9 +452,17 @@ def conv3d(op, cin, cout, stride, din, x=None, w=None, bias=None, g=None):
 def _node_coords(scn):
     p = scn.degree
     edges = getattr(scn, "edges", None)
-    ax = [np.asarray(edges[d], dtype=np.float64) if edges is not None and edges[d] is not None
-          else scn.origin[d] + np.arange(p * scn.ncells[d] + 1) * (scn.extent[d] / (p * scn.ncells[d]))
-          for d in range(3)]
+    ax = []
+    for d in range(3):
+        if edges is not None and edges[d] is not None:
+            e = np.asarray(edges[d], dtype=np.float64)
+            if p == 2:   # mid-edge nodes at the cell midpoints
+                a = np.empty(2 * e.size - 1)
+                a[0::2], a[1::2] = e, 0.5 * (e[:-1] + e[1:])
+                e = a
+            ax.append(e)
+        else:
+            ax.append(scn.origin[d] + np.arange(p * scn.ncells[d] + 1) * (scn.extent[d] / (p * scn.ncells[d])))
     Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
     return X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
 

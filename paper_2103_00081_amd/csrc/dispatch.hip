@@ -7,20 +7,20 @@ template <typename T>
 void launch_q1(int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work, int nwork,
                const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
 template <typename T>
-void launch_q2(int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
-               const EpiArgs<T> &ep, hipStream_t s);
+void launch_q2(int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work, int nwork,
+               const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
 void launch_q1_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s);
 void launch_q2_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s);
 void launch_q1_cell_loads(const OpDev &op, const double *alpha, const double *beta, double *y, hipStream_t s);
 void launch_q2_cell_loads(const OpDev &op, const double *alpha, const double *beta, double *y, hipStream_t s);
 
-// graded: some instance has a graded mesh (degree 1 only)
+// graded: some instance has a graded mesh
 template <typename T>
 void launch_apply(int degree, int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work,
                   int nwork, const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s)
 {
     if (degree == 1) launch_q1<T>(field, epi, masked, graded, ops, work, nwork, x, y, ep, s);
-    else launch_q2<T>(field, epi, masked, ops, work, nwork, x, y, ep, s);
+    else launch_q2<T>(field, epi, masked, graded, ops, work, nwork, x, y, ep, s);
 }
 template void launch_apply<double>(int, int, int, bool, bool, const OpDev *, const WorkItem *, int, const double *,
                                    double *, const EpiArgs<double> &, hipStream_t);

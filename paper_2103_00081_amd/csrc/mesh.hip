@@ -507,7 +507,6 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
                     ARG_CHECK(e[i + 1] > e[i], "cell edges must increase strictly");
             }
         }
-        ARG_CHECK(!graded || desc->degree == 1, "graded meshes are supported for degree 1");
         HTS_HIP(hipSetDevice(desc->device));
         std::unique_ptr<hts_mesh> m(new hts_mesh());
         m->desc = *desc;
@@ -538,9 +537,14 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
                 m->edge[d][0] = m->x0[d];
                 m->edge[d][m->n[d]] = m->x0[d] + m->L[d];
             }
+            // nodes: the cell edges, and for degree 2 also the cell midpoints
             m->node[d].resize(m->N[d]);
             const double hn = m->L[d] / (m->p * m->n[d]);
-            for (int i = 0; i < m->N[d]; i++) m->node[d][i] = graded ? m->edge[d][i] : m->x0[d] + i * hn;
+            for (int i = 0; i < m->N[d]; i++) {
+                if (!graded) m->node[d][i] = m->x0[d] + i * hn;
+                else if (m->p == 1) m->node[d][i] = m->edge[d][i];
+                else m->node[d][i] = (i & 1) ? 0.5 * (m->edge[d][i / 2] + m->edge[d][i / 2 + 1]) : m->edge[d][i / 2];
+            }
             m->desc.edges[d] = nullptr;   // the caller's array is not kept
         }
         if (graded) {

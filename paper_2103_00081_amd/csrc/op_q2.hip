@@ -225,7 +225,7 @@ __device__ __forceinline__ static bool constrained_q(const ColQ &c, int k, int N
     return (c.f & 2) || ((m & 16) && k == 0) || ((m & 32) && k == NZ - 1) || (k >= lo && k <= hi);
 }
 
-template <typename T, int FIELD, int EPI, bool MASKED>
+template <typename T, int FIELD, int EPI, bool MASKED, bool GRADED>
 __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
                                                   const WorkItem *__restrict__ work,
                                                   const T *__restrict__ X, T *__restrict__ Y,
@@ -287,6 +287,14 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
     const T hx = T(o.hx), hy = T(o.hy), hz = T(o.hz);
     const T V = hx * hy * hz;
     const T cxx = hy * hz / hx, cyy = hx * hz / hy, czz = hx * hy / hz;
+    // graded meshes: this thread's cell column sizes (the layer height is
+    // read per layer and the factors formed there)
+    const bool graded = GRADED && o.hzs != nullptr;
+    T ghx = hx, ghy = hy;
+    if (graded) {
+        ghx = T(o.hxs[cx < 0 ? 0 : (cx >= nx ? nx - 1 : cx)]);
+        ghy = T(o.hys[cy < 0 ? 0 : (cy >= ny ? ny - 1 : cy)]);
+    }
     const T cs = T(o.cs), cm = T(o.cm);
     const T ihx = T(1) / hx, ihy = T(1) / hy, ihz = T(1) / hz;
     const T rho_g = T(o.rho_g);
@@ -382,16 +390,28 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
                 const int c = i / 9, b = (i / 3) % 3, a = i % 3;
                 return xs[c == 0 ? s0 : (c == 1 ? s1 : s2)][2 * ty + b][2 * tx + a];
             };
+            T lV = V, lcxx = cxx, lcyy = cyy, lczz = czz, lihx = ihx, lihy = ihy, lihz = ihz, lcw = cw;
+            if (graded) {
+                const T lhz = T(o.hzs[L]);
+                lV = ghx * ghy * lhz;
+                lcxx = ghy * lhz / ghx;
+                lcyy = ghx * lhz / ghy;
+                lczz = ghx * ghy / lhz;
+                lihx = T(1) / ghx;
+                lihy = T(1) / ghy;
+                lihz = T(1) / lhz;
+                lcw = T(o.cadv) * lV;
+            }
             if (FIELD == 0) {
-                q2_mass_stiff(uat, cm * V, cs * ck, cxx, cyy, czz, w);
+                q2_mass_stiff(uat, cm * lV, cs * ck, lcxx, lcyy, lczz, w);
             } else {
-                q2_mass_stiff(uat, cc * V, cs * cl, cxx, cyy, czz, w);
+                q2_mass_stiff(uat, cc * lV, cs * cl, lcxx, lcyy, lczz, w);
                 auto pat = [&](int i) -> T {
                     const int c = i / 9, b = (i / 3) % 3, a = i % 3;
                     return ps[FIELD ? (c == 0 ? s0 : (c == 1 ? s1 : s2)) : 0][FIELD ? 2 * ty + b : 0]
                              [FIELD ? 2 * tx + a : 0];
                 };
-                q2_convect(uat, pat, ck, ihx, ihy, ihz, rho_g, cw, w);
+                q2_convect(uat, pat, ck, lihx, lihy, lihz, rho_g, lcw, w);
             }
         } else {
 #pragma unroll
@@ -487,6 +507,14 @@ __device__ __forceinline__ int q2_cells(int g, int ncell, int *c, int *loc)
     return n;
 }
 
+// size of cell c along axis d (graded meshes: from the per-axis tables)
+__device__ __forceinline__ static double cell_h(const OpDev &o, int d, int c)
+{
+    if (d == 0) return o.hxs ? o.hxs[c] : o.hx;
+    if (d == 1) return o.hys ? o.hys[c] : o.hy;
+    return o.hzs ? o.hzs[c] : o.hz;
+}
+
 __global__ void k_q2_inv_diag(OpDev o, double *__restrict__ out)
 {
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -496,8 +524,6 @@ __global__ void k_q2_inv_diag(OpDev o, double *__restrict__ out)
     ColInfo c = col_info(o, i, j);
     if (constrained(c, k, o.NZ, o.dmask)) { out[n] = 1.0; return; }
     const double md[3] = {4.0 / 30, 16.0 / 30, 4.0 / 30}, kd[3] = {7.0 / 3, 16.0 / 3, 7.0 / 3};
-    const double V = o.hx * o.hy * o.hz;
-    const double cxx = o.hy * o.hz / o.hx, cyy = o.hx * o.hz / o.hy, czz = o.hx * o.hy / o.hz;
     int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
     const int nxc = q2_cells(i, o.nx, cx, lx), nyc = q2_cells(j, o.ny, cy, ly), nzc = q2_cells(k, o.nz, cz, lz);
     double d = 0.0;
@@ -505,6 +531,9 @@ __global__ void k_q2_inv_diag(OpDev o, double *__restrict__ out)
         for (int b = 0; b < nyc; b++)
             for (int a = 0; a < nxc; a++) {
                 const int64_t ci = cx[a] + (int64_t)o.nx * (cy[b] + (int64_t)o.ny * cz[c3]);
+                const double hx = cell_h(o, 0, cx[a]), hy = cell_h(o, 1, cy[b]), hz = cell_h(o, 2, cz[c3]);
+                const double V = hx * hy * hz;
+                const double cxx = hy * hz / hx, cyy = hx * hz / hy, czz = hx * hy / hz;
                 const double mx = md[lx[a]], my = md[ly[b]], mz = md[lz[c3]];
                 const double kx = kd[lx[a]], ky = kd[ly[b]], kz = kd[lz[c3]];
                 double mc, sc;
@@ -530,7 +559,6 @@ __global__ void k_q2_cell_loads(OpDev o, const double *__restrict__ alpha, const
     int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((int64_t)NX * NY));
     const double wint[3] = {1.0 / 6, 2.0 / 3, 1.0 / 6};   // int_0^1 N_i
     const double dend[3] = {-1.0, 0.0, 1.0};              // N_i(1) - N_i(0)
-    const double V = o.hx * o.hy * o.hz, A = o.hx * o.hy;
     int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
     const int nxc = q2_cells(i, o.nx, cx, lx), nyc = q2_cells(j, o.ny, cy, ly), nzc = q2_cells(k, o.nz, cz, lz);
     double s = 0.0;
@@ -538,6 +566,8 @@ __global__ void k_q2_cell_loads(OpDev o, const double *__restrict__ alpha, const
         for (int b = 0; b < nyc; b++)
             for (int a = 0; a < nxc; a++) {
                 const int64_t ci = cx[a] + (int64_t)o.nx * (cy[b] + (int64_t)o.ny * cz[c3]);
+                const double hx = cell_h(o, 0, cx[a]), hy = cell_h(o, 1, cy[b]), hz = cell_h(o, 2, cz[c3]);
+                const double V = hx * hy * hz, A = hx * hy;
                 const double wxy = wint[lx[a]] * wint[ly[b]];
                 if (alpha) s += alpha[ci] * V * wxy * wint[lz[c3]];
                 if (beta) s += beta[ci] * A * wxy * dend[lz[c3]];
@@ -548,41 +578,51 @@ __global__ void k_q2_cell_loads(OpDev o, const double *__restrict__ alpha, const
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-template <typename T, int FIELD, bool MASKED>
+template <typename T, int FIELD, bool MASKED, bool G>
 static void dispatch_epi2(int epi, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
                           const EpiArgs<T> &ep, hipStream_t s)
 {
     dim3 g(nwork), b(256);
     switch (epi) {
-    case EPI_STORE: k_q2_apply<T, FIELD, EPI_STORE, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_RESID: k_q2_apply<T, FIELD, EPI_RESID, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_STORE: k_q2_apply<T, FIELD, EPI_STORE, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_RESID: k_q2_apply<T, FIELD, EPI_RESID, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
     case EPI_RESID_NORM:
-        k_q2_apply<T, FIELD, EPI_RESID_NORM, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep);
+        k_q2_apply<T, FIELD, EPI_RESID_NORM, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep);
         break;
-    case EPI_DOT: k_q2_apply<T, FIELD, EPI_DOT, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_CHEB: k_q2_apply<T, FIELD, EPI_CHEB, MASKED><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_DOT: k_q2_apply<T, FIELD, EPI_DOT, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_CHEB: k_q2_apply<T, FIELD, EPI_CHEB, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
     default: throw Error(-1, "bad epilogue");
     }
 }
 
+template <typename T, bool G>
+static void launch_q2_g(int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork,
+                        const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s)
+{
+    if (field == 0) {
+        if (masked) dispatch_epi2<T, 0, true, G>(epi, ops, work, nwork, x, y, ep, s);
+        else dispatch_epi2<T, 0, false, G>(epi, ops, work, nwork, x, y, ep, s);
+    } else {
+        if (masked) dispatch_epi2<T, 1, true, G>(epi, ops, work, nwork, x, y, ep, s);
+        else dispatch_epi2<T, 1, false, G>(epi, ops, work, nwork, x, y, ep, s);
+    }
+}
+
+// graded: some instance has a graded mesh (those kernels form the cell
+// factors per layer)
 template <typename T>
-void launch_q2(int field, int epi, bool masked, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
-               const EpiArgs<T> &ep, hipStream_t s)
+void launch_q2(int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work, int nwork,
+               const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s)
 {
     if (nwork <= 0) return;
-    if (field == 0) {
-        if (masked) dispatch_epi2<T, 0, true>(epi, ops, work, nwork, x, y, ep, s);
-        else dispatch_epi2<T, 0, false>(epi, ops, work, nwork, x, y, ep, s);
-    } else {
-        if (masked) dispatch_epi2<T, 1, true>(epi, ops, work, nwork, x, y, ep, s);
-        else dispatch_epi2<T, 1, false>(epi, ops, work, nwork, x, y, ep, s);
-    }
+    if (graded) launch_q2_g<T, true>(field, epi, masked, ops, work, nwork, x, y, ep, s);
+    else launch_q2_g<T, false>(field, epi, masked, ops, work, nwork, x, y, ep, s);
     HTS_LAUNCH_CHECK();
 }
 
-template void launch_q2<double>(int, int, bool, const OpDev *, const WorkItem *, int, const double *, double *,
-                                const EpiArgs<double> &, hipStream_t);
-template void launch_q2<float>(int, int, bool, const OpDev *, const WorkItem *, int, const float *, float *,
+template void launch_q2<double>(int, int, bool, bool, const OpDev *, const WorkItem *, int, const double *,
+                                double *, const EpiArgs<double> &, hipStream_t);
+template void launch_q2<float>(int, int, bool, bool, const OpDev *, const WorkItem *, int, const float *, float *,
                                const EpiArgs<float> &, hipStream_t);
 
 void launch_q2_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s)

@@ -53,7 +53,7 @@ def test_error_paths_without_device():
 
 
 def test_graded_mesh_validation_without_device():
-    """Graded axes must span the box with increasing edges; degree 1 only."""
+    """Graded axes must span the box with strictly increasing edges."""
     import numpy as np
     import paper_2103_00081_amd as hts
     L = hts.load()
@@ -75,6 +75,3 @@ def test_graded_mesh_validation_without_device():
     short = np.array([0.0, 1.0, 2.0, 6.0, 9.0])
     assert L.hts_create_mesh(ctypes.byref(desc(short)), ctypes.byref(h)) == -1
     assert b"span" in L.hts_last_error()
-    ok = np.array([0.0, 1.0, 2.5, 6.0, 10.0])
-    assert L.hts_create_mesh(ctypes.byref(desc(ok, degree=2)), ctypes.byref(h)) == -1
-    assert b"degree 1" in L.hts_last_error()

@@ -51,6 +51,15 @@ def small_cases():
     s.name = "c3_graded"
     c.append((s.name, s))
     c.append(("island_graded", synth.island(ncells=(32, 20, 10), n_steps=1, graded=True)))
+    s = synth.island(ncells=(16, 10, 5), n_steps=1, degree=2, graded=True)
+    s.name = "island_q2_graded"
+    c.append((s.name, s))
+    s = synth.config3(degree=2, ncells=(17, 16, 5), n_steps=1)
+    s.edges = (synth.graded_edges(0.0, 1000.0, 17, [(250.0, 750.0)]),
+               synth.graded_edges(0.0, 1000.0, 16, [(250.0, 750.0)]),
+               synth.graded_edges(0.0, 200.0, 5, [(160.0, 200.0)]))
+    s.name = "c3_q2_graded"
+    c.append((s.name, s))
     return c
 
 
@@ -97,13 +106,15 @@ def test_apply_parity(hts, name, scn, field):
             if field == 1:
                 # the FP32 heat operator reads the pressure as the FP32-rounded
                 # piezometric head P + rho_w g z (relative to node 0); the
-                # reference uses that same rounded pressure in FP64
+                # reference uses that same rounded pressure in FP64; z is the
+                # node height above node 0 (k dz on a uniform axis)
                 NX, NY = om.dims[0], om.dims[1]
                 kz = np.arange(om.nnode) // (NX * NY)
                 dz = scn.extent[2] / (scn.degree * scn.ncells[2])
+                zk = kz * dz if getattr(scn, "edges", None) is None else Z - Z[0]
                 rg = scn.rho_w * scn.g
-                phi32 = ((P - P[0]) + rg * (kz * dz)).astype(np.float32)
-                Pt = phi32.astype(np.float64) - rg * (kz * dz) + P[0]
+                phi32 = ((P - P[0]) + rg * zk).astype(np.float32)
+                Pt = phi32.astype(np.float64) - rg * zk + P[0]
                 A, _ = _oracle_reduced(scn, field, P=Pt)
                 y_ref = oracle.reduced_apply(A, mask, x)
             Aabs = abs(A.tocsr())

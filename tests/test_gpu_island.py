@@ -172,3 +172,25 @@ def test_graded_graph_replay_matches_eager(hts):
                 assert st["status"] == [0, 0], st
             out.append((m.get_state(0)[0], m.get_state(1)[0]))
         assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_island_q2_graded_steps(hts, mode):
+    """The graded island on 27-node cells (mid-edge nodes at the cell
+    midpoints): three steps against the oracle."""
+    print_case("island q2 graded mode", mode)
+    scn = synth.island(ncells=(16, 10, 5), n_steps=3, degree=2, graded=True)
+    o = hts.default_opts(rtol=1e-12, mode=mode)
+    m = hts.from_scenario(scn, opts=o)
+    for _ in range(3):
+        code, st = m.solve_step(scn.dt, o)
+        assert st["status"] == [0, 0], st
+    P, _ = m.get_state(0)
+    T, _ = m.get_state(1)
+    Po, To, to = oracle.run(scn, n_steps=3)
+    if mode == 0:
+        assert rel(P, Po) <= 1e-10
+        assert rel(T, To) <= 1e-10
+    else:
+        assert rel(P, Po) <= 1e-8
+        assert np.abs(T - To).max() <= 1e-6

@@ -566,10 +566,12 @@ GY = np.array([0.0, 12.0, 25.0, 50.0, 60.0, 64.0, 80.0, 100.0])
 GZ = np.array([0.0, 5.0, 15.0, 22.0, 30.0, 45.0, 60.0, 63.0, 75.0, 100.0])
 
 
-def test_graded_uniform_darcy_flow_exact():
+@pytest.mark.parametrize("p", [1, 2])
+def test_graded_uniform_darcy_flow_exact(p):
     """Hydrostatic pressure plus a linear drop stays exact on graded cells,
     and q_h = (k dp / L, 0, 0) at every Gauss point."""
     s = synth.config1()
+    s.degree = p
     s.ncells = (GX.size - 1, GY.size - 1, GZ.size - 1)
     nc = int(np.prod(s.ncells))
     s.permeability, s.porosity = np.full(nc, 1e-12), np.full(nc, 0.3)
@@ -579,7 +581,10 @@ def test_graded_uniform_darcy_flow_exact():
     m = Mesh.of(s)
     P, _ = oracle.initial_state(s, m)
     X, Y, Z = m.coords()
-    assert np.allclose(np.unique(X), GX) and np.allclose(np.unique(Z), GZ)
+    if p == 1:
+        assert np.allclose(np.unique(X), GX) and np.allclose(np.unique(Z), GZ)
+    else:   # every edge plus the cell midpoints
+        assert np.allclose(np.unique(X)[0::2], GX) and np.allclose(np.unique(X)[1::2], 0.5 * (GX[1:] + GX[:-1]))
     Pex = 1e5 + s.rho_w * s.g * (100.0 - Z) + 1e4 * (1.0 - X / 100.0)
     assert np.abs(P - Pex).max() <= 1e-12 * np.abs(Pex).max()
     k = 1e-12 / s.mu_w
@@ -606,10 +611,11 @@ def test_graded_layered_geotherm_is_a_fixed_point():
     assert np.abs(T1 - T0).max() <= 1e-10
 
 
-def test_graded_heat_energy_balance():
+@pytest.mark.parametrize("p", [1, 2])
+def test_graded_heat_energy_balance(p):
     """Insulated graded box: the stored heat equals the volume source over the
     actual cell volumes minus the Neumann flux over the whole face."""
-    s = small_scn(n=(4, 3, 3))
+    s = small_scn(n=(4, 3, 3), p=p)
     s.edges = (np.array([0.0, 0.3, 1.0, 2.2, 3.0]), np.array([0.0, 1.0, 5.0, 8.0]),
                np.array([0.0, 0.1, 0.5, 1.0]))
     s.permeability[:] = 0.0
@@ -641,11 +647,12 @@ def test_graded_dirichlet_column_nearest_node():
     assert mask.sum() == 4 and mask[sel].all() and np.all(g[sel] == 300.0)
 
 
-def test_graded_convection_skew_for_uniform_flux():
+@pytest.mark.parametrize("p", [1, 2])
+def test_graded_convection_skew_for_uniform_flux(p):
     """On graded cells a linear P still gives a uniform Darcy flux, so the
     convection matrix stays skew on fields vanishing at the boundary and
     annihilates constants (the per-cell 1/h of the gradients)."""
-    m = Mesh((0.0, 0.0, 0.0), (3.0, 3.0, 3.0), (4, 3, 5), 1,
+    m = Mesh((0.0, 0.0, 0.0), (3.0, 3.0, 3.0), (4, 3, 5), p,
              (np.array([0.0, 0.2, 1.1, 2.0, 3.0]), np.array([0.0, 1.7, 2.2, 3.0]),
               np.array([0.0, 0.5, 0.9, 1.0, 2.4, 3.0])))
     X, Y, Z = m.coords()
