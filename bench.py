@@ -66,7 +66,8 @@ def parse():
     ap.add_argument("--modes", default="fp64,fp32_refined",
                     help="comma list of fp64, fp32_refined; the faster one is the headline")
     ap.add_argument("--workload", default="aquifer",
-                    choices=("aquifer", "piles", "piles-q2", "island", "island-graded", "ates", "batch"))
+                    choices=("aquifer", "piles", "piles-q2", "island", "island-graded", "island-q2",
+                             "island-graded-q2", "ates", "batch"))
     ap.add_argument("--ncells", default=None, help="cells per axis, e.g. 128,128,64 (default: the workload's)")
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--host-loop", type=int, default=1,
@@ -171,13 +172,14 @@ def workload(a, synth, n_steps):
         return [synth.config3(degree=p, ncells=nc, n_steps=n_steps)], 3, \
             "energy-pile field %dx%dx%d Q%d (%%d nodes/field), 400 seasonal line heat sources, " \
             "regional gradient" % (nc + (p,))
-    if a.workload in ("island", "island-graded"):
-        nc = nc or (256, 160, 64)
-        graded = a.workload == "island-graded"
-        s = synth.island(ncells=nc, n_steps=n_steps, graded=graded)
-        return [s], 6, ("island-style pile field %dx%dx%d Q1%s (%%d nodes/field), %d square-wave piles, "
+    if a.workload.startswith("island"):
+        p = 2 if a.workload.endswith("-q2") else 1
+        nc = nc or ((256, 160, 64) if p == 1 else (128, 80, 32))   # same nodes per field
+        graded = "graded" in a.workload
+        s = synth.island(ncells=nc, n_steps=n_steps, graded=graded, degree=p)
+        return [s], 6, ("island-style pile field %dx%dx%d Q%d%s (%%d nodes/field), %d square-wave piles, "
                          "seasonal surface, geothermal inflow"
-                         % (nc + (", graded 3:1 around the footprints and the pile depth" if graded else "",
+                         % (nc + (p, ", graded 3:1 around the footprints and the pile depth" if graded else "",
                                   len(s.dir_columns))))
     if a.workload == "ates":
         nc = nc or (64, 64, 240)

@@ -19,5 +19,6 @@ def test_workloads_are_listed():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                        stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=120)
     assert r.returncode == 0
-    for w in ("aquifer", "piles", "piles-q2", "island", "island-graded", "ates", "batch"):
+    for w in ("aquifer", "piles", "piles-q2", "island", "island-graded", "island-q2",
+              "island-graded-q2", "ates", "batch"):
         assert w in r.stdout
