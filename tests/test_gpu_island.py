@@ -137,13 +137,15 @@ def test_graded_geotherm_fixed_point(hts):
     assert np.abs(T1 - T0).max() <= 1e-9
 
 
-def test_graded_and_uniform_meshes_in_one_batch(hts):
+@pytest.mark.parametrize("p", [1, 2])
+def test_graded_and_uniform_meshes_in_one_batch(hts, p):
     """A batch mixing a graded and a uniform mesh launches the graded kernel
     instances for both; each instance still gives its solo answer bit for
     bit."""
-    print_case("graded + uniform batch")
-    scns = [synth.island(ncells=(24, 16, 8), n_steps=2, graded=True),
-            synth.island(ncells=(20, 12, 8), n_steps=2)]
+    print_case("graded + uniform batch p", p)
+    q = 3 - p   # degree 2: half the cells per axis
+    scns = [synth.island(ncells=(12 * q, 8 * q, 4 * q), n_steps=2, graded=True, degree=p),
+            synth.island(ncells=(10 * q, 6 * q, 4 * q), n_steps=2, degree=p)]
     o = hts.default_opts(rtol=1e-10)
     solo = []
     for s in scns:
@@ -157,11 +159,13 @@ def test_graded_and_uniform_meshes_in_one_batch(hts):
         assert np.array_equal(m.get_state(1)[0], T)
 
 
-def test_graded_graph_replay_matches_eager(hts):
+@pytest.mark.parametrize("p", [1, 2])
+def test_graded_graph_replay_matches_eager(hts, p):
     """Captured-graph replay on a graded mesh gives the eager answer bit for
     bit (both precisions of the inner solves)."""
-    print_case("graded graph replay")
-    scn = synth.island(ncells=(24, 16, 8), n_steps=3, graded=True)
+    print_case("graded graph replay p", p)
+    q = 3 - p
+    scn = synth.island(ncells=(12 * q, 8 * q, 4 * q), n_steps=3, graded=True, degree=p)
     for mode in (0, 1):
         out = []
         for g in (0, 1):
