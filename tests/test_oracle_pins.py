@@ -647,6 +647,22 @@ def test_graded_dirichlet_column_nearest_node():
     assert mask.sum() == 4 and mask[sel].all() and np.all(g[sel] == 300.0)
 
 
+def test_graded_q2_dirichlet_column_takes_mid_edge_nodes():
+    """On degree-2 graded axes the cell midpoints are nodes too: x = 0.7 goes
+    to the midpoint 0.65 of the cell [0.3, 1.0], y = 3.0 is the midpoint of
+    [1, 5], and the column holds all seven z nodes of [0, 1]."""
+    s = small_scn(n=(4, 3, 3), p=2)
+    s.edges = (np.array([0.0, 0.3, 1.0, 2.2, 3.0]), np.array([0.0, 1.0, 5.0, 8.0]),
+               np.array([0.0, 0.1, 0.5, 1.0]))
+    s.dir_columns = [synth.DirColumn(synth.TEMPERATURE, 0.7, 3.0, 0.0, 1.0, synth.timefn(300.0))]
+    m = Mesh.of(s)
+    mask, g = oracle.dirichlet(s, m, synth.TEMPERATURE, 0.0)
+    X, Y, Z = m.coords()
+    sel = (X == 0.65) & (Y == 3.0)
+    assert sel.sum() == 7 and mask.sum() == 7 and mask[sel].all() and np.all(g[sel] == 300.0)
+    assert np.allclose(np.sort(Z[sel]), [0.0, 0.05, 0.1, 0.3, 0.5, 0.75, 1.0])
+
+
 @pytest.mark.parametrize("p", [1, 2])
 def test_graded_convection_skew_for_uniform_flux(p):
     """On graded cells a linear P still gives a uniform Darcy flux, so the
