@@ -198,3 +198,28 @@ def test_island_q2_graded_steps(hts, mode):
     else:
         assert rel(P, Po) <= 1e-8
         assert np.abs(T - To).max() <= 1e-6
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graded_q2_column_at_midpoint(hts, mode):
+    """A Dirichlet column on degree-2 graded axes lands on the nearest node,
+    which is a cell midpoint here (x = 0.7 -> 0.65); one step against the
+    oracle."""
+    from test_oracle_pins import small_scn
+    print_case("graded q2 column at a midpoint, mode", mode)
+    s = small_scn(n=(4, 3, 3), p=2)
+    s.edges = (np.array([0.0, 0.3, 1.0, 2.2, 3.0]), np.array([0.0, 1.0, 5.0, 8.0]),
+               np.array([0.0, 0.1, 0.5, 1.0]))
+    s.dir_columns = [synth.DirColumn(synth.TEMPERATURE, 0.7, 3.0, 0.0, 1.0, synth.timefn(300.0))]
+    Po, To, _ = oracle.run(s, n_steps=1)
+    o = hts.default_opts(rtol=1e-12, mode=mode)
+    m = hts.from_scenario(s, opts=o)
+    code, st = m.solve_step(s.dt, o)
+    assert st["status"] == [0, 0], st
+    T, _ = m.get_state(1)
+    X, Y, Z = oracle.Mesh.of(s).coords()
+    assert np.all(T[(X == 0.65) & (Y == 3.0)] == 300.0)
+    if mode == 0:
+        assert rel(T, To) <= 1e-10 and np.abs(T - To).max() <= 1e-7
+    else:
+        assert np.abs(T - To).max() <= 1e-6
