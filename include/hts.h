@@ -4,8 +4,9 @@
  * The library advances the one-way coupled groundwater-pressure /
  * heat-transport model of Sun et al., "An HPC-Based Hydrothermal Finite
  * Element Simulator for Modeling Underground Response to Community-Scale
- * Geothermal Energy Production" (Section 2, Eqs. 1-4), on uniform
- * hexahedral box meshes with Q1 or Q2 Lagrange elements, one backward-Euler
+ * Geothermal Energy Production" (Section 2, Eqs. 1-4), on hexahedral box
+ * meshes (uniform, or graded per axis as in the refined site mesh of
+ * Section 3.3) with Q1 or Q2 Lagrange elements, one backward-Euler
  * step at a time: first the Darcy pressure P^{n+1} (Eq. 3), then the
  * temperature T^{n+1} (Eq. 4) with the Darcy flux q = -k (grad P + rho_w g)
  * evaluated from P^{n+1} at every quadrature point.
@@ -339,6 +340,18 @@ hts_status hts_nn_conv3d(int32_t op, int32_t cin, int32_t cout, int32_t stride, 
                          const uint16_t *x, const uint16_t *w, const float *bias, const uint16_t *g, float *out,
                          float *out_bias, void *stream);
 
+/* One Adam update (Kingma and Ba) of n FP32 parameters by the kernel that
+ * hts_nn_train runs, exposed for verification: with beta1 0.9, beta2 0.999,
+ * eps 1e-8 and gi = g[i] * gscale (gscale: 1 / minibatch size),
+ *   m = beta1 m + (1 - beta1) gi,  v = beta2 v + (1 - beta2) gi^2,
+ *   w -= lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
+ * w, m, v: host arrays [n], updated in place; g: host [n]; wbf (may be NULL):
+ * host [n] BF16 bit patterns of the new w (round to nearest even).  step >= 1
+ * is the 1-based update count.  HTS_ERR_ARG on n < 0, step < 1, lr <= 0 or
+ * a missing array; stream may be NULL. */
+hts_status hts_nn_adam(int64_t n, int32_t step, double lr, double gscale, float *w, float *m, float *v,
+                       const float *g, uint16_t *wbf, void *stream);
+
 /* Time `reps` forward passes of the network on a node grid dims = {NX, NY,
  * NZ} with HIP events on the network's stream; flop_per_forward (may be
  * NULL) gets 2 * 27 * Cin * Cout * voxels summed over the layers (logical
@@ -359,16 +372,18 @@ hts_status hts_nn_harvest(hts_nn *nn, hts_mesh *const *meshes, int32_t n_draws, 
 /* Train on the harvested pairs of every draw but the last val_draws with the
  * library's BF16 forward and backward kernels and FP32 Adam (beta 0.9,
  * 0.999, eps 1e-8), minibatches of `batch` pairs (gradients averaged),
- * shuffled with the network seed.  On the first call gamma is set to the
- * median rms(e)/rms(r) of the training pairs and targets are divided by
- * it.  out: mean training loss of the first and last epoch and the mean loss
+ * shuffled with the network seed.  Gamma is fixed once, by the first call
+ * (the median rms(e)/rms(r) of its training pairs) or by hts_nn_load; each
+ * call divides the targets of pairs harvested since the previous call by it,
+ * so every stored target is scaled exactly once (epochs may be 0).  out: mean training loss of the first and last epoch and the mean loss
  * on the pairs of the held-out draws. */
 hts_status hts_nn_train(hts_nn *nn, int32_t epochs, double lr, int32_t batch, int32_t val_draws,
                         hts_train_stats *out);
 
 /* Parameters and gamma to / from a binary file (magic "HTSNN001", levels,
  * channels, gamma, count, FP64 exchange-layout parameters).  Load checks
- * the architecture; HTS_ERR_ARG on mismatch or I/O failure. */
+ * the architecture; HTS_ERR_ARG on mismatch or I/O failure.  Load fixes
+ * gamma to the stored value (targets already scaled are rescaled to it). */
 hts_status hts_nn_save(const hts_nn *nn, const char *path);
 hts_status hts_nn_load(hts_nn *nn, const char *path);
 

@@ -29,10 +29,13 @@ per layer W[cout][ci][kz][ky][kx] (cross-correlation weights, the layout of
 Arrays here are [C][z][y][x] (one sample); the GPU path stores the same
 tensors channels-last with x fastest.
 
+Training updates the parameters with Adam (Kingma and Ba), ``adam`` below.
+
 Pins: ``tests/test_oracle_nn.py`` checks the convolutions against direct
 sums, the adjoint identities of convolution and upsampling, exactness of
-the upsampling on linear fields, and the full backward pass against central
-finite differences of the loss.
+the upsampling on linear fields, the full backward pass against central
+finite differences of the loss, and Adam against its closed-form first
+step, constant-gradient steps and a second step worked by hand.
 """
 from __future__ import annotations
 
@@ -204,3 +207,28 @@ def init_params(levels, ch, cin=2, seed=0):
         out.append(rng.standard_normal(co * ci * 27) * sd)
         out.append(np.zeros(co))
     return np.concatenate(out)
+
+
+def adam(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, Algorithm 1), plain per-element loop
+    in FP64.  step is the 1-based update count t.  Returns new (theta, m, v):
+
+    m_t = beta1 m + (1 - beta1) g,  v_t = beta2 v + (1 - beta2) g^2,
+    mhat = m_t / (1 - beta1^t),  vhat = v_t / (1 - beta2^t),
+    theta_t = theta - lr mhat / (sqrt(vhat) + eps).
+
+    The gradient is the minibatch mean (callers pass the summed gradient
+    times 1 / batch)."""
+    th = np.array(theta, dtype=np.float64, copy=True).ravel()
+    g = np.asarray(grad, dtype=np.float64).ravel()
+    m1 = np.array(m, dtype=np.float64, copy=True).ravel()
+    v1 = np.array(v, dtype=np.float64, copy=True).ravel()
+    c1 = 1.0 - beta1 ** step
+    c2 = 1.0 - beta2 ** step
+    for i in range(th.size):
+        m1[i] = beta1 * m1[i] + (1.0 - beta1) * g[i]
+        v1[i] = beta2 * v1[i] + (1.0 - beta2) * g[i] * g[i]
+        mhat = m1[i] / c1
+        vhat = v1[i] / c2
+        th[i] = th[i] - lr * mhat / (np.sqrt(vhat) + eps)
+    return th, m1, v1

@@ -33,7 +33,7 @@ EXPORTS = [
     "hts_apply_operator", "hts_solve_steady_pressure", "hts_solve_step", "hts_advance",
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
     "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing", "hts_nn_num_params",
-    "hts_nn_set_params", "hts_nn_get_params", "hts_nn_eval", "hts_nn_conv3d", "hts_nn_time_forward",
+    "hts_nn_set_params", "hts_nn_get_params", "hts_nn_eval", "hts_nn_conv3d", "hts_nn_adam", "hts_nn_time_forward",
 ]
 
 
@@ -151,6 +151,7 @@ def load():
         "hts_nn_get_params": (st, [vp, vp, C.c_int64]),
         "hts_nn_eval": (st, [vp, P(i32), vp, vp, vp, vp, P(d), vp]),
         "hts_nn_conv3d": (st, [i32, i32, i32, i32, P(i32), vp, vp, vp, vp, vp, vp, vp]),
+        "hts_nn_adam": (st, [C.c_int64, i32, d, d, vp, vp, vp, vp, vp, vp]),
         "hts_nn_time_forward": (st, [vp, P(i32), i32, P(d), P(d)]),
         "hts_nn_save": (st, [vp, C.c_char_p]),
         "hts_nn_load": (st, [vp, C.c_char_p]),
@@ -446,6 +447,17 @@ def conv3d(op, cin, cout, stride, din, x=None, w=None, bias=None, g=None):
     _check(load().hts_nn_conv3d(op, cin, cout, stride, di, _np_ptr(x), _np_ptr(w), _np_ptr(b),
                                 _np_ptr(g), _np_ptr(out), _np_ptr(ob), None))
     return (out, ob) if op == 2 else out
+
+
+def adam_step(step, lr, gscale, w, m, v, g):
+    """One Adam update on the device (verification entry point).  Returns
+    new copies (w, m, v, w as BF16 bit patterns); inputs are FP32."""
+    c = lambda a: np.array(a, dtype=np.float32, copy=True, order="C")
+    w, m, v, g = c(w), c(m), c(v), c(g)
+    wbf = np.empty(w.size, dtype=np.uint16)
+    _check(load().hts_nn_adam(w.size, int(step), float(lr), float(gscale), _np_ptr(w), _np_ptr(m), _np_ptr(v),
+                              _np_ptr(g), _np_ptr(wbf), None))
+    return w, m, v, wbf
 
 
 # --------------------------------------------------- scenario marshalling

@@ -75,9 +75,11 @@ struct hts_nn {
     std::map<std::tuple<int, int, int>, std::unique_ptr<hts::NNWork>> work;
     int adam_step = 0;
     double gamma = 1.0;   // target scale: network output * gamma ~ error / rms(residual)
-    // harvested pairs (all of one node grid)
+    bool gamma_set = false;   // gamma fixed (first train call, or loaded)
+    // harvested pairs (all of one node grid); targets of pairs [0, nscaled)
+    // are divided by gamma already, later ones are not yet
     hts::Dims dd{};
-    int64_t npairs = 0, cap = 0;
+    int64_t npairs = 0, cap = 0, nscaled = 0;
     std::vector<int> pair_draw;
     std::vector<double> pair_scale;
     hts::DBuf<uint16_t> pr, pt;
@@ -595,6 +597,33 @@ hts_status hts_nn_conv3d(int32_t op, int32_t cin, int32_t cout, int32_t stride, 
     });
 }
 
+hts_status hts_nn_adam(int64_t n, int32_t step, double lr, double gscale, float *w, float *m, float *v,
+                       const float *g, uint16_t *wbf, void *stream)
+{
+    return guard_call([&] {
+        if (n < 0 || step < 1 || !(lr > 0.0) || !std::isfinite(gscale)) throw Error(HTS_ERR_ARG, "bad arguments");
+        if (n > 0 && (!w || !m || !v || !g)) throw Error(HTS_ERR_ARG, "null argument");
+        if (n == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        Alloc al;
+        al.s = s;
+        DBuf<float> W, M, V, G;
+        DBuf<uint16_t> B;
+        W.upload(&al, w, (size_t)n, s);
+        M.upload(&al, m, (size_t)n, s);
+        V.upload(&al, v, (size_t)n, s);
+        G.upload(&al, g, (size_t)n, s);
+        if (wbf) B.alloc(&al, (size_t)n);
+        nn_adam(W.p, M.p, V.p, G.p, n, (float)lr, 0.9f, 0.999f, 1e-8f, step, (float)gscale, wbf ? B.p : nullptr,
+                nullptr, s);
+        HTS_HIP(hipMemcpyAsync(w, W.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HTS_HIP(hipMemcpyAsync(m, M.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HTS_HIP(hipMemcpyAsync(v, V.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        if (wbf) HTS_HIP(hipMemcpyAsync(wbf, B.p, (size_t)n * 2, hipMemcpyDeviceToHost, s));
+        HTS_HIP(hipStreamSynchronize(s));
+    });
+}
+
 hts_status hts_nn_time_forward(hts_nn *nn, const int32_t dims[3], int32_t reps, double *ms_per_forward,
                                double *flop_per_forward)
 {
@@ -776,14 +805,20 @@ hts_status hts_nn_train(hts_nn *nn, int32_t epochs, double lr, int32_t batch, in
         std::vector<int64_t> tr, va;
         for (int64_t i = 0; i < nn->npairs; i++) (nn->pair_draw[i] < first_val ? tr : va).push_back(i);
         if (tr.empty()) throw Error(HTS_ERR_STATE, "no training pairs");
-        // target scale: the median error-to-residual ratio of the training pairs
-        if (nn->adam_step == 0) {
+        // target scale: the median error-to-residual ratio of the training
+        // pairs, fixed once; every pair's target is divided by it exactly once
+        if (!nn->gamma_set) {
             std::vector<double> sc;
             for (int64_t i : tr) sc.push_back(nn->pair_scale[i]);
             std::nth_element(sc.begin(), sc.begin() + sc.size() / 2, sc.end());
             const double g = sc[sc.size() / 2];
             nn->gamma = g > 0.0 && std::isfinite(g) ? g : 1.0;
-            nn_scale_bf16(nn->pt.p, nn->npairs * nn->dd.n(), (float)(1.0 / nn->gamma), nn->s);
+            nn->gamma_set = true;
+        }
+        if (nn->nscaled < nn->npairs) {
+            nn_scale_bf16(nn->pt.p + (size_t)nn->nscaled * nn->dd.n(), (nn->npairs - nn->nscaled) * nn->dd.n(),
+                          (float)(1.0 / nn->gamma), nn->s);
+            nn->nscaled = nn->npairs;
         }
         hipStream_t s = nn->s;
         NNWork &W = workspace(nn, nn->dd);
@@ -862,7 +897,12 @@ hts_status hts_nn_load(hts_nn *nn, const char *path)
         std::fclose(f);
         if (!ok) throw Error(HTS_ERR_ARG, "not a network file of this architecture");
         set_params(nn, th.data());
+        // targets already divided by the previous gamma take the loaded one
+        if (nn->nscaled > 0 && gamma != nn->gamma)
+            nn_scale_bf16(nn->pt.p, nn->nscaled * nn->dd.n(), (float)(nn->gamma / gamma), nn->s);
         nn->gamma = gamma;
+        nn->gamma_set = true;
+        HTS_HIP(hipStreamSynchronize(nn->s));
     });
 }
 

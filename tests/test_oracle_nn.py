@@ -6,7 +6,9 @@
   the bias gradient is the sum of g;
 * linear upsampling reproduces linear fields and its adjoint satisfies
   <up(c), f> = <c, up^T(f)>;
-* the full backward pass against central finite differences of the loss.
+* the full backward pass against central finite differences of the loss;
+* Adam: the closed-form first step lr g / (|g| + eps), constant-gradient
+  steps, and a second step computed by hand.
 """
 import numpy as np
 import pytest
@@ -144,3 +146,43 @@ def test_bf16_rounding_ties_to_even():
     assert abs(r[5] - 3.0e38) <= 3.0e38 * 2.0 ** -8
     x = np.random.default_rng(3).standard_normal(1000)
     assert np.all(np.abs(nnet.bf16(x) - x) <= np.abs(x) * 2.0 ** -8)
+
+
+# ------------------------------------------------------------------- Adam
+def test_adam_first_step_closed_form():
+    """From m = v = 0 the bias-corrected moments are g and g^2, so the first
+    update is lr g / (|g| + eps) for every parameter, whatever the scale."""
+    rng = np.random.default_rng(21)
+    th = rng.standard_normal(50)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-6, 3, 50)
+    lr, eps = 2e-3, 1e-8
+    t1, m1, v1 = nnet.adam(th, g, np.zeros(50), np.zeros(50), 1, lr)
+    np.testing.assert_allclose(t1, th - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v1, 0.001 * g * g, rtol=1e-14)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2,
+    so every bias-corrected step is again lr g / (|g| + eps)."""
+    th0 = np.array([0.3, -1.2, 4.0])
+    g = np.array([0.5, -2e-3, 7.0])
+    th, m, v = th0.copy(), np.zeros(3), np.zeros(3)
+    for t in range(1, 8):
+        th, m, v = nnet.adam(th, g, m, v, t, 1e-2)
+    np.testing.assert_allclose(th, th0 - 7 * 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-13)
+
+
+def test_adam_second_step_by_hand():
+    """g1 = 1 then g2 = -1: m2 = 0.9 * 0.1 - 0.1 = -0.01, 1 - 0.9^2 = 0.19,
+    so mhat = -1/19; v2 = 0.999 * 0.001 + 0.001 = 0.001999 = 1 - 0.999^2, so
+    vhat = 1.  Steps: -lr / (1 + eps), then +lr / (19 (1 + eps)).
+    g1 = 2 then g2 = 0: mhat = 0.18 / 0.19 = 18/19, vhat = 0.003996 / 0.001999."""
+    lr, eps = 0.1, 1e-8
+    th, m, v = nnet.adam([1.0, 1.0], [1.0, 2.0], [0.0, 0.0], [0.0, 0.0], 1, lr)
+    th, m, v = nnet.adam(th, [-1.0, 0.0], m, v, 2, lr)
+    exp0 = 1.0 - lr / (1.0 + eps) + lr / (19.0 * (1.0 + eps))
+    exp1 = 1.0 - lr * 2.0 / (2.0 + eps) - lr * (18.0 / 19.0) / (np.sqrt(0.003996 / 0.001999) + eps)
+    np.testing.assert_allclose(th, [exp0, exp1], rtol=1e-14)
+    np.testing.assert_allclose(m, [-0.01, 0.18], rtol=1e-13)
+    np.testing.assert_allclose(v, [0.001999, 0.003996], rtol=1e-13)

@@ -16,6 +16,10 @@ Each test ties one part of the oracle to something other than itself:
 * spatial order     -> manufactured solutions: L2 ratio ~4 (Q1), ~8 (Q2);
 * balances          -> total stored heat / fluid equals the sources and
   boundary fluxes for insulated boxes;
+* injection enthalpy -> one step's stored heat equals h c_w (Q/L) times the
+  line integral of (T_inj - T^{n+1}), both evaluated with an independent
+  Lagrange basis and Gauss rule; a state at T_inj stays there while the
+  well pair drives flow; extraction wells add no heat term;
 * solvers           -> sparse LU on small systems.
 """
 import math
@@ -442,6 +446,131 @@ def test_pressure_mass_balance_well(p):
     stored = np.ones(m.nnode) @ (M @ (P1 - 2e5))
     expect = s.dt * s.B_poro * (2e-4 + 1e-6 * 3.0 * 8.0)
     assert math.isclose(stored, expect, rel_tol=1e-9)
+
+
+# ------------------------------------------ injection enthalpy (Eq. 4, C8)
+def _lagrange_1d(p, t):
+    """Values of the p+1 equispaced Lagrange basis functions on [0, 1] at t."""
+    nodes = np.linspace(0.0, 1.0, p + 1)
+    out = np.ones((p + 1,) + np.shape(t))
+    for a in range(p + 1):
+        for b in range(p + 1):
+            if b != a:
+                out[a] = out[a] * (t - nodes[b]) / (nodes[a] - nodes[b])
+    return out
+
+
+def _fe_eval(s, u, x, y, z):
+    """Value of the finite element function with node values u at one point
+    (uniform box), by the tensor Lagrange basis of the cell containing it."""
+    p = s.degree
+    NX, NY, NZ = s.nodes_per_dim
+    pt = (x, y, z)
+    idx, loc = [], []
+    for d in range(3):
+        h = s.extent[d] / s.ncells[d]
+        c = min(int((pt[d] - s.origin[d]) // h), s.ncells[d] - 1)
+        idx.append(c)
+        loc.append(_lagrange_1d(p, (pt[d] - s.origin[d] - c * h) / h))
+    val = 0.0
+    for c_ in range(p + 1):
+        for b in range(p + 1):
+            for a in range(p + 1):
+                n = (p * idx[0] + a) + NX * ((p * idx[1] + b) + NY * (p * idx[2] + c_))
+                val += loc[0][a] * loc[1][b] * loc[2][c_] * u[n]
+    return val
+
+
+def _stored(s, cT, u):
+    """int c_T u dV with a 4-point Gauss rule per direction in every cell
+    (exact for the tensor degree-2 functions with cellwise c_T)."""
+    gx, gw = np.polynomial.legendre.leggauss(4)
+    gx, gw = 0.5 * (gx + 1.0), 0.5 * gw
+    h = [s.extent[d] / s.ncells[d] for d in range(3)]
+    tot = 0.0
+    nx, ny, nz = s.ncells
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                acc = 0.0
+                for qz, wz in zip(gx, gw):
+                    for qy, wy in zip(gx, gw):
+                        for qx, wx in zip(gx, gw):
+                            acc += wx * wy * wz * _fe_eval(
+                                s, u, s.origin[0] + (i + qx) * h[0], s.origin[1] + (j + qy) * h[1],
+                                s.origin[2] + (k + qz) * h[2])
+                tot += cT[i + nx * (j + ny * k)] * acc * h[0] * h[1] * h[2]
+    return tot
+
+
+def _line_integral(s, u, x, y, z0, z1):
+    """int_{z0}^{z1} u(x, y, z) dz, 4-point Gauss on each cell piece."""
+    hz = s.extent[2] / s.ncells[2]
+    cuts = sorted({z0, z1} | {s.origin[2] + k * hz for k in range(s.ncells[2] + 1) if z0 < s.origin[2] + k * hz < z1})
+    gx, gw = np.polynomial.legendre.leggauss(4)
+    tot = 0.0
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        for q, w in zip(gx, gw):
+            tot += 0.5 * (b - a) * w * _fe_eval(s, u, x, y, a + 0.5 * (b - a) * (q + 1.0))
+    return tot
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_injection_enthalpy_energy_balance(p):
+    """Insulated box without flow (zero permeability), one injection well
+    (Q > 0, water at T_inj) and one extraction well.  Summing Eq. 4 over all
+    test functions (partition of unity) leaves the heat stored in one step
+    equal to the enthalpy the injected water brings in minus what it takes up
+    at the new temperature along the screen:
+        int c_T (T^{n+1} - T^n) dV = h c_w (Q / L) int_line (T_inj - T^{n+1}) dz,
+    while the extraction well adds no heat term.  Both sides are evaluated
+    here from the node values with an independent Lagrange basis and Gauss
+    rule; a missing factor h or c_w, a flipped sign, a wrong per-metre rate or
+    a heat term at the extraction well breaks the equality."""
+    s = small_scn(p=p)
+    s.permeability[:] = 0.0
+    Q, Tin, z0, z1 = 2e-4, 320.0, 0.2, 0.9
+    s.lines = [synth.LineSource(1.3, 5.2, z0, z1, synth.LINE_WELL, synth.timefn(Q), T_inj=Tin),
+               synth.LineSource(2.1, 2.7, 0.1, 0.8, synth.LINE_WELL, synth.timefn(-3e-4), T_inj=400.0)]
+    m = Mesh.of(s)
+    k, lam, cT = oracle.coefficients(s)
+    T0 = 290.0 + np.random.default_rng(9).uniform(-1, 1, m.nnode)
+    T1 = oracle.solve_heat(s, m, T0, np.zeros(m.nnode), s.dt)
+    stored = _stored(s, cT, T1 - T0)
+    inflow = s.dt * s.c_w * Q / (z1 - z0) * (Tin * (z1 - z0) - _line_integral(s, T1, 1.3, 5.2, z0, z1))
+    assert abs(inflow) > 1e3 * abs(s.dt * s.c_w * Q) * 1e-9
+    assert math.isclose(stored, inflow, rel_tol=1e-9)
+    # the extraction well alone leaves the stored heat unchanged
+    s.lines = s.lines[1:]
+    T2 = oracle.solve_heat(s, m, T0, np.zeros(m.nnode), s.dt)
+    assert abs(_stored(s, cT, T2 - T0)) <= 1e-9 * s.dt * s.c_w * Q * 1.0
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_injection_at_ambient_temperature_keeps_state(p):
+    """A box at T_inj everywhere, held at T_inj on its faces, with an
+    injection / extraction well pair driving Darcy flow: the injected water
+    is at the temperature of the rock, so T stays T_inj (conduction and
+    advection of a constant vanish, and the line terms c_w s+ (T_inj - T)
+    cancel only if the matrix and load parts carry the same h, weights and
+    sign)."""
+    s = small_scn(p=p)
+    Tin = 305.0
+    s.lines = [synth.LineSource(1.3, 5.2, 0.2, 0.9, synth.LINE_WELL, synth.timefn(2e-4), T_inj=Tin),
+               synth.LineSource(2.1, 2.7, 0.1, 0.8, synth.LINE_WELL, synth.timefn(-2e-4), T_inj=Tin)]
+    s.bcs = [synth.FaceBC(synth.TEMPERATURE, f, synth.DIRICHLET, synth.timefn(Tin)) for f in range(6)]
+    m = Mesh.of(s)
+    P0 = np.full(m.nnode, 2e5)
+    P1 = oracle.solve_pressure(s, m, P0, s.dt)
+    k, lam, cT = oracle.coefficients(s)
+    q = oracle.flux_qp(m, p + 1, k, P1, s.rho_w * s.g)
+    assert np.abs(q).max() > 1e-9           # the wells do drive a flow
+    T1 = oracle.solve_heat(s, m, np.full(m.nnode, Tin), P1, s.dt)
+    assert np.abs(T1 - Tin).max() <= 1e-10 * Tin
+    # water injected 10 K warmer moves the same state (the pin is not vacuous)
+    s.lines[0] = synth.LineSource(1.3, 5.2, 0.2, 0.9, synth.LINE_WELL, synth.timefn(2e-4), T_inj=Tin + 10.0)
+    T2 = oracle.solve_heat(s, m, np.full(m.nnode, Tin), P1, s.dt)
+    assert np.abs(T2 - Tin).max() > 1e-3
 
 
 # ------------------------------------------------- site-style boundary data
