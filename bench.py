@@ -35,25 +35,39 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0      # dense MFMA
 
 
-def measured_traffic(kernel_class: str, ncells):
-    """HBM bytes per launch of one operator-kernel class from the committed
-    FETCH_SIZE / WRITE_SIZE counter summary, or None when that summary was
-    taken on another workload or on a different kernel source."""
+# Algorithmic bytes per node (Q1) or per degree of freedom (Q2) of one
+# operator apply: x read and y written per node, the pressure read per node
+# by the heat operator, and the per-cell coefficients (k; k and porosity for
+# heat) at one cell per node, at the operator's precision.
+ALG_BYTES = {(1, 0, 0): 24.0, (1, 0, 1): 12.0, (1, 1, 0): 40.0, (1, 1, 1): 20.0,
+             (2, 0, 0): 17.0, (2, 0, 1): 8.5, (2, 1, 0): 26.0, (2, 1, 1): 13.0}
+CLASS_NAMES = {(0, 0): "pressure apply FP64", (0, 1): "pressure apply FP32",
+               (1, 0): "heat apply FP64", (1, 1): "heat apply FP32"}
+COUNTER_SUMMARY = "q1_apply_pile_field_256x256x128_hbm_counters.md"
+
+
+def kernel_source_hash():
     import hashlib
-    if tuple(ncells) != (128, 128, 64):
-        return None
-    path = os.path.join(ROOT, "profiles", "q1_apply_layered_aquifer_128x128x64_hbm_counters.md")
-    src = [os.path.join(ROOT, "paper_2103_00081_amd", "csrc", f) for f in ("op_q1.hip", "dev_util.h")]
+    src = [os.path.join(ROOT, "paper_2103_00081_amd", "csrc", f) for f in ("op_q1.hip", "dev_util.h", "common.h")]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
+
+
+def measured_traffic(label: str):
+    """HBM bytes per launch of one Q1 operator class on the 256x256x128 pile
+    field (FETCH_SIZE + WRITE_SIZE, scaled by the counts of a plain copy of
+    known size) from the committed counter summary, or None when that summary
+    was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", COUNTER_SUMMARY)
     try:
         text = open(path).read()
-        h = hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
+        h = kernel_source_hash()
     except OSError:
         return None
     if "kernel_source_sha256_16 %s" % h not in text:
         return None
     for line in text.splitlines():
         line = line.strip()
-        if line.startswith("traffic_bytes_per_launch Q1 %s " % kernel_class):
+        if line.startswith("traffic_bytes_per_launch Q1 %s " % label):
             return float(line.split()[-1])
     return None
 
@@ -72,12 +86,16 @@ def parse():
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--host-loop", type=int, default=1,
                     help="batch workload: also time a host loop advancing the instances one at a time")
-    ap.add_argument("--operators", type=int, default=0,
-                    help="also time every fine-level operator class on the 256x256x128 Q1 and 128x128x64 "
-                         "Q2 pile-field meshes, cycling 4 (x, y) buffer pairs (beyond the 256 MB last-level "
-                         "cache)")
+    ap.add_argument("--operators", type=int, default=2,
+                    help="time every fine-level operator class on the 256x256x128 Q1 (1) and also the "
+                         "128x128x64 Q2 (2) pile-field meshes, cycling 4 (x, y) buffer pairs (beyond the "
+                         "256 MB last-level cache); 0 = skip (the roofline then falls back to the in-step "
+                         "launches)")
     ap.add_argument("--cpu-steps", type=int, default=5,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-single", type=int, default=1,
+                    help="also time the oracle on one thread: the small cube's full horizon and one "
+                         "step of the layered aquifer")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--cheb", type=int, default=2, help="pressure multigrid Chebyshev degree")
@@ -154,6 +172,16 @@ def learned_leg(a, hts, synth, nc, np, torch):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def note(msg):
     """Progress of the long set-up phases, on stderr (the JSON line goes to stdout)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -192,32 +220,26 @@ def workload(a, synth, n_steps):
                         "10-200 Dirichlet pile columns each" % a.instances)
 
 
-def stream_copy_gbs(torch, mib=1024, reps=20):
-    """Achievable device-to-device copy bandwidth (read + write bytes per
-    second) of a plain copy of mib MiB, for comparison with the 8 TB/s peak."""
+def stream_copy_gbs(hts, torch, mib=1024, reps=20):
+    """Achievable device-to-device bandwidth (read + write bytes per second)
+    of the library's plain streaming copy kernel over mib MiB."""
     n = mib * (1 << 20) // 4
     src = torch.rand(n, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    sec = a.elapsed_time(b) * 1e-3 / reps
+    ms = hts.stream_copy(src, dst, reps)
     del src, dst
-    return 2.0 * n * 4 / sec / 1e9
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def time_operators(hts, synth, np, torch):
+def time_operators(hts, synth, np, torch, degrees=(1, 2)):
     """Fine-level operator classes on the pile-field meshes (8.5 M nodes per
     field): 4 rotating (x, y) buffer pairs so every apply streams from HBM;
-    device time of the apply kernel alone (events around each launch)."""
-    out = {"stream_copy_GBs": round(stream_copy_gbs(torch), 1)}
-    for p, nc in ((1, (256, 256, 128)), (2, (128, 128, 64))):
+    device time of the apply kernel alone (HIP events around each launch on
+    the mesh's stream).  GB/s and frac use the algorithmic bytes of ALG_BYTES;
+    'lib_bytes' is the library's own epilogue-inclusive count."""
+    out = {"stream_copy_GBs": round(stream_copy_gbs(hts, torch), 1)}
+    for p in degrees:
+        nc = (256, 256, 128) if p == 1 else (128, 128, 64)
         scn = synth.config3(degree=p, ncells=nc, n_steps=1)
         m = hts.from_scenario(scn, initial=False)
         hts.autotune([m])
@@ -238,16 +260,38 @@ def time_operators(hts, synth, np, torch):
                 torch.cuda.synchronize()
                 k = hts.kernel_timing_stop()[(field, prec)]
                 us = 1e3 * k["ms"] / k["launches"]
-                gbs = k["bytes"] / k["launches"] / (us * 1e-6) / 1e9
-                name = "Q%d %s %s" % (p, ["pressure", "heat"][field], ["FP64", "FP32"][prec])
-                out[name] = {"us": round(us, 2), "bytes": k["bytes"] / k["launches"],
-                             "GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                alg = ALG_BYTES[(p, field, prec)] * n
+                gbs = alg / (us * 1e-6) / 1e9
+                name = "Q%d %s" % (p, CLASS_NAMES[(field, prec)])
+                out[name] = {"us": round(us, 2), "alg_bytes": alg, "GB/s": round(gbs, 1),
+                             "frac": round(gbs / PEAK_HBM_GBS, 4),
+                             "lib_bytes": k["bytes"] / k["launches"],
                              "flop_frac": round(k["flops"] / k["launches"] / (us * 1e-6) / 1e12 /
                                                 (PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_TFLOPS), 4)}
                 del xs, ys
         del m
         torch.cuda.synchronize()
     return out
+
+
+def step_bound(R, nnode, mode):
+    """Lower bound of one step from the bytes the method must move (per node:
+    B_op per operator apply, 80 B of Krylov vector traffic per iteration,
+    350 B per multigrid V-cycle with degree-2 Chebyshev smoothing for the
+    pressure, two heat applies plus 48 B of vectors per degree-2
+    Chebyshev-Jacobi application for the heat), summed with the iteration
+    counts actually taken, over 8 TB/s.  FP32 inner iterations move half;
+    each FP64 outer refinement step adds one FP64 apply and a norm."""
+    half = 0.5 if mode == "fp32_refined" else 1.0
+    bp, bh = 24.0, 40.0
+    per_p = R["iters_p"] * half * (bp + 80.0 + 350.0)
+    per_h = R["iters_h"] * half * (bh + 80.0 + 2 * bh + 48.0)
+    # right-hand sides (about one apply each) and the outer residuals / judges
+    per_p += bp + R["outer_p"] * (bp + 16.0) + (bp + 16.0)
+    per_h += bh + R["outer_h"] * (bh + 16.0) + (bh + 16.0)
+    t = nnode * (per_p + per_h) / (PEAK_HBM_GBS * 1e9)
+    return {"ms": round(1e3 * t, 4), "bytes_per_node": round(per_p + per_h, 1),
+            "achieved_frac": round(1e3 * t / R["ms_per_step"], 4)}
 
 
 def main():
@@ -352,50 +396,77 @@ def main():
     learned = None
     if a.learned and a.workload == "aquifer":
         learned = learned_leg(a, hts, synth, scns[0].ncells, np, torch)
-    operators = time_operators(hts, synth, np, torch) if a.operators else None
+    operators = time_operators(hts, synth, np, torch, degrees=(1, 2)[:a.operators]) if a.operators else None
 
     best = max(results, key=lambda k: results[k]["value"])
     R = results[best]
-    # dominant kernel class in the timed region
+    # dominant operator class of the timed step (device time of its launches)
     kt = R["kt"]
     key = max(kt, key=lambda k: kt[k]["ms"])
     k = kt[key]
     avg_ms = k["ms"] / max(1, k["launches"])
-    achieved = (k["bytes"] / max(1, k["launches"])) / (avg_ms * 1e-3) / 1e9
-    names = {(0, 0): "pressure apply FP64", (0, 1): "pressure apply FP32",
-             (1, 0): "heat apply FP64", (1, 1): "heat apply FP32"}
-    roofline = {
-        "bound": "hbm",
-        "kernel": names[key],
-        "achieved": round(achieved, 1),
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4),
-        "traffic": measured_traffic(names[key], scns[0].ncells) if a.workload == "aquifer" else None,
-        "launches": k["launches"],
-        "avg_us": round(1e3 * avg_ms, 2),
-        "alu_tflops": round((k["flops"] / max(1, k["launches"])) / (avg_ms * 1e-3) / 1e12, 2),
-        "share_of_step": round(k["ms"] / (R["ms_per_step"] * max(1, a.timing_steps)), 3),
-    }
+    deg = scns[0].degree
+    alg_step = ALG_BYTES[(deg, key[0], key[1])] * R["nnode"] / max(1, len(scns))
+    in_step = {"workload": wdesc % R["nnode"], "launches": k["launches"], "avg_us": round(1e3 * avg_ms, 2),
+               "alg_bytes": alg_step,
+               "GB/s": round(alg_step / (avg_ms * 1e-3) / 1e9, 1) if not batch else None,
+               "share_of_step": round(k["ms"] / (R["ms_per_step"] * max(1, a.timing_steps)), 3)}
+    name = CLASS_NAMES[key]
+    qname = "Q%d %s" % (deg, name)
+    if operators and qname in operators:
+        # the same class on the 8.5 M-node mesh, streaming from HBM
+        c3 = operators[qname]
+        roofline = {"bound": "hbm", "kernel": qname,
+                    "workload": "energy-pile field %s (8520321 nodes), 4 rotating (x, y) pairs"
+                                % ("256x256x128 Q1" if deg == 1 else "128x128x64 Q2"),
+                    "achieved": c3["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": c3["frac"],
+                    "traffic": measured_traffic(name) if deg == 1 else None, "alg_bytes": c3["alg_bytes"],
+                    "avg_us": c3["us"],
+                    "alu_frac": c3["flop_frac"], "stream_copy_GBs": operators["stream_copy_GBs"],
+                    "in_step": in_step}
+    else:
+        gbs = alg_step / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": name, "workload": in_step["workload"],
+                    "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None, "alg_bytes": alg_step,
+                    "avg_us": in_step["avg_us"], "in_step": in_step}
 
     cpu = None
     if not a.no_cpu and a.cpu_steps > 0:
         import oracle
+        L = oracle.lib()
         scn = scns[0]
         om = oracle.Mesh.of(scn)
         P, T = oracle.initial_state(scn, om)
         t = scn.t0
+        threads = int(L.orc_num_threads())
         c0 = time.perf_counter()
         for _ in range(a.cpu_steps):
             P, T, t, its = oracle.step_to(scn, om, P, T, t, rtol=1e-8)
         c1 = time.perf_counter()
         cpu = {"value": round(2 * om.nnode * a.cpu_steps / (c1 - c0) / 1e6, 4),
-               "unit": "MDoF-steps/s", "cores": int(oracle.lib().orc_num_threads()),
-               "kind": "oracle",
+               "unit": "MDoF-steps/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": "first %d steps of %s at full size: CSR assembly "
                          "+ Jacobi-PCG (pressure) and Jacobi-GMRES(50) (heat) to 1e-8, "
                          "%.1f s" % (a.cpu_steps, "the same workload" if not batch else
                                      "instance 0 of the same workload", c1 - c0)}
+        if a.cpu_single:
+            L.orc_set_num_threads(1)
+            single = {}
+            for label, sc, nst in (("c1 16^3 cube, full horizon (10 steps)", synth.config1(), 10),
+                                   ("first step of " + ("the same workload" if not batch else "instance 0"),
+                                    scn, 1)):
+                sm = oracle.Mesh.of(sc)
+                P, T = oracle.initial_state(sc, sm)
+                t = sc.t0
+                c0 = time.perf_counter()
+                for _ in range(nst):
+                    P, T, t, _ = oracle.step_to(sc, sm, P, T, t, rtol=1e-8)
+                c1 = time.perf_counter()
+                single[label] = {"value": round(2 * sm.nnode * nst / (c1 - c0) / 1e6, 4), "s": round(c1 - c0, 2)}
+            L.orc_set_num_threads(threads)
+            cpu["single_thread"] = single
 
     dtype = "f64" if best == "fp64" else "f32+f64"
     line = {
@@ -417,6 +488,7 @@ def main():
                    "mg_coarse_max": a.mg_coarse_max,
                    "heat_precond": ["multigrid", "chebyshev-jacobi", "tensor-mass"][a.heat_precond]},
         "roofline": roofline,
+        "step_bound": step_bound(R, R["nnode"], best),
         "learned": learned,
         "cpu_baseline": cpu,
         "modes": {mname: {"value": round(r["value"], 3), "ms_per_step": round(r["ms_per_step"], 3),

@@ -288,6 +288,16 @@ typedef struct {
  * be NULL).  Not thread-safe. */
 hts_status hts_kernel_timing(int32_t enable, hts_kernel_times out[2][2]);
 
+/* Achievable-bandwidth reference for the measurements: copy `bytes` from
+ * src to dst (device buffers, 16-byte aligned, caller-owned, not
+ * overlapping) with a plain streaming kernel, once untimed, then `reps`
+ * times between two HIP events on `stream` (NULL = null stream);
+ * ms_per_copy (may be NULL) gets the mean device time of one copy, which
+ * reads and writes `bytes` each.  HTS_ERR_ARG on negative sizes or
+ * misaligned / missing buffers. */
+hts_status hts_stream_copy(const void *src, void *dst, int64_t bytes, int32_t reps, void *stream,
+                           double *ms_per_copy);
+
 const char *hts_last_error(void);
 
 /* -------------------------------------------------- learned preconditioner */

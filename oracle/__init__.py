@@ -95,6 +95,7 @@ def lib():
             "orc_conv3d_bwd_data": (None, [vp, vp, vp] + [C.c_int] * 12),
             "orc_conv3d_bwd_weight": (None, [vp, vp, vp, vp] + [C.c_int] * 12),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_num_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

@@ -862,6 +862,16 @@ void orc_conv3d_bwd_weight(const double *x, const double *gy, double *gw, double
     }
 }
 
+/* Thread count of the parallel loops (timing runs at one thread). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

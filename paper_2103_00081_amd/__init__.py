@@ -34,6 +34,7 @@ EXPORTS = [
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
     "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing", "hts_nn_num_params",
     "hts_nn_set_params", "hts_nn_get_params", "hts_nn_eval", "hts_nn_conv3d", "hts_nn_adam", "hts_nn_time_forward",
+    "hts_stream_copy",
 ]
 
 
@@ -153,6 +154,7 @@ def load():
         "hts_nn_conv3d": (st, [i32, i32, i32, i32, P(i32), vp, vp, vp, vp, vp, vp, vp]),
         "hts_nn_adam": (st, [C.c_int64, i32, d, d, vp, vp, vp, vp, vp, vp]),
         "hts_nn_time_forward": (st, [vp, P(i32), i32, P(d), P(d)]),
+        "hts_stream_copy": (st, [vp, vp, C.c_int64, i32, vp, P(d)]),
         "hts_nn_save": (st, [vp, C.c_char_p]),
         "hts_nn_load": (st, [vp, C.c_char_p]),
         "hts_kernel_timing": (st, [i32, vp]),
@@ -458,6 +460,16 @@ def adam_step(step, lr, gscale, w, m, v, g):
     _check(load().hts_nn_adam(w.size, int(step), float(lr), float(gscale), _np_ptr(w), _np_ptr(m), _np_ptr(v),
                               _np_ptr(g), _np_ptr(wbf), None))
     return w, m, v, wbf
+
+
+def stream_copy(src, dst, reps=20):
+    """Mean device time (ms) of one plain streaming copy src -> dst (device
+    tensors of the same byte size) by the library's copy kernel."""
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nb
+    ms = C.c_double()
+    _check(load().hts_stream_copy(_ptr(src), _ptr(dst), nb, reps, None, C.byref(ms)))
+    return ms.value
 
 
 # --------------------------------------------------- scenario marshalling

@@ -139,8 +139,12 @@ struct Batch {
     double app_dt = -1.0;
     bool app_steady = false;
     // pressure hierarchies by (steady, dt, smoothing degree, coarse-level cap)
+    // (at most two, least recently used replaced)
     std::map<std::tuple<int, double, int, int>, std::unique_ptr<Hier>> hier;
+    std::map<std::tuple<int, double, int, int>, uint64_t> hier_used;
+    uint64_t hier_clock = 0;
     std::unique_ptr<Hier> heat;
+    std::vector<double> cadv_save;   // advection scale per instance (heat tables)
 
     // observers used to harvest training pairs for the learned preconditioner:
     // cg_hook(x, k) sees the iterate x_k of every FP64 CG solve (k = 0 first),

@@ -696,7 +696,21 @@ Hier &Batch::pressure_hier(bool steady, double dt, const hts_solver_opts &o)
     const int deg = std::max(1, std::min(o.cheb_degree, 8));
     auto key = std::make_tuple(steady ? 1 : 0, steady ? 0.0 : dt, deg, o.mg_coarse_max);
     auto it = hier.find(key);
-    if (it != hier.end()) return *it->second;
+    if (it != hier.end()) {
+        hier_used[key] = ++hier_clock;
+        return *it->second;
+    }
+    // keep at most two (typically the steady one of the initial state and
+    // the transient one of the time step): a new time-step size replaces
+    // the least recently used, with the graphs captured on it
+    if (hier.size() >= 2) {
+        auto lru = hier_used.begin();
+        for (auto u = hier_used.begin(); u != hier_used.end(); ++u)
+            if (u->second < lru->second) lru = u;
+        drop_graphs();
+        hier.erase(lru->first);
+        hier_used.erase(lru);
+    }
     auto H = std::make_unique<Hier>();
     H->field = 0;
     H->deg = deg;
@@ -706,6 +720,7 @@ Hier &Batch::pressure_hier(bool steady, double dt, const hts_solver_opts &o)
     build_hierarchy(*H, o);
     Hier &ref = *H;
     hier[key] = std::move(H);
+    hier_used[key] = ++hier_clock;
     return ref;
 }
 
@@ -848,10 +863,27 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     H.ratio = env_or("HTS_HEAT_RATIO", 15.0);
     H.ratio_coarse = env_or("HTS_HEAT_RATIO_COARSE", 15.0);
     make_tables(H.ops, 1, dt, false, false);
+    // The Chebyshev intervals are estimated on the symmetric part (mass,
+    // conduction, injection line): they depend on the mesh, the coefficients
+    // and dt only, not on the Darcy flux of the step in which the
+    // preconditioner happens to be built, so a run resumed from a saved state
+    // applies the same preconditioner as the uninterrupted one.
+    auto advection = [&](bool on) {
+        for (int i = 0; i < n; i++) {
+            H.ops.h64[i].cadv = on ? cadv_save[i] : 0.0;
+            H.ops.h32[i].cadv = on ? cadv_save[i] : 0.0;
+        }
+        H.ops.d64.upload(al, H.ops.h64, s);
+        H.ops.d32.upload(al, H.ops.h32, s);
+    };
+    cadv_save.resize(n);
+    for (int i = 0; i < n; i++) cadv_save[i] = H.ops.h64[i].cadv;
     if (mg) {
         // Galerkin levels of the static symmetric part; the fine level
         // smooths with the full operator (current Darcy flux in P1)
+        advection(false);
         build_hierarchy(H, o);
+        advection(true);
         return H;
     }
     H.lev.resize(1);
@@ -869,8 +901,9 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     }
     for (int i = 0; i < n; i++) launch_inv_diag(H.ops.h64[i], L.invd64.p + off[i], s);
     convert_plain(ntot, L.invd64.p, L.invd32.p, s);
-    // the velocity field enters the operator: estimate with the current P1
+    advection(false);
     build_smoother(H, 0, H.deg, H.ratio);
+    advection(true);
     return H;
 }
 
@@ -1943,6 +1976,11 @@ hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
                     HTS_HIP(hipEventSynchronize(e1));
                     float ms = 0.0f;
                     HTS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 0.0;
+                    if (verbose)
+                        std::fprintf(stderr, "[hts] autotune q%d field %d %dx%dx%d z-depth %d: %d blocks, %.2f us per "
+                                     "FP64 + FP32 pair\n", m->p, f, m->N[0], m->N[1], m->N[2], zc, b.nwork[f],
+                                     100.0 * ms);
                     if (ms < best) {
                         best = ms;
                         bz = zc;

@@ -18,6 +18,12 @@ Samples: random rows, rows on and next to the 15-node tile edges (Q1) or
 30-node tile edges (Q2), domain faces, low and high z, and every node of
 the well columns (injection line operator).
 
+Steps: one backward-Euler step of the layered aquifer (128x128x64 Q1)
+and of the pile field (256x256x128 Q1, 128x128x64 Q2), in FP64 and in
+FP32-refined mode, from the closed-form initial state, with the residual of
+the GPU answer evaluated in the oracle's own assembled and eliminated
+matrices (<= 1.0001e-8 ||b||) and the Dirichlet values exact.
+
 The batched design set (64 instances, 32^3 .. 96^3 cells) advances one
 step in one batch with captured graphs; sampled instances are judged by
 their true FP64 residual in the oracle's own assembled matrices, and the
@@ -161,3 +167,71 @@ def test_c4_batched_full_size_step(hts):
     assert np.array_equal(solo.get_state(1)[0], ms[idx].get_state(1)[0])
     del ms, solo
     torch.cuda.synchronize()
+
+
+# ------------------------------------------- full-size steps, oracle judged
+def judge_step(scn, om, P0, T0, P1, T1, label, Ap=None):
+    """Backward error of one step in the oracle's assembled, eliminated
+    systems (long-double residual) and the Dirichlet values as the oracle
+    sets them.  Returns the pressure system so that several modes share it."""
+    t1 = scn.t0 + scn.dt
+    if Ap is None:
+        A, b = oracle.pressure_system(scn, om, P0, t1)
+        mask, g = oracle.dirichlet(scn, om, 0, t1)
+        Ap = (oracle.eliminate(A, b, mask, g), mask, g)
+        del A, b
+    (free, AFF, bF), mask, g = Ap
+    rp = np.linalg.norm(oracle.residual_ld(AFF, bF, P1[free])) / np.linalg.norm(bF)
+    assert np.all(np.abs(P1[mask] - g[mask]) <= 4 * EPS[0] * np.abs(g[mask]))
+    H, hb = oracle.heat_system(scn, om, T0, P1, t1)
+    hm, hg = oracle.dirichlet(scn, om, 1, t1)
+    hfree, HFF, hF = oracle.eliminate(H, hb, hm, hg)
+    del H, hb
+    rh = np.linalg.norm(oracle.residual_ld(HFF, hF, T1[hfree])) / np.linalg.norm(hF)
+    assert np.all(np.abs(T1[hm] - hg[hm]) <= 4 * EPS[0] * np.abs(hg[hm]))
+    print("%s: oracle-CSR relative residuals pressure %.3e heat %.3e" % (label, rp, rh), flush=True)
+    assert rp <= 1.0001e-8 and rh <= 1.0001e-8, (label, rp, rh)
+    return Ap
+
+
+def full_size_step(hts, scn, label):
+    """One step at the benchmark's size, in FP64 and FP32-refined mode, from
+    the scenario's closed-form initial state (the same on both sides),
+    judged in the oracle's matrices (C15 iii)."""
+    import torch
+    om = oracle.Mesh.of(scn)
+    P0, T0 = oracle.initial_state(scn, om)
+    Ap = None
+    for mode, name in ((hts.MODE_FP64, "fp64"), (hts.MODE_FP32_REFINED, "fp32_refined")):
+        print_case(label, name, "nodes", om.nnode)
+        o = hts.default_opts(mode=mode, rtol=1e-8)
+        m = hts.from_scenario(scn, opts=o)
+        hts.autotune([m])
+        # the same affine initial data, evaluated by each side (a few ulps apart)
+        assert np.all(np.abs(m.get_state(0)[0] - P0) <= 8 * EPS[0] * np.abs(P0))
+        assert np.all(np.abs(m.get_state(1)[0] - T0) <= 8 * EPS[0] * np.abs(T0))
+        code, st = m.solve_step(scn.dt, o)
+        assert code == 0 and st["status"] == [0, 0], st
+        P1, T1 = m.get_state(0)[0], m.get_state(1)[0]
+        del m
+        torch.cuda.synchronize()
+        Ap = judge_step(scn, om, P0, T0, P1, T1, "%s %s" % (label, name), Ap)
+
+
+@pytest.mark.timeout(600)
+def test_c2_full_size_step(hts):
+    full_size_step(hts, synth.config2(ncells=(128, 128, 64), n_steps=1), "c2 128x128x64")
+
+
+@pytest.mark.timeout(900)
+def test_c3_q1_full_size_step(hts):
+    s = synth.config3(degree=1, ncells=(256, 256, 128), n_steps=1)
+    s.P0_steady = False     # closed-form hydrostatic + gradient start, a real pressure solve
+    full_size_step(hts, s, "c3 Q1 256x256x128")
+
+
+@pytest.mark.timeout(1200)
+def test_c3_q2_full_size_step(hts):
+    s = synth.config3(degree=2, ncells=(128, 128, 64), n_steps=1)
+    s.P0_steady = False
+    full_size_step(hts, s, "c3 Q2 128x128x64")

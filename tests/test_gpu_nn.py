@@ -16,8 +16,11 @@ dozen voxels, where a flipped BF16 value next to zero also flips a ReLU
 gate, so a few flips move them by percents; a wiring error moves them by
 order one).  The grids keep 36 and 60 voxels on the coarsest level.
 
-Learned solve: every answer is judged by the true FP64 residual; the
-pressure must match the plain FP64 answer to 1e-8 relative.
+Learned solve: every answer is judged against the oracle (parity mode:
+1e-8 relative pressure, 1e-6 K) and by its backward error in the oracle's
+assembled matrices at the working tolerance; the gain over plain multigrid
+is measured and its outcome asserted.  Adam: per element against the
+oracle's Adam with a bound derived from the FP32 operations.
 """
 import numpy as np
 import pytest
@@ -211,25 +214,88 @@ def solve_steps(hts, seed, o, steps=2):
     return m.get_state(0)[0], stats
 
 
-def test_learned_solve_matches_fp64_and_reports_gain(hts, trained):
+def judge_first_step(scn, P1, T1, rtol):
+    """Backward error of one GPU step from the scenario's initial state in
+    the oracle's own assembled, eliminated systems (residual accumulated in
+    long double), and Dirichlet values as the oracle sets them."""
+    om = oracle.Mesh.of(scn)
+    P0, T0 = oracle.initial_state(scn, om)
+    t1 = scn.t0 + scn.dt
+    out = []
+    for field in (0, 1):
+        if field == 0:
+            A, b = oracle.pressure_system(scn, om, P0, t1)
+            x = P1
+        else:
+            A, b = oracle.heat_system(scn, om, T0, P1, t1)
+            x = T1
+        mask, g = oracle.dirichlet(scn, om, field, t1)
+        free, AFF, bF = oracle.eliminate(A, b, mask, g)
+        r = oracle.residual_ld(AFF, bF, x[free])
+        out.append(float(np.linalg.norm(r) / np.linalg.norm(bF)))
+        assert np.all(np.abs(x[mask] - g[mask]) <= 4 * np.finfo(float).eps * np.abs(g[mask]))
+    assert out[0] <= rtol and out[1] <= rtol, out
+    return out
+
+
+def test_learned_solve_matches_oracle(hts, trained):
+    """Learned mode (flexible CG with the network, V-cycle fallback) on a
+    draw the network never saw: parity mode (rtol 1e-12) against the
+    oracle's direct solve (<= 1e-8 relative pressure, also relative to the
+    change of pressure over the steps, <= 1e-6 K temperature), and at the
+    working tolerance 1e-8 the first step's backward error in the oracle's
+    own matrices."""
     net, _ = trained
-    seed = 5100          # a draw the network never saw
-    print_case("learned solve", seed)
-    P64, s64 = solve_steps(hts, seed, hts.default_opts(rtol=1e-8))
+    seed = 5100
+    print_case("learned solve vs oracle", seed)
+    scn = synth.config5(seed, ncells=NC, n_steps=2)
+    o = hts.default_opts(rtol=1e-12, mode=hts.MODE_LEARNED)
+    o.nn = net.h.value
+    m = hts.from_scenario(scn, opts=o)
+    P0 = m.get_state(0)[0]
+    for _ in range(2):
+        code, st = m.solve_step(scn.dt, o)
+        assert code == 0 and st["status"] == [0, 0]
+    PL, TL = m.get_state(0)[0], m.get_state(1)[0]
+    Po, To, _ = oracle.run(scn, n_steps=2)
+    Pi, _ = oracle.initial_state(scn)
+    assert np.linalg.norm(PL - Po) <= 1e-8 * np.linalg.norm(Po)
+    assert np.linalg.norm(PL - Po) <= 1e-6 * np.linalg.norm(Po - Pi)
+    assert np.abs(TL - To).max() <= 1e-6
+    assert np.array_equal(P0, Pi)
+    # working tolerance: one step judged in the oracle's CSR
+    o8 = hts.default_opts(rtol=1e-8, mode=hts.MODE_LEARNED)
+    o8.nn = net.h.value
+    m8 = hts.from_scenario(scn, opts=o8)
+    code, st = m8.solve_step(scn.dt, o8)
+    assert code == 0
+    print("backward errors", judge_first_step(scn, m8.get_state(0)[0], m8.get_state(1)[0], 1.0001e-8))
+
+
+def test_learned_gain_over_multigrid(hts, trained):
+    """What the trained network gains over plain multigrid CG on an unseen
+    draw, measured as pressure iterations to a 1e-8 relative residual.  On
+    this problem it gains nothing: a V-cycle reduces the residual about 20x
+    per iteration, the network's direction less, and the fallback rule
+    switches to the V-cycle within the first iterations.  The test states
+    that measured outcome: the learned solve needs at least as many
+    iterations as plain multigrid and at most 4x as many, and every step
+    converges to the FP64 residual."""
+    net, _ = trained
+    seed = 5100
+    print_case("learned gain", seed)
+    _, s64 = solve_steps(hts, seed, hts.default_opts(rtol=1e-8))
     o = hts.default_opts(rtol=1e-8, mode=hts.MODE_LEARNED)
     o.nn = net.h.value
-    PL, sL = solve_steps(hts, seed, o)
+    _, sL = solve_steps(hts, seed, o)
     for st in sL:
         assert st["status"] == [0, 0]
         assert st["relres"][0] <= 1e-8
-    assert np.linalg.norm(PL - P64) <= 1e-8 * np.linalg.norm(P64)
     it64 = sum(s["iters"][0] for s in s64)
     itL = sum(s["iters"][0] for s in sL)
     fb = sum(s["fallbacks"] for s in sL)
-    ms64 = sum(s["time_ms"][0] for s in s64)
-    msL = sum(s["time_ms"][0] for s in sL)
-    print("pressure iterations: multigrid %d, learned %d (fallbacks %d); ms %.2f vs %.2f"
-          % (it64, itL, fb, ms64, msL))
+    print("pressure iterations: multigrid %d, learned %d (fallbacks %d)" % (it64, itL, fb))
+    assert it64 <= itL <= 4 * it64
 
 
 def test_sabotaged_network_falls_back(hts):
@@ -247,3 +313,74 @@ def test_sabotaged_network_falls_back(hts):
     assert sL[0]["status"] == [0, 0]
     assert sL[0]["relres"][0] <= 1e-8
     assert np.linalg.norm(PL - P64) <= 1e-8 * np.linalg.norm(P64)
+    scn = synth.config5(5101, ncells=NC, n_steps=4)
+    m = hts.from_scenario(scn, opts=o)
+    code, st = m.solve_step(scn.dt, o)
+    assert code == 0 and st["fallbacks"] >= 1
+    print("backward errors", judge_first_step(scn, m.get_state(0)[0], m.get_state(1)[0], 1.0001e-8))
+
+
+# ------------------------------------------------------------------- Adam
+@pytest.mark.parametrize("step", [1, 3, 60])
+def test_adam_kernel_per_element(hts, step):
+    """The FP32 Adam kernel against the FP64 oracle Adam with the kernel's
+    hyperparameters (the FP32 values nearest 0.9, 0.999 and 1e-8), per
+    element.  Bound, from the FP32 operations of one update (u = 2^-24):
+    m: 4u (|b1 m| + |(1-b1) g|);  v: 5u (|b2 v| + |(1-b2) g^2|);  the bias
+    corrections 1/(1 - b^t) carry u (2 kappa + 3) relative, kappa =
+    b^t / (1 - b^t) (powf within 2 ulp, cancellation in 1 - b^t); the step
+    lr mhat / (sqrt(vhat) + eps) adds these relative errors (half of those of
+    vhat) plus 6u, and the final subtraction u |w|.  The BF16 copy must be
+    the round-to-nearest-even of the new FP32 weight, bit for bit."""
+    print_case("adam", step)
+    rng = np.random.default_rng(40 + step)
+    n = 4099
+    f32 = lambda a: np.asarray(a, dtype=np.float32)
+    w = f32(rng.standard_normal(n))
+    g = f32(rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 1, n))
+    g[:5] = 0.0
+    m = f32(0.1 * rng.standard_normal(n)) if step > 1 else np.zeros(n, np.float32)
+    v = f32(0.01 * rng.uniform(0, 1, n) ** 2) if step > 1 else np.zeros(n, np.float32)
+    lr, gs = 2e-3, 0.25
+    wg, mg, vg, wbf = hts.adam_step(step, lr, gs, w, m, v, g)
+    b1, b2, eps = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-8))
+    gi = g.astype(np.float64) * gs
+    wr, mr, vr = nnet.adam(w, gi, m, v, step, lr, beta1=b1, beta2=b2, eps=eps)
+    u = U32
+    em = 4 * u * (np.abs(b1 * m) + np.abs((1 - b1) * gi))
+    ev = 5 * u * (np.abs(b2 * v) + np.abs((1 - b2) * gi * gi))
+    assert np.all(np.abs(mg - mr) <= em)
+    assert np.all(np.abs(vg - vr) <= ev)
+    k1, k2 = b1 ** step / (1 - b1 ** step), b2 ** step / (1 - b2 ** step)
+    rc1, rc2 = u * (2 * k1 + 3), u * (2 * k2 + 3)
+    c1, c2 = 1 / (1 - b1 ** step), 1 / (1 - b2 ** step)
+    sq = np.sqrt(vr * c2)
+    D = sq + eps
+    upd = lr * np.abs(mr) * c1 / D
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rv = np.where(vr > 0, ev / vr, 0.0)
+    eu = lr * em * c1 / D + upd * (rc1 + (0.5 * (rv + rc2) + 2 * u) * sq / D + 6 * u)
+    err = np.abs(wg.astype(np.float64) - wr)
+    tol = eu + u * np.abs(wr)
+    assert np.all(err <= tol), float(np.max(err / tol))
+    assert np.array_equal(bits(nnet.bf16(wg)), wbf)
+
+
+def test_gamma_scales_every_target_once(hts):
+    """Gamma (the target scale) is fixed by the first train call and each
+    harvested target is divided by it exactly once: a train call with no
+    epochs leaves the held-out loss unchanged when repeated, and pairs
+    harvested after a train call (here from a copy of the held-out draw)
+    give the same held-out loss as the original ones."""
+    print_case("gamma bookkeeping")
+    o = hts.default_opts()
+    scn = [synth.config5(5000 + i, ncells=(16, 16, 8), n_steps=2) for i in range(2)]
+    a, b, b2 = (hts.from_scenario(sc, opts=o) for sc in (scn[0], scn[1], scn[1]))
+    net = hts.Net(levels=3, channels=(16, 32, 48), seed=5)
+    net.harvest([a, b], 2, synth.DAY, 4)
+    s1 = net.train(epochs=0, lr=1e-3, batch=2, val_draws=1)
+    s2 = net.train(epochs=0, lr=1e-3, batch=2, val_draws=1)
+    assert s1["val_loss"] > 0 and s1["val_loss"] == s2["val_loss"]
+    net.harvest([b2], 2, synth.DAY, 4)      # draws a, b, b2: b2 is now held out
+    s3 = net.train(epochs=0, lr=1e-3, batch=2, val_draws=1)
+    assert s3["val_loss"] == pytest.approx(s1["val_loss"], rel=1e-6)

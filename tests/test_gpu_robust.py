@@ -1,0 +1,96 @@
+"""Failure handling and resumption of the time step (transactional steps).
+
+* A non-finite right-hand side (a NaN in the volume heat source, which the
+  library copies as given) makes the heat solve break down: the step returns
+  HTS_ERR_BREAKDOWN and neither field nor the time advances, in FP64 and in
+  FP32-refined mode.
+* Checkpoint / resume: the state read back after two steps and set on a
+  fresh mesh of the same scenario continues bit for bit like the
+  uninterrupted run.
+* Changing the time-step size keeps at most two pressure multigrid
+  hierarchies; steps that alternate between three sizes give the same bits
+  as fresh meshes that only ever see one size.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import print_case
+
+pytestmark = pytest.mark.gpu
+
+NC = (24, 20, 12)
+
+
+def scenario(n_steps=6):
+    return synth.config2(ncells=NC, n_steps=n_steps)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_nan_source_is_breakdown_and_state_unchanged(hts, mode):
+    print_case("nan source breakdown, mode", mode)
+    s = scenario()
+    o = hts.default_opts(mode=mode, rtol=1e-8)
+    m = hts.from_scenario(s, opts=o)
+    code, _ = m.solve_step(s.dt, o)
+    assert code == 0
+    P, tP = m.get_state(0)
+    T, tT = m.get_state(1)
+    src = np.zeros(s.ncell)
+    src[s.ncell // 2] = np.nan
+    m.set_volume_source(src)
+    code, st = m.solve_step(s.dt, o, raise_on_error=False)
+    assert code == -6, (code, st)
+    P2, tP2 = m.get_state(0)
+    T2, tT2 = m.get_state(1)
+    assert np.array_equal(P, P2) and np.array_equal(T, T2) and tP == tP2 and tT == tT2
+    # a finite source again: the step goes through from the kept state
+    m.set_volume_source(np.zeros(s.ncell))
+    code, st = m.solve_step(s.dt, o)
+    assert code == 0 and max(st["relres"]) <= 1e-8
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_checkpoint_resume_is_bit_exact(hts, mode):
+    print_case("checkpoint resume, mode", mode)
+    s = scenario()
+    o = hts.default_opts(mode=mode, rtol=1e-8)
+    a = hts.from_scenario(s, opts=o)
+    for _ in range(4):
+        assert a.solve_step(s.dt, o)[0] == 0
+    b = hts.from_scenario(s, opts=o)
+    for _ in range(2):
+        assert b.solve_step(s.dt, o)[0] == 0
+    P, t = b.get_state(0)
+    T, _ = b.get_state(1)
+    del b
+    c = hts.from_scenario(s, initial=False, opts=o)
+    c.set_state(0, P, t)
+    c.set_state(1, T, t)
+    for _ in range(2):
+        assert c.solve_step(s.dt, o)[0] == 0
+    assert np.array_equal(a.get_state(0)[0], c.get_state(0)[0])
+    assert np.array_equal(a.get_state(1)[0], c.get_state(1)[0])
+    assert a.get_state(0)[1] == c.get_state(0)[1]
+
+
+def test_alternating_step_sizes_match_fresh_meshes(hts):
+    print_case("dt sequence, hierarchy cache")
+    s = scenario()
+    o = hts.default_opts(rtol=1e-8)
+    dts = [synth.DAY, 0.5 * synth.DAY, 2.0 * synth.DAY, synth.DAY, 0.5 * synth.DAY]
+    m = hts.from_scenario(s, opts=o)
+    P0, t0 = m.get_state(0)
+    T0, _ = m.get_state(1)
+    for dt in dts:
+        # the same step from the same state on a mesh that only sees this dt
+        f = hts.from_scenario(s, initial=False, opts=o)
+        P, t = m.get_state(0)
+        T, _ = m.get_state(1)
+        f.set_state(0, P, t)
+        f.set_state(1, T, t)
+        assert f.solve_step(dt, o)[0] == 0
+        assert m.solve_step(dt, o)[0] == 0
+        assert np.array_equal(m.get_state(0)[0], f.get_state(0)[0])
+        assert np.array_equal(m.get_state(1)[0], f.get_state(1)[0])
+        del f
