@@ -267,6 +267,23 @@ hts_status hts_solve_step(hts_mesh *mesh, double dt, const hts_solver_opts *opts
 hts_status hts_advance(hts_mesh *const *meshes, int32_t n_instances, int32_t n_steps, double dt,
                        const hts_solver_opts *opts, hts_step_stats *stats);
 
+/* The same operation as hts_apply_operator (same arguments, layout, result
+ * bit for bit) for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * It calls no allocator: the descriptors, the work list, the heat
+ * operator's time slots, line-source coefficients and FP32 piezometric
+ * pressure live in one static 40 MiB device array per GPU, held until the
+ * process ends (FP32 heat applies need 4 bytes per node of it, so meshes up
+ * to about 10 M nodes; larger ones give HTS_ERR_ARG before any device
+ * work).  Every call on a GPU reuses that array: calls that overlap on one
+ * GPU (several streams or threads) race and must be serialised by the
+ * caller.  The mesh's own derived data must exist: HTS_ERR_STATE if the mesh
+ * changed since its last hts_apply_operator, hts_autotune or solve (which
+ * rebuild it), or if the heat operator is asked for without a pressure
+ * state.  All work is enqueued on the mesh's stream; nothing synchronises. */
+hts_status hts_apply_operator_noalloc(hts_mesh *m, hts_field field, hts_precision prec, double dt,
+                                      const void *x_dev, void *y_dev);
+
 /* Time several operator tile shapes on these meshes and keep the fastest
  * per (degree, field, precision, size class) for later launches. */
 hts_status hts_autotune(hts_mesh *const *meshes, int32_t n);

@@ -34,7 +34,7 @@ EXPORTS = [
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
     "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing", "hts_nn_num_params",
     "hts_nn_set_params", "hts_nn_get_params", "hts_nn_eval", "hts_nn_conv3d", "hts_nn_adam", "hts_nn_time_forward",
-    "hts_stream_copy",
+    "hts_stream_copy", "hts_apply_operator_noalloc",
 ]
 
 
@@ -155,6 +155,7 @@ def load():
         "hts_nn_adam": (st, [C.c_int64, i32, d, d, vp, vp, vp, vp, vp, vp]),
         "hts_nn_time_forward": (st, [vp, P(i32), i32, P(d), P(d)]),
         "hts_stream_copy": (st, [vp, vp, C.c_int64, i32, vp, P(d)]),
+        "hts_apply_operator_noalloc": (st, [vp, i32, i32, d, vp, vp]),
         "hts_nn_save": (st, [vp, C.c_char_p]),
         "hts_nn_load": (st, [vp, C.c_char_p]),
         "hts_kernel_timing": (st, [i32, vp]),
@@ -307,6 +308,10 @@ class Mesh:
     def apply_operator(self, field, prec, dt, x, y):
         """y = A x on device tensors (float64 for FP64, float32 for FP32)."""
         _check(load().hts_apply_operator(self.h, field, prec, dt, _ptr(x), _ptr(y)))
+
+    def apply_operator_noalloc(self, field, prec, dt, x, y):
+        """As apply_operator, through the allocation-free entry point."""
+        _check(load().hts_apply_operator_noalloc(self.h, field, prec, dt, _ptr(x), _ptr(y)))
 
     def solve_steady_pressure(self, opts=None):
         st = StepStats()

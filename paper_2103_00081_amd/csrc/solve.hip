@@ -179,18 +179,25 @@ int tuned_zc(int degree, int field, int NX, int NY, int NZ)
     return it == g_tune.end() ? 0 : it->second;
 }
 
-int Batch::pick_zc(int field, const hts_mesh *M, int64_t tiles) const
+int tile_own(int degree) { return degree == 2 ? 30 : 15; }
+
+int zc_for(const hts_mesh *M, int field, int64_t tiles, int force)
 {
     const int NZ = M->N[2];
     // Q2 work items start on even node planes (cell-layer boundaries)
     auto fit = [&](int z) { return M->p == 2 ? std::max(2, (std::min(z, NZ) + 1) / 2 * 2) : std::min(z, NZ); };
-    if (zc_force[field] > 0) return fit(zc_force[field]);
+    if (force > 0) return fit(force);
     const int t = tuned_zc(M->p, field, M->N[0], M->N[1], NZ);
     if (t > 0) return fit(t);
     // enough blocks to fill 256 CUs several times over
     int64_t z = std::max<int64_t>(4, (tiles * NZ) / 2048);
     z = std::min<int64_t>(z, 32);
     return fit((int)z);
+}
+
+int Batch::pick_zc(int field, const hts_mesh *M, int64_t tiles) const
+{
+    return zc_for(M, field, tiles, zc_force[field]);
 }
 
 void Batch::build_work()
@@ -200,7 +207,7 @@ void Batch::build_work()
         std::vector<WorkItem> nat;
         for (int i = 0; i < n; i++) {
             hts_mesh *M = m[i];
-            const int own = M->p == 2 ? 30 : 15;   // owned node columns per tile edge
+            const int own = tile_own(M->p);   // owned node columns per tile edge
             const int tx = (M->N[0] + own - 1) / own, ty = (M->N[1] + own - 1) / own;
             const int zc = pick_zc(f, M, (int64_t)tx * ty);
             for (int z0 = 0; z0 < M->N[2]; z0 += zc)
