@@ -76,6 +76,10 @@ struct OpDev {
     double cs;                 // stiffness scale: pressure dt*B (or 1), heat dt
     double cadv;               // heat: dt * c_w
     double rho_g;              // rho_w * g
+    // Q1 cell factors of the unscaled 1D products on a uniform mesh, formed
+    // on the host: mass V / 216, stiffness cs (hy hz / hx) / 36 (and the
+    // y, z analogues), convection -cadv V / (8 h_d^2)
+    double q1m, q1x, q1y, q1z, q1vx, q1vy, q1vz;
     const void *k;             // [ncell] k_c              (T)
     const void *lam;           // [ncell] lambda_c         (T, heat)
     const void *cT;            // [ncell] c_T,c            (T, heat)

@@ -199,7 +199,8 @@ void prepare_mesh(hts_mesh *m);                 // (re)build derived device data
 void forget_batches(hts_mesh *m);               // drop every cached batch that holds m (solve.hip)
 bool is_constrained(const hts_mesh *m, int field, int i, int j, int k);   // host, after prepare_mesh
 OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, bool mass_only);
-int tile_own(int degree);                       // owned node columns per tile edge of the operator kernels
+int tile_own_x(int degree, int field);          // owned node columns per tile of the operator kernels, x
+int tile_own_y(int degree, int field);          // and y
 // node planes per work item of the operator kernels (force > 0: that depth)
 int zc_for(const hts_mesh *M, int field, int64_t tiles, int force);
 

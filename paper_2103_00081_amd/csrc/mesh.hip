@@ -458,6 +458,16 @@ OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, b
     o.lfcol = (o.lcol && m->lfcol.p) ? m->lfcol.p : nullptr;
     o.lflat = m->lflat.p;
     o.lcoef = nullptr;
+    {
+        const double V = o.hx * o.hy * o.hz, cw8 = o.cadv * V * 0.125;
+        o.q1m = V / 216.0;
+        o.q1x = o.cs * (o.hy * o.hz / o.hx) / 36.0;
+        o.q1y = o.cs * (o.hx * o.hz / o.hy) / 36.0;
+        o.q1z = o.cs * (o.hx * o.hy / o.hz) / 36.0;
+        o.q1vx = -cw8 / (o.hx * o.hx);
+        o.q1vy = -cw8 / (o.hy * o.hy);
+        o.q1vz = -cw8 / (o.hz * o.hz);
+    }
     return o;
 }
 

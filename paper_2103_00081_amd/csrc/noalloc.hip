@@ -118,8 +118,8 @@ extern "C" hts_status hts_apply_operator_noalloc(hts_mesh *m, hts_field field, h
         const hipStream_t s = m->stream;
         const bool fp32 = prec == HTS_FP32;
         const bool steady = field == 0 && (dt <= 0.0 || m->B <= 0.0);
-        const int own = tile_own(m->p);
-        const int ntx = (m->N[0] + own - 1) / own, nty = (m->N[1] + own - 1) / own;
+        const int ox = tile_own_x(m->p, field), oy = tile_own_y(m->p, field);
+        const int ntx = (m->N[0] + ox - 1) / ox, nty = (m->N[1] + oy - 1) / oy;
         const int zc = zc_for(m, field, (int64_t)ntx * nty, 0);
         const int64_t nzc = (m->N[2] + zc - 1) / zc;
         const int64_t nwork = (int64_t)ntx * nty * nzc;

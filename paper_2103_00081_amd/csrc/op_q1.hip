@@ -1,16 +1,22 @@
 // Matrix-free Q1 operators of the pressure (Eq. 3) and heat (Eq. 4)
 // equations on a uniform box, sum-factorised per cell.
 //
-// Kernel layout: a 256-thread workgroup owns a 15 x 15 tile of node columns
-// and marches upward through a range of node planes.  Each thread handles
-// one cell column of the 16 x 16 cells that touch the tile (one-cell halo on
-// the low x/y side).  Per cell layer the two node planes are staged in LDS;
-// each thread evaluates its cell's 8 outputs by Kronecker sum factorisation
-// (1D mass h/6 [2 1; 1 2] and stiffness 1/h [1 -1; -1 1] in each direction,
-// 2-point Gauss for the convection term) and writes its four plane-corner
-// contributions to LDS; the owner of a node adds the four cell contributions
-// in a fixed order.  Every node value is produced by exactly one thread:
-// no atomics, bitwise reproducible.
+// Kernel layout: a 256-thread workgroup (16 x 16 threads) owns a 31 x 15
+// tile of node columns and marches upward through a range of node planes.
+// Each thread handles two neighbouring cell columns along x of the 32 x 16
+// cells that touch the tile (one-cell halo on the low x/y side).  Per cell
+// layer the new node plane is staged in LDS; each thread keeps its own 3 x 2
+// node values of the previous plane in registers, evaluates both cells by
+// Kronecker sum factorisation (1D mass h/6 [2 1; 1 2] and stiffness
+// 1/h [1 -1; -1 1] in each direction; the y-z factors of the face the two
+// cells share are formed once; 2-point Gauss for the convection term), sums
+// the contributions to its 3 x 2 plane corners and passes the four that
+// other threads own through LDS.  A thread owns the node between its two
+// cells and the node to the right of its second cell; the owner of a node
+// adds the contributions in a fixed order.  Every node value is produced by
+// exactly one thread: no atomics, bitwise reproducible.
+#include <type_traits>
+
 #include "common.h"
 #include "dev_util.h"
 
@@ -18,9 +24,17 @@ namespace hts {
 
 namespace {
 
-constexpr int TB = 16;          // cell columns per tile edge
-constexpr int OWN = TB - 1;     // owned node columns per tile edge
-constexpr int NCOL = (TB + 1) * (TB + 1);
+constexpr int TCX = 32;                       // cell columns per tile along x
+constexpr int TCY = 16;                       // cell columns per tile along y
+constexpr int OWNX = TCX - 1, OWNY = TCY - 1; // owned node columns per tile
+constexpr int SXN = TCX + 1, SYN = TCY + 1;   // staged node columns per plane
+constexpr int SXP = SXN + 1;                  // LDS row pitch (even: 16-byte pair reads)
+constexpr int NSTAGE = SXN * SYN;             // 561 staged values per plane
+// node planes loaded ahead of the one being staged: two for the pressure
+// operator, one for the heat operator (whose registers go to the convection
+// term)
+template <int FIELD>
+constexpr int prefetch_planes() { return FIELD ? 1 : 2; }
 
 // The 1D factors are applied unscaled, [2 1; 1 2] for the mass matrix
 // (h/6 times it) and [1 -1; -1 1] for the stiffness matrix (1/h times it);
@@ -133,8 +147,533 @@ __device__ __forceinline__ void cell_convect(const T u[8], const T P[8], T ax_, 
                 w[x + 2 * y + 4 * z] += (ax[y + 2 * z] + ay[x + 2 * z]) + az[x + 2 * y];
 }
 
+// Element i of an instance vector through a 32-bit byte offset from a
+// uniform base (one vector stays below 4 GiB), so the loads and stores take
+// the scalar-base plus 32-bit-offset address form without 64-bit address
+// arithmetic per lane.
+template <typename P>
+__device__ __forceinline__ P *at32(P *base, uint32_t i)
+{
+    using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    return reinterpret_cast<P *>(reinterpret_cast<C *>(base) + i * (uint32_t)sizeof(P));
+}
+template <typename P>
+__device__ __forceinline__ const P HTS_GLOBAL *at32(const P HTS_GLOBAL *base, uint32_t i)
+{
+    return reinterpret_cast<const P HTS_GLOBAL *>(reinterpret_cast<const char HTS_GLOBAL *>(base) +
+                                                  i * (uint32_t)sizeof(P));
+}
+
+// y-z factors of one x-face of a cell from its node values v{y}{z}, with the
+// unscaled 1D factors: c = (Mz My) v (index y + 2 z), the part with the y
+// stiffness (Mz Ky) v in its two magnitudes d[z] (sign + at y = 0, - at
+// y = 1) and the part with the z stiffness (Kz My) v in its two magnitudes
+// e[y] (sign + at z = 0, - at z = 1).  Two cells that share the face share
+// these.
+template <typename T>
+struct FaceYZ {
+    T c[4];
+    T d[2];
+    T e[2];
+};
+
+template <typename T>
+__device__ __forceinline__ FaceYZ<T> face_yz(T v00, T v10, T v01, T v11)
+{
+    FaceYZ<T> f;
+    const T a00 = T(2) * v00 + v01, a01 = v00 + T(2) * v01;   // mass along z, y = 0
+    const T a10 = T(2) * v10 + v11, a11 = v10 + T(2) * v11;   // y = 1
+    const T b0 = v00 - v01, b1 = v10 - v11;                   // stiffness along z, z = 0 row
+    f.c[0] = T(2) * a00 + a10;
+    f.c[1] = a00 + T(2) * a10;
+    f.c[2] = T(2) * a01 + a11;
+    f.c[3] = a01 + T(2) * a11;
+    f.d[0] = a00 - a10;
+    f.d[1] = a01 - a11;
+    f.e[0] = T(2) * b0 + b1;
+    f.e[1] = b0 + T(2) * b1;
+    return f;
+}
+
+// w = m (M x M x M) u + (sx K x M x M + sy M x K x M + sz M x M x K) u of the
+// cell whose x = 0 and x = 1 faces are F0 and F1 (corner index x + 2y + 4z);
+// for mass coefficient c and stiffness coefficient s of a cell: m = c V / 216,
+// sx = s (hy hz / hx) / 36, and so on.
+template <typename T>
+__device__ __forceinline__ void cell_from_faces(const FaceYZ<T> &F0, const FaceYZ<T> &F1, T m, T sx, T sy, T sz,
+                                                T w[8])
+{
+#pragma unroll
+    for (int z = 0; z < 2; z++)
+#pragma unroll
+        for (int y = 0; y < 2; y++) {
+            const int q = y + 2 * z;
+            const T sd = y == 0 ? sy : -sy, se = z == 0 ? sz : -sz;
+            const T f0 = m * F0.c[q] + (sd * F0.d[z] + se * F0.e[y]);
+            const T f1 = m * F1.c[q] + (sd * F1.d[z] + se * F1.e[y]);
+            const T g = sx * (F0.c[q] - F1.c[q]);
+            w[2 * y + 4 * z] = (T(2) * f0 + f1) + g;
+            w[1 + 2 * y + 4 * z] = (f0 + T(2) * f1) - g;
+        }
+}
+
 template <typename T, int FIELD, int EPI, bool MASKED, bool GRADED>
 __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
+                                                  const WorkItem *__restrict__ work,
+                                                  const T *__restrict__ X, T *__restrict__ Y,
+                                                  EpiArgs<T> ep)
+{
+    // Software pipeline over node planes, one barrier per plane: x planes in
+    // an LDS ring (plane p in slot p % XR), pressure planes (heat) in a ring
+    // of 2, the four exchanged plane-corner sums of each thread in a ring of
+    // 2; the global loads of plane L+2, of the coefficients of layer L+1 and
+    // of the epilogue operands of plane L are issued one iteration before
+    // they are used.  Heat: a 5-deep x ring, so that the epilogue of plane P
+    // can read planes P-1 .. P+1 for the injection-line rows while a faster
+    // thread already stores plane P+3.
+    constexpr int XR = FIELD ? 5 : 2;
+    constexpr int PD = prefetch_planes<FIELD>();
+    __shared__ __align__(16) T xs[XR][SYN][SXP];
+    __shared__ __align__(16) T ps[FIELD ? 2 : 1][FIELD ? SYN : 1][FIELD ? SXP : 2];
+    __shared__ T ex[2][4][TCY][17];
+    __shared__ double red[4];
+
+    const WorkItem wi = work[blockIdx.x];
+    if (ep.active && !ep.active[wi.inst]) return;
+    const OpDev &o = ops[wi.inst];
+    const int nx = o.nx, ny = o.ny, nz = o.nz, NZ = o.NZ, m = o.dmask;
+    const T *__restrict__ Xi = X + o.off;
+    T *__restrict__ Yi = Y + o.off;
+    const T HTS_GLOBAL *__restrict__ Pi = gptr<T>(FIELD ? o.P : nullptr);
+    const T HTS_GLOBAL *__restrict__ kk = gptr<T>(o.k);
+    const T HTS_GLOBAL *__restrict__ lamc = gptr<T>(o.lam);
+    const T HTS_GLOBAL *__restrict__ cTc = gptr<T>(o.cT);
+    constexpr bool CHEB = EPI == EPI_CHEB || EPI == EPI_CHEB0;
+    const T *__restrict__ Bi = (EPI == EPI_RESID || EPI == EPI_RESID_NORM || CHEB) ? ep.b + o.off : nullptr;
+    T *__restrict__ Di = CHEB ? ep.d + o.off : nullptr;
+    const T *__restrict__ Ii = CHEB ? ep.invd + o.off : nullptr;
+
+    // Node and cell indices are instance-local and below 2^31: 32-bit index
+    // arithmetic (the vectors are offset to the instance already).
+    // (unsigned offsets: the loads take a uniform base and a 32-bit offset)
+    const uint32_t plane32 = (uint32_t)(o.NX * o.NY);
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int lx = 2 * tx;                        // local x of the thread's first cell
+    const int cx0 = wi.tx * OWNX - 1, cy0 = wi.ty * OWNY - 1;
+    const int cxa = cx0 + lx, cy = cy0 + ty;      // global indices of cell 0 (cell 1 is cxa + 1)
+    const bool cyin = cy >= 0 && cy < ny;
+    const bool cin0 = cyin && cxa >= 0 && cxa < nx;
+    const bool cin1 = cyin && cxa + 1 >= 0 && cxa + 1 < nx;
+    const uint32_t cbase0 = cin0 ? (uint32_t)(cxa + nx * cy) : 0u, cbase1 = cin1 ? (uint32_t)(cxa + 1 + nx * cy) : 0u;
+    const uint32_t cplane = (uint32_t)(nx * ny);
+
+    // staged node columns of this thread (three slots, the third only for
+    // the first NSTAGE - 512 threads): base index (0 outside the mesh, so the
+    // loads stay in range; the value is then discarded), in the mesh, kept
+    // (not on a constraining x/y face), constrained z-range
+    int lj[3], li[3];
+    bool sval[3], scol[3];
+    uint32_t sbase[3];
+    int sdlo[3], sdhi[3];
+    const bool ld2 = tid < NSTAGE - 512;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const int c = tid + q * 256;
+        li[q] = c % SXN;
+        lj[q] = c / SXN;
+        ColInfo lc;
+        if (q < 2 || ld2) lc = col_info(o, cx0 + li[q], cy0 + lj[q]);
+        else { lc.valid = 0; lc.base = 0; lc.xyc = 0; lc.dlo = 1; lc.dhi = 0; li[q] = 0; lj[q] = 0; }
+        sval[q] = lc.valid;
+        scol[q] = lc.valid && !(MASKED && lc.xyc);
+        sbase[q] = lc.valid ? (uint32_t)lc.base : 0u;
+        sdlo[q] = lc.dlo;
+        sdhi[q] = lc.dhi;
+    }
+    // owned nodes: A between the thread's two cells, B right of its second
+    // cell (not for the last thread of a row), both on the upper cell row
+    const bool ownrow = ty < OWNY;
+    const ColInfo ocA = col_info(o, cx0 + lx + 1, cy0 + ty + 1);
+    const ColInfo ocB = col_info(o, cx0 + lx + 2, cy0 + ty + 1);
+    const bool okA = ownrow && ocA.valid, okB = ownrow && tx < 15 && ocB.valid;
+    int lrA = -1, lrB = -1;
+    LineCol lhA{-1, 0, -1, 0}, lhB{-1, 0, -1, 0};
+    if (FIELD && o.lfcol) {
+        const LineCol HTS_GLOBAL *hp = gptr<LineCol>(o.lfcol);
+        if (okA) { lhA.first = hp[ocA.base].first; lhA.kmin = hp[ocA.base].kmin; lhA.kmax = hp[ocA.base].kmax; }
+        if (okB) { lhB.first = hp[ocB.base].first; lhB.kmin = hp[ocB.base].kmin; lhB.kmax = hp[ocB.base].kmax; }
+    }
+    if (FIELD && !o.lfcol && o.lcol) {
+        if (okA) lrA = gptr<int32_t>(o.lcol)[ocA.base];
+        if (okB) lrB = gptr<int32_t>(o.lcol)[ocB.base];
+    }
+
+    // per-cell coefficient factors of the unscaled 1D products (formed in
+    // double on the host, rounded once here)
+    const T fm = T(o.q1m), fx = T(o.q1x), fy = T(o.q1y), fz = T(o.q1z);
+    const T vx = T(o.q1vx), vy = T(o.q1vy), vz = T(o.q1vz);
+    const T pz0 = T(o.rho_g * o.hz);   // rho_g is 0 where the pressure is piezometric
+    const T cm = T(o.cm);
+    const bool adv = o.cadv != 0.0;
+    // graded meshes: every factor is a per-column part (from the cell's hx,
+    // hy, formed once in double and rounded) times hz or 1 / hz of the layer
+    const bool graded = GRADED && o.hzs != nullptr;
+    T gm[2] = {T(0), T(0)}, gx[2] = {T(0), T(0)}, gy[2] = {T(0), T(0)}, gz[2] = {T(0), T(0)};
+    T gvx[2] = {T(0), T(0)}, gvy[2] = {T(0), T(0)}, gvz[2] = {T(0), T(0)};
+    if (graded) {
+        const int iy = cy < 0 ? 0 : (cy >= ny ? ny - 1 : cy);
+        const double ghy = o.hys[iy];
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const int c = cxa + q, ix = c < 0 ? 0 : (c >= nx ? nx - 1 : c);
+            const double ghx = o.hxs[ix], hxy = ghx * ghy;
+            gm[q] = T(hxy / 216.0);                           // x hz
+            gx[q] = T(o.cs * (ghy / ghx) / 36.0);             // x hz
+            gy[q] = T(o.cs * (ghx / ghy) / 36.0);             // x hz
+            gz[q] = T(o.cs * hxy / 36.0);                     // x 1/hz
+            gvx[q] = T(-o.cadv * 0.125 * ghy / ghx);          // x hz
+            gvy[q] = T(-o.cadv * 0.125 * ghx / ghy);          // x hz
+            gvz[q] = T(-o.cadv * 0.125 * hxy);                // x 1/hz
+        }
+    }
+    T c0 = T(0), c1 = T(0), c2 = T(0);
+    if (CHEB) {
+        const double *Sc = ep.S + (int64_t)wi.inst * NSLOT;
+        c1 = T(Sc[ep.s1]);
+        c2 = T(Sc[ep.s2]);
+        if (EPI == EPI_CHEB0) c0 = T(Sc[ep.s0]);
+    }
+
+    // Plane / coefficient / epilogue loads are unconditional (clamped to a
+    // valid address) and the keep-or-zero decision is a select applied when
+    // the value is consumed, so no branch forces an early wait on a load.
+    // PD planes are in flight ahead of the one being stored (slot 0); the
+    // keep decisions are all-ones / zero bit masks held in vector registers
+    // (bool arrays would take a 64-bit scalar mask each)
+    using UT = typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type;
+    T pfx[PD][3], pfp[PD][3];
+    UT pkeep[PD][3], pin[PD][3];
+    auto fetch_plane = [&](int k, int d) {
+        const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
+        const uint32_t koff = (uint32_t)kc * plane32;
+        // the part of the keep decision that is the same for every column
+        const bool kin = k >= 0 && k < NZ;
+        const bool kkeep = kin && !(MASKED && (((m & 16) && k == 0) || ((m & 32) && k == NZ - 1)));
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const uint32_t gi = sbase[q] + koff;
+            // EPI_CHEB0 operand: x0 = c0 D^-1 b, in the order of the
+            // separate first Chebyshev kernel
+            if (EPI == EPI_CHEB0) pfx[d][q] = c0 * *at32(Ii, gi) * *at32(Bi, gi);
+            else pfx[d][q] = *at32(Xi, gi);
+            if (FIELD) pfp[d][q] = *at32(Pi, gi);
+            bool keep = kkeep && scol[q];
+            if (MASKED) keep = keep && !(k >= sdlo[q] && k <= sdhi[q]);
+            pkeep[d][q] = keep ? ~UT(0) : UT(0);
+            pin[d][q] = (kin && sval[q]) ? ~UT(0) : UT(0);
+        }
+    };
+    auto store_plane = [&](int bx, int bp) {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            if (q == 2 && !ld2) continue;
+            xs[bx][lj[q]][li[q]] = __builtin_bit_cast(T, __builtin_bit_cast(UT, pfx[0][q]) & pkeep[0][q]);
+            if (FIELD)
+                ps[FIELD ? bp : 0][lj[q]][li[q]] = __builtin_bit_cast(T, __builtin_bit_cast(UT, pfp[0][q]) & pin[0][q]);
+        }
+    };
+    // the thread's 3 x 2 node values of a staged plane: [y * 3 + c]
+    auto read_plane = [&](int bx, int bp, T *u, T *pp) {
+#pragma unroll
+        for (int y = 0; y < 2; y++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                u[3 * y + c] = xs[bx][ty + y][lx + c];
+                if (FIELD) pp[3 * y + c] = ps[FIELD ? bp : 0][ty + y][lx + c];
+            }
+    };
+    // coefficients of PD layers in flight, slot 0 the layer computed next
+    T cfk[PD][2], cfl[PD][2], cfc[PD][2];
+    double cfh[PD], cfih[PD];     // graded: hz and 1/hz of the layer
+    auto fetch_coef = [&](int L, int d) {
+        const int Lc = L < 0 ? 0 : (L >= nz ? nz - 1 : L);
+        const uint32_t lo = (uint32_t)Lc * cplane;
+        cfk[d][0] = *at32(kk, cbase0 + lo);
+        cfk[d][1] = *at32(kk, cbase1 + lo);
+        if (FIELD) {
+            cfl[d][0] = *at32(lamc, cbase0 + lo);
+            cfl[d][1] = *at32(lamc, cbase1 + lo);
+            cfc[d][0] = *at32(cTc, cbase0 + lo);
+            cfc[d][1] = *at32(cTc, cbase1 + lo);
+        }
+        cfh[d] = 0.0;
+        cfih[d] = 0.0;
+        if (graded) { cfh[d] = o.hzs[Lc]; cfih[d] = o.ihzs[Lc]; }
+    };
+    // advance the prefetch slots by one
+    auto shift = [&]() {
+#pragma unroll
+        for (int d = 0; d + 1 < PD; d++) {
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                pfx[d][q] = pfx[d + 1][q];
+                pfp[d][q] = pfp[d + 1][q];
+                pkeep[d][q] = pkeep[d + 1][q];
+                pin[d][q] = pin[d + 1][q];
+            }
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                cfk[d][q] = cfk[d + 1][q];
+                cfl[d][q] = cfl[d + 1][q];
+                cfc[d][q] = cfc[d + 1][q];
+            }
+            cfh[d] = cfh[d + 1];
+            cfih[d] = cfih[d + 1];
+        }
+    };
+    // epilogue operands of the two owned nodes
+    const uint32_t obA = okA ? (uint32_t)ocA.base : 0u, obB = okB ? (uint32_t)ocB.base : 0u;
+    T eb[2] = {T(0), T(0)}, ed[2] = {T(0), T(0)}, ei[2] = {T(0), T(0)}, exv[2] = {T(0), T(0)};
+    auto fetch_epi = [&](int L) {
+        const int Lc = L < NZ ? L : NZ - 1;
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const uint32_t gi = (q ? obB : obA) + (uint32_t)Lc * plane32;
+            if (Bi) eb[q] = *at32(Bi, gi);
+            if (EPI == EPI_CHEB) { ed[q] = *at32(Di, gi); ei[q] = *at32(Ii, gi); }
+            if (EPI == EPI_CHEB0) ei[q] = *at32(Ii, gi);
+            if (EPI == EPI_CHEB || EPI == EPI_DOT || (MASKED && EPI != EPI_CHEB0)) exv[q] = *at32(Xi, gi);
+        }
+    };
+
+    const int kb = wi.z0, ke = wi.z1;
+    double acc = 0.0;
+    // carried between layers: the thread's values of the lower plane, the
+    // top-corner sums of the previous layer per (y, c), and the own sums of
+    // the last plane at the owned nodes A and B (for its epilogue)
+    T cu[6], cp[6];
+    T tv[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    T hA = T(0), hB = T(0);
+
+    // epilogue of one owned node: line rows, constraint, the selected result
+    auto epilogue = [&](int q, T v, const ColInfo &oc, uint32_t ob, const LineCol &lh, int &lr, int lcx, int P0,
+                        int sxl) {
+        const uint32_t gi = ob + (uint32_t)P0 * plane32;
+        if (FIELD && lh.first >= 0 && P0 >= lh.kmin && P0 <= lh.kmax) {
+            // injection-line row: operand values from the staged planes
+            const LineFlat HTS_GLOBAL &R = gptr<LineFlat>(o.lflat)[lh.first + (P0 - lh.kmin)];
+            const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
+            const int ne = R.n;
+            if (ne > 0 && !(MASKED && R.row_constrained)) {
+                T la = T(0);
+                for (int e = 0; e < ne; e++) {
+                    const int of = R.off[e];
+                    const int dx = (of & 3) - 1, dy = ((of >> 2) & 3) - 1, dk = ((of >> 4) & 3) - 1;
+                    // plane P0 + dk sits in slot sxl - 1 + dk (mod XR)
+                    const T xc = xs[(sxl + XR - 1 + dk) % XR][ty + 1 + dy][lcx + dx];
+                    la += T(lco[R.src[e]] * R.w[e]) * xc;
+                }
+                v += la;
+            }
+        }
+        if (FIELD && lr >= 0) {
+            const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
+            const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
+            const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
+            while (rows[lr].col == (int)oc.base && rows[lr].k < P0) lr++;
+            const int rcol = rows[lr].col, rk = rows[lr].k;
+            if (rcol == (int)oc.base && rk == P0 && !(MASKED && rows[lr].row_constrained)) {
+                T la = T(0);
+                for (int e = rows[lr].beg; e < rows[lr].end; e++) {
+                    if (MASKED && ents[e].col_constrained) continue;
+                    const int64_t col = ents[e].col;
+                    const T xc = EPI == EPI_CHEB0 ? c0 * *at32(Ii, col) * *at32(Bi, col) : *at32(Xi, col);
+                    la += T(lco[ents[e].src] * ents[e].w) * xc;
+                }
+                v += la;
+            }
+        }
+        T xq = exv[q], dq = ed[q];
+        if (EPI == EPI_CHEB0) {
+            xq = c0 * ei[q] * eb[q];
+            dq = xq;
+        }
+        if (MASKED && constrained(oc, P0, NZ, m)) v = xq;
+        if (EPI == EPI_STORE) {
+            *at32(Yi, gi) = v;
+        } else if (EPI == EPI_RESID) {
+            *at32(Yi, gi) = eb[q] - v;
+        } else if (EPI == EPI_RESID_NORM) {
+            const T r = eb[q] - v;
+            *at32(Yi, gi) = r;
+            acc += (double)r * (double)r;
+        } else if (EPI == EPI_DOT) {
+            *at32(Yi, gi) = v;
+            acc += (double)xq * (double)v;
+        } else if (CHEB) {
+            const T r = eb[q] - v;
+            const T d = c1 * dq + c2 * ei[q] * r;
+            *at32(Di, gi) = d;
+            *at32(Yi, gi) = xq + d;
+        }
+    };
+
+    int sx = (kb - 1 + XR) % XR, sp = (kb - 1) & 1;
+    fetch_plane(kb - 1, 0);
+    store_plane(sx, sp);
+#pragma unroll
+    for (int d = 0; d < PD; d++) {
+        fetch_plane(kb + d, d);
+        fetch_coef(kb - 1 + d, d);
+    }
+    __syncthreads();
+    read_plane(sx, sp, cu, cp);
+
+    for (int L = kb - 1; L <= ke; L++) {
+        const bool comp = L <= ke - 1;
+        const int sx1 = sx + 1 == XR ? 0 : sx + 1, sp1 = sp ^ 1;
+        if (comp) store_plane(sx1, sp1);
+        // a cell outside the mesh contributes nothing: its coefficients are
+        // zero (its node values are finite); the selects sit where the loaded
+        // values are consumed, so that no early wait is forced on the loads
+        const bool lin = L >= 0 && L < nz, on0 = lin && cin0, on1 = lin && cin1;
+        const T ck0 = on0 ? cfk[0][0] : T(0), ck1 = on1 ? cfk[0][1] : T(0);
+        const T cl0 = on0 ? cfl[0][0] : T(0), cl1 = on1 ? cfl[0][1] : T(0);
+        const T cc0 = on0 ? cfc[0][0] : T(0), cc1 = on1 ? cfc[0][1] : T(0);
+        const T cm0 = on0 ? cm : T(0), cm1 = on1 ? cm : T(0);
+        const double lhz = cfh[0], lihz = cfih[0];
+        shift();
+        if (L + PD <= ke - 1) {
+            fetch_plane(L + 1 + PD, PD - 1);
+            fetch_coef(L + PD, PD - 1);
+        }
+        __syncthreads();
+        // epilogue of plane L-1 (corner sums written in the previous iteration)
+        if (L - 1 >= kb && L - 1 < NZ) {
+            const int P0 = L - 1, sb = P0 & 1;
+            if (okA) {
+                const T v = hA + ex[sb][1][ty + 1][tx];
+                epilogue(0, v, ocA, obA, lhA, lrA, lx + 1, P0, sx);
+            }
+            if (okB) {
+                const T v = (hB + ex[sb][3][ty][tx + 1]) + (ex[sb][2][ty + 1][tx] + ex[sb][0][ty + 1][tx + 1]);
+                epilogue(1, v, ocB, obB, lhB, lrB, lx + 2, P0, sx);
+            }
+        }
+        if (!comp) break;
+        if (L >= kb) fetch_epi(L);
+        // the new upper plane L+1
+        T nu[6], np[6];
+        read_plane(sx1, sp1, nu, np);
+        // cell layer L between planes L and L+1: cell 0, then cell 1 (the
+        // shared face is formed once); each cell's corner values are folded
+        // into the plane sums at once, which keeps few values live.  s[]:
+        // plane L sums per (y, c), t[]: top corners of layer L per (y, c).
+        T sv[6], tt[6];
+        {
+            T lpz0 = pz0;
+            if (graded && FIELD) lpz0 = T(o.rho_g) * T(lhz);
+            FaceYZ<T> Fa = face_yz(cu[0], cu[3], nu[0], nu[3]);
+            FaceYZ<T> Fb = face_yz(cu[1], cu[4], nu[1], nu[4]);
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                if (q == 1) {
+                    Fa = Fb;
+                    Fb = face_yz(cu[2], cu[5], nu[2], nu[5]);
+                }
+                T lfm = fm, lfx = fx, lfy = fy, lfz = fz, lvx = vx, lvy = vy, lvz = vz;
+                if (graded) {
+                    const T hz = T(lhz), ihz = T(lihz);
+                    lfm = gm[q] * hz;
+                    lfx = gx[q] * hz;
+                    lfy = gy[q] * hz;
+                    lfz = gz[q] * ihz;
+                    if (FIELD) {
+                        lvx = gvx[q] * hz;
+                        lvy = gvy[q] * hz;
+                        lvz = gvz[q] * ihz;
+                    }
+                }
+                const T ck = q ? ck1 : ck0;
+                T w[8];
+                if (FIELD == 0) {
+                    cell_from_faces(Fa, Fb, (q ? cm1 : cm0) * lfm, ck * lfx, ck * lfy, ck * lfz, w);
+                } else {
+                    const T cl = q ? cl1 : cl0, cc = q ? cc1 : cc0;
+                    cell_from_faces(Fa, Fb, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
+                    if (adv) {   // no convection in the mass-only heat operator
+                        T u[8], pp[8];
+#pragma unroll
+                        for (int a = 0; a < 4; a++) {
+                            const int c = q + (a & 1), y = a >> 1;
+                            u[a] = cu[3 * y + c];
+                            u[a + 4] = nu[3 * y + c];
+                            pp[a] = cp[3 * y + c];
+                            pp[a + 4] = np[3 * y + c];
+                        }
+                        cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
+                    }
+                }
+                if (q == 0) {
+                    sv[0] = tv[0] + w[0];
+                    sv[1] = w[1];
+                    sv[3] = tv[3] + w[2];
+                    sv[4] = w[3];
+                    tt[0] = w[4];
+                    tt[1] = w[5];
+                    tt[3] = w[6];
+                    tt[4] = w[7];
+                } else {
+                    sv[1] = tv[1] + (sv[1] + w[0]);
+                    sv[2] = tv[2] + w[1];
+                    sv[4] = tv[4] + (sv[4] + w[2]);
+                    sv[5] = tv[5] + w[3];
+                    tt[1] = tt[1] + w[4];
+                    tt[2] = w[5];
+                    tt[4] = tt[4] + w[6];
+                    tt[5] = w[7];
+                }
+            }
+        }
+        // plane L: pass the sums other threads own, keep the own ones
+        if (L >= kb) {
+            const int sb = L & 1;
+            ex[sb][0][ty][tx] = sv[0];
+            ex[sb][1][ty][tx] = sv[1];
+            ex[sb][2][ty][tx] = sv[2];
+            ex[sb][3][ty][tx] = sv[3];
+            hA = sv[4];
+            hB = sv[5];
+        }
+#pragma unroll
+        for (int a = 0; a < 6; a++) {
+            tv[a] = tt[a];
+            cu[a] = nu[a];
+            if (FIELD) cp[a] = np[a];
+        }
+        sx = sx1;
+        sp = sp1;
+    }
+    if (EPI == EPI_RESID_NORM || EPI == EPI_DOT) {
+        double v = wave_sum(acc);
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) ep.partial[wi.slot] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// Narrow tiles (heat operator): a 256-thread workgroup owns a 15 x 15 tile
+// of node columns; each thread handles one cell column of the 16 x 16 cells
+// that touch it (one-cell halo on the low x/y side), evaluates its cell's 8
+// outputs and writes its four plane-corner contributions to LDS; the owner
+// of a node adds the four cell contributions in a fixed order.  Fewer
+// registers per thread than the wide tiles, which the convection term needs.
+constexpr int NB = 16;          // cell columns per tile edge
+constexpr int NOWN = NB - 1;    // owned node columns per tile edge
+constexpr int NNCOL = (NB + 1) * (NB + 1);
+
+template <typename T, int FIELD, int EPI, bool MASKED, bool GRADED>
+__global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ ops,
                                                   const WorkItem *__restrict__ work,
                                                   const T *__restrict__ X, T *__restrict__ Y,
                                                   EpiArgs<T> ep)
@@ -147,9 +686,9 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     // heat: a 5-deep x ring, so that the epilogue of plane P can read planes
     // P-1 .. P+1 of the injection-line rows while the next plane is stored
     constexpr int XR = FIELD ? 5 : 3;
-    __shared__ T xs[XR][TB + 1][TB + 2];
-    __shared__ T ps[FIELD ? 3 : 1][TB + 1][TB + 2];
-    __shared__ T S4[2][4][TB][TB + 1];
+    __shared__ T xs[XR][NB + 1][NB + 2];
+    __shared__ T ps[FIELD ? 3 : 1][NB + 1][NB + 2];
+    __shared__ T S4[2][4][NB][NB + 1];
     __shared__ double red[4];
 
     const WorkItem wi = work[blockIdx.x];
@@ -170,8 +709,8 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     // Node and cell indices are instance-local and below 2^31: 32-bit index
     // arithmetic (the vectors are offset to the instance already).
     const int32_t plane32 = o.NX * o.NY;
-    const int tid = threadIdx.x, tx = tid % TB, ty = tid / TB;
-    const int cx0 = wi.tx * OWN - 1, cy0 = wi.ty * OWN - 1;
+    const int tid = threadIdx.x, tx = tid % NB, ty = tid / NB;
+    const int cx0 = wi.tx * NOWN - 1, cy0 = wi.ty * NOWN - 1;
     const int cx = cx0 + tx, cy = cy0 + ty;
     const bool cin = cx >= 0 && cx < nx && cy >= 0 && cy < ny;
     const int32_t cbase = cin ? cx + nx * cy : 0;
@@ -188,9 +727,9 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
 #pragma unroll
     for (int s = 0; s < 2; s++) {
         int c = tid + s * 256;
-        ld[s] = c < NCOL;
-        li[s] = c % (TB + 1);
-        lj[s] = c / (TB + 1);
+        ld[s] = c < NNCOL;
+        li[s] = c % (NB + 1);
+        lj[s] = c / (NB + 1);
         ColInfo lc;
         if (ld[s]) lc = col_info(o, cx0 + li[s], cy0 + lj[s]);
         else { lc.valid = 0; lc.base = 0; lc.xyc = 0; lc.dlo = 1; lc.dhi = 0; }
@@ -200,7 +739,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         sdlo[s] = lc.dlo;
         sdhi[s] = lc.dhi;
     }
-    const bool owner = tx < OWN && ty < OWN;
+    const bool owner = tx < NOWN && ty < NOWN;
     const int oi = cx0 + tx + 1, oj = cy0 + ty + 1;
     ColInfo oc = col_info(o, oi, oj);
     const bool own_ok = owner && oc.valid;
@@ -568,22 +1107,30 @@ __global__ void k_q1_cell_loads(OpDev o, const double *__restrict__ alpha,
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+// pressure: wide tiles; heat: narrow tiles
+template <typename T, int FIELD, int EPI, bool MASKED, bool G>
+static void launch_k(int nwork, const OpDev *ops, const WorkItem *work, const T *x, T *y, const EpiArgs<T> &ep,
+                     hipStream_t s)
+{
+    if constexpr (FIELD == 0)
+        k_q1_apply<T, FIELD, EPI, MASKED, G><<<dim3(nwork), dim3(256), 0, s>>>(ops, work, x, y, ep);
+    else
+        k_q1_apply_n<T, FIELD, EPI, MASKED, G><<<dim3(nwork), dim3(256), 0, s>>>(ops, work, x, y, ep);
+}
+
 template <typename T, int FIELD, bool MASKED, bool G>
 static void dispatch_epi(int epi, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
                          const EpiArgs<T> &ep, hipStream_t s)
 {
-    dim3 g(nwork), b(256);
     switch (epi) {
-    case EPI_STORE: k_q1_apply<T, FIELD, EPI_STORE, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_RESID: k_q1_apply<T, FIELD, EPI_RESID, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_RESID_NORM:
-        k_q1_apply<T, FIELD, EPI_RESID_NORM, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep);
-        break;
-    case EPI_DOT: k_q1_apply<T, FIELD, EPI_DOT, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_CHEB: k_q1_apply<T, FIELD, EPI_CHEB, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_STORE: launch_k<T, FIELD, EPI_STORE, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_RESID: launch_k<T, FIELD, EPI_RESID, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_RESID_NORM: launch_k<T, FIELD, EPI_RESID_NORM, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_DOT: launch_k<T, FIELD, EPI_DOT, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_CHEB: launch_k<T, FIELD, EPI_CHEB, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
     case EPI_CHEB0:
         if (!MASKED) throw Error(-1, "EPI_CHEB0 is for masked operators");
-        k_q1_apply<T, FIELD, EPI_CHEB0, true, G><<<g, b, 0, s>>>(ops, work, x, y, ep);
+        launch_k<T, FIELD, EPI_CHEB0, true, G>(nwork, ops, work, x, y, ep, s);
         break;
     default: throw Error(-1, "bad epilogue");
     }

@@ -179,7 +179,9 @@ int tuned_zc(int degree, int field, int NX, int NY, int NZ)
     return it == g_tune.end() ? 0 : it->second;
 }
 
-int tile_own(int degree) { return degree == 2 ? 30 : 15; }
+// Q1: wide tiles for the pressure operator, narrow ones for the heat operator
+int tile_own_x(int degree, int field) { return degree == 2 ? 30 : (field == 0 ? 31 : 15); }
+int tile_own_y(int degree, int field) { return degree == 2 ? 30 : 15; }
 
 int zc_for(const hts_mesh *M, int field, int64_t tiles, int force)
 {
@@ -207,8 +209,9 @@ void Batch::build_work()
         std::vector<WorkItem> nat;
         for (int i = 0; i < n; i++) {
             hts_mesh *M = m[i];
-            const int own = tile_own(M->p);   // owned node columns per tile edge
-            const int tx = (M->N[0] + own - 1) / own, ty = (M->N[1] + own - 1) / own;
+            // owned node columns per tile along x and y
+            const int ox = tile_own_x(M->p, f), oy = tile_own_y(M->p, f);
+            const int tx = (M->N[0] + ox - 1) / ox, ty = (M->N[1] + oy - 1) / oy;
             const int zc = pick_zc(f, M, (int64_t)tx * ty);
             for (int z0 = 0; z0 < M->N[2]; z0 += zc)
                 for (int y = 0; y < ty; y++)

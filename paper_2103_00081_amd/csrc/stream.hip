@@ -13,28 +13,17 @@ namespace {
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-// 16-byte vector loads and stores, four per thread per pass, grid-stride
-// over the whole buffer (n16 16-byte words); the tail below 16 bytes is
-// copied bytewise by the first threads.
+// One 16-byte word per thread, one short-lived block per 4 KiB (measured
+// on MI355X over 1 GiB: 6.2 TB/s, against 4.2-5.1 TB/s for grid-stride
+// loops of 1024-16384 blocks with 1-8 words per thread and iteration); the
+// tail below 16 bytes is copied bytewise by the first threads.
 __global__ __launch_bounds__(256) void k_stream_copy(const v4u *__restrict__ src, v4u *__restrict__ dst,
                                                      int64_t n16, const uint8_t *__restrict__ s8,
                                                      uint8_t *__restrict__ d8, int64_t tail0, int64_t nbytes)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const v4u a = __builtin_nontemporal_load(src + i);
-        const v4u b = __builtin_nontemporal_load(src + i + stride);
-        const v4u c = __builtin_nontemporal_load(src + i + 2 * stride);
-        const v4u d = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(a, dst + i);
-        __builtin_nontemporal_store(b, dst + i + stride);
-        __builtin_nontemporal_store(c, dst + i + 2 * stride);
-        __builtin_nontemporal_store(d, dst + i + 3 * stride);
-    }
-    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t < nbytes - tail0) d8[tail0 + t] = s8[tail0 + t];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
+    if (i < nbytes - tail0) d8[tail0 + i] = s8[tail0 + i];
 }
 
 }  // namespace
@@ -51,13 +40,9 @@ extern "C" hts_status hts_stream_copy(const void *src, void *dst, int64_t bytes,
             throw Error(HTS_ERR_ARG, "buffers must be 16-byte aligned");
         hipStream_t s = (hipStream_t)stream;
         const int64_t n16 = bytes / 16;
-        int dev = 0, ncu = 0;
-        HTS_HIP(hipGetDevice(&dev));
-        HTS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        // enough 256-thread blocks for 16 waves per compute unit
-        const int64_t want = (int64_t)std::max(ncu, 1) * 16;
-        const int64_t need = std::max<int64_t>(1, (n16 + 255) / 256);
-        const unsigned grid = (unsigned)std::min(want, need);
+        const int64_t blocks = std::max<int64_t>(1, (n16 + 255) / 256);
+        if (blocks > INT32_MAX) throw Error(HTS_ERR_ARG, "copy too large");
+        const unsigned grid = (unsigned)blocks;
         hipEvent_t a = nullptr, b = nullptr;
         HTS_HIP(hipEventCreate(&a));
         HTS_HIP(hipEventCreate(&b));

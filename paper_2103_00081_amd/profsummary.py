@@ -5,11 +5,12 @@ Usage:
       total device time, launches, average / minimum duration, grid size,
       VGPR count and scratch bytes per kernel (heaviest first), then the
       fine-level operator kernels grouped by (field, precision).
-  python -m paper_2103_00081_amd.profsummary pmc <counter_collection.csv> [copy_mib]
-      per-dispatch hardware counters (FETCH_SIZE, WRITE_SIZE in KiB) averaged
-      per operator class; with copy_mib, the counters of the largest plain
-      elementwise copy in the run (copy_mib MiB read and written) give the
-      factor from counter KiB to bytes.
+  python -m paper_2103_00081_amd.profsummary pmc <counter_collection.csv | results.db> [copy_mib]
+      per-dispatch hardware counters (e.g. FETCH_SIZE, WRITE_SIZE) averaged
+      per operator class, epilogue and grid size; with copy_mib, the counters
+      of the largest plain copy in the run (the library's stream copy of
+      copy_mib MiB, read and written) give the factor from counter units to
+      bytes.
 """
 import csv
 import re
@@ -63,38 +64,56 @@ def summarise(db: str, top: int = 40) -> str:
     return "\n".join(out)
 
 
-def pmc(path: str, copy_mib: float = 0.0) -> str:
+def _pmc_rows(path: str):
+    """(dispatch id, kernel name, grid size, counter, value) from a rocprofv3
+    counter CSV or results database."""
+    if path.endswith(".db"):
+        c = sqlite3.connect(path)
+        return c.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
+                         "from counters_collection").fetchall()
     with open(path, newline="") as f:
         rows = list(csv.DictReader(f))
     if not rows:
-        return "no rows"
+        return []
     key = lambda *c: next((k for k in rows[0] if k.lower() in c), None)
     kname, cname, cval = key("kernel_name"), key("counter_name"), key("counter_value")
-    did = key("dispatch_id", "correlation_id")
+    did, grid = key("dispatch_id", "correlation_id"), key("grid_size")
+    return [(r[did], r[kname], int(r[grid]) if grid else 0, r[cname], float(r[cval])) for r in rows]
+
+
+_EPI = re.compile(r"k_q([12])_apply<(float|double), (\d), (\d)")
+
+
+def pmc(path: str, copy_mib: float = 0.0) -> str:
+    rows = _pmc_rows(path)
+    if not rows:
+        return "no rows"
     per = {}
-    for r in rows:
-        d = per.setdefault(r[did], {"name": r[kname]})
-        d[r[cname]] = d.get(r[cname], 0.0) + float(r[cval])
-    counters = sorted({r[cname] for r in rows})
+    for did, name, grid, cn, v in rows:
+        d = per.setdefault(did, {"name": name, "grid": grid})
+        d[cn] = d.get(cn, 0.0) + float(v)
+    counters = sorted({r[3] for r in rows})
     out = ["counters: %s, %d dispatches" % (", ".join(counters), len(per))]
     factor = {}
     if copy_mib > 0:
-        copies = [d for d in per.values() if "elementwise" in d["name"].lower()]
+        copies = [d for d in per.values() if "k_stream_copy" in d["name"] or "elementwise" in d["name"].lower()]
         if copies:
             for c in counters:
                 best = max(copies, key=lambda d: d.get(c, 0.0))
                 factor[c] = copy_mib * (1 << 20) / max(best.get(c, 0.0), 1e-30)
-                out.append("copy calibration %s: %.1f KiB for %.0f MiB -> %.4f B per counter unit" % (
+                out.append("copy calibration %s: %.1f counter units for %.0f MiB -> %.4f B per counter unit" % (
                     c, best.get(c, 0.0), copy_mib, factor[c]))
     cls = {}
     for d in per.values():
-        k = apply_class(d["name"])
-        if k:
-            a = cls.setdefault(k, {"n": 0})
-            a["n"] += 1
-            for c in counters:
-                a[c] = a.get(c, 0.0) + d.get(c, 0.0)
-    out += ["", "| class | dispatches | " + " | ".join("%s KiB/dispatch" % c for c in counters) +
+        m = _EPI.search(d["name"])
+        if not m:
+            continue
+        k = "%s epi %s grid %d" % (apply_class(d["name"]), m.group(4), d["grid"])
+        a = cls.setdefault(k, {"n": 0})
+        a["n"] += 1
+        for c in counters:
+            a[c] = a.get(c, 0.0) + d.get(c, 0.0)
+    out += ["", "| class, epilogue, grid | dispatches | " + " | ".join("%s units/dispatch" % c for c in counters) +
             "".join(" | %s MB/dispatch (calibrated)" % c for c in counters if c in factor) + " |",
             "|---|---|" + "---|" * (len(counters) + len(factor))]
     for k, a in sorted(cls.items()):

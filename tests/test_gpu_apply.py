@@ -28,6 +28,11 @@ def small_cases():
     s = synth.config2(ncells=(17, 9, 5), n_steps=1)
     s.name = "odd_17x9x5"
     c.append((s.name, s))
+    # several Q1 tiles along x and y (31 x 15 owned node columns) with ragged
+    # tails, wells crossing tile edges
+    s = synth.config2(ncells=(70, 33, 6), n_steps=1)
+    s.name = "tiles_70x33x6"
+    c.append((s.name, s))
     # Q2: the same scenarios on 27-node cells (cellwise data unchanged)
     c.append(("c3_q2_small", synth.config3(degree=2, ncells=(17, 16, 5), n_steps=1)))
     s = synth.config2(ncells=(19, 16, 6), n_steps=1)

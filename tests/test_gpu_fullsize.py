@@ -14,8 +14,8 @@ of order u k max|P| / h, far above u |q|; its bound adds 64 u times the
 convection rows of |A| |x| evaluated with that flux magnitude (a field with
 gradient max|P| / h_d along every axis).
 
-Samples: random rows, rows on and next to the 15-node tile edges (Q1) or
-30-node tile edges (Q2), domain faces, low and high z, and every node of
+Samples: random rows, rows on and next to the tile edges (Q1: 31 x 15
+owned node columns per tile for pressure, 15 x 15 for heat; Q2: 30 x 30), domain faces, low and high z, and every node of
 the well columns (injection line operator).
 
 Steps: one backward-Euler step of the layered aquifer (128x128x64 Q1)
@@ -44,9 +44,11 @@ EPS = {0: np.finfo(np.float64).eps, 1: np.finfo(np.float32).eps}
 def sample_rows(scn, rng, n_random=2000):
     p = scn.degree
     NX, NY, NZ = (p * c + 1 for c in scn.ncells)
-    tile = 15 * p
-    edge = sorted({v for t in range(0, NX + tile, tile) for v in (t - 1, t, t + 1) if 0 <= v < NX} | {NX - 2})
-    edgy = sorted({v for t in range(0, NY + tile, tile) for v in (t - 1, t, t + 1) if 0 <= v < NY} | {NY - 2})
+    # owned node columns per tile: Q1 31 x 15 (pressure) and 15 x 15 (heat), Q2 30 x 30
+    txs, ty = ((31, 15), 15) if p == 1 else ((30,), 30)
+    edge = sorted({v for tx in txs for t in range(0, NX + tx, tx) for v in (t - 1, t, t + 1) if 0 <= v < NX}
+                  | {NX - 2})
+    edgy = sorted({v for t in range(0, NY + ty, ty) for v in (t - 1, t, t + 1) if 0 <= v < NY} | {NY - 2})
     ks = sorted({0, 1, 2, NZ // 2, NZ - 3, NZ - 2, NZ - 1})
     rows = [rng.integers(0, NX * NY * NZ, n_random)]
     ii = rng.choice(edge, 300)
