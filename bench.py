@@ -41,15 +41,22 @@ PEAK_BF16_TFLOPS = 2500.0      # dense MFMA
 # heat) at one cell per node, at the operator's precision.
 ALG_BYTES = {(1, 0, 0): 24.0, (1, 0, 1): 12.0, (1, 1, 0): 40.0, (1, 1, 1): 20.0,
              (2, 0, 0): 17.0, (2, 0, 1): 8.5, (2, 1, 0): 26.0, (2, 1, 1): 13.0}
+# Algorithmic flops per cell of one apply (sum-factorised Kronecker
+# application; the heat operator adds the Darcy flux and q . grad T at the
+# Gauss points), and the per-kernel bound they give against the ridge of the
+# vector units (FP64 and FP32 without packed instructions: 78.6 TFLOP/s,
+# 9.8 flop/B at 8 TB/s).
+ALG_FLOPS = {(1, 0): 140.0, (1, 1): 390.0, (2, 0): 1460.0, (2, 1): 3500.0}
+PEAK_VALU_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+
 CLASS_NAMES = {(0, 0): "pressure apply FP64", (0, 1): "pressure apply FP32",
                (1, 0): "heat apply FP64", (1, 1): "heat apply FP32"}
 COUNTER_SUMMARY = "q1_apply_pile_field_256x256x128_hbm_counters.md"
 
 
 def kernel_source_hash():
-    import hashlib
-    src = [os.path.join(ROOT, "paper_2103_00081_amd", "csrc", f) for f in ("op_q1.hip", "dev_util.h", "common.h")]
-    return hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
+    from paper_2103_00081_amd.profsummary import kernel_source_hash as h
+    return h(ROOT)
 
 
 def measured_traffic(label: str):
@@ -118,6 +125,10 @@ def parse():
     ap.add_argument("--nn-steps", type=int, default=2)
     ap.add_argument("--nn-pairs", type=int, default=6, help="pairs kept per inner solve")
     ap.add_argument("--nn-epochs", type=int, default=4)
+    ap.add_argument("--nn-test-draws", type=int, default=1, help="unseen draws the learned solve is timed on")
+    ap.add_argument("--nn-scale", default="small", choices=("small", "c5"),
+                    help="c5: 20 training draws x 100 steps x 5 pairs per solve (about 10k pairs), "
+                         "10 unseen test draws (several minutes)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the workload, run a plain elementwise copy of MIB MiB (FP32) three "
                          "times: the reference that scales hardware byte counters")
@@ -125,8 +136,12 @@ def parse():
 
 
 def learned_leg(a, hts, synth, nc, np, torch):
-    """c5: the learned preconditioner against plain multigrid on one unseen
-    permeability draw of the layered aquifer (same grid as the headline)."""
+    """c5: the learned preconditioner against plain multigrid on unseen
+    permeability draws of the layered aquifer (same grid as the headline).
+    Training draws are seeds 5000.., test draws 5100.. (never harvested)."""
+    if a.nn_scale == "c5":
+        a.nn_draws, a.nn_steps, a.nn_pairs, a.nn_test_draws = 21, 100, 5, 10
+        a.nn_epochs = max(a.nn_epochs, 2)
     t_setup = time.perf_counter()
     o64 = hts.default_opts(mode=hts.MODE_FP64, rtol=1e-8)
     draws = [hts.from_scenario(synth.config5(5000 + i, ncells=nc, n_steps=a.nn_steps), opts=o64)
@@ -134,35 +149,44 @@ def learned_leg(a, hts, synth, nc, np, torch):
     net = hts.Net(levels=4, channels=(16, 32, 48, 64), seed=7)
     net.harvest(draws, a.nn_steps, synth.DAY, a.nn_pairs)
     del draws
+    torch.cuda.synchronize()
     t_train = time.perf_counter()
+    note("learned: harvested in %.1f s" % (t_train - t_setup))
     tr = net.train(epochs=a.nn_epochs, lr=2e-3, batch=4, val_draws=1)
     torch.cuda.synchronize()
     t_done = time.perf_counter()
+    note("learned: trained %d epochs on %d pairs in %.1f s" % (a.nn_epochs, tr["pairs"], t_done - t_train))
     n_steps = a.warmup + a.steps
-    out = {"workload": "unseen draw seed 5100, %dx%dx%d Q1" % nc, "train": tr,
-           "harvest_s": round(t_train - t_setup, 2), "train_s": round(t_done - t_train, 2)}
+    tests = [5100 + i for i in range(a.nn_test_draws)]
+    out = {"workload": "unseen draws seeds %d..%d, %dx%dx%d Q1" % ((tests[0], tests[-1]) + tuple(nc)),
+           "train": tr, "train_draws": a.nn_draws - 1, "val_draws": 1, "steps_per_draw": a.nn_steps,
+           "pairs_per_solve": a.nn_pairs, "harvest_s": round(t_train - t_setup, 2),
+           "train_s": round(t_done - t_train, 2)}
     for label, mode in (("learned", hts.MODE_LEARNED), ("multigrid_fp64", hts.MODE_FP64)):
         o = hts.default_opts(mode=mode, rtol=1e-8, use_graph=a.use_graph)
         if mode == hts.MODE_LEARNED:
             o.nn = net.h.value
-        scn = synth.config5(5100, ncells=nc, n_steps=n_steps)
-        m = hts.from_scenario(scn, opts=o)
-        for _ in range(a.warmup):
-            m.solve_step(scn.dt, o)
-        torch.cuda.synchronize()
-        sts = []
-        t0 = time.perf_counter()
-        for _ in range(a.steps):
-            sts.append(m.solve_step(scn.dt, o)[1])
-        torch.cuda.synchronize()
-        dt_s = time.perf_counter() - t0
-        out[label] = {"value": round(2 * m.nnode * a.steps / dt_s / 1e6, 3),
-                      "ms_per_step": round(1e3 * dt_s / a.steps, 3),
+        sts, secs, nodes = [], 0.0, 0
+        for seed in tests:
+            scn = synth.config5(seed, ncells=nc, n_steps=n_steps)
+            m = hts.from_scenario(scn, opts=o)
+            for _ in range(a.warmup):
+                m.solve_step(scn.dt, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                sts.append(m.solve_step(scn.dt, o)[1])
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            nodes = m.nnode
+            del m
+        k = a.steps * len(tests)
+        out[label] = {"value": round(2 * nodes * k / secs / 1e6, 3),
+                      "ms_per_step": round(1e3 * secs / k, 3),
                       "pressure_iters": float(np.mean([s["iters"][0] for s in sts])),
                       "pressure_ms": round(float(np.mean([s["time_ms"][0] for s in sts])), 3),
                       "fallbacks": int(sum(s["fallbacks"] for s in sts)),
                       "max_relres": float(max(max(s["relres"]) for s in sts))}
-        del m
     dims = tuple(c + 1 for c in nc)
     ms, fl = net.time_forward(dims, reps=5)
     out["forward"] = {"ms": round(ms, 3), "gflop": round(fl / 1e9, 2),
@@ -262,12 +286,15 @@ def time_operators(hts, synth, np, torch, degrees=(1, 2)):
                 us = 1e3 * k["ms"] / k["launches"]
                 alg = ALG_BYTES[(p, field, prec)] * n
                 gbs = alg / (us * 1e-6) / 1e9
+                fl = ALG_FLOPS[(p, field)] * m.ncell
+                tfs = fl / (us * 1e-6) / 1e12
                 name = "Q%d %s" % (p, CLASS_NAMES[(field, prec)])
                 out[name] = {"us": round(us, 2), "alg_bytes": alg, "GB/s": round(gbs, 1),
                              "frac": round(gbs / PEAK_HBM_GBS, 4),
-                             "lib_bytes": k["bytes"] / k["launches"],
-                             "flop_frac": round(k["flops"] / k["launches"] / (us * 1e-6) / 1e12 /
-                                                (PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_TFLOPS), 4)}
+                             "alg_flops": fl, "TFLOP/s": round(tfs, 2),
+                             "alu_frac": round(tfs / PEAK_VALU_TFLOPS, 4),
+                             "bound": "alu" if fl / alg > PEAK_VALU_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9) else "hbm",
+                             "lib_bytes": k["bytes"] / k["launches"]}
                 del xs, ys
         del m
         torch.cuda.synchronize()
@@ -414,22 +441,38 @@ def main():
     name = CLASS_NAMES[key]
     qname = "Q%d %s" % (deg, name)
     if operators and qname in operators:
-        # the same class on the 8.5 M-node mesh, streaming from HBM
+        # the same class on the 8.5 M-node mesh, streaming from HBM, against
+        # the bound its algorithmic intensity gives
         c3 = operators[qname]
-        roofline = {"bound": "hbm", "kernel": qname,
-                    "workload": "energy-pile field %s (8520321 nodes), 4 rotating (x, y) pairs"
-                                % ("256x256x128 Q1" if deg == 1 else "128x128x64 Q2"),
-                    "achieved": c3["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": c3["frac"],
-                    "traffic": measured_traffic(name) if deg == 1 else None, "alg_bytes": c3["alg_bytes"],
-                    "avg_us": c3["us"],
-                    "alu_frac": c3["flop_frac"], "stream_copy_GBs": operators["stream_copy_GBs"],
-                    "in_step": in_step}
+        wl = ("energy-pile field %s (8520321 nodes), 4 rotating (x, y) pairs"
+              % ("256x256x128 Q1" if deg == 1 else "128x128x64 Q2"))
+        if c3["bound"] == "alu":
+            roofline = {"bound": "alu", "kernel": qname, "workload": wl, "achieved": c3["TFLOP/s"],
+                        "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": c3["alu_frac"],
+                        "traffic": measured_traffic(name) if deg == 1 else None,
+                        "alg_flops": c3["alg_flops"], "avg_us": c3["us"], "hbm_frac": c3["frac"]}
+        else:
+            roofline = {"bound": "hbm", "kernel": qname, "workload": wl, "achieved": c3["GB/s"],
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": c3["frac"],
+                        "traffic": measured_traffic(name) if deg == 1 else None,
+                        "alg_bytes": c3["alg_bytes"], "avg_us": c3["us"], "alu_frac": c3["alu_frac"]}
+        roofline["stream_copy_GBs"] = operators["stream_copy_GBs"]
+        roofline["in_step"] = in_step
     else:
         gbs = alg_step / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": name, "workload": in_step["workload"],
                     "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None, "alg_bytes": alg_step,
                     "avg_us": in_step["avg_us"], "in_step": in_step}
+    # the HBM-bound operator of the same degree (the pressure apply, FP64)
+    roofline_hbm = None
+    hname = "Q%d %s" % (deg, CLASS_NAMES[(0, 0)])
+    if operators and hname in operators:
+        h = operators[hname]
+        roofline_hbm = {"bound": "hbm", "kernel": hname, "achieved": h["GB/s"], "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": h["frac"], "alg_bytes": h["alg_bytes"], "avg_us": h["us"],
+                        "traffic": measured_traffic(CLASS_NAMES[(0, 0)]) if deg == 1 else None,
+                        "frac_of_stream_copy": round(h["GB/s"] / operators["stream_copy_GBs"], 4)}
 
     cpu = None
     if not a.no_cpu and a.cpu_steps > 0:
@@ -488,6 +531,7 @@ def main():
                    "mg_coarse_max": a.mg_coarse_max,
                    "heat_precond": ["multigrid", "chebyshev-jacobi", "tensor-mass"][a.heat_precond]},
         "roofline": roofline,
+        "roofline_hbm": roofline_hbm,
         "step_bound": step_bound(R, R["nnode"], best),
         "learned": learned,
         "cpu_baseline": cpu,

@@ -30,11 +30,6 @@ constexpr int OWNX = TCX - 1, OWNY = TCY - 1; // owned node columns per tile
 constexpr int SXN = TCX + 1, SYN = TCY + 1;   // staged node columns per plane
 constexpr int SXP = SXN + 1;                  // LDS row pitch (even: 16-byte pair reads)
 constexpr int NSTAGE = SXN * SYN;             // 561 staged values per plane
-// node planes loaded ahead of the one being staged: two for the pressure
-// operator, one for the heat operator (whose registers go to the convection
-// term)
-template <int FIELD>
-constexpr int prefetch_planes() { return FIELD ? 1 : 2; }
 
 // The 1D factors are applied unscaled, [2 1; 1 2] for the mass matrix
 // (h/6 times it) and [1 -1; -1 1] for the stiffness matrix (1/h times it);
@@ -217,24 +212,19 @@ __device__ __forceinline__ void cell_from_faces(const FaceYZ<T> &F0, const FaceY
         }
 }
 
-template <typename T, int FIELD, int EPI, bool MASKED, bool GRADED>
-__global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
-                                                  const WorkItem *__restrict__ work,
-                                                  const T *__restrict__ X, T *__restrict__ Y,
-                                                  EpiArgs<T> ep)
+template <typename T, int EPI, bool MASKED, bool GRADED>
+__global__ __launch_bounds__(256) void k_q1_pressure(const OpDev *__restrict__ ops,
+                                                     const WorkItem *__restrict__ work,
+                                                     const T *__restrict__ X, T *__restrict__ Y,
+                                                     EpiArgs<T> ep)
 {
     // Software pipeline over node planes, one barrier per plane: x planes in
-    // an LDS ring (plane p in slot p % XR), pressure planes (heat) in a ring
-    // of 2, the four exchanged plane-corner sums of each thread in a ring of
-    // 2; the global loads of plane L+2, of the coefficients of layer L+1 and
-    // of the epilogue operands of plane L are issued one iteration before
-    // they are used.  Heat: a 5-deep x ring, so that the epilogue of plane P
-    // can read planes P-1 .. P+1 for the injection-line rows while a faster
-    // thread already stores plane P+3.
-    constexpr int XR = FIELD ? 5 : 2;
-    constexpr int PD = prefetch_planes<FIELD>();
-    __shared__ __align__(16) T xs[XR][SYN][SXP];
-    __shared__ __align__(16) T ps[FIELD ? 2 : 1][FIELD ? SYN : 1][FIELD ? SXP : 2];
+    // an LDS ring of 2 (plane p in slot p & 1; each thread keeps its own
+    // values of the lower plane in registers), the four exchanged
+    // plane-corner sums of each thread in a ring of 2; the global loads of
+    // plane L+2, of the coefficients of layer L+1 and of the epilogue
+    // operands of plane L are issued one iteration before they are used.
+    __shared__ __align__(16) T xs[2][SYN][SXP];
     __shared__ T ex[2][4][TCY][17];
     __shared__ double red[4];
 
@@ -244,18 +234,15 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const int nx = o.nx, ny = o.ny, nz = o.nz, NZ = o.NZ, m = o.dmask;
     const T *__restrict__ Xi = X + o.off;
     T *__restrict__ Yi = Y + o.off;
-    const T HTS_GLOBAL *__restrict__ Pi = gptr<T>(FIELD ? o.P : nullptr);
     const T HTS_GLOBAL *__restrict__ kk = gptr<T>(o.k);
-    const T HTS_GLOBAL *__restrict__ lamc = gptr<T>(o.lam);
-    const T HTS_GLOBAL *__restrict__ cTc = gptr<T>(o.cT);
     constexpr bool CHEB = EPI == EPI_CHEB || EPI == EPI_CHEB0;
     const T *__restrict__ Bi = (EPI == EPI_RESID || EPI == EPI_RESID_NORM || CHEB) ? ep.b + o.off : nullptr;
     T *__restrict__ Di = CHEB ? ep.d + o.off : nullptr;
     const T *__restrict__ Ii = CHEB ? ep.invd + o.off : nullptr;
 
-    // Node and cell indices are instance-local and below 2^31: 32-bit index
-    // arithmetic (the vectors are offset to the instance already).
-    // (unsigned offsets: the loads take a uniform base and a 32-bit offset)
+    // Node and cell indices are instance-local, non-negative and below 2^31:
+    // unsigned 32-bit offsets (the loads take a uniform base and a 32-bit
+    // offset; the vectors are offset to the instance already).
     const uint32_t plane32 = (uint32_t)(o.NX * o.NY);
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int lx = 2 * tx;                        // local x of the thread's first cell
@@ -269,10 +256,10 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
 
     // staged node columns of this thread (three slots, the third only for
     // the first NSTAGE - 512 threads): base index (0 outside the mesh, so the
-    // loads stay in range; the value is then discarded), in the mesh, kept
-    // (not on a constraining x/y face), constrained z-range
+    // loads stay in range; the value is then discarded), kept (in the mesh,
+    // not on a constraining x/y face), constrained z-range
     int lj[3], li[3];
-    bool sval[3], scol[3];
+    bool scol[3];
     uint32_t sbase[3];
     int sdlo[3], sdhi[3];
     const bool ld2 = tid < NSTAGE - 512;
@@ -284,7 +271,6 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         ColInfo lc;
         if (q < 2 || ld2) lc = col_info(o, cx0 + li[q], cy0 + lj[q]);
         else { lc.valid = 0; lc.base = 0; lc.xyc = 0; lc.dlo = 1; lc.dhi = 0; li[q] = 0; lj[q] = 0; }
-        sval[q] = lc.valid;
         scol[q] = lc.valid && !(MASKED && lc.xyc);
         sbase[q] = lc.valid ? (uint32_t)lc.base : 0u;
         sdlo[q] = lc.dlo;
@@ -296,30 +282,15 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     const ColInfo ocA = col_info(o, cx0 + lx + 1, cy0 + ty + 1);
     const ColInfo ocB = col_info(o, cx0 + lx + 2, cy0 + ty + 1);
     const bool okA = ownrow && ocA.valid, okB = ownrow && tx < 15 && ocB.valid;
-    int lrA = -1, lrB = -1;
-    LineCol lhA{-1, 0, -1, 0}, lhB{-1, 0, -1, 0};
-    if (FIELD && o.lfcol) {
-        const LineCol HTS_GLOBAL *hp = gptr<LineCol>(o.lfcol);
-        if (okA) { lhA.first = hp[ocA.base].first; lhA.kmin = hp[ocA.base].kmin; lhA.kmax = hp[ocA.base].kmax; }
-        if (okB) { lhB.first = hp[ocB.base].first; lhB.kmin = hp[ocB.base].kmin; lhB.kmax = hp[ocB.base].kmax; }
-    }
-    if (FIELD && !o.lfcol && o.lcol) {
-        if (okA) lrA = gptr<int32_t>(o.lcol)[ocA.base];
-        if (okB) lrB = gptr<int32_t>(o.lcol)[ocB.base];
-    }
 
     // per-cell coefficient factors of the unscaled 1D products (formed in
     // double on the host, rounded once here)
     const T fm = T(o.q1m), fx = T(o.q1x), fy = T(o.q1y), fz = T(o.q1z);
-    const T vx = T(o.q1vx), vy = T(o.q1vy), vz = T(o.q1vz);
-    const T pz0 = T(o.rho_g * o.hz);   // rho_g is 0 where the pressure is piezometric
     const T cm = T(o.cm);
-    const bool adv = o.cadv != 0.0;
     // graded meshes: every factor is a per-column part (from the cell's hx,
     // hy, formed once in double and rounded) times hz or 1 / hz of the layer
     const bool graded = GRADED && o.hzs != nullptr;
     T gm[2] = {T(0), T(0)}, gx[2] = {T(0), T(0)}, gy[2] = {T(0), T(0)}, gz[2] = {T(0), T(0)};
-    T gvx[2] = {T(0), T(0)}, gvy[2] = {T(0), T(0)}, gvz[2] = {T(0), T(0)};
     if (graded) {
         const int iy = cy < 0 ? 0 : (cy >= ny ? ny - 1 : cy);
         const double ghy = o.hys[iy];
@@ -331,9 +302,6 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
             gx[q] = T(o.cs * (ghy / ghx) / 36.0);             // x hz
             gy[q] = T(o.cs * (ghx / ghy) / 36.0);             // x hz
             gz[q] = T(o.cs * hxy / 36.0);                     // x 1/hz
-            gvx[q] = T(-o.cadv * 0.125 * ghy / ghx);          // x hz
-            gvy[q] = T(-o.cadv * 0.125 * ghx / ghy);          // x hz
-            gvz[q] = T(-o.cadv * 0.125 * hxy);                // x 1/hz
         }
     }
     T c0 = T(0), c1 = T(0), c2 = T(0);
@@ -345,15 +313,14 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     }
 
     // Plane / coefficient / epilogue loads are unconditional (clamped to a
-    // valid address) and the keep-or-zero decision is a select applied when
-    // the value is consumed, so no branch forces an early wait on a load.
-    // PD planes are in flight ahead of the one being stored (slot 0); the
-    // keep decisions are all-ones / zero bit masks held in vector registers
-    // (bool arrays would take a 64-bit scalar mask each)
+    // valid address) and the keep-or-zero decision is applied when the value
+    // is consumed, so that no branch or select forces an early wait on a
+    // load.  Keep decisions are all-ones / zero bit masks in vector
+    // registers (bool arrays would take a 64-bit scalar mask each).
     using UT = typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type;
-    T pfx[PD][3], pfp[PD][3];
-    UT pkeep[PD][3], pin[PD][3];
-    auto fetch_plane = [&](int k, int d) {
+    T pfx[3];
+    UT pkeep[3];
+    auto fetch_plane = [&](int k) {
         const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
         const uint32_t koff = (uint32_t)kc * plane32;
         // the part of the keep decision that is the same for every column
@@ -364,72 +331,35 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
             const uint32_t gi = sbase[q] + koff;
             // EPI_CHEB0 operand: x0 = c0 D^-1 b, in the order of the
             // separate first Chebyshev kernel
-            if (EPI == EPI_CHEB0) pfx[d][q] = c0 * *at32(Ii, gi) * *at32(Bi, gi);
-            else pfx[d][q] = *at32(Xi, gi);
-            if (FIELD) pfp[d][q] = *at32(Pi, gi);
+            if (EPI == EPI_CHEB0) pfx[q] = c0 * *at32(Ii, gi) * *at32(Bi, gi);
+            else pfx[q] = *at32(Xi, gi);
             bool keep = kkeep && scol[q];
             if (MASKED) keep = keep && !(k >= sdlo[q] && k <= sdhi[q]);
-            pkeep[d][q] = keep ? ~UT(0) : UT(0);
-            pin[d][q] = (kin && sval[q]) ? ~UT(0) : UT(0);
+            pkeep[q] = keep ? ~UT(0) : UT(0);
         }
     };
-    auto store_plane = [&](int bx, int bp) {
+    auto store_plane = [&](int bx) {
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             if (q == 2 && !ld2) continue;
-            xs[bx][lj[q]][li[q]] = __builtin_bit_cast(T, __builtin_bit_cast(UT, pfx[0][q]) & pkeep[0][q]);
-            if (FIELD)
-                ps[FIELD ? bp : 0][lj[q]][li[q]] = __builtin_bit_cast(T, __builtin_bit_cast(UT, pfp[0][q]) & pin[0][q]);
+            xs[bx][lj[q]][li[q]] = __builtin_bit_cast(T, __builtin_bit_cast(UT, pfx[q]) & pkeep[q]);
         }
     };
     // the thread's 3 x 2 node values of a staged plane: [y * 3 + c]
-    auto read_plane = [&](int bx, int bp, T *u, T *pp) {
+    auto read_plane = [&](int bx, T *u) {
 #pragma unroll
         for (int y = 0; y < 2; y++)
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                u[3 * y + c] = xs[bx][ty + y][lx + c];
-                if (FIELD) pp[3 * y + c] = ps[FIELD ? bp : 0][ty + y][lx + c];
-            }
+            for (int c = 0; c < 3; c++) u[3 * y + c] = xs[bx][ty + y][lx + c];
     };
-    // coefficients of PD layers in flight, slot 0 the layer computed next
-    T cfk[PD][2], cfl[PD][2], cfc[PD][2];
-    double cfh[PD], cfih[PD];     // graded: hz and 1/hz of the layer
-    auto fetch_coef = [&](int L, int d) {
+    T cfk[2] = {T(0), T(0)};
+    double cfh = 0.0, cfih = 0.0;     // graded: hz and 1/hz of the layer
+    auto fetch_coef = [&](int L) {
         const int Lc = L < 0 ? 0 : (L >= nz ? nz - 1 : L);
         const uint32_t lo = (uint32_t)Lc * cplane;
-        cfk[d][0] = *at32(kk, cbase0 + lo);
-        cfk[d][1] = *at32(kk, cbase1 + lo);
-        if (FIELD) {
-            cfl[d][0] = *at32(lamc, cbase0 + lo);
-            cfl[d][1] = *at32(lamc, cbase1 + lo);
-            cfc[d][0] = *at32(cTc, cbase0 + lo);
-            cfc[d][1] = *at32(cTc, cbase1 + lo);
-        }
-        cfh[d] = 0.0;
-        cfih[d] = 0.0;
-        if (graded) { cfh[d] = o.hzs[Lc]; cfih[d] = o.ihzs[Lc]; }
-    };
-    // advance the prefetch slots by one
-    auto shift = [&]() {
-#pragma unroll
-        for (int d = 0; d + 1 < PD; d++) {
-#pragma unroll
-            for (int q = 0; q < 3; q++) {
-                pfx[d][q] = pfx[d + 1][q];
-                pfp[d][q] = pfp[d + 1][q];
-                pkeep[d][q] = pkeep[d + 1][q];
-                pin[d][q] = pin[d + 1][q];
-            }
-#pragma unroll
-            for (int q = 0; q < 2; q++) {
-                cfk[d][q] = cfk[d + 1][q];
-                cfl[d][q] = cfl[d + 1][q];
-                cfc[d][q] = cfc[d + 1][q];
-            }
-            cfh[d] = cfh[d + 1];
-            cfih[d] = cfih[d + 1];
-        }
+        cfk[0] = *at32(kk, cbase0 + lo);
+        cfk[1] = *at32(kk, cbase1 + lo);
+        if (graded) { cfh = o.hzs[Lc]; cfih = o.ihzs[Lc]; }
     };
     // epilogue operands of the two owned nodes
     const uint32_t obA = okA ? (uint32_t)ocA.base : 0u, obB = okB ? (uint32_t)ocB.base : 0u;
@@ -451,48 +381,13 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
     // carried between layers: the thread's values of the lower plane, the
     // top-corner sums of the previous layer per (y, c), and the own sums of
     // the last plane at the owned nodes A and B (for its epilogue)
-    T cu[6], cp[6];
+    T cu[6];
     T tv[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     T hA = T(0), hB = T(0);
 
-    // epilogue of one owned node: line rows, constraint, the selected result
-    auto epilogue = [&](int q, T v, const ColInfo &oc, uint32_t ob, const LineCol &lh, int &lr, int lcx, int P0,
-                        int sxl) {
+    // epilogue of one owned node: constraint, the selected result
+    auto epilogue = [&](int q, T v, const ColInfo &oc, uint32_t ob, int P0) {
         const uint32_t gi = ob + (uint32_t)P0 * plane32;
-        if (FIELD && lh.first >= 0 && P0 >= lh.kmin && P0 <= lh.kmax) {
-            // injection-line row: operand values from the staged planes
-            const LineFlat HTS_GLOBAL &R = gptr<LineFlat>(o.lflat)[lh.first + (P0 - lh.kmin)];
-            const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
-            const int ne = R.n;
-            if (ne > 0 && !(MASKED && R.row_constrained)) {
-                T la = T(0);
-                for (int e = 0; e < ne; e++) {
-                    const int of = R.off[e];
-                    const int dx = (of & 3) - 1, dy = ((of >> 2) & 3) - 1, dk = ((of >> 4) & 3) - 1;
-                    // plane P0 + dk sits in slot sxl - 1 + dk (mod XR)
-                    const T xc = xs[(sxl + XR - 1 + dk) % XR][ty + 1 + dy][lcx + dx];
-                    la += T(lco[R.src[e]] * R.w[e]) * xc;
-                }
-                v += la;
-            }
-        }
-        if (FIELD && lr >= 0) {
-            const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
-            const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
-            const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
-            while (rows[lr].col == (int)oc.base && rows[lr].k < P0) lr++;
-            const int rcol = rows[lr].col, rk = rows[lr].k;
-            if (rcol == (int)oc.base && rk == P0 && !(MASKED && rows[lr].row_constrained)) {
-                T la = T(0);
-                for (int e = rows[lr].beg; e < rows[lr].end; e++) {
-                    if (MASKED && ents[e].col_constrained) continue;
-                    const int64_t col = ents[e].col;
-                    const T xc = EPI == EPI_CHEB0 ? c0 * *at32(Ii, col) * *at32(Bi, col) : *at32(Xi, col);
-                    la += T(lco[ents[e].src] * ents[e].w) * xc;
-                }
-                v += la;
-            }
-        }
         T xq = exv[q], dq = ed[q];
         if (EPI == EPI_CHEB0) {
             xq = c0 * ei[q] * eb[q];
@@ -518,61 +413,50 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         }
     };
 
-    int sx = (kb - 1 + XR) % XR, sp = (kb - 1) & 1;
-    fetch_plane(kb - 1, 0);
-    store_plane(sx, sp);
-#pragma unroll
-    for (int d = 0; d < PD; d++) {
-        fetch_plane(kb + d, d);
-        fetch_coef(kb - 1 + d, d);
-    }
+    int sx = (kb - 1) & 1;
+    fetch_plane(kb - 1);
+    store_plane(sx);
+    fetch_plane(kb);
+    fetch_coef(kb - 1);
     __syncthreads();
-    read_plane(sx, sp, cu, cp);
+    read_plane(sx, cu);
 
     for (int L = kb - 1; L <= ke; L++) {
         const bool comp = L <= ke - 1;
-        const int sx1 = sx + 1 == XR ? 0 : sx + 1, sp1 = sp ^ 1;
-        if (comp) store_plane(sx1, sp1);
+        const int sx1 = sx ^ 1;
+        if (comp) store_plane(sx1);
         // a cell outside the mesh contributes nothing: its coefficients are
         // zero (its node values are finite); the selects sit where the loaded
-        // values are consumed, so that no early wait is forced on the loads
+        // values are consumed
         const bool lin = L >= 0 && L < nz, on0 = lin && cin0, on1 = lin && cin1;
-        const T ck0 = on0 ? cfk[0][0] : T(0), ck1 = on1 ? cfk[0][1] : T(0);
-        const T cl0 = on0 ? cfl[0][0] : T(0), cl1 = on1 ? cfl[0][1] : T(0);
-        const T cc0 = on0 ? cfc[0][0] : T(0), cc1 = on1 ? cfc[0][1] : T(0);
+        const T ck0 = on0 ? cfk[0] : T(0), ck1 = on1 ? cfk[1] : T(0);
         const T cm0 = on0 ? cm : T(0), cm1 = on1 ? cm : T(0);
-        const double lhz = cfh[0], lihz = cfih[0];
-        shift();
-        if (L + PD <= ke - 1) {
-            fetch_plane(L + 1 + PD, PD - 1);
-            fetch_coef(L + PD, PD - 1);
+        const double lhz = cfh, lihz = cfih;
+        if (L + 1 <= ke - 1) {
+            fetch_plane(L + 2);
+            fetch_coef(L + 1);
         }
         __syncthreads();
         // epilogue of plane L-1 (corner sums written in the previous iteration)
         if (L - 1 >= kb && L - 1 < NZ) {
             const int P0 = L - 1, sb = P0 & 1;
-            if (okA) {
-                const T v = hA + ex[sb][1][ty + 1][tx];
-                epilogue(0, v, ocA, obA, lhA, lrA, lx + 1, P0, sx);
-            }
+            if (okA) epilogue(0, hA + ex[sb][1][ty + 1][tx], ocA, obA, P0);
             if (okB) {
                 const T v = (hB + ex[sb][3][ty][tx + 1]) + (ex[sb][2][ty + 1][tx] + ex[sb][0][ty + 1][tx + 1]);
-                epilogue(1, v, ocB, obB, lhB, lrB, lx + 2, P0, sx);
+                epilogue(1, v, ocB, obB, P0);
             }
         }
         if (!comp) break;
         if (L >= kb) fetch_epi(L);
         // the new upper plane L+1
-        T nu[6], np[6];
-        read_plane(sx1, sp1, nu, np);
+        T nu[6];
+        read_plane(sx1, nu);
         // cell layer L between planes L and L+1: cell 0, then cell 1 (the
         // shared face is formed once); each cell's corner values are folded
-        // into the plane sums at once, which keeps few values live.  s[]:
-        // plane L sums per (y, c), t[]: top corners of layer L per (y, c).
+        // into the plane sums at once, which keeps few values live.  sv[]:
+        // plane L sums per (y, c), tt[]: top corners of layer L per (y, c).
         T sv[6], tt[6];
         {
-            T lpz0 = pz0;
-            if (graded && FIELD) lpz0 = T(o.rho_g) * T(lhz);
             FaceYZ<T> Fa = face_yz(cu[0], cu[3], nu[0], nu[3]);
             FaceYZ<T> Fb = face_yz(cu[1], cu[4], nu[1], nu[4]);
 #pragma unroll
@@ -581,39 +465,17 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
                     Fa = Fb;
                     Fb = face_yz(cu[2], cu[5], nu[2], nu[5]);
                 }
-                T lfm = fm, lfx = fx, lfy = fy, lfz = fz, lvx = vx, lvy = vy, lvz = vz;
+                T lfm = fm, lfx = fx, lfy = fy, lfz = fz;
                 if (graded) {
                     const T hz = T(lhz), ihz = T(lihz);
                     lfm = gm[q] * hz;
                     lfx = gx[q] * hz;
                     lfy = gy[q] * hz;
                     lfz = gz[q] * ihz;
-                    if (FIELD) {
-                        lvx = gvx[q] * hz;
-                        lvy = gvy[q] * hz;
-                        lvz = gvz[q] * ihz;
-                    }
                 }
                 const T ck = q ? ck1 : ck0;
                 T w[8];
-                if (FIELD == 0) {
-                    cell_from_faces(Fa, Fb, (q ? cm1 : cm0) * lfm, ck * lfx, ck * lfy, ck * lfz, w);
-                } else {
-                    const T cl = q ? cl1 : cl0, cc = q ? cc1 : cc0;
-                    cell_from_faces(Fa, Fb, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
-                    if (adv) {   // no convection in the mass-only heat operator
-                        T u[8], pp[8];
-#pragma unroll
-                        for (int a = 0; a < 4; a++) {
-                            const int c = q + (a & 1), y = a >> 1;
-                            u[a] = cu[3 * y + c];
-                            u[a + 4] = nu[3 * y + c];
-                            pp[a] = cp[3 * y + c];
-                            pp[a + 4] = np[3 * y + c];
-                        }
-                        cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
-                    }
-                }
+                cell_from_faces(Fa, Fb, (q ? cm1 : cm0) * lfm, ck * lfx, ck * lfy, ck * lfz, w);
                 if (q == 0) {
                     sv[0] = tv[0] + w[0];
                     sv[1] = w[1];
@@ -649,10 +511,8 @@ __global__ __launch_bounds__(256) void k_q1_apply(const OpDev *__restrict__ ops,
         for (int a = 0; a < 6; a++) {
             tv[a] = tt[a];
             cu[a] = nu[a];
-            if (FIELD) cp[a] = np[a];
         }
         sx = sx1;
-        sp = sp1;
     }
     if (EPI == EPI_RESID_NORM || EPI == EPI_DOT) {
         double v = wave_sum(acc);
@@ -672,8 +532,8 @@ constexpr int NB = 16;          // cell columns per tile edge
 constexpr int NOWN = NB - 1;    // owned node columns per tile edge
 constexpr int NNCOL = (NB + 1) * (NB + 1);
 
-template <typename T, int FIELD, int EPI, bool MASKED, bool GRADED>
-__global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ ops,
+template <typename T, int EPI, bool MASKED, bool GRADED>
+__global__ __launch_bounds__(256) void k_q1_heat(const OpDev *__restrict__ ops,
                                                   const WorkItem *__restrict__ work,
                                                   const T *__restrict__ X, T *__restrict__ Y,
                                                   EpiArgs<T> ep)
@@ -685,9 +545,9 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
     //   operands of plane L are issued one iteration before they are used.
     // heat: a 5-deep x ring, so that the epilogue of plane P can read planes
     // P-1 .. P+1 of the injection-line rows while the next plane is stored
-    constexpr int XR = FIELD ? 5 : 3;
+    constexpr int XR = 5;
     __shared__ T xs[XR][NB + 1][NB + 2];
-    __shared__ T ps[FIELD ? 3 : 1][NB + 1][NB + 2];
+    __shared__ T ps[3][NB + 1][NB + 2];
     __shared__ T S4[2][4][NB][NB + 1];
     __shared__ double red[4];
 
@@ -697,7 +557,7 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
     const int nx = o.nx, ny = o.ny, nz = o.nz, NZ = o.NZ, m = o.dmask;
     const T *__restrict__ Xi = X + o.off;
     T *__restrict__ Yi = Y + o.off;
-    const T HTS_GLOBAL *__restrict__ Pi = gptr<T>(FIELD ? o.P : nullptr);
+    const T HTS_GLOBAL *__restrict__ Pi = gptr<T>(o.P);
     const T HTS_GLOBAL *__restrict__ kk = gptr<T>(o.k);
     const T HTS_GLOBAL *__restrict__ lamc = gptr<T>(o.lam);
     const T HTS_GLOBAL *__restrict__ cTc = gptr<T>(o.cT);
@@ -745,24 +605,19 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
     const bool own_ok = owner && oc.valid;
     int lr = -1;
     LineCol lh{-1, 0, -1, 0};
-    if (FIELD && o.lfcol && own_ok) {
+    if (o.lfcol && own_ok) {
         const LineCol HTS_GLOBAL *hp = gptr<LineCol>(o.lfcol) + oc.base;
         lh.first = hp->first;
         lh.kmin = hp->kmin;
         lh.kmax = hp->kmax;
     }
-    if (FIELD && !o.lfcol && o.lcol && own_ok) lr = gptr<int32_t>(o.lcol)[oc.base];
+    if (!o.lfcol && o.lcol && own_ok) lr = gptr<int32_t>(o.lcol)[oc.base];
 
-    // per-cell coefficient factors of the unscaled 1D products (in double,
-    // then rounded once)
-    const double V = o.hx * o.hy * o.hz;
-    const T fm = T(V / 216.0);
-    const T fx = T(o.cs * (o.hy * o.hz / o.hx) / 36.0), fy = T(o.cs * (o.hx * o.hz / o.hy) / 36.0),
-            fz = T(o.cs * (o.hx * o.hy / o.hz) / 36.0);
-    const double cw8 = o.cadv * V * 0.125;
-    const T vx = T(-cw8 / (o.hx * o.hx)), vy = T(-cw8 / (o.hy * o.hy)), vz = T(-cw8 / (o.hz * o.hz));
-    const T pz0 = T(o.rho_g * o.hz);
-    const T cm = T(o.cm);
+    // per-cell coefficient factors of the unscaled 1D products (formed in
+    // double on the host, rounded once here)
+    const T fm = T(o.q1m), fx = T(o.q1x), fy = T(o.q1y), fz = T(o.q1z);
+    const T vx = T(o.q1vx), vy = T(o.q1vy), vz = T(o.q1vz);
+    const T pz0 = T(o.rho_g * o.hz);   // rho_g is 0 where the pressure is piezometric
     const bool adv = o.cadv != 0.0;
     // graded meshes: every factor is a per-column part (from this thread's
     // hx, hy, formed once in double and rounded) times hz or 1 / hz of the
@@ -806,7 +661,7 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
             // separate first Chebyshev kernel
             if (EPI == EPI_CHEB0) pfx[s] = c0 * Ii[gi] * Bi[gi];
             else pfx[s] = Xi[gi];
-            if (FIELD) pfp[s] = Pi[gi];
+            pfp[s] = Pi[gi];
             bool keep = kkeep && scol[s];
             if (MASKED) keep = keep && !(k >= sdlo[s] && k <= sdhi[s]);
             pkeep[s] = keep;
@@ -819,7 +674,7 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
         for (int s = 0; s < 2; s++) {
             if (!ld[s]) continue;
             xs[bx][lj[s]][li[s]] = pkeep[s] ? pfx[s] : T(0);
-            if (FIELD) ps[FIELD ? b : 0][lj[s]][li[s]] = pin[s] ? pfp[s] : T(0);
+            ps[b][lj[s]][li[s]] = pin[s] ? pfp[s] : T(0);
         }
     };
     T cfk = T(0), cfl = T(0), cfc = T(0);
@@ -828,7 +683,7 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
         const int Lc = L < 0 ? 0 : (L >= nz ? nz - 1 : L);
         const int32_t ci = cbase + Lc * cplane;
         cfk = kk[ci];
-        if (FIELD) { cfl = lamc[ci]; cfc = cTc[ci]; }
+        { cfl = lamc[ci]; cfc = cTc[ci]; }
         if (graded) { cfh = o.hzs[Lc]; cfih = o.ihzs[Lc]; }
     };
     // epilogue operands of one owned node
@@ -870,7 +725,7 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
             const int P0 = L - 1, sb = P0 & 1;
             T v = S4[sb][3][ty][tx] + S4[sb][2][ty][tx + 1] + S4[sb][1][ty + 1][tx] + S4[sb][0][ty + 1][tx + 1];
             const int32_t gi = obase + P0 * plane32;
-            if (FIELD && lh.first >= 0 && P0 >= lh.kmin && P0 <= lh.kmax) {
+            if (lh.first >= 0 && P0 >= lh.kmin && P0 <= lh.kmax) {
                 // injection-line row: operand values from the staged planes
                 const LineFlat HTS_GLOBAL &R = gptr<LineFlat>(o.lflat)[lh.first + (P0 - lh.kmin)];
                 const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
@@ -887,7 +742,7 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
                     v += la;
                 }
             }
-            if (FIELD && lr >= 0) {
+            if (lr >= 0) {
                 const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
                 const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
                 const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
@@ -948,26 +803,20 @@ __global__ __launch_bounds__(256) void k_q1_apply_n(const OpDev *__restrict__ op
                 lfx = gx * hz;
                 lfy = gy * hz;
                 lfz = gz * ihz;
-                if (FIELD) {
-                    lvx = gvx * hz;
-                    lvy = gvy * hz;
-                    lvz = gvz * ihz;
-                    lpz0 = T(o.rho_g) * hz;
-                }
+                lvx = gvx * hz;
+                lvy = gvy * hz;
+                lvz = gvz * ihz;
+                lpz0 = T(o.rho_g) * hz;
             }
-            if (FIELD == 0) {
-                cell_mass_stiff(u, cm * lfm, ck * lfx, ck * lfy, ck * lfz, w);
-            } else {
-                cell_mass_stiff(u, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
-                if (adv) {   // no convection in the mass-only heat operator
-                    T pp[8];
+            cell_mass_stiff(u, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
+            if (adv) {   // no convection in the mass-only heat operator
+                T pp[8];
 #pragma unroll
-                    for (int a = 0; a < 4; a++) {
-                        pp[a] = ps[FIELD ? b0 : 0][ty + (a >> 1)][tx + (a & 1)];
-                        pp[a + 4] = ps[FIELD ? b1 : 0][ty + (a >> 1)][tx + (a & 1)];
-                    }
-                    cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
+                for (int a = 0; a < 4; a++) {
+                    pp[a] = ps[b0][ty + (a >> 1)][tx + (a & 1)];
+                    pp[a + 4] = ps[b1][ty + (a >> 1)][tx + (a & 1)];
                 }
+                cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
             }
 #pragma unroll
             for (int a = 0; a < 4; a++) { bot[a] = w[a]; tp[a] = w[a + 4]; }
@@ -1113,9 +962,9 @@ static void launch_k(int nwork, const OpDev *ops, const WorkItem *work, const T 
                      hipStream_t s)
 {
     if constexpr (FIELD == 0)
-        k_q1_apply<T, FIELD, EPI, MASKED, G><<<dim3(nwork), dim3(256), 0, s>>>(ops, work, x, y, ep);
+        k_q1_pressure<T, EPI, MASKED, G><<<dim3(nwork), dim3(256), 0, s>>>(ops, work, x, y, ep);
     else
-        k_q1_apply_n<T, FIELD, EPI, MASKED, G><<<dim3(nwork), dim3(256), 0, s>>>(ops, work, x, y, ep);
+        k_q1_heat<T, EPI, MASKED, G><<<dim3(nwork), dim3(256), 0, s>>>(ops, work, x, y, ep);
 }
 
 template <typename T, int FIELD, bool MASKED, bool G>

@@ -5,6 +5,11 @@ Usage:
       total device time, launches, average / minimum duration, grid size,
       VGPR count and scratch bytes per kernel (heaviest first), then the
       fine-level operator kernels grouped by (field, precision).
+  python -m paper_2103_00081_amd.profsummary traffic <fetch.db> <write.db> <copy_mib>
+      FETCH_SIZE + WRITE_SIZE bytes per launch of each operator class with
+      the store epilogue, scaled by the counts of the library's plain copy of
+      copy_mib MiB, with the hash of the operator sources they were taken on
+      (the lines the benchmark reads).
   python -m paper_2103_00081_amd.profsummary pmc <counter_collection.csv | results.db> [copy_mib]
       per-dispatch hardware counters (e.g. FETCH_SIZE, WRITE_SIZE) averaged
       per operator class, epilogue and grid size; with copy_mib, the counters
@@ -17,7 +22,23 @@ import re
 import sqlite3
 import sys
 
-_APPLY = re.compile(r"k_q([12])_apply<(float|double), (\d)")
+# operator kernels: k_q1_pressure<T, EPI, ...>, k_q1_heat<T, EPI, ...>,
+# k_q2_apply<T, FIELD, EPI, ...>
+_Q1 = re.compile(r"k_q1_(pressure|heat)<(float|double), (\d)")
+_Q2 = re.compile(r"k_q2_apply<(float|double), (\d), (\d)")
+
+
+def apply_info(name: str):
+    """(class, epilogue) of an operator kernel name, or None."""
+    m = _Q1.search(name)
+    if m:
+        prec = "FP64" if m.group(2) == "double" else "FP32"
+        return "Q1 %s apply %s" % (m.group(1), prec), m.group(3)
+    m = _Q2.search(name)
+    if m:
+        prec = "FP64" if m.group(1) == "double" else "FP32"
+        return "Q2 %s apply %s" % ("pressure" if m.group(2) == "0" else "heat", prec), m.group(3)
+    return None
 
 
 def short_name(name: str) -> str:
@@ -26,12 +47,8 @@ def short_name(name: str) -> str:
 
 
 def apply_class(name: str):
-    m = _APPLY.search(name)
-    if not m:
-        return None
-    field = "pressure" if m.group(3) == "0" else "heat"
-    prec = "FP64" if m.group(2) == "double" else "FP32"
-    return "Q%s %s apply %s" % (m.group(1), field, prec)
+    i = apply_info(name)
+    return i[0] if i else None
 
 
 def summarise(db: str, top: int = 40) -> str:
@@ -81,7 +98,6 @@ def _pmc_rows(path: str):
     return [(r[did], r[kname], int(r[grid]) if grid else 0, r[cname], float(r[cval])) for r in rows]
 
 
-_EPI = re.compile(r"k_q([12])_apply<(float|double), (\d), (\d)")
 
 
 def pmc(path: str, copy_mib: float = 0.0) -> str:
@@ -105,10 +121,10 @@ def pmc(path: str, copy_mib: float = 0.0) -> str:
                     c, best.get(c, 0.0), copy_mib, factor[c]))
     cls = {}
     for d in per.values():
-        m = _EPI.search(d["name"])
-        if not m:
+        info = apply_info(d["name"])
+        if not info:
             continue
-        k = "%s epi %s grid %d" % (apply_class(d["name"]), m.group(4), d["grid"])
+        k = "%s epi %s grid %d" % (info[0], info[1], d["grid"])
         a = cls.setdefault(k, {"n": 0})
         a["n"] += 1
         for c in counters:
@@ -123,9 +139,58 @@ def pmc(path: str, copy_mib: float = 0.0) -> str:
     return "\n".join(out)
 
 
+def kernel_source_hash(root: str) -> str:
+    """First 16 hex digits of the SHA-256 of the Q1 operator sources (the
+    benchmark accepts a counter summary only for the source it was taken on)."""
+    import hashlib
+    import os
+    src = [os.path.join(root, "paper_2103_00081_amd", "csrc", f) for f in ("op_q1.hip", "dev_util.h", "common.h")]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
+
+
+def traffic(fetch_db: str, write_db: str, copy_mib: float) -> str:
+    """HBM-side bytes per launch of each operator class with the store
+    epilogue: FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+    reads for the library's plain copy of copy_mib MiB."""
+    import os
+    out = []
+    per_class = {}
+    for path, cname in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        per = {}
+        for did, name, grid, cn, v in _pmc_rows(path):
+            if cn != cname:
+                continue
+            d = per.setdefault(did, {"name": name, "grid": grid, "v": 0.0})
+            d["v"] += float(v)
+        copies = [d for d in per.values() if "k_stream_copy" in d["name"]]
+        unit = copy_mib * (1 << 20) / max(max(d["v"] for d in copies), 1e-30)
+        out.append("%s: %.4f B per counter unit (copy of %.0f MiB)" % (cname, unit, copy_mib))
+        for d in per.values():
+            info = apply_info(d["name"])
+            if not info or info[1] != "0":
+                continue
+            a = per_class.setdefault(info[0], {}).setdefault(cname, [])
+            a.append(d["v"] * unit)
+    out.append("")
+    out.append("| class | launches | FETCH MB | WRITE MB | total MB |")
+    out.append("|---|---|---|---|---|")
+    lines = []
+    for k, c in sorted(per_class.items()):
+        f = sum(c.get("FETCH_SIZE", [0])) / max(1, len(c.get("FETCH_SIZE", [1])))
+        w = sum(c.get("WRITE_SIZE", [0])) / max(1, len(c.get("WRITE_SIZE", [1])))
+        out.append("| %s | %d | %.2f | %.2f | %.2f |" % (k, len(c.get("FETCH_SIZE", [])), f / 1e6, w / 1e6,
+                                                       (f + w) / 1e6))
+        lines.append("traffic_bytes_per_launch %s %.0f" % (k, f + w))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out += ["", "kernel_source_sha256_16 %s" % kernel_source_hash(root)] + lines
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "pmc":
         print(pmc(sys.argv[2], float(sys.argv[3]) if len(sys.argv) > 3 else 0.0))
+    elif len(sys.argv) >= 5 and sys.argv[1] == "traffic":
+        print(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4])))
     elif len(sys.argv) >= 3 and sys.argv[1] == "trace":
         print(summarise(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 40))
     else:
