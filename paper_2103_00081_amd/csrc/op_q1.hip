@@ -51,22 +51,10 @@ __device__ __forceinline__ void k1p(T &a, T &b)
     b = -d;
 }
 
-template <typename T>
-__device__ __forceinline__ void g1p(T &a, T &b)
-{
-    // values at the two Gauss points 1/2 -+ 1/(2 sqrt 3) from nodal values;
-    // the matrix is symmetric, so it is also its own transpose
-    const T c1 = T(0.78867513459481288225), c2 = T(0.21132486540518711775);
-    const T na = c1 * a + c2 * b;
-    const T nb = c2 * a + c1 * b;
-    a = na;
-    b = nb;
-}
 
 #define PZ(F, v) F(v[0], v[4]); F(v[1], v[5]); F(v[2], v[6]); F(v[3], v[7]);
 #define PY(F, v) F(v[0], v[2]); F(v[1], v[3]); F(v[4], v[6]); F(v[5], v[7]);
 #define PX(F, v) F(v[0], v[1]); F(v[2], v[3]); F(v[4], v[5]); F(v[6], v[7]);
-#define P2(F, v) F(v[0], v[1]); F(v[2], v[3]); F(v[0], v[2]); F(v[1], v[3]);
 
 // w = m (M x M x M) u + (sx K x M x M + sy M x K x M + sz M x M x K) u with
 // the unscaled 1D factors; for mass coefficient c and stiffness coefficient
@@ -96,50 +84,6 @@ __device__ __forceinline__ void cell_mass_stiff(const T u[8], T m, T sx, T sy, T
     PX(k1p, g);
 #pragma unroll
     for (int i = 0; i < 8; i++) w[i] = f[i] + sx * g[i];
-}
-
-// w += sum_q N_a(q) (q_h . grad u)(q) dt c_w V / 8 at the 2 x 2 x 2 Gauss
-// points, q_h = -k (grad P + rho_g e_z).  A derivative along x of a trilinear
-// function is bilinear in (y, z), so it is needed at 4 Gauss points only.
-// ax, ay, az: -k dt c_w V / (8 h_d^2), per cell; pz0 = rho_g hz.
-template <typename T>
-__device__ __forceinline__ void cell_convect(const T u[8], const T P[8], T ax_, T ay_, T az_, T pz0, T w[8])
-{
-    T gx[4], gy[4], gz[4], px[4], py[4], pz[4];
-#pragma unroll
-    for (int s = 0; s < 2; s++)
-#pragma unroll
-        for (int t = 0; t < 2; t++) {
-            gx[s + 2 * t] = u[1 + 2 * s + 4 * t] - u[2 * s + 4 * t];   // (ay, az)
-            gy[s + 2 * t] = u[s + 2 + 4 * t] - u[s + 4 * t];           // (ax, az)
-            gz[s + 2 * t] = u[s + 2 * t + 4] - u[s + 2 * t];           // (ax, ay)
-            px[s + 2 * t] = P[1 + 2 * s + 4 * t] - P[2 * s + 4 * t];
-            py[s + 2 * t] = P[s + 2 + 4 * t] - P[s + 4 * t];
-            pz[s + 2 * t] = P[s + 2 * t + 4] - P[s + 2 * t];
-        }
-    P2(g1p, gx);
-    P2(g1p, gy);
-    P2(g1p, gz);
-    P2(g1p, px);
-    P2(g1p, py);
-    P2(g1p, pz);
-    T ax[4], ay[4], az[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        ax[j] = (ax_ * px[j]) * gx[j];
-        ay[j] = (ay_ * py[j]) * gy[j];
-        az[j] = (az_ * (pz[j] + pz0)) * gz[j];
-    }
-    P2(g1p, ax);
-    P2(g1p, ay);
-    P2(g1p, az);
-#pragma unroll
-    for (int z = 0; z < 2; z++)
-#pragma unroll
-        for (int y = 0; y < 2; y++)
-#pragma unroll
-            for (int x = 0; x < 2; x++)
-                w[x + 2 * y + 4 * z] += (ax[y + 2 * z] + ay[x + 2 * z]) + az[x + 2 * y];
 }
 
 // Element i of an instance vector through a 32-bit byte offset from a
@@ -532,6 +476,111 @@ constexpr int NB = 16;          // cell columns per tile edge
 constexpr int NOWN = NB - 1;    // owned node columns per tile edge
 constexpr int NNCOL = (NB + 1) * (NB + 1);
 
+// Heat cell operator in Haar coordinates.  Along one axis the pair of node
+// values (v0, v1) becomes (s, d) = (v0 + v1, v0 - v1); there the unscaled 1D
+// mass [2 1; 1 2] and stiffness [1 -1; -1 1] are diagonal, (3, 1) and (0, 2),
+// and so is the interpolation to the two Gauss points, (1, 1/sqrt 3).  Mass
+// and conduction become one diagonal scaling of the 8 Haar coefficients, and
+// the convection term of an axis, a Gauss-point product of two bilinear
+// fields on the cell's cross-section, becomes the product rule
+//   out_s = (S s + D d / 3) / 2,  out_d = (S d + D s) / 6
+// per cross-section axis (S, D: the flux field, s, d: the temperature
+// differences), whose result is constant along the axis.  The same quadrature
+// sums as the nodal form, about two thirds of its operations.
+template <typename T>
+__device__ __forceinline__ void haar_pair(T &a, T &b)
+{
+    const T s = a + b, d = a - b;
+    a = s;
+    b = d;
+}
+
+// 3D transform in place, index x + 2y + 4z (its own inverse up to 1/8)
+template <typename T>
+__device__ __forceinline__ void haar3(T v[8])
+{
+    haar_pair(v[0], v[1]); haar_pair(v[2], v[3]); haar_pair(v[4], v[5]); haar_pair(v[6], v[7]);
+    haar_pair(v[0], v[2]); haar_pair(v[1], v[3]); haar_pair(v[4], v[6]); haar_pair(v[5], v[7]);
+    haar_pair(v[0], v[4]); haar_pair(v[1], v[5]); haar_pair(v[2], v[6]); haar_pair(v[3], v[7]);
+}
+
+// 2D transform in place, index i + 2j: 0 ss, 1 ds, 2 sd, 3 dd
+template <typename T>
+__device__ __forceinline__ void haar2(T v[4])
+{
+    haar_pair(v[0], v[1]); haar_pair(v[2], v[3]); haar_pair(v[0], v[2]); haar_pair(v[1], v[3]);
+}
+
+// o += the back-projected Gauss-point product of A and v (2D Haar
+// coordinates); A carries the weights 1/4, 1/12, 1/12, 1/36 of its terms
+template <typename T>
+__device__ __forceinline__ void haar_prod2(const T A[4], const T v[4], T &o0, T &o1, T &o2, T &o3)
+{
+    const T third = T(1) / T(3);
+    const T A03 = A[0] * third, A13 = A[1] * third, A23 = A[2] * third, A09 = A03 * third;
+    o0 += A[0] * v[0] + A[1] * v[1] + A[2] * v[2] + A[3] * v[3];
+    o1 += A03 * v[1] + A[1] * v[0] + A23 * v[3] + A[3] * v[2];
+    o2 += A03 * v[2] + A[2] * v[0] + A13 * v[3] + A[3] * v[1];
+    o3 += A09 * v[3] + A13 * v[2] + A23 * v[1] + A[3] * v[0];
+}
+
+// w = (m M x M x M + sx K x M x M + sy M x K x M + sz M x M x K) u plus
+// sum_q N_a(q) (q_h . grad u)(q) dt c_w V / 8 at the 2 x 2 x 2 Gauss points,
+// q_h = -k (grad P + rho_g e_z), in Haar coordinates.  ax_, ay_, az_:
+// -k dt c_w V / (8 h_d^2), per cell; pz0 = rho_g hz.
+template <typename T>
+__device__ __forceinline__ void cell_heat_haar(const T u[8], const T P[8], T m, T sx, T sy, T sz, T ax_, T ay_,
+                                               T az_, T pz0, T w[8])
+{
+    T U[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) U[i] = u[i];
+    haar3(U);
+    // eigenvalues m mu mu mu + sx kappa mu mu + ..., mu = (3, 1), kappa =
+    // (0, 2), times the 1/8 of the inverse transform
+    const T a = T(0.375) * m, b = T(0.75) * sx, c = T(0.75) * sy, d = T(0.75) * sz;
+    T W[8];
+    W[0] = (T(9) * a) * U[0];
+    W[1] = (T(3) * (a + b)) * U[1];
+    W[2] = (T(3) * (a + c)) * U[2];
+    W[4] = (T(3) * (a + d)) * U[4];
+    W[3] = (a + b + c) * U[3];
+    W[5] = (a + b + d) * U[5];
+    W[6] = (a + c + d) * U[6];
+    W[7] = ((a + b + c + d) * (T(1) / T(3))) * U[7];
+    // per axis: the P differences along it (direct, then 2D Haar over the
+    // cross-section), weighted by the axis factor times -1/4 (the 1/8 of the
+    // inverse, the 2 of the broadcast along the axis, and the sign of the d
+    // coefficients of U) and the per-term weights
+    T px[4], py[4], pz[4];
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            px[s + 2 * t] = P[1 + 2 * s + 4 * t] - P[2 * s + 4 * t];
+            py[s + 2 * t] = P[s + 2 + 4 * t] - P[s + 4 * t];
+            pz[s + 2 * t] = P[s + 2 * t + 4] - P[s + 2 * t];
+        }
+    haar2(px);
+    haar2(py);
+    haar2(pz);
+    pz[0] += T(4) * pz0;
+    const T q4 = T(-1) / T(16), q12 = T(-1) / T(48), q36 = T(-1) / T(144);
+    T A[4], v[4];
+    A[0] = (ax_ * q4) * px[0]; A[1] = (ax_ * q12) * px[1]; A[2] = (ax_ * q12) * px[2]; A[3] = (ax_ * q36) * px[3];
+    v[0] = U[1]; v[1] = U[3]; v[2] = U[5]; v[3] = U[7];
+    haar_prod2(A, v, W[0], W[2], W[4], W[6]);
+    A[0] = (ay_ * q4) * py[0]; A[1] = (ay_ * q12) * py[1]; A[2] = (ay_ * q12) * py[2]; A[3] = (ay_ * q36) * py[3];
+    v[0] = U[2]; v[1] = U[3]; v[2] = U[6]; v[3] = U[7];
+    haar_prod2(A, v, W[0], W[1], W[4], W[5]);
+    A[0] = (az_ * q4) * pz[0]; A[1] = (az_ * q12) * pz[1]; A[2] = (az_ * q12) * pz[2]; A[3] = (az_ * q36) * pz[3];
+    v[0] = U[4]; v[1] = U[5]; v[2] = U[6]; v[3] = U[7];
+    haar_prod2(A, v, W[0], W[1], W[2], W[3]);
+    haar3(W);
+#pragma unroll
+    for (int i = 0; i < 8; i++) w[i] = W[i];
+}
+
 template <typename T, int EPI, bool MASKED, bool GRADED>
 __global__ __launch_bounds__(256) void k_q1_heat(const OpDev *__restrict__ ops,
                                                   const WorkItem *__restrict__ work,
@@ -808,15 +857,16 @@ __global__ __launch_bounds__(256) void k_q1_heat(const OpDev *__restrict__ ops,
                 lvz = gvz * ihz;
                 lpz0 = T(o.rho_g) * hz;
             }
-            cell_mass_stiff(u, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
-            if (adv) {   // no convection in the mass-only heat operator
+            if (adv) {
                 T pp[8];
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
                     pp[a] = ps[b0][ty + (a >> 1)][tx + (a & 1)];
                     pp[a + 4] = ps[b1][ty + (a >> 1)][tx + (a & 1)];
                 }
-                cell_convect(u, pp, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
+                cell_heat_haar(u, pp, cc * lfm, cl * lfx, cl * lfy, cl * lfz, ck * lvx, ck * lvy, ck * lvz, lpz0, w);
+            } else {   // no convection in the mass-only heat operator
+                cell_mass_stiff(u, cc * lfm, cl * lfx, cl * lfy, cl * lfz, w);
             }
 #pragma unroll
             for (int a = 0; a < 4; a++) { bot[a] = w[a]; tp[a] = w[a + 4]; }
