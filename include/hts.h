@@ -182,7 +182,9 @@ typedef struct {
 void hts_default_opts(hts_solver_opts *opts);
 
 /* Create a mesh (Section 3.3: a hexahedral mesh of the site box).
- * degree must be 1 or 2; every ncells entry >= 1; extent > 0.
+ * degree must be 1 or 2; every ncells entry >= 1; extent > 0; fewer than
+ * 65535 nodes along an axis and fewer than 2^29 nodes in all (one FP64 vector
+ * of the mesh stays below 4 GiB, which the kernels' 32-bit offsets assume).
  * HTS_ERR_ARG on bad geometry, HTS_ERR_HIP if the device cannot be set. */
 hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out);
 

@@ -517,6 +517,13 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
                     ARG_CHECK(e[i + 1] > e[i], "cell edges must increase strictly");
             }
         }
+        {
+            // the operator kernels address an instance's vectors with 32-bit
+            // byte offsets: one FP64 vector of the mesh stays below 4 GiB
+            int64_t nn = 1;
+            for (int d = 0; d < 3; d++) nn *= (int64_t)desc->degree * desc->ncells[d] + 1;
+            ARG_CHECK(nn < (int64_t)1 << 29, "mesh too large: 2^29 nodes or more");
+        }
         HTS_HIP(hipSetDevice(desc->device));
         std::unique_ptr<hts_mesh> m(new hts_mesh());
         m->desc = *desc;
@@ -535,7 +542,6 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
             m->nnode *= m->N[d];
             m->ncell *= m->n[d];
         }
-        ARG_CHECK(m->nnode < (int64_t)1 << 31, "mesh too large for 32-bit node indices");
         // node coordinates of every axis; graded meshes keep their edges and
         // upload the cell sizes and node coordinates
         m->graded = graded;

@@ -1962,11 +1962,16 @@ hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
             HTS_HIP(hipEventCreate(&e1));
             for (int f = 0; f < 2; f++) {
                 Tables &t = b.apply_tables(f, dt, f == 0 && m->B <= 0.0);
-                const int cands[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+                const int cands[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 48, 64};
                 double best = 1e30;
                 int bz = 0;
+                std::vector<int> tried;
                 for (int zc : cands) {
                     if (zc > m->N[2] && bz > 0) break;
+                    // Q2 depths are rounded up to whole cell layers
+                    const int eff = zc_for(m, f, 1, zc);
+                    if (std::find(tried.begin(), tried.end(), eff) != tried.end()) continue;
+                    tried.push_back(eff);
                     b.zc_force[f] = zc;
                     b.build_work();
                     EpiArgs<double> e64{};

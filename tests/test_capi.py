@@ -75,3 +75,19 @@ def test_graded_mesh_validation_without_device():
     short = np.array([0.0, 1.0, 2.0, 6.0, 9.0])
     assert L.hts_create_mesh(ctypes.byref(desc(short)), ctypes.byref(h)) == -1
     assert b"span" in L.hts_last_error()
+
+
+def test_mesh_size_limit_without_device():
+    """A mesh with 2^29 nodes or more is refused before any device work (the
+    operator kernels address one FP64 vector with 32-bit byte offsets)."""
+    import paper_2103_00081_amd as hts
+    L = hts.load()
+    h = ctypes.c_void_p()
+    d = hts.MeshDesc()
+    d.degree = 1
+    for k, n in enumerate((1000, 1000, 600)):   # 1001 * 1001 * 601 > 2^29 nodes
+        d.origin[k] = 0.0
+        d.extent[k] = 100.0
+        d.ncells[k] = n
+    assert L.hts_create_mesh(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"too large" in L.hts_last_error()
