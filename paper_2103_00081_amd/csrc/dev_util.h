@@ -2,6 +2,8 @@
 #pragma once
 #include "common.h"
 
+#include <type_traits>
+
 namespace hts {
 
 // Pointers read out of device-resident descriptors are generic; reading
@@ -38,6 +40,24 @@ __device__ __forceinline__ static ColInfo col_info(const OpDev &o, int i, int j)
 __device__ __forceinline__ static bool constrained(const ColInfo &c, int k, int NZ, int m)
 {
     return c.xyc || ((m & 16) && k == 0) || ((m & 32) && k == NZ - 1) || (k >= c.dlo && k <= c.dhi);
+}
+
+// Element i of an instance vector through a 32-bit byte offset from a
+// uniform base (one vector of an instance stays below 4 GiB: meshes have
+// fewer than 2^29 nodes), so the loads and stores take
+// the scalar-base plus 32-bit-offset address form without 64-bit address
+// arithmetic per lane.
+template <typename P>
+__device__ __forceinline__ P *at32(P *base, uint32_t i)
+{
+    using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    return reinterpret_cast<P *>(reinterpret_cast<C *>(base) + i * (uint32_t)sizeof(P));
+}
+template <typename P>
+__device__ __forceinline__ const P HTS_GLOBAL *at32(const P HTS_GLOBAL *base, uint32_t i)
+{
+    return reinterpret_cast<const P HTS_GLOBAL *>(reinterpret_cast<const char HTS_GLOBAL *>(base) +
+                                                  i * (uint32_t)sizeof(P));
 }
 
 __device__ __forceinline__ static double wave_sum(double v)

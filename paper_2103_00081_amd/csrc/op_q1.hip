@@ -86,23 +86,6 @@ __device__ __forceinline__ void cell_mass_stiff(const T u[8], T m, T sx, T sy, T
     for (int i = 0; i < 8; i++) w[i] = f[i] + sx * g[i];
 }
 
-// Element i of an instance vector through a 32-bit byte offset from a
-// uniform base (one vector stays below 4 GiB), so the loads and stores take
-// the scalar-base plus 32-bit-offset address form without 64-bit address
-// arithmetic per lane.
-template <typename P>
-__device__ __forceinline__ P *at32(P *base, uint32_t i)
-{
-    using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
-    return reinterpret_cast<P *>(reinterpret_cast<C *>(base) + i * (uint32_t)sizeof(P));
-}
-template <typename P>
-__device__ __forceinline__ const P HTS_GLOBAL *at32(const P HTS_GLOBAL *base, uint32_t i)
-{
-    return reinterpret_cast<const P HTS_GLOBAL *>(reinterpret_cast<const char HTS_GLOBAL *>(base) +
-                                                  i * (uint32_t)sizeof(P));
-}
-
 // y-z factors of one x-face of a cell from its node values v{y}{z}, with the
 // unscaled 1D factors: c = (Mz My) v (index y + 2 z), the part with the y
 // stiffness (Mz Ky) v in its two magnitudes d[z] (sign + at y = 0, - at

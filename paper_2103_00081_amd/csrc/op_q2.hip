@@ -78,6 +78,8 @@ __device__ __forceinline__ void q2_mass_stiff(const UAt &uat, T mV, T sk, T cxx,
     for (int i = 0; i < 27; i++) w[i] = T(0);
 #pragma unroll
     for (int j = 0; j < 3; j++) {
+        // one node plane's values at a time (no hoisting of the next plane's reads)
+        asm volatile("" ::: "memory");
         T v[9];
 #pragma unroll
         for (int i = 0; i < 9; i++) v[i] = uat(i + 9 * j);
@@ -113,8 +115,13 @@ __device__ __forceinline__ void q2_mass_stiff(const UAt &uat, T mV, T sk, T cxx,
 }
 
 // w_a += cw sum_q W_q N_a(q) (q_h . grad u)(q), q_h = -k (grad P + rho_g e_z),
-// cw = dt c_w V; 3 x 3 x 3 Gauss points, processed one z-plane at a time:
-// first the flux factors of the plane's 9 points from P, then grad u there.
+// cw = dt c_w V; 3 x 3 x 3 Gauss points, one z-plane of points at a time:
+// the plane's z-contractions of P and u (values and z-derivatives at the 9
+// node columns), then per row of points (fixed qy) the y- and x-contractions,
+// the integrand at the three points of the row and its projection back onto
+// the x and y basis functions, accumulated over the rows; the plane's sums
+// go to the 27 outputs through the z basis values.  Only one plane's
+// contractions and one row's values are live at a time.
 template <typename T, typename UAt, typename PAt>
 __device__ __forceinline__ void q2_convect(const UAt &uat, const PAt &pat, T kc, T ihx, T ihy, T ihz, T rho_g,
                                           T cw, T w[27])
@@ -123,106 +130,94 @@ __device__ __forceinline__ void q2_convect(const UAt &uat, const PAt &pat, T kc,
     const T s0 = -kc * cw;
 #pragma unroll 1
     for (int qz = 0; qz < 3; qz++) {
+        // keeps the LDS reads of the nodal values inside the loop (read again
+        // per plane of points instead of 54 values held across it)
+        asm volatile("" ::: "memory");
         const T bz0 = Q::B[qz][0], bz1 = Q::B[qz][1], bz2 = Q::B[qz][2];
         const T dz0 = Q::D[qz][0], dz1 = Q::D[qz][1], dz2 = Q::D[qz][2];
         const T sz = s0 * Q::W[qz];
-        // flux factors cx, cy, cz at the points (qx, qy) of this plane
-        T cx[9], cy[9], cz[9];
-        {
-            T fp[9], fpz[9];
+        T fp[9], fpz[9], fu[9], fuz[9];
 #pragma unroll
-            for (int ij = 0; ij < 9; ij++) {
-                const T p0 = pat(ij), p1 = pat(ij + 9), p2 = pat(ij + 18);
-                fp[ij] = bz0 * p0 + bz1 * p1 + bz2 * p2;
-                fpz[ij] = dz0 * p0 + dz1 * p1 + dz2 * p2;
-            }
-#pragma unroll
-            for (int qy = 0; qy < 3; qy++) {
-                T yp[3], ypd[3], ypz[3];
-#pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    yp[i] = Q::B[qy][0] * fp[i] + Q::B[qy][1] * fp[i + 3] + Q::B[qy][2] * fp[i + 6];
-                    ypd[i] = Q::D[qy][0] * fp[i] + Q::D[qy][1] * fp[i + 3] + Q::D[qy][2] * fp[i + 6];
-                    ypz[i] = Q::B[qy][0] * fpz[i] + Q::B[qy][1] * fpz[i + 3] + Q::B[qy][2] * fpz[i + 6];
-                }
-#pragma unroll
-                for (int qx = 0; qx < 3; qx++) {
-                    const T gpx = Q::D[qx][0] * yp[0] + Q::D[qx][1] * yp[1] + Q::D[qx][2] * yp[2];
-                    const T gpy = Q::B[qx][0] * ypd[0] + Q::B[qx][1] * ypd[1] + Q::B[qx][2] * ypd[2];
-                    const T gpz = Q::B[qx][0] * ypz[0] + Q::B[qx][1] * ypz[1] + Q::B[qx][2] * ypz[2];
-                    const T sw = sz * (Q::W[qx] * Q::W[qy]);
-                    cx[qx + 3 * qy] = sw * ((gpx * ihx) * ihx);
-                    cy[qx + 3 * qy] = sw * ((gpy * ihy) * ihy);
-                    cz[qx + 3 * qy] = sw * ((gpz * ihz + rho_g) * ihz);
-                }
-            }
+        for (int ij = 0; ij < 9; ij++) {
+            const T p0 = pat(ij), p1 = pat(ij + 9), p2 = pat(ij + 18);
+            fp[ij] = bz0 * p0 + bz1 * p1 + bz2 * p2;
+            fpz[ij] = dz0 * p0 + dz1 * p1 + dz2 * p2;
+            const T u0 = uat(ij), u1 = uat(ij + 9), u2 = uat(ij + 18);
+            fu[ij] = bz0 * u0 + bz1 * u1 + bz2 * u2;
+            fuz[ij] = dz0 * u0 + dz1 * u1 + dz2 * u2;
         }
-        T a[9];   // a[qx + 3 qy]
-        {
-            T fu[9], fuz[9];
+        T sacc[9];
 #pragma unroll
-            for (int ij = 0; ij < 9; ij++) {
-                const T u0 = uat(ij), u1 = uat(ij + 9), u2 = uat(ij + 18);
-                fu[ij] = bz0 * u0 + bz1 * u1 + bz2 * u2;
-                fuz[ij] = dz0 * u0 + dz1 * u1 + dz2 * u2;
-            }
+        for (int i = 0; i < 9; i++) sacc[i] = T(0);
 #pragma unroll
-            for (int qy = 0; qy < 3; qy++) {
-                T yu[3], yud[3], yuz[3];
-#pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    yu[i] = Q::B[qy][0] * fu[i] + Q::B[qy][1] * fu[i + 3] + Q::B[qy][2] * fu[i + 6];
-                    yud[i] = Q::D[qy][0] * fu[i] + Q::D[qy][1] * fu[i + 3] + Q::D[qy][2] * fu[i + 6];
-                    yuz[i] = Q::B[qy][0] * fuz[i] + Q::B[qy][1] * fuz[i + 3] + Q::B[qy][2] * fuz[i + 6];
-                }
-#pragma unroll
-                for (int qx = 0; qx < 3; qx++) {
-                    const T gux = Q::D[qx][0] * yu[0] + Q::D[qx][1] * yu[1] + Q::D[qx][2] * yu[2];
-                    const T guy = Q::B[qx][0] * yud[0] + Q::B[qx][1] * yud[1] + Q::B[qx][2] * yud[2];
-                    const T guz = Q::B[qx][0] * yuz[0] + Q::B[qx][1] * yuz[1] + Q::B[qx][2] * yuz[2];
-                    const int q = qx + 3 * qy;
-                    a[q] = cx[q] * gux + cy[q] * guy + cz[q] * guz;
-                }
-            }
-        }
-        // back-projection: s[i + 3 j] = sum_{qx, qy} B[qx][i] B[qy][j] a
-        T t[9];
-#pragma unroll
-        for (int qy = 0; qy < 3; qy++)
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-                t[i + 3 * qy] = Q::B[0][i] * a[3 * qy] + Q::B[1][i] * a[1 + 3 * qy] + Q::B[2][i] * a[2 + 3 * qy];
-#pragma unroll
-        for (int j = 0; j < 3; j++)
+        for (int qy = 0; qy < 3; qy++) {
+            T yp[3], ypd[3], ypz[3], yu[3], yud[3], yuz[3];
 #pragma unroll
             for (int i = 0; i < 3; i++) {
-                const T s = Q::B[0][j] * t[i] + Q::B[1][j] * t[i + 3] + Q::B[2][j] * t[i + 6];
-                w[i + 3 * j] += bz0 * s;
-                w[i + 3 * j + 9] += bz1 * s;
-                w[i + 3 * j + 18] += bz2 * s;
+                yp[i] = Q::B[qy][0] * fp[i] + Q::B[qy][1] * fp[i + 3] + Q::B[qy][2] * fp[i + 6];
+                ypd[i] = Q::D[qy][0] * fp[i] + Q::D[qy][1] * fp[i + 3] + Q::D[qy][2] * fp[i + 6];
+                ypz[i] = Q::B[qy][0] * fpz[i] + Q::B[qy][1] * fpz[i + 3] + Q::B[qy][2] * fpz[i + 6];
+                yu[i] = Q::B[qy][0] * fu[i] + Q::B[qy][1] * fu[i + 3] + Q::B[qy][2] * fu[i + 6];
+                yud[i] = Q::D[qy][0] * fu[i] + Q::D[qy][1] * fu[i + 3] + Q::D[qy][2] * fu[i + 6];
+                yuz[i] = Q::B[qy][0] * fuz[i] + Q::B[qy][1] * fuz[i + 3] + Q::B[qy][2] * fuz[i + 6];
             }
+            T a[3];
+#pragma unroll
+            for (int qx = 0; qx < 3; qx++) {
+                const T gpx = Q::D[qx][0] * yp[0] + Q::D[qx][1] * yp[1] + Q::D[qx][2] * yp[2];
+                const T gpy = Q::B[qx][0] * ypd[0] + Q::B[qx][1] * ypd[1] + Q::B[qx][2] * ypd[2];
+                const T gpz = Q::B[qx][0] * ypz[0] + Q::B[qx][1] * ypz[1] + Q::B[qx][2] * ypz[2];
+                const T gux = Q::D[qx][0] * yu[0] + Q::D[qx][1] * yu[1] + Q::D[qx][2] * yu[2];
+                const T guy = Q::B[qx][0] * yud[0] + Q::B[qx][1] * yud[1] + Q::B[qx][2] * yud[2];
+                const T guz = Q::B[qx][0] * yuz[0] + Q::B[qx][1] * yuz[1] + Q::B[qx][2] * yuz[2];
+                const T sw = sz * (Q::W[qx] * Q::W[qy]);
+                const T cxq = sw * ((gpx * ihx) * ihx);
+                const T cyq = sw * ((gpy * ihy) * ihy);
+                const T czq = sw * ((gpz * ihz + rho_g) * ihz);
+                a[qx] = cxq * gux + cyq * guy + czq * guz;
+            }
+            // back onto the x basis functions, then the y basis functions of this row
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const T t = Q::B[0][i] * a[0] + Q::B[1][i] * a[1] + Q::B[2][i] * a[2];
+#pragma unroll
+                for (int j = 0; j < 3; j++) sacc[i + 3 * j] += Q::B[qy][j] * t;
+            }
+        }
+#pragma unroll
+        for (int ij = 0; ij < 9; ij++) {
+            w[ij] += bz0 * sacc[ij];
+            w[ij + 9] += bz1 * sacc[ij];
+            w[ij + 18] += bz2 * sacc[ij];
+        }
     }
 }
 
-// Compact node-column data of the apply kernel (three registers per column
-// instead of ColInfo's six): node column index, packed constrained z-range,
-// bit 0 valid and bit 1 constrained by an x/y face.
+// Compact node-column data of the apply kernel (two registers per column
+// instead of ColInfo's six): bf = instance-local node column index (bits
+// 0..29), bit 30 valid, bit 31 constrained by an x/y face; dl = packed
+// constrained z-range.  A node plane has fewer than 2^30 columns: a mesh
+// has fewer than 2^31 nodes (checked when it is created) and at least two
+// node planes.
 struct ColQ {
-    int32_t base, dl, f;
+    uint32_t bf;
+    int32_t dl;
+    __device__ __forceinline__ int base() const { return (int)(bf & 0x3FFFFFFFu); }
+    __device__ __forceinline__ bool valid() const { return (bf >> 30) & 1u; }
+    __device__ __forceinline__ bool xyc() const { return bf >> 31; }
 };
 __device__ __forceinline__ static ColQ colq(const OpDev &o, int i, int j)
 {
     const ColInfo c = col_info(o, i, j);
     ColQ q;
-    q.base = (int32_t)c.base;
+    q.bf = (uint32_t)c.base | (c.valid ? 1u << 30 : 0u) | (c.xyc ? 1u << 31 : 0u);
     q.dl = c.dlo | (c.dhi << 16);
-    q.f = (c.valid ? 1 : 0) | (c.xyc ? 2 : 0);
     return q;
 }
 __device__ __forceinline__ static bool constrained_q(const ColQ &c, int k, int NZ, int m)
 {
     const int lo = c.dl & 0xFFFF, hi = (c.dl >> 16) & 0xFFFF;
-    return (c.f & 2) || ((m & 16) && k == 0) || ((m & 32) && k == NZ - 1) || (k >= lo && k <= hi);
+    return c.xyc() || ((m & 16) && k == 0) || ((m & 32) && k == NZ - 1) || (k >= lo && k <= hi);
 }
 
 template <typename T, int FIELD, int EPI, bool MASKED, bool GRADED>
@@ -233,7 +228,10 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
 {
     __shared__ T xs[3][NL][NL + 1];
     __shared__ T ps[FIELD ? 3 : 1][FIELD ? NL : 1][FIELD ? NL + 1 : 1];
-    __shared__ T C[2][9][256];
+    // heat: one node plane of cell contributions at a time (keeps the
+    // workgroup's LDS under half a CU's); pressure: two
+    constexpr bool ONEP = FIELD == 1;
+    __shared__ T C[ONEP ? 1 : 2][9][256];
     __shared__ double red[4];
 
     const WorkItem wi = work[blockIdx.x];
@@ -259,29 +257,26 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
     const int64_t cplane = (int64_t)nx * ny;
     const int nx0 = 2 * cx0, ny0 = 2 * cy0;                     // node of local column 0
 
-    // staged node columns of this thread
+    // staged node columns of this thread: column tid + 256 s of the staged
+    // 33 x 33 (local coordinates recomputed where used)
     ColQ sc[SPT];
-    int sli[SPT], slj[SPT];
 #pragma unroll
     for (int s = 0; s < SPT; s++) {
         const int c = tid + 256 * s;
-        sli[s] = c % NL;
-        slj[s] = c / NL;
-        if (c < NSTAGE) sc[s] = colq(o, nx0 + sli[s], ny0 + slj[s]);
-        else sc[s] = ColQ{0, DCOL_NONE, 0};
+        if (c < NSTAGE) sc[s] = colq(o, nx0 + c % NL, ny0 + c / NL);
+        else sc[s] = ColQ{0u, DCOL_NONE};
     }
-    // owned node columns of this thread (local columns 2 .. 31)
+    // owned node columns of this thread: column tid + 256 s of the owned
+    // 30 x 30 (local columns 2 .. 31)
     ColQ oc[OPT];
-    int oli[OPT], olj[OPT], lr[OPT];
+    int lr[OPT];
 #pragma unroll
     for (int s = 0; s < OPT; s++) {
         const int c = tid + 256 * s;
-        oli[s] = 2 + c % OWNN;
-        olj[s] = 2 + c / OWNN;
-        if (c < NOWN) oc[s] = colq(o, nx0 + oli[s], ny0 + olj[s]);
-        else oc[s] = ColQ{0, DCOL_NONE, 0};
+        if (c < NOWN) oc[s] = colq(o, nx0 + 2 + c % OWNN, ny0 + 2 + c / OWNN);
+        else oc[s] = ColQ{0u, DCOL_NONE};
         lr[s] = -1;
-        if (FIELD && o.lcol && (oc[s].f & 1)) lr[s] = gptr<int32_t>(o.lcol)[oc[s].base];
+        if (FIELD && o.lcol && oc[s].valid()) lr[s] = gptr<int32_t>(o.lcol)[oc[s].base()];
     }
 
     const T hx = T(o.hx), hy = T(o.hy), hz = T(o.hz);
@@ -312,16 +307,19 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
         const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
 #pragma unroll
         for (int s = 0; s < SPT; s++) {
-            if (tid + 256 * s >= NSTAGE) continue;
-            const bool in = (sc[s].f & 1) && k >= 0 && k < NZ;
-            const int64_t gi = (sc[s].f & 1) ? (int64_t)sc[s].base + kc * plane : 0;
+            const int c = tid + 256 * s;
+            if (c >= NSTAGE) continue;
+            const int li = c % NL, lj = c / NL;
+            const bool val = sc[s].valid();
+            const bool in = val && k >= 0 && k < NZ;
+            const int64_t gi = val ? (int64_t)sc[s].base() + kc * plane : 0;
             bool keep = in;
             if (MASKED) keep = keep && !constrained_q(sc[s], k, NZ, m);
             const T xv = Xi[gi];
-            xs[b][slj[s]][sli[s]] = keep ? xv : T(0);
+            xs[b][lj][li] = keep ? xv : T(0);
             if (FIELD) {
                 const T pv = Pi[gi];
-                ps[FIELD ? b : 0][FIELD ? slj[s] : 0][FIELD ? sli[s] : 0] = in ? pv : T(0);
+                ps[FIELD ? b : 0][FIELD ? lj : 0][FIELD ? li : 0] = in ? pv : T(0);
             }
         }
     };
@@ -335,7 +333,7 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
         const int kc = k < 0 ? 0 : (k >= NZ ? NZ - 1 : k);
 #pragma unroll
         for (int s = 0; s < SPT; s++) {
-            const int64_t gi = (sc[s].f & 1) ? (int64_t)sc[s].base + kc * plane : 0;
+            const int64_t gi = sc[s].valid() ? (int64_t)sc[s].base() + kc * plane : 0;
             dst[s] = Xi[gi];
         }
     };
@@ -343,19 +341,87 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
         const int b = (k + 6) % 3;
 #pragma unroll
         for (int s = 0; s < SPT; s++) {
-            if (tid + 256 * s >= NSTAGE) continue;
-            bool keep = (sc[s].f & 1) && k >= 0 && k < NZ;
+            const int c = tid + 256 * s;
+            if (c >= NSTAGE) continue;
+            bool keep = sc[s].valid() && k >= 0 && k < NZ;
             if (MASKED) keep = keep && !constrained_q(sc[s], k, NZ, m);
-            xs[b][slj[s]][sli[s]] = keep ? src[s] : T(0);
+            xs[b][c / NL][c % NL] = keep ? src[s] : T(0);
         }
     };
 
     const int z0 = wi.z0, z1 = wi.z1;            // owned node planes, z0 even
     const int L0 = z0 / 2 - 1, L1 = (z1 - 1) / 2;  // cell layers marched
     double acc = 0.0;
-    T top[9];
+    // pressure: the cell's top-plane contributions wait in registers for the
+    // next layer; heat: in the thread's own slots of C
+    T top[ONEP ? 1 : 9];
 #pragma unroll
-    for (int a = 0; a < 9; a++) top[a] = T(0);
+    for (int a = 0; a < (ONEP ? 1 : 9); a++) top[a] = T(0);
+    if (ONEP) {
+#pragma unroll
+        for (int a = 0; a < 9; a++) C[0][a][tid] = T(0);
+    }
+
+    // the owners of node plane P0 = 2L + h add the cell contributions in Cp
+    auto gather = [&](int h, int L, const T (*Cp)[256]) {
+        const int P0 = 2 * L + h;
+        if (P0 < z0 || P0 >= z1 || P0 >= NZ) return;
+#pragma unroll
+        for (int s = 0; s < OPT; s++) {
+            const int c = tid + 256 * s;
+            if (c >= NOWN || !oc[s].valid()) continue;
+            // cells around the node: x index i (local node column li)
+            const int li = 2 + c % OWNN, lj = 2 + c / OWNN;
+            int cxs[2], ixs[2], ncx, cys[2], iys[2], ncy;
+            if (li & 1) { cxs[0] = li >> 1; ixs[0] = 1; ncx = 1; }
+            else { cxs[0] = (li >> 1) - 1; ixs[0] = 2; cxs[1] = li >> 1; ixs[1] = 0; ncx = 2; }
+            if (lj & 1) { cys[0] = lj >> 1; iys[0] = 1; ncy = 1; }
+            else { cys[0] = (lj >> 1) - 1; iys[0] = 2; cys[1] = lj >> 1; iys[1] = 0; ncy = 2; }
+            T v = T(0);
+            for (int b = 0; b < ncy; b++)
+                for (int a = 0; a < ncx; a++) {
+                    const int cell = cxs[a] + TC * cys[b];
+                    v += Cp[ixs[a] + 3 * iys[b]][cell];
+                }
+            const int64_t gi = (int64_t)oc[s].base() + (int64_t)P0 * plane;
+            if (FIELD && lr[s] >= 0) {
+                const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
+                const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
+                const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
+                int r = lr[s];
+                while (rows[r].col == oc[s].base() && rows[r].k < P0) r++;
+                lr[s] = r;
+                if (rows[r].col == oc[s].base() && rows[r].k == P0 && !(MASKED && rows[r].row_constrained)) {
+                    T la = T(0);
+                    for (int e = rows[r].beg; e < rows[r].end; e++) {
+                        if (MASKED && ents[e].col_constrained) continue;
+                        la += T(lco[ents[e].src] * ents[e].w) * Xi[ents[e].col];
+                    }
+                    v += la;
+                }
+            }
+            T ex = T(0);
+            if (EPI == EPI_CHEB || EPI == EPI_DOT || MASKED) ex = Xi[gi];
+            if (MASKED && constrained_q(oc[s], P0, NZ, m)) v = ex;
+            if (EPI == EPI_STORE) {
+                Yi[gi] = v;
+            } else if (EPI == EPI_RESID) {
+                Yi[gi] = Bi[gi] - v;
+            } else if (EPI == EPI_RESID_NORM) {
+                const T r = Bi[gi] - v;
+                Yi[gi] = r;
+                acc += (double)r * (double)r;
+            } else if (EPI == EPI_DOT) {
+                Yi[gi] = v;
+                acc += (double)ex * (double)v;
+            } else if (EPI == EPI_CHEB) {
+                const T r = Bi[gi] - v;
+                const T d = c1 * Di[gi] + c2 * Ii[gi] * r;
+                Di[gi] = d;
+                Yi[gi] = ex + d;
+            }
+        }
+    };
 
     stage(2 * L0);
     if (PF) {
@@ -417,72 +483,32 @@ __global__ __launch_bounds__(256) void k_q2_apply(const OpDev *__restrict__ ops,
 #pragma unroll
             for (int a = 0; a < 27; a++) w[a] = T(0);
         }
+        if (!ONEP) {
+            // both planes at once, one barrier
 #pragma unroll
-        for (int a = 0; a < 9; a++) {
-            C[0][a][tid] = top[a] + w[a];
-            C[1][a][tid] = w[a + 9];
-            top[a] = w[a + 18];
-        }
-        __syncthreads();
-        // owners finish node planes 2L and 2L+1
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int P0 = 2 * L + h;
-            if (P0 < z0 || P0 >= z1 || P0 >= NZ) continue;
-#pragma unroll
-            for (int s = 0; s < OPT; s++) {
-                if (tid + 256 * s >= NOWN || !(oc[s].f & 1)) continue;
-                // cells around the node: x index i (local node column li)
-                const int li = oli[s], lj = olj[s];
-                int cxs[2], ixs[2], ncx, cys[2], iys[2], ncy;
-                if (li & 1) { cxs[0] = li >> 1; ixs[0] = 1; ncx = 1; }
-                else { cxs[0] = (li >> 1) - 1; ixs[0] = 2; cxs[1] = li >> 1; ixs[1] = 0; ncx = 2; }
-                if (lj & 1) { cys[0] = lj >> 1; iys[0] = 1; ncy = 1; }
-                else { cys[0] = (lj >> 1) - 1; iys[0] = 2; cys[1] = lj >> 1; iys[1] = 0; ncy = 2; }
-                T v = T(0);
-                for (int b = 0; b < ncy; b++)
-                    for (int a = 0; a < ncx; a++) {
-                        const int cell = cxs[a] + TC * cys[b];
-                        v += C[h][ixs[a] + 3 * iys[b]][cell];
-                    }
-                const int64_t gi = (int64_t)oc[s].base + (int64_t)P0 * plane;
-                if (FIELD && lr[s] >= 0) {
-                    const LineRow HTS_GLOBAL *rows = gptr<LineRow>(o.lrows);
-                    const LineEnt HTS_GLOBAL *ents = gptr<LineEnt>(o.lents);
-                    const double HTS_GLOBAL *lco = gptr<double>(o.lcoef);
-                    int r = lr[s];
-                    while (rows[r].col == oc[s].base && rows[r].k < P0) r++;
-                    lr[s] = r;
-                    if (rows[r].col == oc[s].base && rows[r].k == P0 && !(MASKED && rows[r].row_constrained)) {
-                        T la = T(0);
-                        for (int e = rows[r].beg; e < rows[r].end; e++) {
-                            if (MASKED && ents[e].col_constrained) continue;
-                            la += T(lco[ents[e].src] * ents[e].w) * Xi[ents[e].col];
-                        }
-                        v += la;
-                    }
-                }
-                T ex = T(0);
-                if (EPI == EPI_CHEB || EPI == EPI_DOT || MASKED) ex = Xi[gi];
-                if (MASKED && constrained_q(oc[s], P0, NZ, m)) v = ex;
-                if (EPI == EPI_STORE) {
-                    Yi[gi] = v;
-                } else if (EPI == EPI_RESID) {
-                    Yi[gi] = Bi[gi] - v;
-                } else if (EPI == EPI_RESID_NORM) {
-                    const T r = Bi[gi] - v;
-                    Yi[gi] = r;
-                    acc += (double)r * (double)r;
-                } else if (EPI == EPI_DOT) {
-                    Yi[gi] = v;
-                    acc += (double)ex * (double)v;
-                } else if (EPI == EPI_CHEB) {
-                    const T r = Bi[gi] - v;
-                    const T d = c1 * Di[gi] + c2 * Ii[gi] * r;
-                    Di[gi] = d;
-                    Yi[gi] = ex + d;
-                }
+            for (int a = 0; a < 9; a++) {
+                C[0][a][tid] = top[a] + w[a];
+                C[ONEP ? 0 : 1][a][tid] = w[a + 9];
+                top[a] = w[a + 18];
             }
+            __syncthreads();
+            gather(0, L, C[0]);
+            gather(1, L, C[ONEP ? 0 : 1]);
+        } else {
+            // node plane 2L: the previous layer's top contributions (already in
+            // the thread's slots) plus this layer's bottom ones
+#pragma unroll
+            for (int a = 0; a < 9; a++) C[0][a][tid] += w[a];
+            __syncthreads();
+            gather(0, L, C[0]);
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 9; a++) C[0][a][tid] = w[a + 9];
+            __syncthreads();
+            gather(1, L, C[0]);
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 9; a++) C[0][a][tid] = w[a + 18];
         }
     }
     if (EPI == EPI_RESID_NORM || EPI == EPI_DOT) {
@@ -578,19 +604,23 @@ __global__ void k_q2_cell_loads(OpDev o, const double *__restrict__ alpha, const
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+template <typename T, int FIELD, int EPI, bool MASKED, bool G>
+static void launch_k2(int nwork, const OpDev *ops, const WorkItem *work, const T *x, T *y, const EpiArgs<T> &ep,
+                      hipStream_t s)
+{
+    k_q2_apply<T, FIELD, EPI, MASKED, G><<<dim3(nwork), dim3(256), 0, s>>>(ops, work, x, y, ep);
+}
+
 template <typename T, int FIELD, bool MASKED, bool G>
 static void dispatch_epi2(int epi, const OpDev *ops, const WorkItem *work, int nwork, const T *x, T *y,
                           const EpiArgs<T> &ep, hipStream_t s)
 {
-    dim3 g(nwork), b(256);
     switch (epi) {
-    case EPI_STORE: k_q2_apply<T, FIELD, EPI_STORE, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_RESID: k_q2_apply<T, FIELD, EPI_RESID, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_RESID_NORM:
-        k_q2_apply<T, FIELD, EPI_RESID_NORM, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep);
-        break;
-    case EPI_DOT: k_q2_apply<T, FIELD, EPI_DOT, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
-    case EPI_CHEB: k_q2_apply<T, FIELD, EPI_CHEB, MASKED, G><<<g, b, 0, s>>>(ops, work, x, y, ep); break;
+    case EPI_STORE: launch_k2<T, FIELD, EPI_STORE, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_RESID: launch_k2<T, FIELD, EPI_RESID, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_RESID_NORM: launch_k2<T, FIELD, EPI_RESID_NORM, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_DOT: launch_k2<T, FIELD, EPI_DOT, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
+    case EPI_CHEB: launch_k2<T, FIELD, EPI_CHEB, MASKED, G>(nwork, ops, work, x, y, ep, s); break;
     default: throw Error(-1, "bad epilogue");
     }
 }
