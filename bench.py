@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--cheb", type=int, default=2, help="pressure multigrid Chebyshev degree")
     ap.add_argument("--heat-cheb", type=int, default=2, help="heat Chebyshev-Jacobi degree")
-    ap.add_argument("--inner-rtol", type=float, default=1e-4)
+    ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--mg-coarse-max", type=int, default=None,
                     help="coarsen until a level has at most this many nodes (dense FP64 solve there); "

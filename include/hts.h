@@ -134,7 +134,7 @@ typedef struct {
                                 FP64 inverse (n^2 entries, read whole by every
                                 coarse solve)                                 */
     int32_t heat_cheb_degree;/* degree of the heat Chebyshev-Jacobi preconditioner */
-    double inner_rtol;       /* inner tolerance of FP32_REFINED (1e-4)          */
+    double inner_rtol;       /* inner tolerance of FP32_REFINED (1e-5)          */
     int32_t check_every;     /* host convergence check every n iterations (1)   */
     int32_t use_graph;       /* replay captured HIP graphs for time steps       */
     hts_nn *nn;              /* network for HTS_MODE_LEARNED                    */
