@@ -119,6 +119,9 @@ enum Slot {
     S_OBB = 19, S_OTOL2, S_ORR, S_ONORM, S_OINV, S_OSTATUS, S_FSCALE,
     S_CYC = 26,                // 1 if the instance takes part in the current FGMRES cycle
     S_CHEB = 28,               // Chebyshev coefficients: 2 per step, up to 16 steps
+    // learned preconditioner in an inner solve: last ||r||^2 it was applied
+    // to (-1: none yet), consecutive weak iterations, fallback flag, fallbacks
+    S_NN_PREV = 60, S_NN_FAIL, S_NN_FB, S_NN_NFB,
     NSLOT = 64
 };
 

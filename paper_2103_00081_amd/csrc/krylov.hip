@@ -105,6 +105,77 @@ __global__ void k_set_inner_tol(int ninst, const int32_t *active, double *S, dou
     Si[S_STATUS] = 1.0;
 }
 
+// Learned preconditioner: after two consecutive network-preconditioned
+// iterations that each leave ||r_{k+1}||^2 > 0.81 ||r_k||^2 (a residual
+// norm reduction weaker than 0.9), or on a non-finite residual or network
+// output, the instance takes the V-cycle for the rest of the inner solve.
+__global__ void k_nn_gate_init(int ninst, double *S)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    double *Si = S + (int64_t)i * NSLOT;
+    Si[S_NN_PREV] = -1.0;
+    Si[S_NN_FAIL] = 0.0;
+    Si[S_NN_FB] = 0.0;
+    Si[S_NN_NFB] = 0.0;
+}
+
+__global__ void k_nn_gate_begin(int ninst, const int32_t *active, double *S, int32_t *use_nn, int32_t *use_mg,
+                                int32_t *act_save)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    const int32_t act = active[i];
+    act_save[i] = act;
+    if (!act) {
+        use_nn[i] = 0;
+        use_mg[i] = 0;
+        return;
+    }
+    double *Si = S + (int64_t)i * NSLOT;
+    bool fb = Si[S_NN_FB] != 0.0;
+    if (!fb) {
+        const double rr = Si[S_RR], prev = Si[S_NN_PREV];
+        double fails = Si[S_NN_FAIL];
+        if (!isfinite(rr)) {
+            fb = true;
+        } else if (prev >= 0.0 && rr > 0.81 * prev) {
+            fails += 1.0;
+            fb = fails >= 2.0;
+        } else {
+            fails = 0.0;
+        }
+        Si[S_NN_PREV] = rr;
+        Si[S_NN_FAIL] = fails;
+        if (fb) {
+            Si[S_NN_FB] = 1.0;
+            Si[S_NN_NFB] += 1.0;
+        }
+    }
+    use_nn[i] = fb ? 0 : 1;
+    use_mg[i] = fb ? 1 : 0;
+}
+
+__global__ void k_nn_gate_check(int ninst, double *S, int32_t *use_nn, int32_t *use_mg, int32_t *active)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    double *Si = S + (int64_t)i * NSLOT;
+    if (use_nn[i] && !isfinite(Si[S_TMP2])) {
+        Si[S_NN_FB] = 1.0;
+        Si[S_NN_NFB] += 1.0;
+        use_nn[i] = 0;
+        use_mg[i] = 1;
+    }
+    active[i] = use_mg[i];
+}
+
+__global__ void k_nn_gate_end(int ninst, const int32_t *act_save, int32_t *active)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ninst) active[i] = act_save[i];
+}
+
 __global__ void k_convert_plain_df(int64_t n, const double *in, float *out)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -116,6 +187,33 @@ __global__ void k_convert_plain_df(int64_t n, const double *in, float *out)
 void set_inner_tol(int ninst, const int32_t *active, double *S, double floor2, double factor2, hipStream_t s)
 {
     k_set_inner_tol<<<dim3((ninst + 63) / 64), dim3(64), 0, s>>>(ninst, active, S, floor2, factor2);
+    HTS_LAUNCH_CHECK();
+}
+
+static dim3 inst_grid(int ninst) { return dim3((unsigned)((ninst + 63) / 64)); }
+
+void nn_gate_init(int ninst, double *S, hipStream_t s)
+{
+    k_nn_gate_init<<<inst_grid(ninst), dim3(64), 0, s>>>(ninst, S);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_gate_begin(int ninst, const int32_t *active, double *S, int32_t *use_nn, int32_t *use_mg,
+                   int32_t *act_save, hipStream_t s)
+{
+    k_nn_gate_begin<<<inst_grid(ninst), dim3(64), 0, s>>>(ninst, active, S, use_nn, use_mg, act_save);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_gate_check(int ninst, double *S, int32_t *use_nn, int32_t *use_mg, int32_t *active, hipStream_t s)
+{
+    k_nn_gate_check<<<inst_grid(ninst), dim3(64), 0, s>>>(ninst, S, use_nn, use_mg, active);
+    HTS_LAUNCH_CHECK();
+}
+
+void nn_gate_end(int ninst, const int32_t *act_save, int32_t *active, hipStream_t s)
+{
+    k_nn_gate_end<<<inst_grid(ninst), dim3(64), 0, s>>>(ninst, act_save, active);
     HTS_LAUNCH_CHECK();
 }
 

@@ -12,6 +12,7 @@
 // Activations and weights are BF16 (channels-last), accumulation FP32, FP32
 // master weights with Adam.  Stored channel counts are padded to multiples
 // of 8 (input 2 -> 8, output 1 -> 8) with zero weights.
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -75,7 +76,9 @@ struct hts_nn {
     std::map<std::tuple<int, int, int>, std::unique_ptr<hts::NNWork>> work;
     int adam_step = 0;
     double gamma = 1.0;   // target scale: network output * gamma ~ error / rms(residual)
+    hts::DBuf<double> dgamma;   // gamma on the device (read by the preconditioner's output kernel)
     bool gamma_set = false;   // gamma fixed (first train call, or loaded)
+    uint64_t serial = 0;      // unique per network object (keys captured graphs)
     // harvested pairs (all of one node grid); targets of pairs [0, nscaled)
     // are divided by gamma already, later ones are not yet
     hts::Dims dd{};
@@ -267,30 +270,32 @@ static const uint16_t *d_of(const hts_nn *nn, const NNWork &W, int l)
     return l == nn->L - 1 ? e_of(W, l) : W.dsum[l].p;
 }
 
-static void conv(hts_nn *nn, NNWork &W, int k, const uint16_t *X, uint16_t *Ybf, float *Yf, hipStream_t s)
+static void conv(hts_nn *nn, NNWork &W, int k, const uint16_t *X, uint16_t *Ybf, float *Yf, hipStream_t s,
+                 const int32_t *gate = nullptr)
 {
     const NNLayer &Ly = nn->layers[k];
     nn_conv_fwd(X, Ly.cinp, W.d[Ly.lin], Ly.wbf.p, Ly.kp, Ly.b.p, Ly.coutp, W.d[Ly.lout], Ly.stride, Ly.relu, nullptr,
-                Ybf, Yf, Ly.coutp, s);
+                Ybf, Yf, Ly.coutp, s, gate);
 }
 
-// out [n0][8] (FP32, channel 0 meaningful) from x0
-static void forward(hts_nn *nn, NNWork &W, hipStream_t s)
+// out [n0][8] (FP32, channel 0 meaningful) from x0; gate: optional device
+// flag that switches every launch off
+static void forward(hts_nn *nn, NNWork &W, hipStream_t s, const int32_t *gate = nullptr)
 {
     const int L = nn->L;
-    conv(nn, W, 0, W.x0.p, W.y[0].p, nullptr, s);
-    conv(nn, W, 1, W.y[0].p, W.y[1].p, nullptr, s);
+    conv(nn, W, 0, W.x0.p, W.y[0].p, nullptr, s, gate);
+    conv(nn, W, 1, W.y[0].p, W.y[1].p, nullptr, s, gate);
     for (int l = 1; l < L; l++) {
-        conv(nn, W, 2 * l, W.y[2 * l - 1].p, W.y[2 * l].p, nullptr, s);
-        conv(nn, W, 2 * l + 1, W.y[2 * l].p, W.y[2 * l + 1].p, nullptr, s);
+        conv(nn, W, 2 * l, W.y[2 * l - 1].p, W.y[2 * l].p, nullptr, s, gate);
+        conv(nn, W, 2 * l + 1, W.y[2 * l].p, W.y[2 * l + 1].p, nullptr, s, gate);
     }
     for (int l = L - 2; l >= 0; l--) {
         const int k = 3 * L - 2 - l;
-        nn_upsample(d_of(nn, W, l + 1), W.d[l + 1], nn->ch[l + 1], W.up[l].p, W.d[l], s);
-        conv(nn, W, k, W.up[l].p, W.y[k].p, nullptr, s);
-        nn_add_bf16(W.y[k].p, e_of(W, l), W.n[l] * nn->ch[l], W.dsum[l].p, s);
+        nn_upsample(d_of(nn, W, l + 1), W.d[l + 1], nn->ch[l + 1], W.up[l].p, W.d[l], s, gate);
+        conv(nn, W, k, W.up[l].p, W.y[k].p, nullptr, s, gate);
+        nn_add_bf16(W.y[k].p, e_of(W, l), W.n[l] * nn->ch[l], W.dsum[l].p, s, gate);
     }
-    conv(nn, W, 3 * L - 1, W.dsum[0].p, nullptr, W.out.p, s);
+    conv(nn, W, 3 * L - 1, W.dsum[0].p, nullptr, W.out.p, s, gate);
 }
 
 // weight and bias gradients from gy (FP32 [n0][8]); acc = add to the stored ones
@@ -407,18 +412,39 @@ static void ensure_mesh_inputs(hts_mesh *m)
 }
 
 // --------------------------------------------- preconditioner in a solve
+// Network inputs and workspaces of every instance of the batch, so that the
+// preconditioner itself allocates nothing (it may be captured in a graph).
+void nn_prepare(hts_nn *nn, Batch &B)
+{
+    for (int i = 0; i < B.n; i++) {
+        hts_mesh *m = B.m[i];
+        ensure_mesh_inputs(m);
+        (void)workspace(nn, Dims{m->N[0], m->N[1], m->N[2]});
+    }
+}
+
+uint64_t nn_serial(const hts_nn *nn) { return nn->serial; }
+
 // z (instance slice) = gamma rms(r) Net(r / rms(r), feature), zero on
-// Dirichlet rows; rms(r)^2 = S[inst][S_RR] / (free nodes).
-void nn_precondition(hts_nn *nn, Batch &B, int inst, const double *r, double *z)
+// Dirichlet rows; rms(r)^2 = S[inst][S_RR] / (free nodes).  gate: device
+// flag of the instance (0: every launch returns at once, z untouched).
+void nn_precondition(hts_nn *nn, Batch &B, int inst, const double *r, double *z, const int32_t *gate)
 {
     hts_mesh *m = B.m[inst];
     ensure_mesh_inputs(m);
     NNWork &W = workspace(nn, Dims{m->N[0], m->N[1], m->N[2]});
     const int64_t off = B.off[inst], n = m->nnode;
     const double *rr = B.S.p + (int64_t)inst * NSLOT + S_RR;
-    nn_pack_input_dev(r + off, rr, m->nn_nfree, m->nn_feat.p, n, W.x0.p, B.s);
-    forward(nn, W, B.s);
-    nn_unpack_output_dev(W.out.p, 8, rr, m->nn_nfree, nn->gamma, m->nn_mask.p, n, z + off, B.s);
+    nn_pack_input_dev(r + off, rr, m->nn_nfree, m->nn_feat.p, n, W.x0.p, B.s, gate);
+    forward(nn, W, B.s, gate);
+    nn_unpack_output_dev(W.out.p, 8, rr, m->nn_nfree, nn->dgamma.p, m->nn_mask.p, n, z + off, B.s, gate);
+}
+
+// gamma on the host and on the device
+static void set_gamma(hts_nn *nn, double g)
+{
+    nn->gamma = g;
+    nn->dgamma.upload(&nn->al, &nn->gamma, 1, nn->s);
 }
 
 }  // namespace hts
@@ -445,6 +471,9 @@ hts_status hts_nn_create(const hts_nn_desc *desc, hts_nn **out)
         for (int l = 0; l < 4; l++) nn->ch[l] = l < desc->levels ? desc->channels[l] : 0;
         build_layers(nn.get());
         init_params(nn.get());
+        static std::atomic<uint64_t> next_serial{1};
+        nn->serial = next_serial++;
+        set_gamma(nn.get(), 1.0);
         *out = nn.release();
     });
 }
@@ -812,7 +841,7 @@ hts_status hts_nn_train(hts_nn *nn, int32_t epochs, double lr, int32_t batch, in
             for (int64_t i : tr) sc.push_back(nn->pair_scale[i]);
             std::nth_element(sc.begin(), sc.begin() + sc.size() / 2, sc.end());
             const double g = sc[sc.size() / 2];
-            nn->gamma = g > 0.0 && std::isfinite(g) ? g : 1.0;
+            set_gamma(nn, g > 0.0 && std::isfinite(g) ? g : 1.0);
             nn->gamma_set = true;
         }
         if (nn->nscaled < nn->npairs) {
@@ -900,7 +929,7 @@ hts_status hts_nn_load(hts_nn *nn, const char *path)
         // targets already divided by the previous gamma take the loaded one
         if (nn->nscaled > 0 && gamma != nn->gamma)
             nn_scale_bf16(nn->pt.p, nn->nscaled * nn->dd.n(), (float)(nn->gamma / gamma), nn->s);
-        nn->gamma = gamma;
+        set_gamma(nn, gamma);
         nn->gamma_set = true;
         HTS_HIP(hipStreamSynchronize(nn->s));
     });

@@ -60,8 +60,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ X
                                                   const uint16_t *__restrict__ W, int kp,
                                                   const float *__restrict__ bias, int cout, int3 dout, int stride,
                                                   int relu, const uint16_t *__restrict__ skip,
-                                                  uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy)
+                                                  uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy,
+                                                  const int32_t *gate)
 {
+    if (gate && !*gate) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t nout = (int64_t)dout.x * dout.y * dout.z;
     const int64_t vbase = ((int64_t)blockIdx.x * 4 + w) * 16;
@@ -118,8 +120,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd_splitk(const uint16_t *__restr
                                                          const uint16_t *__restrict__ W, int kp,
                                                          const float *__restrict__ bias, int cout, int3 dout,
                                                          int stride, int relu, const uint16_t *__restrict__ skip,
-                                                         uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy)
+                                                         uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy,
+                                                         const int32_t *gate)
 {
+    if (gate && !*gate) return;
     __shared__ f32x4 part[4][NT][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t nout = (int64_t)dout.x * dout.y * dout.z;
@@ -188,8 +192,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(const uint16_t *__restric
                                                        const float *__restrict__ bias, int cout, int relu,
                                                        const uint16_t *__restrict__ skip,
                                                        uint16_t *__restrict__ Ybf, float *__restrict__ Yf, int ldy,
-                                                       int cs, int flip)
+                                                       int cs, int flip, const int32_t *gate)
 {
+    if (gate && !*gate) return;
     extern __shared__ uint4 conv_tile_raw[];
     uint16_t *tile = reinterpret_cast<uint16_t *>(conv_tile_raw);
     const int nbx = (d.x + CT_X - 1) / CT_X, nby = (d.y + CT_Y - 1) / CT_Y;
@@ -497,8 +502,10 @@ __device__ __forceinline__ int up_parents(int i, int nc, int *p, float *wt)
     return 2;
 }
 
-__global__ void k_upsample(const uint16_t *__restrict__ C, int3 dc, int ch, uint16_t *__restrict__ F, int3 df)
+__global__ void k_upsample(const uint16_t *__restrict__ C, int3 dc, int ch, uint16_t *__restrict__ F, int3 df,
+                           const int32_t *gate)
 {
+    if (gate && !*gate) return;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nf = (int64_t)df.x * df.y * df.z;
     if (e >= nf * ch) return;
@@ -520,8 +527,10 @@ __global__ void k_upsample(const uint16_t *__restrict__ C, int3 dc, int ch, uint
 
 // k_upsample for ch a multiple of 8: one thread per fine voxel and group of
 // 8 channels (16-byte loads and stores), parents summed in the same order
-__global__ void k_upsample8(const uint16_t *__restrict__ C, int3 dc, int ch, uint16_t *__restrict__ F, int3 df)
+__global__ void k_upsample8(const uint16_t *__restrict__ C, int3 dc, int ch, uint16_t *__restrict__ F, int3 df,
+                            const int32_t *gate)
 {
+    if (gate && !*gate) return;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nf = (int64_t)df.x * df.y * df.z;
     const int groups = ch / 8;
@@ -700,8 +709,10 @@ __global__ void k_pack_input_bf(const uint16_t *__restrict__ r, const float *__r
 // network input in a solve: channel 0 = r / rms(r) with rms(r)^2 = rr / nfree
 // read from device memory
 __global__ void k_pack_input_dev(const double *__restrict__ r, const double *__restrict__ rr, double nfree,
-                                 const float *__restrict__ feat, int64_t n, uint16_t *__restrict__ X)
+                                 const float *__restrict__ feat, int64_t n, uint16_t *__restrict__ X,
+                                 const int32_t *gate)
 {
+    if (gate && !*gate) return;
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= n) return;
     const double q = *rr;
@@ -714,9 +725,12 @@ __global__ void k_pack_input_dev(const double *__restrict__ r, const double *__r
 
 // z = gamma rms(r) out[v][0], zero where mask
 __global__ void k_unpack_output_dev(const float *__restrict__ Y, int ldy, const double *__restrict__ rr,
-                                    double nfree, double gamma, const uint8_t *__restrict__ mask, int64_t n,
-                                    double *__restrict__ z)
+                                    double nfree, const double *__restrict__ gamma_p,
+                                    const uint8_t *__restrict__ mask, int64_t n, double *__restrict__ z,
+                                    const int32_t *gate)
 {
+    if (gate && !*gate) return;
+    const double gamma = *gamma_p;
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= n) return;
     const double q = *rr;
@@ -728,8 +742,9 @@ __global__ void k_unpack_output_dev(const float *__restrict__ Y, int ldy, const 
 
 // c = bf16(a + b), 8 entries per thread (n a multiple of 8)
 __global__ void k_add_bf16x8(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, int64_t n8,
-                             uint16_t *__restrict__ c)
+                             uint16_t *__restrict__ c, const int32_t *gate)
 {
+    if (gate && !*gate) return;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= n8) return;
     const uint4 qa = reinterpret_cast<const uint4 *>(a)[e], qb = reinterpret_cast<const uint4 *>(b)[e];
@@ -746,8 +761,9 @@ __global__ void k_add_bf16x8(const uint16_t *__restrict__ a, const uint16_t *__r
 
 // c = bf16(a + b)
 __global__ void k_add_bf16(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, int64_t n,
-                           uint16_t *__restrict__ c)
+                           uint16_t *__restrict__ c, const int32_t *gate)
 {
+    if (gate && !*gate) return;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e < n) c[e] = f2bf(bf2f(a[e]) + bf2f(b[e]));
 }
@@ -766,7 +782,7 @@ inline dim3 g256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 // ------------------------------------------------------------- launchers
 void nn_conv_fwd(const uint16_t *X, int cin, Dims din, const uint16_t *W, int kp, const float *bias, int cout,
                  Dims dout, int stride, int relu, const uint16_t *skip, uint16_t *Ybf, float *Yf, int ldy,
-                 hipStream_t s)
+                 hipStream_t s, const int32_t *gate)
 {
     const int64_t nout = dout.n();
     const dim3 g((unsigned)((nout + 63) / 64)), b(256);
@@ -777,10 +793,10 @@ void nn_conv_fwd(const uint16_t *X, int cin, Dims din, const uint16_t *W, int kp
         // four waves of a block
         const dim3 gs((unsigned)((nout + 15) / 16));
         switch (nt) {
-        case 1: k_conv_fwd_splitk<1><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
-        case 2: k_conv_fwd_splitk<2><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
-        case 3: k_conv_fwd_splitk<3><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
-        case 4: k_conv_fwd_splitk<4><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
+        case 1: k_conv_fwd_splitk<1><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
+        case 2: k_conv_fwd_splitk<2><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
+        case 3: k_conv_fwd_splitk<3><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
+        case 4: k_conv_fwd_splitk<4><<<gs, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
         default: throw Error(-7, "at most 64 output channels");
         }
         HTS_LAUNCH_CHECK();
@@ -798,20 +814,20 @@ void nn_conv_fwd(const uint16_t *X, int cin, Dims din, const uint16_t *W, int kp
             const dim3 gt((unsigned)nb);
             const size_t lds = (size_t)CH_V * cs * 2;
             switch (nt) {
-            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
-            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
-            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
-            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0); break;
+            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0, gate); break;
+            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0, gate); break;
+            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0, gate); break;
+            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(X, cin, di, W, kp, bias, cout, relu, skip, Ybf, Yf, ldy, cs, 0, gate); break;
             }
             HTS_LAUNCH_CHECK();
             return;
         }
     }
     switch (nt) {
-    case 1: k_conv_fwd<1><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
-    case 2: k_conv_fwd<2><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
-    case 3: k_conv_fwd<3><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
-    case 4: k_conv_fwd<4><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy); break;
+    case 1: k_conv_fwd<1><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
+    case 2: k_conv_fwd<2><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
+    case 3: k_conv_fwd<3><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
+    case 4: k_conv_fwd<4><<<g, b, 0, s>>>(X, cin, di, W, kp, bias, cout, dn, stride, relu, skip, Ybf, Yf, ldy, gate); break;
     default: throw Error(-7, "at most 64 output channels");
     }
     HTS_LAUNCH_CHECK();
@@ -836,10 +852,10 @@ void nn_conv_bwd_data(const uint16_t *G, int cout, Dims dout, const uint16_t *Wt
             const dim3 gt((unsigned)nb);
             const size_t lds = (size_t)CH_V * cs * 2;
             switch (nt) {
-            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
-            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
-            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
-            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1); break;
+            case 1: k_conv_fwd_tile<1><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1, nullptr); break;
+            case 2: k_conv_fwd_tile<2><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1, nullptr); break;
+            case 3: k_conv_fwd_tile<3><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1, nullptr); break;
+            default: k_conv_fwd_tile<4><<<gt, b, lds, s>>>(G, cout, di, Wt, ktp, nullptr, cin, 0, nullptr, nullptr, GX, cin, cs, 1, nullptr); break;
             }
             HTS_LAUNCH_CHECK();
             return;
@@ -922,13 +938,14 @@ void nn_transpose_w(const uint16_t *W, int cout, int cin, int kp, uint16_t *Wt, 
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-void nn_upsample(const uint16_t *C, Dims dc, int ch, uint16_t *F, Dims df, hipStream_t s)
+void nn_upsample(const uint16_t *C, Dims dc, int ch, uint16_t *F, Dims df, hipStream_t s, const int32_t *gate)
 {
     if (ch % 8 == 0 && aligned16(C) && aligned16(F))
         k_upsample8<<<g256(df.n() * (ch / 8)), dim3(256), 0, s>>>(C, int3{dc.x, dc.y, dc.z}, ch, F,
-                                                                   int3{df.x, df.y, df.z});
+                                                                   int3{df.x, df.y, df.z}, gate);
     else
-        k_upsample<<<g256(df.n() * ch), dim3(256), 0, s>>>(C, int3{dc.x, dc.y, dc.z}, ch, F, int3{df.x, df.y, df.z});
+        k_upsample<<<g256(df.n() * ch), dim3(256), 0, s>>>(C, int3{dc.x, dc.y, dc.z}, ch, F, int3{df.x, df.y, df.z},
+                                                           gate);
     HTS_LAUNCH_CHECK();
 }
 
@@ -987,25 +1004,25 @@ void nn_pack_input_bf(const uint16_t *r, const float *feat, int64_t n, uint16_t 
 }
 
 void nn_pack_input_dev(const double *r, const double *rr, double nfree, const float *feat, int64_t n, uint16_t *X,
-                       hipStream_t s)
+                       hipStream_t s, const int32_t *gate)
 {
-    k_pack_input_dev<<<g256(n), dim3(256), 0, s>>>(r, rr, nfree, feat, n, X);
+    k_pack_input_dev<<<g256(n), dim3(256), 0, s>>>(r, rr, nfree, feat, n, X, gate);
     HTS_LAUNCH_CHECK();
 }
 
-void nn_unpack_output_dev(const float *Y, int ldy, const double *rr, double nfree, double gamma, const uint8_t *mask,
-                          int64_t n, double *z, hipStream_t s)
+void nn_unpack_output_dev(const float *Y, int ldy, const double *rr, double nfree, const double *gamma,
+                          const uint8_t *mask, int64_t n, double *z, hipStream_t s, const int32_t *gate)
 {
-    k_unpack_output_dev<<<g256(n), dim3(256), 0, s>>>(Y, ldy, rr, nfree, gamma, mask, n, z);
+    k_unpack_output_dev<<<g256(n), dim3(256), 0, s>>>(Y, ldy, rr, nfree, gamma, mask, n, z, gate);
     HTS_LAUNCH_CHECK();
 }
 
-void nn_add_bf16(const uint16_t *a, const uint16_t *b, int64_t n, uint16_t *c, hipStream_t s)
+void nn_add_bf16(const uint16_t *a, const uint16_t *b, int64_t n, uint16_t *c, hipStream_t s, const int32_t *gate)
 {
     if (n % 8 == 0 && aligned16(a) && aligned16(b) && aligned16(c))
-        k_add_bf16x8<<<g256(n / 8), dim3(256), 0, s>>>(a, b, n / 8, c);
+        k_add_bf16x8<<<g256(n / 8), dim3(256), 0, s>>>(a, b, n / 8, c, gate);
     else
-        k_add_bf16<<<g256(n), dim3(256), 0, s>>>(a, b, n, c);
+        k_add_bf16<<<g256(n), dim3(256), 0, s>>>(a, b, n, c, gate);
     HTS_LAUNCH_CHECK();
 }
 

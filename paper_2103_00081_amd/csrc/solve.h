@@ -105,6 +105,9 @@ struct Batch {
 
     DBuf<double> S;
     DBuf<int32_t> active;
+    // learned preconditioner: which instances take the network or the
+    // multigrid fallback in the current application, and the solve's flags
+    DBuf<int32_t> nn_use, nn_mg, act_save;
     double *hS = nullptr;
     int32_t *hact = nullptr;      // flags as last exported (coherent pinned)
     double *hexpS = nullptr;      // slots as last exported (coherent pinned)
@@ -165,6 +168,10 @@ struct Batch {
     hipStream_t cap = nullptr;
     bool use_graph = false;
     std::string graph_tag;   // identifies the preconditioner a captured chunk calls
+    // optional: a suffix for the key of the next captured chunk (a
+    // preconditioner whose launch sequence changes between chunks)
+    std::function<std::string()> chunk_mode;
+    int chunk_cap = 0;   // > 0: at most this many CG iterations per captured chunk
     std::map<std::string, int> last_iters;   // iterations of the previous solve per captured system
     int hist_tag = 0;                          // outer refinement step of the current inner solve
     void drop_graphs();
@@ -231,8 +238,12 @@ struct Batch {
 };
 
 std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms);
-// learned preconditioner on one instance's slice: z = gamma rms(r) Net(r / rms(r), feature)
-void nn_precondition(hts_nn *nn, Batch &B, int inst, const double *r, double *z);
+// learned preconditioner on one instance's slice: z = gamma rms(r) Net(r / rms(r), feature);
+// gate: device flag of the instance (0: nothing runs, z untouched)
+void nn_precondition(hts_nn *nn, Batch &B, int inst, const double *r, double *z, const int32_t *gate);
+// network inputs and workspaces of every instance (before graph capture)
+void nn_prepare(hts_nn *nn, Batch &B);
+uint64_t nn_serial(const hts_nn *nn);
 // tuned z-chunk depth of the fine operator kernels (0 = none recorded)
 int tuned_zc(int degree, int field, int NX, int NY, int NZ);
 void set_tuned_zc(int degree, int field, int NX, int NY, int NZ, int zc);

@@ -285,6 +285,9 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->S.alloc(al, (size_t)n * NSLOT);
     B->S.zero(s);
     B->active.alloc(al, n);
+    B->nn_use.alloc(al, n);
+    B->nn_mg.alloc(al, n);
+    B->act_save.alloc(al, n);
     HTS_HIP(hipHostMalloc((void **)&B->hS, sizeof(double) * n * NSLOT, hipHostMallocDefault));
     HTS_HIP(hipHostMalloc((void **)&B->hact, sizeof(int32_t) * n, hipHostMallocCoherent));
     HTS_HIP(hipHostMalloc((void **)&B->hexpS, sizeof(double) * n * NSLOT, hipHostMallocCoherent));
@@ -1240,7 +1243,9 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
         int done = 0;
         while (done < maxit) {
             K = std::max(1, std::min(K, maxit - done));
-            replay(base + "|K" + std::to_string(K), [&] {
+            if (chunk_cap > 0) K = std::min(K, chunk_cap);
+            const std::string mode = chunk_mode ? chunk_mode() : std::string();
+            replay(base + mode + "|K" + std::to_string(K), [&] {
                 VecCtx vg = vctx();
                 for (int c = 0; c < K; c++) {
                     EpiArgs<T> e2{};
@@ -1433,7 +1438,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
     st.fallbacks.assign(n, 0);
     const bool fp32 = o.mode == HTS_MODE_FP32_REFINED;
     const bool learned = o.mode == HTS_MODE_LEARNED && field == 0;
-    use_graph = o.use_graph != 0 && !learned;
+    use_graph = o.use_graph != 0;
     if (learned && !o.nn) throw Error(HTS_ERR_ARG, "learned mode needs opts.nn");
     if (learned && !mg) throw Error(HTS_ERR_STATE, "learned mode needs the multigrid fallback");
     const double rtol = o.rtol > 0 ? o.rtol : 1e-8;
@@ -1501,52 +1506,46 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
             };
             graph_tag = (mg ? "mg" : "cheb") + std::to_string((uintptr_t)(mg ? mg : hprec));
             if (learned) {
-                // Flexible CG with the network as preconditioner.  Fallback:
-                // after two consecutive NN-preconditioned iterations that each
-                // leave ||r_{k+1}|| > 0.9 ||r_k||, or a non-finite residual or
-                // network output, the instance uses the V-cycle for the rest
-                // of this solve.
-                std::vector<double> prev(n, -1.0);
-                std::vector<int> fails(n, 0), fb(n, 0);
+                // Flexible CG with the network as preconditioner; the
+                // fallback rule runs on the device (nn_gate_*: two
+                // consecutive weak iterations or a non-finite residual or
+                // network output send the instance to the V-cycle for the
+                // rest of this inner solve), so an application needs no
+                // host round trip and the loop can be replayed as a graph.
+                nn_prepare(o.nn, *this);
+                nn_gate_init(n, S.p, s);
+                graph_tag = "nn" + std::to_string(nn_serial(o.nn)) + "|" + std::to_string((uintptr_t)mg);
+                // Once every instance still iterating has fallen back (as the
+                // exports between chunks or iterations show), the network's
+                // gated launches are left out: the remaining chunks are plain
+                // V-cycle-preconditioned iterations.
+                const uint32_t seq0 = exp_seq;
+                auto all_fell_back = [&]() {
+                    if (exp_seq == seq0) return false;
+                    for (int i = 0; i < n; i++)
+                        if (hact[i] && hexpS[(size_t)i * NSLOT + S_NN_FB] == 0.0) return false;
+                    return true;
+                };
+                chunk_mode = [&]() { return all_fell_back() ? std::string("|mg") : std::string("|nn"); };
+                // short chunks while the network is in use, so that a
+                // fallback is seen (and its gated launches dropped) soon
+                chunk_cap = 2;
                 auto ML = [&](const double *r_, double *z_) {
-                    download_S();
-                    const std::vector<int32_t> act = get_active();
-                    std::vector<int32_t> use_nn(n, 0), use_mg(n, 0);
-                    bool any_nn = false, any_mg = false;
-                    for (int i = 0; i < n; i++) {
-                        if (!act[i]) continue;
-                        const double rr = hS[(size_t)i * NSLOT + S_RR];
-                        if (!fb[i]) {
-                            if (!std::isfinite(rr)) fb[i] = 1;
-                            else if (prev[i] >= 0.0 && rr > 0.81 * prev[i]) fb[i] = ++fails[i] >= 2;
-                            else fails[i] = 0;
-                            prev[i] = rr;
-                            if (fb[i]) st.fallbacks[i]++;
-                        }
-                        if (fb[i]) use_mg[i] = 1, any_mg = true;
-                        else use_nn[i] = 1, any_nn = true;
-                    }
-                    if (any_nn) {
-                        for (int i = 0; i < n; i++)
-                            if (use_nn[i]) nn_precondition(o.nn, *this, i, r_, z_);
-                        vdot<double>(vctx(), z_, z_, nullptr, partial.p);
-                        vreduce(rch, partial.p, 2, RED_STORE, S_TMP2, S.p, active.p, 0, 0.0, nullptr, s);
-                        download_S();
-                        for (int i = 0; i < n; i++)
-                            if (use_nn[i] && !std::isfinite(hS[(size_t)i * NSLOT + S_TMP2])) {
-                                fb[i] = 1;
-                                st.fallbacks[i]++;
-                                use_mg[i] = 1;
-                                any_mg = true;
-                            }
-                    }
-                    if (any_mg) {
-                        set_active(use_mg);
+                    if (all_fell_back()) {
                         vcycle<double>(*mg, 0, r_, z_);
-                        set_active(act);
+                        return;
                     }
+                    nn_gate_begin(n, active.p, S.p, nn_use.p, nn_mg.p, act_save.p, s);
+                    for (int i = 0; i < n; i++) nn_precondition(o.nn, *this, i, r_, z_, nn_use.p + i);
+                    vdot<double>(vctx(), z_, z_, nullptr, partial.p);
+                    vreduce(rch, partial.p, 2, RED_STORE, S_TMP2, S.p, active.p, 0, 0.0, nullptr, s);
+                    nn_gate_check(n, S.p, nn_use.p, nn_mg.p, active.p, s);
+                    vcycle<double>(*mg, 0, r_, z_);   // the fallback instances only
+                    nn_gate_end(n, act_save.p, active.p, s);
                 };
                 cg<double>(A, ML, inner_b.p, inner_x.p, maxit, true, 1);
+                chunk_mode = nullptr;
+                chunk_cap = 0;
             } else if (field == 0) {
                 cg<double>(A, M, inner_b.p, inner_x.p, maxit, false, o.check_every);
             } else
@@ -1575,6 +1574,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
             if (outer[i]) {
                 st.iters[i] += (int)hS[(size_t)i * NSLOT + S_ITER];
                 total_inner += (int)hS[(size_t)i * NSLOT + S_ITER];
+                if (learned) st.fallbacks[i] += (int)hS[(size_t)i * NSLOT + S_NN_NFB];
                 const double ist = hS[(size_t)i * NSLOT + S_STATUS];
                 if (ist == -6.0) st.status[i] = -6;
             }

@@ -298,6 +298,29 @@ def test_learned_gain_over_multigrid(hts, trained):
     assert it64 <= itL <= 4 * it64
 
 
+def test_learned_graph_replay_equals_eager(hts, trained):
+    """The learned preconditioner's fallback rule runs on the device, so the
+    learned flexible CG replays as captured graphs: graph replay and eager
+    launches give the same pressure and temperature bit for bit, the same
+    iteration counts and the same fallbacks, over three steps (the first
+    replays capture, the later ones reuse the graphs)."""
+    net, _ = trained
+    seed = 5100
+    print_case("learned graph vs eager", seed)
+    og = hts.default_opts(rtol=1e-8, mode=hts.MODE_LEARNED, use_graph=1)
+    og.nn = net.h.value
+    oe = hts.default_opts(rtol=1e-8, mode=hts.MODE_LEARNED, use_graph=0)
+    oe.nn = net.h.value
+    mg, me = mesh_of(hts, seed, og), mesh_of(hts, seed, oe)
+    for _ in range(3):
+        cg_, sg = mg.solve_step(synth.DAY, og)
+        ce, se = me.solve_step(synth.DAY, oe)
+        assert cg_ == 0 and ce == 0
+        assert sg["iters"] == se["iters"] and sg["fallbacks"] == se["fallbacks"]
+    for f in (0, 1):
+        assert np.array_equal(mg.get_state(f)[0], me.get_state(f)[0])
+
+
 def test_sabotaged_network_falls_back(hts):
     """Random weights give directions that do not reduce the residual: the
     solve switches to the V-cycle and still meets the FP64 residual."""
