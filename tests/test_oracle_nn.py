@@ -186,3 +186,43 @@ def test_adam_second_step_by_hand():
     np.testing.assert_allclose(th, [exp0, exp1], rtol=1e-14)
     np.testing.assert_allclose(m, [-0.01, 0.18], rtol=1e-13)
     np.testing.assert_allclose(v, [0.001999, 0.003996], rtol=1e-13)
+
+
+def test_network_gradient_check_detects_wiring_errors():
+    """The GPU network's gradients are judged per layer against 3x the
+    oracle's own sensitivity to sub-FP32 perturbations before each BF16
+    rounding (nn_cases.sensitivity).  That tolerance must still catch a
+    wrongly wired network: taps flipped in one layer (convolution instead of
+    cross-correlation), the two input channels swapped, or the input mirrored
+    along x each move the output by more than 0.1 relative and some layer's
+    weight gradient by more than 0.3, and by more than 3x the sensitivity."""
+    import nn_cases
+    dims = (29, 22, 19)
+    theta, inp, tgt, mask = nn_cases.net_case(11, dims)
+    y0, _, g0 = nn_cases.oracle_grads(theta, inp, tgt, mask)
+    sens = nn_cases.sensitivity(theta, inp, tgt, mask, g0)
+    assert max(sens.values()) < 0.1
+    specs = nnet.layer_specs(nn_cases.LEVELS, nn_cases.CH)
+
+    def flipped(layer):
+        th, o = theta.copy(), 0
+        for name, ci, co, s, relu in specs:
+            nw = co * ci * 27
+            if name == layer:
+                th[o:o + nw] = th[o:o + nw].reshape(co, ci, 3, 3, 3)[:, :, ::-1, ::-1, ::-1].ravel()
+            o += nw + co
+        return th
+
+    planted = {
+        "taps flipped in enc1": (flipped("enc1"), inp),
+        "taps flipped in dec1": (flipped("dec1"), inp),
+        "input channels swapped": (theta, inp[::-1].copy()),
+        "input mirrored along x": (theta, inp[:, :, :, ::-1].copy()),
+    }
+    for what, (th, x) in planted.items():
+        y1, _, g1 = nn_cases.oracle_grads(th, x, tgt, mask)
+        dev = dict(nn_cases.layer_rel(g1, g0))
+        caught = [k for k in dev if dev[k] > 0.3 and dev[k] > 3 * sens[k]]
+        print(what, "output", np.linalg.norm(y1 - y0) / np.linalg.norm(y0), "layers caught", caught)
+        assert np.linalg.norm(y1 - y0) > 0.1 * np.linalg.norm(y0), what
+        assert caught, what
