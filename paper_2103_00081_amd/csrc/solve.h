@@ -206,7 +206,8 @@ struct Batch {
     template <typename T> void apply_op(const Tables &t, int epi, bool masked, const T *x, T *y, EpiArgs<T> ep);
 
     void estimate_lmax(Hier &H, int l, std::vector<double> &lmax);
-    void build_smoother(Hier &H, int l, int steps, double ratio);
+    // given: lmax(D^-1 A) per instance (else estimated by power iteration)
+    void build_smoother(Hier &H, int l, int steps, double ratio, const std::vector<double> *given = nullptr);
     void build_hierarchy(Hier &H, const hts_solver_opts &o);
     Hier &pressure_hier(bool steady, double dt, const hts_solver_opts &o);
     Hier &heat_prec(double dt, const hts_solver_opts &o);

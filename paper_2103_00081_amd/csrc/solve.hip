@@ -687,11 +687,12 @@ static void level_alloc(Level &L, Alloc *al, hipStream_t s, int64_t ntot)
     for (DBuf<float> *v : {&L.x32, &L.xb32, &L.b32, &L.d32, &L.t32, &L.invd32}) { v->alloc(al, m); v->zero(s); }
 }
 
-void Batch::build_smoother(Hier &H, int l, int steps, double ratio)
+void Batch::build_smoother(Hier &H, int l, int steps, double ratio, const std::vector<double> *given)
 {
     Level &L = H.lev[l];
     std::vector<double> lm;
-    estimate_lmax(H, l, lm);
+    if (given) lm = *given;
+    else estimate_lmax(H, l, lm);
     std::vector<double> c((size_t)n * NSLOT, 0.0);
     static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 0.0;
     for (int i = 0; i < n; i++) {
@@ -877,10 +878,12 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     H.ratio_coarse = env_or("HTS_HEAT_RATIO_COARSE", 15.0);
     make_tables(H.ops, 1, dt, false, false);
     // The Chebyshev intervals are estimated on the symmetric part (mass,
-    // conduction, injection line): they depend on the mesh, the coefficients
-    // and dt only, not on the Darcy flux of the step in which the
-    // preconditioner happens to be built, so a run resumed from a saved state
-    // applies the same preconditioner as the uninterrupted one.
+    // conduction, injection line) wherever convection does not widen the
+    // spectrum much: they then depend on the mesh, the coefficients and dt
+    // only, not on the Darcy flux of the step in which the preconditioner
+    // happens to be built, so a run resumed from a saved state applies the
+    // same preconditioner as the uninterrupted one (convection-dominated
+    // instances take the full operator's estimate, below).
     auto advection = [&](bool on) {
         for (int i = 0; i < n; i++) {
             H.ops.h64[i].cadv = on ? cadv_save[i] : 0.0;
@@ -914,9 +917,27 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     }
     for (int i = 0; i < n; i++) launch_inv_diag(H.ops.h64[i], L.invd64.p + off[i], s);
     convert_plain(ntot, L.invd64.p, L.invd32.p, s);
+    // Where the Darcy flux does not move the largest eigenvalue of D^-1 A by
+    // more than 25 % (conduction-dominated transport), the interval comes
+    // from the symmetric part alone, so that it does not depend on the step
+    // in which the preconditioner is built.  Where it does (convection-
+    // dominated, e.g. next to an injection well), the convection term's
+    // imaginary spectrum makes the symmetric interval far too narrow and
+    // the preconditioned iteration stagnates: the full operator's estimate
+    // (with the flux of the build step) is used instead.
+    std::vector<double> lsym, lfull, lm(n);
     advection(false);
-    build_smoother(H, 0, H.deg, H.ratio);
+    estimate_lmax(H, 0, lsym);
     advection(true);
+    estimate_lmax(H, 0, lfull);
+    static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 0.0;
+    for (int i = 0; i < n; i++) {
+        lm[i] = lfull[i] > 1.25 * lsym[i] ? lfull[i] : lsym[i];
+        if (verbose)
+            std::fprintf(stderr, "[hts] heat Chebyshev instance %d: lmax symmetric %.6g, with convection %.6g\n", i,
+                         lsym[i], lfull[i]);
+    }
+    build_smoother(H, 0, H.deg, H.ratio, &lm);
     return H;
 }
 

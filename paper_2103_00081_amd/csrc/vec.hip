@@ -126,58 +126,118 @@ __global__ __launch_bounds__(VB) void k_cg_update(const Chunk *__restrict__ chun
 }
 
 // GMRES: multi-dot h_i = V_i . w for i < nv (V_i = V + i*ld)
-template <typename T>
+// Sums over the block of NC per-thread values at once (component c in
+// a[c], c < nc): each wave reduces by shuffles, then thread c adds the four
+// wave sums in wave order and writes out[c].  Fixed order: deterministic.
+template <int NC>
+__device__ __forceinline__ void block_multi_sum(const double (&a)[NC], int nc, double (*sh)[NC], double *out)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        if (c < nc) {
+            const double v = wave_sum(a[c]);
+            if (lane == 0) sh[w][c] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+        const int c = threadIdx.x;
+        out[c] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+    }
+}
+
+// Partials of V_i . w (i < nv) in one pass over the chunk: every thread
+// keeps nv running sums (NB >= nv, compile-time bucket).
+template <typename T, int NB>
 __global__ __launch_bounds__(VB) void k_multidot(const Chunk *__restrict__ chunks, const int32_t *active,
                                                  const double *S, const T *__restrict__ V, int64_t ld,
                                                  int nv, const T *__restrict__ w, double *partial,
                                                  int ncomp)
 {
-    __shared__ double sh[4];
+    __shared__ double sh[4][NB];
     CHUNK_PROLOGUE
-    for (int i = 0; i < nv; i++) {
-        const T *Vi = V + (int64_t)i * ld;
-        double a = 0.0;
-        for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) a += (double)Vi[e] * (double)w[e];
-        a = block_sum(a, sh);
-        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncomp + i] = a;
+    double a[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) a[i] = 0.0;
+    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        const double we = (double)w[e];
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < nv) a[i] += (double)V[(int64_t)i * ld + e] * we;
     }
+    block_multi_sum<NB>(a, nv, sh, partial + (int64_t)blockIdx.x * ncomp);
 }
 
 // GMRES: w -= sum_i h_i V_i (h per instance: H + inst*hld), then partials of
-// V_i . w (i < nv, if dots) and w . w (component nv, or 0 without dots).
-template <typename T>
+// V_i . w (i < nv, if dots) and w . w (component nv, or 0 without dots),
+// taken on the stored (type T) values of the new w in the same pass.
+template <typename T, int NB>
 __global__ __launch_bounds__(VB) void k_orth_update(const Chunk *__restrict__ chunks, const int32_t *active,
                                                     const double *S, const T *__restrict__ V, int64_t ld,
                                                     int nv, const double *__restrict__ H, int hld,
                                                     T *__restrict__ w, int dots, double *partial,
                                                     int ncomp, int scale_slot)
 {
-    __shared__ double sh[4];
-    __shared__ double hs[64];
+    __shared__ double sh[4][NB + 1];
+    __shared__ double hs[NB];
     CHUNK_PROLOGUE
     if (threadIdx.x < nv) hs[threadIdx.x] = H[(int64_t)ch.inst * hld + threadIdx.x];
     __syncthreads();
     const double sc = scale_slot >= 0 ? Si[scale_slot] : 1.0;
+    double a[NB], aw = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; i++) a[i] = 0.0;
+    const bool sums = partial != nullptr;
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+        double v[NB];
         double acc = (double)w[e];
-        for (int i = 0; i < nv; i++) acc -= hs[i] * (double)V[(int64_t)i * ld + e];
-        w[e] = T(scale_slot >= 0 ? acc * sc : acc);
-    }
-    if (!partial) return;
-    __syncthreads();
-    if (dots) {
-        for (int i = 0; i < nv; i++) {
-            const T *Vi = V + (int64_t)i * ld;
-            double a = 0.0;
-            for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) a += (double)Vi[e] * (double)w[e];
-            a = block_sum(a, sh);
-            if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncomp + i] = a;
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            if (i < nv) {
+                v[i] = (double)V[(int64_t)i * ld + e];
+                acc -= hs[i] * v[i];
+            }
+        const T wn = T(scale_slot >= 0 ? acc * sc : acc);
+        w[e] = wn;
+        if (sums) {
+            const double wd = (double)wn;
+            if (dots) {
+                // long bases read V again (cache hits) rather than hold it
+                if constexpr (NB > 24) asm volatile("" ::: "memory");
+#pragma unroll
+                for (int i = 0; i < NB; i++)
+                    if (i < nv) a[i] += (NB > 24 ? (double)V[(int64_t)i * ld + e] : v[i]) * wd;
+            }
+            aw += wd * wd;
         }
     }
-    double a = 0.0;
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) a += (double)w[e] * (double)w[e];
-    a = block_sum(a, sh);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncomp + (dots ? nv : 0)] = a;
+    if (!sums) return;
+    // components: the nv dots (if dots), then w . w; wave sums into sh[w][c]
+    // (w . w at column NB), then thread c adds the four waves in order
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (dots) {
+#pragma unroll
+        for (int c = 0; c < NB; c++)
+            if (c < nv) {
+                const double r = wave_sum(a[c]);
+                if (lane == 0) sh[wv][c] = r;
+            }
+    }
+    {
+        const double r = wave_sum(aw);
+        if (lane == 0) sh[wv][NB] = r;
+    }
+    __syncthreads();
+    const int nd = dots ? nv : 0;
+    double *out = partial + (int64_t)blockIdx.x * ncomp;
+    if ((int)threadIdx.x < nd) {
+        const int c = threadIdx.x;
+        out[c] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+    } else if ((int)threadIdx.x == nd) {
+        out[nd] = (sh[0][NB] + sh[1][NB]) + (sh[2][NB] + sh[3][NB]);
+    }
 }
 
 // x += sum_{i < kdim[inst]} y_i Z_i   (y per instance: Y + inst*yld)
@@ -477,7 +537,17 @@ void vcg_update(const VecCtx &v, T *x, T *r, const T *p, const T *q, T *r_old, d
 template <typename T>
 void vmultidot(const VecCtx &v, const T *V, int64_t ld, int nv, const T *w, double *partial, int ncomp)
 {
-    k_multidot<T><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, w, partial, ncomp);
+    if (nv < 1 || nv > 64) throw Error(-1, "vmultidot: 1..64 vectors");
+#define HTS_MDOT(NB) k_multidot<T, NB><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, w, partial, ncomp)
+    if (nv <= 4) HTS_MDOT(4);
+    else if (nv <= 8) HTS_MDOT(8);
+    else if (nv <= 12) HTS_MDOT(12);
+    else if (nv <= 16) HTS_MDOT(16);
+    else if (nv <= 24) HTS_MDOT(24);
+    else if (nv <= 32) HTS_MDOT(32);
+    else if (nv <= 48) HTS_MDOT(48);
+    else HTS_MDOT(64);
+#undef HTS_MDOT
     HTS_LAUNCH_CHECK();
 }
 template <typename T>
@@ -485,7 +555,17 @@ void vorth_update(const VecCtx &v, const T *V, int64_t ld, int nv, const double 
                   double *partial, int ncomp, int scale_slot)
 {
     if (scale_slot >= 0 && partial) throw Error(-1, "vorth_update: scaling takes no partial sums");
-    k_orth_update<T><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, H, hld, w, dots, partial, ncomp, scale_slot);
+    if (nv < 1 || nv > 64) throw Error(-1, "vorth_update: 1..64 vectors");
+#define HTS_ORTH(NB) k_orth_update<T, NB><<<GRID>>>(v.chunks, v.active, v.S, V, ld, nv, H, hld, w, dots, partial, ncomp, scale_slot)
+    if (nv <= 4) HTS_ORTH(4);
+    else if (nv <= 8) HTS_ORTH(8);
+    else if (nv <= 12) HTS_ORTH(12);
+    else if (nv <= 16) HTS_ORTH(16);
+    else if (nv <= 24) HTS_ORTH(24);
+    else if (nv <= 32) HTS_ORTH(32);
+    else if (nv <= 48) HTS_ORTH(48);
+    else HTS_ORTH(64);
+#undef HTS_ORTH
     HTS_LAUNCH_CHECK();
 }
 template <typename T, typename TX>
