@@ -55,7 +55,8 @@ LINE_HEAT, LINE_WELL = 0, 1
 
 class _Mesh(C.Structure):
     _fields_ = [("x0", C.c_double * 3), ("L", C.c_double * 3),
-                ("n", C.c_int32 * 3), ("p", C.c_int32), ("edges", C.c_void_p * 3)]
+                ("n", C.c_int32 * 3), ("p", C.c_int32), ("edges", C.c_void_p * 3),
+                ("xyz", C.c_void_p)]
 
 
 class _Op(C.Structure):
@@ -121,12 +122,16 @@ def _f64(a) -> np.ndarray:
 class Mesh:
     """Box mesh of degree p: uniform, or rectilinear (graded) when edges
     gives the cell-edge coordinates of every axis (n[d] + 1 increasing values
-    from x0[d] to x0[d] + L[d])."""
+    from x0[d] to x0[d] + L[d]), or general hexahedra of the box topology when
+    xyz gives the coordinates of every node ([nnode][3], x fastest): the
+    isoparametric map of each cell (Section 3.3 meshes the site with
+    hexahedra refined around the piles, Fig. 10b)."""
     x0: Tuple[float, float, float]
     L: Tuple[float, float, float]
     n: Tuple[int, int, int]
     p: int
     edges: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = field(default=None, compare=False)
+    xyz: Optional[np.ndarray] = field(default=None, compare=False)
 
     def __post_init__(self):
         if self.edges is not None:
@@ -134,11 +139,15 @@ class Mesh:
             for d in range(3):
                 e = self.edges[d]
                 assert e.size == self.n[d] + 1 and np.all(np.diff(e) > 0)
+        if self.xyz is not None:
+            assert self.edges is None, "general hexahedra take node coordinates, not edges"
+            self.xyz = np.ascontiguousarray(self.xyz, dtype=np.float64).reshape(-1, 3)
+            assert self.xyz.shape[0] == self.nnode
 
     @classmethod
     def of(cls, scn) -> "Mesh":
         return cls(tuple(scn.origin), tuple(scn.extent), tuple(scn.ncells), scn.degree,
-                   getattr(scn, "edges", None))
+                   getattr(scn, "edges", None), getattr(scn, "coords", None))
 
     def c(self) -> _Mesh:
         m = _Mesh()
@@ -148,6 +157,7 @@ class Mesh:
             m.n[d] = self.n[d]
             m.edges[d] = None if self.edges is None else self.edges[d].ctypes.data
         m.p = self.p
+        m.xyz = None if self.xyz is None else self.xyz.ctypes.data
         return m
 
     def axis_nodes(self, d: int) -> np.ndarray:
@@ -178,6 +188,8 @@ class Mesh:
 
     def coords(self):
         """Node coordinates (x, y, z), each of length nnode."""
+        if self.xyz is not None:
+            return self.xyz[:, 0].copy(), self.xyz[:, 1].copy(), self.xyz[:, 2].copy()
         ax = [self.axis_nodes(d) for d in range(3)]
         Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
         return X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
@@ -270,7 +282,13 @@ def load_face(m: Mesh, face: int, value: float) -> np.ndarray:
     return out
 
 
+def _box_only(m: Mesh, what: str):
+    if m.xyz is not None:
+        raise NotImplementedError(what + " needs box geometry (vertical node columns)")
+
+
 def load_line(m: Mesh, x, y, z0, z1, value) -> np.ndarray:
+    _box_only(m, "a line source")
     out = np.zeros(m.nnode)
     mc = m.c()
     lib().orc_load_line(C.byref(mc), float(x), float(y), float(z0), float(z1), float(value),
@@ -279,6 +297,7 @@ def load_line(m: Mesh, x, y, z0, z1, value) -> np.ndarray:
 
 
 def line_mass(m: Mesh, x, y, z0, z1, coef) -> sp.csr_matrix:
+    _box_only(m, "a line source")
     nl = (m.p + 1) ** 3
     cap = m.n[2] * nl * nl
     ri = np.zeros(cap, dtype=np.int64)
@@ -419,6 +438,7 @@ def dirichlet(scn, m: Mesh, field: int, t: float):
     for col in scn.dir_columns:
         if col.field != field:
             continue
+        _box_only(m, "a Dirichlet column")
         ci = nearest(0, col.x, NX)
         cj = nearest(1, col.y, NY)
         tol = 1e-9 * m.L[2]

@@ -8,8 +8,11 @@
  *
  * What it computes (plain definitions, no blocking or fusion):
  *   - tensor-product Lagrange Q_p elements (p = 1, 2) with equispaced nodes on
- *     a uniform box mesh, Gauss-Legendre quadrature with (p+1) points per
- *     direction unless the caller asks for more;
+ *     a box mesh (uniform or rectilinear) or, given the coordinates of every
+ *     node, on general hexahedra of the box topology (isoparametric map with
+ *     the same basis: x(xi) = sum_a x_a N_a(xi), gradients through the
+ *     inverse Jacobian, volume element |det J|), Gauss-Legendre quadrature
+ *     with (p+1) points per direction unless the caller asks for more;
  *   - element matrices of the bilinear form
  *         a(v,u) = m_c (v,u) + s_c (grad v, grad u) + (v, beta . grad u)
  *     where beta = adv_scale * q_h and q_h = -k_c (grad P_h + rho_w g e_z) is
@@ -41,6 +44,9 @@ typedef struct {
     /* Rectilinear (graded) meshes: cell-edge coordinates per axis, n[d] + 1
      * increasing values from x0[d] to x0[d] + L[d]; NULL = uniform spacing. */
     const double *edges[3];
+    /* General hexahedra: coordinates of every node, [node][3] (node index
+     * i + NX (j + NY k)); NULL = box geometry from x0, L and edges. */
+    const double *xyz;
 } orc_mesh;
 
 typedef struct {
@@ -195,10 +201,66 @@ static inline int64_t gnode(const orc_mesh *m, int cx, int cy, int cz, int ax, i
     return (int64_t)(p * cx + ax) + NX * ((int64_t)(p * cy + ay) + NY * (int64_t)(p * cz + az));
 }
 
+/* Shape functions N[a] and physical gradients G[a][d] of the nl local basis
+ * functions of cell (cx,cy,cz) at the reference point whose 1D basis values
+ * and derivatives along x, y, z are bx, dx, by, dy, bz, dz; returns the
+ * volume element det J (> 0 for a valid cell).  Box cells map each axis
+ * affinely (J = diag(h)); general hexahedra use the isoparametric map,
+ * J_ij = d x_i / d xi_j = sum_a x_a,i dN_a/dxi_j, and grad N_a = J^-T
+ * grad_xi N_a. */
+static double cell_geometry(const orc_mesh *m, int cx, int cy, int cz, const double *bx, const double *dx,
+                            const double *by, const double *dy, const double *bz, const double *dz,
+                            double *N, double (*G)[3])
+{
+    int p = m->p, n1 = p + 1;
+    double R[MAXNL][3];
+    for (int az = 0; az < n1; az++)
+        for (int ay = 0; ay < n1; ay++)
+            for (int ax = 0; ax < n1; ax++) {
+                int a = ax + n1 * (ay + n1 * az);
+                N[a] = bx[ax] * by[ay] * bz[az];
+                R[a][0] = dx[ax] * by[ay] * bz[az];
+                R[a][1] = bx[ax] * dy[ay] * bz[az];
+                R[a][2] = bx[ax] * by[ay] * dz[az];
+            }
+    int nl = n1 * n1 * n1;
+    if (!m->xyz) {
+        double h[3] = {cell_h(m, 0, cx), cell_h(m, 1, cy), cell_h(m, 2, cz)};
+        for (int a = 0; a < nl; a++)
+            for (int d = 0; d < 3; d++) G[a][d] = R[a][d] / h[d];
+        return h[0] * h[1] * h[2];
+    }
+    double J[3][3] = {{0.0}};
+    for (int az = 0; az < n1; az++)
+        for (int ay = 0; ay < n1; ay++)
+            for (int ax = 0; ax < n1; ax++) {
+                int a = ax + n1 * (ay + n1 * az);
+                const double *X = m->xyz + 3 * gnode(m, cx, cy, cz, ax, ay, az);
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) J[i][j] += X[i] * R[a][j];
+            }
+    /* inverse by cofactors: Jinv = adj(J) / det J */
+    double C[3][3];
+    C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    /* (J^-1)_{ji} = C_ij / det, so (J^-T grad_xi N)_i = sum_j C_ij R_j / det */
+    for (int a = 0; a < nl; a++)
+        for (int i = 0; i < 3; i++)
+            G[a][i] = (C[i][0] * R[a][0] + C[i][1] * R[a][1] + C[i][2] * R[a][2]) / det;
+    return det;
+}
+
 void orc_element_matrix(const orc_mesh *m, const orc_op *op, int cx, int cy, int cz, double *Ae)
 {
     int p = m->p, n1 = p + 1, nl = n1 * n1 * n1, nq = op->nq;
-    double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
     int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
@@ -216,17 +278,9 @@ void orc_element_matrix(const orc_mesh *m, const orc_op *op, int cx, int cy, int
     for (int qz = 0; qz < nq; qz++)
         for (int qy = 0; qy < nq; qy++)
             for (int qx = 0; qx < nq; qx++) {
-                double w = gw[qx] * gw[qy] * gw[qz] * hx * hy * hz;
                 double N[MAXNL], G[MAXNL][3];
-                for (int az = 0; az < n1; az++)
-                    for (int ay = 0; ay < n1; ay++)
-                        for (int ax = 0; ax < n1; ax++) {
-                            int a = ax + n1 * (ay + n1 * az);
-                            N[a] = B[qx][ax] * B[qy][ay] * B[qz][az];
-                            G[a][0] = D[qx][ax] / hx * B[qy][ay] * B[qz][az];
-                            G[a][1] = B[qx][ax] * D[qy][ay] / hy * B[qz][az];
-                            G[a][2] = B[qx][ax] * B[qy][ay] * D[qz][az] / hz;
-                        }
+                double detj = cell_geometry(m, cx, cy, cz, B[qx], D[qx], B[qy], D[qy], B[qz], D[qz], N, G);
+                double w = gw[qx] * gw[qy] * gw[qz] * detj;
                 double beta[3] = {0.0, 0.0, 0.0};
                 if (adv) {
                     double gp[3] = {0.0, 0.0, 0.0};
@@ -354,7 +408,7 @@ void orc_apply_rows_abs(const orc_mesh *m, const orc_op *op, const double *x, co
  * every cell (cell-major, then qx fastest). */
 void orc_load_qp(const orc_mesh *m, int nq, const double *fq, double *out)
 {
-    int p = m->p, n1 = p + 1;
+    int p = m->p, n1 = p + 1, nl = n1 * n1 * n1;
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     double B[MAXQ][3], D[MAXQ][3];
@@ -364,27 +418,26 @@ void orc_load_qp(const orc_mesh *m, int nq, const double *fq, double *out)
         for (int cy = 0; cy < m->n[1]; cy++)
             for (int cx = 0; cx < m->n[0]; cx++) {
                 int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
-                double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
+                double s[MAXNL] = {0.0};
+                for (int qz = 0; qz < nq; qz++)
+                    for (int qy = 0; qy < nq; qy++)
+                        for (int qx = 0; qx < nq; qx++) {
+                            double N[MAXNL], G[MAXNL][3];
+                            double detj = cell_geometry(m, cx, cy, cz, B[qx], D[qx], B[qy], D[qy], B[qz], D[qz], N, G);
+                            double w = gw[qx] * gw[qy] * gw[qz] * detj * fq[c * nq3 + qx + nq * (qy + nq * qz)];
+                            for (int a = 0; a < nl; a++) s[a] += w * N[a];
+                        }
                 for (int az = 0; az < n1; az++)
                     for (int ay = 0; ay < n1; ay++)
-                        for (int ax = 0; ax < n1; ax++) {
-                            double s = 0.0;
-                            for (int qz = 0; qz < nq; qz++)
-                                for (int qy = 0; qy < nq; qy++)
-                                    for (int qx = 0; qx < nq; qx++) {
-                                        double w = gw[qx] * gw[qy] * gw[qz] * hx * hy * hz;
-                                        s += w * B[qx][ax] * B[qy][ay] * B[qz][az] *
-                                             fq[c * nq3 + qx + nq * (qy + nq * qz)];
-                                    }
-                            out[gnode(m, cx, cy, cz, ax, ay, az)] += s;
-                        }
+                        for (int ax = 0; ax < n1; ax++)
+                            out[gnode(m, cx, cy, cz, ax, ay, az)] += s[ax + n1 * (ay + n1 * az)];
             }
 }
 
 /* out_a += sum_cells g_c int dN_a/dz dV  (cellwise-constant g). */
 void orc_load_gradz(const orc_mesh *m, const double *g, int nq, double *out)
 {
-    int p = m->p, n1 = p + 1;
+    int p = m->p, n1 = p + 1, nl = n1 * n1 * n1;
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     double B[MAXQ][3], D[MAXQ][3];
@@ -393,23 +446,24 @@ void orc_load_gradz(const orc_mesh *m, const double *g, int nq, double *out)
         for (int cy = 0; cy < m->n[1]; cy++)
             for (int cx = 0; cx < m->n[0]; cx++) {
                 int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
-                double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
+                double s[MAXNL] = {0.0};
+                for (int qz = 0; qz < nq; qz++)
+                    for (int qy = 0; qy < nq; qy++)
+                        for (int qx = 0; qx < nq; qx++) {
+                            double N[MAXNL], G[MAXNL][3];
+                            double detj = cell_geometry(m, cx, cy, cz, B[qx], D[qx], B[qy], D[qy], B[qz], D[qz], N, G);
+                            double w = gw[qx] * gw[qy] * gw[qz] * detj;
+                            for (int a = 0; a < nl; a++) s[a] += w * G[a][2];
+                        }
                 for (int az = 0; az < n1; az++)
                     for (int ay = 0; ay < n1; ay++)
-                        for (int ax = 0; ax < n1; ax++) {
-                            double s = 0.0;
-                            for (int qz = 0; qz < nq; qz++)
-                                for (int qy = 0; qy < nq; qy++)
-                                    for (int qx = 0; qx < nq; qx++) {
-                                        double w = gw[qx] * gw[qy] * gw[qz] * hx * hy * hz;
-                                        s += w * B[qx][ax] * B[qy][ay] * D[qz][az] / hz;
-                                    }
-                            out[gnode(m, cx, cy, cz, ax, ay, az)] += g[c] * s;
-                        }
+                        for (int ax = 0; ax < n1; ax++)
+                            out[gnode(m, cx, cy, cz, ax, ay, az)] += g[c] * s[ax + n1 * (ay + n1 * az)];
             }
 }
 
-/* out_a += value * int_face N_a dA over boundary face f (0..5 = x-,x+,y-,y+,z-,z+). */
+/* out_a += value * int_face N_a dA over boundary face f (0..5 = x-,x+,y-,y+,z-,z+).
+ * General hexahedra: dA = |dx/dxi_1 x dx/dxi_2| dxi_1 dxi_2 on the face. */
 void orc_load_face(const orc_mesh *m, int face, double value, int nq, double *out)
 {
     int p = m->p, n1 = p + 1;
@@ -422,20 +476,42 @@ void orc_load_face(const orc_mesh *m, int face, double value, int nq, double *ou
     int cn = side ? m->n[dn] - 1 : 0;
     int an = side ? p : 0;
     for (int c2 = 0; c2 < m->n[d2]; c2++)
-        for (int c1 = 0; c1 < m->n[d1]; c1++)
+        for (int c1 = 0; c1 < m->n[d1]; c1++) {
+            int cc[3];
+            cc[dn] = cn; cc[d1] = c1; cc[d2] = c2;
             for (int a2 = 0; a2 < n1; a2++)
                 for (int a1 = 0; a1 < n1; a1++) {
-                    double h1 = cell_h(m, d1, c1), h2 = cell_h(m, d2, c2);
                     double s = 0.0;
                     for (int q2 = 0; q2 < nq; q2++)
-                        for (int q1 = 0; q1 < nq; q1++)
-                            s += gw[q1] * gw[q2] * h1 * h2 * B[q1][a1] * B[q2][a2];
-                    int cc[3], aa[3];
-                    cc[dn] = cn; aa[dn] = an;
-                    cc[d1] = c1; aa[d1] = a1;
-                    cc[d2] = c2; aa[d2] = a2;
+                        for (int q1 = 0; q1 < nq; q1++) {
+                            double da;
+                            if (!m->xyz) {
+                                da = cell_h(m, d1, c1) * cell_h(m, d2, c2);
+                            } else {
+                                /* tangents of the face's isoparametric map */
+                                double t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
+                                for (int b2 = 0; b2 < n1; b2++)
+                                    for (int b1 = 0; b1 < n1; b1++) {
+                                        int aa[3];
+                                        aa[dn] = an; aa[d1] = b1; aa[d2] = b2;
+                                        const double *X = m->xyz + 3 * gnode(m, cc[0], cc[1], cc[2], aa[0], aa[1], aa[2]);
+                                        for (int i = 0; i < 3; i++) {
+                                            t1[i] += X[i] * D[q1][b1] * B[q2][b2];
+                                            t2[i] += X[i] * B[q1][b1] * D[q2][b2];
+                                        }
+                                    }
+                                double nx = t1[1] * t2[2] - t1[2] * t2[1];
+                                double ny = t1[2] * t2[0] - t1[0] * t2[2];
+                                double nz = t1[0] * t2[1] - t1[1] * t2[0];
+                                da = sqrt(nx * nx + ny * ny + nz * nz);
+                            }
+                            s += gw[q1] * gw[q2] * da * B[q1][a1] * B[q2][a2];
+                        }
+                    int aa[3];
+                    aa[dn] = an; aa[d1] = a1; aa[d2] = a2;
                     out[gnode(m, cc[0], cc[1], cc[2], aa[0], aa[1], aa[2])] += value * s;
                 }
+        }
 }
 
 /* Cell and local coordinate of a point along axis d (closed box). */
@@ -568,7 +644,7 @@ void orc_eval_qp(const orc_mesh *m, int nq, const double *u, double *out)
 void orc_flux_qp(const orc_mesh *m, int nq, const double *kc, const double *P, double rho_g,
                  double *out)
 {
-    int p = m->p, n1 = p + 1;
+    int p = m->p, n1 = p + 1, nl = n1 * n1 * n1;
     double gx[MAXQ], gw[MAXQ];
     gauss01(nq, gx, gw);
     double B[MAXQ][3], D[MAXQ][3];
@@ -579,19 +655,19 @@ void orc_flux_qp(const orc_mesh *m, int nq, const double *kc, const double *P, d
         for (int cy = 0; cy < m->n[1]; cy++)
             for (int cx = 0; cx < m->n[0]; cx++) {
                 int64_t c = cx + (int64_t)m->n[0] * (cy + (int64_t)m->n[1] * cz);
-                double hx = cell_h(m, 0, cx), hy = cell_h(m, 1, cy), hz = cell_h(m, 2, cz);
+                double Pl[MAXNL];
+                for (int az = 0; az < n1; az++)
+                    for (int ay = 0; ay < n1; ay++)
+                        for (int ax = 0; ax < n1; ax++)
+                            Pl[ax + n1 * (ay + n1 * az)] = P[gnode(m, cx, cy, cz, ax, ay, az)];
                 for (int qz = 0; qz < nq; qz++)
                     for (int qy = 0; qy < nq; qy++)
                         for (int qx = 0; qx < nq; qx++) {
+                            double N[MAXNL], G[MAXNL][3];
+                            (void)cell_geometry(m, cx, cy, cz, B[qx], D[qx], B[qy], D[qy], B[qz], D[qz], N, G);
                             double g[3] = {0.0, 0.0, 0.0};
-                            for (int az = 0; az < n1; az++)
-                                for (int ay = 0; ay < n1; ay++)
-                                    for (int ax = 0; ax < n1; ax++) {
-                                        double Pv = P[gnode(m, cx, cy, cz, ax, ay, az)];
-                                        g[0] += D[qx][ax] / hx * B[qy][ay] * B[qz][az] * Pv;
-                                        g[1] += B[qx][ax] * D[qy][ay] / hy * B[qz][az] * Pv;
-                                        g[2] += B[qx][ax] * B[qy][ay] * D[qz][az] / hz * Pv;
-                                    }
+                            for (int a = 0; a < nl; a++)
+                                for (int d = 0; d < 3; d++) g[d] += G[a][d] * Pl[a];
                             int64_t o = (c * nq3 + qx + nq * (qy + nq * qz)) * 3;
                             out[o + 0] = -kc[c] * g[0];
                             out[o + 1] = -kc[c] * g[1];

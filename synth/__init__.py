@@ -113,6 +113,9 @@ class Scenario:
     # Graded (rectilinear) meshes: cell-edge coordinates per axis (ncells + 1
     # increasing values spanning the box); None = uniform spacing.
     edges: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
+    # General hexahedra of the box topology: coordinates of every node,
+    # [nnode][3] with x fastest; None = box geometry.
+    coords: Optional[np.ndarray] = None
     bcs: List[FaceBC] = field(default_factory=list)
     lines: List[LineSource] = field(default_factory=list)
     dir_columns: List[DirColumn] = field(default_factory=list)
@@ -244,6 +247,56 @@ def config2(seed: int = 2, ncells=(128, 128, 64), n_steps: int = 100) -> Scenari
                LineSource(350.0, 250.0, 0.0, 100.0, LINE_WELL, timefn(-0.01),
                           T_inj=0.0)]
     s.P0 = p_hyd
+    s.T0 = timefn(T15C)
+    return s
+
+
+def terrain_coords(origin, extent, ncells, top_amp=8.0, bottom_amp=5.0, shear=0.03):
+    """Node coordinates of a terrain-following hexahedral mesh of the box
+    topology: every node column keeps its (i, j) but its node planes are
+    stretched between a curved bottom and a curved top surface (sigma
+    layers), and the interior is sheared horizontally (the shear vanishes on
+    the four side faces, which stay planar).  Cells are general hexahedra:
+    non-parallel, non-planar faces.  Returns [nnode][3], x fastest."""
+    (x0, y0, z0), (Lx, Ly, Lz) = origin, extent
+    nx, ny, nz = ncells
+    x = x0 + Lx * np.arange(nx + 1) / nx
+    y = y0 + Ly * np.arange(ny + 1) / ny
+    s = np.arange(nz + 1) / nz
+    Z3, Y3, X3 = np.meshgrid(s, y, x, indexing="ij")
+    u, v = (X3 - x0) / Lx, (Y3 - y0) / Ly
+    top = z0 + Lz + top_amp * np.sin(2.0 * np.pi * u) * np.sin(np.pi * v)
+    bot = z0 + bottom_amp * np.cos(np.pi * u) * np.cos(2.0 * np.pi * v)
+    zz = bot + Z3 * (top - bot)
+    xx = X3 + shear * Lx * (Z3 - 0.5) * np.sin(np.pi * u) * np.sin(np.pi * v)
+    yy = Y3 + shear * Ly * np.sin(2.0 * np.pi * u) * np.sin(np.pi * v) * (1.0 - Z3)
+    return np.stack([xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)], axis=1)
+
+
+def aquifer_hex(seed: int = 7, ncells=(128, 128, 64), n_steps: int = 10) -> Scenario:
+    """The 500 x 500 x 100 m layered aquifer on a terrain-following mesh of
+    general hexahedra (terrain_coords): layered lognormal permeability by
+    cell layer, transient pressure with a regional hydraulic gradient of
+    0.005 along x (hydrostatic plus gradient on the x faces), a heated zone
+    (50 W/m^3 in a block of cells) in a 15 C ground held at 15 C on the side
+    and top faces."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    origin, extent = (0.0, 0.0, 0.0), (500.0, 500.0, 100.0)
+    perm, phi = layered_lognormal(rng, origin, extent, ncells, 5)
+    nc = perm.size
+    s = Scenario("aquifer_hex", origin, extent, tuple(ncells), 1, permeability=perm,
+                 porosity=phi, lambda_solid=_uniform(nc, 2.5),
+                 rhoc_solid=_uniform(nc, 2.0e6), B_poro=1.0e5, dt=DAY,
+                 n_steps=n_steps)
+    s.coords = terrain_coords(origin, extent, ncells)
+    p_g = hydrostatic(100.0, 1.0e5, s.rho_w, s.g, grad_x=0.005, x_ref=500.0)
+    s.bcs = [FaceBC(PRESSURE, 0, DIRICHLET, p_g), FaceBC(PRESSURE, 1, DIRICHLET, p_g)]
+    s.bcs += [FaceBC(TEMPERATURE, f, DIRICHLET, timefn(T15C)) for f in (0, 1, 2, 3, 5)]
+    nx, ny, nz = ncells
+    q = np.zeros((nz, ny, nx))
+    q[nz // 4:nz // 2, 3 * ny // 8:5 * ny // 8, nx // 4:3 * nx // 8] = 50.0
+    s.heat_source = q.reshape(-1)
+    s.P0 = p_g
     s.T0 = timefn(T15C)
     return s
 
