@@ -40,7 +40,9 @@ PEAK_BF16_TFLOPS = 2500.0      # dense MFMA
 # by the heat operator, and the per-cell coefficients (k; k and porosity for
 # heat) at one cell per node, at the operator's precision.
 ALG_BYTES = {(1, 0, 0): 24.0, (1, 0, 1): 12.0, (1, 1, 0): 40.0, (1, 1, 1): 20.0,
-             (2, 0, 0): 17.0, (2, 0, 1): 8.5, (2, 1, 0): 26.0, (2, 1, 1): 13.0}
+             (2, 0, 0): 17.0, (2, 0, 1): 8.5, (2, 1, 0): 26.0, (2, 1, 1): 13.0,
+             # general hexahedra: the Q1 bytes plus the FP64 node coordinates
+             ("hex", 0, 0): 48.0, ("hex", 0, 1): 36.0, ("hex", 1, 0): 64.0, ("hex", 1, 1): 44.0}
 # Algorithmic flops per cell of one apply (sum-factorised Kronecker
 # application; the heat operator adds the Darcy flux and q . grad T at the
 # Gauss points), and the per-kernel bound they give against the ridge of the
@@ -87,8 +89,8 @@ def parse():
     ap.add_argument("--modes", default="fp64,fp32_refined",
                     help="comma list of fp64, fp32_refined; the faster one is the headline")
     ap.add_argument("--workload", default="aquifer",
-                    choices=("aquifer", "piles", "piles-q2", "island", "island-graded", "island-q2",
-                             "island-graded-q2", "ates", "batch"))
+                    choices=("aquifer", "aquifer-hex", "piles", "piles-q2", "island", "island-graded",
+                             "island-q2", "island-graded-q2", "ates", "batch"))
     ap.add_argument("--ncells", default=None, help="cells per axis, e.g. 128,128,64 (default: the workload's)")
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--host-loop", type=int, default=1,
@@ -218,6 +220,11 @@ def workload(a, synth, n_steps):
         nc = nc or (128, 128, 64)
         return [synth.config2(ncells=nc, n_steps=n_steps)], 2, \
             "layered aquifer %dx%dx%d Q1 (%%d nodes/field), well pair" % nc
+    if a.workload == "aquifer-hex":
+        nc = nc or (128, 128, 64)
+        return [synth.aquifer_hex(ncells=nc, n_steps=n_steps)], None, \
+            ("layered aquifer on terrain-following general hexahedra %dx%dx%d Q1 (%%d nodes/field), "
+             "regional gradient, heated block" % nc)
     if a.workload in ("piles", "piles-q2"):
         p = 1 if a.workload == "piles" else 2
         nc = nc or ((256, 256, 128) if p == 1 else (128, 128, 64))
@@ -432,14 +439,14 @@ def main():
     key = max(kt, key=lambda k: kt[k]["ms"])
     k = kt[key]
     avg_ms = k["ms"] / max(1, k["launches"])
-    deg = scns[0].degree
+    deg = scns[0].degree if getattr(scns[0], "coords", None) is None else "hex"
     alg_step = ALG_BYTES[(deg, key[0], key[1])] * R["nnode"] / max(1, len(scns))
     in_step = {"workload": wdesc % R["nnode"], "launches": k["launches"], "avg_us": round(1e3 * avg_ms, 2),
                "alg_bytes": alg_step,
                "GB/s": round(alg_step / (avg_ms * 1e-3) / 1e9, 1) if not batch else None,
                "share_of_step": round(k["ms"] / (R["ms_per_step"] * max(1, a.timing_steps)), 3)}
     name = CLASS_NAMES[key]
-    qname = "Q%d %s" % (deg, name)
+    qname = ("Q%d %s" % (deg, name)) if deg != "hex" else "hex " + name
     if operators and qname in operators:
         # the same class on the 8.5 M-node mesh, streaming from HBM, against
         # the bound its algorithmic intensity gives
@@ -466,7 +473,7 @@ def main():
                     "avg_us": in_step["avg_us"], "in_step": in_step}
     # the HBM-bound operator of the same degree (the pressure apply, FP64)
     roofline_hbm = None
-    hname = "Q%d %s" % (deg, CLASS_NAMES[(0, 0)])
+    hname = "Q%d %s" % (deg, CLASS_NAMES[(0, 0)]) if deg != "hex" else None
     if operators and hname in operators:
         h = operators[hname]
         roofline_hbm = {"bound": "hbm", "kernel": hname, "achieved": h["GB/s"], "peak": PEAK_HBM_GBS,

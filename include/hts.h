@@ -104,6 +104,15 @@ typedef struct {
     void *stream;         /* hipStream_t; NULL = null stream */
     hts_allocator alloc;
     const double *edges[3];   /* NULL = uniform axis */
+    /* General hexahedra (degree 1 only): coordinates of every node, host
+     * [nnode][3] with x fastest (node i + NX (j + NY k)), copied.  The box
+     * topology is kept and each cell is the trilinear image of the unit
+     * cube (Section 3.3, Fig. 10b: a site mesh refined around the piles);
+     * origin and extent are then not used for geometry and edges must be
+     * NULL.  Every cell must keep det J > 0 at its Gauss points (else
+     * HTS_ERR_ARG).  Line sources, Dirichlet columns and Neumann faces need
+     * the box geometry and return HTS_ERR_UNSUPPORTED on such meshes. */
+    const double *coords;
 } hts_mesh_desc;
 
 /* Materials (Section 2 mixture rules and mobility, Tables 1 and 3):

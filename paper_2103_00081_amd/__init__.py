@@ -66,7 +66,7 @@ class Allocator(C.Structure):
 class MeshDesc(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("extent", C.c_double * 3), ("ncells", C.c_int32 * 3),
                 ("degree", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
-                ("alloc", Allocator), ("edges", C.c_void_p * 3)]
+                ("alloc", Allocator), ("edges", C.c_void_p * 3), ("coords", C.c_void_p)]
 
 
 class Materials(C.Structure):
@@ -213,7 +213,7 @@ class Mesh:
     """Owner of one hts_mesh."""
 
     def __init__(self, origin, extent, ncells, degree=1, device=0, stream=None,
-                 torch_allocator=True, edges=None):
+                 torch_allocator=True, edges=None, coords=None):
         L = load()
         import torch
         self.device = int(device)
@@ -236,6 +236,10 @@ class Mesh:
                     raise ValueError("edges[%d] must have ncells + 1 values" % k)
                 keep.append(e)
                 desc.edges[k] = e.ctypes.data
+        if coords is not None:
+            xyz = np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 3)
+            keep.append(xyz)
+            desc.coords = xyz.ctypes.data
         desc.stream = C.c_void_p(int(stream)) if stream else None
         if torch_allocator:
             desc.alloc = _torch_allocator(self.device)
@@ -479,6 +483,9 @@ def stream_copy(src, dst, reps=20):
 
 # --------------------------------------------------- scenario marshalling
 def _node_coords(scn):
+    if getattr(scn, "coords", None) is not None:
+        xyz = np.asarray(scn.coords, dtype=np.float64).reshape(-1, 3)
+        return xyz[:, 0].copy(), xyz[:, 1].copy(), xyz[:, 2].copy()
     p = scn.degree
     edges = getattr(scn, "edges", None)
     ax = []
@@ -508,7 +515,7 @@ def from_scenario(scn, device=0, stream=None, initial=True, opts=None) -> Mesh:
     receives).  With initial=True the state is set from the scenario's
     initial functions, and the steady pressure is solved when requested."""
     m = Mesh(scn.origin, scn.extent, scn.ncells, scn.degree, device, stream,
-             edges=getattr(scn, "edges", None))
+             edges=getattr(scn, "edges", None), coords=getattr(scn, "coords", None))
     m.set_materials(scn.permeability, scn.porosity, scn.lambda_solid, scn.rhoc_solid,
                     scn.rho_w, scn.mu_w, scn.c_w, scn.lambda_w, scn.g, scn.B_poro,
                     hydraulic_conductivity=getattr(scn, "hydraulic_conductivity", None),

@@ -30,6 +30,7 @@ struct BcDev {
     double x0, y0, z0;         // origin
     double dx, dy, dz;         // node spacing (uniform meshes)
     const double *xn, *yn, *zn;   // node coordinates per axis (graded meshes; null = uniform)
+    const double *xyz;         // general hexahedra: node coordinates [nnode][3] (null = box)
     const int32_t *colspec;    // [NX*NY] Dirichlet column spec per node column or -1 (null = none)
     const TimeFnDev *coltf;    // column specs
 };

@@ -20,8 +20,13 @@ __global__ __launch_bounds__(256) void k_dirichlet(const OpDev *__restrict__ ops
         // instance-local node index (below 2^31): 32-bit index arithmetic
         const int n = (int)(e - o.off);
         const int nxy = n / o.NX, i = n - nxy * o.NX, k = nxy / o.NY, j = nxy - k * o.NY;
-        const double x = b.xn ? b.xn[i] : b.x0 + i * b.dx, y = b.yn ? b.yn[j] : b.y0 + j * b.dy,
-                     z = b.zn ? b.zn[k] : b.z0 + k * b.dz;
+        double x = b.xn ? b.xn[i] : b.x0 + i * b.dx, y = b.yn ? b.yn[j] : b.y0 + j * b.dy,
+               z = b.zn ? b.zn[k] : b.z0 + k * b.dz;
+        if (b.xyz) {
+            x = b.xyz[3 * (int64_t)n];
+            y = b.xyz[3 * (int64_t)n + 1];
+            z = b.xyz[3 * (int64_t)n + 2];
+        }
         double v = 0.0;
         for (int f = 0; f < b.nface; f++) {
             const int face = b.faces[f];

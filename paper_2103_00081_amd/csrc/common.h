@@ -91,6 +91,7 @@ struct OpDev {
     const LineCol *lfcol;      // [NX*NY] (Q1) dense per-column rows, or null
     const LineFlat *lflat;
     const double *lcoef;       // per line source: dt c_w max(Q,0)/L at t^{n+1}
+    const double *xyz;         // general hexahedra: node coordinates [nnode][3]; null on box meshes
     int64_t off;               // offset of the instance in batch node vectors
     int64_t nnode;
     int32_t field;
@@ -159,7 +160,9 @@ struct LevelGeo {              // one instance on one multigrid level
 };
 
 // ------------------------------------------------------------ launchers
-// Operator kernels (op_q1.hip / op_q2.hip)
+// Operator kernels (op_q1.hip / op_q2.hip / op_hex.hip); degree 3 selects the
+// Q1 kernels of general hexahedra (node coordinates in OpDev::xyz)
+constexpr int DEGREE_HEX = 3;
 template <typename T>
 void launch_apply(int degree, int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work,
                   int nwork, const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
@@ -170,6 +173,8 @@ void launch_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s);
 // 27-point assembled stencil [27][nnode] of the (Dirichlet-eliminated)
 // symmetric part of a Q1 operator; offset e = (dx+1) + 3(dy+1) + 9(dz+1).
 void launch_q1_stencil(const OpDev &op, double *S, hipStream_t s);
+// the same for a Q1 operator of box or general hexahedral geometry
+void launch_fine_stencil(const OpDev &op, double *S, hipStream_t s);
 // y_a = sum_c alpha_c int N_a + beta_c int dN_a/dz   (static load vectors)
 void launch_cell_loads(const OpDev &op, const double *alpha, const double *beta, double *y,
                        hipStream_t s);

@@ -142,6 +142,10 @@ struct hts_mesh {
     bool graded = false;
     std::vector<double> edge[3], node[3];
     hts::DBuf<double> dh[3], dnode[3], dihz;
+    // general hexahedra: node coordinates [nnode][3] (host and device)
+    bool general = false;
+    std::vector<double> hxyz;
+    hts::DBuf<double> xyz;
     double cell_lo(int d, int i) const { return graded ? edge[d][i] : x0[d] + i * h[d]; }
     double cell_h(int d, int i) const { return graded ? edge[d][i + 1] - edge[d][i] : h[d]; }
 
@@ -199,6 +203,8 @@ void prepare_mesh(hts_mesh *m);                 // (re)build derived device data
 void forget_batches(hts_mesh *m);               // drop every cached batch that holds m (solve.hip)
 bool is_constrained(const hts_mesh *m, int field, int i, int j, int k);   // host, after prepare_mesh
 OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, bool mass_only);
+// kernel family of a mesh: its degree, or DEGREE_HEX for general hexahedra
+inline int kernel_degree(const hts_mesh *m) { return m->general ? DEGREE_HEX : m->p; }
 int tile_own_x(int degree, int field);          // owned node columns per tile of the operator kernels, x
 int tile_own_y(int degree, int field);          // and y
 // node planes per work item of the operator kernels (force > 0: that depth)

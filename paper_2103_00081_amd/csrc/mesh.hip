@@ -1,6 +1,7 @@
 // Meshes: creation, materials, boundary data, sources and the derived
 // device data every solve uses.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "internal.h"
@@ -458,6 +459,7 @@ OpDev make_op(const hts_mesh *m, int field, bool fp32, double dt, bool steady, b
     o.lfcol = (o.lcol && m->lfcol.p) ? m->lfcol.p : nullptr;
     o.lflat = m->lflat.p;
     o.lcoef = nullptr;
+    o.xyz = m->general ? m->xyz.p : nullptr;
     {
         const double V = o.hx * o.hy * o.hz, cw8 = o.cadv * V * 0.125;
         o.q1m = V / 216.0;
@@ -497,6 +499,43 @@ void hts_default_opts(hts_solver_opts *o)
     o->heat_precond = 1;
 }
 
+// General hexahedra: det J > 0 at the 2 x 2 x 2 Gauss points of every cell
+// (the points the operators integrate at), and all coordinates finite.
+static void check_hex_cells(const double *xyz, const int n[3])
+{
+    const int NX = n[0] + 1, NY = n[1] + 1;
+    const int64_t nnode = (int64_t)NX * NY * (n[2] + 1);
+    const double g[2] = {0.21132486540518711775, 0.78867513459481288225};
+    for (int64_t i = 0; i < 3 * nnode; i++) ARG_CHECK(std::isfinite(xyz[i]), "node coordinates must be finite");
+    for (int cz = 0; cz < n[2]; cz++)
+        for (int cy = 0; cy < n[1]; cy++)
+            for (int cx = 0; cx < n[0]; cx++) {
+                double X[8][3];
+                for (int a = 0; a < 8; a++) {
+                    const int64_t nd = (int64_t)(cx + (a & 1)) + (int64_t)NX * ((cy + ((a >> 1) & 1)) +
+                                                                                (int64_t)NY * (cz + (a >> 2)));
+                    for (int d = 0; d < 3; d++) X[a][d] = xyz[3 * nd + d];
+                }
+                for (int q = 0; q < 8; q++) {
+                    const double p3[3] = {g[q & 1], g[(q >> 1) & 1], g[q >> 2]};
+                    double J[3][3] = {{0.0}};
+                    for (int a = 0; a < 8; a++)
+                        for (int j = 0; j < 3; j++) {
+                            double r = 1.0;
+                            for (int d = 0; d < 3; d++) {
+                                const int ad = (a >> d) & 1;
+                                r *= d == j ? (ad ? 1.0 : -1.0) : (ad ? p3[d] : 1.0 - p3[d]);
+                            }
+                            for (int i = 0; i < 3; i++) J[i][j] += X[a][i] * r;
+                        }
+                    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                    ARG_CHECK(det > 0.0, "a hexahedron is inverted or degenerate (det J <= 0 at a Gauss point)");
+                }
+            }
+}
+
 hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
 {
     return guard([&] {
@@ -523,6 +562,11 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
             int64_t nn = 1;
             for (int d = 0; d < 3; d++) nn *= (int64_t)desc->degree * desc->ncells[d] + 1;
             ARG_CHECK(nn < (int64_t)1 << 29, "mesh too large: 2^29 nodes or more");
+        }
+        if (desc->coords) {
+            ARG_CHECK(desc->degree == 1, "node coordinates (general hexahedra) need degree 1");
+            ARG_CHECK(!graded, "give either node coordinates or graded edges");
+            check_hex_cells(desc->coords, desc->ncells);
         }
         HTS_HIP(hipSetDevice(desc->device));
         std::unique_ptr<hts_mesh> m(new hts_mesh());
@@ -575,6 +619,12 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
                 }
             }
             HTS_HIP(hipStreamSynchronize(m->stream));
+        }
+        if (desc->coords) {
+            m->general = true;
+            m->hxyz.assign(desc->coords, desc->coords + 3 * m->nnode);
+            m->xyz.upload(&m->alloc, m->hxyz, m->stream);
+            m->desc.coords = nullptr;   // the caller's array is not kept
         }
         m->P.alloc(&m->alloc, m->nnode);
         m->T.alloc(&m->alloc, m->nnode);
@@ -654,8 +704,10 @@ hts_status hts_set_face_bc(hts_mesh *m, hts_field field, int32_t face, int32_t k
         ARG_CHECK(face >= 0 && face < 6, "face must be 0..5");
         ARG_CHECK(kind == HTS_BC_DIRICHLET || kind == HTS_BC_NEUMANN || kind == HTS_BC_NONE, "bad kind");
         ARG_CHECK(kind == HTS_BC_NONE || value, "null value");
-        if (kind == HTS_BC_NEUMANN)
+        if (kind == HTS_BC_NEUMANN) {
             ARG_CHECK(value->cx == 0 && value->cy == 0 && value->cz == 0, "Neumann flux must be spatially constant");
+            if (m->general) throw Error(HTS_ERR_UNSUPPORTED, "Neumann faces need a box mesh");
+        }
         if (value) ARG_CHECK(value->kind >= 0 && value->kind <= 2, "bad time function kind");
         if (value && value->kind != 0) ARG_CHECK(value->period > 0, "period must be > 0");
         auto &v = m->bcs[field];
@@ -684,6 +736,7 @@ hts_status hts_add_line_source(hts_mesh *m, double x, double y, double z0, doubl
         ARG_CHECK(z1 > z0, "z1 must exceed z0");
         ARG_CHECK(rate->cx == 0 && rate->cy == 0 && rate->cz == 0, "line rate must be spatially constant");
         ARG_CHECK(rate->kind == 0 || rate->period > 0, "period must be > 0");
+        if (m->general) throw Error(HTS_ERR_UNSUPPORTED, "line sources need a box mesh (vertical node columns)");
         m->lines.push_back({x, y, z0, z1, kind, *rate, T_inj});
         m->dirty = true;
     });
@@ -696,6 +749,7 @@ hts_status hts_add_dirichlet_column(hts_mesh *m, hts_field field, double x, doub
         ARG_CHECK(m && value, "null argument");
         ARG_CHECK(field == 0 || field == 1, "bad field");
         ARG_CHECK(z1 >= z0, "z1 must not be below z0");
+        if (m->general) throw Error(HTS_ERR_UNSUPPORTED, "Dirichlet columns need a box mesh (vertical node columns)");
         m->cols[field].push_back({x, y, z0, z1, *value});
         m->dirty = true;
     });

@@ -118,7 +118,7 @@ extern "C" hts_status hts_apply_operator_noalloc(hts_mesh *m, hts_field field, h
         const hipStream_t s = m->stream;
         const bool fp32 = prec == HTS_FP32;
         const bool steady = field == 0 && (dt <= 0.0 || m->B <= 0.0);
-        const int ox = tile_own_x(m->p, field), oy = tile_own_y(m->p, field);
+        const int ox = tile_own_x(kernel_degree(m), field), oy = tile_own_y(kernel_degree(m), field);
         const int ntx = (m->N[0] + ox - 1) / ox, nty = (m->N[1] + oy - 1) / oy;
         const int zc = zc_for(m, field, (int64_t)ntx * nty, 0);
         const int64_t nzc = (m->N[2] + zc - 1) / zc;
@@ -186,11 +186,11 @@ extern "C" hts_status hts_apply_operator_noalloc(hts_mesh *m, hts_field field, h
         }
         if (!fp32) {
             EpiArgs<double> ep{};
-            launch_apply<double>(m->p, field, EPI_STORE, true, m->graded, ops, work, (int)nwork,
+            launch_apply<double>(kernel_degree(m), field, EPI_STORE, true, m->graded, ops, work, (int)nwork,
                                  static_cast<const double *>(x_dev), static_cast<double *>(y_dev), ep, s);
         } else {
             EpiArgs<float> ep{};
-            launch_apply<float>(m->p, field, EPI_STORE, true, m->graded, ops + 1, work, (int)nwork,
+            launch_apply<float>(kernel_degree(m), field, EPI_STORE, true, m->graded, ops + 1, work, (int)nwork,
                                 static_cast<const float *>(x_dev), static_cast<float *>(y_dev), ep, s);
         }
     });

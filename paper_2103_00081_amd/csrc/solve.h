@@ -19,6 +19,7 @@ void launch_apply(int degree, int field, int epi, bool masked, bool graded, cons
                   int nwork, const T *x, T *y, const EpiArgs<T> &ep, hipStream_t s);
 void launch_inv_diag(const OpDev &op, double *inv_diag, hipStream_t s);
 void launch_q1_stencil(const OpDev &op, double *S, hipStream_t s);
+void launch_fine_stencil(const OpDev &op, double *S, hipStream_t s);
 
 // Per-instance operator descriptors of one operator variant (FP64 and FP32).
 struct Tables {
@@ -89,6 +90,7 @@ struct Batch {
     std::vector<int64_t> off;
     int64_t ntot = 0, ctot = 0;
     bool graded = false;       // some instance has a graded mesh
+    bool general = false;      // the instances are general hexahedral meshes
 
     std::vector<Chunk> hch;
     DBuf<Chunk> ch;

@@ -180,7 +180,8 @@ int tuned_zc(int degree, int field, int NX, int NY, int NZ)
 }
 
 // Q1: wide tiles for the pressure operator, narrow ones for the heat operator
-int tile_own_x(int degree, int field) { return degree == 2 ? 30 : (field == 0 ? 31 : 15); }
+// (degree: the kernel family; general hexahedra use the narrow tiles)
+int tile_own_x(int degree, int field) { return degree == 2 ? 30 : (field == 0 && degree == 1 ? 31 : 15); }
 int tile_own_y(int degree, int field) { return degree == 2 ? 30 : 15; }
 
 int zc_for(const hts_mesh *M, int field, int64_t tiles, int force)
@@ -189,7 +190,7 @@ int zc_for(const hts_mesh *M, int field, int64_t tiles, int force)
     // Q2 work items start on even node planes (cell-layer boundaries)
     auto fit = [&](int z) { return M->p == 2 ? std::max(2, (std::min(z, NZ) + 1) / 2 * 2) : std::min(z, NZ); };
     if (force > 0) return fit(force);
-    const int t = tuned_zc(M->p, field, M->N[0], M->N[1], NZ);
+    const int t = tuned_zc(kernel_degree(M), field, M->N[0], M->N[1], NZ);
     if (t > 0) return fit(t);
     // enough blocks to fill 256 CUs several times over
     int64_t z = std::max<int64_t>(4, (tiles * NZ) / 2048);
@@ -210,7 +211,7 @@ void Batch::build_work()
         for (int i = 0; i < n; i++) {
             hts_mesh *M = m[i];
             // owned node columns per tile along x and y
-            const int ox = tile_own_x(M->p, f), oy = tile_own_y(M->p, f);
+            const int ox = tile_own_x(kernel_degree(M), f), oy = tile_own_y(kernel_degree(M), f);
             const int tx = (M->N[0] + ox - 1) / ox, ty = (M->N[1] + oy - 1) / oy;
             const int zc = pick_zc(f, M, (int64_t)tx * ty);
             for (int z0 = 0; z0 < M->N[2]; z0 += zc)
@@ -255,6 +256,8 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->device = ms[0]->desc.device;
     for (hts_mesh *M : ms) {
         if (M->p != B->p) throw Error(HTS_ERR_ARG, "all meshes of a batch must have the same degree");
+        if (M->general != ms[0]->general)
+            throw Error(HTS_ERR_ARG, "general hexahedral and box meshes cannot share a batch");
         if (M->desc.device != B->device) throw Error(HTS_ERR_ARG, "all meshes of a batch must share a device");
         prepare_mesh(M);
     }
@@ -274,6 +277,7 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     for (int i = 0; i < n; i++) B->ctot += ms[i]->ncell;
     B->graded = false;
     for (int i = 0; i < n; i++) B->graded = B->graded || ms[i]->graded;
+    B->general = ms[0]->general;
     std::vector<int32_t> sp;
     build_chunks(B->off, cnt, CHUNK_LEN, B->hch, sp);
     B->nch = (int)B->hch.size();
@@ -328,6 +332,7 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
             b.dx = M->L[0] / (M->p * M->n[0]);
             b.dy = M->L[1] / (M->p * M->n[1]);
             b.dz = M->L[2] / (M->p * M->n[2]);
+            b.xyz = M->general ? M->xyz.p : nullptr;
             b.xn = M->graded ? M->dnode[0].p : nullptr;
             b.yn = M->graded ? M->dnode[1].p : nullptr;
             b.zn = M->graded ? M->dnode[2].p : nullptr;
@@ -501,7 +506,8 @@ template <typename T>
 void Batch::fine_apply(int field, const OpDev *ops, int epi, bool masked, const T *x, T *y, const EpiArgs<T> &ep)
 {
     if (!g_timing.on) {
-        launch_apply<T>(p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y, ep, s);
+        launch_apply<T>(general ? DEGREE_HEX : p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y,
+                        ep, s);
         return;
     }
     TimingRec r{};
@@ -512,7 +518,8 @@ void Batch::fine_apply(int field, const OpDev *ops, int epi, bool masked, const 
     r.bytes = apply_bytes(field, epi, ntot, ctot, sizeof(T));
     r.flops = apply_flops(field, p, ctot);
     HTS_HIP(hipEventRecord(r.a, s));
-    launch_apply<T>(p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y, ep, s);
+    launch_apply<T>(general ? DEGREE_HEX : p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y, ep,
+                    s);
     HTS_HIP(hipEventRecord(r.b, s));
     g_timing.recs.push_back(r);
 }
@@ -1037,7 +1044,7 @@ void Batch::build_hierarchy(Hier &H, const hts_solver_opts &o)
                 if (p == 1) {
                     DBuf<double> Sf;
                     Sf.alloc(al, (size_t)27 * m[i]->nnode);
-                    launch_q1_stencil(H.ops.h64[i], Sf.p, s);
+                    launch_fine_stencil(H.ops.h64[i], Sf.p, s);
                     launch_rap(fN[0], fN[1], fN[2], Sf.p, cN[0], cN[1], cN[2], Sc, s);
                     sync(s);
                 } else {
@@ -2023,7 +2030,7 @@ hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
                     }
                 }
                 b.zc_force[f] = 0;
-                set_tuned_zc(m->p, f, m->N[0], m->N[1], m->N[2], bz);
+                set_tuned_zc(kernel_degree(m), f, m->N[0], m->N[1], m->N[2], bz);
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);

@@ -308,7 +308,8 @@ __global__ __launch_bounds__(VB) void k_piezo32(const Chunk *__restrict__ chunks
     const int64_t pl = (int64_t)o.NX * o.NY;
     for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
         const int64_t k = (e - o.off) / pl;
-        const double zk = o.zn ? o.zn[k] - o.zn[0] : k * dz;
+        double zk = o.zn ? o.zn[k] - o.zn[0] : k * dz;
+        if (o.xyz) zk = o.xyz[3 * (e - o.off) + 2] - o.xyz[2];   // general hexahedra
         P32[e] = (float)((P[e] - ref) + o.rho_g * zk);
     }
 }

@@ -91,3 +91,45 @@ def test_mesh_size_limit_without_device():
         d.ncells[k] = n
     assert L.hts_create_mesh(ctypes.byref(d), ctypes.byref(h)) == -1
     assert b"too large" in L.hts_last_error()
+
+
+def test_hexahedral_mesh_validation_without_device():
+    """Node coordinates need degree 1 and no graded edges; every cell must
+    have det J > 0 at its Gauss points and finite coordinates.  All refused
+    before any device work."""
+    import numpy as np
+    import paper_2103_00081_amd as hts
+    import synth
+    L = hts.load()
+    h = ctypes.c_void_p()
+    n = (4, 3, 2)
+
+    def desc(xyz, degree=1, edges=None):
+        d = hts.MeshDesc()
+        d.degree = degree
+        for k in range(3):
+            d.origin[k] = 0.0
+            d.extent[k] = 10.0
+            d.ncells[k] = n[k]
+        d.coords = xyz.ctypes.data
+        if edges is not None:
+            d.edges[0] = edges.ctypes.data
+        return d
+
+    xyz = np.ascontiguousarray(synth.terrain_coords((0.0, 0.0, 0.0), (10.0, 10.0, 10.0), n,
+                                                    top_amp=1.0, bottom_amp=0.5))
+    assert L.hts_create_mesh(ctypes.byref(desc(xyz, degree=2)), ctypes.byref(h)) == -1
+    assert b"degree 1" in L.hts_last_error()
+    edges = np.linspace(0.0, 10.0, n[0] + 1)
+    assert L.hts_create_mesh(ctypes.byref(desc(xyz, edges=edges)), ctypes.byref(h)) == -1
+    assert b"either" in L.hts_last_error()
+    # swap two node planes: every cell between them turns inside out
+    inv = xyz.reshape(n[2] + 1, -1, 3).copy()
+    inv[[0, 1]] = inv[[1, 0]]
+    inv = np.ascontiguousarray(inv.reshape(-1, 3))
+    assert L.hts_create_mesh(ctypes.byref(desc(inv)), ctypes.byref(h)) == -1
+    assert b"inverted" in L.hts_last_error()
+    bad = xyz.copy()
+    bad[5, 1] = np.nan
+    assert L.hts_create_mesh(ctypes.byref(desc(bad)), ctypes.byref(h)) == -1
+    assert b"finite" in L.hts_last_error()

@@ -65,7 +65,29 @@ def small_cases():
                synth.graded_edges(0.0, 200.0, 5, [(160.0, 200.0)]))
     s.name = "c3_q2_graded"
     c.append((s.name, s))
+    # general hexahedra: terrain-following cells over several 15 x 15 tiles
+    # with ragged tails, and a box mesh with randomly jittered interior nodes
+    c.append(("aquifer_hex_tiles", synth.aquifer_hex(ncells=(40, 33, 6), n_steps=1)))
+    s = synth.aquifer_hex(ncells=(17, 9, 5), n_steps=1)
+    s.coords = jittered_coords(s, 0.12, seed=5)
+    s.name = "jitter_hex"
+    c.append((s.name, s))
     return c
+
+
+def jittered_coords(scn, frac, seed):
+    """Box node coordinates with every interior node moved by up to frac
+    of a cell width along each axis (boundary nodes stay on their faces)."""
+    nx, ny, nz = scn.ncells
+    ax = [scn.origin[d] + scn.extent[d] * np.arange(n + 1) / n for d, n in enumerate(scn.ncells)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    xyz = np.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], axis=1)
+    rng = np.random.default_rng(seed)
+    k, j, i = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    inner = ((i > 0) & (i < nx) & (j > 0) & (j < ny) & (k > 0) & (k < nz)).reshape(-1)
+    h = np.array([scn.extent[d] / scn.ncells[d] for d in range(3)])
+    xyz[inner] += frac * h * rng.uniform(-1.0, 1.0, (int(inner.sum()), 3))
+    return xyz
 
 
 def _mesh(hts, scn):
@@ -116,7 +138,8 @@ def test_apply_parity(hts, name, scn, field):
                 NX, NY = om.dims[0], om.dims[1]
                 kz = np.arange(om.nnode) // (NX * NY)
                 dz = scn.extent[2] / (scn.degree * scn.ncells[2])
-                zk = kz * dz if getattr(scn, "edges", None) is None else Z - Z[0]
+                box = getattr(scn, "edges", None) is None and getattr(scn, "coords", None) is None
+                zk = kz * dz if box else Z - Z[0]
                 rg = scn.rho_w * scn.g
                 phi32 = ((P - P[0]) + rg * zk).astype(np.float32)
                 Pt = phi32.astype(np.float64) - rg * zk + P[0]

@@ -248,3 +248,10 @@ def test_f4_injection_column_full_size_step(hts):
     the symmetric part alone, with which restarted FGMRES stagnates near
     4e-4) and is judged in the oracle's matrices."""
     full_size_step(hts, synth.ates(ncells=(64, 64, 240), n_steps=1), "f4 injection column 64x64x240")
+
+
+@pytest.mark.timeout(600)
+def test_f2_terrain_aquifer_full_size_step(hts):
+    """The layered aquifer on 128 x 128 x 64 terrain-following general
+    hexahedra (per-cell Jacobians in every operator)."""
+    full_size_step(hts, synth.aquifer_hex(ncells=(128, 128, 64), n_steps=1), "f2 terrain aquifer 128x128x64")
