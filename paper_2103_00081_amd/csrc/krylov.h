@@ -7,8 +7,6 @@ namespace hts {
 void gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_t *kdim, hipStream_t s);
 // h1: first projection (j+1 per instance); h2: second projection (j+1) and
 // the squared norm of w after the first projection (entry j+1)
-void gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit, const double *h1,
-                const double *h2, double *H, double *cs, double *sn, double *g, int32_t *kdim, hipStream_t s);
 void gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g, const int32_t *kdim,
               double *y, hipStream_t s);
 void outer_check(int ninst, int32_t *active, double *S, const double *rr, hipStream_t s);

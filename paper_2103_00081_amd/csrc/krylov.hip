@@ -37,14 +37,6 @@ __global__ void k_gm_begin(int ninst, int32_t *active, double *S, double *g, int
     Si[S_STATUS] = 1;
 }
 
-// one thread per instance (the column update itself is in arnoldi.h)
-__global__ void k_gm_arnoldi(int ninst, int32_t *active, double *S, ArnArgs A, const double *h2)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ninst || !active[i]) return;
-    arnoldi_column(i, active, S, A, h2 + (int64_t)i * (A.j + 2));
-}
-
 __global__ void k_gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g,
                            const int32_t *kdim, double *y)
 {
@@ -229,13 +221,6 @@ static dim3 g1(int n) { return dim3((n + 63) / 64); }
 void gm_begin(int ninst, int32_t *active, double *S, double *g, int mres, int32_t *kdim, hipStream_t s)
 {
     k_gm_begin<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, g, mres, kdim);
-    HTS_LAUNCH_CHECK();
-}
-void gm_arnoldi(int ninst, int32_t *active, double *S, int j, int mres, int maxit, const double *h1,
-                const double *h2, double *H, double *cs, double *sn, double *g, int32_t *kdim, hipStream_t s)
-{
-    ArnArgs A{j, mres, maxit, 0, h1, H, cs, sn, g, kdim};
-    k_gm_arnoldi<<<g1(ninst), dim3(64), 0, s>>>(ninst, active, S, A, h2);
     HTS_LAUNCH_CHECK();
 }
 void gm_solve(int ninst, const int32_t *cyc, int mres, const double *H, const double *g, const int32_t *kdim,

@@ -388,15 +388,19 @@ __device__ void scalar_op(int op, int inst, const double *v, const double *pre, 
 // instance's flag, its segment and the scalar slots the update reads) are
 // issued together, then the partial sums; a kernel of a few dependent memory
 // latencies in the solver's critical path.
-__global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partial, int ncomp,
+constexpr int RB = 1024;   // threads of the final reduction (one block per instance)
+constexpr int RU = 8;      // loads in flight per thread
+
+__global__ __launch_bounds__(RB) void k_reduce(const double *__restrict__ partial, int ncomp,
                                                const int32_t *__restrict__ seg_ptr, int single, int op,
                                                int slot, double *S, int32_t *active, int maxit, double aux,
                                                double *out, ArnArgs arn)
 {
     __shared__ double vals[64];
+    __shared__ double rows[RB];
     const int inst = blockIdx.x;
     const int on = active ? active[inst] : 1;
-    const int b = single >= 0 ? 0 : seg_ptr[inst], e = single >= 0 ? single : seg_ptr[inst + 1];
+    const int b = single >= 0 ? 0 : seg_ptr[inst], n = (single >= 0 ? single : seg_ptr[inst + 1]) - b;
     double pre[3] = {0.0, 0.0, 0.0};
     if (threadIdx.x == 0) {
         const double *Si = S + (int64_t)inst * NSLOT;
@@ -404,55 +408,42 @@ __global__ __launch_bounds__(VB) void k_reduce(const double *__restrict__ partia
         pre[1] = Si[S_TOL2];
         pre[2] = Si[S_ITER];
     }
-    // fixed summation order: few components use the whole block each, many
-    // components one wave each.  Each thread adds the entries t, t + stride,
-    // t + 2 stride, ... in that order; four consecutive loads go out together.
-    if (ncomp <= 2) {
-        __shared__ double sh[4];
-        double a[2] = {0.0, 0.0};
-        for (int t = b + threadIdx.x; t < e; t += 4 * VB) {
-            double p[4][2];
+    // The partials are rows of ncomp values.  Thread t takes component
+    // c = t % ncomp of rows r0, r0 + R, r0 + 2R, ... (r0 = t / ncomp,
+    // R = RB / ncomp rows per pass), so each pass reads R * ncomp consecutive
+    // values; RU loads go out together.  Then a wave per component adds the
+    // R row sums in row order.  Fixed order throughout: deterministic.
+    const int R = RB / ncomp;
+    const int t = threadIdx.x, c = t % ncomp, r0 = t / ncomp;
+    double a = 0.0;
+    if (r0 < R) {
+        const double *pc = partial + (int64_t)b * ncomp + c;
+        for (int r = r0; r < n; r += RU * R) {
+            double p[RU];
 #pragma unroll
-            for (int u = 0; u < 4; u++)
+            for (int u = 0; u < RU; u++) p[u] = r + u * R < n ? pc[(int64_t)(r + u * R) * ncomp] : 0.0;
 #pragma unroll
-                for (int c = 0; c < 2; c++)
-                    p[u][c] = (t + u * VB < e && c < ncomp) ? partial[(int64_t)(t + u * VB) * ncomp + c] : 0.0;
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-                if (t + u * VB < e) {
-                    a[0] += p[u][0];
-                    a[1] += p[u][1];
-                }
+            for (int u = 0; u < RU; u++)
+                if (r + u * R < n) a += p[u];
         }
-        for (int c = 0; c < ncomp; c++) {
-            const double r = block_sum(a[c], sh);
-            if (threadIdx.x == 0) vals[c] = r;
-        }
-    } else {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        for (int c = w; c < ncomp; c += VB / 64) {
-            double a = 0.0;
-            for (int t = b + lane; t < e; t += 4 * 64) {
-                double p[4];
-#pragma unroll
-                for (int u = 0; u < 4; u++) p[u] = t + u * 64 < e ? partial[(int64_t)(t + u * 64) * ncomp + c] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 4; u++)
-                    if (t + u * 64 < e) a += p[u];
-            }
-            a = wave_sum(a);
-            if (lane == 0) vals[c] = a;
-        }
+    }
+    rows[t] = a;
+    __syncthreads();
+    const int lane = t & 63, w = t >> 6;
+    for (int cc = w; cc < ncomp; cc += RB / 64) {
+        double v = 0.0;
+        for (int r = lane; r < R; r += 64) v += rows[r * ncomp + cc];
+        v = wave_sum(v);
+        if (lane == 0) vals[cc] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && on) {
-        if (out)
-            for (int c = 0; c < ncomp; c++) out[(int64_t)inst * ncomp + c] = vals[c];
-        // FGMRES: the second-pass coefficients and |w'|^2 go straight into
-        // the Arnoldi column update of this instance
-        if (op == RED_ARNOLDI) arnoldi_column(inst, active, S, arn, vals);
-        else scalar_op(op, inst, vals, pre, S, active, maxit, slot, aux);
-    }
+    if (!on) return;   // the same for the whole block
+    if (threadIdx.x == 0 && out)
+        for (int c = 0; c < ncomp; c++) out[(int64_t)inst * ncomp + c] = vals[c];
+    // FGMRES: the second-pass coefficients and |w'|^2 go straight into the
+    // Arnoldi column update of this instance (the whole block takes part)
+    if (op == RED_ARNOLDI) arnoldi_column(inst, active, S, arn, vals, rows, rows + 64, rows + 128);
+    else if (threadIdx.x == 0) scalar_op(op, inst, vals, pre, S, active, maxit, slot, aux);
 }
 
 // Copy between the batch vector (chunk ranges) and the per-instance arrays of
@@ -604,7 +595,8 @@ void vpiezo32(const VecCtx &v, const OpDev *ops64, const double *P, float *P32)
 void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot, double *S, int32_t *active,
              int maxit, double aux, double *out, hipStream_t s)
 {
-    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, r.single, op, slot, S,
+    if (ncomp < 1 || ncomp > 64) throw Error(-1, "vreduce: 1..64 components");
+    k_reduce<<<dim3((unsigned)r.nseg), dim3(RB), 0, s>>>(partial, ncomp, r.seg_ptr, r.single, op, slot, S,
                                                           active, maxit, aux, out, ArnArgs{});
     HTS_LAUNCH_CHECK();
 }
@@ -612,7 +604,8 @@ void vreduce(const RedCtx &r, const double *partial, int ncomp, int op, int slot
 void vreduce_arnoldi(const RedCtx &r, const double *partial, int ncomp, double *S, int32_t *active,
                      const ArnArgs &arn, double *out, hipStream_t s)
 {
-    k_reduce<<<dim3((unsigned)r.nseg), dim3(VB), 0, s>>>(partial, ncomp, r.seg_ptr, r.single, RED_ARNOLDI, 0, S,
+    if (ncomp < 1 || ncomp > 64) throw Error(-1, "vreduce: 1..64 components");
+    k_reduce<<<dim3((unsigned)r.nseg), dim3(RB), 0, s>>>(partial, ncomp, r.seg_ptr, r.single, RED_ARNOLDI, 0, S,
                                                           active, 0, 0.0, out, arn);
     HTS_LAUNCH_CHECK();
 }
