@@ -11,8 +11,6 @@
 
 namespace hts {
 
-constexpr int CHUNK_LEN = 1024;       // nodes per block of the vector kernels
-constexpr int CHUNK_LEN_COARSE = 256; // nodes per block on coarse multigrid levels
 
 template <typename T>
 void launch_apply(int degree, int field, int epi, bool masked, bool graded, const OpDev *ops, const WorkItem *work,

@@ -7,6 +7,12 @@
 
 namespace hts {
 
+// Chunks: nodes per block of the vector kernels (at most 4 per thread of a
+// 256-thread block; the basis kernels assume that bound) and on the coarse
+// multigrid levels.
+constexpr int CHUNK_LEN = 1024;
+constexpr int CHUNK_LEN_COARSE = 256;
+
 struct VecCtx {
     const Chunk *chunks;       // device chunk list of the batch vectors
     int nchunk;

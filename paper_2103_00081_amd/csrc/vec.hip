@@ -147,8 +147,17 @@ __device__ __forceinline__ void block_multi_sum(const double (&a)[NC], int nc, d
     }
 }
 
+// Chunks hold at most EPT * VB nodes.  The basis kernels issue every load of
+// a thread at once: loads are unconditional (indices clamped to the chunk's
+// last node and to vector nv - 1) and the clamped terms are discarded by
+// their factors (0 weight, 0 coefficient) or by never being written out, so
+// the sums keep the order of the plain loop.
+constexpr int EPT = 4;
+static_assert(CHUNK_LEN <= EPT * VB && CHUNK_LEN_COARSE <= EPT * VB, "chunks longer than the basis kernels cover");
+
 // Partials of V_i . w (i < nv) in one pass over the chunk: every thread
-// keeps nv running sums (NB >= nv, compile-time bucket).
+// keeps NB running sums (NB >= nv, compile-time bucket; sums i >= nv are
+// not written out).
 template <typename T, int NB>
 __global__ __launch_bounds__(VB) void k_multidot(const Chunk *__restrict__ chunks, const int32_t *active,
                                                  const double *S, const T *__restrict__ V, int64_t ld,
@@ -160,11 +169,15 @@ __global__ __launch_bounds__(VB) void k_multidot(const Chunk *__restrict__ chunk
     double a[NB];
 #pragma unroll
     for (int i = 0; i < NB; i++) a[i] = 0.0;
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
-        const double we = (double)w[e];
+    const int64_t last = ch.end - 1;
+    constexpr int UN = NB <= 16 ? EPT : 1;
+#pragma unroll UN
+    for (int u = 0; u < EPT; u++) {
+        const int64_t e = ch.beg + threadIdx.x + u * VB;
+        const int64_t ec = e < ch.end ? e : last;
+        const double we = e < ch.end ? (double)w[ec] : 0.0;
 #pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < nv) a[i] += (double)V[(int64_t)i * ld + e] * we;
+        for (int i = 0; i < NB; i++) a[i] += (double)V[(int64_t)(i < nv ? i : nv - 1) * ld + ec] * we;
     }
     block_multi_sum<NB>(a, nv, sh, partial + (int64_t)blockIdx.x * ncomp);
 }
@@ -182,32 +195,37 @@ __global__ __launch_bounds__(VB) void k_orth_update(const Chunk *__restrict__ ch
     __shared__ double sh[4][NB + 1];
     __shared__ double hs[NB];
     CHUNK_PROLOGUE
-    if (threadIdx.x < nv) hs[threadIdx.x] = H[(int64_t)ch.inst * hld + threadIdx.x];
+    if (threadIdx.x < NB) hs[threadIdx.x] = (int)threadIdx.x < nv ? H[(int64_t)ch.inst * hld + threadIdx.x] : 0.0;
     __syncthreads();
     const double sc = scale_slot >= 0 ? Si[scale_slot] : 1.0;
     double a[NB], aw = 0.0;
 #pragma unroll
     for (int i = 0; i < NB; i++) a[i] = 0.0;
     const bool sums = partial != nullptr;
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
+    const int64_t last = ch.end - 1;
+    constexpr int UN = NB <= 16 ? EPT : 1;
+#pragma unroll UN
+    for (int u = 0; u < EPT; u++) {
+        const int64_t e = ch.beg + threadIdx.x + u * VB;
+        const bool in = e < ch.end;
+        const int64_t ec = in ? e : last;
         double v[NB];
-        double acc = (double)w[e];
+        double acc = (double)w[ec];
 #pragma unroll
-        for (int i = 0; i < NB; i++)
-            if (i < nv) {
-                v[i] = (double)V[(int64_t)i * ld + e];
-                acc -= hs[i] * v[i];
-            }
+        for (int i = 0; i < NB; i++) {
+            v[i] = (double)V[(int64_t)(i < nv ? i : nv - 1) * ld + ec];
+            acc -= hs[i] * v[i];
+        }
         const T wn = T(scale_slot >= 0 ? acc * sc : acc);
-        w[e] = wn;
-        if (sums) {
+        if (in) w[e] = wn;
+        if (sums && in) {
             const double wd = (double)wn;
             if (dots) {
                 // long bases read V again (cache hits) rather than hold it
                 if constexpr (NB > 24) asm volatile("" ::: "memory");
 #pragma unroll
                 for (int i = 0; i < NB; i++)
-                    if (i < nv) a[i] += (NB > 24 ? (double)V[(int64_t)i * ld + e] : v[i]) * wd;
+                    a[i] += (NB > 24 ? (double)V[(int64_t)(i < nv ? i : nv - 1) * ld + ec] : v[i]) * wd;
             }
             aw += wd * wd;
         }
