@@ -19,6 +19,31 @@ namespace {
 
 constexpr int VB = 256;
 
+// A chunk holds at most EPT * VB nodes, so a thread has at most EPT of them:
+// e[u] = beg + tid + u VB, present if below end.  The kernels read all of a
+// thread's operands before they store anything, at indices clamped to the
+// chunk's last node (c[u]), so every load can be in flight at once; values
+// of absent nodes are dropped.
+constexpr int EPT = 4;
+static_assert(CHUNK_LEN <= EPT * VB && CHUNK_LEN_COARSE <= EPT * VB, "chunks longer than EPT nodes per thread");
+
+struct Lanes {
+    int64_t e[EPT], c[EPT];
+    bool in[EPT];
+};
+
+__device__ __forceinline__ Lanes chunk_lanes(const Chunk &ch)
+{
+    Lanes l;
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        l.e[u] = ch.beg + threadIdx.x + u * VB;
+        l.in[u] = l.e[u] < ch.end;
+        l.c[u] = l.in[u] ? l.e[u] : ch.end - 1;
+    }
+    return l;
+}
+
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
     v = wave_sum(v);
@@ -50,7 +75,13 @@ __global__ __launch_bounds__(VB) void k_copy(const Chunk *__restrict__ chunks, c
                                              const double *S, const T *__restrict__ x, T *__restrict__ y)
 {
     CHUNK_PROLOGUE
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = x[e];
+    const Lanes l = chunk_lanes(ch);
+    T v[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) v[u] = x[l.c[u]];
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) y[l.e[u]] = v[u];
 }
 
 // y = a * x + b * y with a = sa * S[ia] (ia < 0: a = sa), same for b
@@ -62,10 +93,20 @@ __global__ __launch_bounds__(VB) void k_axpby(const Chunk *__restrict__ chunks, 
     CHUNK_PROLOGUE
     const T a = T(ia >= 0 ? sa * Si[ia] : sa);
     const T b = T(ib >= 0 ? sb * Si[ib] : sb);
+    const Lanes l = chunk_lanes(ch);
+    T xv[EPT], yv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) xv[u] = x[l.c[u]];
     if (b == T(0)) {
-        for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = a * x[e];
+#pragma unroll
+        for (int u = 0; u < EPT; u++)
+            if (l.in[u]) y[l.e[u]] = a * xv[u];
     } else {
-        for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = a * x[e] + b * y[e];
+#pragma unroll
+        for (int u = 0; u < EPT; u++) yv[u] = y[l.c[u]];
+#pragma unroll
+        for (int u = 0; u < EPT; u++)
+            if (l.in[u]) y[l.e[u]] = a * xv[u] + b * yv[u];
     }
 }
 
@@ -77,7 +118,16 @@ __global__ __launch_bounds__(VB) void k_jacobi(const Chunk *__restrict__ chunks,
 {
     CHUNK_PROLOGUE
     const T a = T(ic >= 0 ? c * Si[ic] : c);
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) z[e] = a * d[e] * r[e];
+    const Lanes l = chunk_lanes(ch);
+    T dv[EPT], rv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        dv[u] = d[l.c[u]];
+        rv[u] = r[l.c[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) z[l.e[u]] = a * dv[u] * rv[u];
 }
 
 // partial[blk*2 + 0] = x.y (and partial[blk*2+1] = x.w if w)
@@ -89,11 +139,21 @@ __global__ __launch_bounds__(VB) void k_dot(const Chunk *__restrict__ chunks, co
     __shared__ double sh[4];
     CHUNK_PROLOGUE
     double a = 0.0, b = 0.0;
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
-        const double xe = (double)x[e];
-        a += xe * (double)y[e];
-        if (w) b += xe * (double)w[e];
+    const Lanes l = chunk_lanes(ch);
+    T xv[EPT], yv[EPT], wv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        xv[u] = x[l.c[u]];
+        yv[u] = y[l.c[u]];
+        wv[u] = w ? w[l.c[u]] : T(0);
     }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) {
+            const double xe = (double)xv[u];
+            a += xe * (double)yv[u];
+            if (w) b += xe * (double)wv[u];
+        }
     a = block_sum(a, sh);
     if (w) b = block_sum(b, sh);
     if (threadIdx.x == 0) {
@@ -113,14 +173,26 @@ __global__ __launch_bounds__(VB) void k_cg_update(const Chunk *__restrict__ chun
     CHUNK_PROLOGUE
     const T al = T(Si[S_ALPHA]);
     double a = 0.0;
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) {
-        x[e] += al * p[e];
-        T re = r[e];
-        if (r_old) r_old[e] = re;
-        re -= al * q[e];
-        r[e] = re;
-        a += (double)re * (double)re;
+    const Lanes l = chunk_lanes(ch);
+    T xv[EPT], rv[EPT], pv[EPT], qv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        xv[u] = x[l.c[u]];
+        rv[u] = r[l.c[u]];
+        pv[u] = p[l.c[u]];
+        qv[u] = q[l.c[u]];
     }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) {
+            const int64_t e = l.e[u];
+            x[e] = xv[u] + al * pv[u];
+            T re = rv[u];
+            if (r_old) r_old[e] = re;
+            re -= al * qv[u];
+            r[e] = re;
+            a += (double)re * (double)re;
+        }
     a = block_sum(a, sh);
     if (threadIdx.x == 0) partial[2 * blockIdx.x] = a;
 }
@@ -147,13 +219,9 @@ __device__ __forceinline__ void block_multi_sum(const double (&a)[NC], int nc, d
     }
 }
 
-// Chunks hold at most EPT * VB nodes.  The basis kernels issue every load of
-// a thread at once: loads are unconditional (indices clamped to the chunk's
-// last node and to vector nv - 1) and the clamped terms are discarded by
-// their factors (0 weight, 0 coefficient) or by never being written out, so
-// the sums keep the order of the plain loop.
-constexpr int EPT = 4;
-static_assert(CHUNK_LEN <= EPT * VB && CHUNK_LEN_COARSE <= EPT * VB, "chunks longer than the basis kernels cover");
+// The basis kernels also clamp the vector index to nv - 1; the clamped
+// terms are discarded by their factors (0 weight, 0 coefficient) or by never
+// being written out, so the sums keep the order of the plain loop.
 
 // Partials of V_i . w (i < nv) in one pass over the chunk: every thread
 // keeps NB running sums (NB >= nv, compile-time bucket; sums i >= nv are
@@ -287,7 +355,13 @@ __global__ __launch_bounds__(VB) void k_convert(const Chunk *__restrict__ chunks
 {
     CHUNK_PROLOGUE
     const double c = ic >= 0 ? sc * Si[ic] : sc;
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) y[e] = TY(c * (double)x[e]);
+    const Lanes l = chunk_lanes(ch);
+    TX xv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) xv[u] = x[l.c[u]];
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) y[l.e[u]] = TY(c * (double)xv[u]);
 }
 
 // x (FP64) += c * d (type T)
@@ -298,7 +372,17 @@ __global__ __launch_bounds__(VB) void k_add_scaled(const Chunk *__restrict__ chu
 {
     CHUNK_PROLOGUE
     const double c = ic >= 0 ? sc * Si[ic] : sc;
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += VB) x[e] += c * (double)d[e];
+    const Lanes l = chunk_lanes(ch);
+    T dv[EPT];
+    double xv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        dv[u] = d[l.c[u]];
+        xv[u] = x[l.c[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) x[l.e[u]] = xv[u] + c * (double)dv[u];
 }
 
 // y[n] = v at constrained nodes of instance (n in chunk), others untouched
