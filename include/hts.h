@@ -158,6 +158,12 @@ typedef struct {
                                 (M_z + a K_z) line solves scaled by the nodal
                                 capacity, a = dt median(lambda / c_T) (Q1;
                                 Q2 uses 1)                                      */
+    int32_t extrapolate;     /* 1 (default): each field's solve starts from the
+                                linear extrapolation X^n + (dt / dt_prev)
+                                (X^n - X^{n-1}) of the last two time levels
+                                when the previous level is known (see
+                                hts_set_previous_state); 0: from X^n.  Either
+                                way the step meets the same residual test.  */
 } hts_solver_opts;
 
 typedef struct {
@@ -230,9 +236,23 @@ hts_status hts_add_line_source(hts_mesh *mesh, double x, double y, double z0, do
 hts_status hts_add_dirichlet_column(hts_mesh *mesh, hts_field field, double x, double y,
                                     double z0, double z1, const hts_timefn *value);
 
-/* Set / get a field's nodal state (host [nnode]) and the mesh time. */
+/* Set / get a field's nodal state (host [nnode]) and the mesh time.
+ * Setting a field's state forgets its previous time level. */
 hts_status hts_set_state(hts_mesh *mesh, hts_field field, const double *host, double t);
 hts_status hts_get_state(hts_mesh *mesh, hts_field field, double *host, double *t);
+
+/* The previous time level of a field: the state before the last committed
+ * step, and that step's size dt_prev (0: none known).  A committed step
+ * (hts_solve_step, hts_advance) records it; the next step starts its solve
+ * from the linear extrapolation of the two levels (opts.extrapolate), which
+ * changes the iterate's rounding, not the residual test.  A checkpoint that
+ * must resume bit for bit saves both levels: get the state and the previous
+ * state, and set both on the resumed mesh (hts_set_state first; it forgets
+ * the previous level).  host: [nnode], ignored (may be NULL) when dt_prev is
+ * 0 on set and when none is known on get.  Errors: HTS_ERR_ARG for a bad
+ * field, negative or non-finite dt_prev, or non-finite values. */
+hts_status hts_set_previous_state(hts_mesh *mesh, hts_field field, const double *host, double dt_prev);
+hts_status hts_get_previous_state(hts_mesh *mesh, hts_field field, double *host, double *dt_prev);
 
 /* Node / cell counts of a mesh. */
 hts_status hts_mesh_sizes(const hts_mesh *mesh, int64_t *nnode, int64_t *ncell);

@@ -29,7 +29,8 @@ STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_STATE", -3: "ERR_NOMEM", -4: "ERR_HIP
 EXPORTS = [
     "hts_default_opts", "hts_create_mesh", "hts_destroy_mesh", "hts_set_materials",
     "hts_set_face_bc", "hts_set_volume_source", "hts_add_line_source",
-    "hts_add_dirichlet_column", "hts_set_state", "hts_get_state", "hts_mesh_sizes",
+    "hts_add_dirichlet_column", "hts_set_state", "hts_get_state", "hts_set_previous_state",
+    "hts_get_previous_state", "hts_mesh_sizes",
     "hts_apply_operator", "hts_solve_steady_pressure", "hts_solve_step", "hts_advance",
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
     "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing", "hts_nn_num_params",
@@ -82,7 +83,8 @@ class SolverOpts(C.Structure):
                 ("gmres_restart", C.c_int32), ("cheb_degree", C.c_int32),
                 ("mg_coarse_max", C.c_int32), ("heat_cheb_degree", C.c_int32),
                 ("inner_rtol", C.c_double), ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("nn", C.c_void_p), ("verbose", C.c_int32), ("heat_precond", C.c_int32)]
+                ("nn", C.c_void_p), ("verbose", C.c_int32), ("heat_precond", C.c_int32),
+                ("extrapolate", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -136,6 +138,8 @@ def load():
         "hts_add_dirichlet_column": (st, [vp, i32, d, d, d, d, P(TimeFn)]),
         "hts_set_state": (st, [vp, i32, vp, d]),
         "hts_get_state": (st, [vp, i32, vp, P(d)]),
+        "hts_set_previous_state": (st, [vp, i32, vp, d]),
+        "hts_get_previous_state": (st, [vp, i32, vp, P(d)]),
         "hts_mesh_sizes": (st, [vp, P(C.c_int64), P(C.c_int64)]),
         "hts_apply_operator": (st, [vp, i32, i32, d, vp, vp]),
         "hts_solve_steady_pressure": (st, [vp, P(SolverOpts), P(StepStats)]),
@@ -307,6 +311,25 @@ class Mesh:
         t = C.c_double()
         _check(load().hts_get_state(self.h, field, out.ctypes.data, C.byref(t)))
         return out, t.value
+
+    def set_previous_state(self, field, values, dt_prev):
+        """The field's previous time level and the step size since it
+        (dt_prev 0 forgets it; values may then be None)."""
+        if values is None:
+            _check(load().hts_set_previous_state(self.h, field, None, dt_prev))
+            return
+        x = np.ascontiguousarray(values, dtype=np.float64)
+        if x.size != self.nnode:
+            raise ValueError("state must have %d entries" % self.nnode)
+        _check(load().hts_set_previous_state(self.h, field, x.ctypes.data, dt_prev))
+
+    def get_previous_state(self, field):
+        """(values, dt_prev) of the previous time level; values None when
+        none is known (dt_prev 0)."""
+        out = np.zeros(self.nnode)
+        dt = C.c_double()
+        _check(load().hts_get_previous_state(self.h, field, out.ctypes.data, C.byref(dt)))
+        return (out if dt.value > 0.0 else None), dt.value
 
     # --------------------------------------------------------- operators
     def apply_operator(self, field, prec, dt, x, y):

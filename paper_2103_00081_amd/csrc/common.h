@@ -119,6 +119,7 @@ enum Slot {
     // outer (FP64) system of a field solve
     S_OBB = 19, S_OTOL2, S_ORR, S_ONORM, S_OINV, S_OSTATUS, S_FSCALE,
     S_CYC = 26,                // 1 if the instance takes part in the current FGMRES cycle
+    S_XTRA = 27,               // initial guess X^n + S_XTRA (X^n - X^{n-1}); 0: X^n
     S_CHEB = 28,               // Chebyshev coefficients: 2 per step, up to 16 steps
     // learned preconditioner in an inner solve: last ||r||^2 it was applied
     // to (-1: none yet), consecutive weak iterations, fallback flag, fallbacks

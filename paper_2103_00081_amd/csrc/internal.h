@@ -166,6 +166,10 @@ struct hts_mesh {
     hts::DBuf<double> P, T;
     double t = 0.0;
     bool has_state[2] = {false, false};
+    // previous time level of each field (the state before the last committed
+    // step) and that step's size; hist_dt 0: none known
+    hts::DBuf<double> Pprev, Tprev;
+    double hist_dt[2] = {0.0, 0.0};
 
     // derived device data (rebuilt when dirty)
     bool dirty = true;

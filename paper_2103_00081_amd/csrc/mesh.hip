@@ -497,6 +497,7 @@ void hts_default_opts(hts_solver_opts *o)
     o->nn = nullptr;
     o->verbose = 0;
     o->heat_precond = 1;
+    o->extrapolate = 1;
 }
 
 // General hexahedra: det J > 0 at the 2 x 2 x 2 Gauss points of every cell
@@ -628,8 +629,12 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
         }
         m->P.alloc(&m->alloc, m->nnode);
         m->T.alloc(&m->alloc, m->nnode);
+        m->Pprev.alloc(&m->alloc, m->nnode);
+        m->Tprev.alloc(&m->alloc, m->nnode);
         m->P.zero(m->stream);
         m->T.zero(m->stream);
+        m->Pprev.zero(m->stream);
+        m->Tprev.zero(m->stream);
         *out = m.release();
     });
 }
@@ -768,6 +773,41 @@ hts_status hts_set_state(hts_mesh *m, hts_field field, const double *host, doubl
         HTS_HIP(hipStreamSynchronize(m->stream));
         m->t = t;
         m->has_state[field] = true;
+        m->hist_dt[field] = 0.0;   // the previous level no longer belongs to this state
+    });
+}
+
+hts_status hts_set_previous_state(hts_mesh *m, hts_field field, const double *host, double dt_prev)
+{
+    return guard([&] {
+        ARG_CHECK(m, "null mesh");
+        ARG_CHECK(field == 0 || field == 1, "bad field");
+        ARG_CHECK(std::isfinite(dt_prev) && dt_prev >= 0.0, "dt_prev must be finite and >= 0");
+        ARG_CHECK(host || dt_prev == 0.0, "null values with dt_prev > 0");
+        HTS_HIP(hipSetDevice(m->desc.device));
+        if (dt_prev > 0.0) {
+            for (int64_t i = 0; i < m->nnode; i++)
+                if (!std::isfinite(host[i])) throw Error(HTS_ERR_ARG, "non-finite state value");
+            DBuf<double> &s = field == 0 ? m->Pprev : m->Tprev;
+            HTS_HIP(hipMemcpyAsync(s.p, host, m->nnode * sizeof(double), hipMemcpyHostToDevice, m->stream));
+            HTS_HIP(hipStreamSynchronize(m->stream));
+        }
+        m->hist_dt[field] = dt_prev;
+    });
+}
+
+hts_status hts_get_previous_state(hts_mesh *m, hts_field field, double *host, double *dt_prev)
+{
+    return guard([&] {
+        ARG_CHECK(m, "null mesh");
+        ARG_CHECK(field == 0 || field == 1, "bad field");
+        HTS_HIP(hipSetDevice(m->desc.device));
+        if (host && m->hist_dt[field] > 0.0) {
+            DBuf<double> &s = field == 0 ? m->Pprev : m->Tprev;
+            HTS_HIP(hipMemcpyAsync(host, s.p, m->nnode * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+            HTS_HIP(hipStreamSynchronize(m->stream));
+        }
+        if (dt_prev) *dt_prev = m->hist_dt[field];
     });
 }
 

@@ -119,6 +119,7 @@ struct Batch {
     DBuf<double> partial, redout, redout2, redout3;
 
     DBuf<double> Pn, Tn, P1, T1, g, b, x, r, z, pp, q, rold, y, ld0, ld1, inner_b, inner_x;
+    DBuf<double> Pp, Tp;   // previous time level of the state (valid where hist_dt > 0)
     DBuf<float> P32, b32, x32, r32, z32, p32, q32, rold32, y32;
 
     int gm_m = 0;
@@ -228,7 +229,9 @@ struct Batch {
 
     FieldStats solve_field(int field, Hier *mg, const Tables &A, double *b64, double *x64, const hts_solver_opts &o,
                            std::vector<int32_t> participants, Hier *hprec);
-    void set_time(const std::vector<double> &tnew, const std::vector<double> &fscale);
+    void set_time(const std::vector<double> &tnew, const std::vector<double> &fscale,
+                  const std::vector<double> *xtra = nullptr);
+    std::vector<double> xtra_factors(int field, double dt, const hts_solver_opts &o) const;
     void pressure_rhs(Hier &H, bool steady);
     void heat_rhs(Hier &H);
     void gather_state();

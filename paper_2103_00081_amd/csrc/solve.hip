@@ -302,8 +302,8 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->redout2.alloc(al, (size_t)n * 64);
     B->redout3.alloc(al, (size_t)n * 64);
 
-    for (DBuf<double> *v : {&B->Pn, &B->Tn, &B->P1, &B->T1, &B->g, &B->b, &B->x, &B->r, &B->z, &B->pp, &B->q,
-                            &B->rold, &B->y, &B->ld0, &B->ld1, &B->inner_b, &B->inner_x}) {
+    for (DBuf<double> *v : {&B->Pn, &B->Tn, &B->Pp, &B->Tp, &B->P1, &B->T1, &B->g, &B->b, &B->x, &B->r, &B->z,
+                            &B->pp, &B->q, &B->rold, &B->y, &B->ld0, &B->ld1, &B->inner_b, &B->inner_x}) {
         v->alloc(al, tot);
         v->zero(s);
     }
@@ -1649,11 +1649,23 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
 }
 
 // ------------------------------------------------------------- one step
-void Batch::set_time(const std::vector<double> &tnew, const std::vector<double> &fscale)
+void Batch::set_time(const std::vector<double> &tnew, const std::vector<double> &fscale,
+                     const std::vector<double> *xtra)
 {
-    const int slots[2] = {S_TNEW, S_FSCALE};
-    const double *vals[2] = {tnew.data(), fscale.data()};
-    vset_slots(slots, 2, vals, n, S.p, s);
+    const int slots[3] = {S_TNEW, S_FSCALE, S_XTRA};
+    const double *vals[3] = {tnew.data(), fscale.data(), xtra ? xtra->data() : nullptr};
+    vset_slots(slots, xtra ? 3 : 2, vals, n, S.p, s);
+}
+
+// Extrapolation factor of each instance's initial guess: dt / dt_prev where
+// the previous time level is known, else 0 (start from X^n).
+std::vector<double> Batch::xtra_factors(int field, double dt, const hts_solver_opts &o) const
+{
+    std::vector<double> f(n, 0.0);
+    if (o.extrapolate && dt > 0.0)
+        for (int i = 0; i < n; i++)
+            if (m[i]->hist_dt[field] > 0.0) f[i] = dt / m[i]->hist_dt[field];
+    return f;
 }
 
 void Batch::pressure_rhs(Hier &H, bool steady)
@@ -1699,6 +1711,16 @@ void Batch::gather_state()
     }
     vgather_scatter(ch.p, hch, P, off, Pn.p, true, s);
     vgather_scatter(ch.p, hch, T, off, Tn.p, true, s);
+    bool hist = false;
+    for (int i = 0; i < n; i++) hist |= m[i]->hist_dt[0] > 0.0 || m[i]->hist_dt[1] > 0.0;
+    if (hist) {
+        for (int i = 0; i < n; i++) {
+            P[i] = m[i]->Pprev.p;
+            T[i] = m[i]->Tprev.p;
+        }
+        vgather_scatter(ch.p, hch, P, off, Pp.p, true, s);
+        vgather_scatter(ch.p, hch, T, off, Tp.p, true, s);
+    }
 }
 
 void Batch::scatter_state()
@@ -1710,6 +1732,16 @@ void Batch::scatter_state()
     }
     vgather_scatter(ch.p, hch, P, off, Pn.p, false, s);
     vgather_scatter(ch.p, hch, T, off, Tn.p, false, s);
+    bool hist = false;
+    for (int i = 0; i < n; i++) hist |= m[i]->hist_dt[0] > 0.0 || m[i]->hist_dt[1] > 0.0;
+    if (hist) {
+        for (int i = 0; i < n; i++) {
+            P[i] = m[i]->Pprev.p;
+            T[i] = m[i]->Tprev.p;
+        }
+        vgather_scatter(ch.p, hch, P, off, Pp.p, false, s);
+        vgather_scatter(ch.p, hch, T, off, Tp.p, false, s);
+    }
     export_state();   // completion wait (spin on the export's sequence number)
 }
 
@@ -1727,11 +1759,12 @@ FieldStats Batch::solve_pressure(double dt, bool steady_all, const hts_solver_op
         tn[i] = m[i]->t + (steady_all ? 0.0 : dt);
         fs[i] = steady ? 1.0 : dt * m[i]->B;
     }
-    set_time(tn, fs);
+    const std::vector<double> xf = xtra_factors(0, steady_all ? 0.0 : dt, o);
+    set_time(tn, fs, &xf);
     Hier &H = pressure_hier(steady, dt, o);
     pressure_rhs(H, steady);
     VecCtx v = vctx(false);
-    vcopy<double>(v, Pn.p, x.p);
+    vextrapolate(v, S_XTRA, Pn.p, Pp.p, x.p);
     vmask<double>(v, H.ops.d64.p, x.p, 0.0);
     std::vector<int32_t> all(n, 1);
     FieldStats st = solve_field(0, &H, H.ops, b.p, x.p, o, all, nullptr);
@@ -1749,7 +1782,8 @@ FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
         tn[i] = m[i]->t + dt;
         fs[i] = dt;
     }
-    set_time(tn, fs);
+    const std::vector<double> xf = xtra_factors(1, dt, o);
+    set_time(tn, fs, &xf);
     std::vector<int32_t> all(n, 1);
     set_active(all);
     VecCtx v = vctx(false);
@@ -1758,7 +1792,7 @@ FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
     launch_source_values(lsrc.p, nlsrc, S.p, lcoef.p, s);
     Hier &H = heat_prec(dt, o);
     heat_rhs(H);
-    vcopy<double>(v, Tn.p, x.p);
+    vextrapolate(v, S_XTRA, Tn.p, Tp.p, x.p);
     vmask<double>(v, H.ops.d64.p, x.p, 0.0);
     FieldStats st = solve_field(1, H.multigrid ? &H : nullptr, H.ops, b.p, x.p, o, all, &H);
     set_active(all);
@@ -1795,9 +1829,12 @@ int Batch::step(double dt, const hts_solver_opts &o, std::vector<hts_step_stats>
         std::vector<int32_t> all(n, 1);
         set_active(all);
         VecCtx v = vctx(false);
-        vcopy<double>(v, P1.p, Pn.p);
-        vcopy<double>(v, T1.p, Tn.p);
-        for (int i = 0; i < n; i++) m[i]->t += dt;
+        vshift(v, P1.p, Pn.p, Pp.p);
+        vshift(v, T1.p, Tn.p, Tp.p);
+        for (int i = 0; i < n; i++) {
+            m[i]->t += dt;
+            m[i]->hist_dt[0] = m[i]->hist_dt[1] = dt;
+        }
     }
     // no wait here: the statistics came from the solvers' exports, and the
     // caller's scatter of the state waits for the stream
@@ -2062,6 +2099,7 @@ hts_status hts_solve_steady_pressure(hts_mesh *m, const hts_solver_opts *opts, h
         HTS_HIP(hipMemcpyAsync(m->P.p, B->P1.p, m->nnode * sizeof(double), hipMemcpyDeviceToDevice, B->s));
         HTS_HIP(hipStreamSynchronize(B->s));
         m->has_state[0] = true;
+        m->hist_dt[0] = 0.0;   // not a time step: no previous level
     });
 }
 

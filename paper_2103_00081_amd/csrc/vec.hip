@@ -385,6 +385,47 @@ __global__ __launch_bounds__(VB) void k_add_scaled(const Chunk *__restrict__ chu
         if (l.in[u]) x[l.e[u]] = xv[u] + c * (double)dv[u];
 }
 
+// Initial guess from the last two time levels: x = Xn + c (Xn - Xp),
+// c = S[slot] of the instance; c == 0 copies Xn (Xp is then not read).
+__global__ __launch_bounds__(VB) void k_extrapolate(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                    const double *S, int slot, const double *__restrict__ Xn,
+                                                    const double *__restrict__ Xp, double *__restrict__ x)
+{
+    CHUNK_PROLOGUE
+    const double c = Si[slot];
+    const Lanes l = chunk_lanes(ch);
+    double a[EPT], b[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        a[u] = Xn[l.c[u]];
+        b[u] = c != 0.0 ? Xp[l.c[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) x[l.e[u]] = c != 0.0 ? a[u] + c * (a[u] - b[u]) : a[u];
+}
+
+// Xp = Xn, Xn = X1 (commit of a step, keeping the previous level)
+__global__ __launch_bounds__(VB) void k_shift(const Chunk *__restrict__ chunks, const int32_t *active,
+                                              const double *S, const double *__restrict__ X1,
+                                              double *__restrict__ Xn, double *__restrict__ Xp)
+{
+    CHUNK_PROLOGUE
+    const Lanes l = chunk_lanes(ch);
+    double a[EPT], b[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        a[u] = X1[l.c[u]];
+        b[u] = Xn[l.c[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) {
+            Xp[l.e[u]] = b[u];
+            Xn[l.e[u]] = a[u];
+        }
+}
+
 // y[n] = v at constrained nodes of instance (n in chunk), others untouched
 template <typename T>
 __global__ __launch_bounds__(VB) void k_mask(const Chunk *__restrict__ chunks, const int32_t *active,
@@ -602,6 +643,16 @@ __global__ __launch_bounds__(VB) void k_set_slots(SlotBlock b, int beg, int cnt,
 
 template <typename T>
 void vfill(const VecCtx &v, T *y, T val) { k_fill<T><<<GRID>>>(v.chunks, v.active, v.S, y, val); HTS_LAUNCH_CHECK(); }
+void vextrapolate(const VecCtx &v, int slot, const double *Xn, const double *Xp, double *x)
+{
+    k_extrapolate<<<GRID>>>(v.chunks, v.active, v.S, slot, Xn, Xp, x);
+    HTS_LAUNCH_CHECK();
+}
+void vshift(const VecCtx &v, const double *X1, double *Xn, double *Xp)
+{
+    k_shift<<<GRID>>>(v.chunks, v.active, v.S, X1, Xn, Xp);
+    HTS_LAUNCH_CHECK();
+}
 template <typename T>
 void vcopy(const VecCtx &v, const T *x, T *y) { k_copy<T><<<GRID>>>(v.chunks, v.active, v.S, x, y); HTS_LAUNCH_CHECK(); }
 template <typename T>

@@ -4,12 +4,16 @@
   library copies as given) makes the heat solve break down: the step returns
   HTS_ERR_BREAKDOWN and neither field nor the time advances, in FP64 and in
   FP32-refined mode.
-* Checkpoint / resume: the state read back after two steps and set on a
-  fresh mesh of the same scenario continues bit for bit like the
-  uninterrupted run.
+* Checkpoint / resume: the state and the previous time level read back
+  after two steps and set on a fresh mesh of the same scenario continue bit
+  for bit like the uninterrupted run.
 * Changing the time-step size keeps at most two pressure multigrid
   hierarchies; steps that alternate between three sizes give the same bits
-  as fresh meshes that only ever see one size.
+  as fresh meshes that only ever see one size (given the same two levels).
+* The extrapolated initial guess: the previous level is the state one step
+  earlier, setting a state forgets it (the next step is then the plain one
+  bit for bit), and extrapolated steps meet the same residual test in fewer
+  iterations, with answers within the solver tolerance of the plain ones.
 """
 import numpy as np
 import pytest
@@ -63,10 +67,14 @@ def test_checkpoint_resume_is_bit_exact(hts, mode):
         assert b.solve_step(s.dt, o)[0] == 0
     P, t = b.get_state(0)
     T, _ = b.get_state(1)
+    prev = [b.get_previous_state(f) for f in (0, 1)]
+    assert prev[0][1] == s.dt and prev[1][1] == s.dt
     del b
     c = hts.from_scenario(s, initial=False, opts=o)
     c.set_state(0, P, t)
     c.set_state(1, T, t)
+    for f in (0, 1):
+        c.set_previous_state(f, *prev[f])
     for _ in range(2):
         assert c.solve_step(s.dt, o)[0] == 0
     assert np.array_equal(a.get_state(0)[0], c.get_state(0)[0])
@@ -89,8 +97,52 @@ def test_alternating_step_sizes_match_fresh_meshes(hts):
         T, _ = m.get_state(1)
         f.set_state(0, P, t)
         f.set_state(1, T, t)
+        for fld in (0, 1):
+            f.set_previous_state(fld, *m.get_previous_state(fld))
         assert f.solve_step(dt, o)[0] == 0
         assert m.solve_step(dt, o)[0] == 0
         assert np.array_equal(m.get_state(0)[0], f.get_state(0)[0])
         assert np.array_equal(m.get_state(1)[0], f.get_state(1)[0])
         del f
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_extrapolated_initial_guess(hts, mode):
+    print_case("extrapolated initial guess, mode", mode)
+    s = scenario(n_steps=6)
+    ox = hts.default_opts(mode=mode, rtol=1e-8)
+    op = hts.default_opts(mode=mode, rtol=1e-8, extrapolate=0)
+    a = hts.from_scenario(s, opts=ox)
+    b = hts.from_scenario(s, opts=op)
+    assert a.get_previous_state(0) == (None, 0.0)
+    its = {0: [0, 0], 1: [0, 0]}
+    for k in range(6):
+        P_before = a.get_state(0)[0]
+        ca, sa = a.solve_step(s.dt, ox)
+        cb, sb = b.solve_step(s.dt, op)
+        assert ca == 0 and cb == 0 and max(sa["relres"]) <= 1e-8 and max(sb["relres"]) <= 1e-8
+        # the previous level is the state one step earlier, bit for bit
+        Pp, dtp = a.get_previous_state(0)
+        assert dtp == s.dt and np.array_equal(Pp, P_before)
+        if k >= 2:
+            for f in (0, 1):
+                its[f][0] += sa["iters"][f]
+                its[f][1] += sb["iters"][f]
+        # both answers solve the same systems to 1e-8: they agree to about
+        # that relative level (kappa ~ 1e3 for pressure)
+        for f in (0, 1):
+            x, y = a.get_state(f)[0], b.get_state(f)[0]
+            assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(y)
+    print("iterations over steps 3-6 (extrapolated, plain):", its)
+    assert its[0][0] + its[1][0] < its[0][1] + its[1][1]
+    # setting the state forgets the previous level: the next step is the
+    # plain step from that state
+    c = hts.from_scenario(s, initial=False, opts=ox)
+    d = hts.from_scenario(s, initial=False, opts=op)
+    for m in (c, d):
+        for f in (0, 1):
+            m.set_state(f, *a.get_state(f))
+    assert c.get_previous_state(1) == (None, 0.0)
+    assert c.solve_step(s.dt, ox)[0] == 0 and d.solve_step(s.dt, op)[0] == 0
+    for f in (0, 1):
+        assert np.array_equal(c.get_state(f)[0], d.get_state(f)[0])

@@ -297,8 +297,9 @@ def test_cached_batch_is_dropped_when_a_mesh_changes(hts):
     s1.bcs = list(s1.bcs) + [synth.FaceBC(synth.TEMPERATURE, 5, synth.DIRICHLET, hot)]
     c = [hts.from_scenario(scns[0], opts=o), hts.from_scenario(s1, opts=o)]
     for m, src in zip(c, a):
-        m.set_state(0, src.get_state(0)[0], src.get_state(0)[1])
-        m.set_state(1, src.get_state(1)[0], src.get_state(1)[1])
+        for f in (0, 1):
+            m.set_state(f, src.get_state(f)[0], src.get_state(f)[1])
+            m.set_previous_state(f, *src.get_previous_state(f))
     hts.advance(c, 1, scns[0].dt, o)
     for mb, mc in zip(b, c):
         assert np.array_equal(mb.get_state(0)[0], mc.get_state(0)[0])
