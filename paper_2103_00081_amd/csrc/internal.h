@@ -212,6 +212,6 @@ inline int kernel_degree(const hts_mesh *m) { return m->general ? DEGREE_HEX : m
 int tile_own_x(int degree, int field);          // owned node columns per tile of the operator kernels, x
 int tile_own_y(int degree, int field);          // and y
 // node planes per work item of the operator kernels (force > 0: that depth)
-int zc_for(const hts_mesh *M, int field, int64_t tiles, int force);
+int zc_for(const hts_mesh *M, int field, int prec, int64_t tiles, int force);
 
 }  // namespace hts

@@ -120,7 +120,7 @@ extern "C" hts_status hts_apply_operator_noalloc(hts_mesh *m, hts_field field, h
         const bool steady = field == 0 && (dt <= 0.0 || m->B <= 0.0);
         const int ox = tile_own_x(kernel_degree(m), field), oy = tile_own_y(kernel_degree(m), field);
         const int ntx = (m->N[0] + ox - 1) / ox, nty = (m->N[1] + oy - 1) / oy;
-        const int zc = zc_for(m, field, (int64_t)ntx * nty, 0);
+        const int zc = zc_for(m, field, fp32 ? 1 : 0, (int64_t)ntx * nty, 0);
         const int64_t nzc = (m->N[2] + zc - 1) / zc;
         const int64_t nwork = (int64_t)ntx * nty * nzc;
         const int nsrc = field == 1 ? (int)m->line_srcs.size() : 0;

@@ -95,13 +95,15 @@ struct Batch {
     int nch = 0;
     DBuf<int32_t> chp;
     RedCtx rch{};
-    // fine-level work lists per field (the z-chunk depth is tuned per field)
-    std::vector<WorkItem> hwork[2];
-    DBuf<WorkItem> work[2];
-    int nwork[2] = {0, 0};
-    DBuf<int32_t> wkp[2];
-    RedCtx rwk[2]{};
-    int zc_force[2] = {0, 0};
+    // fine-level work lists per field and precision (index [field][prec],
+    // prec 0 FP64, 1 FP32: the z-chunk depth is tuned per field and
+    // precision)
+    std::vector<WorkItem> hwork[2][2];
+    DBuf<WorkItem> work[2][2];
+    int nwork[2][2] = {{0, 0}, {0, 0}};
+    DBuf<int32_t> wkp[2][2];
+    RedCtx rwk[2][2]{};
+    int zc_force[2][2] = {{0, 0}, {0, 0}};
 
     DBuf<double> S;
     DBuf<int32_t> active;
@@ -179,7 +181,7 @@ struct Batch {
     void replay(const std::string &key, const std::function<void()> &body);
 
     ~Batch();
-    int pick_zc(int field, const hts_mesh *M, int64_t tiles) const;
+    int pick_zc(int field, int prec, const hts_mesh *M, int64_t tiles) const;
     void build_work();
     void make_tables(Tables &t, int field, double dt, bool steady, bool mass_only);
     Tables &apply_tables(int field, double dt, bool steady)
@@ -249,8 +251,8 @@ void nn_precondition(hts_nn *nn, Batch &B, int inst, const double *r, double *z,
 void nn_prepare(hts_nn *nn, Batch &B);
 uint64_t nn_serial(const hts_nn *nn);
 // tuned z-chunk depth of the fine operator kernels (0 = none recorded)
-int tuned_zc(int degree, int field, int NX, int NY, int NZ);
-void set_tuned_zc(int degree, int field, int NX, int NY, int NZ, int zc);
+int tuned_zc(int degree, int field, int prec, int NX, int NY, int NZ);
+void set_tuned_zc(int degree, int field, int prec, int NX, int NY, int NZ, int zc);
 void save_tuning();
 std::shared_ptr<Batch> solo_batch(hts_mesh *m);
 // cached batch of several meshes (same meshes, same order)

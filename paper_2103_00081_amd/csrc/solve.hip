@@ -117,10 +117,10 @@ namespace {
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_key(int degree, int field, int NX, int NY, int NZ)
+std::string tune_key(int degree, int field, int prec, int NX, int NY, int NZ)
 {
     char b[96];
-    snprintf(b, sizeof(b), "q%d_f%d_%dx%dx%d", degree, field, NX, NY, NZ);
+    snprintf(b, sizeof(b), "q%d_f%d_%s_%dx%dx%d", degree, field, prec ? "fp32" : "fp64", NX, NY, NZ);
     return b;
 }
 
@@ -164,18 +164,18 @@ void tune_save()
 }
 }  // namespace
 
-void set_tuned_zc(int degree, int field, int NX, int NY, int NZ, int zc)
+void set_tuned_zc(int degree, int field, int prec, int NX, int NY, int NZ, int zc)
 {
     tune_load();
-    g_tune[tune_key(degree, field, NX, NY, NZ)] = zc;
+    g_tune[tune_key(degree, field, prec, NX, NY, NZ)] = zc;
 }
 
 void save_tuning() { tune_save(); }
 
-int tuned_zc(int degree, int field, int NX, int NY, int NZ)
+int tuned_zc(int degree, int field, int prec, int NX, int NY, int NZ)
 {
     tune_load();
-    auto it = g_tune.find(tune_key(degree, field, NX, NY, NZ));
+    auto it = g_tune.find(tune_key(degree, field, prec, NX, NY, NZ));
     return it == g_tune.end() ? 0 : it->second;
 }
 
@@ -184,13 +184,17 @@ int tuned_zc(int degree, int field, int NX, int NY, int NZ)
 int tile_own_x(int degree, int field) { return degree == 2 ? 30 : (field == 0 && degree == 1 ? 31 : 15); }
 int tile_own_y(int degree, int field) { return degree == 2 ? 30 : 15; }
 
-int zc_for(const hts_mesh *M, int field, int64_t tiles, int force)
+// work-list / tuning index of an operand type: 0 FP64, 1 FP32
+template <typename T>
+constexpr int prec_of() { return std::is_same<T, double>::value ? 0 : 1; }
+
+int zc_for(const hts_mesh *M, int field, int prec, int64_t tiles, int force)
 {
     const int NZ = M->N[2];
     // Q2 work items start on even node planes (cell-layer boundaries)
     auto fit = [&](int z) { return M->p == 2 ? std::max(2, (std::min(z, NZ) + 1) / 2 * 2) : std::min(z, NZ); };
     if (force > 0) return fit(force);
-    const int t = tuned_zc(kernel_degree(M), field, M->N[0], M->N[1], NZ);
+    const int t = tuned_zc(kernel_degree(M), field, prec, M->N[0], M->N[1], NZ);
     if (t > 0) return fit(t);
     // enough blocks to fill 256 CUs several times over
     int64_t z = std::max<int64_t>(4, (tiles * NZ) / 2048);
@@ -198,22 +202,23 @@ int zc_for(const hts_mesh *M, int field, int64_t tiles, int force)
     return fit((int)z);
 }
 
-int Batch::pick_zc(int field, const hts_mesh *M, int64_t tiles) const
+int Batch::pick_zc(int field, int prec, const hts_mesh *M, int64_t tiles) const
 {
-    return zc_for(M, field, tiles, zc_force[field]);
+    return zc_for(M, field, prec, tiles, zc_force[field][prec]);
 }
 
 void Batch::build_work()
 {
     drop_graphs();
-    for (int f = 0; f < 2; f++) {
+    for (int f = 0; f < 2; f++)
+    for (int pr = 0; pr < 2; pr++) {
         std::vector<WorkItem> nat;
         for (int i = 0; i < n; i++) {
             hts_mesh *M = m[i];
             // owned node columns per tile along x and y
             const int ox = tile_own_x(kernel_degree(M), f), oy = tile_own_y(kernel_degree(M), f);
             const int tx = (M->N[0] + ox - 1) / ox, ty = (M->N[1] + oy - 1) / oy;
-            const int zc = pick_zc(f, M, (int64_t)tx * ty);
+            const int zc = pick_zc(f, pr, M, (int64_t)tx * ty);
             for (int z0 = 0; z0 < M->N[2]; z0 += zc)
                 for (int y = 0; y < ty; y++)
                     for (int x = 0; x < tx; x++) {
@@ -226,23 +231,26 @@ void Batch::build_work()
         // XCD-aware order: block b is dispatched to XCD b % 8; give each XCD a
         // contiguous run of neighbouring tiles so halos stay in its L2.
         const int64_t T = (int64_t)nat.size(), per = (T + 7) / 8;
-        hwork[f].clear();
+        hwork[f][pr].clear();
         for (int64_t b = 0; b < 8 * per; b++) {
             int64_t idx = (b % 8) * per + b / 8;
-            if (idx < T) hwork[f].push_back(nat[idx]);
+            if (idx < T) hwork[f][pr].push_back(nat[idx]);
         }
-        nwork[f] = (int)hwork[f].size();
-        work[f].upload(al, hwork[f], s);
+        nwork[f][pr] = (int)hwork[f][pr].size();
+        work[f][pr].upload(al, hwork[f][pr], s);
         // a block writes its partial sum at the tile's natural index, so the
         // partials of an instance are contiguous and reduced in natural tile
         // order: a batched instance sums exactly like the same instance alone
         std::vector<int32_t> sp(n + 1, 0);
         for (const WorkItem &w : nat) sp[w.inst + 1]++;
         for (int i = 0; i < n; i++) sp[i + 1] += sp[i];
-        wkp[f].upload(al, sp, s);
-        rwk[f] = RedCtx{wkp[f].p, n, n == 1 ? sp[1] : -1};
+        wkp[f][pr].upload(al, sp, s);
+        rwk[f][pr] = RedCtx{wkp[f][pr].p, n, n == 1 ? sp[1] : -1};
     }
-    partial.alloc(al, (size_t)std::max<int64_t>(std::max(nwork[0], nwork[1]), nch) * 64 + 64);
+    int64_t mw = nch;
+    for (int f = 0; f < 2; f++)
+        for (int pr = 0; pr < 2; pr++) mw = std::max<int64_t>(mw, nwork[f][pr]);
+    partial.alloc(al, (size_t)mw * 64 + 64);
 }
 
 std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
@@ -505,9 +513,10 @@ static double apply_flops(int field, int p, int64_t cells)
 template <typename T>
 void Batch::fine_apply(int field, const OpDev *ops, int epi, bool masked, const T *x, T *y, const EpiArgs<T> &ep)
 {
+    constexpr int pr = std::is_same<T, double>::value ? 0 : 1;
     if (!g_timing.on) {
-        launch_apply<T>(general ? DEGREE_HEX : p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y,
-                        ep, s);
+        launch_apply<T>(general ? DEGREE_HEX : p, field, epi, masked, graded, ops, work[field][pr].p,
+                        nwork[field][pr], x, y, ep, s);
         return;
     }
     TimingRec r{};
@@ -518,8 +527,8 @@ void Batch::fine_apply(int field, const OpDev *ops, int epi, bool masked, const 
     r.bytes = apply_bytes(field, epi, ntot, ctot, sizeof(T));
     r.flops = apply_flops(field, p, ctot);
     HTS_HIP(hipEventRecord(r.a, s));
-    launch_apply<T>(general ? DEGREE_HEX : p, field, epi, masked, graded, ops, work[field].p, nwork[field], x, y, ep,
-                    s);
+    launch_apply<T>(general ? DEGREE_HEX : p, field, epi, masked, graded, ops, work[field][pr].p, nwork[field][pr], x,
+                    y, ep, s);
     HTS_HIP(hipEventRecord(r.b, s));
     g_timing.recs.push_back(r);
 }
@@ -1240,7 +1249,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
     ep.partial = partial.p;
     exported_last = false;
     apply_op<T>(A, EPI_RESID_NORM, true, x, r, ep);
-    vreduce(rwk[A.field], partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+    vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
     const bool hook = std::is_same<T, double>::value && cg_hook;
     const bool graphed = use_graph && !hook && !g_timing.on;
     // (replayed chunks skip instances that converged at the start, so only
@@ -1279,7 +1288,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
                     EpiArgs<T> e2{};
                     e2.partial = partial.p;
                     apply_op<T>(A, EPI_DOT, true, pv, q, e2);
-                    vreduce(rwk[A.field], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+                    vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
                     vcg_update<T>(vg, x, r, pv, q, ro, partial.p);
                     vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
                     M(r, z);
@@ -1305,7 +1314,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
         EpiArgs<T> e2{};
         e2.partial = partial.p;
         apply_op<T>(A, EPI_DOT, true, pv, q, e2);
-        vreduce(rwk[A.field], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+        vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
         vcg_update<T>(v, x, r, pv, q, ro, partial.p);
         if (hook) cg_hook(reinterpret_cast<const double *>(x), it);
         vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
@@ -1341,7 +1350,7 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
         ep.b = b;
         ep.partial = partial.p;
         apply_op<T>(A, EPI_RESID_NORM, true, x, V, ep);
-        vreduce(rwk[A.field], partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
+        vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
         // which instances take part (S_CYC) is read back with the first
         // check of the Arnoldi steps, not on its own
         gm_begin(n, active.p, S.p, gg.p, mres, gkdim.p, s);
@@ -1489,7 +1498,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         ep.b = b64;
         ep.partial = partial.p;
         apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
-        vreduce(rwk[A.field], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
+        vreduce(rwk[A.field][0], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
         outer_check(n, active.p, S.p, redout.p, s);
         HTS_HIP(hipEventRecord(e1, s));
         // The first check is read back with the inner solve's last export
@@ -1615,7 +1624,7 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
         if (stop) {
             // final judge with the last update
             apply_op<double>(A, EPI_RESID_NORM, true, x64, this->y.p, ep);
-            vreduce(rwk[A.field], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
+            vreduce(rwk[A.field][0], partial.p, 1, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
             outer_check(n, active.p, S.p, redout.p, s);
             HTS_HIP(hipEventRecord(e1, s));
             outer = get_active();
@@ -2005,7 +2014,7 @@ hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
     return guard_call([&] {
         if (!meshes || n < 1) throw Error(HTS_ERR_ARG, "no meshes");
         for (int i = 0; i < n; i++) check_ready(meshes[i]);
-        tuned_zc(1, 0, 0, 0, 0);   // load the cache file once
+        tuned_zc(1, 0, 0, 0, 0, 0);   // load the cache file once
         for (int i = 0; i < n; i++) {
             hts_mesh *m = meshes[i];
             HTS_HIP(hipSetDevice(m->desc.device));
@@ -2022,22 +2031,23 @@ hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
             launch_source_values(b.lsrc.p, b.nlsrc, b.S.p, b.lcoef.p, b.s);
             vfill<double>(v, b.inner_x.p, 1.0);
             vfill<float>(v, b.x32.p, 1.0f);
-            hipEvent_t e0, e1;
+            hipEvent_t e0, e1, e2;
             HTS_HIP(hipEventCreate(&e0));
             HTS_HIP(hipEventCreate(&e1));
+            HTS_HIP(hipEventCreate(&e2));
             for (int f = 0; f < 2; f++) {
                 Tables &t = b.apply_tables(f, dt, f == 0 && m->B <= 0.0);
                 const int cands[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 48, 64};
-                double best = 1e30;
-                int bz = 0;
+                double best[2] = {1e30, 1e30};
+                int bz[2] = {0, 0};
                 std::vector<int> tried;
                 for (int zc : cands) {
-                    if (zc > m->N[2] && bz > 0) break;
+                    if (zc > m->N[2] && bz[0] > 0) break;
                     // Q2 depths are rounded up to whole cell layers
-                    const int eff = zc_for(m, f, 1, zc);
+                    const int eff = zc_for(m, f, 0, 1, zc);
                     if (std::find(tried.begin(), tried.end(), eff) != tried.end()) continue;
                     tried.push_back(eff);
-                    b.zc_force[f] = zc;
+                    b.zc_force[f][0] = b.zc_force[f][1] = zc;
                     b.build_work();
                     EpiArgs<double> e64{};
                     e64.b = b.inner_x.p;
@@ -2047,28 +2057,33 @@ hts_status hts_autotune(hts_mesh *const *meshes, int32_t n)
                         b.apply_op<double>(t, EPI_RESID, true, b.inner_x.p, b.y.p, e64);
                         b.apply_op<float>(t, EPI_RESID, true, b.x32.p, b.y32.p, e32);
                     }
+                    // each precision timed on its own (their kernels differ in
+                    // registers and occupancy, so their best depths differ)
                     HTS_HIP(hipEventRecord(e0, b.s));
-                    for (int r = 0; r < 10; r++) {
-                        b.apply_op<double>(t, EPI_RESID, true, b.inner_x.p, b.y.p, e64);
-                        b.apply_op<float>(t, EPI_RESID, true, b.x32.p, b.y32.p, e32);
-                    }
+                    for (int r = 0; r < 10; r++) b.apply_op<double>(t, EPI_RESID, true, b.inner_x.p, b.y.p, e64);
                     HTS_HIP(hipEventRecord(e1, b.s));
-                    HTS_HIP(hipEventSynchronize(e1));
-                    float ms = 0.0f;
-                    HTS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    for (int r = 0; r < 10; r++) b.apply_op<float>(t, EPI_RESID, true, b.x32.p, b.y32.p, e32);
+                    HTS_HIP(hipEventRecord(e2, b.s));
+                    HTS_HIP(hipEventSynchronize(e2));
+                    float ms[2] = {0.0f, 0.0f};
+                    HTS_HIP(hipEventElapsedTime(&ms[0], e0, e1));
+                    HTS_HIP(hipEventElapsedTime(&ms[1], e1, e2));
                     static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 0.0;
                     if (verbose)
-                        std::fprintf(stderr, "[hts] autotune q%d field %d %dx%dx%d z-depth %d: %d blocks, %.2f us per "
-                                     "FP64 + FP32 pair\n", m->p, f, m->N[0], m->N[1], m->N[2], zc, b.nwork[f],
-                                     100.0 * ms);
-                    if (ms < best) {
-                        best = ms;
-                        bz = zc;
-                    }
+                        std::fprintf(stderr, "[hts] autotune q%d field %d %dx%dx%d z-depth %d: %d blocks, %.2f us FP64, "
+                                     "%.2f us FP32\n", m->p, f, m->N[0], m->N[1], m->N[2], zc, b.nwork[f][0],
+                                     100.0 * ms[0], 100.0 * ms[1]);
+                    for (int pr = 0; pr < 2; pr++)
+                        if (ms[pr] < best[pr]) {
+                            best[pr] = ms[pr];
+                            bz[pr] = zc;
+                        }
                 }
-                b.zc_force[f] = 0;
-                set_tuned_zc(kernel_degree(m), f, m->N[0], m->N[1], m->N[2], bz);
+                b.zc_force[f][0] = b.zc_force[f][1] = 0;
+                for (int pr = 0; pr < 2; pr++)
+                    set_tuned_zc(kernel_degree(m), f, pr, m->N[0], m->N[1], m->N[2], bz[pr]);
             }
+            (void)hipEventDestroy(e2);
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
         }
