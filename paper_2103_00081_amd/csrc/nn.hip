@@ -727,6 +727,7 @@ hts_status hts_nn_harvest(hts_nn *nn, hts_mesh *const *meshes, int32_t n_draws, 
         o.mode = HTS_MODE_FP64;
         o.rtol = 1e-10;
         o.max_iter = 200;
+        o.extrapolate = 0;   // plain warm starts: the march does not keep time levels
         for (int d = 0; d < n_draws; d++) {
             hts_mesh *m = meshes[d];
             HTS_HIP(hipSetDevice(m->desc.device));
@@ -746,6 +747,15 @@ hts_status hts_nn_harvest(hts_nn *nn, hts_mesh *const *meshes, int32_t n_draws, 
             Batch &B = *Bp;
             B.gather_state();
             const double t0 = m->t;
+            // the march below advances the batch's pressure, which is the
+            // mesh's own state for a single mesh: keep it and put it back
+            DBuf<double> psave;
+            psave.alloc(B.al, (size_t)n);
+            HTS_HIP(hipMemcpyAsync(psave.p, B.Pn.p, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, B.s));
+            auto restore = [&] {
+                (void)hipMemcpyAsync(B.Pn.p, psave.p, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, B.s);
+                (void)hipStreamSynchronize(B.s);
+            };
             DBuf<double> iters, e, r;
             DBuf<float> tmp;
             iters.alloc(B.al, (size_t)(o.max_iter + 1) * n);
@@ -812,11 +822,13 @@ hts_status hts_nn_harvest(hts_nn *nn, hts_mesh *const *meshes, int32_t n_draws, 
                 B.cg_hook = nullptr;
                 B.inner_hook = nullptr;
                 m->t = t0;
+                restore();
                 throw;
             }
             B.cg_hook = nullptr;
             B.inner_hook = nullptr;
             m->t = t0;
+            restore();
             HTS_HIP(hipStreamSynchronize(B.s));
         }
     });

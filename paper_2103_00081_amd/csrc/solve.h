@@ -122,6 +122,9 @@ struct Batch {
 
     DBuf<double> Pn, Tn, P1, T1, g, b, x, r, z, pp, q, rold, y, ld0, ld1, inner_b, inner_x;
     DBuf<double> Pp, Tp;   // previous time level of the state (valid where hist_dt > 0)
+    // one instance: Pn, Tn, Pp, Tp are the mesh's own state buffers (no
+    // gather or scatter copies)
+    bool alias_state = false;
     DBuf<float> P32, b32, x32, r32, z32, p32, q32, rold32, y32;
 
     int gm_m = 0;

@@ -310,7 +310,24 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     B->redout2.alloc(al, (size_t)n * 64);
     B->redout3.alloc(al, (size_t)n * 64);
 
-    for (DBuf<double> *v : {&B->Pn, &B->Tn, &B->Pp, &B->Tp, &B->P1, &B->T1, &B->g, &B->b, &B->x, &B->r, &B->z,
+    B->alias_state = n == 1;
+    if (B->alias_state) {
+        // views of the mesh's buffers (no allocator: not released here)
+        hts_mesh *M = ms[0];
+        DBuf<double> *views[4] = {&B->Pn, &B->Tn, &B->Pp, &B->Tp};
+        double *bufs[4] = {M->P.p, M->T.p, M->Pprev.p, M->Tprev.p};
+        for (int k = 0; k < 4; k++) {
+            views[k]->p = bufs[k];
+            views[k]->n = (size_t)tot;
+            views[k]->al = nullptr;
+        }
+    } else {
+        for (DBuf<double> *v : {&B->Pn, &B->Tn, &B->Pp, &B->Tp}) {
+            v->alloc(al, tot);
+            v->zero(s);
+        }
+    }
+    for (DBuf<double> *v : {&B->P1, &B->T1, &B->g, &B->b, &B->x, &B->r, &B->z,
                             &B->pp, &B->q, &B->rold, &B->y, &B->ld0, &B->ld1, &B->inner_b, &B->inner_x}) {
         v->alloc(al, tot);
         v->zero(s);
@@ -1713,6 +1730,7 @@ void Batch::heat_rhs(Hier &H)
 // instances (a copy per instance would cost one launch each).
 void Batch::gather_state()
 {
+    if (alias_state) return;
     std::vector<double *> P(n), T(n);
     for (int i = 0; i < n; i++) {
         P[i] = m[i]->P.p;
@@ -1734,6 +1752,10 @@ void Batch::gather_state()
 
 void Batch::scatter_state()
 {
+    if (alias_state) {
+        export_state();   // completion wait
+        return;
+    }
     std::vector<double *> P(n), T(n);
     for (int i = 0; i < n; i++) {
         P[i] = m[i]->P.p;
