@@ -315,8 +315,11 @@ hts_status hts_advance(hts_mesh *const *meshes, int32_t n_instances, int32_t n_s
 hts_status hts_apply_operator_noalloc(hts_mesh *m, hts_field field, hts_precision prec, double dt,
                                       const void *x_dev, void *y_dev);
 
-/* Time several operator tile shapes on these meshes and keep the fastest
- * per (degree, field, precision, size class) for later launches. */
+/* Time the fine-level operators of these meshes at several z-chunk depths
+ * (node planes one workgroup marches through) and keep the fastest per
+ * (kernel family, field, precision, node dims) for later launches; with
+ * HTS_TUNE_CACHE set to a path the choices are also written there and read
+ * back by later processes.  Forgets the meshes' cached batches (graphs). */
 hts_status hts_autotune(hts_mesh *const *meshes, int32_t n);
 
 /* Device time and algorithmic traffic of the matrix-free fine-level
