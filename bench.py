@@ -108,13 +108,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--cheb", type=int, default=2, help="pressure multigrid Chebyshev degree")
-    ap.add_argument("--heat-cheb", type=int, default=2, help="heat Chebyshev-Jacobi degree")
+    ap.add_argument("--heat-cheb", type=int, default=4, help="heat Chebyshev-Jacobi degree")
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--mg-coarse-max", type=int, default=None,
                     help="coarsen until a level has at most this many nodes (dense FP64 solve there); "
                          "default 5000 for one mesh, 600 per instance for the batch")
     ap.add_argument("--heat-precond", type=int, default=1, help="0 multigrid, 1 Chebyshev-Jacobi, 2 separable mass")
+    ap.add_argument("--gmres-restart", type=int, default=30, help="FGMRES restart length of the heat solve")
     ap.add_argument("--use-graph", type=int, default=1,
                     help="replay captured HIP graphs for the Krylov iteration chunks (1) or launch eagerly (0)")
     ap.add_argument("--timing-steps", type=int, default=3,
@@ -361,6 +362,7 @@ def main():
         o = hts.default_opts(mode=mode_id[mode], rtol=1e-8, check_every=a.check_every,
                              cheb_degree=a.cheb, heat_cheb_degree=a.heat_cheb,
                              inner_rtol=a.inner_rtol, heat_precond=a.heat_precond,
+                             gmres_restart=a.gmres_restart,
                              use_graph=a.use_graph, mg_coarse_max=a.mg_coarse_max)
         ms = []
         for i, sc in enumerate(scns):
@@ -536,7 +538,8 @@ def main():
                    "seed": seed, "cheb_degree": a.cheb, "heat_cheb_degree": a.heat_cheb,
                    "inner_rtol": a.inner_rtol, "autotune": not a.no_autotune, "use_graph": bool(a.use_graph),
                    "mg_coarse_max": a.mg_coarse_max,
-                   "heat_precond": ["multigrid", "chebyshev-jacobi", "tensor-mass"][a.heat_precond]},
+                   "heat_precond": ["multigrid", "chebyshev-jacobi", "tensor-mass"][a.heat_precond],
+                   "gmres_restart": a.gmres_restart},
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
         "step_bound": step_bound(R, R["nnode"], best),

@@ -142,7 +142,12 @@ typedef struct {
                                 many nodes; that level is solved with a dense
                                 FP64 inverse (n^2 entries, read whole by every
                                 coarse solve)                                 */
-    int32_t heat_cheb_degree;/* degree of the heat Chebyshev-Jacobi preconditioner */
+    int32_t heat_cheb_degree;/* degree of the heat Chebyshev-Jacobi preconditioner
+                                (4); its polynomial is the Chebyshev one of the
+                                ellipse over the real interval of D^-1 A with
+                                the imaginary extent of the convection term;
+                                instances whose imaginary extent reaches the
+                                interval's half-width keep degree 2          */
     double inner_rtol;       /* inner tolerance of FP32_REFINED (1e-5)          */
     int32_t check_every;     /* host convergence check every n iterations (1)   */
     int32_t use_graph;       /* replay captured HIP graphs for time steps       */
@@ -253,6 +258,18 @@ hts_status hts_get_state(hts_mesh *mesh, hts_field field, double *host, double *
  * field, negative or non-finite dt_prev, or non-finite values. */
 hts_status hts_set_previous_state(hts_mesh *mesh, hts_field field, const double *host, double dt_prev);
 hts_status hts_get_previous_state(hts_mesh *mesh, hts_field field, double *host, double *dt_prev);
+
+/* Spectral estimates behind the heat Chebyshev preconditioner of a mesh:
+ * v[0] the step size they were made for (0: none), v[1] and v[2] the largest
+ * eigenvalue of D^-1 A without and with the convection term, v[3] the
+ * imaginary extent of D^-1 A (the convection term's).  They depend on the
+ * Darcy flux of the step in which the preconditioner was first built for
+ * that dt, and are reused while dt stays (a new dt or changed coefficients
+ * or boundary data estimate again).  A checkpoint that must resume bit for
+ * bit saves them with the state and the previous level.  set: entries must
+ * be finite and >= 0, v[1], v[2] > 0 unless v[0] is 0; HTS_ERR_ARG else. */
+hts_status hts_get_heat_spectrum(hts_mesh *mesh, double *v4);
+hts_status hts_set_heat_spectrum(hts_mesh *mesh, const double *v4);
 
 /* Node / cell counts of a mesh. */
 hts_status hts_mesh_sizes(const hts_mesh *mesh, int64_t *nnode, int64_t *ncell);

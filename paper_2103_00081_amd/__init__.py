@@ -30,7 +30,7 @@ EXPORTS = [
     "hts_default_opts", "hts_create_mesh", "hts_destroy_mesh", "hts_set_materials",
     "hts_set_face_bc", "hts_set_volume_source", "hts_add_line_source",
     "hts_add_dirichlet_column", "hts_set_state", "hts_get_state", "hts_set_previous_state",
-    "hts_get_previous_state", "hts_mesh_sizes",
+    "hts_get_previous_state", "hts_get_heat_spectrum", "hts_set_heat_spectrum", "hts_mesh_sizes",
     "hts_apply_operator", "hts_solve_steady_pressure", "hts_solve_step", "hts_advance",
     "hts_autotune", "hts_last_error", "hts_nn_create", "hts_nn_destroy", "hts_nn_harvest",
     "hts_nn_train", "hts_nn_save", "hts_nn_load", "hts_kernel_timing", "hts_nn_num_params",
@@ -139,6 +139,8 @@ def load():
         "hts_set_state": (st, [vp, i32, vp, d]),
         "hts_get_state": (st, [vp, i32, vp, P(d)]),
         "hts_set_previous_state": (st, [vp, i32, vp, d]),
+        "hts_get_heat_spectrum": (st, [vp, vp]),
+        "hts_set_heat_spectrum": (st, [vp, vp]),
         "hts_get_previous_state": (st, [vp, i32, vp, P(d)]),
         "hts_mesh_sizes": (st, [vp, P(C.c_int64), P(C.c_int64)]),
         "hts_apply_operator": (st, [vp, i32, i32, d, vp, vp]),
@@ -322,6 +324,19 @@ class Mesh:
         if x.size != self.nnode:
             raise ValueError("state must have %d entries" % self.nnode)
         _check(load().hts_set_previous_state(self.h, field, x.ctypes.data, dt_prev))
+
+    def get_heat_spectrum(self):
+        """(dt, lmax without convection, lmax with convection, imaginary
+        extent) behind the heat preconditioner; dt 0 when none was made."""
+        out = np.zeros(4)
+        _check(load().hts_get_heat_spectrum(self.h, out.ctypes.data))
+        return tuple(float(v) for v in out)
+
+    def set_heat_spectrum(self, values):
+        x = np.ascontiguousarray(values, dtype=np.float64)
+        if x.size != 4:
+            raise ValueError("4 values")
+        _check(load().hts_set_heat_spectrum(self.h, x.ctypes.data))
 
     def get_previous_state(self, field):
         """(values, dt_prev) of the previous time level; values None when

@@ -170,6 +170,11 @@ struct hts_mesh {
     // step) and that step's size; hist_dt 0: none known
     hts::DBuf<double> Pprev, Tprev;
     double hist_dt[2] = {0.0, 0.0};
+    // spectral estimates of the heat preconditioner (they depend on the
+    // Darcy flux of the step that made them): dt, lmax of D^-1 A without and
+    // with convection, imaginary extent; dt 0: none.  Reused by any batch
+    // that builds the heat preconditioner for the same dt.
+    double heat_spec[4] = {0.0, 0.0, 0.0, 0.0};
 
     // derived device data (rebuilt when dirty)
     bool dirty = true;

@@ -490,7 +490,7 @@ void hts_default_opts(hts_solver_opts *o)
     o->gmres_restart = 30;
     o->cheb_degree = 2;
     o->mg_coarse_max = 600;
-    o->heat_cheb_degree = 2;
+    o->heat_cheb_degree = 4;
     o->inner_rtol = 1e-5;
     o->check_every = 1;
     o->use_graph = 0;
@@ -698,6 +698,7 @@ hts_status hts_set_materials(hts_mesh *m, const hts_materials *mat)
         m->cT32.upload(&m->alloc, f, m->stream);
         m->has_mat = true;
         m->dirty = true;
+        m->heat_spec[0] = 0.0;   // operator data changed: the heat spectrum is estimated again
     });
 }
 
@@ -719,6 +720,7 @@ hts_status hts_set_face_bc(hts_mesh *m, hts_field field, int32_t face, int32_t k
         v.erase(std::remove_if(v.begin(), v.end(), [&](const FaceSpec &f) { return f.face == face; }), v.end());
         if (kind != HTS_BC_NONE) v.push_back({face, kind, *value});
         m->dirty = true;
+        m->heat_spec[0] = 0.0;   // operator data changed: the heat spectrum is estimated again
     });
 }
 
@@ -729,6 +731,7 @@ hts_status hts_set_volume_source(hts_mesh *m, const double *w)
         if (w) m->vsrc.assign(w, w + m->ncell);
         else m->vsrc.clear();
         m->dirty = true;
+        m->heat_spec[0] = 0.0;   // operator data changed: the heat spectrum is estimated again
     });
 }
 
@@ -744,6 +747,7 @@ hts_status hts_add_line_source(hts_mesh *m, double x, double y, double z0, doubl
         if (m->general) throw Error(HTS_ERR_UNSUPPORTED, "line sources need a box mesh (vertical node columns)");
         m->lines.push_back({x, y, z0, z1, kind, *rate, T_inj});
         m->dirty = true;
+        m->heat_spec[0] = 0.0;   // operator data changed: the heat spectrum is estimated again
     });
 }
 
@@ -757,6 +761,7 @@ hts_status hts_add_dirichlet_column(hts_mesh *m, hts_field field, double x, doub
         if (m->general) throw Error(HTS_ERR_UNSUPPORTED, "Dirichlet columns need a box mesh (vertical node columns)");
         m->cols[field].push_back({x, y, z0, z1, *value});
         m->dirty = true;
+        m->heat_spec[0] = 0.0;   // operator data changed: the heat spectrum is estimated again
     });
 }
 
@@ -793,6 +798,24 @@ hts_status hts_set_previous_state(hts_mesh *m, hts_field field, const double *ho
             HTS_HIP(hipStreamSynchronize(m->stream));
         }
         m->hist_dt[field] = dt_prev;
+    });
+}
+
+hts_status hts_get_heat_spectrum(hts_mesh *m, double *out)
+{
+    return guard([&] {
+        ARG_CHECK(m && out, "null argument");
+        for (int k = 0; k < 4; k++) out[k] = m->heat_spec[k];
+    });
+}
+
+hts_status hts_set_heat_spectrum(hts_mesh *m, const double *in)
+{
+    return guard([&] {
+        ARG_CHECK(m && in, "null argument");
+        for (int k = 0; k < 4; k++) ARG_CHECK(std::isfinite(in[k]) && in[k] >= 0.0, "bad spectrum entry");
+        ARG_CHECK(in[0] == 0.0 || (in[1] > 0.0 && in[2] > 0.0), "lmax estimates must be > 0");
+        for (int k = 0; k < 4; k++) m->heat_spec[k] = in[k];
     });
 }
 

@@ -55,7 +55,8 @@ struct Level {
 
 struct Hier {
     int field = 0;
-    int deg = 2;
+    int deg = 2;                  // Chebyshev steps launched
+    int deg_req = 2;              // the degree asked for (the cache key)
     bool multigrid = true;
     double ratio = 15.0;          // Chebyshev interval [lmax/ratio, 1.1 lmax] on the fine level
     double ratio_coarse = 15.0;   // and on coarse levels
@@ -213,7 +214,8 @@ struct Batch {
 
     void estimate_lmax(Hier &H, int l, std::vector<double> &lmax);
     // given: lmax(D^-1 A) per instance (else estimated by power iteration)
-    void build_smoother(Hier &H, int l, int steps, double ratio, const std::vector<double> *given = nullptr);
+    void build_smoother(Hier &H, int l, int steps, double ratio, const std::vector<double> *given = nullptr,
+                        const std::vector<double> *beta = nullptr, const std::vector<int> *steps_i = nullptr);
     void build_hierarchy(Hier &H, const hts_solver_opts &o);
     Hier &pressure_hier(bool steady, double dt, const hts_solver_opts &o);
     Hier &heat_prec(double dt, const hts_solver_opts &o);

@@ -661,19 +661,29 @@ static bool invert_spd_banded(std::vector<double> &A, int n, int bw)
     return true;
 }
 
-static void cheb_coeffs(double lmax_est, double ratio, int steps, double *out /* 2*steps */)
+// Chebyshev iteration for a spectrum of D^-1 A inside the ellipse with
+// centre theta on the real axis, real semi-axis delta and imaginary
+// semi-axis beta (beta = 0: the interval [lmin, lmax]).  Its foci are
+// theta +- c with c^2 = delta^2 - beta^2, real or imaginary; with
+// mu_k = rho_k / c the recurrence needs c^2 only and stays real:
+//   d_0 = D^-1 r_0 / theta,  mu_0 = 1 / theta,
+//   mu_k = 1 / (2 theta - c^2 mu_{k-1}),
+//   d_k = c^2 mu_k mu_{k-1} d_{k-1} + 2 mu_k D^-1 r_k,  x_{k+1} = x_k + d_k.
+// out[2k], out[2k+1] are the two factors of step k (out[0] = 0).
+static void cheb_coeffs(double lmax_est, double ratio, int steps, double beta_est, double *out /* 2*steps */)
 {
     static const double safety = env_or("HTS_LMAX_SAFETY", 1.1);
     const double lmax = safety * lmax_est, lmin = lmax / ratio;
-    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-    double rho_prev = 1.0 / sigma;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), beta = safety * beta_est;
+    const double c2 = delta * delta - beta * beta;
+    double mu_prev = 1.0 / theta;
     out[0] = 0.0;
-    out[1] = 1.0 / theta;
+    out[1] = mu_prev;
     for (int k = 1; k < steps; k++) {
-        const double rho = 1.0 / (2.0 * sigma - rho_prev);
-        out[2 * k] = rho * rho_prev;
-        out[2 * k + 1] = 2.0 * rho / delta;
-        rho_prev = rho;
+        const double mu = 1.0 / (2.0 * theta - c2 * mu_prev);
+        out[2 * k] = c2 * mu * mu_prev;
+        out[2 * k + 1] = 2.0 * mu;
+        mu_prev = mu;
     }
 }
 
@@ -720,7 +730,8 @@ static void level_alloc(Level &L, Alloc *al, hipStream_t s, int64_t ntot)
     for (DBuf<float> *v : {&L.x32, &L.xb32, &L.b32, &L.d32, &L.t32, &L.invd32}) { v->alloc(al, m); v->zero(s); }
 }
 
-void Batch::build_smoother(Hier &H, int l, int steps, double ratio, const std::vector<double> *given)
+void Batch::build_smoother(Hier &H, int l, int steps, double ratio, const std::vector<double> *given,
+                           const std::vector<double> *beta, const std::vector<int> *steps_i)
 {
     Level &L = H.lev[l];
     std::vector<double> lm;
@@ -729,7 +740,11 @@ void Batch::build_smoother(Hier &H, int l, int steps, double ratio, const std::v
     std::vector<double> c((size_t)n * NSLOT, 0.0);
     static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 0.0;
     for (int i = 0; i < n; i++) {
-        cheb_coeffs(lm[i], ratio, steps, &c[(size_t)i * NSLOT + S_CHEB]);
+        double *ci = &c[(size_t)i * NSLOT + S_CHEB];
+        cheb_coeffs(lm[i], ratio, steps, beta ? (*beta)[i] : 0.0, ci);
+        // an instance of lower degree: its later steps add nothing (d_k = 0)
+        if (steps_i)
+            for (int k = std::max(1, (*steps_i)[i]); k < steps; k++) ci[2 * k] = ci[2 * k + 1] = 0.0;
         if (L.cont[i]) H.lmax.push_back(lm[i]);
         if (verbose && L.cont[i])
             std::fprintf(stderr, "[hts] field %d level %d instance %d lmax(D^-1 A) %.6g ratio %g steps %d\n", H.field, l,
@@ -891,13 +906,15 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     const bool mg = o.heat_precond == 0;
     const bool tensor = o.heat_precond == 2 && p == 1;
     const int deg = mg ? std::max(1, std::min(o.heat_cheb_degree, 8)) : std::max(1, std::min(o.heat_cheb_degree, 16));
-    if (heat && heat->dt == dt && heat->deg == deg && heat->multigrid == mg && heat->tensor == tensor) return *heat;
+    if (heat && heat->dt == dt && heat->deg_req == deg && heat->multigrid == mg && heat->tensor == tensor)
+        return *heat;
     drop_graphs();
     heat = std::make_unique<Hier>();
     Hier &H = *heat;
     H.field = 1;
     H.dt = dt;
     H.deg = deg;
+    H.deg_req = deg;
     H.multigrid = mg;
     if (tensor) {
         make_tables(H.ops, 1, dt, false, false);
@@ -958,19 +975,96 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
     // imaginary spectrum makes the symmetric interval far too narrow and
     // the preconditioned iteration stagnates: the full operator's estimate
     // (with the flux of the build step) is used instead.
-    std::vector<double> lsym, lfull, lm(n);
-    advection(false);
-    estimate_lmax(H, 0, lsym);
-    advection(true);
-    estimate_lmax(H, 0, lfull);
+    std::vector<double> lsym(n, 1.0), lfull(n, 1.0), lm(n);
+    bool cached = true;
+    for (int i = 0; i < n; i++) cached = cached && m[i]->heat_spec[0] == dt;
+    if (!cached) {
+        advection(false);
+        estimate_lmax(H, 0, lsym);
+        advection(true);
+        estimate_lmax(H, 0, lfull);
+    }
     static const bool verbose = env_or("HTS_VERBOSE", 0.0) > 0.0;
+    // Imaginary extent of the spectrum: the convection part C = A - A_0 (A_0
+    // the operator without the Darcy flux term) is close to skew, so D^-1 C
+    // has nearly imaginary eigenvalues +-i beta.  beta^2 comes from power
+    // iteration on (D^-1 C)^2 with the interval estimates' probe; the
+    // Chebyshev polynomial is then the one of the ellipse over the real
+    // interval with that imaginary semi-axis (a real-interval polynomial of
+    // degree 3 or more grows on the imaginary part and can stall FGMRES).
+    std::vector<double> beta(n, 0.0);
+    if (!cached) {
+        Tables T0;
+        make_tables(T0, 1, dt, false, false);
+        for (int i = 0; i < n; i++) T0.h64[i].cadv = T0.h32[i].cadv = 0.0;
+        T0.d64.upload(al, T0.h64, s);
+        T0.d32.upload(al, T0.h32, s);
+        std::vector<double> hv(std::max<int64_t>(L.ntot, 1), 0.0);
+        for (int i = 0; i < n; i++) {
+            std::mt19937_64 rng(12345);
+            std::uniform_real_distribution<double> U(-1.0, 1.0);
+            const int64_t b0 = L.h64[i].off, cnt = L.h64[i].n;
+            for (int64_t e = 0; e < cnt; e++) hv[b0 + e] = U(rng);
+        }
+        HTS_HIP(hipMemcpyAsync(L.x64.p, hv.data(), L.ntot * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<int32_t> all(n, 1);
+        set_active(all);
+        VecCtx v{L.ch_ext, L.nch, active.p, S.p, s};
+        vmask<double>(v, H.ops.d64.p, L.x64.p, 0.0);
+        EpiArgs<double> ep{};
+        // w = D^-1 C x into dst (t, u: scratch)
+        auto dinv_c = [&](const double *x, double *dst) {
+            apply_op<double>(H.ops, EPI_STORE, true, x, L.t64.p, ep);
+            apply_op<double>(T0, EPI_STORE, true, x, L.b64.p, ep);
+            vaxpby<double>(v, -1.0, -1, L.b64.p, 1.0, -1, L.t64.p);
+            vjacobi<double>(v, 1.0, -1, L.invd64.p, L.t64.p, dst);
+        };
+        const int iters = (int)env_or("HTS_LMAX_ITERS", 12.0);
+        for (int it = 0; it < iters; it++) {
+            dinv_c(L.x64.p, L.xb64.p);
+            dinv_c(L.xb64.p, L.d64.p);
+            vdot<double>(v, L.d64.p, L.d64.p, nullptr, partial.p);
+            vreduce(rch, partial.p, 2, RED_INVSQRT, S_TMP0, S.p, active.p, 0, 0.0, nullptr, s);
+            vaxpby<double>(v, 1.0, S_TMP1, L.d64.p, 0.0, -1, L.x64.p);
+        }
+        download_S();
+        for (int i = 0; i < n; i++) beta[i] = std::pow(std::max(hS[(size_t)i * NSLOT + S_TMP0], 0.0), 0.25);
+    }
+    // a mesh that already holds estimates for this dt keeps them (a run
+    // resumed with them builds the same preconditioner as the run that made
+    // them); the others record the new ones
+    for (int i = 0; i < n; i++) {
+        double *hs = m[i]->heat_spec;
+        if (hs[0] == dt) {
+            lsym[i] = hs[1];
+            lfull[i] = hs[2];
+            beta[i] = hs[3];
+        } else {
+            hs[0] = dt;
+            hs[1] = lsym[i];
+            hs[2] = lfull[i];
+            hs[3] = beta[i];
+        }
+    }
+    // Where the imaginary extent reaches the real half-width of the interval
+    // (convection-dominated), the ellipse reaches nearly to the origin
+    // relative to its size and higher polynomial degrees no longer pay (the
+    // injection column stalls at degree 4): such instances keep degree 2,
+    // their later steps add nothing.
+    static const double safety = env_or("HTS_LMAX_SAFETY", 1.1);
+    std::vector<int> degi(n, deg);
+    int dmax = 1;
     for (int i = 0; i < n; i++) {
         lm[i] = lfull[i] > 1.25 * lsym[i] ? lfull[i] : lsym[i];
+        const double lmax = safety * lm[i], half = 0.5 * (lmax - lmax / H.ratio);
+        if (safety * beta[i] >= half) degi[i] = std::min(deg, 2);
+        dmax = std::max(dmax, degi[i]);
         if (verbose)
-            std::fprintf(stderr, "[hts] heat Chebyshev instance %d: lmax symmetric %.6g, with convection %.6g\n", i,
-                         lsym[i], lfull[i]);
+            std::fprintf(stderr, "[hts] heat Chebyshev instance %d: lmax symmetric %.6g, with convection %.6g, "
+                         "imaginary extent %.6g, degree %d\n", i, lsym[i], lfull[i], beta[i], degi[i]);
     }
-    build_smoother(H, 0, H.deg, H.ratio, &lm);
+    H.deg = dmax;
+    build_smoother(H, 0, H.deg, H.ratio, &lm, &beta, &degi);
     return H;
 }
 

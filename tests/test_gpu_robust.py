@@ -4,9 +4,10 @@
   library copies as given) makes the heat solve break down: the step returns
   HTS_ERR_BREAKDOWN and neither field nor the time advances, in FP64 and in
   FP32-refined mode.
-* Checkpoint / resume: the state and the previous time level read back
-  after two steps and set on a fresh mesh of the same scenario continue bit
-  for bit like the uninterrupted run.
+* Checkpoint / resume: the state, the previous time level and the heat
+  preconditioner's spectral estimates read back after two steps and set on
+  a fresh mesh of the same scenario continue bit for bit like the
+  uninterrupted run.
 * Changing the time-step size keeps at most two pressure multigrid
   hierarchies; steps that alternate between three sizes give the same bits
   as fresh meshes that only ever see one size (given the same two levels).
@@ -69,12 +70,15 @@ def test_checkpoint_resume_is_bit_exact(hts, mode):
     T, _ = b.get_state(1)
     prev = [b.get_previous_state(f) for f in (0, 1)]
     assert prev[0][1] == s.dt and prev[1][1] == s.dt
+    spec = b.get_heat_spectrum()
+    assert spec[0] == s.dt and spec[1] > 0 and spec[2] > 0
     del b
     c = hts.from_scenario(s, initial=False, opts=o)
     c.set_state(0, P, t)
     c.set_state(1, T, t)
     for f in (0, 1):
         c.set_previous_state(f, *prev[f])
+    c.set_heat_spectrum(spec)
     for _ in range(2):
         assert c.solve_step(s.dt, o)[0] == 0
     assert np.array_equal(a.get_state(0)[0], c.get_state(0)[0])
