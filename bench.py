@@ -108,7 +108,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--cheb", type=int, default=2, help="pressure multigrid Chebyshev degree")
-    ap.add_argument("--heat-cheb", type=int, default=4, help="heat Chebyshev-Jacobi degree")
+    ap.add_argument("--heat-cheb", type=int, default=0,
+                    help="heat Chebyshev-Jacobi degree (0: 4 on Q1 and 2 on Q2 cells)")
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--mg-coarse-max", type=int, default=None,

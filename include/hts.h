@@ -143,7 +143,8 @@ typedef struct {
                                 FP64 inverse (n^2 entries, read whole by every
                                 coarse solve)                                 */
     int32_t heat_cheb_degree;/* degree of the heat Chebyshev-Jacobi preconditioner
-                                (4); its polynomial is the Chebyshev one of the
+                                (0, the default: 4 on degree-1 cells, 2 on
+                                degree-2 cells); its polynomial is the Chebyshev one of the
                                 ellipse over the real interval of D^-1 A with
                                 the imaginary extent of the convection term;
                                 instances whose imaginary extent reaches the

@@ -490,7 +490,7 @@ void hts_default_opts(hts_solver_opts *o)
     o->gmres_restart = 30;
     o->cheb_degree = 2;
     o->mg_coarse_max = 600;
-    o->heat_cheb_degree = 4;
+    o->heat_cheb_degree = 0;
     o->inner_rtol = 1e-5;
     o->check_every = 1;
     o->use_graph = 0;

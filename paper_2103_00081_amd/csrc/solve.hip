@@ -905,7 +905,11 @@ Hier &Batch::heat_prec(double dt, const hts_solver_opts &o)
 {
     const bool mg = o.heat_precond == 0;
     const bool tensor = o.heat_precond == 2 && p == 1;
-    const int deg = mg ? std::max(1, std::min(o.heat_cheb_degree, 8)) : std::max(1, std::min(o.heat_cheb_degree, 16));
+    // degree 0: automatic, 4 on degree-1 cells, 2 on degree-2 cells (a Q2
+    // apply costs about eight times the flops of a Q1 apply per node, so
+    // fewer products per Krylov iteration pay there)
+    const int dreq = o.heat_cheb_degree > 0 ? o.heat_cheb_degree : (p == 2 ? 2 : 4);
+    const int deg = mg ? std::max(1, std::min(dreq, 8)) : std::max(1, std::min(dreq, 16));
     if (heat && heat->dt == dt && heat->deg_req == deg && heat->multigrid == mg && heat->tensor == tensor)
         return *heat;
     drop_graphs();
