@@ -3,6 +3,7 @@
 // time level).
 #include "bc.h"
 #include "dev_util.h"
+#include "vec.h"
 
 namespace hts {
 
@@ -16,30 +17,42 @@ __global__ __launch_bounds__(256) void k_dirichlet(const OpDev *__restrict__ ops
     const OpDev &o = ops[ch.inst];
     const BcDev &b = bcs[ch.inst];
     const double t = S[(int64_t)ch.inst * NSLOT + S_TNEW];
-    for (int64_t e = ch.beg + threadIdx.x; e < ch.end; e += 256) {
+    // at most 4 nodes per thread (the batch's fine chunks): the face and
+    // column tests first, coordinates and time functions only on
+    // constrained nodes
+    static_assert(CHUNK_LEN <= 4 * 256, "k_dirichlet covers 4 nodes per thread");
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int64_t e = ch.beg + threadIdx.x + 256 * u;
+        if (e >= ch.end) break;
         // instance-local node index (below 2^31): 32-bit index arithmetic
         const int n = (int)(e - o.off);
         const int nxy = n / o.NX, i = n - nxy * o.NX, k = nxy / o.NY, j = nxy - k * o.NY;
-        double x = b.xn ? b.xn[i] : b.x0 + i * b.dx, y = b.yn ? b.yn[j] : b.y0 + j * b.dy,
-               z = b.zn ? b.zn[k] : b.z0 + k * b.dz;
-        if (b.xyz) {
-            x = b.xyz[3 * (int64_t)n];
-            y = b.xyz[3 * (int64_t)n + 1];
-            z = b.xyz[3 * (int64_t)n + 2];
-        }
-        double v = 0.0;
+        int fsel = -1;   // the last Dirichlet face through the node
         for (int f = 0; f < b.nface; f++) {
             const int face = b.faces[f];
             const bool on = (face == 0 && i == 0) || (face == 1 && i == o.NX - 1) || (face == 2 && j == 0) ||
                             (face == 3 && j == o.NY - 1) || (face == 4 && k == 0) || (face == 5 && k == o.NZ - 1);
-            if (on) v = tf_eval(b.ftf[f], x, y, z, t);
+            if (on) fsel = f;
         }
+        int csel = -1;   // a Dirichlet column through the node (it takes precedence)
         if (b.colspec && o.dcol) {
             const int64_t c = i + (int64_t)o.NX * j;
             const int packed = o.dcol[c];
             const int lo = packed & 0xFFFF, hi = (packed >> 16) & 0xFFFF;
             const int sp = b.colspec[c];
-            if (sp >= 0 && k >= lo && k <= hi) v = tf_eval(b.coltf[sp], x, y, z, t);
+            if (sp >= 0 && k >= lo && k <= hi) csel = sp;
+        }
+        double v = 0.0;
+        if (fsel >= 0 || csel >= 0) {
+            double x = b.xn ? b.xn[i] : b.x0 + i * b.dx, y = b.yn ? b.yn[j] : b.y0 + j * b.dy,
+                   z = b.zn ? b.zn[k] : b.z0 + k * b.dz;
+            if (b.xyz) {
+                x = b.xyz[3 * (int64_t)n];
+                y = b.xyz[3 * (int64_t)n + 1];
+                z = b.xyz[3 * (int64_t)n + 2];
+            }
+            v = csel >= 0 ? tf_eval(b.coltf[csel], x, y, z, t) : tf_eval(b.ftf[fsel], x, y, z, t);
         }
         g[e] = v;
     }

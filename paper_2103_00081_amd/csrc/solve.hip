@@ -1802,8 +1802,7 @@ void Batch::pressure_rhs(Hier &H, bool steady)
     if (!steady) apply_op<double>(massP, EPI_STORE, false, Pn.p, b.p, ep);
     else vfill<double>(v, b.p, 0.0);
     apply_op<double>(H.ops, EPI_STORE, false, g.p, y.p, ep);
-    vaxpby<double>(v, -1.0, -1, y.p, 1.0, -1, b.p);
-    vaxpby<double>(v, 1.0, S_FSCALE, ld0.p, 1.0, -1, b.p);
+    vrhs_combine(v, y.p, ld0.p, S_FSCALE, b.p);
     launch_sources(srows[0].p, srowptr[0].p, sents[0].p, nsrows[0], ssrc[0].p, S.p, b.p, s);
     vmask<double>(v, H.ops.d64.p, b.p, 0.0);
 }
@@ -1818,8 +1817,7 @@ void Batch::heat_rhs(Hier &H)
     EpiArgs<double> ep{};
     apply_op<double>(massH, EPI_STORE, false, Tn.p, b.p, ep);
     apply_op<double>(H.ops, EPI_STORE, false, g.p, y.p, ep);
-    vaxpby<double>(v, -1.0, -1, y.p, 1.0, -1, b.p);
-    vaxpby<double>(v, 1.0, S_FSCALE, ld1.p, 1.0, -1, b.p);
+    vrhs_combine(v, y.p, ld1.p, S_FSCALE, b.p);
     launch_sources(srows[1].p, srowptr[1].p, sents[1].p, nsrows[1], ssrc[1].p, S.p, b.p, s);
     vmask<double>(v, H.ops.d64.p, b.p, 0.0);
 }
@@ -1893,14 +1891,12 @@ FieldStats Batch::solve_pressure(double dt, bool steady_all, const hts_solver_op
     Hier &H = pressure_hier(steady, dt, o);
     pressure_rhs(H, steady);
     VecCtx v = vctx(false);
-    vextrapolate(v, S_XTRA, Pn.p, Pp.p, x.p);
-    vmask<double>(v, H.ops.d64.p, x.p, 0.0);
+    vextrapolate(v, S_XTRA, H.ops.d64.p, Pn.p, Pp.p, x.p);
     std::vector<int32_t> all(n, 1);
     FieldStats st = solve_field(0, &H, H.ops, b.p, x.p, o, all, nullptr);
     std::vector<int32_t> a(n, 1);
     set_active(a);
-    vaxpby<double>(vctx(false), 1.0, -1, x.p, 0.0, -1, P1.p);
-    vaxpby<double>(vctx(false), 1.0, -1, g.p, 1.0, -1, P1.p);
+    vadd(vctx(false), x.p, g.p, P1.p);
     return st;
 }
 
@@ -1921,12 +1917,10 @@ FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
     launch_source_values(lsrc.p, nlsrc, S.p, lcoef.p, s);
     Hier &H = heat_prec(dt, o);
     heat_rhs(H);
-    vextrapolate(v, S_XTRA, Tn.p, Tp.p, x.p);
-    vmask<double>(v, H.ops.d64.p, x.p, 0.0);
+    vextrapolate(v, S_XTRA, H.ops.d64.p, Tn.p, Tp.p, x.p);
     FieldStats st = solve_field(1, H.multigrid ? &H : nullptr, H.ops, b.p, x.p, o, all, &H);
     set_active(all);
-    vaxpby<double>(vctx(false), 1.0, -1, x.p, 0.0, -1, T1.p);
-    vaxpby<double>(vctx(false), 1.0, -1, g.p, 1.0, -1, T1.p);
+    vadd(vctx(false), x.p, g.p, T1.p);
     return st;
 }
 

@@ -65,8 +65,13 @@ void vbasis_update(const VecCtx &v, const T *Z, int64_t ld, const int32_t *kdim,
                    double scale, int iscale, TX *x);
 template <typename TX, typename TY> void vconvert(const VecCtx &v, double sc, int ic, const TX *x, TY *y);
 template <typename T> void vadd_scaled(const VecCtx &v, double sc, int ic, const T *d, double *x);
-// x = Xn + c (Xn - Xp), c = S[slot] per instance; c == 0: x = Xn exactly
-void vextrapolate(const VecCtx &v, int slot, const double *Xn, const double *Xp, double *x);
+// x = Xn + c (Xn - Xp), c = S[slot] per instance; c == 0: x = Xn exactly;
+// 0 at the constrained nodes of ops when ops is given
+void vextrapolate(const VecCtx &v, int slot, const OpDev *ops, const double *Xn, const double *Xp, double *x);
+// b = (b - y) + S[slot] ld
+void vrhs_combine(const VecCtx &v, const double *y, const double *ld, int slot, double *b);
+// z = x + y
+void vadd(const VecCtx &v, const double *x, const double *y, double *z);
 // time-level shift: Xp = Xn, then Xn = X1
 void vshift(const VecCtx &v, const double *X1, double *Xn, double *Xp);
 template <typename T> void vmask(const VecCtx &v, const OpDev *ops, T *y, T val);

@@ -386,10 +386,12 @@ __global__ __launch_bounds__(VB) void k_add_scaled(const Chunk *__restrict__ chu
 }
 
 // Initial guess from the last two time levels: x = Xn + c (Xn - Xp),
-// c = S[slot] of the instance; c == 0 copies Xn (Xp is then not read).
+// c = S[slot] of the instance; c == 0 copies Xn (Xp is then not read);
+// constrained nodes of ops (if given) get 0.
 __global__ __launch_bounds__(VB) void k_extrapolate(const Chunk *__restrict__ chunks, const int32_t *active,
-                                                    const double *S, int slot, const double *__restrict__ Xn,
-                                                    const double *__restrict__ Xp, double *__restrict__ x)
+                                                    const double *S, int slot, const OpDev *__restrict__ ops,
+                                                    const double *__restrict__ Xn, const double *__restrict__ Xp,
+                                                    double *__restrict__ x)
 {
     CHUNK_PROLOGUE
     const double c = Si[slot];
@@ -402,7 +404,52 @@ __global__ __launch_bounds__(VB) void k_extrapolate(const Chunk *__restrict__ ch
     }
 #pragma unroll
     for (int u = 0; u < EPT; u++)
-        if (l.in[u]) x[l.e[u]] = c != 0.0 ? a[u] + c * (a[u] - b[u]) : a[u];
+        if (l.in[u]) {
+            double v = c != 0.0 ? a[u] + c * (a[u] - b[u]) : a[u];
+            if (ops) {
+                const OpDev &o = ops[ch.inst];
+                if (node_constrained(o, l.e[u] - o.off)) v = 0.0;
+            }
+            x[l.e[u]] = v;
+        }
+}
+
+// Right-hand side assembly: b = (b - y) + c ld, c = S[slot] of the instance
+__global__ __launch_bounds__(VB) void k_rhs_combine(const Chunk *__restrict__ chunks, const int32_t *active,
+                                                    const double *S, const double *__restrict__ y,
+                                                    const double *__restrict__ ld, int slot, double *__restrict__ b)
+{
+    CHUNK_PROLOGUE
+    const double c = Si[slot];
+    const Lanes l = chunk_lanes(ch);
+    double bv[EPT], yv[EPT], lv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        bv[u] = b[l.c[u]];
+        yv[u] = y[l.c[u]];
+        lv[u] = ld[l.c[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) b[l.e[u]] = c * lv[u] + (bv[u] - yv[u]);
+}
+
+// z = x + y
+__global__ __launch_bounds__(VB) void k_add(const Chunk *__restrict__ chunks, const int32_t *active,
+                                            const double *S, const double *__restrict__ x,
+                                            const double *__restrict__ y, double *__restrict__ z)
+{
+    CHUNK_PROLOGUE
+    const Lanes l = chunk_lanes(ch);
+    double xv[EPT], yv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        xv[u] = x[l.c[u]];
+        yv[u] = y[l.c[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; u++)
+        if (l.in[u]) z[l.e[u]] = xv[u] + yv[u];
 }
 
 // Xp = Xn, Xn = X1 (commit of a step, keeping the previous level)
@@ -643,9 +690,19 @@ __global__ __launch_bounds__(VB) void k_set_slots(SlotBlock b, int beg, int cnt,
 
 template <typename T>
 void vfill(const VecCtx &v, T *y, T val) { k_fill<T><<<GRID>>>(v.chunks, v.active, v.S, y, val); HTS_LAUNCH_CHECK(); }
-void vextrapolate(const VecCtx &v, int slot, const double *Xn, const double *Xp, double *x)
+void vextrapolate(const VecCtx &v, int slot, const OpDev *ops, const double *Xn, const double *Xp, double *x)
 {
-    k_extrapolate<<<GRID>>>(v.chunks, v.active, v.S, slot, Xn, Xp, x);
+    k_extrapolate<<<GRID>>>(v.chunks, v.active, v.S, slot, ops, Xn, Xp, x);
+    HTS_LAUNCH_CHECK();
+}
+void vrhs_combine(const VecCtx &v, const double *y, const double *ld, int slot, double *b)
+{
+    k_rhs_combine<<<GRID>>>(v.chunks, v.active, v.S, y, ld, slot, b);
+    HTS_LAUNCH_CHECK();
+}
+void vadd(const VecCtx &v, const double *x, const double *y, double *z)
+{
+    k_add<<<GRID>>>(v.chunks, v.active, v.S, x, y, z);
     HTS_LAUNCH_CHECK();
 }
 void vshift(const VecCtx &v, const double *X1, double *Xn, double *Xp)
