@@ -164,12 +164,12 @@ typedef struct {
                                 (M_z + a K_z) line solves scaled by the nodal
                                 capacity, a = dt median(lambda / c_T) (Q1;
                                 Q2 uses 1)                                      */
-    int32_t extrapolate;     /* 1 (default): each field's solve starts from the
-                                linear extrapolation X^n + (dt / dt_prev)
-                                (X^n - X^{n-1}) of the last two time levels
-                                when the previous level is known (see
-                                hts_set_previous_state); 0: from X^n.  Either
-                                way the step meets the same residual test.  */
+    int32_t extrapolate;     /* 2 (default): each field's solve starts from the
+                                value at t^n + dt of the polynomial through the
+                                known time levels X^n, X^{n-1}, X^{n-2} (at most
+                                quadratic; see hts_set_previous_state); 1: at
+                                most linear; 0: from X^n.  Either way the step
+                                meets the same residual test.                */
 } hts_solver_opts;
 
 typedef struct {
@@ -247,18 +247,21 @@ hts_status hts_add_dirichlet_column(hts_mesh *mesh, hts_field field, double x, d
 hts_status hts_set_state(hts_mesh *mesh, hts_field field, const double *host, double t);
 hts_status hts_get_state(hts_mesh *mesh, hts_field field, double *host, double *t);
 
-/* The previous time level of a field: the state before the last committed
- * step, and that step's size dt_prev (0: none known).  A committed step
- * (hts_solve_step, hts_advance) records it; the next step starts its solve
- * from the linear extrapolation of the two levels (opts.extrapolate), which
- * changes the iterate's rounding, not the residual test.  A checkpoint that
- * must resume bit for bit saves both levels: get the state and the previous
- * state, and set both on the resumed mesh (hts_set_state first; it forgets
- * the previous level).  host: [nnode], ignored (may be NULL) when dt_prev is
- * 0 on set and when none is known on get.  Errors: HTS_ERR_ARG for a bad
- * field, negative or non-finite dt_prev, or non-finite values. */
-hts_status hts_set_previous_state(hts_mesh *mesh, hts_field field, const double *host, double dt_prev);
-hts_status hts_get_previous_state(hts_mesh *mesh, hts_field field, double *host, double *dt_prev);
+/* The previous time levels of a field: level 1 is the state before the last
+ * committed step and dt_prev that step's size, level 2 the state before the
+ * second-last one and its step's size (dt_prev 0: not known).  A committed
+ * step (hts_solve_step, hts_advance) shifts them; the next step starts its
+ * solve from the extrapolation through the known levels (opts.extrapolate),
+ * which changes the iterate's rounding, not the residual test.  A checkpoint
+ * that must resume bit for bit saves all three levels: set the state first
+ * (it forgets both previous levels), then level 1 (it forgets level 2), then
+ * level 2.  host: [nnode], ignored (may be NULL) when dt_prev is 0 on set
+ * and when the level is not known on get.  Errors: HTS_ERR_ARG for a bad
+ * field or level, negative or non-finite dt_prev, non-finite values, or
+ * level 2 without level 1. */
+hts_status hts_set_previous_state(hts_mesh *mesh, hts_field field, int32_t level, const double *host,
+                                  double dt_prev);
+hts_status hts_get_previous_state(hts_mesh *mesh, hts_field field, int32_t level, double *host, double *dt_prev);
 
 /* Spectral estimates behind the heat Chebyshev preconditioner of a mesh:
  * v[0] the step size they were made for (0: none), v[1] and v[2] the largest

@@ -138,10 +138,10 @@ def load():
         "hts_add_dirichlet_column": (st, [vp, i32, d, d, d, d, P(TimeFn)]),
         "hts_set_state": (st, [vp, i32, vp, d]),
         "hts_get_state": (st, [vp, i32, vp, P(d)]),
-        "hts_set_previous_state": (st, [vp, i32, vp, d]),
+        "hts_set_previous_state": (st, [vp, i32, i32, vp, d]),
         "hts_get_heat_spectrum": (st, [vp, vp]),
         "hts_set_heat_spectrum": (st, [vp, vp]),
-        "hts_get_previous_state": (st, [vp, i32, vp, P(d)]),
+        "hts_get_previous_state": (st, [vp, i32, i32, vp, P(d)]),
         "hts_mesh_sizes": (st, [vp, P(C.c_int64), P(C.c_int64)]),
         "hts_apply_operator": (st, [vp, i32, i32, d, vp, vp]),
         "hts_solve_steady_pressure": (st, [vp, P(SolverOpts), P(StepStats)]),
@@ -314,16 +314,17 @@ class Mesh:
         _check(load().hts_get_state(self.h, field, out.ctypes.data, C.byref(t)))
         return out, t.value
 
-    def set_previous_state(self, field, values, dt_prev):
-        """The field's previous time level and the step size since it
-        (dt_prev 0 forgets it; values may then be None)."""
+    def set_previous_state(self, field, values, dt_prev, level=1):
+        """A previous time level of the field (level 1: before the last
+        step, 2: before the one before) and the step size after it (dt_prev
+        0 forgets it; values may then be None).  Set level 1 before 2."""
         if values is None:
-            _check(load().hts_set_previous_state(self.h, field, None, dt_prev))
+            _check(load().hts_set_previous_state(self.h, field, level, None, dt_prev))
             return
         x = np.ascontiguousarray(values, dtype=np.float64)
         if x.size != self.nnode:
             raise ValueError("state must have %d entries" % self.nnode)
-        _check(load().hts_set_previous_state(self.h, field, x.ctypes.data, dt_prev))
+        _check(load().hts_set_previous_state(self.h, field, level, x.ctypes.data, dt_prev))
 
     def get_heat_spectrum(self):
         """(dt, lmax without convection, lmax with convection, imaginary
@@ -338,12 +339,12 @@ class Mesh:
             raise ValueError("4 values")
         _check(load().hts_set_heat_spectrum(self.h, x.ctypes.data))
 
-    def get_previous_state(self, field):
-        """(values, dt_prev) of the previous time level; values None when
-        none is known (dt_prev 0)."""
+    def get_previous_state(self, field, level=1):
+        """(values, dt_prev) of a previous time level; values None when it
+        is not known (dt_prev 0)."""
         out = np.zeros(self.nnode)
         dt = C.c_double()
-        _check(load().hts_get_previous_state(self.h, field, out.ctypes.data, C.byref(dt)))
+        _check(load().hts_get_previous_state(self.h, field, level, out.ctypes.data, C.byref(dt)))
         return (out if dt.value > 0.0 else None), dt.value
 
     # --------------------------------------------------------- operators

@@ -115,11 +115,11 @@ struct Chunk {
 // Per-instance scalar slots of the Krylov solvers.
 enum Slot {
     S_BB = 0, S_RR, S_RZ, S_PQ, S_ALPHA, S_BETA, S_TOL2, S_ITER, S_STATUS, S_RR0,
-    S_C1, S_C2, S_SCALE, S_TNEW, S_DT, S_TMP0, S_TMP1, S_TMP2, S_TMP3,
+    S_C1, S_C2, S_SCALE, S_TNEW, S_XTRA2, S_TMP0, S_TMP1, S_TMP2, S_TMP3,
     // outer (FP64) system of a field solve
     S_OBB = 19, S_OTOL2, S_ORR, S_ONORM, S_OINV, S_OSTATUS, S_FSCALE,
     S_CYC = 26,                // 1 if the instance takes part in the current FGMRES cycle
-    S_XTRA = 27,               // initial guess X^n + S_XTRA (X^n - X^{n-1}); 0: X^n
+    S_XTRA = 27,               // initial guess X^n + S_XTRA (X^n - X^{n-1}) + S_XTRA2 (X^{n-1} - X^{n-2})
     S_CHEB = 28,               // Chebyshev coefficients: 2 per step, up to 16 steps
     // learned preconditioner in an inner solve: last ||r||^2 it was applied
     // to (-1: none yet), consecutive weak iterations, fallback flag, fallbacks

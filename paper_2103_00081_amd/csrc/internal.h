@@ -166,10 +166,11 @@ struct hts_mesh {
     hts::DBuf<double> P, T;
     double t = 0.0;
     bool has_state[2] = {false, false};
-    // previous time level of each field (the state before the last committed
-    // step) and that step's size; hist_dt 0: none known
-    hts::DBuf<double> Pprev, Tprev;
-    double hist_dt[2] = {0.0, 0.0};
+    // the two previous time levels of each field (the states before the last
+    // and the second-last committed step) and those steps' sizes; hist_dt 0:
+    // level n-1 not known, hist_dt2 0: level n-2 not known
+    hts::DBuf<double> Pprev, Tprev, Pprev2, Tprev2;
+    double hist_dt[2] = {0.0, 0.0}, hist_dt2[2] = {0.0, 0.0};
     // spectral estimates of the heat preconditioner (they depend on the
     // Darcy flux of the step that made them): dt, lmax of D^-1 A without and
     // with convection, imaginary extent; dt 0: none.  Reused by any batch

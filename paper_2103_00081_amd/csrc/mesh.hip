@@ -497,7 +497,7 @@ void hts_default_opts(hts_solver_opts *o)
     o->nn = nullptr;
     o->verbose = 0;
     o->heat_precond = 1;
-    o->extrapolate = 1;
+    o->extrapolate = 2;
 }
 
 // General hexahedra: det J > 0 at the 2 x 2 x 2 Gauss points of every cell
@@ -631,10 +631,14 @@ hts_status hts_create_mesh(const hts_mesh_desc *desc, hts_mesh **out)
         m->T.alloc(&m->alloc, m->nnode);
         m->Pprev.alloc(&m->alloc, m->nnode);
         m->Tprev.alloc(&m->alloc, m->nnode);
+        m->Pprev2.alloc(&m->alloc, m->nnode);
+        m->Tprev2.alloc(&m->alloc, m->nnode);
         m->P.zero(m->stream);
         m->T.zero(m->stream);
         m->Pprev.zero(m->stream);
         m->Tprev.zero(m->stream);
+        m->Pprev2.zero(m->stream);
+        m->Tprev2.zero(m->stream);
         *out = m.release();
     });
 }
@@ -778,26 +782,33 @@ hts_status hts_set_state(hts_mesh *m, hts_field field, const double *host, doubl
         HTS_HIP(hipStreamSynchronize(m->stream));
         m->t = t;
         m->has_state[field] = true;
-        m->hist_dt[field] = 0.0;   // the previous level no longer belongs to this state
+        m->hist_dt[field] = m->hist_dt2[field] = 0.0;   // the previous levels no longer belong to this state
     });
 }
 
-hts_status hts_set_previous_state(hts_mesh *m, hts_field field, const double *host, double dt_prev)
+hts_status hts_set_previous_state(hts_mesh *m, hts_field field, int32_t level, const double *host, double dt_prev)
 {
     return guard([&] {
         ARG_CHECK(m, "null mesh");
         ARG_CHECK(field == 0 || field == 1, "bad field");
+        ARG_CHECK(level == 1 || level == 2, "level must be 1 or 2");
         ARG_CHECK(std::isfinite(dt_prev) && dt_prev >= 0.0, "dt_prev must be finite and >= 0");
         ARG_CHECK(host || dt_prev == 0.0, "null values with dt_prev > 0");
+        ARG_CHECK(level == 1 || dt_prev == 0.0 || m->hist_dt[field] > 0.0, "level 2 needs level 1 first");
         HTS_HIP(hipSetDevice(m->desc.device));
         if (dt_prev > 0.0) {
             for (int64_t i = 0; i < m->nnode; i++)
                 if (!std::isfinite(host[i])) throw Error(HTS_ERR_ARG, "non-finite state value");
-            DBuf<double> &s = field == 0 ? m->Pprev : m->Tprev;
+            DBuf<double> &s = field == 0 ? (level == 1 ? m->Pprev : m->Pprev2) : (level == 1 ? m->Tprev : m->Tprev2);
             HTS_HIP(hipMemcpyAsync(s.p, host, m->nnode * sizeof(double), hipMemcpyHostToDevice, m->stream));
             HTS_HIP(hipStreamSynchronize(m->stream));
         }
-        m->hist_dt[field] = dt_prev;
+        if (level == 1) {
+            m->hist_dt[field] = dt_prev;
+            m->hist_dt2[field] = 0.0;   // level 2 belongs to the old level 1
+        } else {
+            m->hist_dt2[field] = dt_prev;
+        }
     });
 }
 
@@ -819,18 +830,20 @@ hts_status hts_set_heat_spectrum(hts_mesh *m, const double *in)
     });
 }
 
-hts_status hts_get_previous_state(hts_mesh *m, hts_field field, double *host, double *dt_prev)
+hts_status hts_get_previous_state(hts_mesh *m, hts_field field, int32_t level, double *host, double *dt_prev)
 {
     return guard([&] {
         ARG_CHECK(m, "null mesh");
         ARG_CHECK(field == 0 || field == 1, "bad field");
+        ARG_CHECK(level == 1 || level == 2, "level must be 1 or 2");
         HTS_HIP(hipSetDevice(m->desc.device));
-        if (host && m->hist_dt[field] > 0.0) {
-            DBuf<double> &s = field == 0 ? m->Pprev : m->Tprev;
+        const double dt = level == 1 ? m->hist_dt[field] : m->hist_dt2[field];
+        if (host && dt > 0.0) {
+            DBuf<double> &s = field == 0 ? (level == 1 ? m->Pprev : m->Pprev2) : (level == 1 ? m->Tprev : m->Tprev2);
             HTS_HIP(hipMemcpyAsync(host, s.p, m->nnode * sizeof(double), hipMemcpyDeviceToHost, m->stream));
             HTS_HIP(hipStreamSynchronize(m->stream));
         }
-        if (dt_prev) *dt_prev = m->hist_dt[field];
+        if (dt_prev) *dt_prev = dt;
     });
 }
 

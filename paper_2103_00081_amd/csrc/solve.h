@@ -122,7 +122,7 @@ struct Batch {
     DBuf<double> partial, redout, redout2, redout3;
 
     DBuf<double> Pn, Tn, P1, T1, g, b, x, r, z, pp, q, rold, y, ld0, ld1, inner_b, inner_x;
-    DBuf<double> Pp, Tp;   // previous time level of the state (valid where hist_dt > 0)
+    DBuf<double> Pp, Tp, Ppp, Tpp;   // previous time levels n-1, n-2 (valid where hist_dt, hist_dt2 > 0)
     // one instance: Pn, Tn, Pp, Tp are the mesh's own state buffers (no
     // gather or scatter copies)
     bool alias_state = false;
@@ -237,8 +237,9 @@ struct Batch {
     FieldStats solve_field(int field, Hier *mg, const Tables &A, double *b64, double *x64, const hts_solver_opts &o,
                            std::vector<int32_t> participants, Hier *hprec);
     void set_time(const std::vector<double> &tnew, const std::vector<double> &fscale,
-                  const std::vector<double> *xtra = nullptr);
-    std::vector<double> xtra_factors(int field, double dt, const hts_solver_opts &o) const;
+                  const std::vector<double> *xtra = nullptr, const std::vector<double> *xtra2 = nullptr);
+    void xtra_factors(int field, double dt, const hts_solver_opts &o, std::vector<double> &c1,
+                      std::vector<double> &c2) const;
     void pressure_rhs(Hier &H, bool steady);
     void heat_rhs(Hier &H);
     void gather_state();

@@ -314,15 +314,15 @@ std::shared_ptr<Batch> build_batch(const std::vector<hts_mesh *> &ms)
     if (B->alias_state) {
         // views of the mesh's buffers (no allocator: not released here)
         hts_mesh *M = ms[0];
-        DBuf<double> *views[4] = {&B->Pn, &B->Tn, &B->Pp, &B->Tp};
-        double *bufs[4] = {M->P.p, M->T.p, M->Pprev.p, M->Tprev.p};
-        for (int k = 0; k < 4; k++) {
+        DBuf<double> *views[6] = {&B->Pn, &B->Tn, &B->Pp, &B->Tp, &B->Ppp, &B->Tpp};
+        double *bufs[6] = {M->P.p, M->T.p, M->Pprev.p, M->Tprev.p, M->Pprev2.p, M->Tprev2.p};
+        for (int k = 0; k < 6; k++) {
             views[k]->p = bufs[k];
             views[k]->n = (size_t)tot;
             views[k]->al = nullptr;
         }
     } else {
-        for (DBuf<double> *v : {&B->Pn, &B->Tn, &B->Pp, &B->Tp}) {
+        for (DBuf<double> *v : {&B->Pn, &B->Tn, &B->Pp, &B->Tp, &B->Ppp, &B->Tpp}) {
             v->alloc(al, tot);
             v->zero(s);
         }
@@ -1774,22 +1774,37 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
 
 // ------------------------------------------------------------- one step
 void Batch::set_time(const std::vector<double> &tnew, const std::vector<double> &fscale,
-                     const std::vector<double> *xtra)
+                     const std::vector<double> *xtra, const std::vector<double> *xtra2)
 {
-    const int slots[3] = {S_TNEW, S_FSCALE, S_XTRA};
-    const double *vals[3] = {tnew.data(), fscale.data(), xtra ? xtra->data() : nullptr};
-    vset_slots(slots, xtra ? 3 : 2, vals, n, S.p, s);
+    const int slots[4] = {S_TNEW, S_FSCALE, S_XTRA, S_XTRA2};
+    const double *vals[4] = {tnew.data(), fscale.data(), xtra ? xtra->data() : nullptr,
+                             xtra2 ? xtra2->data() : nullptr};
+    vset_slots(slots, xtra ? (xtra2 ? 4 : 3) : 2, vals, n, S.p, s);
 }
 
-// Extrapolation factor of each instance's initial guess: dt / dt_prev where
-// the previous time level is known, else 0 (start from X^n).
-std::vector<double> Batch::xtra_factors(int field, double dt, const hts_solver_opts &o) const
+// Factors of each instance's initial guess X^n + c1 (X^n - X^{n-1}) +
+// c2 (X^{n-1} - X^{n-2}): the value at t^n + dt of the polynomial through
+// the known levels (Lagrange form at the times 0, -h1, -(h1 + h2) relative to
+// t^n; three levels: quadratic, two: linear, one: X^n).  extrapolate = 1
+// stops at the linear one.
+void Batch::xtra_factors(int field, double dt, const hts_solver_opts &o, std::vector<double> &c1,
+                         std::vector<double> &c2) const
 {
-    std::vector<double> f(n, 0.0);
-    if (o.extrapolate && dt > 0.0)
-        for (int i = 0; i < n; i++)
-            if (m[i]->hist_dt[field] > 0.0) f[i] = dt / m[i]->hist_dt[field];
-    return f;
+    c1.assign(n, 0.0);
+    c2.assign(n, 0.0);
+    if (o.extrapolate <= 0 || !(dt > 0.0)) return;
+    for (int i = 0; i < n; i++) {
+        const double h1 = m[i]->hist_dt[field], h2 = m[i]->hist_dt2[field];
+        if (!(h1 > 0.0)) continue;
+        if (o.extrapolate >= 2 && h2 > 0.0) {
+            const double Ln = (dt + h1) * (dt + h1 + h2) / (h1 * (h1 + h2));
+            const double Lpp = dt * (dt + h1) / ((h1 + h2) * h2);
+            c1[i] = Ln - 1.0;
+            c2[i] = -Lpp;
+        } else {
+            c1[i] = dt / h1;
+        }
+    }
 }
 
 void Batch::pressure_rhs(Hier &H, bool steady)
@@ -1834,8 +1849,11 @@ void Batch::gather_state()
     }
     vgather_scatter(ch.p, hch, P, off, Pn.p, true, s);
     vgather_scatter(ch.p, hch, T, off, Tn.p, true, s);
-    bool hist = false;
-    for (int i = 0; i < n; i++) hist |= m[i]->hist_dt[0] > 0.0 || m[i]->hist_dt[1] > 0.0;
+    bool hist = false, hist2 = false;
+    for (int i = 0; i < n; i++) {
+        hist |= m[i]->hist_dt[0] > 0.0 || m[i]->hist_dt[1] > 0.0;
+        hist2 |= m[i]->hist_dt2[0] > 0.0 || m[i]->hist_dt2[1] > 0.0;
+    }
     if (hist) {
         for (int i = 0; i < n; i++) {
             P[i] = m[i]->Pprev.p;
@@ -1843,6 +1861,14 @@ void Batch::gather_state()
         }
         vgather_scatter(ch.p, hch, P, off, Pp.p, true, s);
         vgather_scatter(ch.p, hch, T, off, Tp.p, true, s);
+    }
+    if (hist2) {
+        for (int i = 0; i < n; i++) {
+            P[i] = m[i]->Pprev2.p;
+            T[i] = m[i]->Tprev2.p;
+        }
+        vgather_scatter(ch.p, hch, P, off, Ppp.p, true, s);
+        vgather_scatter(ch.p, hch, T, off, Tpp.p, true, s);
     }
 }
 
@@ -1859,8 +1885,11 @@ void Batch::scatter_state()
     }
     vgather_scatter(ch.p, hch, P, off, Pn.p, false, s);
     vgather_scatter(ch.p, hch, T, off, Tn.p, false, s);
-    bool hist = false;
-    for (int i = 0; i < n; i++) hist |= m[i]->hist_dt[0] > 0.0 || m[i]->hist_dt[1] > 0.0;
+    bool hist = false, hist2 = false;
+    for (int i = 0; i < n; i++) {
+        hist |= m[i]->hist_dt[0] > 0.0 || m[i]->hist_dt[1] > 0.0;
+        hist2 |= m[i]->hist_dt2[0] > 0.0 || m[i]->hist_dt2[1] > 0.0;
+    }
     if (hist) {
         for (int i = 0; i < n; i++) {
             P[i] = m[i]->Pprev.p;
@@ -1868,6 +1897,14 @@ void Batch::scatter_state()
         }
         vgather_scatter(ch.p, hch, P, off, Pp.p, false, s);
         vgather_scatter(ch.p, hch, T, off, Tp.p, false, s);
+    }
+    if (hist2) {
+        for (int i = 0; i < n; i++) {
+            P[i] = m[i]->Pprev2.p;
+            T[i] = m[i]->Tprev2.p;
+        }
+        vgather_scatter(ch.p, hch, P, off, Ppp.p, false, s);
+        vgather_scatter(ch.p, hch, T, off, Tpp.p, false, s);
     }
     export_state();   // completion wait (spin on the export's sequence number)
 }
@@ -1886,12 +1923,13 @@ FieldStats Batch::solve_pressure(double dt, bool steady_all, const hts_solver_op
         tn[i] = m[i]->t + (steady_all ? 0.0 : dt);
         fs[i] = steady ? 1.0 : dt * m[i]->B;
     }
-    const std::vector<double> xf = xtra_factors(0, steady_all ? 0.0 : dt, o);
-    set_time(tn, fs, &xf);
+    std::vector<double> xf, xf2;
+    xtra_factors(0, steady_all ? 0.0 : dt, o, xf, xf2);
+    set_time(tn, fs, &xf, &xf2);
     Hier &H = pressure_hier(steady, dt, o);
     pressure_rhs(H, steady);
     VecCtx v = vctx(false);
-    vextrapolate(v, S_XTRA, H.ops.d64.p, Pn.p, Pp.p, x.p);
+    vextrapolate(v, S_XTRA, S_XTRA2, H.ops.d64.p, Pn.p, Pp.p, Ppp.p, x.p);
     std::vector<int32_t> all(n, 1);
     FieldStats st = solve_field(0, &H, H.ops, b.p, x.p, o, all, nullptr);
     std::vector<int32_t> a(n, 1);
@@ -1907,8 +1945,9 @@ FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
         tn[i] = m[i]->t + dt;
         fs[i] = dt;
     }
-    const std::vector<double> xf = xtra_factors(1, dt, o);
-    set_time(tn, fs, &xf);
+    std::vector<double> xf, xf2;
+    xtra_factors(1, dt, o, xf, xf2);
+    set_time(tn, fs, &xf, &xf2);
     std::vector<int32_t> all(n, 1);
     set_active(all);
     VecCtx v = vctx(false);
@@ -1917,7 +1956,7 @@ FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
     launch_source_values(lsrc.p, nlsrc, S.p, lcoef.p, s);
     Hier &H = heat_prec(dt, o);
     heat_rhs(H);
-    vextrapolate(v, S_XTRA, H.ops.d64.p, Tn.p, Tp.p, x.p);
+    vextrapolate(v, S_XTRA, S_XTRA2, H.ops.d64.p, Tn.p, Tp.p, Tpp.p, x.p);
     FieldStats st = solve_field(1, H.multigrid ? &H : nullptr, H.ops, b.p, x.p, o, all, &H);
     set_active(all);
     vadd(vctx(false), x.p, g.p, T1.p);
@@ -1952,11 +1991,14 @@ int Batch::step(double dt, const hts_solver_opts &o, std::vector<hts_step_stats>
         std::vector<int32_t> all(n, 1);
         set_active(all);
         VecCtx v = vctx(false);
-        vshift(v, P1.p, Pn.p, Pp.p);
-        vshift(v, T1.p, Tn.p, Tp.p);
+        vshift(v, P1.p, Pn.p, Pp.p, Ppp.p);
+        vshift(v, T1.p, Tn.p, Tp.p, Tpp.p);
         for (int i = 0; i < n; i++) {
             m[i]->t += dt;
-            m[i]->hist_dt[0] = m[i]->hist_dt[1] = dt;
+            for (int f = 0; f < 2; f++) {
+                m[i]->hist_dt2[f] = m[i]->hist_dt[f];
+                m[i]->hist_dt[f] = dt;
+            }
         }
     }
     // no wait here: the statistics came from the solvers' exports, and the
@@ -2228,7 +2270,7 @@ hts_status hts_solve_steady_pressure(hts_mesh *m, const hts_solver_opts *opts, h
         HTS_HIP(hipMemcpyAsync(m->P.p, B->P1.p, m->nnode * sizeof(double), hipMemcpyDeviceToDevice, B->s));
         HTS_HIP(hipStreamSynchronize(B->s));
         m->has_state[0] = true;
-        m->hist_dt[0] = 0.0;   // not a time step: no previous level
+        m->hist_dt[0] = m->hist_dt2[0] = 0.0;   // not a time step: no previous levels
     });
 }
 

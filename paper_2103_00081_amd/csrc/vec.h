@@ -65,15 +65,17 @@ void vbasis_update(const VecCtx &v, const T *Z, int64_t ld, const int32_t *kdim,
                    double scale, int iscale, TX *x);
 template <typename TX, typename TY> void vconvert(const VecCtx &v, double sc, int ic, const TX *x, TY *y);
 template <typename T> void vadd_scaled(const VecCtx &v, double sc, int ic, const T *d, double *x);
-// x = Xn + c (Xn - Xp), c = S[slot] per instance; c == 0: x = Xn exactly;
-// 0 at the constrained nodes of ops when ops is given
-void vextrapolate(const VecCtx &v, int slot, const OpDev *ops, const double *Xn, const double *Xp, double *x);
+// x = Xn + c1 (Xn - Xp) + c2 (Xp - Xpp), c1 = S[slot1], c2 = S[slot2] per
+// instance (Xp read only if a factor is nonzero, Xpp only if c2 is); 0 at
+// the constrained nodes of ops when ops is given
+void vextrapolate(const VecCtx &v, int slot1, int slot2, const OpDev *ops, const double *Xn, const double *Xp,
+                  const double *Xpp, double *x);
 // b = (b - y) + S[slot] ld
 void vrhs_combine(const VecCtx &v, const double *y, const double *ld, int slot, double *b);
 // z = x + y
 void vadd(const VecCtx &v, const double *x, const double *y, double *z);
-// time-level shift: Xp = Xn, then Xn = X1
-void vshift(const VecCtx &v, const double *X1, double *Xn, double *Xp);
+// time-level shift: Xpp = Xp, Xp = Xn, Xn = X1
+void vshift(const VecCtx &v, const double *X1, double *Xn, double *Xp, double *Xpp);
 template <typename T> void vmask(const VecCtx &v, const OpDev *ops, T *y, T val);
 
 // P32 = (P - P[node 0 of the instance]) + rho_w g z (FP32 heat operator input)

@@ -385,27 +385,33 @@ __global__ __launch_bounds__(VB) void k_add_scaled(const Chunk *__restrict__ chu
         if (l.in[u]) x[l.e[u]] = xv[u] + c * (double)dv[u];
 }
 
-// Initial guess from the last two time levels: x = Xn + c (Xn - Xp),
-// c = S[slot] of the instance; c == 0 copies Xn (Xp is then not read);
-// constrained nodes of ops (if given) get 0.
+// Initial guess from the last time levels: x = Xn + c1 (Xn - Xp) +
+// c2 (Xp - Xpp), c1 = S[slot1], c2 = S[slot2] of the instance; with both 0
+// it copies Xn (the older levels are then not read); constrained nodes of
+// ops (if given) get 0.
 __global__ __launch_bounds__(VB) void k_extrapolate(const Chunk *__restrict__ chunks, const int32_t *active,
-                                                    const double *S, int slot, const OpDev *__restrict__ ops,
-                                                    const double *__restrict__ Xn, const double *__restrict__ Xp,
+                                                    const double *S, int slot1, int slot2,
+                                                    const OpDev *__restrict__ ops, const double *__restrict__ Xn,
+                                                    const double *__restrict__ Xp, const double *__restrict__ Xpp,
                                                     double *__restrict__ x)
 {
     CHUNK_PROLOGUE
-    const double c = Si[slot];
+    const double c1 = Si[slot1], c2 = Si[slot2];
+    const bool lin = c1 != 0.0 || c2 != 0.0, quad = c2 != 0.0;
     const Lanes l = chunk_lanes(ch);
-    double a[EPT], b[EPT];
+    double a[EPT], b[EPT], q[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; u++) {
         a[u] = Xn[l.c[u]];
-        b[u] = c != 0.0 ? Xp[l.c[u]] : 0.0;
+        b[u] = lin ? Xp[l.c[u]] : 0.0;
+        q[u] = quad ? Xpp[l.c[u]] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < EPT; u++)
         if (l.in[u]) {
-            double v = c != 0.0 ? a[u] + c * (a[u] - b[u]) : a[u];
+            double v = a[u];
+            if (lin) v = a[u] + c1 * (a[u] - b[u]);
+            if (quad) v += c2 * (b[u] - q[u]);
             if (ops) {
                 const OpDev &o = ops[ch.inst];
                 if (node_constrained(o, l.e[u] - o.off)) v = 0.0;
@@ -452,22 +458,25 @@ __global__ __launch_bounds__(VB) void k_add(const Chunk *__restrict__ chunks, co
         if (l.in[u]) z[l.e[u]] = xv[u] + yv[u];
 }
 
-// Xp = Xn, Xn = X1 (commit of a step, keeping the previous level)
+// Xpp = Xp, Xp = Xn, Xn = X1 (commit of a step, keeping two older levels)
 __global__ __launch_bounds__(VB) void k_shift(const Chunk *__restrict__ chunks, const int32_t *active,
                                               const double *S, const double *__restrict__ X1,
-                                              double *__restrict__ Xn, double *__restrict__ Xp)
+                                              double *__restrict__ Xn, double *__restrict__ Xp,
+                                              double *__restrict__ Xpp)
 {
     CHUNK_PROLOGUE
     const Lanes l = chunk_lanes(ch);
-    double a[EPT], b[EPT];
+    double a[EPT], b[EPT], c[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; u++) {
         a[u] = X1[l.c[u]];
         b[u] = Xn[l.c[u]];
+        c[u] = Xp[l.c[u]];
     }
 #pragma unroll
     for (int u = 0; u < EPT; u++)
         if (l.in[u]) {
+            Xpp[l.e[u]] = c[u];
             Xp[l.e[u]] = b[u];
             Xn[l.e[u]] = a[u];
         }
@@ -690,9 +699,10 @@ __global__ __launch_bounds__(VB) void k_set_slots(SlotBlock b, int beg, int cnt,
 
 template <typename T>
 void vfill(const VecCtx &v, T *y, T val) { k_fill<T><<<GRID>>>(v.chunks, v.active, v.S, y, val); HTS_LAUNCH_CHECK(); }
-void vextrapolate(const VecCtx &v, int slot, const OpDev *ops, const double *Xn, const double *Xp, double *x)
+void vextrapolate(const VecCtx &v, int slot1, int slot2, const OpDev *ops, const double *Xn, const double *Xp,
+                  const double *Xpp, double *x)
 {
-    k_extrapolate<<<GRID>>>(v.chunks, v.active, v.S, slot, ops, Xn, Xp, x);
+    k_extrapolate<<<GRID>>>(v.chunks, v.active, v.S, slot1, slot2, ops, Xn, Xp, Xpp, x);
     HTS_LAUNCH_CHECK();
 }
 void vrhs_combine(const VecCtx &v, const double *y, const double *ld, int slot, double *b)
@@ -705,9 +715,9 @@ void vadd(const VecCtx &v, const double *x, const double *y, double *z)
     k_add<<<GRID>>>(v.chunks, v.active, v.S, x, y, z);
     HTS_LAUNCH_CHECK();
 }
-void vshift(const VecCtx &v, const double *X1, double *Xn, double *Xp)
+void vshift(const VecCtx &v, const double *X1, double *Xn, double *Xp, double *Xpp)
 {
-    k_shift<<<GRID>>>(v.chunks, v.active, v.S, X1, Xn, Xp);
+    k_shift<<<GRID>>>(v.chunks, v.active, v.S, X1, Xn, Xp, Xpp);
     HTS_LAUNCH_CHECK();
 }
 template <typename T>

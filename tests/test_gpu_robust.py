@@ -4,17 +4,18 @@
   library copies as given) makes the heat solve break down: the step returns
   HTS_ERR_BREAKDOWN and neither field nor the time advances, in FP64 and in
   FP32-refined mode.
-* Checkpoint / resume: the state, the previous time level and the heat
-  preconditioner's spectral estimates read back after two steps and set on
-  a fresh mesh of the same scenario continue bit for bit like the
+* Checkpoint / resume: the state, the two previous time levels and the heat
+  preconditioner's spectral estimates read back after three steps and set
+  on a fresh mesh of the same scenario continue bit for bit like the
   uninterrupted run.
 * Changing the time-step size keeps at most two pressure multigrid
   hierarchies; steps that alternate between three sizes give the same bits
   as fresh meshes that only ever see one size (given the same two levels).
-* The extrapolated initial guess: the previous level is the state one step
-  earlier, setting a state forgets it (the next step is then the plain one
-  bit for bit), and extrapolated steps meet the same residual test in fewer
-  iterations, with answers within the solver tolerance of the plain ones.
+* The extrapolated initial guess: the previous levels are the states one
+  and two steps earlier, setting a state forgets them (the next step is
+  then the plain one bit for bit), and extrapolated steps meet the same
+  residual test in fewer iterations, with answers within the solver
+  tolerance of the plain ones.
 """
 import numpy as np
 import pytest
@@ -25,6 +26,13 @@ from gpu_util import print_case
 pytestmark = pytest.mark.gpu
 
 NC = (24, 20, 12)
+
+
+def copy_levels(dst, src):
+    """The previous time levels of src, set on dst (level 1 first)."""
+    for f in (0, 1):
+        for level in (1, 2):
+            dst.set_previous_state(f, *src.get_previous_state(f, level), level=level)
 
 
 def scenario(n_steps=6):
@@ -61,24 +69,24 @@ def test_checkpoint_resume_is_bit_exact(hts, mode):
     s = scenario()
     o = hts.default_opts(mode=mode, rtol=1e-8)
     a = hts.from_scenario(s, opts=o)
-    for _ in range(4):
+    for _ in range(5):
         assert a.solve_step(s.dt, o)[0] == 0
     b = hts.from_scenario(s, opts=o)
-    for _ in range(2):
+    for _ in range(3):
         assert b.solve_step(s.dt, o)[0] == 0
     P, t = b.get_state(0)
     T, _ = b.get_state(1)
-    prev = [b.get_previous_state(f) for f in (0, 1)]
-    assert prev[0][1] == s.dt and prev[1][1] == s.dt
+    for f in (0, 1):
+        for level in (1, 2):
+            assert b.get_previous_state(f, level)[1] == s.dt
     spec = b.get_heat_spectrum()
     assert spec[0] == s.dt and spec[1] > 0 and spec[2] > 0
-    del b
     c = hts.from_scenario(s, initial=False, opts=o)
     c.set_state(0, P, t)
     c.set_state(1, T, t)
-    for f in (0, 1):
-        c.set_previous_state(f, *prev[f])
+    copy_levels(c, b)
     c.set_heat_spectrum(spec)
+    del b
     for _ in range(2):
         assert c.solve_step(s.dt, o)[0] == 0
     assert np.array_equal(a.get_state(0)[0], c.get_state(0)[0])
@@ -101,8 +109,7 @@ def test_alternating_step_sizes_match_fresh_meshes(hts):
         T, _ = m.get_state(1)
         f.set_state(0, P, t)
         f.set_state(1, T, t)
-        for fld in (0, 1):
-            f.set_previous_state(fld, *m.get_previous_state(fld))
+        copy_levels(f, m)
         assert f.solve_step(dt, o)[0] == 0
         assert m.solve_step(dt, o)[0] == 0
         assert np.array_equal(m.get_state(0)[0], f.get_state(0)[0])
@@ -120,6 +127,7 @@ def test_extrapolated_initial_guess(hts, mode):
     b = hts.from_scenario(s, opts=op)
     assert a.get_previous_state(0) == (None, 0.0)
     its = {0: [0, 0], 1: [0, 0]}
+    P_older = None
     for k in range(6):
         P_before = a.get_state(0)[0]
         ca, sa = a.solve_step(s.dt, ox)
@@ -128,6 +136,12 @@ def test_extrapolated_initial_guess(hts, mode):
         # the previous level is the state one step earlier, bit for bit
         Pp, dtp = a.get_previous_state(0)
         assert dtp == s.dt and np.array_equal(Pp, P_before)
+        Ppp, dtpp = a.get_previous_state(0, 2)
+        if P_older is None:
+            assert Ppp is None and dtpp == 0.0
+        else:
+            assert dtpp == s.dt and np.array_equal(Ppp, P_older)
+        P_older = P_before
         if k >= 2:
             for f in (0, 1):
                 its[f][0] += sa["iters"][f]

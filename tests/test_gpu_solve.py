@@ -299,7 +299,8 @@ def test_cached_batch_is_dropped_when_a_mesh_changes(hts):
     for m, src in zip(c, a):
         for f in (0, 1):
             m.set_state(f, src.get_state(f)[0], src.get_state(f)[1])
-            m.set_previous_state(f, *src.get_previous_state(f))
+            for level in (1, 2):
+                m.set_previous_state(f, *src.get_previous_state(f, level), level=level)
     # the unchanged mesh keeps the heat preconditioner's estimates of its
     # first step; the changed one estimates again (as its fresh copy does)
     c[0].set_heat_spectrum(a[0].get_heat_spectrum())
