@@ -2,8 +2,8 @@
 
 hts_apply_operator_noalloc runs the same kernels on the same data with its
 buffers in a static device array, so its result must equal that of
-hts_apply_operator bit for bit, for both fields and precisions, on Q1, Q2
-and graded meshes.  Two calls in a row share the array: the second, on a
+hts_apply_operator bit for bit, for both fields and precisions, on Q1, Q2,
+graded and general hexahedral meshes.  Two calls in a row share the array: the second, on a
 smaller mesh, must not see anything of the first.  A mesh whose buffers do
 not fit is refused before any device work, and a changed mesh must be
 prepared again by the allocating path first.
@@ -21,7 +21,8 @@ def cases():
     return [("aquifer 40x36x20 Q1", synth.config2(ncells=(40, 36, 20), n_steps=1)),
             ("aquifer 17x13x9 Q1", synth.config2(ncells=(17, 13, 9), n_steps=1)),
             ("piles 24x24x12 Q2", synth.config3(degree=2, ncells=(24, 24, 12), n_steps=1)),
-            ("island graded 32x20x8 Q1", synth.island(ncells=(32, 20, 8), n_steps=1, graded=True, degree=1))]
+            ("island graded 32x20x8 Q1", synth.island(ncells=(32, 20, 8), n_steps=1, graded=True, degree=1)),
+            ("terrain hexahedra 20x16x8 Q1", synth.aquifer_hex(ncells=(20, 16, 8), n_steps=1))]
 
 
 def check(hts, label, scn, rng):
