@@ -164,3 +164,42 @@ def test_extrapolated_initial_guess(hts, mode):
     assert c.solve_step(s.dt, ox)[0] == 0 and d.solve_step(s.dt, op)[0] == 0
     for f in (0, 1):
         assert np.array_equal(c.get_state(f)[0], d.get_state(f)[0])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_extrapolation_is_exact_for_quadratic_histories(hts, mode):
+    """Previous levels set on a quadratic in time through the state S and the
+    answer P* of the next step (any step sizes): the quadratic extrapolation
+    (Lagrange form at t^n - h1 - h2, t^n - h1, t^n) reproduces P*, so the
+    pressure solve starts converged; with level 2 forgotten, levels on a
+    line through S and P* do the same for the linear extrapolation."""
+    print_case("exact extrapolation, mode", mode)
+    s = scenario(n_steps=2)
+    o = hts.default_opts(mode=mode, rtol=1e-8)
+    a = hts.from_scenario(s, opts=o)
+    S, t0 = a.get_state(0)
+    T0, _ = a.get_state(1)
+    assert a.solve_step(s.dt, o)[0] == 0
+    Pstar = a.get_state(0)[0]
+    dt, h1, h2 = s.dt, 0.7 * s.dt, 1.6 * s.dt
+    rng = np.random.default_rng(4)
+    # X(tau) = S + alpha tau + beta tau^2 with X(dt) = P*
+    beta = 0.3 * (Pstar - S) / dt ** 2 * rng.uniform(0.5, 1.5, S.size)
+    alpha = (Pstar - S - beta * dt ** 2) / dt
+    X = lambda tau: S + alpha * tau + beta * tau ** 2
+    for levels in (2, 1):
+        b = hts.from_scenario(s, initial=False, opts=o)
+        b.set_state(0, S, t0)
+        b.set_state(1, T0, t0)
+        if levels == 2:
+            b.set_previous_state(0, X(-h1), h1, level=1)
+            b.set_previous_state(0, X(-h1 - h2), h2, level=2)
+        else:
+            lin = lambda tau: S + (Pstar - S) / dt * tau
+            b.set_previous_state(0, lin(-h1), h1, level=1)
+        code, st = b.solve_step(dt, o)
+        assert code == 0, st
+        print("levels", levels, "pressure iterations", st["iters"][0], "relres", st["relres"][0])
+        assert st["iters"][0] == 0, st
+        P = b.get_state(0)[0]
+        assert np.linalg.norm(P - Pstar) <= 1e-8 * np.linalg.norm(Pstar)
