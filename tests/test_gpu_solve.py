@@ -310,3 +310,40 @@ def test_cached_batch_is_dropped_when_a_mesh_changes(hts):
         assert np.array_equal(mb.get_state(1)[0], mc.get_state(1)[0])
     T1 = b[1].get_state(1)[0]
     assert np.isclose(T1.max(), 330.0)
+
+
+def test_heat_spectral_estimates_against_the_oracle(hts):
+    """The heat preconditioner's estimates after one step: the largest
+    eigenvalue of D^-1 A without convection and the imaginary extent of the
+    convection part, D^-1 (A - A_0) (A_0 the operator with the Darcy flux
+    removed), against the oracle's matrices (ARPACK on the assembled,
+    eliminated systems).  Power iteration approaches the extremes from
+    below; the bounds leave room for its 12 steps."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    print_case("heat spectrum vs oracle")
+    scn = synth.config2(ncells=(24, 24, 12), n_steps=1)
+    o = hts.default_opts(rtol=1e-10)
+    m = hts.from_scenario(scn, opts=o)
+    P0, _ = m.get_state(0)
+    T0, _ = m.get_state(1)
+    assert m.solve_step(scn.dt, o)[0] == 0
+    dt_s, lsym, lfull, beta = m.get_heat_spectrum()
+    assert dt_s == scn.dt
+    P1, _ = m.get_state(0)
+    om = oracle.Mesh.of(scn)
+    t1 = scn.t0 + scn.dt
+    X, Y, Z = om.coords()
+    Phyd = P1[0] + scn.rho_w * scn.g * (Z[0] - Z)       # no Darcy flux
+    H, hb = oracle.heat_system(scn, om, T0, P1, t1)
+    H0, _ = oracle.heat_system(scn, om, T0, Phyd, t1)
+    mask, g = oracle.dirichlet(scn, om, 1, t1)
+    free, HF, _ = oracle.eliminate(H, hb, mask, g)
+    _, H0F, _ = oracle.eliminate(H0, hb, mask, g)
+    dinv = sp.diags(1.0 / H0F.diagonal())
+    ls = abs(spla.eigs(dinv @ H0F, k=1, which="LM", return_eigenvectors=False)[0])
+    C = dinv @ (HF - H0F)
+    b_ex = abs(spla.eigs(C, k=1, which="LM", return_eigenvectors=False)[0])
+    print("lmax symmetric %.5g (oracle %.5g), imaginary extent %.5g (oracle %.5g)" % (lsym, ls, beta, b_ex))
+    assert 0.9 * ls <= lsym <= 1.02 * ls
+    assert 0.8 * b_ex <= beta <= 1.05 * b_ex
