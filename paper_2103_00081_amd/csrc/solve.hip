@@ -1381,7 +1381,11 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
     if (graphed) {
         // Chunks replayed as graphs with a host check between them: the first
         // chunk as long as the previous solve of this system took, then
-        // chunks of two (or check_every) iterations.
+        // chunks of one (or check_every) iteration.  Every chunk ends right
+        // after a convergence check, so a chunk of the right length launches
+        // no preconditioner application past convergence; the later chunks
+        // start with the preconditioner and the direction update that the
+        // eager loop runs at the end of an iteration.
         char key[256];
         std::snprintf(key, sizeof key, "cg%d|%d|%p|%p|%p|%d|%d", (int)sizeof(T), A.field, (const void *)&A,
                       (const void *)b, (const void *)x, maxit, flexible ? 1 : 0);
@@ -1397,24 +1401,27 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
             K = std::max(1, std::min(K, maxit - done));
             if (chunk_cap > 0) K = std::min(K, chunk_cap);
             const std::string mode = chunk_mode ? chunk_mode() : std::string();
-            replay(base + mode + "|K" + std::to_string(K), [&] {
+            const bool lead = done > 0;
+            replay(base + mode + (lead ? "|c" : "|f") + std::to_string(K), [&] {
                 VecCtx vg = vctx();
                 for (int c = 0; c < K; c++) {
+                    if (c > 0 || lead) {
+                        M(r, z);
+                        vdot<T>(vg, z, r, ro, partial.p);
+                        vreduce(rch, partial.p, 2, RED_CG_BETA, 0, S.p, active.p, 0, 0.0, nullptr, s);
+                        vaxpby<T>(vg, 1.0, -1, z, 1.0, S_BETA, pv);
+                    }
                     EpiArgs<T> e2{};
                     e2.partial = partial.p;
                     apply_op<T>(A, EPI_DOT, true, pv, q, e2);
                     vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_CG_ALPHA, 0, S.p, active.p, 0, 0.0, nullptr, s);
                     vcg_update<T>(vg, x, r, pv, q, ro, partial.p);
                     vreduce(rch, partial.p, 2, RED_CG_CONV, 0, S.p, active.p, maxit, 0.0, nullptr, s);
-                    M(r, z);
-                    vdot<T>(vg, z, r, ro, partial.p);
-                    vreduce(rch, partial.p, 2, RED_CG_BETA, 0, S.p, active.p, 0, 0.0, nullptr, s);
-                    vaxpby<T>(vg, 1.0, -1, z, 1.0, S_BETA, pv);
                 }
             });
             done += K;
             if (!any_active()) break;
-            K = check_every > 1 ? check_every : 2;
+            K = std::max(1, check_every);
         }
         // every chunk ends with an export: the slots are those of the last one
         slots_from_export();
@@ -1489,7 +1496,8 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
         };
         if (use_graph && !g_timing.on) {
             // the whole cycle as one graph, in chunks of K steps with a host
-            // check between them
+            // check between them: the first as long as the previous cycle of
+            // this system, then one (or check_every) step at a time
             char key[256];
             std::snprintf(key, sizeof key, "gm%d|%d|%p|%p|%p|%d|%d", (int)sizeof(T), A.field, (const void *)&A,
                           (const void *)b, (const void *)x, maxit, mres);
@@ -1505,7 +1513,7 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
                 });
                 j0 = j1;
                 if (!any_active()) break;
-                K = check_every > 1 ? check_every : 2;
+                K = std::max(1, check_every);
             }
         } else {
             for (int j = 0; j < mres; j++) {
