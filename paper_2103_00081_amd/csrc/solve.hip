@@ -1556,8 +1556,10 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
                 more = true;
             }
         }
-        set_active(again);
+        // (without a next cycle the caller sets the flags it needs before
+        // its next launch)
         if (!more) break;
+        set_active(again);
     }
     exported_last = true;
 }
@@ -1615,8 +1617,10 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
     std::vector<int32_t> outer = participants;
     int total_inner = 0;
     bool fresh = false;   // the last export holds the final slots
+    // The device flags equal outer at the top of every outer step: set to the
+    // participants above (nothing in between changes them) and to outer at
+    // the end of the previous step (the update there only reads them).
     for (int oit = 0; oit < 40; oit++) {
-        set_active(outer);
         EpiArgs<double> ep{};
         ep.b = b64;
         ep.partial = partial.p;
