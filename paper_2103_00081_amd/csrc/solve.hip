@@ -1609,7 +1609,8 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
     HTS_HIP(hipEventCreate(&e0));
     HTS_HIP(hipEventCreate(&e1));
     HTS_HIP(hipEventRecord(e0, s));
-    set_active(participants);
+    // the device flags equal participants on entry: both callers set them
+    // with the right-hand side, and nothing launched since changes them
     VecCtx vall = vctx();
     vdot<double>(vall, b64, b64, nullptr, partial.p);
     vreduce(rch, partial.p, 2, RED_NONE, 0, S.p, active.p, 0, 0.0, redout.p, s);
@@ -1617,9 +1618,10 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
     std::vector<int32_t> outer = participants;
     int total_inner = 0;
     bool fresh = false;   // the last export holds the final slots
-    // The device flags equal outer at the top of every outer step: set to the
-    // participants above (nothing in between changes them) and to outer at
-    // the end of the previous step (the update there only reads them).
+    // The device flags equal outer at the top of every outer step: the
+    // participants on entry (the norm and tolerance launches above only read
+    // them) and outer as set at the end of the previous step (the update
+    // there only reads them).
     for (int oit = 0; oit < 40; oit++) {
         EpiArgs<double> ep{};
         ep.b = b64;
@@ -1961,7 +1963,8 @@ FieldStats Batch::solve_heat(double dt, const hts_solver_opts &o)
     xtra_factors(1, dt, o, xf, xf2);
     set_time(tn, fs, &xf, &xf2);
     std::vector<int32_t> all(n, 1);
-    set_active(all);
+    // every instance's flag is set: the pressure solve of the same step
+    // ends by setting them all (the preconditioner set-up below needs them)
     VecCtx v = vctx(false);
     vpiezo32(v, massH.d64.p, P1.p, P32.p);
     // line coefficients before the preconditioner setup reads the operator
