@@ -227,11 +227,12 @@ struct Batch {
     template <typename T> void tmass_prec(Hier &H, const T *b, T *x);
     void build_tmass(Hier &H, double dt);
     template <typename T>
+    // x0_zero: x holds zeros on entry, so the initial residual is b itself
     int cg(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit, bool flexible,
-           int check_every);
+           int check_every, bool x0_zero = false);
     template <typename T>
     void fgmres(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit, int mres,
-                int check_every);
+                int check_every, bool x0_zero = false);
     void ensure_gmres(int mres);
 
     FieldStats solve_field(int field, Hier *mg, const Tables &A, double *b64, double *x64, const hts_solver_opts &o,

@@ -1354,7 +1354,7 @@ void Batch::cheb_prec(Hier &H, const T *b, T *x)
 // ------------------------------------------------------------------- CG
 template <typename T>
 int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit,
-              bool flexible, int check_every)
+              bool flexible, int check_every, bool x0_zero)
 {
     T *r = PK(T, this->r, r32), *z = PK(T, this->z, z32), *pv = PK(T, pp, p32), *q = PK(T, this->q, q32);
     T *ro = flexible ? PK(T, rold, rold32) : nullptr;
@@ -1363,8 +1363,15 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
     ep.b = b;
     ep.partial = partial.p;
     exported_last = false;
-    apply_op<T>(A, EPI_RESID_NORM, true, x, r, ep);
-    vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+    if (x0_zero) {
+        // r = b - A 0 = b: a copy and a norm instead of an operator pass
+        vcopy<T>(v, b, r);
+        vdot<T>(v, b, b, nullptr, partial.p);
+        vreduce(rch, partial.p, 2, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+    } else {
+        apply_op<T>(A, EPI_RESID_NORM, true, x, r, ep);
+        vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_CG_INIT, 0, S.p, active.p, maxit, 0.0, nullptr, s);
+    }
     const bool hook = std::is_same<T, double>::value && cg_hook;
     const bool graphed = use_graph && !hook && !g_timing.on;
     // (replayed chunks skip instances that converged at the start, so only
@@ -1461,7 +1468,7 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
 // ---------------------------------------------------------------- FGMRES
 template <typename T>
 void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M, const T *b, T *x, int maxit,
-                   int mres, int check_every)
+                   int mres, int check_every, bool x0_zero)
 {
     ensure_gmres(mres);
     T *V = PK(T, V64, V32), *Z = PK(T, Z64, Z32);
@@ -1471,8 +1478,15 @@ void Batch::fgmres(const Tables &A, const std::function<void(const T *, T *)> &M
         EpiArgs<T> ep{};
         ep.b = b;
         ep.partial = partial.p;
-        apply_op<T>(A, EPI_RESID_NORM, true, x, V, ep);
-        vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
+        if (x0_zero && cycle == 0) {
+            // V_0 = b - A 0 = b
+            vcopy<T>(v, b, V);
+            vdot<T>(v, b, b, nullptr, partial.p);
+            vreduce(rch, partial.p, 2, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
+        } else {
+            apply_op<T>(A, EPI_RESID_NORM, true, x, V, ep);
+            vreduce(rwk[A.field][prec_of<T>()], partial.p, 1, RED_STORE, S_RR, S.p, active.p, 0, 0.0, nullptr, s);
+        }
         // which instances take part (S_CYC) is read back with the first
         // check of the Arnoldi steps, not on its own
         gm_begin(n, active.p, S.p, gg.p, mres, gkdim.p, s);
@@ -1659,8 +1673,9 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
                 else cheb_prec<float>(*hprec, r_, z_);
             };
             graph_tag = (mg ? "mg" : "cheb") + std::to_string((uintptr_t)(mg ? mg : hprec));
-            if (field == 0) cg<float>(A, M, b32.p, x32.p, maxit, false, o.check_every);
-            else fgmres<float>(A, M, b32.p, x32.p, maxit, std::max(2, std::min(o.gmres_restart, 60)), o.check_every);
+            if (field == 0) cg<float>(A, M, b32.p, x32.p, maxit, false, o.check_every, true);
+            else fgmres<float>(A, M, b32.p, x32.p, maxit, std::max(2, std::min(o.gmres_restart, 60)), o.check_every,
+                                 true);
         } else {
             // inner RHS r / ||r||; the Krylov work vectors are r, z, pp, q, rold
             vaxpby<double>(v, 1.0, S_OINV, this->y.p, 0.0, -1, inner_b.p);
@@ -1709,14 +1724,14 @@ FieldStats Batch::solve_field(int field, Hier *mg, const Tables &A, double *b64,
                     vcycle<double>(*mg, 0, r_, z_);   // the fallback instances only
                     nn_gate_end(n, act_save.p, active.p, s);
                 };
-                cg<double>(A, ML, inner_b.p, inner_x.p, maxit, true, 1);
+                cg<double>(A, ML, inner_b.p, inner_x.p, maxit, true, 1, true);
                 chunk_mode = nullptr;
                 chunk_cap = 0;
             } else if (field == 0) {
-                cg<double>(A, M, inner_b.p, inner_x.p, maxit, false, o.check_every);
+                cg<double>(A, M, inner_b.p, inner_x.p, maxit, false, o.check_every, true);
             } else
                 fgmres<double>(A, M, inner_b.p, inner_x.p, maxit, std::max(2, std::min(o.gmres_restart, 60)),
-                               o.check_every);
+                               o.check_every, true);
         }
         if (inner_hook && field == 0 && !fp32) {
             inner_hook(A, inner_x.p);
