@@ -1435,7 +1435,9 @@ int Batch::cg(const Tables &A, const std::function<void(const T *, T *)> &M, con
         exported_last = true;
         int used = 0;
         for (int i = 0; i < n; i++) used = std::max(used, (int)hS[(size_t)i * NSLOT + S_ITER]);
-        last_iters[hkey] = std::max(1, used);
+        // a solve in which no instance iterated (all converged at the start)
+        // keeps the chunk length, so that it captures no new graph
+        if (used > 0) last_iters[hkey] = used;
         return done;
     }
     int it = 0;

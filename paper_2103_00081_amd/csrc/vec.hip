@@ -636,7 +636,12 @@ __global__ __launch_bounds__(RB) void k_reduce(const double *__restrict__ partia
         if (lane == 0) vals[cc] = v;
     }
     __syncthreads();
-    if (!on) return;   // the same for the whole block
+    if (!on) {   // the same for the whole block
+        // a CG solve that finds the instance already inactive counts no
+        // iteration for it (no stale count from an earlier solve)
+        if (op == RED_CG_INIT && threadIdx.x == 0) S[(int64_t)inst * NSLOT + S_ITER] = 0.0;
+        return;
+    }
     if (threadIdx.x == 0 && out)
         for (int c = 0; c < ncomp; c++) out[(int64_t)inst * ncomp + c] = vals[c];
     // FGMRES: the second-pass coefficients and |w'|^2 go straight into the
